@@ -1,0 +1,260 @@
+"""CPU oracle for the lattice-Boltzmann nanochannel path (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check of
+``__graft_entry__`` and by the CPU-baseline leg of ``bench.py``.  The product
+path never imports it and shares no code with it.
+
+The arithmetic lives in ``lbm_oracle.c`` (plain scalar loops, FP64, or x87
+long double for the self-floor check); this module only compiles it with gcc
+and marshals arguments through ctypes.  See the C file's header for what is
+computed and which passages of the paper each part follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIBS = {
+    "f64": os.path.join(_HERE, "liblbm_oracle.so"),
+    "f80": os.path.join(_HERE, "liblbm_oracle_ld.so"),
+}
+
+SLAB, DUCT, TUBE = 0, 1, 2
+
+
+def build(verbose: bool = False) -> None:
+    """Compile both oracle variants with gcc (no FMA contraction, -O2)."""
+    for kind, out in _LIBS.items():
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+               "-Wall", "-Wextra", "-o", out + ".tmp", _SRC, "-lm"]
+        if kind == "f80":
+            cmd.insert(1, "-DORACLE_LONG_DOUBLE")
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("precision", C.c_int), ("geometry", C.c_int),
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("tube_radius", C.c_double), ("tube_cy", C.c_double), ("tube_cz", C.c_double),
+        ("tau", C.c_double), ("rho0", C.c_double),
+        ("force", C.c_double * 3),
+        ("wall_velocity_top", C.c_double),
+    ]
+
+
+class _Spectral(C.Structure):
+    _fields_ = [
+        ("T", C.c_double), ("omega0", C.c_double), ("gamma_s", C.c_double),
+        ("omega_l", C.c_double), ("gamma_l", C.c_double), ("a_l", C.c_double),
+        ("d", C.c_double), ("nq", C.c_int), ("nw", C.c_int),
+        ("q_max", C.c_double), ("w_max", C.c_double),
+        ("lambda_target", C.c_double), ("dispersion", C.c_int),
+    ]
+
+
+_loaded: dict = {}
+
+
+def _lib(kind: str = "f64") -> C.CDLL:
+    if kind in _loaded:
+        return _loaded[kind]
+    path = _LIBS[kind]
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build()
+    lib = C.CDLL(path)
+    vp, dp, lp = C.c_void_p, C.POINTER(C.c_double), C.c_long
+    lib.ora_create.argtypes = [C.POINTER(_Params), C.POINTER(vp)]
+    lib.ora_create.restype = C.c_int
+    lib.ora_destroy.argtypes = [vp]
+    lib.ora_wall_count.argtypes = [vp]
+    lib.ora_wall_count.restype = lp
+    lib.ora_fluid_count.argtypes = [vp]
+    lib.ora_fluid_count.restype = lp
+    lib.ora_step_count.argtypes = [vp]
+    lib.ora_step_count.restype = lp
+    lib.ora_wall_coords.argtypes = [vp, C.POINTER(C.c_int32)]
+    lib.ora_wall_links.argtypes = [vp, dp]
+    lib.ora_set_friction.argtypes = [vp, dp]
+    lib.ora_set_friction.restype = C.c_int
+    lib.ora_step.argtypes = [vp, lp]
+    lib.ora_fields.argtypes = [vp, dp, dp, dp, dp]
+    lib.ora_invariants.argtypes = [vp, dp]
+    lib.ora_get_populations.argtypes = [vp, dp]
+    lib.ora_set_populations.argtypes = [vp, dp, lp]
+    sp = C.POINTER(_Spectral)
+    lib.ora_img_l.argtypes = [sp, C.c_double]
+    lib.ora_img_l.restype = C.c_double
+    lib.ora_img_s.argtypes = [sp, C.c_double, C.c_double, C.c_double]
+    lib.ora_img_s.restype = C.c_double
+    lib.ora_friction_raw.argtypes = [sp, C.c_double]
+    lib.ora_friction_raw.restype = C.c_double
+    lib.ora_friction.argtypes = [sp, dp, lp, dp, dp]
+    lib.ora_sizeof_real.restype = C.c_int
+    _loaded[kind] = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Lattice:
+    """One lattice-Boltzmann channel in the oracle.
+
+    geometry: SLAB (walls on y, periodic z), DUCT (walls on y and z) or TUBE
+    (circular cross-section of ``tube_radius`` centred at (tube_cy, tube_cz) in
+    the box).  For SLAB/DUCT the box is all fluid and the walls lie half a link
+    outside it.  ``kind`` = "f64" or "f80" (long double).
+    """
+
+    def __init__(self, lattice: int, geometry: int, nx: int, ny: int, nz: int,
+                 tau: float, force=(0.0, 0.0, 0.0), rho0: float = 1.0,
+                 tube_radius: float = 0.0, tube_cy: float = 0.0, tube_cz: float = 0.0,
+                 wall_velocity_top: float = 0.0, kind: str = "f64"):
+        self._lib = _lib(kind)
+        p = _Params()
+        p.lattice, p.precision, p.geometry = lattice, 0, geometry
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.tube_radius, p.tube_cy, p.tube_cz = tube_radius, tube_cy, tube_cz
+        p.tau, p.rho0 = tau, rho0
+        p.force = (C.c_double * 3)(*force)
+        p.wall_velocity_top = wall_velocity_top
+        h = C.c_void_p()
+        rc = self._lib.ora_create(C.byref(p), C.byref(h))
+        if rc != 0:
+            raise OracleError(f"ora_create failed with {rc}")
+        self._h = h
+        self.q, self.nx, self.ny, self.nz = lattice, nx, ny, nz
+        self.shape = (nz, ny, nx)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.ora_destroy(h)
+            self._h = None
+
+    @property
+    def wall_count(self) -> int:
+        return int(self._lib.ora_wall_count(self._h))
+
+    @property
+    def fluid_count(self) -> int:
+        return int(self._lib.ora_fluid_count(self._h))
+
+    @property
+    def step_count(self) -> int:
+        return int(self._lib.ora_step_count(self._h))
+
+    def wall_coords(self) -> np.ndarray:
+        out = np.zeros((self.wall_count, 3), dtype=np.int32)
+        self._lib.ora_wall_coords(self._h, out.ctypes.data_as(C.POINTER(C.c_int32)))
+        return out
+
+    def wall_links(self) -> np.ndarray:
+        """Bouzidi fraction per (wall node, direction); 0 where no wall link."""
+        out = np.zeros((self.wall_count, 19), dtype=np.float64)
+        self._lib.ora_wall_links(self._h, _dptr(out))
+        return out[:, : self.q]
+
+    def set_friction(self, lam) -> None:
+        lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64),
+                                                   (self.wall_count,)))
+        if self._lib.ora_set_friction(self._h, _dptr(lam)) != 0:
+            raise OracleError("friction must be >= 0 (inf allowed)")
+
+    def step(self, n: int) -> None:
+        self._lib.ora_step(self._h, int(n))
+
+    def fields(self):
+        """(rho, ux, uy, uz), each shaped (nz, ny, nx); zero on solid cells."""
+        outs = [np.zeros(self.shape) for _ in range(4)]
+        self._lib.ora_fields(self._h, *[_dptr(a) for a in outs])
+        return tuple(outs)
+
+    def invariants(self):
+        """(flux Q, mass M, mass deviation sum(rho - rho0))."""
+        out = np.zeros(3)
+        self._lib.ora_invariants(self._h, _dptr(out))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def get_populations(self) -> np.ndarray:
+        out = np.zeros((self.q,) + self.shape)
+        self._lib.ora_get_populations(self._h, _dptr(out))
+        return out
+
+    def set_populations(self, g: np.ndarray, step: int = 0) -> None:
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert g.shape == (self.q,) + self.shape
+        self._lib.ora_set_populations(self._h, _dptr(g), int(step))
+
+
+@dataclass
+class Spectral:
+    """Synthetic surface-response spectra of the friction quadrature."""
+    T: float
+    omega0: float
+    gamma_s: float
+    omega_l: float
+    gamma_l: float
+    a_l: float = 0.5
+    d: float = 1.0
+    nq: int = 256
+    nw: int = 1024
+    q_max: float | None = None
+    w_max: float | None = None
+    lambda_target: float = 0.05
+    dispersion: int = 1
+
+    def _c(self) -> _Spectral:
+        s = _Spectral()
+        s.T, s.omega0, s.gamma_s = self.T, self.omega0, self.gamma_s
+        s.omega_l, s.gamma_l, s.a_l, s.d = self.omega_l, self.gamma_l, self.a_l, self.d
+        s.nq, s.nw = self.nq, self.nw
+        s.q_max = self.q_max if self.q_max is not None else 10.0 / self.d
+        s.w_max = self.w_max if self.w_max is not None else 20.0 * self.T
+        s.lambda_target, s.dispersion = self.lambda_target, self.dispersion
+        return s
+
+
+def img_l(sp: Spectral, w: float, kind: str = "f64") -> float:
+    s = sp._c()
+    return _lib(kind).ora_img_l(C.byref(s), float(w))
+
+
+def img_s(sp: Spectral, Omega: float, q: float, w: float, kind: str = "f64") -> float:
+    s = sp._c()
+    return _lib(kind).ora_img_s(C.byref(s), float(Omega), float(q), float(w))
+
+
+def friction_raw(sp: Spectral, Omega: float, kind: str = "f64") -> float:
+    s = sp._c()
+    return _lib(kind).ora_friction_raw(C.byref(s), float(Omega))
+
+
+def friction(sp: Spectral, Omega, kind: str = "f64"):
+    """(raw lambda_k, lattice lambda_k) for the plasmon frequencies Omega_k."""
+    Om = np.ascontiguousarray(np.atleast_1d(np.asarray(Omega, dtype=np.float64)))
+    raw = np.zeros_like(Om)
+    lat = np.zeros_like(Om)
+    s = sp._c()
+    _lib(kind).ora_friction(C.byref(s), _dptr(Om), len(Om), _dptr(raw), _dptr(lat))
+    return raw, lat
+
+
+def sizeof_real(kind: str = "f64") -> int:
+    return int(_lib(kind).ora_sizeof_real())

@@ -1,0 +1,556 @@
+/*
+ * oracle/lbm_oracle.c -- plain, slow, obviously-correct CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code, header,
+ * table or constant with the GPU library; it is written from the paper and the
+ * readings listed in the design notes, in plain scalar loops, and computes in
+ * `real` = double (or x87 long double when built with ORACLE_LONG_DOUBLE, to
+ * bound its own rounding floor).
+ *
+ * What it computes (Keldysh-lattice-Boltzmann paper, arXiv 2403.15768):
+ *
+ *  - Water as one lattice-Boltzmann population set (Sec. 4, "one set of
+ *    discrete distributions per species"; Eqs. 1-2 are the continuity and
+ *    momentum equations it reproduces, inertia kept).  Lattices: D2Q9 with the
+ *    velocity numbering the paper gives beside Eqs. 18-20 (0 = rest, 1 = +x,
+ *    2 = +y, 3 = -x, 4 = -y, 5 = (+,+), 6 = (-,+), 7 = (-,-), 8 = (+,-)), and
+ *    D3Q19 (0 rest; 1..6 = +x,-x,+y,-y,+z,-z; then (+,+,0),(-,-,0),(+,-,0),
+ *    (-,+,0),(+,0,+),(-,0,-),(+,0,-),(-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+)).
+ *  - Collision: single-relaxation-time BGK with the second-order equilibrium;
+ *    body force (the pressure-gradient-like bulk force F of Eq. 2) by Guo's
+ *    scheme.  The paper only says "well established procedures" (Sec. 4).
+ *  - State: post-collision populations stored as deviations from the rest
+ *    equilibrium, g_i = f_i - w_i rho0 ("shifted" storage).  Algebraically the
+ *    textbook scheme; it only changes rounding.
+ *  - Walls (Sec. 4.2): the paper's bounce-back rule for no-slip outer walls and
+ *    its free-slip rule at the liquid/solid interface are mixed per wall node
+ *    with weight r = 3 lambda / (1 + 3 lambda), lambda being the interfacial
+ *    friction coefficient of the linear drag law (Eq. 5 and the appendix
+ *    result F_kl = gamma_kl (u_k - u_l), Eq. 26) in lattice units.  The slip
+ *    half is the same-node transverse reversal (c_x, -c_y, -c_z).  Bounce-back
+ *    is half-way on planar walls and Bouzidi-Firdaouss-Lallemand linear
+ *    interpolation on the circular tube.  Inlet/outlet are periodic in x (the
+ *    first option of Sec. 4.2).
+ *  - Friction quadrature: a (q, omega) midpoint sum of the imaginary parts of
+ *    a Drude solid response and a Lorentzian liquid response with a thermal
+ *    factor; the paper states only that the Keldysh analysis yields linear
+ *    friction coefficients (appendix, Eq. 26), the integrand is this build's
+ *    synthetic stand-in.
+ *
+ * Step n -> n+1, for every fluid cell x (no blocking, no fusion):
+ *   1. pull:   df_i = g_i(x - c_i), periodic in x (and z for the slab);
+ *              if x - c_i is solid, the wall rule gives df_i instead;
+ *   2. moments: rho = rho0 + sum df_i;  rho u = sum df_i c_i + F/2;
+ *   3. dfeq_i = w_i [ (rho - rho0) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u) ];
+ *   4. g_i(x, n+1) = df_i - (df_i - dfeq_i)/tau
+ *                    + (1 - 1/(2 tau)) w_i [ 3 (c_i - u) + 9 (c_i.u) c_i ].F
+ *   Reported rho, u "after n steps" are the moments of step 2 built from g(n).
+ *
+ * Parity pins: exact discrete slip-Poiseuille and Couette profiles, exact
+ * mass conservation, free-slip plug acceleration, Hagen-Poiseuille
+ * convergence in the tube, long-double self-floor; quadrature pinned by
+ * complex-arithmetic brute force on tiny grids, the f-sum rule, the closed
+ * form of the q integral and an adaptive integrator (see tests/).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_LONG_DOUBLE
+typedef long double real;
+#define R_SQRT sqrtl
+#define R_EXP expl
+#define R_SINH sinhl
+#define R_ISFINITE(v) isfinite(v)
+#else
+typedef double real;
+#define R_SQRT sqrt
+#define R_EXP exp
+#define R_SINH sinh
+#define R_ISFINITE(v) isfinite(v)
+#endif
+
+#define ORA_OK 0
+#define ORA_EINVAL -1
+#define ORA_ENOMEM -2
+
+enum { ORA_SLAB = 0, ORA_DUCT = 1, ORA_TUBE = 2 };
+
+/* Same field order as the GPU library's parameter struct, but declared here
+ * independently: only the layout of plain numbers is common. */
+typedef struct {
+  int lattice;  /* 9 or 19 */
+  int precision; /* ignored by the oracle (always real) */
+  int geometry; /* ORA_SLAB / ORA_DUCT / ORA_TUBE */
+  int nx, ny, nz;
+  double tube_radius, tube_cy, tube_cz;
+  double tau, rho0;
+  double force[3];
+  double wall_velocity_top; /* moving top wall (y = ny - 1/2), slab/duct only */
+} ora_params;
+
+typedef struct {
+  ora_params p;
+  int q;
+  int c[19][3];
+  real w[19];
+  int opp[19];  /* c_opp = -c */
+  int sig[19];  /* c_sig = (c_x, -c_y, -c_z) */
+  long ncell;   /* nx*ny*nz */
+  unsigned char *fluid;
+  long *wall_id; /* canonical wall-node index or -1 */
+  long nwall;
+  long nfluid;
+  real *r;     /* per cell (wall nodes only) */
+  real *qlink; /* per cell * 19: Bouzidi fraction of wall links (0 if none) */
+  real *g, *gn;
+  long step;
+} ora_ctx;
+
+/* ---------------------------------------------------------------- lattice */
+
+static void set_lattice(ora_ctx *o) {
+  static const int d2q9[9][2] = {{0, 0}, {1, 0},  {0, 1},   {-1, 0}, {0, -1},
+                                 {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+  static const int d3q19[19][3] = {
+      {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+      {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+      {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+      {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  int i, k;
+  o->q = o->p.lattice;
+  for (i = 0; i < o->q; i++) {
+    if (o->q == 9) {
+      o->c[i][0] = d2q9[i][0];
+      o->c[i][1] = d2q9[i][1];
+      o->c[i][2] = 0;
+    } else {
+      o->c[i][0] = d3q19[i][0];
+      o->c[i][1] = d3q19[i][1];
+      o->c[i][2] = d3q19[i][2];
+    }
+  }
+  /* weights from |c|^2: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36 */
+  for (i = 0; i < o->q; i++) {
+    int c2 = o->c[i][0] * o->c[i][0] + o->c[i][1] * o->c[i][1] +
+             o->c[i][2] * o->c[i][2];
+    if (o->q == 9)
+      o->w[i] = c2 == 0 ? (real)4 / 9 : (c2 == 1 ? (real)1 / 9 : (real)1 / 36);
+    else
+      o->w[i] = c2 == 0 ? (real)1 / 3 : (c2 == 1 ? (real)1 / 18 : (real)1 / 36);
+  }
+  /* opposite and transverse reversal found by search over the velocity set */
+  for (i = 0; i < o->q; i++) {
+    o->opp[i] = -1;
+    o->sig[i] = -1;
+    for (k = 0; k < o->q; k++) {
+      if (o->c[k][0] == -o->c[i][0] && o->c[k][1] == -o->c[i][1] &&
+          o->c[k][2] == -o->c[i][2])
+        o->opp[i] = k;
+      if (o->c[k][0] == o->c[i][0] && o->c[k][1] == -o->c[i][1] &&
+          o->c[k][2] == -o->c[i][2])
+        o->sig[i] = k;
+    }
+  }
+}
+
+/* --------------------------------------------------------------- geometry */
+
+static long cell(const ora_ctx *o, int x, int y, int z) {
+  return (long)x + (long)o->p.nx * ((long)y + (long)o->p.ny * (long)z);
+}
+
+/* Is the lattice point (x, y, z) -- already wrapped in the periodic
+ * directions -- a solid point? */
+static int is_solid(const ora_ctx *o, int x, int y, int z) {
+  (void)x;
+  if (y < 0 || y >= o->p.ny || z < 0 || z >= o->p.nz) return 1;
+  if (o->p.geometry == ORA_TUBE) {
+    double dy = (double)y - o->p.tube_cy, dz = (double)z - o->p.tube_cz;
+    return !(dy * dy + dz * dz < o->p.tube_radius * o->p.tube_radius);
+  }
+  return 0;
+}
+
+/* upstream point of link i at (x, y, z): x - c_i with periodic wrap */
+static void upstream(const ora_ctx *o, int x, int y, int z, int i, int *sx,
+                     int *sy, int *sz) {
+  *sx = ((x - o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
+  *sy = y - o->c[i][1];
+  *sz = z - o->c[i][2];
+  if (o->p.geometry == ORA_SLAB) *sz = ((*sz) % o->p.nz + o->p.nz) % o->p.nz;
+}
+
+/* Bouzidi fraction: distance from the fluid node P to the circular wall
+ * along -c (in units of |c|, transverse plane only since the tube axis is x).
+ * Solves |P - s C|^2 = R^2 for the root s in (0, 1]. */
+static real bouzidi_q(const ora_ctx *o, int y, int z, int i) {
+  real py = (real)y - (real)o->p.tube_cy, pz = (real)z - (real)o->p.tube_cz;
+  real cy = (real)o->c[i][1], cz = (real)o->c[i][2];
+  real a = cy * cy + cz * cz;
+  real b = -2 * (py * cy + pz * cz);
+  real cc = py * py + pz * pz - (real)o->p.tube_radius * (real)o->p.tube_radius;
+  return (-b + R_SQRT(b * b - 4 * a * cc)) / (2 * a);
+}
+
+/* ------------------------------------------------------------- life cycle */
+
+void ora_destroy(ora_ctx *o);
+
+int ora_create(const ora_params *p, ora_ctx **out) {
+  ora_ctx *o;
+  int x, y, z, i;
+  *out = NULL;
+  if (!(p->lattice == 9 || p->lattice == 19)) return ORA_EINVAL;
+  if (p->geometry < 0 || p->geometry > 2) return ORA_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return ORA_EINVAL;
+  if (p->lattice == 9 && (p->nz != 1 || p->geometry != ORA_SLAB)) return ORA_EINVAL;
+  if (!(p->tau > 0.5)) return ORA_EINVAL;
+  if (p->wall_velocity_top != 0.0 && p->geometry == ORA_TUBE) return ORA_EINVAL;
+  o = (ora_ctx *)calloc(1, sizeof(ora_ctx));
+  if (!o) return ORA_ENOMEM;
+  o->p = *p;
+  set_lattice(o);
+  o->ncell = (long)p->nx * p->ny * p->nz;
+  o->fluid = (unsigned char *)calloc(o->ncell, 1);
+  o->wall_id = (long *)malloc(sizeof(long) * o->ncell);
+  o->r = (real *)calloc(o->ncell, sizeof(real));
+  o->qlink = (real *)calloc(o->ncell * 19, sizeof(real));
+  o->g = (real *)calloc(o->ncell * o->q, sizeof(real));
+  o->gn = (real *)calloc(o->ncell * o->q, sizeof(real));
+  if (!o->fluid || !o->wall_id || !o->r || !o->qlink || !o->g || !o->gn) {
+    ora_destroy(o);
+    return ORA_ENOMEM;
+  }
+  /* classify cells and wall links; wall nodes numbered by increasing linear
+   * index x + nx (y + ny z) */
+  o->nwall = 0;
+  o->nfluid = 0;
+  for (z = 0; z < p->nz; z++)
+    for (y = 0; y < p->ny; y++)
+      for (x = 0; x < p->nx; x++) {
+        long n = cell(o, x, y, z);
+        int is_wall = 0;
+        o->wall_id[n] = -1;
+        if (is_solid(o, x, y, z)) continue;
+        o->fluid[n] = 1;
+        o->nfluid++;
+        for (i = 0; i < o->q; i++) {
+          int sx, sy, sz;
+          upstream(o, x, y, z, i, &sx, &sy, &sz);
+          if (is_solid(o, sx, sy, sz)) {
+            is_wall = 1;
+            o->qlink[n * 19 + i] =
+                p->geometry == ORA_TUBE ? bouzidi_q(o, y, z, i) : (real)0.5;
+          }
+        }
+        if (is_wall) {
+          o->wall_id[n] = o->nwall++;
+          o->r[n] = 1; /* default: no-slip bounce-back */
+        }
+      }
+  *out = o;
+  return ORA_OK;
+}
+
+void ora_destroy(ora_ctx *o) {
+  if (!o) return;
+  free(o->fluid);
+  free(o->wall_id);
+  free(o->r);
+  free(o->qlink);
+  free(o->g);
+  free(o->gn);
+  free(o);
+}
+
+long ora_wall_count(const ora_ctx *o) { return o->nwall; }
+long ora_fluid_count(const ora_ctx *o) { return o->nfluid; }
+long ora_step_count(const ora_ctx *o) { return o->step; }
+
+/* xyz: 3*nwall ints (x, y, z) in canonical order */
+void ora_wall_coords(const ora_ctx *o, int32_t *xyz) {
+  int x, y, z;
+  for (z = 0; z < o->p.nz; z++)
+    for (y = 0; y < o->p.ny; y++)
+      for (x = 0; x < o->p.nx; x++) {
+        long k = o->wall_id[cell(o, x, y, z)];
+        if (k >= 0) {
+          xyz[3 * k] = x;
+          xyz[3 * k + 1] = y;
+          xyz[3 * k + 2] = z;
+        }
+      }
+}
+
+/* Bouzidi fractions of the wall links: out[k*19 + i] for wall node k */
+void ora_wall_links(const ora_ctx *o, double *out) {
+  long n;
+  int i;
+  for (n = 0; n < o->ncell; n++) {
+    long k = o->wall_id[n];
+    if (k < 0) continue;
+    for (i = 0; i < 19; i++) out[k * 19 + i] = (double)o->qlink[n * 19 + i];
+  }
+}
+
+/* lambda in lattice units per wall node (canonical order); +inf = no slip.
+ * r = 3 lambda / (1 + 3 lambda) makes the slip length nu / lambda. */
+int ora_set_friction(ora_ctx *o, const double *lambda) {
+  long n;
+  for (n = 0; n < o->ncell; n++) {
+    long k = o->wall_id[n];
+    if (k < 0) continue;
+    if (!(lambda[k] >= 0)) return ORA_EINVAL; /* rejects NaN and < 0 */
+  }
+  for (n = 0; n < o->ncell; n++) {
+    long k = o->wall_id[n];
+    real l;
+    if (k < 0) continue;
+    l = (real)lambda[k];
+    o->r[n] = isinf(lambda[k]) ? (real)1 : 3 * l / (1 + 3 * l);
+  }
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------ the update */
+
+/* Value of the incoming population i at fluid cell (x,y,z) whose upstream
+ * point is solid: the Navier-slip wall rule. */
+static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
+                       int i, int sy) {
+  long n = cell(o, x, y, z);
+  int ib = o->opp[i];
+  real bb, qv;
+  /* moving top wall (Couette check): bounce-back plus the momentum the wall
+   * hands over, 6 w_i rho0 (c_i . U) with U along x */
+  if (o->p.wall_velocity_top != 0.0 && sy >= o->p.ny)
+    return g[(long)ib * o->ncell + n] +
+           6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
+               (real)o->p.wall_velocity_top;
+  qv = o->qlink[n * 19 + i];
+  if (o->p.geometry != ORA_TUBE) {
+    bb = g[(long)ib * o->ncell + n]; /* half-way bounce-back */
+  } else if (qv < (real)0.5) {
+    /* wall closer than half a link: interpolate between this node's and the
+     * next node's (along +c_i) populations heading into the wall */
+    int xn = ((x + o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
+    int yn = y + o->c[i][1], zn = z + o->c[i][2];
+    if (is_solid(o, xn, yn, zn))
+      bb = g[(long)ib * o->ncell + n];
+    else
+      bb = 2 * qv * g[(long)ib * o->ncell + n] +
+           (1 - 2 * qv) * g[(long)ib * o->ncell + cell(o, xn, yn, zn)];
+  } else {
+    /* wall farther than half a link: interpolate between the bounced
+     * population and this node's own outgoing population i */
+    bb = g[(long)ib * o->ncell + n] / (2 * qv) +
+         (2 * qv - 1) / (2 * qv) * g[(long)i * o->ncell + n];
+  }
+  return o->r[n] * bb + (1 - o->r[n]) * g[(long)o->sig[i] * o->ncell + n];
+}
+
+/* steps 1 and 2: gather the populations a collision at (x,y,z) sees */
+static void gather(const ora_ctx *o, const real *g, int x, int y, int z,
+                   real *df) {
+  int i;
+  for (i = 0; i < o->q; i++) {
+    int sx, sy, sz;
+    upstream(o, x, y, z, i, &sx, &sy, &sz);
+    if (is_solid(o, sx, sy, sz))
+      df[i] = wall_value(o, g, x, y, z, i, sy);
+    else
+      df[i] = g[(long)i * o->ncell + cell(o, sx, sy, sz)];
+  }
+}
+
+static void moments(const ora_ctx *o, const real *df, real *rho, real u[3],
+                    real j[3]) {
+  int i, a;
+  real drho = 0;
+  for (a = 0; a < 3; a++) j[a] = 0;
+  for (i = 0; i < o->q; i++) {
+    drho += df[i];
+    for (a = 0; a < 3; a++) j[a] += df[i] * (real)o->c[i][a];
+  }
+  for (a = 0; a < 3; a++) j[a] += (real)o->p.force[a] / 2;
+  *rho = (real)o->p.rho0 + drho;
+  for (a = 0; a < 3; a++) u[a] = j[a] / *rho;
+}
+
+void ora_step(ora_ctx *o, long nsteps) {
+  long s;
+  int x, y, z, i, a;
+  real tau = (real)o->p.tau, rho0 = (real)o->p.rho0;
+  real F[3];
+  for (a = 0; a < 3; a++) F[a] = (real)o->p.force[a];
+  for (s = 0; s < nsteps; s++) {
+    for (z = 0; z < o->p.nz; z++)
+      for (y = 0; y < o->p.ny; y++)
+        for (x = 0; x < o->p.nx; x++) {
+          long n = cell(o, x, y, z);
+          real df[19], rho, u[3], j[3], usq, uF;
+          if (!o->fluid[n]) continue;
+          gather(o, o->g, x, y, z, df);
+          moments(o, df, &rho, u, j);
+          usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+          uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+          for (i = 0; i < o->q; i++) {
+            real cu = 0, cF = 0, feq, src;
+            for (a = 0; a < 3; a++) {
+              cu += (real)o->c[i][a] * u[a];
+              cF += (real)o->c[i][a] * F[a];
+            }
+            feq = o->w[i] *
+                  ((rho - rho0) + rho * (3 * cu + (real)4.5 * cu * cu -
+                                         (real)1.5 * usq));
+            src = (1 - 1 / (2 * tau)) * o->w[i] * (3 * (cF - uF) + 9 * cu * cF);
+            o->gn[(long)i * o->ncell + n] = df[i] - (df[i] - feq) / tau + src;
+          }
+        }
+    {
+      real *t = o->g;
+      o->g = o->gn;
+      o->gn = t;
+    }
+    o->step++;
+  }
+}
+
+/* Fields after the current step: rho, ux, uy, uz per cell (dense box, zero
+ * on solid cells).  Any pointer may be NULL. */
+void ora_fields(const ora_ctx *o, double *rho, double *ux, double *uy,
+                double *uz) {
+  int x, y, z;
+  for (z = 0; z < o->p.nz; z++)
+    for (y = 0; y < o->p.ny; y++)
+      for (x = 0; x < o->p.nx; x++) {
+        long n = cell(o, x, y, z);
+        real df[19], r, u[3], j[3];
+        if (!o->fluid[n]) {
+          if (rho) rho[n] = 0;
+          if (ux) ux[n] = 0;
+          if (uy) uy[n] = 0;
+          if (uz) uz[n] = 0;
+          continue;
+        }
+        gather(o, o->g, x, y, z, df);
+        moments(o, df, &r, u, j);
+        if (rho) rho[n] = (double)r;
+        if (ux) ux[n] = (double)u[0];
+        if (uy) uy[n] = (double)u[1];
+        if (uz) uz[n] = (double)u[2];
+      }
+}
+
+/* out[0] = flux Q = (1/nx) sum_fluid rho u_x ; out[1] = mass M = sum rho ;
+ * out[2] = sum (rho - rho0), the mass deviation, summed on its own so that
+ * drift is visible below the rounding of M itself. */
+void ora_invariants(const ora_ctx *o, double *out) {
+  int x, y, z, i;
+  real q = 0, dm = 0;
+  for (z = 0; z < o->p.nz; z++)
+    for (y = 0; y < o->p.ny; y++)
+      for (x = 0; x < o->p.nx; x++) {
+        long n = cell(o, x, y, z);
+        real df[19], r, u[3], j[3];
+        if (!o->fluid[n]) continue;
+        gather(o, o->g, x, y, z, df);
+        moments(o, df, &r, u, j);
+        q += j[0];
+        for (i = 0; i < o->q; i++) dm += df[i];
+      }
+  out[0] = (double)(q / (real)o->p.nx);
+  out[1] = (double)((real)o->nfluid * (real)o->p.rho0 + dm);
+  out[2] = (double)dm;
+}
+
+/* populations g_i (shifted, post-collision) of the current state, dense box,
+ * layout [i][z][y][x] in double */
+void ora_get_populations(const ora_ctx *o, double *out) {
+  long k, n = o->ncell * o->q;
+  for (k = 0; k < n; k++) out[k] = (double)o->g[k];
+}
+
+void ora_set_populations(ora_ctx *o, const double *in, long step) {
+  long k, n = o->ncell * o->q;
+  for (k = 0; k < n; k++) o->g[k] = (real)in[k];
+  o->step = step;
+}
+
+/* ------------------------------------------------- friction quadrature */
+
+/* Spectral parameters (units hbar = k_B = 1, lengths in units of the gap) */
+typedef struct {
+  double T, omega0, gamma_s, omega_l, gamma_l, a_l, d;
+  int nq, nw;
+  double q_max, w_max;
+  double lambda_target;
+  int dispersion; /* 1: omega_p^2 = Omega^2 q d ; 0: omega_p^2 = Omega^2 */
+} ora_spectral;
+
+/* imaginary part of the Lorentzian liquid response at frequency w */
+double ora_img_l(const ora_spectral *s, double w) {
+  real wl2 = (real)s->omega_l * (real)s->omega_l, ww = (real)w;
+  real den = (wl2 - ww * ww) * (wl2 - ww * ww) +
+             (real)s->gamma_l * (real)s->gamma_l * ww * ww;
+  return (double)((real)s->a_l * wl2 * (real)s->gamma_l * ww / den);
+}
+
+/* imaginary part of the Drude-like solid response with plasmon frequency
+ * omega_p(q)^2 = Omega^2 q d (2-D plasmon dispersion) at wavevector q */
+double ora_img_s(const ora_spectral *s, double Omega, double q, double w) {
+  real wp2 = (real)Omega * (real)Omega *
+             (s->dispersion ? (real)q * (real)s->d : (real)1);
+  real ww = (real)w;
+  real den = (wp2 - ww * ww) * (wp2 - ww * ww) +
+             (real)s->gamma_s * (real)s->gamma_s * ww * ww;
+  return (double)(wp2 * (real)s->gamma_s * ww / den);
+}
+
+/* raw friction sum for one plasmon frequency Omega:
+ *   C sum_a sum_b dq dw q^3 e^{-2 q d} Im g_s Im g_l / sinh^2(w / 2T),
+ *   C = 1 / (8 pi^2 T), midpoint grids on (0, q_max) and (0, w_max). */
+double ora_friction_raw(const ora_spectral *s, double Omega) {
+  real pi = (real)3.14159265358979323846264338327950288L;
+  real C = 1 / (8 * pi * pi * (real)s->T);
+  real dq = (real)s->q_max / s->nq, dw = (real)s->w_max / s->nw;
+  real sum = 0;
+  int a, b;
+  for (a = 0; a < s->nq; a++) {
+    real q = ((real)a + (real)0.5) * dq;
+    real kq = q * q * q * R_EXP(-2 * q * (real)s->d);
+    for (b = 0; b < s->nw; b++) {
+      real w = ((real)b + (real)0.5) * dw;
+      real sh = R_SINH(w / (2 * (real)s->T));
+      real wp2 = (real)Omega * (real)Omega *
+                 (s->dispersion ? q * (real)s->d : (real)1);
+      real ims = wp2 * (real)s->gamma_s * w /
+                 ((wp2 - w * w) * (wp2 - w * w) +
+                  (real)s->gamma_s * (real)s->gamma_s * w * w);
+      real wl2 = (real)s->omega_l * (real)s->omega_l;
+      real iml = (real)s->a_l * wl2 * (real)s->gamma_l * w /
+                 ((wl2 - w * w) * (wl2 - w * w) +
+                  (real)s->gamma_l * (real)s->gamma_l * w * w);
+      sum += dq * dw * kq * ims * iml / (sh * sh);
+    }
+  }
+  return (double)(C * sum);
+}
+
+/* per wall node: raw[k] (may be NULL) and lattice friction
+ *   lambda_k = lambda_target * raw(Omega_k) / raw(omega0) */
+void ora_friction(const ora_spectral *s, const double *Omega, long n,
+                  double *raw, double *lambda_lat) {
+  double ref = ora_friction_raw(s, s->omega0);
+  long k;
+  for (k = 0; k < n; k++) {
+    double v = ora_friction_raw(s, Omega[k]);
+    if (raw) raw[k] = v;
+    if (lambda_lat) lambda_lat[k] = (double)((real)s->lambda_target * (real)v / (real)ref);
+  }
+}
+
+int ora_sizeof_real(void) { return (int)sizeof(real); }
