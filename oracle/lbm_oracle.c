@@ -42,7 +42,8 @@
  *   1. pull:   df_i = g_i(x - c_i), periodic in x (and z for the slab);
  *              if x - c_i is solid, the wall rule gives df_i instead;
  *   2. moments: rho = rho0 + sum df_i;  rho u = sum df_i c_i + F/2;
- *   3. dfeq_i = w_i [ (rho - rho0) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u) ];
+ *   3. dfeq_i = w_i [ (rho - rho0) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u) ],
+ *      with rho - rho0 taken as the summed deviation sum df_i;
  *   4. g_i(x, n+1) = df_i - (df_i - dfeq_i)/tau
  *                    + (1 - 1/(2 tau)) w_i [ 3 (c_i - u) + 9 (c_i.u) c_i ].F
  *   Reported rho, u "after n steps" are the moments of step 2 built from g(n).
@@ -366,24 +367,28 @@ static void gather(const ora_ctx *o, const real *g, int x, int y, int z,
   }
 }
 
-static void moments(const ora_ctx *o, const real *df, real *rho, real u[3],
-                    real j[3]) {
+/* drho = sum df is the density deviation rho - rho0 itself; it is kept as
+ * summed rather than recovered as (rho0 + drho) - rho0, which would round it
+ * to the spacing of numbers near rho0 and undo the point of storing
+ * deviations. */
+static void moments(const ora_ctx *o, const real *df, real *drho, real *rho,
+                    real u[3], real j[3]) {
   int i, a;
-  real drho = 0;
+  *drho = 0;
   for (a = 0; a < 3; a++) j[a] = 0;
   for (i = 0; i < o->q; i++) {
-    drho += df[i];
+    *drho += df[i];
     for (a = 0; a < 3; a++) j[a] += df[i] * (real)o->c[i][a];
   }
   for (a = 0; a < 3; a++) j[a] += (real)o->p.force[a] / 2;
-  *rho = (real)o->p.rho0 + drho;
+  *rho = (real)o->p.rho0 + *drho;
   for (a = 0; a < 3; a++) u[a] = j[a] / *rho;
 }
 
 void ora_step(ora_ctx *o, long nsteps) {
   long s;
   int x, y, z, i, a;
-  real tau = (real)o->p.tau, rho0 = (real)o->p.rho0;
+  real tau = (real)o->p.tau;
   real F[3];
   for (a = 0; a < 3; a++) F[a] = (real)o->p.force[a];
   for (s = 0; s < nsteps; s++) {
@@ -391,10 +396,10 @@ void ora_step(ora_ctx *o, long nsteps) {
       for (y = 0; y < o->p.ny; y++)
         for (x = 0; x < o->p.nx; x++) {
           long n = cell(o, x, y, z);
-          real df[19], rho, u[3], j[3], usq, uF;
+          real df[19], drho, rho, u[3], j[3], usq, uF;
           if (!o->fluid[n]) continue;
           gather(o, o->g, x, y, z, df);
-          moments(o, df, &rho, u, j);
+          moments(o, df, &drho, &rho, u, j);
           usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
           uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
           for (i = 0; i < o->q; i++) {
@@ -404,7 +409,7 @@ void ora_step(ora_ctx *o, long nsteps) {
               cF += (real)o->c[i][a] * F[a];
             }
             feq = o->w[i] *
-                  ((rho - rho0) + rho * (3 * cu + (real)4.5 * cu * cu -
+                  (drho + rho * (3 * cu + (real)4.5 * cu * cu -
                                          (real)1.5 * usq));
             src = (1 - 1 / (2 * tau)) * o->w[i] * (3 * (cF - uF) + 9 * cu * cF);
             o->gn[(long)i * o->ncell + n] = df[i] - (df[i] - feq) / tau + src;
@@ -428,7 +433,7 @@ void ora_fields(const ora_ctx *o, double *rho, double *ux, double *uy,
     for (y = 0; y < o->p.ny; y++)
       for (x = 0; x < o->p.nx; x++) {
         long n = cell(o, x, y, z);
-        real df[19], r, u[3], j[3];
+        real df[19], dr, r, u[3], j[3];
         if (!o->fluid[n]) {
           if (rho) rho[n] = 0;
           if (ux) ux[n] = 0;
@@ -437,7 +442,7 @@ void ora_fields(const ora_ctx *o, double *rho, double *ux, double *uy,
           continue;
         }
         gather(o, o->g, x, y, z, df);
-        moments(o, df, &r, u, j);
+        moments(o, df, &dr, &r, u, j);
         if (rho) rho[n] = (double)r;
         if (ux) ux[n] = (double)u[0];
         if (uy) uy[n] = (double)u[1];
@@ -449,18 +454,18 @@ void ora_fields(const ora_ctx *o, double *rho, double *ux, double *uy,
  * out[2] = sum (rho - rho0), the mass deviation, summed on its own so that
  * drift is visible below the rounding of M itself. */
 void ora_invariants(const ora_ctx *o, double *out) {
-  int x, y, z, i;
+  int x, y, z;
   real q = 0, dm = 0;
   for (z = 0; z < o->p.nz; z++)
     for (y = 0; y < o->p.ny; y++)
       for (x = 0; x < o->p.nx; x++) {
         long n = cell(o, x, y, z);
-        real df[19], r, u[3], j[3];
+        real df[19], dr, r, u[3], j[3];
         if (!o->fluid[n]) continue;
         gather(o, o->g, x, y, z, df);
-        moments(o, df, &r, u, j);
+        moments(o, df, &dr, &r, u, j);
         q += j[0];
-        for (i = 0; i < o->q; i++) dm += df[i];
+        dm += dr;
       }
   out[0] = (double)(q / (real)o->p.nx);
   out[1] = (double)((real)o->nfluid * (real)o->p.rho0 + dm);

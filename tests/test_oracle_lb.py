@@ -159,7 +159,8 @@ def test_channel_profile_symmetric_and_x_uniform():
     # bitwise x-uniform: every column does identical arithmetic
     assert np.all(ux[0] == ux[0, :, :1])
     prof = ux[0, :, 0]
-    assert np.max(np.abs(prof - prof[::-1])) < 1e-15 * prof.max()
+    # mirror pairs are summed in different orders: a few ulps, not bitwise
+    assert np.max(np.abs(prof - prof[::-1])) < 1e-14 * prof.max()
 
 
 def test_x_uniform_friction_gives_bitwise_x_uniform_duct():
