@@ -1,0 +1,188 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice-Boltzmann nanochannel library
+ * (liblbm.so).  Hot path of the Keldysh-lattice-Boltzmann method of
+ * arXiv 2403.15768: water in a nanochannel (Sec. 2) as one lattice-Boltzmann
+ * population set (Sec. 4), driven by a bulk pressure-gradient force (Eq. 2),
+ * closed at the liquid/solid interface by a friction wall whose per-node
+ * coefficient is the linear drag of Eq. 5 / Eq. 26, with periodic inlet and
+ * outlet (Sec. 4.2).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns lbm_status (0 = LBM_OK).  Nothing aborts, throws
+ *    or prints.  lbm_last_error() describes the last failure of a context.
+ *  - Units are lattice units (dx = dt = 1).  The paper's mapping dx = 1 nm,
+ *    dt = 1 ps (Sec. 6) is the caller's business.
+ *  - Device memory is owned by the caller: lbm_create() borrows an arena of
+ *    lbm_footprint() bytes (256-byte aligned) and never frees it.  Host
+ *    arrays are owned by the caller and only touched during the call.
+ *  - A context is used from one host thread and runs on the HIP stream given
+ *    at creation.  lbm_step() and the kernel part of lbm_set_* are
+ *    asynchronous; device errors are latched and returned by the next
+ *    synchronising call (lbm_sync, lbm_invariants, lbm_flux, lbm_mass,
+ *    lbm_get_*, lbm_run_to_steady).
+ *  - Population order: D2Q9 uses the paper's numbering beside Eqs. 18-20
+ *    (0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-));
+ *    D3Q19: 0 rest, 1..6 = +x,-x,+y,-y,+z,-z, 7..18 = (+,+,0), (-,-,0),
+ *    (+,-,0), (-,+,0), (+,0,+), (-,0,-), (+,0,-), (-,0,+), (0,+,+), (0,-,-),
+ *    (0,+,-), (0,-,+).
+ *  - Dense host fields are laid out [z][y][x] (x fastest), populations
+ *    [i][z][y][x].  Wall nodes are numbered in increasing linear index
+ *    x + nx (y + ny z) ("canonical order").
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* bad argument; nothing changed */
+  LBM_ENOMEM = -2,    /* arena too small */
+  LBM_EDEVICE = -3,   /* a HIP call failed (message in lbm_last_error) */
+  LBM_ENOTCONV = -4,  /* run_to_steady reached max_steps */
+  LBM_EDIVERGED = -5, /* NaN/Inf in the flux or mass */
+  LBM_ESTATE = -6     /* call not valid in the context's current state */
+} lbm_status;
+
+typedef enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 } lbm_lattice;
+
+/* Storage and arithmetic: F64 stores and computes in double; F32 stores
+ * float and computes in double (FP32 arithmetic would feed the rounding error
+ * of the computed moments back into every collision as a momentum source,
+ * which near steady state accumulates over the slowest viscous time to
+ * ~1e-4 of the flow); F16S stores half-precision deviations from the rest
+ * equilibrium and computes in float.  Flux/mass reductions are double in
+ * every mode. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_precision;
+
+/* SLAB: walls half a link below y = 0 and above y = ny-1, z periodic (D2Q9
+ *       requires SLAB with nz = 1).
+ * DUCT: walls on both y and both z faces, half a link outside the box.
+ * TUBE: circular wall of radius tube_radius around the x axis through
+ *       (tube_cy, tube_cz); cells with (y-cy)^2 + (z-cz)^2 < R^2 are fluid;
+ *       interpolated (Bouzidi) bounce-back at the curved wall.
+ * x is periodic in every geometry (inlet/outlet option 1 of Sec. 4.2). */
+typedef enum { LBM_SLAB = 0, LBM_DUCT = 1, LBM_TUBE = 2 } lbm_geometry;
+
+typedef struct {
+  int lattice;   /* lbm_lattice */
+  int precision; /* lbm_precision */
+  int geometry;  /* lbm_geometry */
+  int nx, ny, nz;
+  double tube_radius, tube_cy, tube_cz; /* TUBE only */
+  double tau;                           /* BGK relaxation time, > 0.5 */
+  double rho0;                          /* reference density */
+  double force[3];          /* body-force density (the bulk force of Eq. 2) */
+  double wall_velocity_top; /* != 0: the y = ny-1/2 wall of SLAB/DUCT moves
+                               along x at this speed as a no-slip wall
+                               (Couette check); 0 otherwise */
+} lbm_params;
+
+/* Synthetic surface-response spectra of the friction quadrature (units
+ * hbar = k_B = 1, lengths in units of the gap d):
+ *   raw(Omega) = C sum_a sum_b dq dw q_a^3 e^{-2 q_a d}
+ *                  Im g_s(q_a, w_b; Omega) Im g_l(w_b) / sinh^2(w_b / 2T),
+ *   C = 1/(8 pi^2 T), q_a = (a+1/2) dq, dq = q_max/nq, w_b = (b+1/2) dw,
+ *   dw = w_max/nw,
+ *   Im g_l(w) = a_l w_l^2 gamma_l w / ((w_l^2 - w^2)^2 + gamma_l^2 w^2),
+ *   Im g_s(q,w;Omega) = P gamma_s w / ((P - w^2)^2 + gamma_s^2 w^2),
+ *   P = Omega^2 q d (dispersion = 1) or Omega^2 (dispersion = 0).
+ * Lattice friction of node k: lambda_k = lambda_target raw(Omega_k)/raw(omega0).
+ * Stand-in for the friction coefficients of the Keldysh analysis (appendix,
+ * Eq. 26), which the paper does not give in closed form. */
+typedef struct {
+  double T, omega0, gamma_s, omega_l, gamma_l, a_l, d;
+  int nq, nw;
+  double q_max, w_max;
+  double lambda_target;
+  int dispersion;
+} lbm_spectral;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque */
+
+/* Device bytes lbm_create() needs for these parameters (LBM_EINVAL on bad
+ * parameters). */
+lbm_status lbm_footprint(const lbm_params *p, size_t *bytes);
+
+/* Set up a channel: classify cells and wall links (Sec. 4.2 boundary sites),
+ * carve the arena, set no-slip walls (lambda = +inf) and the rest state
+ * g_i = 0 (f_i = w_i rho0).  arena: device pointer, >= footprint bytes,
+ * 256-byte aligned, owned by the caller.  hip_stream: a hipStream_t (NULL =
+ * default stream). */
+lbm_status lbm_create(const lbm_params *p, void *arena, size_t arena_bytes,
+                      void *hip_stream, lbm_ctx **out);
+void lbm_destroy(lbm_ctx *ctx); /* never frees the arena */
+
+lbm_status lbm_fluid_count(const lbm_ctx *ctx, size_t *n);
+lbm_status lbm_wall_count(const lbm_ctx *ctx, size_t *n);
+/* xyz: host, 3*wall_count int32 (x, y, z) per wall node, canonical order */
+lbm_status lbm_wall_coords(const lbm_ctx *ctx, int32_t *xyz);
+/* links: host, wall_count * Q doubles: fraction q in (0, 1] of the link from
+ * the node to the wall along -c_i for every wall link (0.5 on planar walls),
+ * 0 where the upstream point is fluid. */
+lbm_status lbm_wall_links(const lbm_ctx *ctx, double *links);
+
+/* Friction per wall node, lattice units, canonical order: lambda >= 0,
+ * +inf = no slip (bounce-back, end of Sec. 4.2), 0 = free slip.  The wall
+ * rule mixes bounce-back and transverse reversal with r = 3l/(1+3l), which
+ * gives slip length nu/lambda on planar walls.  on_device != 0: lambda is a
+ * device pointer.  n must equal wall_count.  Negative or NaN -> LBM_EINVAL
+ * (nothing changed).  Synchronous. */
+lbm_status lbm_set_friction(lbm_ctx *ctx, const double *lambda, size_t n,
+                            int on_device);
+/* Run the friction quadrature on the GPU for every wall node (Omega: the
+ * node's plasmon frequency, canonical order, n = wall_count) and set the wall
+ * from the result.  Host or device Omega.  Synchronous. */
+lbm_status lbm_set_friction_spectral(lbm_ctx *ctx, const lbm_spectral *sp,
+                                     const double *omega, size_t n,
+                                     int on_device);
+/* Current friction: lambda (lattice units) and, after a spectral set, the raw
+ * quadrature sums (raw has wall_count + 1 entries, the last being
+ * raw(omega0)); either pointer may be NULL.  Host arrays. */
+lbm_status lbm_get_friction(lbm_ctx *ctx, double *lambda, double *raw);
+
+/* Advance nsteps >= 0 time steps (asynchronous). */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+/* Step in chunks of check_every until |Q(n) - Q(n - check_every)| <
+ * rel_tol |Q(n)| (Q = flux), or max_steps (LBM_ENOTCONV) or a NaN/Inf
+ * (LBM_EDIVERGED).  steps_taken may be NULL.  Synchronous. */
+lbm_status lbm_run_to_steady(lbm_ctx *ctx, double rel_tol, int64_t check_every,
+                             int64_t max_steps, int64_t *steps_taken);
+
+/* Invariants of the current state (the moments the next collision sees):
+ * out[0] = flux Q = (1/nx) sum_fluid rho u_x, out[1] = mass M = sum_fluid rho,
+ * out[2] = sum_fluid (rho - rho0).  Deterministic FP64 reductions.
+ * Synchronous. */
+lbm_status lbm_invariants(lbm_ctx *ctx, double out[3]);
+lbm_status lbm_flux(lbm_ctx *ctx, double *q);
+lbm_status lbm_mass(lbm_ctx *ctx, double *m);
+/* which: 0 rho, 1 u_x, 2 u_y, 3 u_z; host_out: nz*ny*nx doubles, 0 on solid
+ * cells.  Synchronous. */
+lbm_status lbm_get_field(lbm_ctx *ctx, int which, double *host_out);
+/* Shifted post-collision populations g_i = f_i - w_i rho0 as doubles,
+ * host_out: Q*nz*ny*nx ([i][z][y][x]), 0 on solid cells.  Synchronous. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *host_out);
+
+/* Checkpoint: the populations in storage precision plus the step counter.
+ * lbm_state_bytes gives the size; get/set are synchronous; set restores a
+ * state bit for bit. */
+lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+lbm_status lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes,
+                         int64_t *step);
+lbm_status lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes,
+                         int64_t step);
+
+lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
+lbm_status lbm_sync(lbm_ctx *ctx);               /* waits, surfaces errors */
+const char *lbm_last_error(const lbm_ctx *ctx);  /* owned by ctx */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

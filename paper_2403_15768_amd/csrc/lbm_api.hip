@@ -1,0 +1,713 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// Owns no device memory: every buffer is carved out of the caller's arena.
+// Geometry set-up (which cells are fluid, which links end on the wall, the
+// interpolated bounce-back coefficients) runs once per context on the host;
+// everything per step runs in the kernels of lbm_kernels.hip on the
+// context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_launch.h"
+
+using lbm::ColInfo;
+using lbm::StepArgs;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kGraphSteps = 64;  // steps per captured graph (even: keeps buffer parity)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Plan {
+  int Q = 0, prec = 0;
+  size_t ssize = 0, wsize = 0;  // storage bytes, wall-table bytes per value
+  int nx = 0, nxp = 0, ny = 0, nz = 0;
+  int64_t ncolbox = 0, stride = 0;
+  std::vector<int32_t> active;     // fluid column ids, increasing
+  std::vector<ColInfo> colinfo;    // per box column
+  std::vector<int32_t> wallcols;   // column id of each wall column, increasing
+  std::vector<double> linkq;       // [wallcol][Q] wall fraction (0: no wall link)
+  std::vector<double> bzc;         // [wallcol][Q][2] interpolation coefficients b, c (TUBE)
+  int64_t nfluid = 0, nwall = 0;
+  int bx = 0, segs = 0;
+  int64_t nblocks = 0;
+  bool bouz = false;
+  // arena offsets
+  size_t off_pop[2] = {0, 0}, pop_bytes = 0;
+  size_t off_active = 0, off_colinfo = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
+         off_partials = 0, off_out = 0, off_flag = 0, total = 0;
+};
+
+int lat_c(int Q, int i, int a) {
+  if (Q == 9) return a == 0 ? lbm::D2Q9::cx[i] : (a == 1 ? lbm::D2Q9::cy[i] : 0);
+  return a == 0 ? lbm::D3Q19::cx[i] : (a == 1 ? lbm::D3Q19::cy[i] : lbm::D3Q19::cz[i]);
+}
+
+// Positive root s of |P - s C|^2 = R^2 with P inside and P - C outside the
+// circle (the fraction of the link from the fluid node to the wall).
+double wall_fraction(double py, double pz, double cy, double cz, double R) {
+  const double a = cy * cy + cz * cz;
+  const double b = -2.0 * (py * cy + pz * cz);
+  const double c = py * py + pz * pz - R * R;  // < 0
+  const double disc = std::sqrt(b * b - 4.0 * a * c);
+  return b >= 0.0 ? (2.0 * c) / (-b - disc) : (-b + disc) / (2.0 * a);
+}
+
+lbm_status validate(const lbm_params* p, std::string* err) {
+  auto fail = [&](const char* m) {
+    if (err) *err = m;
+    return LBM_EINVAL;
+  };
+  if (!p) return fail("null parameters");
+  if (p->lattice != 9 && p->lattice != 19) return fail("lattice must be 9 or 19");
+  if (p->precision < 0 || p->precision > 2) return fail("bad precision");
+  if (p->geometry < 0 || p->geometry > 2) return fail("bad geometry");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("sizes must be >= 1");
+  if ((int64_t)p->ny * p->nz > (int64_t)1 << 28 || p->nx > (1 << 24)) return fail("box too large");
+  if (p->lattice == 9 && (p->nz != 1 || p->geometry != LBM_SLAB))
+    return fail("D2Q9 needs SLAB geometry with nz = 1");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail("tau must be finite and > 0.5");
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail("rho0 must be finite and > 0");
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(p->force[a])) return fail("force must be finite");
+  if (!std::isfinite(p->wall_velocity_top)) return fail("wall velocity must be finite");
+  if (p->wall_velocity_top != 0.0 && p->geometry == LBM_TUBE)
+    return fail("moving top wall needs SLAB or DUCT");
+  if (p->geometry == LBM_TUBE &&
+      (!(p->tube_radius > 0.0) || !std::isfinite(p->tube_cy) || !std::isfinite(p->tube_cz)))
+    return fail("tube needs radius > 0 and a finite centre");
+  return LBM_OK;
+}
+
+lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
+  lbm_status s = validate(p, err);
+  if (s != LBM_OK) return s;
+  Plan& pl = *P;
+  pl.Q = p->lattice;
+  pl.prec = p->precision;
+  pl.ssize = p->precision == LBM_F64 ? 8 : (p->precision == LBM_F32 ? 4 : 2);
+  // wall tables in the arithmetic type: double for F64 and F32 (FP32 storage,
+  // FP64 arithmetic), float for F16S
+  pl.wsize = p->precision == LBM_F16S ? 4 : 8;
+  pl.nx = p->nx;
+  pl.nxp = (p->nx + 63) / 64 * 64;
+  pl.ny = p->ny;
+  pl.nz = p->nz;
+  pl.ncolbox = (int64_t)p->ny * p->nz;
+  pl.stride = pl.ncolbox * pl.nxp;
+  pl.bouz = p->geometry == LBM_TUBE;
+  const bool slab = p->geometry == LBM_SLAB;
+
+  std::vector<unsigned char> fluid(pl.ncolbox, 1);
+  if (p->geometry == LBM_TUBE) {
+    const double R2 = p->tube_radius * p->tube_radius;
+    for (int z = 0; z < p->nz; z++)
+      for (int y = 0; y < p->ny; y++) {
+        const double dy = y - p->tube_cy, dz = z - p->tube_cz;
+        fluid[y + (int64_t)p->ny * z] = (dy * dy + dz * dz < R2) ? 1 : 0;
+      }
+  }
+  auto fluid_at = [&](int y, int z) {
+    if (slab) z = ((z % p->nz) + p->nz) % p->nz;
+    if (y < 0 || y >= p->ny || z < 0 || z >= p->nz) return false;
+    return fluid[y + (int64_t)p->ny * z] != 0;
+  };
+
+  pl.colinfo.assign(pl.ncolbox, ColInfo{-1, lbm::kSolidColumn});
+  pl.active.clear();
+  pl.wallcols.clear();
+  for (int z = 0; z < p->nz; z++)
+    for (int y = 0; y < p->ny; y++) {
+      const int64_t col = y + (int64_t)p->ny * z;
+      if (!fluid[col]) continue;
+      uint32_t mask = 0;
+      for (int i = 1; i < pl.Q; i++)
+        if (!fluid_at(y - lat_c(pl.Q, i, 1), z - lat_c(pl.Q, i, 2))) mask |= 1u << i;
+      ColInfo ci{-1, mask};
+      if (mask) {
+        ci.wallcol = (int32_t)pl.wallcols.size();
+        pl.wallcols.push_back((int32_t)col);
+      }
+      pl.colinfo[col] = ci;
+      pl.active.push_back((int32_t)col);
+    }
+  const int64_t nwc = (int64_t)pl.wallcols.size();
+  pl.linkq.assign(nwc * pl.Q, 0.0);
+  if (pl.bouz) pl.bzc.assign(nwc * pl.Q * 2, 0.0);
+  for (int64_t k = 0; k < nwc; k++) {
+    const int col = pl.wallcols[k];
+    const int y = col % p->ny, z = col / p->ny;
+    const uint32_t mask = pl.colinfo[col].mask;
+    for (int i = 0; i < pl.Q; i++) {
+      if (!(mask & (1u << i))) continue;
+      double q = 0.5;
+      if (pl.bouz)
+        q = wall_fraction(y - p->tube_cy, z - p->tube_cz, lat_c(pl.Q, i, 1), lat_c(pl.Q, i, 2),
+                          p->tube_radius);
+      pl.linkq[k * pl.Q + i] = q;
+      if (pl.bouz) {
+        // BB = a g_opp(x) + b g_opp(x + c_i) + c g_i(x) with a = 1 - b - c:
+        // q < 1/2: a = 2q, b = 1 - 2q; q >= 1/2: a = 1/(2q), c = (2q - 1)/(2q);
+        // q < 1/2 with no fluid node behind the link: half-way (b = c = 0)
+        double* co = &pl.bzc[(k * pl.Q + i) * 2];
+        if (q < 0.5 && fluid_at(y + lat_c(pl.Q, i, 1), z + lat_c(pl.Q, i, 2))) {
+          co[0] = 1.0 - 2.0 * q;
+          co[1] = 0.0;
+        } else if (q < 0.5) {
+          co[0] = 0.0;
+          co[1] = 0.0;
+        } else {
+          co[0] = 0.0;
+          co[1] = (2.0 * q - 1.0) / (2.0 * q);
+        }
+      }
+    }
+  }
+  if (pl.active.empty()) {
+    if (err) *err = "geometry has no fluid cell";
+    return LBM_EINVAL;
+  }
+  pl.nfluid = (int64_t)pl.active.size() * pl.nx;
+  pl.nwall = nwc * pl.nx;
+  pl.bx = std::min((pl.nx + 63) / 64 * 64, 512);
+  pl.segs = (pl.nx + pl.bx - 1) / pl.bx;
+  pl.nblocks = (int64_t)pl.active.size() * pl.segs;
+  if (pl.nblocks >= ((int64_t)1 << 31)) {
+    if (err) *err = "grid too large";
+    return LBM_EINVAL;
+  }
+
+  // every load the step kernel issues must land on a fluid column of the box
+  for (int32_t col : pl.active) {
+    const int y = col % p->ny, z = col / p->ny;
+    const ColInfo ci = pl.colinfo[col];
+    for (int i = 0; i < pl.Q; i++) {
+      const bool wall = ci.mask & (1u << i);
+      if (!wall && !fluid_at(y - lat_c(pl.Q, i, 1), z - lat_c(pl.Q, i, 2))) {
+        if (err) *err = "internal: fluid link to a solid column";
+        return LBM_EINVAL;
+      }
+      if (wall && pl.bouz && pl.bzc[((int64_t)ci.wallcol * pl.Q + i) * 2] != 0.0 &&
+          !fluid_at(y + lat_c(pl.Q, i, 1), z + lat_c(pl.Q, i, 2))) {
+        if (err) *err = "internal: interpolation node is solid";
+        return LBM_EINVAL;
+      }
+    }
+  }
+
+  size_t off = 0;
+  pl.pop_bytes = (size_t)pl.Q * pl.stride * pl.ssize;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  pl.off_pop[0] = take(pl.pop_bytes);
+  pl.off_pop[1] = take(pl.pop_bytes);
+  pl.off_active = take(pl.active.size() * sizeof(int32_t));
+  pl.off_colinfo = take(pl.colinfo.size() * sizeof(ColInfo));
+  pl.off_r = take((size_t)pl.nwall * pl.wsize);
+  pl.off_bz = take(pl.bouz ? (size_t)nwc * pl.Q * 2 * pl.wsize : 0);
+  pl.off_lambda = take((size_t)pl.nwall * sizeof(double));
+  pl.off_raw = take((size_t)(pl.nwall + 1) * sizeof(double));
+  pl.off_partials = take((size_t)pl.nblocks * 2 * sizeof(double));
+  pl.off_out = take(4 * sizeof(double));
+  pl.off_flag = take(4 * sizeof(int));
+  pl.total = off;
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  Plan pl;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  void* pop[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t step = 0;
+  StepArgs args{};
+  std::string err;
+  bool have_raw = false;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool graphs_ok = true;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(arena + off);
+  }
+  lbm_status fail(lbm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return s;
+  }
+  lbm_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBM_OK;
+    return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+};
+
+#define HIPCHK(ctx, call)                                    \
+  do {                                                       \
+    lbm_status _s = (ctx)->hip((call), #call);               \
+    if (_s != LBM_OK) return _s;                             \
+  } while (0)
+
+namespace {
+
+lbm_status upload(lbm_ctx* c, size_t off, const void* host, size_t bytes) {
+  if (bytes == 0) return LBM_OK;
+  HIPCHK(c, hipMemcpyAsync(c->arena + off, host, bytes, hipMemcpyHostToDevice, c->stream));
+  return LBM_OK;
+}
+
+lbm_status sync(lbm_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipGetLastError());
+  return LBM_OK;
+}
+
+void fill_args(lbm_ctx* c) {
+  const Plan& pl = c->pl;
+  StepArgs& a = c->args;
+  a.nx = pl.nx;
+  a.nxp = pl.nxp;
+  a.ny = pl.ny;
+  a.nz = pl.nz;
+  a.stride = pl.stride;
+  a.nactive = (int)pl.active.size();
+  a.bx = pl.bx;
+  a.segs = pl.segs;
+  a.slab = c->p.geometry == LBM_SLAB;
+  a.active = c->at<int32_t>(pl.off_active);
+  a.colinfo = c->at<ColInfo>(pl.off_colinfo);
+  a.rwall = c->at<void>(pl.off_r);
+  a.bz = pl.bouz ? c->at<void>(pl.off_bz) : nullptr;
+  a.rho0 = c->p.rho0;
+  a.omega = 1.0 / c->p.tau;
+  for (int i = 0; i < 3; i++) a.F[i] = c->p.force[i];
+  a.utop = c->p.wall_velocity_top;
+}
+
+template <typename W>
+std::vector<W> convert(const std::vector<double>& v) {
+  return std::vector<W>(v.begin(), v.end());
+}
+
+lbm_status upload_wall_r(lbm_ctx* c, const double* lambda_dev, int64_t n) {
+  int* flag = c->at<int>(c->pl.off_flag);
+  HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+  HIPCHK(c, lbm::launch_set_r(c->pl.prec, lambda_dev, n, c->at<void>(c->pl.off_r), flag, c->stream));
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  if (h) return c->fail(LBM_EINVAL, "friction must be >= 0 (NaN rejected)");
+  return LBM_OK;
+}
+
+lbm_status launch_one_step(lbm_ctx* c) {
+  HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], c->args,
+                             c->pl.bouz, c->stream));
+  c->cur = 1 - c->cur;
+  c->step++;
+  return LBM_OK;
+}
+
+// A graph of kGraphSteps chained step kernels starting from buffer `parity`.
+lbm_status build_graph(lbm_ctx* c, int parity) {
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipGraphCreate(&g, 0));
+  const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz);
+  hipGraphNode_t prev = nullptr;
+  // kernel arguments must outlive instantiation only; keep them on the stack
+  const void* srcs[2] = {c->pop[parity], c->pop[1 - parity]};
+  void* dsts[2] = {c->pop[1 - parity], c->pop[parity]};
+  StepArgs a = c->args;
+  for (int k = 0; k < kGraphSteps; k++) {
+    void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&a};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = dim3((unsigned)c->pl.nblocks);
+    kp.blockDim = dim3(c->pl.bx);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return c->hip(e, "hipGraphAddKernelNode");
+    }
+    prev = node;
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return c->hip(e, "hipGraphInstantiate");
+  }
+  c->graph[parity] = g;
+  c->gexec[parity] = ex;
+  return LBM_OK;
+}
+
+lbm_status do_steps(lbm_ctx* c, int64_t n) {
+  while (n >= kGraphSteps && c->graphs_ok) {
+    if (!c->gexec[c->cur]) {
+      lbm_status s = build_graph(c, c->cur);
+      if (s != LBM_OK) {
+        c->graphs_ok = false;  // fall back to plain launches
+        c->err.clear();
+        (void)hipGetLastError();
+        break;
+      }
+    }
+    HIPCHK(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
+    c->step += kGraphSteps;  // even count: buffer parity unchanged
+    n -= kGraphSteps;
+  }
+  for (; n > 0; n--) {
+    lbm_status s = launch_one_step(c);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+lbm_status invariants(lbm_ctx* c, double out[3]) {
+  double* partials = c->at<double>(c->pl.off_partials);
+  double* dout = c->at<double>(c->pl.off_out);
+  HIPCHK(c, lbm::launch_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args, c->pl.bouz, -1,
+                                nullptr, partials, c->stream));
+  HIPCHK(c, lbm::launch_reduce_final(partials, c->pl.nblocks, dout, c->stream));
+  double h[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  out[0] = h[0] / c->pl.nx;
+  out[1] = (double)c->pl.nfluid * c->p.rho0 + h[1];
+  out[2] = h[1];
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+    return c->fail(LBM_EDIVERGED, "flux or mass is not finite");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_footprint(const lbm_params* p, size_t* bytes) {
+  if (!bytes) return LBM_EINVAL;
+  Plan pl;
+  lbm_status s = make_plan(p, &pl, nullptr);
+  if (s != LBM_OK) return s;
+  *bytes = pl.total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void* hip_stream,
+                      lbm_ctx** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  lbm_status s = make_plan(p, &c->pl, &c->err);
+  if (s != LBM_OK) {
+    delete c;
+    return s;
+  }
+  if (!arena || (reinterpret_cast<uintptr_t>(arena) % kAlign) != 0) {
+    delete c;
+    return LBM_EINVAL;
+  }
+  if (arena_bytes < c->pl.total) {
+    delete c;
+    return LBM_ENOMEM;
+  }
+  c->p = *p;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->arena = static_cast<char*>(arena);
+  c->pop[0] = c->arena + c->pl.off_pop[0];
+  c->pop[1] = c->arena + c->pl.off_pop[1];
+  fill_args(c);
+  const Plan& pl = c->pl;
+  lbm_status st = LBM_OK;
+  do {
+    if ((st = c->hip(hipMemsetAsync(c->arena, 0, pl.total, c->stream), "hipMemsetAsync")) != LBM_OK) break;
+    if ((st = upload(c, pl.off_active, pl.active.data(), pl.active.size() * sizeof(int32_t))) != LBM_OK) break;
+    if ((st = upload(c, pl.off_colinfo, pl.colinfo.data(), pl.colinfo.size() * sizeof(ColInfo))) != LBM_OK) break;
+    std::vector<double> inf(pl.nwall, INFINITY);
+    std::vector<double> ones(pl.nwall, 1.0);
+    if ((st = upload(c, pl.off_lambda, inf.data(), inf.size() * sizeof(double))) != LBM_OK) break;
+    if (pl.wsize == 8) {
+      if ((st = upload(c, pl.off_r, ones.data(), ones.size() * 8)) != LBM_OK) break;
+      if (pl.bouz && (st = upload(c, pl.off_bz, pl.bzc.data(), pl.bzc.size() * 8)) != LBM_OK) break;
+      if ((st = sync(c)) != LBM_OK) break;
+    } else {
+      std::vector<float> onesf = convert<float>(ones), bzf = convert<float>(pl.bzc);
+      if ((st = upload(c, pl.off_r, onesf.data(), onesf.size() * 4)) != LBM_OK) break;
+      if (pl.bouz && (st = upload(c, pl.off_bz, bzf.data(), bzf.size() * 4)) != LBM_OK) break;
+      if ((st = sync(c)) != LBM_OK) break;
+    }
+  } while (0);
+  if (st != LBM_OK) {
+    lbm_destroy(c);
+    return st;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  for (int k = 0; k < 2; k++) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+  }
+  delete c;
+}
+
+lbm_status lbm_fluid_count(const lbm_ctx* c, size_t* n) {
+  if (!c || !n) return LBM_EINVAL;
+  *n = (size_t)c->pl.nfluid;
+  return LBM_OK;
+}
+
+lbm_status lbm_wall_count(const lbm_ctx* c, size_t* n) {
+  if (!c || !n) return LBM_EINVAL;
+  *n = (size_t)c->pl.nwall;
+  return LBM_OK;
+}
+
+lbm_status lbm_wall_coords(const lbm_ctx* c, int32_t* xyz) {
+  if (!c || (!xyz && c->pl.nwall)) return LBM_EINVAL;
+  const Plan& pl = c->pl;
+  int64_t k = 0;
+  for (size_t w = 0; w < pl.wallcols.size(); w++) {
+    const int col = pl.wallcols[w];
+    for (int x = 0; x < pl.nx; x++, k++) {
+      xyz[3 * k] = x;
+      xyz[3 * k + 1] = col % pl.ny;
+      xyz[3 * k + 2] = col / pl.ny;
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_wall_links(const lbm_ctx* c, double* links) {
+  if (!c || (!links && c->pl.nwall)) return LBM_EINVAL;
+  const Plan& pl = c->pl;
+  int64_t k = 0;
+  for (size_t w = 0; w < pl.wallcols.size(); w++)
+    for (int x = 0; x < pl.nx; x++, k++)
+      for (int i = 0; i < pl.Q; i++) links[k * pl.Q + i] = pl.linkq[w * pl.Q + i];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_friction(lbm_ctx* c, const double* lambda, size_t n, int on_device) {
+  if (!c) return LBM_EINVAL;
+  if (n != (size_t)c->pl.nwall) return c->fail(LBM_EINVAL, "expected %lld friction values", (long long)c->pl.nwall);
+  if (n == 0) return LBM_OK;
+  if (!lambda) return c->fail(LBM_EINVAL, "null friction array");
+  std::vector<double> h;
+  const double* src = lambda;
+  if (on_device) {
+    h.resize(n);
+    HIPCHK(c, hipMemcpyAsync(h.data(), lambda, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    lbm_status s = sync(c);
+    if (s != LBM_OK) return s;
+    src = h.data();
+  }
+  for (size_t k = 0; k < n; k++)
+    if (!(src[k] >= 0.0)) return c->fail(LBM_EINVAL, "friction[%zu] must be >= 0 (inf allowed)", k);
+  double* dl = c->at<double>(c->pl.off_lambda);
+  HIPCHK(c, hipMemcpyAsync(dl, lambda, n * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  c->have_raw = false;
+  return upload_wall_r(c, dl, (int64_t)n);
+}
+
+lbm_status lbm_set_friction_spectral(lbm_ctx* c, const lbm_spectral* sp, const double* omega,
+                                     size_t n, int on_device) {
+  if (!c || !sp) return LBM_EINVAL;
+  if (n != (size_t)c->pl.nwall) return c->fail(LBM_EINVAL, "expected %lld plasmon frequencies", (long long)c->pl.nwall);
+  if (!(sp->T > 0) || !(sp->d > 0) || !(sp->gamma_s > 0) || !(sp->gamma_l > 0) ||
+      !(sp->omega_l > 0) || !(sp->a_l > 0) || !(sp->q_max > 0) || !(sp->w_max > 0) ||
+      !(sp->omega0 > 0) || sp->nq < 1 || sp->nw < 1 || !(sp->lambda_target >= 0) ||
+      !std::isfinite(sp->T + sp->d + sp->gamma_s + sp->gamma_l + sp->omega_l + sp->a_l +
+                     sp->q_max + sp->w_max + sp->omega0 + sp->lambda_target))
+    return c->fail(LBM_EINVAL, "bad spectral parameters");
+  std::vector<double> h;
+  const double* hsrc = omega;
+  if (n && !omega) return c->fail(LBM_EINVAL, "null omega array");
+  if (n && on_device) {
+    h.resize(n);
+    HIPCHK(c, hipMemcpyAsync(h.data(), omega, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    lbm_status s = sync(c);
+    if (s != LBM_OK) return s;
+    hsrc = h.data();
+  }
+  for (size_t k = 0; k < n; k++)
+    if (!(hsrc[k] >= 0.0) || !std::isfinite(hsrc[k]))
+      return c->fail(LBM_EINVAL, "omega[%zu] must be finite and >= 0", k);
+  // the lambda buffer holds Omega until the quadrature has read it
+  double* dl = c->at<double>(c->pl.off_lambda);
+  double* draw = c->at<double>(c->pl.off_raw);
+  if (n)
+    HIPCHK(c, hipMemcpyAsync(dl, omega, n * sizeof(double),
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  lbm::SpecArgs a{sp->T,  sp->omega0, sp->gamma_s, sp->omega_l, sp->gamma_l, sp->a_l, sp->d,
+                  sp->nq, sp->nw,     sp->q_max,   sp->w_max,   sp->lambda_target, sp->dispersion};
+  HIPCHK(c, lbm::launch_friction(a, dl, (int64_t)n, draw, dl, c->stream));
+  c->have_raw = true;
+  return upload_wall_r(c, dl, (int64_t)n);
+}
+
+lbm_status lbm_get_friction(lbm_ctx* c, double* lambda, double* raw) {
+  if (!c) return LBM_EINVAL;
+  const size_t n = (size_t)c->pl.nwall;
+  if (lambda && n)
+    HIPCHK(c, hipMemcpyAsync(lambda, c->at<double>(c->pl.off_lambda), n * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  if (raw) {
+    if (!c->have_raw) return c->fail(LBM_ESTATE, "no spectral friction has been set");
+    HIPCHK(c, hipMemcpyAsync(raw, c->at<double>(c->pl.off_raw), (n + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  return sync(c);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  return do_steps(c, nsteps);
+}
+
+lbm_status lbm_run_to_steady(lbm_ctx* c, double rel_tol, int64_t check_every, int64_t max_steps,
+                             int64_t* steps_taken) {
+  if (!c || !(rel_tol > 0) || check_every < 1 || max_steps < 0) return LBM_EINVAL;
+  if (steps_taken) *steps_taken = 0;
+  double inv[3];
+  lbm_status s = invariants(c, inv);
+  if (s != LBM_OK) return s;
+  double prev = inv[0];
+  int64_t taken = 0;
+  while (taken < max_steps) {
+    const int64_t k = std::min(check_every, max_steps - taken);
+    if ((s = do_steps(c, k)) != LBM_OK) return s;
+    taken += k;
+    if (steps_taken) *steps_taken = taken;
+    if ((s = invariants(c, inv)) != LBM_OK) return s;
+    if (std::fabs(inv[0] - prev) < rel_tol * std::fabs(inv[0])) return LBM_OK;
+    prev = inv[0];
+  }
+  return c->fail(LBM_ENOTCONV, "no steady state after %lld steps", (long long)taken);
+}
+
+lbm_status lbm_invariants(lbm_ctx* c, double out[3]) {
+  if (!c || !out) return LBM_EINVAL;
+  return invariants(c, out);
+}
+
+lbm_status lbm_flux(lbm_ctx* c, double* q) {
+  if (!c || !q) return LBM_EINVAL;
+  double inv[3];
+  lbm_status s = invariants(c, inv);
+  if (s == LBM_OK) *q = inv[0];
+  return s;
+}
+
+lbm_status lbm_mass(lbm_ctx* c, double* m) {
+  if (!c || !m) return LBM_EINVAL;
+  double inv[3];
+  lbm_status s = invariants(c, inv);
+  if (s == LBM_OK) *m = inv[1];
+  return s;
+}
+
+lbm_status lbm_get_field(lbm_ctx* c, int which, double* host_out) {
+  if (!c || !host_out || which < 0 || which > 3) return LBM_EINVAL;
+  // the buffer the next step overwrites serves as scratch (>= 8 B per cell)
+  double* scratch = static_cast<double*>(c->pop[1 - c->cur]);
+  const size_t bytes = (size_t)c->pl.ncolbox * c->pl.nx * sizeof(double);
+  HIPCHK(c, hipMemsetAsync(scratch, 0, bytes, c->stream));
+  HIPCHK(c, lbm::launch_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args, c->pl.bouz, which,
+                                scratch, c->at<double>(c->pl.off_partials), c->stream));
+  HIPCHK(c, hipMemcpyAsync(host_out, scratch, bytes, hipMemcpyDeviceToHost, c->stream));
+  return sync(c);
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
+  if (!c || !host_out) return LBM_EINVAL;
+  const Plan& pl = c->pl;
+  std::vector<unsigned char> raw(pl.pop_bytes);
+  HIPCHK(c, hipMemcpyAsync(raw.data(), c->pop[c->cur], pl.pop_bytes, hipMemcpyDeviceToHost, c->stream));
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  for (int i = 0; i < pl.Q; i++)
+    for (int64_t col = 0; col < pl.ncolbox; col++) {
+      const bool solid = pl.colinfo[col].mask & lbm::kSolidColumn;
+      for (int x = 0; x < pl.nx; x++) {
+        const int64_t src = i * pl.stride + col * pl.nxp + x;
+        double v = 0.0;
+        if (!solid) {
+          if (pl.prec == LBM_F64) v = reinterpret_cast<const double*>(raw.data())[src];
+          else if (pl.prec == LBM_F32) v = reinterpret_cast<const float*>(raw.data())[src];
+          else v = (double)reinterpret_cast<const _Float16*>(raw.data())[src];
+        }
+        host_out[((int64_t)i * pl.ncolbox + col) * pl.nx + x] = v;
+      }
+    }
+  return LBM_OK;
+}
+
+lbm_status lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return LBM_EINVAL;
+  *bytes = c->pl.pop_bytes;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, void* host_buf, size_t bytes, int64_t* step) {
+  if (!c || !host_buf || bytes != c->pl.pop_bytes) return LBM_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(host_buf, c->pop[c->cur], bytes, hipMemcpyDeviceToHost, c->stream));
+  lbm_status s = sync(c);
+  if (s == LBM_OK && step) *step = c->step;
+  return s;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const void* host_buf, size_t bytes, int64_t step) {
+  if (!c || !host_buf || bytes != c->pl.pop_bytes || step < 0) return LBM_EINVAL;
+  HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], host_buf, bytes, hipMemcpyHostToDevice, c->stream));
+  lbm_status s = sync(c);
+  if (s == LBM_OK) c->step = step;
+  return s;
+}
+
+lbm_status lbm_step_count(const lbm_ctx* c, int64_t* step) {
+  if (!c || !step) return LBM_EINVAL;
+  *step = c->step;
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  return sync(c);
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

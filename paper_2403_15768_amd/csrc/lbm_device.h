@@ -1,0 +1,207 @@
+// lbm_device.h -- device-side building blocks of the stream-collide update.
+//
+// Lattice tables, the pull gather with the Navier-slip wall rule, and the
+// BGK + Guo collision, shared by the step kernel, the moments kernel and the
+// batched kernel.  Follows the paper's LB procedure (Sec. 4: one population
+// set for the water, local equilibria, forcing as a source; Sec. 4.2: the
+// boundary rules at liquid/solid sites, periodic inlet/outlet).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ------------------------------------------------------------------ lattices
+// D2Q9 in the paper's numbering (Sec. 4.2, beside Eqs. 18-20).
+struct D2Q9 {
+  static constexpr int Q = 9;
+  static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  // transverse reversal (c_x, -c_y)
+  static constexpr int sig[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+  static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  // transverse reversal (c_x, -c_y, -c_z)
+  static constexpr int sig[19] = {0, 1, 2, 4, 3, 6, 5, 9, 10, 7, 8, 13, 14, 11, 12, 16, 15, 18, 17};
+  static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+
+// ------------------------------------------------------------------ layout
+// Populations live in a dense box of "columns" (y, z), col = y + ny z, each
+// column an x-line padded to nxp elements: g[i][col][x].  Every geometry here
+// is x-invariant, so a column is entirely fluid or entirely solid and a
+// column's wall links are the same for every x.
+
+constexpr uint32_t kSolidColumn = 0x80000000u;
+
+struct ColInfo {
+  int32_t wallcol;  // index among wall columns, -1 for interior columns
+  uint32_t mask;    // bit i: link i pulls from a solid point; kSolidColumn
+};
+
+struct StepArgs {
+  int nx, nxp, ny, nz;
+  int64_t stride;     // elements between population planes = ncolbox * nxp
+  int nactive;        // number of fluid columns
+  int bx;             // threads per block along x
+  int segs;           // blocks per column = ceil(nx / bx)
+  int slab;           // z periodic
+  const int32_t* active;    // fluid column ids
+  const ColInfo* colinfo;   // per box column
+  const void* rwall;        // [wallcol][nx] wall mixing weight r (arithmetic type)
+  const void* bz;           // [wallcol][Q][2] interpolated bounce-back coefs (b, c) or null
+  double rho0, omega;       // omega = 1/tau
+  double F[3];
+  double utop;              // moving top wall speed (0: none)
+};
+
+// ------------------------------------------------------------------ storage
+template <typename S, typename M>
+__device__ __forceinline__ M ld(const S* p) {
+  return static_cast<M>(*p);
+}
+template <typename S, typename M>
+__device__ __forceinline__ void st(S* p, M v) {
+  *p = static_cast<S>(v);
+}
+
+// source column of link i for the pull at column (y, z)
+template <class L>
+__device__ __forceinline__ int src_col(const StepArgs& a, int i, int y, int z) {
+  int ys = y - L::cy[i];
+  int zs = z - L::cz[i];
+  if (a.slab) {
+    if (zs < 0) zs += a.nz;
+    if (zs >= a.nz) zs -= a.nz;
+  }
+  return ys + a.ny * zs;
+}
+
+// Pull gather: df_i = g_i(x - c_i), periodic in x; a link whose upstream
+// point is solid takes the wall rule
+//   df_i = r BB_i + (1 - r) g_sig(i)(x),
+// BB_i = g_opp(i)(x) (half-way) or the interpolated bounce-back
+//   a g_opp(i)(x) + b g_opp(i)(x + c_i) + c g_i(x),  a + b + c = 1,
+// and on a moving top wall BB_i = g_opp(i)(x) + 6 w_i rho0 c_ix U.
+// Mixtures are evaluated as g + r (bb - g) and gb + b (gnb - gb) + c (gi - gb)
+// so that their weights sum to one exactly in the working precision (a
+// rounded 1 - r would multiply the wall populations by 1 + eps every step).
+template <class L, typename S, typename M, typename W, bool BOUZ>
+__device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& a, int col,
+                                       int y, int z, int x, ColInfo info, M* df) {
+  const int64_t sp = a.stride;
+  const int xm = (x == 0) ? a.nx - 1 : x - 1;
+  const int xp = (x == a.nx - 1) ? 0 : x + 1;
+  if (info.mask == 0u) {
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      const int sx = L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : x);
+      const int sc = src_col<L>(a, i, y, z);
+      df[i] = ld<S, M>(g + i * sp + (int64_t)sc * a.nxp + sx);
+    }
+    return;
+  }
+  const int64_t own = (int64_t)col * a.nxp + x;
+  const M r = static_cast<M>(static_cast<const W*>(a.rwall)[(int64_t)info.wallcol * a.nx + x]);
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    if (info.mask & (1u << i)) {
+      const M gb = ld<S, M>(g + L::opp[i] * sp + own);
+      M v;
+      if (a.utop != 0.0 && L::cy[i] == -1 && y == a.ny - 1) {
+        v = gb + static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i] * a.utop);
+      } else {
+        M bb = gb;
+        if (BOUZ) {
+          const W* cw = static_cast<const W*>(a.bz) + ((int64_t)info.wallcol * L::Q + i) * 2;
+          const M cb = static_cast<M>(cw[0]), cc = static_cast<M>(cw[1]);
+          if (cb != M(0)) {
+            const int nxx = L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : x);
+            const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
+            bb += cb * (ld<S, M>(g + L::opp[i] * sp + (int64_t)nc * a.nxp + nxx) - gb);
+          }
+          if (cc != M(0)) bb += cc * (ld<S, M>(g + i * sp + own) - gb);
+        }
+        const M gs = ld<S, M>(g + L::sig[i] * sp + own);
+        v = gs + r * (bb - gs);
+      }
+      df[i] = v;
+    } else {
+      const int sx = L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : x);
+      const int sc = src_col<L>(a, i, y, z);
+      df[i] = ld<S, M>(g + i * sp + (int64_t)sc * a.nxp + sx);
+    }
+  }
+}
+
+// Weights of the terms linear in c_i (3 w_i), chosen so that
+// sum_i t_i c_ia c_ib = delta_ab holds exactly in the working precision:
+// with 3 w_i rounded independently the equilibrium's momentum would come out
+// as (1 + eps) rho u and every collision would add eps omega rho u, a
+// systematic anti-friction that grows to eps omega / (nu k^2) relative.
+template <class L, typename M>
+__device__ __forceinline__ M lin_weight(int i) {
+  const int c2 = L::cx[i] * L::cx[i] + L::cy[i] * L::cy[i] + L::cz[i] * L::cz[i];
+  if (c2 == 0) return M(0);
+  if (L::Q == 19) {  // 2 t1 + 8 t2 = 1
+    const M t2 = M(1) / M(12);
+    return c2 == 2 ? t2 : (M(1) - M(8) * t2) * M(0.5);
+  }
+  const M t1 = M(1) / M(3);  // D2Q9: 2 t1 + 4 t2 = 1
+  return c2 == 1 ? t1 : (M(1) - M(2) * t1) * M(0.25);
+}
+
+// BGK relaxation with Guo forcing on shifted populations, in place:
+//   rho = rho0 + sum df, j = rho u = sum df c + F/2,
+//   dfeq_i = w_i [(rho - rho0) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
+//   df_i <- df_i - omega (df_i - dfeq_i) + (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i].F
+// with rho (3 c.u) written as t_i (c.j) (t_i = 3 w_i, see lin_weight).
+template <class L, typename M>
+__device__ __forceinline__ void collide(M* df, const StepArgs& a) {
+  M drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    drho += df[i];
+    if (L::cx[i]) jx += L::cx[i] > 0 ? df[i] : -df[i];
+    if (L::cy[i]) jy += L::cy[i] > 0 ? df[i] : -df[i];
+    if (L::cz[i]) jz += L::cz[i] > 0 ? df[i] : -df[i];
+  }
+  const M Fx = static_cast<M>(a.F[0]), Fy = static_cast<M>(a.F[1]), Fz = static_cast<M>(a.F[2]);
+  jx += Fx * M(0.5);
+  jy += Fy * M(0.5);
+  jz += Fz * M(0.5);
+  const M rho = static_cast<M>(a.rho0) + drho;
+  const M irho = M(1) / rho;
+  const M ux = jx * irho, uy = jy * irho, uz = jz * irho;
+  const M usq15 = M(1.5) * (ux * ux + uy * uy + uz * uz);
+  const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);
+  const M om = static_cast<M>(a.omega);
+  const M A = M(1) - M(0.5) * om;
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    const M wi = static_cast<M>(L::w[i]);
+    const M ti = lin_weight<L, M>(i);
+    const M cu = M(L::cx[i]) * ux + M(L::cy[i]) * uy + M(L::cz[i]) * uz;
+    const M cj = M(L::cx[i]) * jx + M(L::cy[i]) * jy + M(L::cz[i]) * jz;
+    const M cF = M(L::cx[i]) * Fx + M(L::cy[i]) * Fy + M(L::cz[i]) * Fz;
+    const M feq = wi * drho + ti * cj + wi * rho * (M(4.5) * cu * cu - usq15);
+    const M src = A * (ti * cF + wi * (M(9) * cu * cF - uF3));
+    df[i] = df[i] - om * (df[i] - feq) + src;
+  }
+}
+
+}  // namespace lbm

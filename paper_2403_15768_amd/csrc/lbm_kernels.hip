@@ -1,0 +1,330 @@
+// lbm_kernels.hip -- HIP kernels for gfx950 (MI355X) and their launchers.
+//
+//  k_step           fused pull stream + Navier-slip wall + BGK/Guo collide,
+//                   one thread per fluid cell, ping-pong buffers
+//  k_moments        moments of the current state (the populations the next
+//                   collision sees), per-block FP64 partials of the flux and
+//                   the mass deviation, optional dense field output
+//  k_reduce_final   fixed-order FP64 sum of the per-block partials
+//  k_friction_raw   (q, omega) friction quadrature, omega table tiled
+//                   through LDS, FP64 sums, wavefront + block reduction
+//  k_friction_lat   normalisation lambda_k = lambda_target raw_k / raw_ref
+//  k_set_r          lambda -> wall mixing weight r = 3 lambda / (1 + 3 lambda)
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+#include "lbm_launch.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------ stream-collide
+template <class L, typename S, typename M, bool BOUZ>
+__global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
+                                              StepArgs a) {
+  const int slot = blockIdx.x / a.segs;
+  const int seg = blockIdx.x - slot * a.segs;
+  const int x = seg * a.bx + threadIdx.x;
+  if (x >= a.nx) return;
+  const int col = a.active[slot];
+  const ColInfo info = a.colinfo[col];
+  const int y = col % a.ny;
+  const int z = col / a.ny;
+  M df[L::Q];
+  gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
+  collide<L, M>(df, a);
+  S* out = dst + (int64_t)col * a.nxp + x;
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) st<S, M>(out + i * a.stride, df[i]);
+}
+
+// ------------------------------------------------------------ moments
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class L, typename S, typename W, bool BOUZ>
+__global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, StepArgs a,
+                                                 int which, double* __restrict__ field,
+                                                 double* __restrict__ partials) {
+  __shared__ double red[2][8];
+  const int slot = blockIdx.x / a.segs;
+  const int seg = blockIdx.x - slot * a.segs;
+  const int x = seg * a.bx + threadIdx.x;
+  double jx_cell = 0.0, drho_cell = 0.0;
+  if (x < a.nx) {
+    const int col = a.active[slot];
+    const ColInfo info = a.colinfo[col];
+    const int y = col % a.ny;
+    const int z = col / a.ny;
+    double df[L::Q];
+    gather<L, S, double, W, BOUZ>(src, a, col, y, z, x, info, df);
+    double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      drho += df[i];
+      jx += L::cx[i] * df[i];
+      jy += L::cy[i] * df[i];
+      jz += L::cz[i] * df[i];
+    }
+    jx += a.F[0] / 2;
+    jy += a.F[1] / 2;
+    jz += a.F[2] / 2;
+    const double rho = a.rho0 + drho;
+    jx_cell = jx;
+    drho_cell = drho;
+    if (field) {
+      double v = which == 0 ? rho : (which == 1 ? jx / rho : (which == 2 ? jy / rho : jz / rho));
+      field[(int64_t)col * a.nx + x] = v;
+    }
+  }
+  // deterministic block reduction: fixed butterfly within a wave, waves in order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double s0 = wave_sum(jx_cell), s1 = wave_sum(drho_cell);
+  if (lane == 0) {
+    red[0][wv] = s0;
+    red[1][wv] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double t0 = 0, t1 = 0;
+    for (int k = 0; k < nw; k++) {
+      t0 += red[0][k];
+      t1 += red[1][k];
+    }
+    partials[2 * (int64_t)blockIdx.x] = t0;
+    partials[2 * (int64_t)blockIdx.x + 1] = t1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ partials,
+                                                      int64_t nblocks, double* __restrict__ out) {
+  __shared__ double red[2][256];
+  double t0 = 0, t1 = 0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
+    t0 += partials[2 * b];
+    t1 += partials[2 * b + 1];
+  }
+  red[0][threadIdx.x] = t0;
+  red[1][threadIdx.x] = t1;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+// ------------------------------------------------------------ friction quadrature
+constexpr int kQuadThreads = 256;
+constexpr int kQuadNodes = 4;     // wall nodes per workgroup (share the LDS tile)
+constexpr int kQuadTile = 1024;   // omega points per LDS tile
+
+struct OmegaEntry {
+  double s, t, v, pad;  // w^2, gamma_s^2 w^2, gamma_s w Im g_l(w) / sinh^2(w/2T)
+};
+
+// raw[k] for k < n uses omega[k]; raw[n] is the reference at omega0.
+__global__ void __launch_bounds__(kQuadThreads) k_friction_raw(SpecArgs s,
+                                                               const double* __restrict__ omega,
+                                                               int64_t n,
+                                                               double* __restrict__ raw) {
+  __shared__ OmegaEntry tab[kQuadTile];
+  __shared__ double red[kQuadNodes][kQuadThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kQuadNodes;
+  double om2[kQuadNodes];
+#pragma unroll
+  for (int j = 0; j < kQuadNodes; j++) {
+    const int64_t k = k0 + j;
+    const double o = k < n ? omega[k] : s.omega0;  // k >= n: reference (k == n) or padding
+    om2[j] = o * o;
+  }
+  const double dq = s.q_max / s.nq, dw = s.w_max / s.nw;
+  const double gs2 = s.gamma_s * s.gamma_s, wl2 = s.omega_l * s.omega_l;
+  const double gl2 = s.gamma_l * s.gamma_l;
+  double acc[kQuadNodes];
+#pragma unroll
+  for (int j = 0; j < kQuadNodes; j++) acc[j] = 0.0;
+
+  for (int b0 = 0; b0 < s.nw; b0 += kQuadTile) {
+    const int nb = min(kQuadTile, s.nw - b0);
+    __syncthreads();
+    for (int b = tid; b < nb; b += kQuadThreads) {
+      const double w = ((double)(b0 + b) + 0.5) * dw;
+      const double w2 = w * w;
+      const double sh = sinh(w / (2.0 * s.T));
+      const double dl = wl2 - w2;
+      const double iml = s.a_l * wl2 * s.gamma_l * w / (dl * dl + gl2 * w2);
+      OmegaEntry e;
+      e.s = w2;
+      e.t = gs2 * w2;
+      e.v = s.gamma_s * w * iml / (sh * sh);
+      e.pad = 0.0;
+      tab[b] = e;
+    }
+    __syncthreads();
+    for (int ai = tid; ai < s.nq; ai += kQuadThreads) {
+      const double q = ((double)ai + 0.5) * dq;
+      const double kq = q * q * q * exp(-2.0 * q * s.d);
+      const double qd = s.dispersion ? q * s.d : 1.0;
+      double P[kQuadNodes], S[kQuadNodes];
+#pragma unroll
+      for (int j = 0; j < kQuadNodes; j++) {
+        P[j] = om2[j] * qd;
+        S[j] = 0.0;
+      }
+      for (int b = 0; b < nb; b++) {
+        const OmegaEntry e = tab[b];  // same b for every lane: LDS broadcast
+#pragma unroll
+        for (int j = 0; j < kQuadNodes; j++) {
+          const double dd = P[j] - e.s;
+          S[j] += e.v / (dd * dd + e.t);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kQuadNodes; j++) acc[j] += kq * P[j] * S[j];
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < kQuadNodes; j++) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) red[j][wv] = v;
+  }
+  __syncthreads();
+  if (tid < kQuadNodes) {
+    const int64_t k = k0 + tid;
+    if (k <= n) {
+      double t = 0;
+      for (int w = 0; w < kQuadThreads / 64; w++) t += red[tid][w];
+      const double C = 1.0 / (8.0 * M_PI * M_PI * s.T);
+      raw[k] = C * dq * dw * t;
+    }
+  }
+}
+
+__global__ void k_friction_lat(const double* __restrict__ raw, int64_t n, double target,
+                               double* __restrict__ lambda) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) lambda[k] = target * raw[k] / raw[n];
+}
+
+template <typename W>
+__global__ void k_set_r(const double* __restrict__ lambda, int64_t n, W* __restrict__ r,
+                        int* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double l = lambda[k];
+  if (!(l >= 0.0)) {
+    *bad = 1;  // every writer stores the same value
+    return;
+  }
+  r[k] = static_cast<W>(isinf(l) ? 1.0 : 3.0 * l / (1.0 + 3.0 * l));
+}
+
+// ------------------------------------------------------------ launchers
+template <class L, typename S, typename M>
+static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, bool bouz,
+                                hipStream_t st) {
+  const dim3 grid((unsigned)((int64_t)a.nactive * a.segs)), block(a.bx);
+  if (bouz)
+    hipLaunchKernelGGL((k_step<L, S, M, true>), grid, block, 0, st, (const S*)src, (S*)dst, a);
+  else
+    hipLaunchKernelGGL((k_step<L, S, M, false>), grid, block, 0, st, (const S*)src, (S*)dst, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
+                       hipStream_t st) {
+  if (q == 9) {
+    if (prec == 0) return launch_step_t<D2Q9, double, double>(src, dst, a, bouz, st);
+    if (prec == 1) return launch_step_t<D2Q9, float, double>(src, dst, a, bouz, st);
+    return launch_step_t<D2Q9, _Float16, float>(src, dst, a, bouz, st);
+  }
+  if (prec == 0) return launch_step_t<D3Q19, double, double>(src, dst, a, bouz, st);
+  if (prec == 1) return launch_step_t<D3Q19, float, double>(src, dst, a, bouz, st);
+  return launch_step_t<D3Q19, _Float16, float>(src, dst, a, bouz, st);
+}
+
+const void* step_kernel_ptr(int q, int prec, bool bouz) {
+#define KP(L, S, M)                                                                       \
+  (bouz ? reinterpret_cast<const void*>(&k_step<L, S, M, true>)                           \
+        : reinterpret_cast<const void*>(&k_step<L, S, M, false>))
+  if (q == 9) {
+    if (prec == 0) return KP(D2Q9, double, double);
+    if (prec == 1) return KP(D2Q9, float, double);
+    return KP(D2Q9, _Float16, float);
+  }
+  if (prec == 0) return KP(D3Q19, double, double);
+  if (prec == 1) return KP(D3Q19, float, double);
+  return KP(D3Q19, _Float16, float);
+#undef KP
+}
+
+template <class L, typename S, typename W>
+static hipError_t launch_moments_t(const void* src, const StepArgs& a, bool bouz, int which,
+                                   double* field, double* partials, hipStream_t st) {
+  const dim3 grid((unsigned)((int64_t)a.nactive * a.segs)), block(a.bx);
+  if (bouz)
+    hipLaunchKernelGGL((k_moments<L, S, W, true>), grid, block, 0, st, (const S*)src, a, which,
+                       field, partials);
+  else
+    hipLaunchKernelGGL((k_moments<L, S, W, false>), grid, block, 0, st, (const S*)src, a, which,
+                       field, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, bool bouz,
+                          int which, double* field, double* partials, hipStream_t st) {
+  if (q == 9) {
+    if (prec == 0) return launch_moments_t<D2Q9, double, double>(src, a, bouz, which, field, partials, st);
+    if (prec == 1) return launch_moments_t<D2Q9, float, double>(src, a, bouz, which, field, partials, st);
+    return launch_moments_t<D2Q9, _Float16, float>(src, a, bouz, which, field, partials, st);
+  }
+  if (prec == 0) return launch_moments_t<D3Q19, double, double>(src, a, bouz, which, field, partials, st);
+  if (prec == 1) return launch_moments_t<D3Q19, float, double>(src, a, bouz, which, field, partials, st);
+  return launch_moments_t<D3Q19, _Float16, float>(src, a, bouz, which, field, partials, st);
+}
+
+hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, double* raw,
+                           double* lambda, hipStream_t st) {
+  const int64_t nodes = n + 1;
+  const unsigned blocks = (unsigned)((nodes + kQuadNodes - 1) / kQuadNodes);
+  hipLaunchKernelGGL(k_friction_raw, dim3(blocks), dim3(kQuadThreads), 0, st, s, omega, n, raw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n > 0)
+    hipLaunchKernelGGL(k_friction_lat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, raw, n,
+                       s.lambda_target, lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_r(int prec, const double* lambda, int64_t n, void* r, int* bad,
+                        hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (prec != 2)
+    hipLaunchKernelGGL(k_set_r<double>, grid, block, 0, st, lambda, n, (double*)r, bad);
+  else
+    hipLaunchKernelGGL(k_set_r<float>, grid, block, 0, st, lambda, n, (float*)r, bad);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

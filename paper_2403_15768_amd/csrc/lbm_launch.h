@@ -1,0 +1,34 @@
+// lbm_launch.h -- host-side launchers of the kernels in lbm_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Spectral parameters as the quadrature kernel takes them (mirrors
+// lbm_spectral of the public header).
+struct SpecArgs {
+  double T, omega0, gamma_s, omega_l, gamma_l, a_l, d;
+  int nq, nw;
+  double q_max, w_max;
+  double lambda_target;
+  int dispersion;
+};
+
+// q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S
+hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
+                       hipStream_t st);
+const void* step_kernel_ptr(int q, int prec, bool bouz);
+hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, bool bouz,
+                          int which, double* field, double* partials, hipStream_t st);
+hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,
+                               hipStream_t st);
+hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, double* raw,
+                           double* lambda, hipStream_t st);
+hipError_t launch_set_r(int prec, const double* lambda, int64_t n, void* r, int* bad,
+                        hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,315 @@
+"""Thin ctypes binding of liblbm.so (the C ABI in include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies the device arena (a uint8 tensor) and the HIP
+stream; nothing here computes on the data.  Loading fails loudly when the
+library has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+D2Q9, D3Q19 = 9, 19
+F64, F32, F16S = 0, 1, 2
+SLAB, DUCT, TUBE = 0, 1, 2
+PRECISION = {"f64": F64, "f32": F32, "f16s": F16S}
+
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
+          -4: "LBM_ENOTCONV", -5: "LBM_EDIVERGED", -6: "LBM_ESTATE"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("precision", C.c_int), ("geometry", C.c_int),
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("tube_radius", C.c_double), ("tube_cy", C.c_double), ("tube_cz", C.c_double),
+        ("tau", C.c_double), ("rho0", C.c_double),
+        ("force", C.c_double * 3),
+        ("wall_velocity_top", C.c_double),
+    ]
+
+
+class Spectral(C.Structure):
+    _fields_ = [
+        ("T", C.c_double), ("omega0", C.c_double), ("gamma_s", C.c_double),
+        ("omega_l", C.c_double), ("gamma_l", C.c_double), ("a_l", C.c_double),
+        ("d", C.c_double), ("nq", C.c_int), ("nw", C.c_int),
+        ("q_max", C.c_double), ("w_max", C.c_double),
+        ("lambda_target", C.c_double), ("dispersion", C.c_int),
+    ]
+
+
+# every symbol include/lbm.h declares
+EXPORTS = [
+    "lbm_footprint", "lbm_create", "lbm_destroy", "lbm_fluid_count", "lbm_wall_count",
+    "lbm_wall_coords", "lbm_wall_links", "lbm_set_friction", "lbm_set_friction_spectral",
+    "lbm_get_friction", "lbm_step", "lbm_run_to_steady", "lbm_invariants", "lbm_flux",
+    "lbm_mass", "lbm_get_field", "lbm_get_populations", "lbm_state_bytes", "lbm_get_state",
+    "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error",
+]
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(hipcc, gfx950); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, sz, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_size_t, C.c_int64
+    pp = C.POINTER(Params)
+    sig = {
+        "lbm_footprint": [pp, C.POINTER(sz)],
+        "lbm_create": [pp, vp, sz, vp, C.POINTER(vp)],
+        "lbm_fluid_count": [vp, C.POINTER(sz)],
+        "lbm_wall_count": [vp, C.POINTER(sz)],
+        "lbm_wall_coords": [vp, C.POINTER(C.c_int32)],
+        "lbm_wall_links": [vp, dp],
+        "lbm_set_friction": [vp, vp, sz, C.c_int],
+        "lbm_set_friction_spectral": [vp, C.POINTER(Spectral), vp, sz, C.c_int],
+        "lbm_get_friction": [vp, dp, dp],
+        "lbm_step": [vp, i64],
+        "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
+        "lbm_invariants": [vp, dp],
+        "lbm_flux": [vp, dp],
+        "lbm_mass": [vp, dp],
+        "lbm_get_field": [vp, C.c_int, dp],
+        "lbm_get_populations": [vp, dp],
+        "lbm_state_bytes": [vp, C.POINTER(sz)],
+        "lbm_get_state": [vp, vp, sz, C.POINTER(i64)],
+        "lbm_set_state": [vp, vp, sz, i64],
+        "lbm_step_count": [vp, C.POINTER(i64)],
+        "lbm_sync": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = [vp]
+    lib.lbm_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(lattice: int, geometry: int, nx: int, ny: int, nz: int, tau: float,
+                force=(0.0, 0.0, 0.0), precision="f32", rho0: float = 1.0,
+                tube_radius: float = 0.0, tube_cy: float = 0.0, tube_cz: float = 0.0,
+                wall_velocity_top: float = 0.0) -> Params:
+    p = Params()
+    p.lattice, p.geometry = lattice, geometry
+    p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.tube_radius, p.tube_cy, p.tube_cz = tube_radius, tube_cy, tube_cz
+    p.tau, p.rho0 = tau, rho0
+    p.force = (C.c_double * 3)(*force)
+    p.wall_velocity_top = wall_velocity_top
+    return p
+
+
+def footprint(params: Params) -> int:
+    n = C.c_size_t()
+    rc = load().lbm_footprint(C.byref(params), C.byref(n))
+    if rc != 0:
+        raise LBMError(rc, "lbm_footprint rejected the parameters")
+    return int(n.value)
+
+
+def make_spectral(sp) -> Spectral:
+    """From any object with the lbm_spectral fields (q_max/w_max default to
+    10/d and 20 T)."""
+    s = Spectral()
+    for f in ("T", "omega0", "gamma_s", "omega_l", "gamma_l", "a_l", "d", "nq", "nw",
+              "lambda_target"):
+        setattr(s, f, getattr(sp, f))
+    s.q_max = getattr(sp, "q_max", None) or 10.0 / sp.d
+    s.w_max = getattr(sp, "w_max", None) or 20.0 * sp.T
+    s.dispersion = int(getattr(sp, "dispersion", 1))
+    return s
+
+
+class Channel:
+    """One lattice-Boltzmann channel on the GPU (a context of liblbm)."""
+
+    def __init__(self, lattice: int, geometry: int, nx: int, ny: int, nz: int, tau: float,
+                 force=(0.0, 0.0, 0.0), precision="f32", rho0: float = 1.0,
+                 tube_radius: float = 0.0, tube_cy: float = 0.0, tube_cz: float = 0.0,
+                 wall_velocity_top: float = 0.0, device: str = "cuda", stream=None):
+        import torch  # device memory and streams only
+
+        self._lib = load()
+        self.params = make_params(lattice, geometry, nx, ny, nz, tau, force, precision, rho0,
+                                  tube_radius, tube_cy, tube_cz, wall_velocity_top)
+        self.nbytes = footprint(self.params)
+        dev = torch.device(device)
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = C.c_void_p()
+        rc = self._lib.lbm_create(C.byref(self.params), C.c_void_p(self.arena.data_ptr()),
+                                  self.nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise LBMError(rc, "lbm_create failed")
+        self._h = h
+        self.q, self.nx, self.ny, self.nz = lattice, nx, ny, nz
+        self.shape = (nz, ny, nx)
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lbm_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _ck(self, rc: int, what: str) -> None:
+        if rc != 0:
+            raise LBMError(rc, f"{what}: {self._lib.lbm_last_error(self._h).decode()}")
+
+    # ---- geometry
+    @property
+    def fluid_count(self) -> int:
+        n = C.c_size_t()
+        self._ck(self._lib.lbm_fluid_count(self._h, C.byref(n)), "lbm_fluid_count")
+        return int(n.value)
+
+    @property
+    def wall_count(self) -> int:
+        n = C.c_size_t()
+        self._ck(self._lib.lbm_wall_count(self._h, C.byref(n)), "lbm_wall_count")
+        return int(n.value)
+
+    def wall_coords(self) -> np.ndarray:
+        out = np.zeros((self.wall_count, 3), dtype=np.int32)
+        self._ck(self._lib.lbm_wall_coords(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))),
+                 "lbm_wall_coords")
+        return out
+
+    def wall_links(self) -> np.ndarray:
+        out = np.zeros((self.wall_count, self.q), dtype=np.float64)
+        self._ck(self._lib.lbm_wall_links(self._h, _dptr(out)), "lbm_wall_links")
+        return out
+
+    # ---- friction
+    def set_friction(self, lam) -> None:
+        """Per wall node (canonical order): numpy array or float (host) or a
+        torch CUDA float64 tensor (device)."""
+        if hasattr(lam, "is_cuda") and lam.is_cuda:
+            assert lam.dtype.itemsize == 8 and lam.is_contiguous()
+            self._ck(self._lib.lbm_set_friction(self._h, C.c_void_p(lam.data_ptr()), lam.numel(), 1),
+                     "lbm_set_friction")
+            return
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, dtype=np.float64),
+                                                 (self.wall_count,)))
+        self._ck(self._lib.lbm_set_friction(self._h, a.ctypes.data_as(C.c_void_p), a.size, 0),
+                 "lbm_set_friction")
+
+    def set_friction_spectral(self, sp, omega) -> None:
+        s = make_spectral(sp)
+        if hasattr(omega, "is_cuda") and omega.is_cuda:
+            self._ck(self._lib.lbm_set_friction_spectral(self._h, C.byref(s),
+                                                         C.c_void_p(omega.data_ptr()),
+                                                         omega.numel(), 1),
+                     "lbm_set_friction_spectral")
+            return
+        a = np.ascontiguousarray(np.asarray(omega, dtype=np.float64))
+        self._ck(self._lib.lbm_set_friction_spectral(self._h, C.byref(s),
+                                                     a.ctypes.data_as(C.c_void_p), a.size, 0),
+                 "lbm_set_friction_spectral")
+
+    def get_friction(self, raw: bool = False):
+        lam = np.zeros(self.wall_count)
+        r = np.zeros(self.wall_count + 1) if raw else None
+        self._ck(self._lib.lbm_get_friction(self._h, _dptr(lam), _dptr(r) if raw else None),
+                 "lbm_get_friction")
+        return (lam, r) if raw else lam
+
+    # ---- time stepping
+    def step(self, n: int) -> None:
+        self._ck(self._lib.lbm_step(self._h, int(n)), "lbm_step")
+
+    def run_to_steady(self, rel_tol: float = 1e-8, check_every: int = 1000,
+                      max_steps: int = 10 ** 7) -> int:
+        taken = C.c_int64()
+        self._ck(self._lib.lbm_run_to_steady(self._h, rel_tol, check_every, max_steps,
+                                             C.byref(taken)), "lbm_run_to_steady")
+        return int(taken.value)
+
+    def sync(self) -> None:
+        self._ck(self._lib.lbm_sync(self._h), "lbm_sync")
+
+    @property
+    def step_count(self) -> int:
+        s = C.c_int64()
+        self._ck(self._lib.lbm_step_count(self._h, C.byref(s)), "lbm_step_count")
+        return int(s.value)
+
+    # ---- outputs
+    def invariants(self):
+        out = np.zeros(3)
+        self._ck(self._lib.lbm_invariants(self._h, _dptr(out)), "lbm_invariants")
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def flux(self) -> float:
+        q = C.c_double()
+        self._ck(self._lib.lbm_flux(self._h, C.byref(q)), "lbm_flux")
+        return q.value
+
+    def mass(self) -> float:
+        m = C.c_double()
+        self._ck(self._lib.lbm_mass(self._h, C.byref(m)), "lbm_mass")
+        return m.value
+
+    def field(self, which: int) -> np.ndarray:
+        out = np.zeros(self.shape)
+        self._ck(self._lib.lbm_get_field(self._h, int(which), _dptr(out)), "lbm_get_field")
+        return out
+
+    def fields(self):
+        return tuple(self.field(k) for k in range(4))
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros((self.q,) + self.shape)
+        self._ck(self._lib.lbm_get_populations(self._h, _dptr(out)), "lbm_get_populations")
+        return out
+
+    def get_state(self):
+        n = C.c_size_t()
+        self._ck(self._lib.lbm_state_bytes(self._h, C.byref(n)), "lbm_state_bytes")
+        buf = np.zeros(n.value, dtype=np.uint8)
+        step = C.c_int64()
+        self._ck(self._lib.lbm_get_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.size,
+                                         C.byref(step)), "lbm_get_state")
+        return buf, int(step.value)
+
+    def set_state(self, buf: np.ndarray, step: int) -> None:
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._ck(self._lib.lbm_set_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.size,
+                                         int(step)), "lbm_set_state")
+
+
+def no_slip() -> float:
+    return math.inf

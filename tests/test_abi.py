@@ -1,0 +1,59 @@
+"""Host-side checks of the C-ABI library (no GPU compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2403_15768_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(lbm.EXPORTS) == names
+
+
+def test_footprint_host_logic():
+    p = lbm.make_params(lbm.D3Q19, lbm.DUCT, 256, 128, 64, tau=0.7, precision="f32")
+    nb = lbm.footprint(p)
+    pops = 2 * 19 * 256 * 128 * 64 * 4
+    assert pops <= nb < pops * 1.05
+    p64 = lbm.make_params(lbm.D3Q19, lbm.DUCT, 256, 128, 64, tau=0.7, precision="f64")
+    assert lbm.footprint(p64) > 1.9 * nb
+    # padded x-lines: nx = 37 is stored as 64
+    p = lbm.make_params(lbm.D3Q19, lbm.DUCT, 37, 5, 4, tau=0.7, precision="f32")
+    assert lbm.footprint(p) >= 2 * 19 * 64 * 20 * 4
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau=0.5), dict(tau=float("nan")), dict(nx=0), dict(lattice=27),
+    dict(lattice=9, nz=2), dict(lattice=9, geometry=lbm.DUCT, nz=1),
+    dict(geometry=lbm.TUBE, tube_radius=0.0), dict(wall_velocity_top=0.1, geometry=lbm.TUBE,
+                                                  tube_radius=3.0),
+    dict(force=(float("inf"), 0, 0)), dict(precision=7),
+])
+def test_footprint_rejects_bad_parameters(kw):
+    base = dict(lattice=lbm.D3Q19, geometry=lbm.DUCT, nx=8, ny=8, nz=8, tau=0.7)
+    base.update(kw)
+    p = lbm.make_params(**base)
+    lib = lbm.load()
+    n = C.c_size_t()
+    assert lib.lbm_footprint(C.byref(p), C.byref(n)) == -1
+
+
+def test_tube_footprint_counts_box():
+    p = lbm.make_params(lbm.D3Q19, lbm.TUBE, 512, 72, 72, tau=0.8, tube_radius=32,
+                        tube_cy=35.5, tube_cz=35.5)
+    assert lbm.footprint(p) >= 2 * 19 * 512 * 72 * 72 * 4

@@ -1,0 +1,358 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 results within 1e-12 relative of the oracle, FP32 velocity
+fields within 1e-5 (normalised by the largest axial velocity), wall geometry
+bit-exact.  Inputs are seeded and synthetic (paper_2403_15768_amd.inputs).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15768_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_15768_amd import lbm as mod
+
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def vel_err(g, o):
+    """max |u_gpu - u_ora| per component over max |u_x,ora| (and rho - 1)."""
+    rg, ro = g.fields(), o.fields()
+    ref = np.max(np.abs(ro[1]))
+    errs = [np.max(np.abs(rg[k] - ro[k])) / ref for k in (1, 2, 3)]
+    return max(errs), np.max(np.abs(rg[0] - ro[0]))
+
+
+def pair(lbm, lattice, geometry, nx, ny, nz, tau, g, precision, **kw):
+    G = lbm.Channel(lattice, geometry, nx, ny, nz, tau=tau, force=(g, 0, 0), precision=precision, **kw)
+    O = oracle.Lattice(lattice, geometry, nx, ny, nz, tau=tau, force=(g, 0, 0), **kw)
+    return G, O
+
+
+def tube_kw(R):
+    ny, nz, cy, cz = inputs.tube_box(R)
+    return dict(tube_radius=float(R), tube_cy=cy, tube_cz=cz), ny, nz
+
+
+# ------------------------------------------------------------------ geometry
+@pytest.mark.parametrize("case", ["slab", "duct", "d2q9", "tube8", "tube32_full", "ragged"])
+def test_wall_geometry_bit_exact(lbm, case):
+    say("geometry", case)
+    if case == "slab":
+        args = (19, lbm.SLAB, 16, 9, 7, {})
+    elif case == "duct":
+        args = (19, lbm.DUCT, 16, 9, 7, {})
+    elif case == "d2q9":
+        args = (9, lbm.SLAB, 64, 30, 1, {})
+    elif case == "ragged":
+        args = (19, lbm.DUCT, 37, 5, 3, {})
+    else:
+        R = 8 if case == "tube8" else 32
+        kw, ny, nz = tube_kw(R)
+        args = (19, lbm.TUBE, 512 if R == 32 else 20, ny, nz, kw)
+    q, geom, nx, ny, nz, kw = args
+    G = lbm.Channel(q, geom, nx, ny, nz, tau=0.7, precision="f32", **kw)
+    O = oracle.Lattice(q, geom, nx, ny, nz, tau=0.7, **kw)
+    assert G.fluid_count == O.fluid_count
+    assert G.wall_count == O.wall_count
+    assert np.array_equal(G.wall_coords(), O.wall_coords())
+    lg, lo = G.wall_links(), O.wall_links()
+    assert np.array_equal(lg > 0, lo > 0)
+    assert np.max(np.abs(lg - lo)) < 1e-14
+    if case == "tube32_full":
+        assert G.fluid_count == 1652736 and G.wall_count == 129024
+
+
+# ------------------------------------------------------------------ channel
+@pytest.mark.parametrize("lam", [math.inf, 0.025])
+def test_channel2d_full_config_fp64(lbm, lam):
+    # D2Q9 64 x 32 box (rows 0 and 31 solid), tau 0.8, g 1e-6, 10,000 steps
+    say("channel2d fp64 lam", lam)
+    G, O = pair(lbm, 9, lbm.SLAB, 64, 30, 1, 0.8, 1e-6, "f64")
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.step(10000)
+    O.step(10000)
+    eu, er = vel_err(G, O)
+    say("  u err", eu, "rho err", er)
+    assert eu < TOL["f64"] and er < 1e-14
+    qg, mg, dg = G.invariants()
+    qo, mo, do = O.invariants()
+    assert abs(qg / qo - 1) < TOL["f64"]
+    assert abs(dg - do) < 1e-12
+    pg, po = G.populations(), O.get_populations()
+    assert np.max(np.abs(pg - po)) < 1e-12 * np.max(np.abs(po))
+
+
+def test_channel2d_run_to_steady_closed_form(lbm):
+    say("channel2d run_to_steady")
+    H, tau, g, lam = 30, 0.8, 1e-6, 0.025
+    G = lbm.Channel(9, lbm.SLAB, 64, H, 1, tau=tau, force=(g, 0, 0), precision="f64")
+    G.set_friction(lam)
+    n = G.run_to_steady(rel_tol=1e-12, check_every=1000, max_steps=200000)
+    nu = (tau - 0.5) / 3
+    y = np.arange(H) - (H - 1) / 2
+    ue = g / (2 * nu) * (H * H / 4 - y * y) + g * H / (2 * lam) + g * (16 * (tau - 0.5) ** 2 - 3) / (24 * nu)
+    u = G.field(1)[0]
+    say("  steps", n, "err", np.max(np.abs(u - ue[:, None])) / ue.max())
+    assert np.max(np.abs(u - ue[:, None])) / ue.max() < 1e-9
+
+
+def test_couette_fp64(lbm):
+    say("couette")
+    G, O = pair(lbm, 9, lbm.SLAB, 8, 20, 1, 0.9, 0.0, "f64", wall_velocity_top=1e-3)
+    G.set_friction(0.05)
+    O.set_friction(0.05)
+    G.step(3000)
+    O.step(3000)
+    eu, _ = vel_err(G, O)
+    assert eu < TOL["f64"]
+
+
+# ------------------------------------------------------------------ duct
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_duct_replica_random_friction(lbm, precision):
+    say("duct replica", precision)
+    nx, ny, nz = 48, 24, 12
+    G, O = pair(lbm, 19, lbm.DUCT, nx, ny, nz, 0.7, 1e-6, precision)
+    lam = inputs.duct_friction(G.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 11))
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.step(1000)
+    O.step(1000)
+    eu, er = vel_err(G, O)
+    say("  u err", eu)
+    assert eu < TOL[precision]
+    qg, _, dg = G.invariants()
+    qo, _, do = O.invariants()
+    assert abs(qg / qo - 1) < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_duct_full_size_truncated(lbm, precision):
+    # the 256 x 128 x 64 duct at full size, few steps (oracle cost)
+    say("duct full size", precision)
+    nx, ny, nz = 256, 128, 64
+    G, O = pair(lbm, 19, lbm.DUCT, nx, ny, nz, 0.7, 1e-6, precision)
+    lam = inputs.duct_friction(G.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 0))
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.step(3)
+    O.step(3)
+    eu, _ = vel_err(G, O)
+    say("  u err", eu)
+    assert eu < TOL[precision]
+    if precision == "f64":
+        pg, po = G.populations(), O.get_populations()
+        assert np.max(np.abs(pg - po)) < 1e-12 * np.max(np.abs(po))
+
+
+def test_duct_full_steps_fp32_against_fp64(lbm):
+    # 20,000 steps at full size: FP32 against the FP64 GPU path (itself pinned
+    # to the oracle above); reported as the FP32 error of the configuration
+    say("duct 20000 steps fp32 vs fp64")
+    nx, ny, nz = 256, 128, 64
+    out = {}
+    for prec in ("f64", "f32"):
+        G = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0, 0), precision=prec)
+        lam = inputs.duct_friction(G.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 0))
+        G.set_friction(lam)
+        G.step(20000)
+        out[prec] = (G.field(1), G.invariants())
+        G.close()
+    ref = np.max(np.abs(out["f64"][0]))
+    e = np.max(np.abs(out["f32"][0] - out["f64"][0])) / ref
+    eq = abs(out["f32"][1][0] / out["f64"][1][0] - 1)
+    say("  fp32 field err", e, "flux err", eq)
+    assert e < 1e-5 and eq < 1e-5
+
+
+# ------------------------------------------------------------------ tube
+def small_spectral(nq=32, nw=128, seed=3):
+    sp = inputs.draw_spectral(inputs.rng_for("tube", seed), nq=nq, nw=nw)
+    return sp
+
+
+def oracle_spectral(sp, **kw):
+    return oracle.Spectral(T=sp.T, omega0=sp.omega0, gamma_s=sp.gamma_s, omega_l=sp.omega_l,
+                           gamma_l=sp.gamma_l, a_l=sp.a_l, d=sp.d, nq=sp.nq, nw=sp.nw,
+                           lambda_target=sp.lambda_target, **kw)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tube_replica_spectral_friction(lbm, precision):
+    say("tube replica", precision)
+    R = 10
+    kw, ny, nz = tube_kw(R)
+    nx = 40
+    G, O = pair(lbm, 19, lbm.TUBE, nx, ny, nz, 0.8, 1e-6, precision, **kw)
+    sp = small_spectral()
+    om = inputs.tube_plasmon_frequencies(G.wall_coords(), nx, R, kw["tube_cy"], kw["tube_cz"],
+                                         sp.omega0, inputs.rng_for("tube", 5), sigma=4.0)
+    G.set_friction_spectral(sp, om)
+    lam_g = G.get_friction()
+    _, lam_o = oracle.friction(oracle_spectral(sp), om)
+    assert np.max(np.abs(lam_g / lam_o - 1)) < 1e-12
+    O.set_friction(lam_o)
+    G.step(1000)
+    O.step(1000)
+    eu, _ = vel_err(G, O)
+    say("  u err", eu)
+    assert eu < TOL[precision]
+
+
+def test_tube_full_size_truncated_fp32(lbm):
+    say("tube full size fp32")
+    R, nx = 32, 512
+    kw, ny, nz = tube_kw(R)
+    G, O = pair(lbm, 19, lbm.TUBE, nx, ny, nz, 0.8, 1e-6, "f32", **kw)
+    sp = inputs.draw_spectral(inputs.rng_for("tube", 0))
+    om = inputs.tube_plasmon_frequencies(G.wall_coords(), nx, R, kw["tube_cy"], kw["tube_cz"],
+                                         sp.omega0, inputs.rng_for("tube", 1))
+    G.set_friction_spectral(sp, om)
+    lam_g, raw_g = G.get_friction(raw=True)
+    # quadrature parity on sampled wall nodes (the oracle costs ~10 ms a node)
+    idx = np.random.default_rng(0).choice(len(om), 48, replace=False)
+    raw_o, lam_o = oracle.friction(oracle_spectral(sp), om[idx])
+    assert np.max(np.abs(raw_g[idx] / raw_o - 1)) < 1e-12
+    assert np.max(np.abs(lam_g[idx] / lam_o - 1)) < 1e-12
+    assert abs(raw_g[-1] / oracle.friction_raw(oracle_spectral(sp), sp.omega0) - 1) < 1e-12
+    O.set_friction(lam_g)
+    G.step(3)
+    O.step(3)
+    eu, _ = vel_err(G, O)
+    say("  u err", eu)
+    assert eu < TOL["f32"]
+
+
+@pytest.mark.parametrize("nq,nw,disp", [(1, 1, 1), (2, 4, 0), (4, 16, 1), (7, 1500, 1), (300, 64, 1)])
+def test_quadrature_grids(lbm, nq, nw, disp):
+    say("quadrature", nq, nw, disp)
+    G = lbm.Channel(19, lbm.DUCT, 3, 4, 4, tau=0.7, precision="f64")
+    sp = small_spectral(nq=nq, nw=nw, seed=9)
+    sp.dispersion = disp
+    om = np.linspace(0.3, 4.0, G.wall_count)
+    G.set_friction_spectral(sp, om)
+    lam_g, raw_g = G.get_friction(raw=True)
+    raw_o, lam_o = oracle.friction(oracle_spectral(sp, dispersion=disp), om)
+    assert np.max(np.abs(raw_g[:-1] / raw_o - 1)) < 1e-13
+    assert np.max(np.abs(lam_g / lam_o - 1)) < 1e-13
+
+
+# ------------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("case", ["nx1", "ragged37", "ragged100", "ny1_d2q9", "slab_d3q19",
+                                  "tube_r3", "nx600"])
+def test_edge_shapes_fp64(lbm, case):
+    say("edge", case)
+    kw = {}
+    if case == "nx1":
+        q, geom, nx, ny, nz = 19, lbm.DUCT, 1, 6, 5
+    elif case == "ragged37":
+        q, geom, nx, ny, nz = 19, lbm.DUCT, 37, 6, 5
+    elif case == "ragged100":
+        q, geom, nx, ny, nz = 19, lbm.SLAB, 100, 7, 3
+    elif case == "ny1_d2q9":
+        q, geom, nx, ny, nz = 9, lbm.SLAB, 10, 1, 1
+    elif case == "slab_d3q19":
+        q, geom, nx, ny, nz = 19, lbm.SLAB, 8, 12, 4
+    elif case == "nx600":
+        q, geom, nx, ny, nz = 19, lbm.DUCT, 600, 3, 3
+    else:
+        kw, ny, nz = tube_kw(3)
+        q, geom, nx = 19, lbm.TUBE, 5
+    G, O = pair(lbm, q, geom, nx, ny, nz, 0.65, 1e-5, "f64", **kw)
+    lam = 0.01 + 0.1 * np.random.default_rng(1).random(G.wall_count)
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.step(150)
+    O.step(150)
+    eu, er = vel_err(G, O)
+    assert eu < TOL["f64"] and er < 1e-13
+
+
+def test_mass_conservation_fp64(lbm):
+    say("mass conservation")
+    nx, ny, nz = 64, 20, 16
+    G = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-5, 0, 0), precision="f64")
+    lam = inputs.duct_friction(G.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 3), std=0.05)
+    G.set_friction(lam)
+    G.step(2000)
+    _, m, dm = G.invariants()
+    assert abs(dm) < 1e-15 * G.fluid_count
+
+
+# ------------------------------------------------------------------ runtime
+def test_graph_and_plain_launches_bitwise_equal_and_deterministic(lbm):
+    say("determinism")
+    nx, ny, nz = 64, 16, 8
+    runs = []
+    for mode in ("graph", "plain", "graph"):
+        G = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-5, 0, 0), precision="f32")
+        G.set_friction(inputs.duct_friction(G.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 4)))
+        if mode == "graph":
+            G.step(200)
+        else:
+            for _ in range(200):
+                G.step(1)
+        runs.append((G.get_state()[0], G.invariants()))
+        assert G.step_count == 200
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][0], runs[2][0])
+    assert runs[0][1] == runs[2][1]
+
+
+def test_checkpoint_round_trip(lbm):
+    say("checkpoint")
+    args = (19, lbm.DUCT, 40, 10, 8)
+    A = lbm.Channel(*args, tau=0.7, force=(1e-5, 0, 0), precision="f32")
+    A.set_friction(0.03)
+    A.step(77)
+    buf, step = A.get_state()
+    A.step(70)
+    ref = A.get_state()[0]
+    B = lbm.Channel(*args, tau=0.7, force=(1e-5, 0, 0), precision="f32")
+    B.set_friction(0.03)
+    B.set_state(buf, step)
+    B.step(70)
+    assert np.array_equal(B.get_state()[0], ref) and B.step_count == 147
+
+
+def test_error_paths(lbm):
+    say("errors")
+    G = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, force=(1e-5, 0, 0), precision="f64")
+    G.set_friction(0.05)
+    with pytest.raises(lbm.LBMError) as e:
+        G.set_friction(-1.0)
+    assert e.value.status == -1
+    lam = np.full(G.wall_count, 0.05)
+    lam[3] = np.nan
+    with pytest.raises(lbm.LBMError):
+        G.set_friction(lam)
+    assert np.all(G.get_friction() == 0.05)  # unchanged
+    with pytest.raises(lbm.LBMError) as e:
+        G.run_to_steady(rel_tol=1e-14, check_every=10, max_steps=30)
+    assert e.value.status == -4
+    buf, step = G.get_state()
+    f = buf.view(np.float64).copy()
+    f[5] = np.nan
+    G.set_state(f.view(np.uint8), step)
+    with pytest.raises(lbm.LBMError) as e:
+        G.invariants()
+    assert e.value.status == -5
