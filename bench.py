@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice-Boltzmann nanochannel hot path on one MI355X.
+
+Headline: D3Q19 MLUPS (fluid-cell lattice updates per second) of the fused
+pull stream-collide with the Navier-slip friction wall on the 256 x 128 x 64
+rectangular duct (tau 0.7, g 1e-6, smooth random wall friction, FP32
+population storage), with the HBM roofline fraction of the stream-collide
+kernel and the CPU oracle timed on the same workload.
+
+A "step" is one lattice time step of the whole duct; every ``--check-every``
+steps the flux and mass are reduced in FP64 and brought to the host, as the
+run-to-steady loop does.  Per-query set-up (geometry, friction field -> wall
+weights, rest state) happens before the timed region.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q19 MLUPS + % of HBM roofline; batched solves/s and p99 time-to-steady"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = {"f32": 152, "f64": 304, "f16s": 76}  # 19 reads + 19 writes
+DUCT = (256, 128, 64)
+KERNEL_SOURCES = ["paper_2403_15768_amd/csrc/lbm_device.h",
+                  "paper_2403_15768_amd/csrc/lbm_kernels.hip"]
+COUNTERS = os.path.join(ROOT, "profiles", "stream_collide_duct_256x128x64_f32.counters.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_duct(lbm, inputs, precision):
+    nx, ny, nz = DUCT
+    ch = lbm.Channel(lbm.D3Q19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
+                     precision=precision)
+    lam = inputs.duct_friction(ch.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 0))
+    ch.set_friction(lam)
+    return ch
+
+
+def timed_run(torch, ch, steps, check_every):
+    """Run `steps` steps with an FP64 flux/mass check every `check_every`.
+    Returns wall seconds and the summed HIP-event time of the step chunks
+    (events on the stream the kernels run on)."""
+    stream = ch.stream
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(check_every, steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ch.step(k)
+        b.record(stream)
+        ev.append((a, b, k))
+        ch.invariants()  # synchronising FP64 reduction + host check
+        done += k
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    return t1 - t0, kernel_ms
+
+
+def copy_ceiling(torch, lbm, nbytes=1 << 30, reps=10):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        lbm.copy_probe(src, dst, nbytes, s)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        lbm.copy_probe(src, dst, nbytes, s)
+    b.record(s)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def cpu_baseline(steps):
+    import numpy as np
+
+    import oracle
+    from paper_2403_15768_amd import inputs
+
+    nx, ny, nz = DUCT
+    o = oracle.Lattice(19, oracle.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0, 0))
+    o.set_friction(inputs.duct_friction(o.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 0)))
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(o.fluid_count * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the 256x128x64 duct (D3Q19, FP64, single-threaded "
+                      f"scalar C), {dt:.1f} s"}
+
+
+def extras(torch, lbm, inputs, args):
+    """Secondary measurements: FP64 duct, the R = 32 nanotube with its
+    spectral friction quadrature."""
+    out = {}
+    ch = make_duct(lbm, inputs, "f64")
+    ch.step(200)
+    wall, kms = timed_run(torch, ch, 2000, 1000)
+    cells = ch.fluid_count
+    out["duct_f64"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                       "kernel_us": round(kms * 1e3 / 2000, 2),
+                       "hbm_frac": round(304 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
+    ch.close()
+    del ch
+    R, nx = 32, 512
+    ny, nz, cy, cz = inputs.tube_box(R)
+    tb = lbm.Channel(lbm.D3Q19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), precision="f32",
+                     tube_radius=float(R), tube_cy=cy, tube_cz=cz)
+    sp = inputs.draw_spectral(inputs.rng_for("tube", 0))
+    om = inputs.tube_plasmon_frequencies(tb.wall_coords(), nx, R, cy, cz, sp.omega0,
+                                         inputs.rng_for("tube", 1))
+    tb.set_friction_spectral(sp, om)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tb.set_friction_spectral(sp, om)
+    qs = time.perf_counter() - t0
+    n = tb.wall_count
+    out["quadrature"] = {"nodes": n, "grid": [sp.nq, sp.nw], "s": round(qs, 4),
+                         "gpoints_per_s": round((n + 1) * sp.nq * sp.nw / qs / 1e9, 2)}
+    tb.step(200)
+    wall, kms = timed_run(torch, tb, 2000, 1000)
+    cells = tb.fluid_count
+    out["tube_r32_f32"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                           "kernel_us": round(kms * 1e3 / 2000, 2),
+                           "hbm_frac_fluid_bytes": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
+                                                         / HBM_PEAK_GBS, 4)}
+    tb.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--check-every", type=int, default=1000)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(the per-GPU kernel is measured at N = 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2403_15768_amd import inputs, lbm
+
+    lbm.load()
+    torch.cuda.set_device(0)
+    log("bench: duct 256x128x64", args.precision, "steps", args.steps)
+    ch = make_duct(lbm, inputs, args.precision)
+    cells = ch.fluid_count
+    ch.step(args.warmup)
+    ch.invariants()
+    wall, kernel_ms = timed_run(torch, ch, args.steps, args.check_every)
+    q, m, dm = ch.invariants()
+    ch.close()
+    del ch
+
+    mlups = cells * args.steps / wall / 1e6
+    kern_s = kernel_ms * 1e-3 / args.steps
+    bpu = BYTES_PER_UPDATE[args.precision]
+    achieved = bpu * cells / kern_s / 1e9
+    log(f"bench: {mlups:.1f} MLUPS, step kernel {kern_s * 1e6:.2f} us, {achieved:.0f} GB/s")
+
+    traffic = None
+    if os.path.exists(COUNTERS) and args.precision == "f32":
+        c = json.load(open(COUNTERS))
+        if c.get("kernel_hash") == kernel_hash():
+            traffic = c.get("bytes_per_launch")
+
+    copy_gbs, _ = copy_ceiling(torch, lbm)
+    log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
+    ext = {} if args.no_extras else extras(torch, lbm, inputs, args)
+    ext["copy_ceiling_GBs"] = round(copy_gbs, 1)
+    ext["frac_of_copy_ceiling"] = round(achieved / copy_gbs, 4)
+    ext["final_flux"] = q
+    ext["mass_deviation"] = dm
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        cpu = cpu_baseline(args.cpu_steps)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"duct_256x128x64_d3q19_{args.precision}storage",
+                   "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
+                   "g": 1e-6, "storage": args.precision, "arithmetic": "f64",
+                   "friction": "smooth random lambda(x,s): mean 0.05, std 0.02, corr. length 16",
+                   "check_every": args.check_every},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step<D3Q19>",
+                     "kernel_us": round(kern_s * 1e6, 3), "bytes_per_update": bpu},
+        "cpu_baseline": cpu,
+        "extras": ext,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,12 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes,
                          int64_t step);
 
 lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
+
+/* Plain streaming device-to-device copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned) on hip_stream, asynchronous.  Not part of the
+ * method: it measures the copy-bandwidth ceiling the stream-collide kernel is
+ * compared with, and calibrates the memory-traffic counters. */
+lbm_status lbm_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
 lbm_status lbm_sync(lbm_ctx *ctx);               /* waits, surfaces errors */
 const char *lbm_last_error(const lbm_ctx *ctx);  /* owned by ctx */
 

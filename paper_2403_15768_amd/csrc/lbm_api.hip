@@ -710,4 +710,14 @@ lbm_status lbm_sync(lbm_ctx* c) {
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+lbm_status lbm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (!src || !dst || bytes == 0 || bytes % 16 ||
+      (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+    return LBM_EINVAL;
+  return lbm::launch_copy(src, dst, (int64_t)bytes, reinterpret_cast<hipStream_t>(hip_stream)) ==
+                 hipSuccess
+             ? LBM_OK
+             : LBM_EDEVICE;
+}
+
 }  // extern "C"

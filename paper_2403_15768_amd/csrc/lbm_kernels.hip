@@ -10,9 +10,12 @@
 //                   through LDS, FP64 sums, wavefront + block reduction
 //  k_friction_lat   normalisation lambda_k = lambda_target raw_k / raw_ref
 //  k_set_r          lambda -> wall mixing weight r = 3 lambda / (1 + 3 lambda)
+//  k_copy           plain 16-byte streaming copy (measured bandwidth ceiling)
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "lbm_device.h"
 #include "lbm_launch.h"
@@ -233,7 +236,23 @@ __global__ void k_set_r(const double* __restrict__ lambda, int64_t n, W* __restr
   r[k] = static_cast<W>(isinf(l) ? 1.0 : 3.0 * l / (1.0 + 3.0 * l));
 }
 
+// ------------------------------------------------------------ copy probe
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                              int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
 // ------------------------------------------------------------ launchers
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
+  const int64_t n16 = bytes / 16;
+  const int64_t want = (n16 + 255) / 256;
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 64));
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n16);
+  return hipGetLastError();
+}
+
 template <class L, typename S, typename M>
 static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, bool bouz,
                                 hipStream_t st) {

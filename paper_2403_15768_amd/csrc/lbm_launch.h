@@ -28,6 +28,7 @@ hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* 
                                hipStream_t st);
 hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, double* raw,
                            double* lambda, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_set_r(int prec, const double* lambda, int64_t n, void* r, int* bad,
                         hipStream_t st);
 

@@ -58,7 +58,7 @@ EXPORTS = [
     "lbm_wall_coords", "lbm_wall_links", "lbm_set_friction", "lbm_set_friction_spectral",
     "lbm_get_friction", "lbm_step", "lbm_run_to_steady", "lbm_invariants", "lbm_flux",
     "lbm_mass", "lbm_get_field", "lbm_get_populations", "lbm_state_bytes", "lbm_get_state",
-    "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error",
+    "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error", "lbm_copy_probe",
 ]
 
 _lib = None
@@ -97,6 +97,7 @@ def load() -> C.CDLL:
         "lbm_set_state": [vp, vp, sz, i64],
         "lbm_step_count": [vp, C.POINTER(i64)],
         "lbm_sync": [vp],
+        "lbm_copy_probe": [vp, vp, sz, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -309,6 +310,14 @@ class Channel:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._ck(self._lib.lbm_set_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.size,
                                          int(step)), "lbm_set_state")
+
+
+def copy_probe(src, dst, nbytes: int, stream) -> None:
+    """Plain streaming copy between two torch CUDA tensors (bandwidth probe)."""
+    rc = load().lbm_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), int(nbytes),
+                               C.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise LBMError(rc, "lbm_copy_probe")
 
 
 def no_slip() -> float:
