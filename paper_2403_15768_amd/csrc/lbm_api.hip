@@ -31,8 +31,8 @@ struct Plan {
   int Q = 0, prec = 0;
   size_t ssize = 0, wsize = 0;  // storage bytes, wall-table bytes per value
   int nx = 0, nxp = 0, ny = 0, nz = 0;
-  int64_t ncolbox = 0, stride = 0;
-  std::vector<int32_t> active;     // fluid column ids, increasing
+  int64_t ncolbox = 0, sI = 0, sC = 0;  // layout g[col][i][x]: col * sC + i * sI + x
+  std::vector<int32_t> active;     // fluid column ids: wall columns, then interior ones
   std::vector<ColInfo> colinfo;    // per box column
   std::vector<int32_t> wallcols;   // column id of each wall column, increasing
   std::vector<double> linkq;       // [wallcol][Q] wall fraction (0: no wall link)
@@ -103,7 +103,8 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.ny = p->ny;
   pl.nz = p->nz;
   pl.ncolbox = (int64_t)p->ny * p->nz;
-  pl.stride = pl.ncolbox * pl.nxp;
+  pl.sI = pl.nxp;
+  pl.sC = (int64_t)pl.Q * pl.nxp;
   pl.bouz = p->geometry == LBM_TUBE;
   const bool slab = p->geometry == LBM_SLAB;
 
@@ -125,6 +126,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.colinfo.assign(pl.ncolbox, ColInfo{-1, lbm::kSolidColumn});
   pl.active.clear();
   pl.wallcols.clear();
+  std::vector<int32_t> interior;
   for (int z = 0; z < p->nz; z++)
     for (int y = 0; y < p->ny; y++) {
       const int64_t col = y + (int64_t)p->ny * z;
@@ -136,10 +138,15 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
       if (mask) {
         ci.wallcol = (int32_t)pl.wallcols.size();
         pl.wallcols.push_back((int32_t)col);
+      } else {
+        interior.push_back((int32_t)col);
       }
       pl.colinfo[col] = ci;
-      pl.active.push_back((int32_t)col);
     }
+  // wall columns first: their blocks do more work, so they start early
+  // instead of forming the tail of the grid
+  pl.active = pl.wallcols;
+  pl.active.insert(pl.active.end(), interior.begin(), interior.end());
   const int64_t nwc = (int64_t)pl.wallcols.size();
   pl.linkq.assign(nwc * pl.Q, 0.0);
   if (pl.bouz) pl.bzc.assign(nwc * pl.Q * 2, 0.0);
@@ -205,7 +212,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   }
 
   size_t off = 0;
-  pl.pop_bytes = (size_t)pl.Q * pl.stride * pl.ssize;
+  pl.pop_bytes = (size_t)pl.ncolbox * pl.sC * pl.ssize;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off = align_up(off + std::max<size_t>(bytes, 1));
@@ -289,7 +296,8 @@ void fill_args(lbm_ctx* c) {
   a.nxp = pl.nxp;
   a.ny = pl.ny;
   a.nz = pl.nz;
-  a.stride = pl.stride;
+  a.sI = pl.sI;
+  a.sC = pl.sC;
   a.nactive = (int)pl.active.size();
   a.bx = pl.bx;
   a.segs = pl.segs;
@@ -662,7 +670,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
     for (int64_t col = 0; col < pl.ncolbox; col++) {
       const bool solid = pl.colinfo[col].mask & lbm::kSolidColumn;
       for (int x = 0; x < pl.nx; x++) {
-        const int64_t src = i * pl.stride + col * pl.nxp + x;
+        const int64_t src = col * pl.sC + i * pl.sI + x;
         double v = 0.0;
         if (!solid) {
           if (pl.prec == LBM_F64) v = reinterpret_cast<const double*>(raw.data())[src];

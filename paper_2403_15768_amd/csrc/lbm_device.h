@@ -41,10 +41,12 @@ struct D3Q19 {
 };
 
 // ------------------------------------------------------------------ layout
-// Populations live in a dense box of "columns" (y, z), col = y + ny z, each
-// column an x-line padded to nxp elements: g[i][col][x].  Every geometry here
-// is x-invariant, so a column is entirely fluid or entirely solid and a
-// column's wall links are the same for every x.
+// Populations live in a dense box of "columns" (y, z), col = y + ny z.  A
+// column holds its Q x-lines back to back, each padded to nxp elements:
+// g[col][i][x] (address col * sC + i * sI + x, sI = nxp, sC = Q nxp), so the
+// block that updates a column writes one contiguous Q * nxp run.  Every
+// geometry here is x-invariant: a column is entirely fluid or entirely solid
+// and its wall links are the same for every x.
 
 constexpr uint32_t kSolidColumn = 0x80000000u;
 
@@ -55,7 +57,8 @@ struct ColInfo {
 
 struct StepArgs {
   int nx, nxp, ny, nz;
-  int64_t stride;     // elements between population planes = ncolbox * nxp
+  int64_t sI;         // elements between the x-lines of two directions (nxp)
+  int64_t sC;         // elements between two columns (Q nxp)
   int nactive;        // number of fluid columns
   int bx;             // threads per block along x
   int segs;           // blocks per column = ceil(nx / bx)
@@ -70,13 +73,26 @@ struct StepArgs {
 };
 
 // ------------------------------------------------------------------ storage
-template <typename S, typename M>
-__device__ __forceinline__ M ld(const S* p) {
-  return static_cast<M>(*p);
+// Every population access is (uniform line base) + (32-bit lane index).  The
+// byte offset is formed in 32-bit unsigned arithmetic so that the compiler
+// can address with a scalar base and a 32-bit vector offset instead of one
+// 64-bit vector address per access (x < nxp <= 2^24, so it cannot wrap).
+template <typename S>
+__device__ __forceinline__ const S* at(const S* line, unsigned i) {
+  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(line) + i * (unsigned)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ S* at(S* line, unsigned i) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(line) + i * (unsigned)sizeof(S));
 }
 template <typename S, typename M>
-__device__ __forceinline__ void st(S* p, M v) {
-  *p = static_cast<S>(v);
+__device__ __forceinline__ M ld(const S* line, unsigned i) {
+  return static_cast<M>(*at(line, i));
+}
+// (plain stores: non-temporal stores measured slightly slower on the duct)
+template <typename S, typename M>
+__device__ __forceinline__ void st(S* line, unsigned i, M v) {
+  *at(line, i) = static_cast<S>(v);
 }
 
 // source column of link i for the pull at column (y, z)
@@ -103,48 +119,62 @@ __device__ __forceinline__ int src_col(const StepArgs& a, int i, int y, int z) {
 template <class L, typename S, typename M, typename W, bool BOUZ>
 __device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& a, int col,
                                        int y, int z, int x, ColInfo info, M* df) {
-  const int64_t sp = a.stride;
-  const int xm = (x == 0) ? a.nx - 1 : x - 1;
-  const int xp = (x == a.nx - 1) ? 0 : x + 1;
-  if (info.mask == 0u) {
+  const int64_t sI = a.sI, sC = a.sC;
+  const unsigned ux = (unsigned)x;
+  const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
+  const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
+  const uint32_t mask = info.mask;
+  if (mask == 0u) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-      const int sx = L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : x);
-      const int sc = src_col<L>(a, i, y, z);
-      df[i] = ld<S, M>(g + i * sp + (int64_t)sc * a.nxp + sx);
+      const S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;  // uniform
+      df[i] = ld<S, M>(line, L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
     }
     return;
   }
-  const int64_t own = (int64_t)col * a.nxp + x;
+  // Wall column: issue every load first (the mask is uniform over the block,
+  // so these are uniform branches around loads only), then combine.
+  //   pv[i]: the pulled value of a fluid link, or for an interpolated wall
+  //          link the node behind it, g_opp(i)(x + c_i);
+  //   ow[k]: this node's own g_k, for every k pointing into the wall (and
+  //          for wall links that interpolate with g_i(x)).
+  const S* gown = g + (int64_t)col * sC;
+  const W* cw = BOUZ ? static_cast<const W*>(a.bz) + (int64_t)info.wallcol * L::Q * 2 : nullptr;
+  S pv[L::Q], ow[L::Q];
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    const bool wall = mask & (1u << i);
+    if (!wall) {
+      const S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;
+      pv[i] = *at(line, L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+    } else if (BOUZ && cw[2 * i] != W(0)) {
+      const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
+      const S* line = g + (int64_t)nc * sC + L::opp[i] * sI;
+      pv[i] = *at(line, L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : ux));
+    }
+    if ((mask & (1u << L::opp[i])) || (BOUZ && wall && cw[2 * i + 1] != W(0)))
+      ow[i] = *at(gown + i * sI, ux);
+  }
   const M r = static_cast<M>(static_cast<const W*>(a.rwall)[(int64_t)info.wallcol * a.nx + x]);
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
-    if (info.mask & (1u << i)) {
-      const M gb = ld<S, M>(g + L::opp[i] * sp + own);
-      M v;
-      if (a.utop != 0.0 && L::cy[i] == -1 && y == a.ny - 1) {
-        v = gb + static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i] * a.utop);
-      } else {
-        M bb = gb;
-        if (BOUZ) {
-          const W* cw = static_cast<const W*>(a.bz) + ((int64_t)info.wallcol * L::Q + i) * 2;
-          const M cb = static_cast<M>(cw[0]), cc = static_cast<M>(cw[1]);
-          if (cb != M(0)) {
-            const int nxx = L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : x);
-            const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
-            bb += cb * (ld<S, M>(g + L::opp[i] * sp + (int64_t)nc * a.nxp + nxx) - gb);
-          }
-          if (cc != M(0)) bb += cc * (ld<S, M>(g + i * sp + own) - gb);
-        }
-        const M gs = ld<S, M>(g + L::sig[i] * sp + own);
-        v = gs + r * (bb - gs);
-      }
-      df[i] = v;
-    } else {
-      const int sx = L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : x);
-      const int sc = src_col<L>(a, i, y, z);
-      df[i] = ld<S, M>(g + i * sp + (int64_t)sc * a.nxp + sx);
+    if (!(mask & (1u << i))) {
+      df[i] = static_cast<M>(pv[i]);
+      continue;
     }
+    const M gb = static_cast<M>(ow[L::opp[i]]);
+    if (a.utop != 0.0 && L::cy[i] == -1 && y == a.ny - 1) {
+      df[i] = gb + static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i] * a.utop);
+      continue;
+    }
+    M bb = gb;
+    if (BOUZ) {
+      const M cb = static_cast<M>(cw[2 * i]), cc = static_cast<M>(cw[2 * i + 1]);
+      if (cb != M(0)) bb += cb * (static_cast<M>(pv[i]) - gb);
+      if (cc != M(0)) bb += cc * (static_cast<M>(ow[i]) - gb);
+    }
+    const M gs = static_cast<M>(ow[L::sig[i]]);
+    df[i] = gs + r * (bb - gs);
   }
 }
 
@@ -165,13 +195,15 @@ __device__ __forceinline__ M lin_weight(int i) {
   return c2 == 1 ? t1 : (M(1) - M(2) * t1) * M(0.25);
 }
 
-// BGK relaxation with Guo forcing on shifted populations, in place:
+// BGK relaxation with Guo forcing on shifted populations; each result is
+// stored as soon as it is computed (out_col: the column's base, uniform):
 //   rho = rho0 + sum df, j = rho u = sum df c + F/2,
 //   dfeq_i = w_i [(rho - rho0) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
 //   df_i <- df_i - omega (df_i - dfeq_i) + (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i].F
 // with rho (3 c.u) written as t_i (c.j) (t_i = 3 w_i, see lin_weight).
-template <class L, typename M>
-__device__ __forceinline__ void collide(M* df, const StepArgs& a) {
+template <class L, typename M, typename S>
+__device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, S* __restrict__ out_col,
+                                              unsigned x) {
   M drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
@@ -200,7 +232,7 @@ __device__ __forceinline__ void collide(M* df, const StepArgs& a) {
     const M cF = M(L::cx[i]) * Fx + M(L::cy[i]) * Fy + M(L::cz[i]) * Fz;
     const M feq = wi * drho + ti * cj + wi * rho * (M(4.5) * cu * cu - usq15);
     const M src = A * (ti * cF + wi * (M(9) * cu * cF - uF3));
-    df[i] = df[i] - om * (df[i] - feq) + src;
+    st<S, M>(out_col + i * a.sI, x, df[i] - om * (df[i] - feq) + src);
   }
 }
 

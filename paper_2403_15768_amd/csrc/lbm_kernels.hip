@@ -36,10 +36,7 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   const int z = col / a.ny;
   M df[L::Q];
   gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
-  collide<L, M>(df, a);
-  S* out = dst + (int64_t)col * a.nxp + x;
-#pragma unroll
-  for (int i = 0; i < L::Q; i++) st<S, M>(out + i * a.stride, df[i]);
+  collide_store<L, M, S>(df, a, dst + (int64_t)col * a.sC, (unsigned)x);
 }
 
 // ------------------------------------------------------------ moments
