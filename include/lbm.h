@@ -51,13 +51,19 @@ typedef enum {
 
 typedef enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 } lbm_lattice;
 
-/* Storage and arithmetic: F64 stores and computes in double; F32 stores
- * float and computes in double (FP32 arithmetic would feed the rounding error
- * of the computed moments back into every collision as a momentum source,
- * which near steady state accumulates over the slowest viscous time to
- * ~1e-4 of the flow); F16S stores half-precision deviations from the rest
- * equilibrium and computes in float.  Flux/mass reductions are double in
- * every mode. */
+/* Storage and arithmetic:
+ *  F64  stores and computes in double;
+ *  F32  stores float and computes in double (FP32 arithmetic would feed the
+ *       rounding error of the computed moments back into every collision as
+ *       a momentum source that accumulates over the slowest viscous time to
+ *       ~1e-4 of the flow);
+ *  F16S stores half-precision deviations from the rest equilibrium, scaled
+ *       by 2^12, and computes in float.
+ * Storage narrower than the arithmetic is rounded stochastically (counter-
+ * based random bits from the context's step and cell), which keeps results
+ * reproducible bit for bit; round-to-nearest would stall the approach to
+ * steady state once the per-step change drops below half an ulp.  Flux and
+ * mass reductions are double in every mode. */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_precision;
 
 /* SLAB: walls half a link below y = 0 and above y = ny-1, z periodic (D2Q9
@@ -178,6 +184,13 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes,
                          int64_t step);
 
 lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
+
+/* Copy the state of src into dst: populations (converted to dst's storage
+ * precision, round to nearest), step counter and friction.  Both contexts
+ * must have the same lattice, geometry and box; their precisions may differ
+ * (e.g. a half-precision run handed to a float context to finish).  Waits for
+ * src; the copy runs on dst's stream and is complete on return. */
+lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
 
 /* Plain streaming device-to-device copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) on hip_stream, asynchronous.  Not part of the

@@ -24,6 +24,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kGraphSteps = 64;  // steps per captured graph (even: keeps buffer parity)
+constexpr uint32_t kSeed = 0x2403157u;  // stochastic-rounding stream (same for every context)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -44,7 +45,7 @@ struct Plan {
   // arena offsets
   size_t off_pop[2] = {0, 0}, pop_bytes = 0;
   size_t off_active = 0, off_colinfo = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
-         off_partials = 0, off_out = 0, off_flag = 0, total = 0;
+         off_partials = 0, off_out = 0, off_flag = 0, off_step = 0, total = 0;
 };
 
 int lat_c(int Q, int i, int a) {
@@ -229,6 +230,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_partials = take((size_t)pl.nblocks * 2 * sizeof(double));
   pl.off_out = take(4 * sizeof(double));
   pl.off_flag = take(4 * sizeof(int));
+  pl.off_step = take(sizeof(int64_t));
   pl.total = off;
   return LBM_OK;
 }
@@ -249,6 +251,7 @@ struct lbm_ctx {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool graphs_ok = true;
+  int64_t dstep_value = 0;  // value the device step base holds after enqueued work
 
   template <typename T>
   T* at(size_t off) const {
@@ -310,6 +313,9 @@ void fill_args(lbm_ctx* c) {
   a.omega = 1.0 / c->p.tau;
   for (int i = 0; i < 3; i++) a.F[i] = c->p.force[i];
   a.utop = c->p.wall_velocity_top;
+  a.dstep = nullptr;
+  a.step_off = 0;
+  a.seed = kSeed;
 }
 
 template <typename W>
@@ -330,7 +336,9 @@ lbm_status upload_wall_r(lbm_ctx* c, const double* lambda_dev, int64_t n) {
 }
 
 lbm_status launch_one_step(lbm_ctx* c) {
-  HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], c->args,
+  StepArgs a = c->args;
+  a.step_off = c->step;  // plain launch: the step travels as an argument
+  HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
                              c->pl.bouz, c->stream));
   c->cur = 1 - c->cur;
   c->step++;
@@ -346,9 +354,14 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   // kernel arguments must outlive instantiation only; keep them on the stack
   const void* srcs[2] = {c->pop[parity], c->pop[1 - parity]};
   void* dsts[2] = {c->pop[1 - parity], c->pop[parity]};
-  StepArgs a = c->args;
+  // node k runs step (*d_step + k); a last node advances *d_step
+  StepArgs args[kGraphSteps];
+  int64_t* dstep = c->at<int64_t>(c->pl.off_step);
   for (int k = 0; k < kGraphSteps; k++) {
-    void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&a};
+    args[k] = c->args;
+    args[k].dstep = dstep;
+    args[k].step_off = k;
+    void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&args[k]};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
     kp.gridDim = dim3((unsigned)c->pl.nblocks);
@@ -363,6 +376,21 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
       return c->hip(e, "hipGraphAddKernelNode");
     }
     prev = node;
+  }
+  {
+    int64_t inc = kGraphSteps;
+    void* kargs[2] = {(void*)&dstep, (void*)&inc};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(lbm::add_step_kernel_ptr());
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.kernelParams = kargs;
+    hipGraphNode_t node = nullptr;
+    hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return c->hip(e, "hipGraphAddKernelNode");
+    }
   }
   hipGraphExec_t ex = nullptr;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -386,8 +414,13 @@ lbm_status do_steps(lbm_ctx* c, int64_t n) {
         break;
       }
     }
+    if (c->dstep_value != c->step) {
+      HIPCHK(c, lbm::launch_set_step(c->at<int64_t>(c->pl.off_step), c->step, c->stream));
+      c->dstep_value = c->step;
+    }
     HIPCHK(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
     c->step += kGraphSteps;  // even count: buffer parity unchanged
+    c->dstep_value += kGraphSteps;
     n -= kGraphSteps;
   }
   for (; n > 0; n--) {
@@ -675,7 +708,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
         if (!solid) {
           if (pl.prec == LBM_F64) v = reinterpret_cast<const double*>(raw.data())[src];
           else if (pl.prec == LBM_F32) v = reinterpret_cast<const float*>(raw.data())[src];
-          else v = (double)reinterpret_cast<const _Float16*>(raw.data())[src];
+          else v = (double)(float)reinterpret_cast<const _Float16*>(raw.data())[src] / 4096.0;
         }
         host_out[((int64_t)i * pl.ncolbox + col) * pl.nx + x] = v;
       }
@@ -717,6 +750,32 @@ lbm_status lbm_sync(lbm_ctx* c) {
 }
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+lbm_status lbm_transfer_state(lbm_ctx* dst, lbm_ctx* src) {
+  if (!dst || !src || dst == src) return LBM_EINVAL;
+  const lbm_params &a = dst->p, &b = src->p;
+  if (a.lattice != b.lattice || a.geometry != b.geometry || a.nx != b.nx || a.ny != b.ny ||
+      a.nz != b.nz || a.tube_radius != b.tube_radius || a.tube_cy != b.tube_cy ||
+      a.tube_cz != b.tube_cz)
+    return dst->fail(LBM_EINVAL, "transfer needs the same lattice and geometry");
+  lbm_status s = sync(src);
+  if (s != LBM_OK) return s;
+  const Plan &pd = dst->pl, &ps = src->pl;
+  const int64_t n = ps.ncolbox * ps.sC;  // same element count in both layouts
+  HIPCHK(dst, lbm::launch_convert(ps.prec, src->pop[src->cur], pd.prec, dst->pop[dst->cur], n,
+                                  dst->stream));
+  const size_t nw = (size_t)pd.nwall;
+  if (nw) {
+    HIPCHK(dst, hipMemcpyAsync(dst->at<double>(pd.off_lambda), src->at<double>(ps.off_lambda),
+                               nw * sizeof(double), hipMemcpyDeviceToDevice, dst->stream));
+    HIPCHK(dst, hipMemcpyAsync(dst->at<double>(pd.off_raw), src->at<double>(ps.off_raw),
+                               (nw + 1) * sizeof(double), hipMemcpyDeviceToDevice, dst->stream));
+  }
+  dst->have_raw = src->have_raw;
+  dst->step = src->step;
+  s = upload_wall_r(dst, dst->at<double>(pd.off_lambda), (int64_t)nw);
+  return s;
+}
 
 lbm_status lbm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
   if (!src || !dst || bytes == 0 || bytes % 16 ||

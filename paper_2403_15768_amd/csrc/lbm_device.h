@@ -70,6 +70,11 @@ struct StepArgs {
   double rho0, omega;       // omega = 1/tau
   double F[3];
   double utop;              // moving top wall speed (0: none)
+  // time step of this launch, for the stochastic-rounding bits:
+  // (dstep ? *dstep : 0) + step_off
+  const int64_t* dstep;
+  int64_t step_off;
+  uint32_t seed;
 };
 
 // ------------------------------------------------------------------ storage
@@ -86,13 +91,85 @@ __device__ __forceinline__ S* at(S* line, unsigned i) {
   return reinterpret_cast<S*>(reinterpret_cast<char*>(line) + i * (unsigned)sizeof(S));
 }
 template <typename S, typename M>
-__device__ __forceinline__ M ld(const S* line, unsigned i) {
-  return static_cast<M>(*at(line, i));
+__device__ __forceinline__ M ld(const S* line, unsigned i);  // defined after dec()
+// ------------------------------------------------------------------ rounding
+// Storage below the arithmetic precision is rounded stochastically: rounding
+// to nearest stalls once the per-step change of a population falls below
+// half a unit in the last place, and near steady state that bias is the
+// same every step, so it accumulates over the slowest viscous time (measured
+// 2e-5..7e-5 of the flux for float storage in a CPU emulation, 1e-7 with
+// stochastic rounding).  The random bits come from a counter-based hash of
+// (seed, step, cell): the MurmurHash3 32-bit finaliser.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
 }
-// (plain stores: non-temporal stores measured slightly slower on the duct)
+
+// 16 random bits per population of one cell and step
+struct RoundBits {
+  uint32_t base;
+  __device__ __forceinline__ RoundBits(uint32_t seed, int64_t step, uint32_t cell)
+      : base(fmix32(cell ^ fmix32(seed ^ fmix32((uint32_t)step ^ (uint32_t)(step >> 32))))) {}
+  __device__ __forceinline__ uint32_t bits16(int i) const {
+    const uint32_t h = fmix32(base + (uint32_t)((i >> 1) + 1) * 0x9e3779b9u);
+    return (i & 1) ? (h >> 16) : (h & 0xffffu);
+  }
+};
+
+// Half-precision deviations are stored scaled by 2^12 so that the values of
+// interest (1e-8 .. 1e-2) sit in the normal half range.
+constexpr float kHalfScale = 4096.0f;
+constexpr float kHalfUnscale = 1.0f / 4096.0f;
+
+// double -> float, stochastic: add 16 random bits at the top of the 29
+// discarded mantissa bits and truncate (carries into the exponent are what
+// the integer add does; exact for results in the normal float range)
+__device__ __forceinline__ float sr_float(double v, uint32_t r16) {
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  b = (b + ((uint64_t)r16 << 13)) & ~((1ull << 29) - 1ull);
+  return (float)__longlong_as_double((long long)b);
+}
+// float -> half of v * 2^12, stochastic over the 13 discarded bits
+__device__ __forceinline__ _Float16 sr_half(float v, uint32_t r16) {
+  uint32_t b = __float_as_uint(v * kHalfScale);
+  b = (b + (r16 >> 3)) & ~0x1fffu;
+  return (_Float16)__uint_as_float(b);
+}
+
 template <typename S, typename M>
-__device__ __forceinline__ void st(S* line, unsigned i, M v) {
-  *at(line, i) = static_cast<S>(v);
+struct Store {  // same precision: plain store
+  static constexpr bool kRandom = false;
+  __device__ __forceinline__ static S enc(M v, uint32_t) { return static_cast<S>(v); }
+};
+template <>
+struct Store<float, double> {
+  static constexpr bool kRandom = true;
+  __device__ __forceinline__ static float enc(double v, uint32_t r) { return sr_float(v, r); }
+};
+template <>
+struct Store<_Float16, float> {
+  static constexpr bool kRandom = true;
+  __device__ __forceinline__ static _Float16 enc(float v, uint32_t r) { return sr_half(v, r); }
+};
+template <typename S, typename M>
+__device__ __forceinline__ M dec(S v) {
+  return static_cast<M>(v);
+}
+template <>
+__device__ __forceinline__ float dec<_Float16, float>(_Float16 v) {
+  return static_cast<float>(v) * kHalfUnscale;
+}
+template <>
+__device__ __forceinline__ double dec<_Float16, double>(_Float16 v) {
+  return static_cast<double>(static_cast<float>(v) * kHalfUnscale);
+}
+template <typename S, typename M>
+__device__ __forceinline__ M ld(const S* line, unsigned i) {
+  return dec<S, M>(*at(line, i));
 }
 
 // source column of link i for the pull at column (y, z)
@@ -159,10 +236,10 @@ __device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& 
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     if (!(mask & (1u << i))) {
-      df[i] = static_cast<M>(pv[i]);
+      df[i] = dec<S, M>(pv[i]);
       continue;
     }
-    const M gb = static_cast<M>(ow[L::opp[i]]);
+    const M gb = dec<S, M>(ow[L::opp[i]]);
     if (a.utop != 0.0 && L::cy[i] == -1 && y == a.ny - 1) {
       df[i] = gb + static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i] * a.utop);
       continue;
@@ -170,10 +247,10 @@ __device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& 
     M bb = gb;
     if (BOUZ) {
       const M cb = static_cast<M>(cw[2 * i]), cc = static_cast<M>(cw[2 * i + 1]);
-      if (cb != M(0)) bb += cb * (static_cast<M>(pv[i]) - gb);
-      if (cc != M(0)) bb += cc * (static_cast<M>(ow[i]) - gb);
+      if (cb != M(0)) bb += cb * (dec<S, M>(pv[i]) - gb);
+      if (cc != M(0)) bb += cc * (dec<S, M>(ow[i]) - gb);
     }
-    const M gs = static_cast<M>(ow[L::sig[i]]);
+    const M gs = dec<S, M>(ow[L::sig[i]]);
     df[i] = gs + r * (bb - gs);
   }
 }
@@ -203,7 +280,7 @@ __device__ __forceinline__ M lin_weight(int i) {
 // with rho (3 c.u) written as t_i (c.j) (t_i = 3 w_i, see lin_weight).
 template <class L, typename M, typename S>
 __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, S* __restrict__ out_col,
-                                              unsigned x) {
+                                              unsigned x, uint32_t cell) {
   M drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
@@ -223,6 +300,8 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, S*
   const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);
   const M om = static_cast<M>(a.omega);
   const M A = M(1) - M(0.5) * om;
+  const RoundBits rb(a.seed, (a.dstep ? *a.dstep : 0) + a.step_off,
+                     Store<S, M>::kRandom ? cell : 0u);
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     const M wi = static_cast<M>(L::w[i]);
@@ -232,7 +311,8 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, S*
     const M cF = M(L::cx[i]) * Fx + M(L::cy[i]) * Fy + M(L::cz[i]) * Fz;
     const M feq = wi * drho + ti * cj + wi * rho * (M(4.5) * cu * cu - usq15);
     const M src = A * (ti * cF + wi * (M(9) * cu * cF - uF3));
-    st<S, M>(out_col + i * a.sI, x, df[i] - om * (df[i] - feq) + src);
+    const M v = df[i] - om * (df[i] - feq) + src;
+    *at(out_col + i * a.sI, x) = Store<S, M>::enc(v, Store<S, M>::kRandom ? rb.bits16(i) : 0u);
   }
 }
 

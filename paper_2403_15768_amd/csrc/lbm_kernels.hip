@@ -11,6 +11,7 @@
 //  k_friction_lat   normalisation lambda_k = lambda_target raw_k / raw_ref
 //  k_set_r          lambda -> wall mixing weight r = 3 lambda / (1 + 3 lambda)
 //  k_copy           plain 16-byte streaming copy (measured bandwidth ceiling)
+//  k_set_step, k_add_step   device-resident step base read by graph-launched steps
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -36,7 +37,8 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   const int z = col / a.ny;
   M df[L::Q];
   gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
-  collide_store<L, M, S>(df, a, dst + (int64_t)col * a.sC, (unsigned)x);
+  collide_store<L, M, S>(df, a, dst + (int64_t)col * a.sC, (unsigned)x,
+                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x);
 }
 
 // ------------------------------------------------------------ moments
@@ -241,7 +243,52 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
     dst[i] = src[i];
 }
 
+// ------------------------------------------------------------ precision change
+template <typename A, typename B>
+__global__ void __launch_bounds__(256) k_convert(const A* __restrict__ in, B* __restrict__ out,
+                                                 int64_t n) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
+    const double v = dec<A, double>(in[k]);
+    if constexpr (sizeof(B) == 2)
+      out[k] = (B)(float)(v * kHalfScale);
+    else
+      out[k] = (B)v;
+  }
+}
+
+// ------------------------------------------------------------ step base
+__global__ void k_set_step(int64_t* __restrict__ d, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d = v;
+}
+__global__ void k_add_step(int64_t* __restrict__ d, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d += v;
+}
+
 // ------------------------------------------------------------ launchers
+hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, st, d, v);
+  return hipGetLastError();
+}
+const void* add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_add_step); }
+
+template <typename A>
+static hipError_t convert_from(const void* in, int pout, void* out, int64_t n, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
+  if (pout == 0)
+    hipLaunchKernelGGL((k_convert<A, double>), dim3(blocks), dim3(256), 0, st, (const A*)in, (double*)out, n);
+  else if (pout == 1)
+    hipLaunchKernelGGL((k_convert<A, float>), dim3(blocks), dim3(256), 0, st, (const A*)in, (float*)out, n);
+  else
+    hipLaunchKernelGGL((k_convert<A, _Float16>), dim3(blocks), dim3(256), 0, st, (const A*)in, (_Float16*)out, n);
+  return hipGetLastError();
+}
+hipError_t launch_convert(int pin, const void* in, int pout, void* out, int64_t n, hipStream_t st) {
+  if (pin == 0) return convert_from<double>(in, pout, out, n, st);
+  if (pin == 1) return convert_from<float>(in, pout, out, n, st);
+  return convert_from<_Float16>(in, pout, out, n, st);
+}
+
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
   const int64_t n16 = bytes / 16;
   const int64_t want = (n16 + 255) / 256;

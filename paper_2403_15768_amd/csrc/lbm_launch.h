@@ -28,6 +28,10 @@ hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* 
                                hipStream_t st);
 hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, double* raw,
                            double* lambda, hipStream_t st);
+hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st);
+const void* add_step_kernel_ptr();  // k_add_step(int64_t* d, int64_t v)
+// elementwise storage-precision change of n populations (0 F64, 1 F32, 2 F16S)
+hipError_t launch_convert(int pin, const void* in, int pout, void* out, int64_t n, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_set_r(int prec, const double* lambda, int64_t n, void* r, int* bad,
                         hipStream_t st);

@@ -59,6 +59,7 @@ EXPORTS = [
     "lbm_get_friction", "lbm_step", "lbm_run_to_steady", "lbm_invariants", "lbm_flux",
     "lbm_mass", "lbm_get_field", "lbm_get_populations", "lbm_state_bytes", "lbm_get_state",
     "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error", "lbm_copy_probe",
+    "lbm_transfer_state",
 ]
 
 _lib = None
@@ -98,6 +99,7 @@ def load() -> C.CDLL:
         "lbm_step_count": [vp, C.POINTER(i64)],
         "lbm_sync": [vp],
         "lbm_copy_probe": [vp, vp, sz, vp],
+        "lbm_transfer_state": [vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -305,6 +307,11 @@ class Channel:
         self._ck(self._lib.lbm_get_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.size,
                                          C.byref(step)), "lbm_get_state")
         return buf, int(step.value)
+
+    def transfer_from(self, other: "Channel") -> None:
+        """Take over the state of another channel of the same geometry (any
+        storage precision)."""
+        self._ck(self._lib.lbm_transfer_state(self._h, other._h), "lbm_transfer_state")
 
     def set_state(self, buf: np.ndarray, step: int) -> None:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
