@@ -192,6 +192,41 @@ lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
  * src; the copy runs on dst's stream and is complete on return. */
 lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
 
+/* ---- Batches (many channels, one kernel launch per step) -------------------
+ * A batch groups n existing contexts with the same lattice, storage
+ * precision and wall kind (TUBE or planar); sizes, tau, force and friction
+ * may differ.  One launch per time step advances every member over a work
+ * list of 64-cell x-segments (wall segments first); runs of 64 steps are
+ * replayed from a captured hipGraph.  Members keep their own buffers,
+ * parameters and step counters, and a member advanced in a batch is bit-for-
+ * bit the same as the member advanced alone.  While a batch is alive, step
+ * its members only through it; their lbm_get_*, lbm_invariants and
+ * lbm_get_state calls stay valid between batch calls. */
+typedef struct lbm_batch lbm_batch; /* opaque */
+/* Device bytes a batch of these contexts needs (descriptors, work list,
+ * reduction partials). */
+lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
+/* arena: device, >= footprint bytes, 256-byte aligned, owned by the caller
+ * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
+ * lattice, precision or wall kind, or one appears twice. */
+lbm_status lbm_batch_create(lbm_ctx *const *ctxs, int n, void *arena, size_t arena_bytes,
+                            void *hip_stream, lbm_batch **out);
+void lbm_batch_destroy(lbm_batch *b);  /* members and arena untouched */
+lbm_status lbm_batch_items(const lbm_batch *b, int64_t *nitems);
+/* Advance every member nsteps steps (asynchronous, on the batch stream). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+/* Per member m: out[3m] flux, out[3m+1] mass, out[3m+2] mass deviation, as
+ * lbm_invariants.  Deterministic FP64 reductions.  Synchronous. */
+lbm_status lbm_batch_invariants(lbm_batch *b, double *out);
+/* Autotuner: time the candidate workgroup shapes (1, 2, 4 or 8 work items per
+ * workgroup) on this batch and keep the fastest; *chosen may be NULL.  The
+ * timed launches write only the buffers the next step overwrites: no state
+ * or counter changes.  Synchronous. */
+lbm_status lbm_batch_tune(lbm_batch *b, int *chosen);
+/* Set the workgroup shape directly (1, 2, 4 or 8). */
+lbm_status lbm_batch_set_shape(lbm_batch *b, int waves_per_group);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
 /* Plain streaming device-to-device copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) on hip_stream, asynchronous.  Not part of the
  * method: it measures the copy-bandwidth ceiling the stream-collide kernel is

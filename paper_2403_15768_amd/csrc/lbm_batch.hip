@@ -1,0 +1,417 @@
+// lbm_batch.hip -- batches of channels advanced by one kernel launch per step.
+//
+// A batch groups existing contexts (same lattice, storage precision and wall
+// kind; any sizes and parameters).  Its work list holds one item per 64-cell
+// x-segment of every fluid column of every member, wall segments first; one
+// wave updates one item.  Members keep their own buffers, parameters and step
+// counters: a member's step number decides which of its two buffers is
+// current and which stochastic-rounding bits it uses, so a channel advanced
+// inside a batch is bit-identical to the same channel advanced alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+
+using lbm::MemberDesc;
+using lbm::WorkItem;
+using namespace lbm_host;
+
+struct lbm_batch {
+  std::vector<lbm_ctx*> m;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  int Q = 0, prec = 0;
+  bool bouz = false;
+  int64_t nitems = 0;
+  int wpb = 4;  // waves (work items) per workgroup, set by lbm_batch_tune
+  size_t off_desc = 0, off_items = 0, off_order = 0, off_mstart = 0, off_partials = 0,
+         off_out = 0, off_steps = 0, total = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_wpb = 0;
+  bool graphs_ok = true;
+  std::string err;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(arena + off);
+  }
+  lbm_status fail(lbm_status s, const char* msg) {
+    err = msg;
+    return s;
+  }
+  lbm_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBM_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EDEVICE;
+  }
+};
+
+#define BCHK(b, call)                               \
+  do {                                              \
+    lbm_status _s = (b)->hip((call), #call);        \
+    if (_s != LBM_OK) return _s;                    \
+  } while (0)
+
+namespace {
+
+struct Lists {
+  std::vector<WorkItem> items;
+  std::vector<int32_t> order;
+  std::vector<int64_t> mstart;
+};
+
+// wall segments of every member first (they do more work), then the rest;
+// `order` lists each member's items contiguously for the reductions
+void make_lists(lbm_ctx* const* ctxs, int n, Lists* L) {
+  L->items.clear();
+  std::vector<std::vector<int32_t>> mine(n);
+  for (int pass = 0; pass < 2; pass++)
+    for (int m = 0; m < n; m++) {
+      const Plan& pl = ctxs[m]->pl;
+      const int nwc = (int)pl.wallcols.size();
+      const int segs = (pl.nx + 63) / 64;
+      const int lo = pass == 0 ? 0 : nwc, hi = pass == 0 ? nwc : (int)pl.active.size();
+      for (int slot = lo; slot < hi; slot++)
+        for (int sg = 0; sg < segs; sg++) {
+          mine[m].push_back((int32_t)L->items.size());
+          L->items.push_back(WorkItem{m, slot, sg * 64, 0});
+        }
+    }
+  L->order.clear();
+  L->mstart.assign(n + 1, 0);
+  for (int m = 0; m < n; m++) {
+    L->mstart[m] = (int64_t)L->order.size();
+    L->order.insert(L->order.end(), mine[m].begin(), mine[m].end());
+  }
+  L->mstart[n] = (int64_t)L->order.size();
+}
+
+lbm_status check_members(lbm_ctx* const* ctxs, int n) {
+  if (!ctxs || n < 1) return LBM_EINVAL;
+  for (int m = 0; m < n; m++) {
+    if (!ctxs[m]) return LBM_EINVAL;
+    for (int k = 0; k < m; k++)
+      if (ctxs[k] == ctxs[m]) return LBM_EINVAL;
+    const lbm_params &a = ctxs[0]->p, &b = ctxs[m]->p;
+    if (a.lattice != b.lattice || a.precision != b.precision ||
+        (a.geometry == LBM_TUBE) != (b.geometry == LBM_TUBE))
+      return LBM_EINVAL;
+  }
+  return LBM_OK;
+}
+
+void layout(lbm_batch* b, int n, int64_t nitems) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  b->off_desc = take(n * sizeof(MemberDesc));
+  b->off_items = take(nitems * sizeof(WorkItem));
+  b->off_order = take(nitems * sizeof(int32_t));
+  b->off_mstart = take((n + 1) * sizeof(int64_t));
+  b->off_partials = take(nitems * 2 * sizeof(double));
+  b->off_out = take(n * 2 * sizeof(double));
+  b->off_steps = take(n * sizeof(int64_t*));
+  b->total = off;
+}
+
+int64_t count_items(lbm_ctx* const* ctxs, int n) {
+  int64_t t = 0;
+  for (int m = 0; m < n; m++) t += (int64_t)ctxs[m]->pl.active.size() * ((ctxs[m]->pl.nx + 63) / 64);
+  return t;
+}
+
+lbm_status launch_batch(lbm_batch* b, int64_t step_off, int wpb) {
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
+  const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
+  const WorkItem* items = b->at<WorkItem>(b->off_items);
+  int64_t nitems = b->nitems;
+  void* args[5] = {(void*)&md, (void*)&items, (void*)&nitems, (void*)&step_off, (void*)&wpb};
+  const dim3 grid((unsigned)((nitems + wpb - 1) / wpb)), block(64 * wpb);
+  BCHK(b, hipLaunchKernel(fn, grid, block, args, 0, b->stream));
+  return LBM_OK;
+}
+
+lbm_status launch_bump(lbm_batch* b, int64_t v) {
+  const void* fn = lbm::batch_add_step_kernel_ptr();
+  int64_t* const* steps = b->at<int64_t* const>(b->off_steps);
+  int n = (int)b->m.size();
+  void* args[3] = {(void*)&steps, (void*)&n, (void*)&v};
+  BCHK(b, hipLaunchKernel(fn, dim3((n + 255) / 256), dim3(256), args, 0, b->stream));
+  return LBM_OK;
+}
+
+void advance_members(lbm_batch* b, int64_t k) {
+  for (lbm_ctx* c : b->m) {
+    c->step += k;
+    c->dstep_value += k;
+    if (k & 1) c->cur = 1 - c->cur;
+  }
+}
+
+lbm_status build_graph(lbm_batch* b) {
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+  }
+  if (b->graph) {
+    (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  BCHK(b, hipGraphCreate(&g, 0));
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
+  const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
+  const WorkItem* items = b->at<WorkItem>(b->off_items);
+  int64_t nitems = b->nitems;
+  int wpb = b->wpb;
+  hipGraphNode_t prev = nullptr;
+  int64_t offs[kGraphSteps];
+  for (int k = 0; k < kGraphSteps; k++) {
+    offs[k] = k;
+    void* args[5] = {(void*)&md, (void*)&items, (void*)&nitems, (void*)&offs[k], (void*)&wpb};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = dim3((unsigned)((nitems + wpb - 1) / wpb));
+    kp.blockDim = dim3(64 * wpb);
+    kp.kernelParams = args;
+    hipGraphNode_t node = nullptr;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return b->hip(e, "hipGraphAddKernelNode");
+    }
+    prev = node;
+  }
+  {
+    int64_t* const* steps = b->at<int64_t* const>(b->off_steps);
+    int n = (int)b->m.size();
+    int64_t inc = kGraphSteps;
+    void* args[3] = {(void*)&steps, (void*)&n, (void*)&inc};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(lbm::batch_add_step_kernel_ptr());
+    kp.gridDim = dim3((n + 255) / 256);
+    kp.blockDim = dim3(256);
+    kp.kernelParams = args;
+    hipGraphNode_t node = nullptr;
+    hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &kp);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return b->hip(e, "hipGraphAddKernelNode");
+    }
+  }
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return b->hip(e, "hipGraphInstantiate");
+  }
+  b->graph = g;
+  b->gexec = ex;
+  b->graph_wpb = b->wpb;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_footprint(lbm_ctx* const* ctxs, int n, size_t* bytes) {
+  if (!bytes) return LBM_EINVAL;
+  lbm_status s = check_members(ctxs, n);
+  if (s != LBM_OK) return s;
+  lbm_batch tmp;
+  layout(&tmp, n, count_items(ctxs, n));
+  *bytes = tmp.total;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t arena_bytes,
+                            void* hip_stream, lbm_batch** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_status s = check_members(ctxs, n);
+  if (s != LBM_OK) return s;
+  if (!arena || reinterpret_cast<uintptr_t>(arena) % kAlign) return LBM_EINVAL;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ENOMEM;
+  b->m.assign(ctxs, ctxs + n);
+  b->Q = ctxs[0]->p.lattice;
+  b->prec = ctxs[0]->p.precision;
+  b->bouz = ctxs[0]->p.geometry == LBM_TUBE;
+  Lists L;
+  make_lists(ctxs, n, &L);
+  b->nitems = (int64_t)L.items.size();
+  layout(b, n, b->nitems);
+  if (arena_bytes < b->total || b->nitems >= ((int64_t)1 << 31)) {
+    const lbm_status e = arena_bytes < b->total ? LBM_ENOMEM : LBM_EINVAL;
+    delete b;
+    return e;
+  }
+  b->arena = static_cast<char*>(arena);
+  b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<MemberDesc> desc(n);
+  std::vector<int64_t*> steps(n);
+  for (int m = 0; m < n; m++) {
+    lbm_ctx* c = ctxs[m];
+    if ((s = sync(c)) != LBM_OK) {
+      delete b;
+      return s;
+    }
+    MemberDesc& d = desc[m];
+    std::memset(&d, 0, sizeof d);
+    d.a = c->args;
+    d.a.dstep = c->at<int64_t>(c->pl.off_step);
+    d.a.step_off = 0;
+    d.pop[0] = c->pop[0];
+    d.pop[1] = c->pop[1];
+    d.base_step = c->step;
+    d.cur_base = c->cur;
+    steps[m] = c->at<int64_t>(c->pl.off_step);
+  }
+  lbm_status st = LBM_OK;
+  do {
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_desc), desc.data(), n * sizeof(MemberDesc),
+                                    hipMemcpyHostToDevice, b->stream), "upload")) != LBM_OK) break;
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_items), L.items.data(),
+                                    L.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                    b->stream), "upload")) != LBM_OK) break;
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_order), L.order.data(),
+                                    L.order.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    b->stream), "upload")) != LBM_OK) break;
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_mstart), L.mstart.data(),
+                                    L.mstart.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                                    b->stream), "upload")) != LBM_OK) break;
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_steps), steps.data(), n * sizeof(int64_t*),
+                                    hipMemcpyHostToDevice, b->stream), "upload")) != LBM_OK) break;
+    // every member's device step base must hold its current step
+    for (lbm_ctx* c : b->m)
+      if (c->dstep_value != c->step) {
+        if ((st = b->hip(lbm::launch_set_step(c->at<int64_t>(c->pl.off_step), c->step, b->stream),
+                         "launch_set_step")) != LBM_OK) break;
+        c->dstep_value = c->step;
+      }
+    if (st != LBM_OK) break;
+    st = b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+  } while (0);
+  if (st != LBM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+}
+
+lbm_status lbm_batch_items(const lbm_batch* b, int64_t* nitems) {
+  if (!b || !nitems) return LBM_EINVAL;
+  *nitems = b->nitems;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  while (nsteps >= kGraphSteps && b->graphs_ok) {
+    if (!b->gexec || b->graph_wpb != b->wpb) {
+      if (build_graph(b) != LBM_OK) {
+        b->graphs_ok = false;  // fall back to plain launches
+        (void)hipGetLastError();
+        break;
+      }
+    }
+    BCHK(b, hipGraphLaunch(b->gexec, b->stream));
+    advance_members(b, kGraphSteps);
+    nsteps -= kGraphSteps;
+  }
+  for (; nsteps > 0; nsteps--) {
+    lbm_status s = launch_batch(b, 0, b->wpb);
+    if (s != LBM_OK) return s;
+    if ((s = launch_bump(b, 1)) != LBM_OK) return s;
+    advance_members(b, 1);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_invariants(lbm_batch* b, double* out) {
+  if (!b || !out) return LBM_EINVAL;
+  const int n = (int)b->m.size();
+  double* dout = b->at<double>(b->off_out);
+  BCHK(b, lbm::launch_batch_moments(b->Q, b->prec, b->at<MemberDesc>(b->off_desc),
+                                    b->at<WorkItem>(b->off_items), b->nitems,
+                                    b->at<double>(b->off_partials), b->at<int32_t>(b->off_order),
+                                    b->at<int64_t>(b->off_mstart), n, dout, b->bouz, b->stream));
+  std::vector<double> h(2 * n);
+  BCHK(b, hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         b->stream));
+  BCHK(b, hipStreamSynchronize(b->stream));
+  bool finite = true;
+  for (int m = 0; m < n; m++) {
+    const lbm_ctx* c = b->m[m];
+    out[3 * m] = h[2 * m] / c->pl.nx;
+    out[3 * m + 1] = (double)c->pl.nfluid * c->p.rho0 + h[2 * m + 1];
+    out[3 * m + 2] = h[2 * m + 1];
+    finite = finite && std::isfinite(out[3 * m]) && std::isfinite(out[3 * m + 1]);
+  }
+  return finite ? LBM_OK : b->fail(LBM_EDIVERGED, "a member's flux or mass is not finite");
+}
+
+lbm_status lbm_batch_tune(lbm_batch* b, int* chosen) {
+  if (!b) return LBM_EINVAL;
+  // time each candidate shape on launches whose results land in the buffers
+  // the next step overwrites anyway (counters unchanged)
+  static const int cand[4] = {1, 2, 4, 8};
+  hipEvent_t e0, e1;
+  BCHK(b, hipEventCreate(&e0));
+  BCHK(b, hipEventCreate(&e1));
+  float best = 1e30f;
+  int pick = b->wpb;
+  lbm_status s = LBM_OK;
+  for (int k = 0; k < 4 && s == LBM_OK; k++) {
+    const int w = cand[k];
+    for (int r = 0; r < 2 && s == LBM_OK; r++) s = launch_batch(b, 0, w);
+    if (s != LBM_OK) break;
+    if ((s = b->hip(hipEventRecord(e0, b->stream), "hipEventRecord")) != LBM_OK) break;
+    for (int r = 0; r < 5 && s == LBM_OK; r++) s = launch_batch(b, 0, w);
+    if (s != LBM_OK) break;
+    if ((s = b->hip(hipEventRecord(e1, b->stream), "hipEventRecord")) != LBM_OK) break;
+    if ((s = b->hip(hipEventSynchronize(e1), "hipEventSynchronize")) != LBM_OK) break;
+    float ms = 0;
+    if ((s = b->hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) != LBM_OK) break;
+    if (ms < best) {
+      best = ms;
+      pick = w;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != LBM_OK) return s;
+  b->wpb = pick;
+  if (chosen) *chosen = pick;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_shape(lbm_batch* b, int waves_per_group) {
+  if (!b || !(waves_per_group == 1 || waves_per_group == 2 || waves_per_group == 4 ||
+              waves_per_group == 8))
+    return LBM_EINVAL;
+  b->wpb = waves_per_group;
+  return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

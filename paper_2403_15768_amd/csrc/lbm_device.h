@@ -77,29 +77,69 @@ struct StepArgs {
   uint32_t seed;
 };
 
+// ------------------------------------------------------------------ uniformity
+// Values that are the same for every lane of a wave but were loaded through a
+// pointer the compiler cannot prove uniform: move them to scalar registers so
+// that everything derived from them (column, buffer, line bases) stays scalar.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// ------------------------------------------------------------------ batches
+// One member of a batch: its step arguments (a.dstep points at the member's
+// own step base), its two population buffers, and the buffer that held its
+// state at step base_step.  Buffer parity follows from the step:
+// src = pop[(cur_base + step - base_step) & 1].
+struct MemberDesc {
+  StepArgs a;
+  const void* pop[2];
+  int64_t base_step;
+  int32_t cur_base;
+  int32_t pad;
+};
+
+// A batch work item: one 64-cell x-segment of one fluid column of one member.
+struct WorkItem {
+  int32_t member, slot, x0, pad;
+};
+
 // ------------------------------------------------------------------ storage
-// Every population access is (uniform line base) + (32-bit lane index).  The
-// byte offset is formed in 32-bit unsigned arithmetic so that the compiler
-// can address with a scalar base and a 32-bit vector offset instead of one
-// 64-bit vector address per access (x < nxp <= 2^24, so it cannot wrap).
-template <typename S>
-__device__ __forceinline__ const S* at(const S* line, unsigned i) {
-  return reinterpret_cast<const S*>(reinterpret_cast<const char*>(line) + i * (unsigned)sizeof(S));
+// Device arrays are addressed through global-address-space pointers (plain
+// pointers read from a descriptor would be accessed with flat instructions),
+// and every population access is (uniform line base) + (32-bit lane index).
+// The byte offset is formed in 32-bit unsigned arithmetic so that the
+// compiler can address with a scalar base and a 32-bit vector offset instead
+// of one 64-bit vector address per access (x < nxp <= 2^24: no wrap).
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const LBM_GLOBAL T* gbl(const T* p) {
+  return (const LBM_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T* gbl(T* p) {
+  return (LBM_GLOBAL T*)p;
 }
 template <typename S>
-__device__ __forceinline__ S* at(S* line, unsigned i) {
-  return reinterpret_cast<S*>(reinterpret_cast<char*>(line) + i * (unsigned)sizeof(S));
+__device__ __forceinline__ const LBM_GLOBAL S* at(const LBM_GLOBAL S* line, unsigned i) {
+  return (const LBM_GLOBAL S*)((const LBM_GLOBAL char*)line + i * (unsigned)sizeof(S));
+}
+template <typename S>
+__device__ __forceinline__ LBM_GLOBAL S* at(LBM_GLOBAL S* line, unsigned i) {
+  return (LBM_GLOBAL S*)((LBM_GLOBAL char*)line + i * (unsigned)sizeof(S));
 }
 template <typename S, typename M>
-__device__ __forceinline__ M ld(const S* line, unsigned i);  // defined after dec()
+__device__ __forceinline__ M ld(const LBM_GLOBAL S* line, unsigned i);  // defined after dec()
 // ------------------------------------------------------------------ rounding
 // Storage below the arithmetic precision is rounded stochastically: rounding
 // to nearest stalls once the per-step change of a population falls below
 // half a unit in the last place, and near steady state that bias is the
 // same every step, so it accumulates over the slowest viscous time (measured
 // 2e-5..7e-5 of the flux for float storage in a CPU emulation, 1e-7 with
-// stochastic rounding).  The random bits come from a counter-based hash of
-// (seed, step, cell): the MurmurHash3 32-bit finaliser.
+// stochastic rounding).  The random bits are counter-based (a function of
+// seed, step and cell only), so results are reproducible bit for bit.
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;
   h *= 0x85ebca6bu;
@@ -109,14 +149,19 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
-// 16 random bits per population of one cell and step
+// 16 random bits per population of one cell and step: the MurmurHash3
+// finaliser of (seed, step, cell) seeds a Marsaglia xorshift32 stream, one
+// 32-bit word per two populations (shifts and xors only), drawn as needed.
 struct RoundBits {
-  uint32_t base;
+  uint32_t x;
   __device__ __forceinline__ RoundBits(uint32_t seed, int64_t step, uint32_t cell)
-      : base(fmix32(cell ^ fmix32(seed ^ fmix32((uint32_t)step ^ (uint32_t)(step >> 32))))) {}
-  __device__ __forceinline__ uint32_t bits16(int i) const {
-    const uint32_t h = fmix32(base + (uint32_t)((i >> 1) + 1) * 0x9e3779b9u);
-    return (i & 1) ? (h >> 16) : (h & 0xffffu);
+      : x(fmix32(cell ^ fmix32(seed ^ fmix32((uint32_t)step ^ (uint32_t)(step >> 32)))) | 1u) {}
+  // the next 32-bit word (xorshift32 must not start at zero: hence the | 1)
+  __device__ __forceinline__ uint32_t next() {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
   }
 };
 
@@ -168,7 +213,7 @@ __device__ __forceinline__ double dec<_Float16, double>(_Float16 v) {
   return static_cast<double>(static_cast<float>(v) * kHalfUnscale);
 }
 template <typename S, typename M>
-__device__ __forceinline__ M ld(const S* line, unsigned i) {
+__device__ __forceinline__ M ld(const LBM_GLOBAL S* line, unsigned i) {
   return dec<S, M>(*at(line, i));
 }
 
@@ -194,8 +239,9 @@ __device__ __forceinline__ int src_col(const StepArgs& a, int i, int y, int z) {
 // so that their weights sum to one exactly in the working precision (a
 // rounded 1 - r would multiply the wall populations by 1 + eps every step).
 template <class L, typename S, typename M, typename W, bool BOUZ>
-__device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& a, int col,
+__device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs& a, int col,
                                        int y, int z, int x, ColInfo info, M* df) {
+  const LBM_GLOBAL S* g = gbl(g0);
   const int64_t sI = a.sI, sC = a.sC;
   const unsigned ux = (unsigned)x;
   const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
@@ -204,7 +250,7 @@ __device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& 
   if (mask == 0u) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-      const S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;  // uniform
+      const LBM_GLOBAL S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;  // uniform
       df[i] = ld<S, M>(line, L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
     }
     return;
@@ -215,24 +261,25 @@ __device__ __forceinline__ void gather(const S* __restrict__ g, const StepArgs& 
   //          link the node behind it, g_opp(i)(x + c_i);
   //   ow[k]: this node's own g_k, for every k pointing into the wall (and
   //          for wall links that interpolate with g_i(x)).
-  const S* gown = g + (int64_t)col * sC;
-  const W* cw = BOUZ ? static_cast<const W*>(a.bz) + (int64_t)info.wallcol * L::Q * 2 : nullptr;
+  const LBM_GLOBAL S* gown = g + (int64_t)col * sC;
+  const LBM_GLOBAL W* cw =
+      BOUZ ? gbl(static_cast<const W*>(a.bz)) + (int64_t)info.wallcol * L::Q * 2 : nullptr;
   S pv[L::Q], ow[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     const bool wall = mask & (1u << i);
     if (!wall) {
-      const S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;
+      const LBM_GLOBAL S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;
       pv[i] = *at(line, L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
     } else if (BOUZ && cw[2 * i] != W(0)) {
       const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
-      const S* line = g + (int64_t)nc * sC + L::opp[i] * sI;
+      const LBM_GLOBAL S* line = g + (int64_t)nc * sC + L::opp[i] * sI;
       pv[i] = *at(line, L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : ux));
     }
     if ((mask & (1u << L::opp[i])) || (BOUZ && wall && cw[2 * i + 1] != W(0)))
       ow[i] = *at(gown + i * sI, ux);
   }
-  const M r = static_cast<M>(static_cast<const W*>(a.rwall)[(int64_t)info.wallcol * a.nx + x]);
+  const M r = static_cast<M>(gbl(static_cast<const W*>(a.rwall))[(int64_t)info.wallcol * a.nx + x]);
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     if (!(mask & (1u << i))) {
@@ -272,15 +319,43 @@ __device__ __forceinline__ M lin_weight(int i) {
   return c2 == 1 ? t1 : (M(1) - M(2) * t1) * M(0.25);
 }
 
+// c_i . (vx, vy, vz) from the nonzero components of c_i only: a product with
+// a literal zero cannot be dropped under IEEE rules, so it is never formed
+template <class L, typename M>
+__device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
+  M r = M(0);
+  bool any = false;
+  if (L::cx[i]) {
+    r = L::cx[i] > 0 ? vx : -vx;
+    any = true;
+  }
+  if (L::cy[i]) {
+    const M t = L::cy[i] > 0 ? vy : -vy;
+    r = any ? r + t : t;
+    any = true;
+  }
+  if (L::cz[i]) {
+    const M t = L::cz[i] > 0 ? vz : -vz;
+    r = any ? r + t : t;
+  }
+  return r;
+}
+
 // BGK relaxation with Guo forcing on shifted populations; each result is
 // stored as soon as it is computed (out_col: the column's base, uniform):
 //   rho = rho0 + sum df, j = rho u = sum df c + F/2,
 //   dfeq_i = w_i [(rho - rho0) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
 //   df_i <- df_i - omega (df_i - dfeq_i) + (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i].F
-// with rho (3 c.u) written as t_i (c.j) (t_i = 3 w_i, see lin_weight).
+// with rho (3 c.u) written as t_i (c.j) (t_i = 3 w_i, see lin_weight).  Per
+// cell the terms common to all directions are gathered first:
+//   C0 = omega (drho - 1.5 rho u.u) - 3 A u.F,      A = 1 - omega/2,
+//   U  = 4.5 omega rho u + 9 A F,  J = omega j + A F,
+// so that  df_i <- (1 - omega) df_i + w_i C0 + w_i (c.u)(c.U) + t_i (c.J).
+// Opposite directions are computed with exactly negated operands, so their
+// odd parts cancel exactly in the next step's moments.
 template <class L, typename M, typename S>
-__device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, S* __restrict__ out_col,
-                                              unsigned x, uint32_t cell) {
+__device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LBM_GLOBAL S* out_col,
+                                              unsigned x, uint32_t cell, int64_t step) {
   M drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
@@ -296,23 +371,34 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, S*
   const M rho = static_cast<M>(a.rho0) + drho;
   const M irho = M(1) / rho;
   const M ux = jx * irho, uy = jy * irho, uz = jz * irho;
-  const M usq15 = M(1.5) * (ux * ux + uy * uy + uz * uz);
-  const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);
   const M om = static_cast<M>(a.omega);
   const M A = M(1) - M(0.5) * om;
-  const RoundBits rb(a.seed, (a.dstep ? *a.dstep : 0) + a.step_off,
-                     Store<S, M>::kRandom ? cell : 0u);
+  const M usq15 = M(1.5) * (ux * ux + uy * uy + uz * uz);
+  const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);
+  const M C0 = om * (drho - rho * usq15) - A * uF3;
+  const M k45 = M(4.5) * om * rho, a9 = M(9) * A;
+  const M Ux = k45 * ux + a9 * Fx, Uy = k45 * uy + a9 * Fy, Uz = k45 * uz + a9 * Fz;
+  const M Jx = om * jx + A * Fx, Jy = om * jy + A * Fy, Jz = om * jz + A * Fz;
+  const M keep = M(1) - om;
+  RoundBits rb(a.seed, step, Store<S, M>::kRandom ? cell : 0u);
+  uint32_t word = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     const M wi = static_cast<M>(L::w[i]);
-    const M ti = lin_weight<L, M>(i);
-    const M cu = M(L::cx[i]) * ux + M(L::cy[i]) * uy + M(L::cz[i]) * uz;
-    const M cj = M(L::cx[i]) * jx + M(L::cy[i]) * jy + M(L::cz[i]) * jz;
-    const M cF = M(L::cx[i]) * Fx + M(L::cy[i]) * Fy + M(L::cz[i]) * Fz;
-    const M feq = wi * drho + ti * cj + wi * rho * (M(4.5) * cu * cu - usq15);
-    const M src = A * (ti * cF + wi * (M(9) * cu * cF - uF3));
-    const M v = df[i] - om * (df[i] - feq) + src;
-    *at(out_col + i * a.sI, x) = Store<S, M>::enc(v, Store<S, M>::kRandom ? rb.bits16(i) : 0u);
+    M v = keep * df[i] + wi * C0;
+    if (i != 0) {
+      const M cu = cdot<L, M>(i, ux, uy, uz);
+      const M cU = cdot<L, M>(i, Ux, Uy, Uz);
+      const M cJ = cdot<L, M>(i, Jx, Jy, Jz);
+      v += wi * cu * cU;
+      v += lin_weight<L, M>(i) * cJ;
+    }
+    uint32_t bits = 0u;
+    if (Store<S, M>::kRandom) {
+      if ((i & 1) == 0) word = rb.next();
+      bits = (i & 1) ? (word >> 16) : (word & 0xffffu);
+    }
+    *at(out_col + i * a.sI, x) = Store<S, M>::enc(v, bits);
   }
 }
 

@@ -1,0 +1,92 @@
+// lbm_internal.h -- host-side context and plan shared by the API files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_launch.h"
+
+namespace lbm_host {
+
+using lbm::ColInfo;
+using lbm::StepArgs;
+
+constexpr size_t kAlign = 256;
+constexpr int kGraphSteps = 64;  // steps per captured graph (even: keeps buffer parity)
+constexpr uint32_t kSeed = 0x2403157u;  // stochastic-rounding stream (same for every context)
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Plan {
+  int Q = 0, prec = 0;
+  size_t ssize = 0, wsize = 0;  // storage bytes, wall-table bytes per value
+  int nx = 0, nxp = 0, ny = 0, nz = 0;
+  int64_t ncolbox = 0, sI = 0, sC = 0;  // layout g[col][i][x]: col * sC + i * sI + x
+  std::vector<int32_t> active;     // fluid column ids: wall columns, then interior ones
+  std::vector<ColInfo> colinfo;    // per box column
+  std::vector<int32_t> wallcols;   // column id of each wall column, increasing
+  std::vector<double> linkq;       // [wallcol][Q] wall fraction (0: no wall link)
+  std::vector<double> bzc;         // [wallcol][Q][2] interpolation coefficients b, c (TUBE)
+  int64_t nfluid = 0, nwall = 0;
+  int bx = 0, segs = 0;
+  int64_t nblocks = 0;
+  bool bouz = false;
+  // arena offsets
+  size_t off_pop[2] = {0, 0}, pop_bytes = 0;
+  size_t off_active = 0, off_colinfo = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
+         off_partials = 0, off_out = 0, off_flag = 0, off_step = 0, total = 0;
+};
+
+}  // namespace lbm_host
+
+struct lbm_ctx {
+  lbm_params p{};
+  lbm_host::Plan pl;
+  hipStream_t stream = nullptr;
+  char* arena = nullptr;
+  void* pop[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t step = 0;
+  lbm::StepArgs args{};
+  std::string err;
+  bool have_raw = false;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool graphs_ok = true;
+  int64_t dstep_value = 0;  // value the device step base holds after enqueued work
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(arena + off);
+  }
+  lbm_status fail(lbm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return s;
+  }
+  lbm_status hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBM_OK;
+    return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  }
+};
+
+#define HIPCHK(ctx, call)                                    \
+  do {                                                       \
+    lbm_status _s = (ctx)->hip((call), #call);               \
+    if (_s != LBM_OK) return _s;                             \
+  } while (0)
+
+
+namespace lbm_host {
+lbm_status sync(lbm_ctx* c);
+lbm_status launch_one_step(lbm_ctx* c);
+}  // namespace lbm_host

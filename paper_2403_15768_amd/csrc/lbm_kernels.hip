@@ -12,6 +12,10 @@
 //  k_set_r          lambda -> wall mixing weight r = 3 lambda / (1 + 3 lambda)
 //  k_copy           plain 16-byte streaming copy (measured bandwidth ceiling)
 //  k_set_step, k_add_step   device-resident step base read by graph-launched steps
+//  k_batch_step     k_step over the work list of a batch of channels, one
+//                   64-cell line segment per wave
+//  k_batch_moments, k_batch_reduce   per-member flux and mass of a batch
+//  k_batch_add_step advance every member's step base
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -31,14 +35,17 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   const int seg = blockIdx.x - slot * a.segs;
   const int x = seg * a.bx + threadIdx.x;
   if (x >= a.nx) return;
-  const int col = a.active[slot];
-  const ColInfo info = a.colinfo[col];
+  const int col = uniform(gbl(a.active)[slot]);
+  ColInfo info;
+  info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
+  info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
   const int y = col % a.ny;
   const int z = col / a.ny;
+  const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
   M df[L::Q];
   gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
-  collide_store<L, M, S>(df, a, dst + (int64_t)col * a.sC, (unsigned)x,
-                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x);
+  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step);
 }
 
 // ------------------------------------------------------------ moments
@@ -58,8 +65,10 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
   const int x = seg * a.bx + threadIdx.x;
   double jx_cell = 0.0, drho_cell = 0.0;
   if (x < a.nx) {
-    const int col = a.active[slot];
-    const ColInfo info = a.colinfo[col];
+    const int col = uniform(gbl(a.active)[slot]);
+    ColInfo info;
+    info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
+    info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
     const int y = col % a.ny;
     const int z = col / a.ny;
     double df[L::Q];
@@ -257,6 +266,110 @@ __global__ void __launch_bounds__(256) k_convert(const A* __restrict__ in, B* __
   }
 }
 
+// ------------------------------------------------------------ batches
+template <class L, typename S, typename M, bool BOUZ>
+__global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
+                                                    const WorkItem* __restrict__ items,
+                                                    int64_t nitems, int64_t step_off, int wpb) {
+  // wave index in a scalar register: the item and member are wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t it = (int64_t)blockIdx.x * wpb + wv;
+  if (it >= nitems) return;
+  const WorkItem item = items[it];
+  const MemberDesc& d = md[item.member];
+  StepArgs a = d.a;
+  a.step_off = step_off;
+  const int x = item.x0 + (int)(threadIdx.x & 63);
+  if (x >= a.nx) return;
+  const int64_t n = uniform64(*gbl(a.dstep)) + step_off;
+  const int par = (int)((d.cur_base + (n - d.base_step)) & 1);
+  const S* src = static_cast<const S*>(d.pop[par]);
+  S* dst = static_cast<S*>(const_cast<void*>(d.pop[par ^ 1]));
+  const int col = uniform(gbl(a.active)[item.slot]);
+  ColInfo info;
+  info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
+  info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
+  const int y = col % a.ny;
+  const int z = col / a.ny;
+  M df[L::Q];
+  gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
+  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, n);
+}
+
+// per-item partial sums of (j_x, rho - rho0); one wave per item
+template <class L, typename S, typename W, bool BOUZ>
+__global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restrict__ md,
+                                                       const WorkItem* __restrict__ items,
+                                                       int64_t nitems,
+                                                       double* __restrict__ partials) {
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t it = (int64_t)blockIdx.x * 4 + wv;
+  if (it >= nitems) return;
+  const WorkItem item = items[it];
+  const MemberDesc& d = md[item.member];
+  const StepArgs& a = d.a;
+  const int x = item.x0 + (int)(threadIdx.x & 63);
+  double jx = 0.0, dr = 0.0;
+  if (x < a.nx) {
+    const int64_t n = uniform64(*gbl(a.dstep));
+    const int par = (int)((d.cur_base + (n - d.base_step)) & 1);
+    const S* src = static_cast<const S*>(d.pop[par]);
+    const int col = uniform(gbl(a.active)[item.slot]);
+    ColInfo info;
+    info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
+    info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
+    double df[L::Q];
+    gather<L, S, double, W, BOUZ>(src, a, col, col % a.ny, col / a.ny, x, info, df);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      dr += df[i];
+      jx += L::cx[i] * df[i];
+    }
+    jx += a.F[0] / 2;
+  }
+  jx = wave_sum(jx);
+  dr = wave_sum(dr);
+  if ((threadIdx.x & 63) == 0) {
+    partials[2 * it] = jx;
+    partials[2 * it + 1] = dr;
+  }
+}
+
+// one block per member: its items' partials in the member-sorted order
+__global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__ partials,
+                                                      const int32_t* __restrict__ order,
+                                                      const int64_t* __restrict__ mstart,
+                                                      double* __restrict__ out) {
+  __shared__ double red[2][256];
+  const int m = blockIdx.x;
+  double t0 = 0, t1 = 0;
+  for (int64_t k = mstart[m] + threadIdx.x; k < mstart[m + 1]; k += 256) {
+    const int64_t it = order[k];
+    t0 += partials[2 * it];
+    t1 += partials[2 * it + 1];
+  }
+  red[0][threadIdx.x] = t0;
+  red[1][threadIdx.x] = t1;
+  __syncthreads();
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s2];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s2];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * m] = red[0][0];
+    out[2 * m + 1] = red[1][0];
+  }
+}
+
+__global__ void k_batch_add_step(int64_t* const* __restrict__ steps, int n, int64_t v) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n) *steps[m] += v;
+}
+
 // ------------------------------------------------------------ step base
 __global__ void k_set_step(int64_t* __restrict__ d, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *d = v;
@@ -271,6 +384,51 @@ hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st) {
   return hipGetLastError();
 }
 const void* add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_add_step); }
+
+template <class L, typename S, typename M>
+static const void* batch_kernel_t(bool bouz) {
+  return bouz ? reinterpret_cast<const void*>(&k_batch_step<L, S, M, true>)
+              : reinterpret_cast<const void*>(&k_batch_step<L, S, M, false>);
+}
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz) {
+  if (q == 9) {
+    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz);
+    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz);
+    return batch_kernel_t<D2Q9, _Float16, float>(bouz);
+  }
+  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz);
+  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz);
+  return batch_kernel_t<D3Q19, _Float16, float>(bouz);
+}
+const void* batch_add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_batch_add_step); }
+
+template <class L, typename S, typename W>
+static hipError_t batch_moments_t(const MemberDesc* md, const WorkItem* items, int64_t nitems,
+                                  double* partials, bool bouz, hipStream_t st) {
+  const dim3 grid((unsigned)((nitems + 3) / 4)), block(256);
+  if (bouz)
+    hipLaunchKernelGGL((k_batch_moments<L, S, W, true>), grid, block, 0, st, md, items, nitems, partials);
+  else
+    hipLaunchKernelGGL((k_batch_moments<L, S, W, false>), grid, block, 0, st, md, items, nitems, partials);
+  return hipGetLastError();
+}
+hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,
+                                int64_t nitems, double* partials, const int32_t* order,
+                                const int64_t* mstart, int nmembers, double* out, bool bouz,
+                                hipStream_t st) {
+  hipError_t e;
+  if (q == 9)
+    e = prec == 0 ? batch_moments_t<D2Q9, double, double>(md, items, nitems, partials, bouz, st)
+      : prec == 1 ? batch_moments_t<D2Q9, float, double>(md, items, nitems, partials, bouz, st)
+                  : batch_moments_t<D2Q9, _Float16, float>(md, items, nitems, partials, bouz, st);
+  else
+    e = prec == 0 ? batch_moments_t<D3Q19, double, double>(md, items, nitems, partials, bouz, st)
+      : prec == 1 ? batch_moments_t<D3Q19, float, double>(md, items, nitems, partials, bouz, st)
+                  : batch_moments_t<D3Q19, _Float16, float>(md, items, nitems, partials, bouz, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_reduce, dim3(nmembers), dim3(256), 0, st, partials, order, mstart, out);
+  return hipGetLastError();
+}
 
 template <typename A>
 static hipError_t convert_from(const void* in, int pout, void* out, int64_t n, hipStream_t st) {

@@ -59,7 +59,9 @@ EXPORTS = [
     "lbm_get_friction", "lbm_step", "lbm_run_to_steady", "lbm_invariants", "lbm_flux",
     "lbm_mass", "lbm_get_field", "lbm_get_populations", "lbm_state_bytes", "lbm_get_state",
     "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error", "lbm_copy_probe",
-    "lbm_transfer_state",
+    "lbm_transfer_state", "lbm_batch_footprint", "lbm_batch_create", "lbm_batch_destroy",
+    "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
+    "lbm_batch_set_shape", "lbm_batch_last_error",
 ]
 
 _lib = None
@@ -100,6 +102,13 @@ def load() -> C.CDLL:
         "lbm_sync": [vp],
         "lbm_copy_probe": [vp, vp, sz, vp],
         "lbm_transfer_state": [vp, vp],
+        "lbm_batch_footprint": [vp, C.c_int, C.POINTER(sz)],
+        "lbm_batch_create": [vp, C.c_int, vp, sz, vp, C.POINTER(vp)],
+        "lbm_batch_items": [vp, C.POINTER(i64)],
+        "lbm_batch_step": [vp, i64],
+        "lbm_batch_invariants": [vp, dp],
+        "lbm_batch_tune": [vp, C.POINTER(C.c_int)],
+        "lbm_batch_set_shape": [vp, C.c_int],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -109,6 +118,10 @@ def load() -> C.CDLL:
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = C.c_char_p
+    lib.lbm_batch_destroy.argtypes = [vp]
+    lib.lbm_batch_destroy.restype = None
+    lib.lbm_batch_last_error.argtypes = [vp]
+    lib.lbm_batch_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -317,6 +330,73 @@ class Channel:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._ck(self._lib.lbm_set_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.size,
                                          int(step)), "lbm_set_state")
+
+
+class Batch:
+    """Many channels advanced by one kernel launch per step (lbm_batch_*)."""
+
+    def __init__(self, channels, stream=None, tune: bool = False):
+        import torch
+
+        self._lib = load()
+        self.channels = list(channels)
+        n = len(self.channels)
+        arr = (C.c_void_p * n)(*[ch._h.value for ch in self.channels])
+        self._arr = arr
+        nb = C.c_size_t()
+        rc = self._lib.lbm_batch_footprint(arr, n, C.byref(nb))
+        if rc != 0:
+            raise LBMError(rc, "lbm_batch_footprint rejected the members")
+        dev = self.channels[0].arena.device
+        self.arena = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else self.channels[0].stream
+        h = C.c_void_p()
+        rc = self._lib.lbm_batch_create(arr, n, C.c_void_p(self.arena.data_ptr()), nb.value,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise LBMError(rc, "lbm_batch_create failed")
+        self._h = h
+        self.shape = None
+        if tune:
+            self.tune()
+
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lbm_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _ck(self, rc: int, what: str) -> None:
+        if rc != 0:
+            raise LBMError(rc, f"{what}: {self._lib.lbm_batch_last_error(self._h).decode()}")
+
+    @property
+    def items(self) -> int:
+        n = C.c_int64()
+        self._ck(self._lib.lbm_batch_items(self._h, C.byref(n)), "lbm_batch_items")
+        return int(n.value)
+
+    def step(self, n: int) -> None:
+        self._ck(self._lib.lbm_batch_step(self._h, int(n)), "lbm_batch_step")
+
+    def invariants(self) -> np.ndarray:
+        """(n, 3): flux, mass, mass deviation per member."""
+        out = np.zeros(3 * len(self.channels))
+        self._ck(self._lib.lbm_batch_invariants(self._h, _dptr(out)), "lbm_batch_invariants")
+        return out.reshape(-1, 3)
+
+    def tune(self) -> int:
+        w = C.c_int()
+        self._ck(self._lib.lbm_batch_tune(self._h, C.byref(w)), "lbm_batch_tune")
+        self.shape = int(w.value)
+        return self.shape
+
+    def set_shape(self, waves_per_group: int) -> None:
+        self._ck(self._lib.lbm_batch_set_shape(self._h, int(waves_per_group)), "lbm_batch_set_shape")
+        self.shape = int(waves_per_group)
 
 
 def copy_probe(src, dst, nbytes: int, stream) -> None:

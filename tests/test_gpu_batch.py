@@ -1,0 +1,131 @@
+"""GPU: batches of uneven channels (lbm_batch_*) against the same channels
+stepped alone, and against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15768_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_15768_amd import lbm as mod
+
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_ducts(lbm, specs, precision):
+    out = []
+    for k, (nx, ny, nz, tau, g) in enumerate(specs):
+        ch = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=tau, force=(g, 0, 0), precision=precision)
+        ch.set_friction(inputs.duct_friction(ch.wall_coords(), nx, ny, nz, inputs.rng_for("batch", 100 + k),
+                                             sigma=6.0))
+        out.append(ch)
+    return out
+
+
+SPECS = [(37, 12, 9, 0.65, 2e-6), (64, 10, 14, 0.9, 1e-6), (100, 8, 8, 1.1, 1.5e-6),
+         (128, 16, 12, 0.7, 0.7e-6), (33, 9, 11, 0.6, 1.2e-6)]
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+def test_batch_bit_identical_to_alone(lbm, precision):
+    say("batch vs alone", precision)
+    alone = make_ducts(lbm, SPECS, precision)
+    mixed = make_ducts(lbm, SPECS, precision)
+    for ch in alone:
+        ch.step(20)
+    for ch in mixed:
+        ch.step(20)  # members join with some history (different parities)
+    mixed[1].step(1)
+    alone[1].step(1)
+    b = lbm.Batch(mixed)
+    b.step(150)  # 2 graph replays + 22 single launches
+    for ch in alone:
+        ch.step(150)
+    for a, m in zip(alone, mixed):
+        assert m.step_count == a.step_count
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    inv_b = b.invariants()
+    for k, a in enumerate(alone):
+        q, mass, dm = a.invariants()
+        assert abs(inv_b[k, 0] / q - 1) < 1e-13
+        assert abs(inv_b[k, 1] - mass) < 1e-9
+    b.close()
+
+
+def test_batch_tubes_f16s_bit_identical(lbm):
+    say("batch tubes f16s")
+    chans = []
+    for R, nx, seed in ((6, 40, 0), (9, 70, 1), (4, 64, 2)):
+        ny, nz, cy, cz = inputs.tube_box(R)
+        pair = []
+        for _ in range(2):
+            ch = lbm.Channel(19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), precision="f16s",
+                             tube_radius=float(R), tube_cy=cy, tube_cz=cz)
+            sp = inputs.draw_spectral(inputs.rng_for("serving", 10 + seed), nq=16, nw=64)
+            om = inputs.tube_plasmon_frequencies(ch.wall_coords(), nx, R, cy, cz, sp.omega0,
+                                                 inputs.rng_for("serving", 20 + seed), sigma=4.0)
+            ch.set_friction_spectral(sp, om)
+            pair.append(ch)
+        chans.append(pair)
+    b = lbm.Batch([p[1] for p in chans])
+    b.step(100)
+    for p in chans:
+        p[0].step(100)
+        assert np.array_equal(p[0].get_state()[0], p[1].get_state()[0])
+
+
+def test_batch_fp64_against_oracle(lbm):
+    say("batch fp64 vs oracle")
+    specs = SPECS[:3]
+    chans = make_ducts(lbm, specs, "f64")
+    b = lbm.Batch(chans)
+    b.step(300)
+    for k, (nx, ny, nz, tau, g) in enumerate(specs):
+        o = oracle.Lattice(19, oracle.DUCT, nx, ny, nz, tau=tau, force=(g, 0, 0))
+        o.set_friction(inputs.duct_friction(o.wall_coords(), nx, ny, nz, inputs.rng_for("batch", 100 + k),
+                                            sigma=6.0))
+        o.step(300)
+        ug, uo = chans[k].field(1), o.fields()[1]
+        err = np.max(np.abs(ug - uo)) / np.max(np.abs(uo))
+        say("  member", k, "err", err)
+        assert err < 1e-12
+
+
+def test_batch_tune_leaves_state(lbm):
+    say("batch tune")
+    chans = make_ducts(lbm, SPECS, "f32")
+    b = lbm.Batch(chans)
+    b.step(10)
+    before = [c.get_state()[0].copy() for c in chans]
+    w = b.tune()
+    assert w in (1, 2, 4, 8)
+    for c, s in zip(chans, before):
+        assert np.array_equal(c.get_state()[0], s) and c.step_count == 10
+    ref = make_ducts(lbm, SPECS, "f32")
+    for c in ref:
+        c.step(80)
+    b.step(70)
+    for c, r in zip(chans, ref):
+        assert np.array_equal(c.get_state()[0], r.get_state()[0])
+
+
+def test_batch_rejects_mixed_members(lbm):
+    a = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f32")
+    c = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f64")
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([a, c])
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([a, a])
