@@ -382,10 +382,14 @@ class Batch:
     def step(self, n: int) -> None:
         self._ck(self._lib.lbm_batch_step(self._h, int(n)), "lbm_batch_step")
 
-    def invariants(self) -> np.ndarray:
-        """(n, 3): flux, mass, mass deviation per member."""
+    def invariants(self, raise_on_divergence: bool = True) -> np.ndarray:
+        """(n, 3): flux, mass, mass deviation per member.  With
+        raise_on_divergence=False a member whose flux or mass is not finite
+        shows up as NaN/Inf in its row instead of raising."""
         out = np.zeros(3 * len(self.channels))
-        self._ck(self._lib.lbm_batch_invariants(self._h, _dptr(out)), "lbm_batch_invariants")
+        rc = self._lib.lbm_batch_invariants(self._h, _dptr(out))
+        if rc != 0 and not (rc == -5 and not raise_on_divergence):
+            self._ck(rc, "lbm_batch_invariants")
         return out.reshape(-1, 3)
 
     def tune(self) -> int:

@@ -1,0 +1,288 @@
+"""Continuous-batching serving loop for nanotube design queries.
+
+A query is a nanotube design: radius R (box 512 x (2R+8)^2), relaxation time,
+pressure-gradient force and the spectral parameters of its wall friction
+(paper Sec. 5.1: permeability of carbon nanotubes against diameter and
+charge-carrier density).  The server
+
+* admits arrived queries while their device footprint fits the HBM budget
+  (each admitted query owns a context whose state stays resident on the GPU);
+* computes each query's wall friction with the GPU quadrature once;
+* advances every active query together through one batch (one kernel launch
+  per step, graph-replayed) in chunks of ``check_every`` steps;
+* retires a query when its flux changes by less than ``rel_tol`` relative over
+  ``check_every`` steps of its own step counter, and frees its memory.
+
+``mode="f32"`` runs every query in FP32 storage (FP64 arithmetic).
+``mode="mixed"`` runs a query first with half-precision storage (FP32
+arithmetic) until its flux change per check falls below ``switch_tol`` or
+stops shrinking, then hands its state to an FP32 context
+(``lbm_transfer_state``) which converges to the same ``rel_tol``: both modes
+end at the same accuracy.
+
+Scheduling, admission and bookkeeping are host logic here; every numerical
+step runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from collections import deque
+from dataclasses import asdict, dataclass, field
+
+import numpy as np
+
+from . import inputs, lbm
+
+
+@dataclass
+class Result:
+    qid: int
+    radius: int
+    tau: float
+    arrival_s: float
+    admitted_s: float
+    done_s: float
+    steps: int
+    steps_half: int
+    flux: float
+    status: str  # "ok", "not_converged", "diverged"
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+@dataclass
+class _Slot:
+    query: inputs.Query
+    ch: lbm.Channel
+    phase: str  # "half" or "f32"
+    admitted_s: float
+    reserved: int
+    prev_q: float | None = None
+    prev_rel: float | None = None
+    steps_half: int = 0
+    omega: np.ndarray = field(default=None, repr=False)
+    uid: int = 0  # serial number of the context currently serving the query
+
+
+def tube_params(q: inputs.Query):
+    ny, nz, cy, cz = inputs.tube_box(q.radius)
+    return dict(lattice=lbm.D3Q19, geometry=lbm.TUBE, nx=q.nx, ny=ny, nz=nz, tau=q.tau,
+                force=(q.g, 0.0, 0.0), tube_radius=float(q.radius), tube_cy=cy, tube_cz=cz)
+
+
+def footprint(q: inputs.Query, precision: str) -> int:
+    kw = tube_params(q)
+    p = lbm.make_params(kw["lattice"], kw["geometry"], kw["nx"], kw["ny"], kw["nz"], kw["tau"],
+                        kw["force"], precision, 1.0, kw["tube_radius"], kw["tube_cy"], kw["tube_cz"])
+    return lbm.footprint(p)
+
+
+class Server:
+    def __init__(self, mode: str = "f32", hbm_budget: int = 32 << 30, check_every: int = 1000,
+                 rel_tol: float = 1e-8, switch_tol: float = 1e-5, max_steps: int = 500_000,
+                 tune: bool = True, realtime: bool = True, log=None):
+        assert mode in ("f32", "mixed")
+        self.mode = mode
+        self.budget = int(hbm_budget)
+        self.check_every = int(check_every)
+        self.rel_tol = rel_tol
+        self.switch_tol = switch_tol
+        self.max_steps = max_steps
+        self.tune = tune
+        self.realtime = realtime
+        self.log = log
+        self.shape = None  # workgroup shape chosen by the autotuner
+        self._serial = 0
+        self.stats = {"batch_rebuilds": 0, "chunks": 0, "max_active": 0, "lattice_updates": 0}
+
+    # ------------------------------------------------------------- helpers
+    def _say(self, *a):
+        if self.log:
+            self.log(" ".join(str(x) for x in a))
+
+    def _reserve(self, q) -> int:
+        # mixed mode ends in FP32 and holds both contexts during the hand-off
+        f32 = footprint(q, "f32")
+        return f32 + (footprint(q, "f16s") if self.mode == "mixed" else 0)
+
+    def _open(self, q, precision) -> lbm.Channel:
+        kw = tube_params(q)
+        ch = lbm.Channel(kw["lattice"], kw["geometry"], kw["nx"], kw["ny"], kw["nz"], kw["tau"],
+                         kw["force"], precision, 1.0, kw["tube_radius"], kw["tube_cy"], kw["tube_cz"])
+        return ch
+
+    def _admit(self, q, now) -> _Slot:
+        ch = self._open(q, "f16s" if self.mode == "mixed" else "f32")
+        kw = tube_params(q)
+        om = inputs.tube_plasmon_frequencies(ch.wall_coords(), kw["nx"], q.radius, kw["tube_cy"],
+                                             kw["tube_cz"], q.spectral.omega0,
+                                             inputs.rng_for("serving", 1000 + q.qid))
+        ch.set_friction_spectral(q.spectral, om)
+        self._serial += 1
+        return _Slot(query=q, ch=ch, phase="half" if self.mode == "mixed" else "f32",
+                     admitted_s=now, reserved=self._reserve(q), omega=om, uid=self._serial)
+
+    def _hand_off(self, s: _Slot) -> None:
+        f32 = self._open(s.query, "f32")
+        f32.transfer_from(s.ch)
+        s.ch.close()
+        s.ch = f32
+        s.phase = "f32"
+        s.steps_half = f32.step_count
+        self._serial += 1
+        s.uid = self._serial
+
+    # ------------------------------------------------------------- the loop
+    def run(self, trace: list[inputs.Query]) -> list[Result]:
+        trace = sorted(trace, key=lambda q: q.arrival_s)
+        if not self.realtime:  # saturation: every query is there at t = 0
+            trace = [inputs.Query(**{**q.__dict__, "arrival_s": 0.0}) for q in trace]
+        clock = time.perf_counter
+        t0 = clock()
+        now = lambda: clock() - t0
+        i, n = 0, len(trace)
+        waiting: deque = deque()
+        active: list[_Slot] = []
+        used = 0
+        results: list[Result] = []
+        batches: dict = {}
+        members: dict = {}
+        while i < n or waiting or active:
+            t = now()
+            while i < n and trace[i].arrival_s <= t:
+                waiting.append(trace[i])
+                i += 1
+            # admission by device footprint, first come first served
+            while waiting and used + self._reserve(waiting[0]) <= self.budget:
+                q = waiting.popleft()
+                s = self._admit(q, now())
+                used += s.reserved
+                active.append(s)
+            if waiting and not active:
+                raise RuntimeError(f"query {waiting[0].qid} does not fit the HBM budget")
+            if not active:
+                if i < n and self.realtime:
+                    time.sleep(max(0.0, min(0.05, trace[i].arrival_s - now())))
+                continue
+            self.stats["max_active"] = max(self.stats["max_active"], len(active))
+            # one chunk of check_every steps for every active query, per phase
+            stepped: dict = {}
+            for phase in ("half", "f32"):
+                group = [s for s in active if s.phase == phase]
+                stepped[phase] = group
+                if not group:
+                    batches.pop(phase, None)
+                    members.pop(phase, None)
+                    continue
+                ids = [s.uid for s in group]
+                if members.get(phase) != ids:
+                    old = batches.pop(phase, None)
+                    if old is not None:
+                        old.close()
+                    b = lbm.Batch([s.ch for s in group])
+                    if self.shape is None and self.tune:
+                        self.shape = b.tune()
+                    elif self.shape is not None:
+                        b.set_shape(self.shape)
+                    batches[phase], members[phase] = b, ids
+                    self.stats["batch_rebuilds"] += 1
+                batches[phase].step(self.check_every)
+                self.stats["lattice_updates"] += self.check_every * sum(s.ch.fluid_count for s in group)
+            self.stats["chunks"] += 1
+            # convergence on each query's own step counter
+            retire: list[tuple[_Slot, str, float]] = []
+            for phase in ("half", "f32"):
+                group = stepped[phase]  # as stepped: hand-offs below move slots to "f32"
+                if not group:
+                    continue
+                inv = batches[phase].invariants(raise_on_divergence=False)
+                for k, s in enumerate(group):
+                    q = float(inv[k, 0])
+                    steps = s.ch.step_count
+                    if not math.isfinite(q):
+                        retire.append((s, "diverged", q))
+                        continue
+                    rel = abs(q - s.prev_q) / abs(q) if s.prev_q is not None and q != 0 else math.inf
+                    if phase == "f32" and rel < self.rel_tol:
+                        retire.append((s, "ok", q))
+                    elif steps >= self.max_steps:
+                        retire.append((s, "not_converged", q))
+                    elif phase == "half" and (rel < self.switch_tol or (
+                            rel < 1e-4 and s.prev_rel is not None and rel > 0.7 * s.prev_rel)):
+                        s.prev_rel = rel
+                        s.prev_q = q
+                        self._hand_off(s)
+                        continue
+                    s.prev_rel = rel
+                    s.prev_q = q
+            t_done = now()
+            for s, status, q in retire:
+                active.remove(s)
+                used -= s.reserved
+                steps = s.ch.step_count
+                results.append(Result(qid=s.query.qid, radius=s.query.radius, tau=s.query.tau,
+                                      arrival_s=s.query.arrival_s, admitted_s=s.admitted_s,
+                                      done_s=t_done, steps=steps,
+                                      steps_half=s.steps_half, flux=q, status=status))
+                s.ch.close()
+                self._say(f"done q{s.query.qid} R={s.query.radius} steps={steps} "
+                          f"half={s.steps_half} t={t_done:.2f}s active={len(active)}")
+        for b in batches.values():
+            b.close()
+        return sorted(results, key=lambda r: r.qid)
+
+
+def summarize(results: list[Result], wall_s: float) -> dict:
+    lat = np.array([r.latency_s for r in results])
+    ok = [r for r in results if r.status == "ok"]
+    first = min(r.arrival_s for r in results)
+    last = max(r.done_s for r in results)
+    return {"queries": len(results), "converged": len(ok),
+            "solves_per_s": round(len(ok) / max(last - first, 1e-9), 4),
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+            "makespan_s": round(last - first, 3), "wall_s": round(wall_s, 3),
+            "mean_steps": round(float(np.mean([r.steps for r in results])), 1),
+            "mean_steps_half": round(float(np.mean([r.steps_half for r in results])), 1)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="serve a Poisson trace of nanotube queries")
+    ap.add_argument("--queries", type=int, default=500)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--mode", default="f32", choices=["f32", "mixed"])
+    ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--rmin", type=int, default=8)
+    ap.add_argument("--rmax", type=int, default=32)
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--check-every", type=int, default=1000)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args(argv)
+    import torch
+
+    lbm.load()
+    torch.cuda.set_device(0)
+    trace = inputs.serving_trace(args.queries, args.rate, args.nx, (args.rmin, args.rmax))
+    srv = Server(mode=args.mode, hbm_budget=int(args.budget_gb * (1 << 30)),
+                 check_every=args.check_every,
+                 log=(lambda m: print(m, flush=True)) if args.verbose else None)
+    t0 = time.perf_counter()
+    res = srv.run(trace)
+    wall = time.perf_counter() - t0
+    summ = summarize(res, wall)
+    summ.update(mode=args.mode, rate=args.rate, budget_gb=args.budget_gb,
+                radius=[args.rmin, args.rmax], shape=srv.shape, **srv.stats)
+    print(json.dumps(summ), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump({"summary": summ, "results": [asdict(r) for r in res]}, f)
+
+
+if __name__ == "__main__":
+    main()
