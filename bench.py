@@ -160,6 +160,110 @@ def extras(torch, lbm, inputs, args):
     return out
 
 
+def batch_workload(args):
+    """256 uneven ducts in one batch: throughput and per-channel error after
+    1000 steps for FP64 / FP32 / half storage, then run-to-steady solves/s for
+    FP32 storage against mixed precision (half storage handed to FP32)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_15768_amd import inputs, lbm, serve
+
+    specs = inputs.batch_channels(256)
+    cells = sum(c.nx * c.ny * c.nz for c in specs)
+    out = {"workload": "batch_256_ducts", "channels": len(specs), "cells": cells}
+    fields, fluxes = {}, {}
+    for prec in ("f64", "f32", "f16s"):
+        log("batch:", prec)
+        chs = [serve.open_channel(c, prec, serve.DuctQueries) for c in specs]
+        b = lbm.Batch(chs)
+        shape = b.tune()
+        b.step(64)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        b.step(args.batch_steps - 64)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        n = args.batch_steps - 64
+        inv = b.invariants()
+        fluxes[prec] = inv[:, 0].copy()
+        fields[prec] = [ch.field(1) for ch in chs]
+        bpu = BYTES_PER_UPDATE[prec]
+        out[prec] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1),
+                     "us_per_step": round(ms * 1e3 / n, 2),
+                     "hbm_frac": round(bpu * cells * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "workgroup_items": shape}
+        b.close()
+        for ch in chs:
+            ch.close()
+        del chs
+        torch.cuda.empty_cache()
+    for prec in ("f32", "f16s"):
+        fe = [float(np.max(np.abs(a - r)) / np.max(np.abs(r))) for a, r in zip(fields[prec], fields["f64"])]
+        qe = np.abs(fluxes[prec] / fluxes["f64"] - 1)
+        out[prec].update(field_err_max=float(np.max(fe)), field_err_median=float(np.median(fe)),
+                         flux_err_max=float(np.max(qe)), flux_err_median=float(np.median(qe)))
+    # the FP64 reference against the oracle on the two smallest channels
+    import oracle
+
+    small = sorted(range(len(specs)), key=lambda k: specs[k].nx * specs[k].ny * specs[k].nz)[:2]
+    errs = []
+    for k in small:
+        c = specs[k]
+        o = oracle.Lattice(19, oracle.DUCT, c.nx, c.ny, c.nz, tau=c.tau, force=(c.g, 0, 0))
+        o.set_friction(inputs.duct_friction(o.wall_coords(), c.nx, c.ny, c.nz,
+                                            inputs.rng_for("batch", c.seed_index)))
+        o.step(args.batch_steps)
+        uo = o.fields()[1]
+        errs.append(float(np.max(np.abs(fields["f64"][k] - uo)) / np.max(np.abs(uo))))
+    out["f64_vs_oracle_smallest"] = errs
+    # run to steady: FP32 storage vs mixed, same tolerance
+    for mode in ("f32", "mixed"):
+        log("batch: run to steady", mode)
+        srv = serve.Server(mode=mode, hbm_budget=64 << 30, realtime=False, kind=serve.DuctQueries)
+        t0 = time.perf_counter()
+        res = srv.run(specs)
+        wall = time.perf_counter() - t0
+        sm = serve.summarize(res, wall)
+        sm["lattice_updates"] = srv.stats["lattice_updates"]
+        sm["glups"] = round(srv.stats["lattice_updates"] / wall / 1e9, 2)
+        out["steady_" + mode] = sm
+        out["steady_" + mode + "_flux"] = {r.qid: r.flux for r in res}
+    fa, fb = out.pop("steady_f32_flux"), out.pop("steady_mixed_flux")
+    d = [abs(fb[k] / fa[k] - 1) for k in fa]
+    out["steady_mixed_vs_f32_flux_diff_max"] = float(max(d))
+    out["speedup_mixed_over_f32"] = round(out["steady_f32"]["makespan_s"] /
+                                          out["steady_mixed"]["makespan_s"], 3)
+    print(json.dumps(out), flush=True)
+
+
+def serving_workload(args):
+    """Poisson-arriving nanotube queries (radius 8..32), continuous batching,
+    FP32 storage against mixed precision on the same trace."""
+    import torch
+
+    from paper_2403_15768_amd import inputs, lbm, serve
+
+    trace = inputs.serving_trace(args.queries, args.rate)
+    out = {"workload": "serving_tubes", "queries": len(trace), "rate_per_s": args.rate,
+           "radius": [8, 32], "box": "512 x (2R+8)^2"}
+    for mode in ("f32", "mixed"):
+        log("serving:", mode)
+        srv = serve.Server(mode=mode, hbm_budget=int(args.budget_gb * (1 << 30)), realtime=True)
+        t0 = time.perf_counter()
+        res = srv.run(trace)
+        wall = time.perf_counter() - t0
+        sm = serve.summarize(res, wall)
+        sm.update(max_active=srv.stats["max_active"], batch_rebuilds=srv.stats["batch_rebuilds"],
+                  glups=round(srv.stats["lattice_updates"] / wall / 1e9, 2))
+        out[mode] = sm
+        torch.cuda.empty_cache()
+    out["speedup_mixed_over_f32"] = round(out["f32"]["makespan_s"] / out["mixed"]["makespan_s"], 3)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +274,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--workload", default="duct", choices=["duct", "batch", "serving"],
+                    help="duct: the headline line; batch / serving: their own JSON line")
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--queries", type=int, default=500)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--budget-gb", type=float, default=32.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -184,6 +294,10 @@ def main():
 
     lbm.load()
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return batch_workload(args)
+    if args.workload == "serving":
+        return serving_workload(args)
     log("bench: duct 256x128x64", args.precision, "steps", args.steps)
     ch = make_duct(lbm, inputs, args.precision)
     cells = ch.fluid_count

@@ -137,6 +137,8 @@ class Channel:
     tau: float
     g: float
     seed_index: int
+    qid: int = 0
+    arrival_s: float = 0.0
 
 
 def batch_channels(n: int = 256) -> list[Channel]:
@@ -145,7 +147,7 @@ def batch_channels(n: int = 256) -> list[Channel]:
     for k in range(n):
         out.append(Channel(nx=int(rng.integers(32, 129)), ny=int(rng.integers(32, 65)),
                            nz=int(rng.integers(32, 65)), tau=float(rng.uniform(0.6, 1.2)),
-                           g=float(rng.uniform(0.5e-6, 2e-6)), seed_index=k + 1))
+                           g=float(rng.uniform(0.5e-6, 2e-6)), seed_index=k + 1, qid=k))
     return out
 
 

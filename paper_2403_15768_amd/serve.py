@@ -26,6 +26,7 @@ step runs in the library's kernels.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import time
@@ -65,7 +66,6 @@ class _Slot:
     prev_q: float | None = None
     prev_rel: float | None = None
     steps_half: int = 0
-    omega: np.ndarray = field(default=None, repr=False)
     uid: int = 0  # serial number of the context currently serving the query
 
 
@@ -75,18 +75,57 @@ def tube_params(q: inputs.Query):
                 force=(q.g, 0.0, 0.0), tube_radius=float(q.radius), tube_cy=cy, tube_cz=cz)
 
 
-def footprint(q: inputs.Query, precision: str) -> int:
-    kw = tube_params(q)
+class TubeQueries:
+    """Nanotube design queries: friction from the spectral quadrature."""
+
+    @staticmethod
+    def params(q) -> dict:
+        return tube_params(q)
+
+    @staticmethod
+    def set_friction(ch: lbm.Channel, q) -> None:
+        kw = tube_params(q)
+        om = inputs.tube_plasmon_frequencies(ch.wall_coords(), kw["nx"], q.radius, kw["tube_cy"],
+                                             kw["tube_cz"], q.spectral.omega0,
+                                             inputs.rng_for("serving", 1000 + q.qid))
+        ch.set_friction_spectral(q.spectral, om)
+
+
+class DuctQueries:
+    """Rectangular ducts (inputs.Channel specs): smooth random friction field."""
+
+    @staticmethod
+    def params(q) -> dict:
+        return dict(lattice=lbm.D3Q19, geometry=lbm.DUCT, nx=q.nx, ny=q.ny, nz=q.nz, tau=q.tau,
+                    force=(q.g, 0.0, 0.0), tube_radius=0.0, tube_cy=0.0, tube_cz=0.0)
+
+    @staticmethod
+    def set_friction(ch: lbm.Channel, q) -> None:
+        ch.set_friction(inputs.duct_friction(ch.wall_coords(), q.nx, q.ny, q.nz,
+                                             inputs.rng_for("batch", q.seed_index)))
+
+
+def footprint(q, precision: str, kind=TubeQueries) -> int:
+    kw = kind.params(q)
     p = lbm.make_params(kw["lattice"], kw["geometry"], kw["nx"], kw["ny"], kw["nz"], kw["tau"],
                         kw["force"], precision, 1.0, kw["tube_radius"], kw["tube_cy"], kw["tube_cz"])
     return lbm.footprint(p)
 
 
+def open_channel(q, precision: str, kind=TubeQueries) -> lbm.Channel:
+    kw = kind.params(q)
+    ch = lbm.Channel(kw["lattice"], kw["geometry"], kw["nx"], kw["ny"], kw["nz"], kw["tau"],
+                     kw["force"], precision, 1.0, kw["tube_radius"], kw["tube_cy"], kw["tube_cz"])
+    kind.set_friction(ch, q)
+    return ch
+
+
 class Server:
     def __init__(self, mode: str = "f32", hbm_budget: int = 32 << 30, check_every: int = 1000,
                  rel_tol: float = 1e-8, switch_tol: float = 1e-5, max_steps: int = 500_000,
-                 tune: bool = True, realtime: bool = True, log=None):
+                 tune: bool = True, realtime: bool = True, log=None, kind=TubeQueries):
         assert mode in ("f32", "mixed")
+        self.kind = kind
         self.mode = mode
         self.budget = int(hbm_budget)
         self.check_every = int(check_every)
@@ -107,25 +146,21 @@ class Server:
 
     def _reserve(self, q) -> int:
         # mixed mode ends in FP32 and holds both contexts during the hand-off
-        f32 = footprint(q, "f32")
-        return f32 + (footprint(q, "f16s") if self.mode == "mixed" else 0)
+        f32 = footprint(q, "f32", self.kind)
+        return f32 + (footprint(q, "f16s", self.kind) if self.mode == "mixed" else 0)
 
     def _open(self, q, precision) -> lbm.Channel:
-        kw = tube_params(q)
-        ch = lbm.Channel(kw["lattice"], kw["geometry"], kw["nx"], kw["ny"], kw["nz"], kw["tau"],
-                         kw["force"], precision, 1.0, kw["tube_radius"], kw["tube_cy"], kw["tube_cz"])
-        return ch
+        kw = self.kind.params(q)
+        return lbm.Channel(kw["lattice"], kw["geometry"], kw["nx"], kw["ny"], kw["nz"], kw["tau"],
+                           kw["force"], precision, 1.0, kw["tube_radius"], kw["tube_cy"],
+                           kw["tube_cz"])
 
     def _admit(self, q, now) -> _Slot:
         ch = self._open(q, "f16s" if self.mode == "mixed" else "f32")
-        kw = tube_params(q)
-        om = inputs.tube_plasmon_frequencies(ch.wall_coords(), kw["nx"], q.radius, kw["tube_cy"],
-                                             kw["tube_cz"], q.spectral.omega0,
-                                             inputs.rng_for("serving", 1000 + q.qid))
-        ch.set_friction_spectral(q.spectral, om)
+        self.kind.set_friction(ch, q)
         self._serial += 1
         return _Slot(query=q, ch=ch, phase="half" if self.mode == "mixed" else "f32",
-                     admitted_s=now, reserved=self._reserve(q), omega=om, uid=self._serial)
+                     admitted_s=now, reserved=self._reserve(q), uid=self._serial)
 
     def _hand_off(self, s: _Slot) -> None:
         f32 = self._open(s.query, "f32")
@@ -139,9 +174,9 @@ class Server:
 
     # ------------------------------------------------------------- the loop
     def run(self, trace: list[inputs.Query]) -> list[Result]:
-        trace = sorted(trace, key=lambda q: q.arrival_s)
+        trace = sorted(trace, key=lambda q: getattr(q, "arrival_s", 0.0))
         if not self.realtime:  # saturation: every query is there at t = 0
-            trace = [inputs.Query(**{**q.__dict__, "arrival_s": 0.0}) for q in trace]
+            trace = [dataclasses.replace(q, arrival_s=0.0) for q in trace]
         clock = time.perf_counter
         t0 = clock()
         now = lambda: clock() - t0
@@ -154,7 +189,7 @@ class Server:
         members: dict = {}
         while i < n or waiting or active:
             t = now()
-            while i < n and trace[i].arrival_s <= t:
+            while i < n and getattr(trace[i], "arrival_s", 0.0) <= t:
                 waiting.append(trace[i])
                 i += 1
             # admission by device footprint, first come first served
@@ -225,12 +260,14 @@ class Server:
                 active.remove(s)
                 used -= s.reserved
                 steps = s.ch.step_count
-                results.append(Result(qid=s.query.qid, radius=s.query.radius, tau=s.query.tau,
-                                      arrival_s=s.query.arrival_s, admitted_s=s.admitted_s,
+                results.append(Result(qid=s.query.qid, radius=getattr(s.query, "radius", 0),
+                                      tau=s.query.tau,
+                                      arrival_s=getattr(s.query, "arrival_s", 0.0),
+                                      admitted_s=s.admitted_s,
                                       done_s=t_done, steps=steps,
                                       steps_half=s.steps_half, flux=q, status=status))
                 s.ch.close()
-                self._say(f"done q{s.query.qid} R={s.query.radius} steps={steps} "
+                self._say(f"done q{s.query.qid} steps={steps} "
                           f"half={s.steps_half} t={t_done:.2f}s active={len(active)}")
         for b in batches.values():
             b.close()
