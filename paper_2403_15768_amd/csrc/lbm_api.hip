@@ -99,7 +99,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   };
 
   pl.colinfo.assign(pl.ncolbox, ColInfo{-1, lbm::kSolidColumn});
-  pl.active.clear();
+  pl.slots.clear();
   pl.wallcols.clear();
   std::vector<int32_t> interior;
   for (int z = 0; z < p->nz; z++)
@@ -120,8 +120,9 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     }
   // wall columns first: their blocks do more work, so they start early
   // instead of forming the tail of the grid
-  pl.active = pl.wallcols;
-  pl.active.insert(pl.active.end(), interior.begin(), interior.end());
+  for (int32_t col : pl.wallcols)
+    pl.slots.push_back(lbm::ColSlot{col, pl.colinfo[col].wallcol, pl.colinfo[col].mask, 0});
+  for (int32_t col : interior) pl.slots.push_back(lbm::ColSlot{col, -1, 0u, 0});
   const int64_t nwc = (int64_t)pl.wallcols.size();
   pl.linkq.assign(nwc * pl.Q, 0.0);
   if (pl.bouz) pl.bzc.assign(nwc * pl.Q * 2, 0.0);
@@ -154,24 +155,25 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
       }
     }
   }
-  if (pl.active.empty()) {
+  if (pl.slots.empty()) {
     if (err) *err = "geometry has no fluid cell";
     return LBM_EINVAL;
   }
-  pl.nfluid = (int64_t)pl.active.size() * pl.nx;
+  pl.nfluid = (int64_t)pl.slots.size() * pl.nx;
   pl.nwall = nwc * pl.nx;
   pl.bx = std::min((pl.nx + 63) / 64 * 64, 512);
   pl.segs = (pl.nx + pl.bx - 1) / pl.bx;
-  pl.nblocks = (int64_t)pl.active.size() * pl.segs;
+  pl.nblocks = (int64_t)pl.slots.size() * pl.segs;
   if (pl.nblocks >= ((int64_t)1 << 31)) {
     if (err) *err = "grid too large";
     return LBM_EINVAL;
   }
 
   // every load the step kernel issues must land on a fluid column of the box
-  for (int32_t col : pl.active) {
+  for (const lbm::ColSlot& cs : pl.slots) {
+    const int col = cs.col;
     const int y = col % p->ny, z = col / p->ny;
-    const ColInfo ci = pl.colinfo[col];
+    const ColInfo ci{cs.wallcol, cs.mask};
     for (int i = 0; i < pl.Q; i++) {
       const bool wall = ci.mask & (1u << i);
       if (!wall && !fluid_at(y - lat_c(pl.Q, i, 1), z - lat_c(pl.Q, i, 2))) {
@@ -195,8 +197,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   };
   pl.off_pop[0] = take(pl.pop_bytes);
   pl.off_pop[1] = take(pl.pop_bytes);
-  pl.off_active = take(pl.active.size() * sizeof(int32_t));
-  pl.off_colinfo = take(pl.colinfo.size() * sizeof(ColInfo));
+  pl.off_slots = take(pl.slots.size() * sizeof(lbm::ColSlot));
   pl.off_r = take((size_t)pl.nwall * pl.wsize);
   pl.off_bz = take(pl.bouz ? (size_t)nwc * pl.Q * 2 * pl.wsize : 0);
   pl.off_lambda = take((size_t)pl.nwall * sizeof(double));
@@ -238,12 +239,11 @@ void fill_args(lbm_ctx* c) {
   a.nz = pl.nz;
   a.sI = pl.sI;
   a.sC = pl.sC;
-  a.nactive = (int)pl.active.size();
+  a.nactive = (int)pl.slots.size();
   a.bx = pl.bx;
   a.segs = pl.segs;
   a.slab = c->p.geometry == LBM_SLAB;
-  a.active = c->at<int32_t>(pl.off_active);
-  a.colinfo = c->at<ColInfo>(pl.off_colinfo);
+  a.slots = c->at<lbm::ColSlot>(pl.off_slots);
   a.rwall = c->at<void>(pl.off_r);
   a.bz = pl.bouz ? c->at<void>(pl.off_bz) : nullptr;
   a.rho0 = c->p.rho0;
@@ -431,8 +431,7 @@ lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void
   lbm_status st = LBM_OK;
   do {
     if ((st = c->hip(hipMemsetAsync(c->arena, 0, pl.total, c->stream), "hipMemsetAsync")) != LBM_OK) break;
-    if ((st = upload(c, pl.off_active, pl.active.data(), pl.active.size() * sizeof(int32_t))) != LBM_OK) break;
-    if ((st = upload(c, pl.off_colinfo, pl.colinfo.data(), pl.colinfo.size() * sizeof(ColInfo))) != LBM_OK) break;
+    if ((st = upload(c, pl.off_slots, pl.slots.data(), pl.slots.size() * sizeof(lbm::ColSlot))) != LBM_OK) break;
     std::vector<double> inf(pl.nwall, INFINITY);
     std::vector<double> ones(pl.nwall, 1.0);
     if ((st = upload(c, pl.off_lambda, inf.data(), inf.size() * sizeof(double))) != LBM_OK) break;

@@ -3,10 +3,14 @@
 // A batch groups existing contexts (same lattice, storage precision and wall
 // kind; any sizes and parameters).  Its work list holds one item per 64-cell
 // x-segment of every fluid column of every member, wall segments first; one
-// wave updates one item.  Members keep their own buffers, parameters and step
-// counters: a member's step number decides which of its two buffers is
-// current and which stochastic-rounding bits it uses, so a channel advanced
-// inside a batch is bit-identical to the same channel advanced alone.
+// wave updates one item, and every item carries its column's record so that
+// a wave's set-up is one chain of two scalar loads (item, member).  Members
+// keep their own buffers, parameters and step counters: a member's step
+// number decides which of its two buffers is current and which
+// stochastic-rounding bits it uses, so a channel advanced inside a batch is
+// bit-identical to the same channel advanced alone.  On the device the batch
+// keeps one counter, the steps taken since its member table was written; a
+// member's step is its base step plus that counter.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,8 +33,10 @@ struct lbm_batch {
   bool bouz = false;
   int64_t nitems = 0;
   int wpb = 4;  // waves (work items) per workgroup, set by lbm_batch_tune
+  int64_t k = 0;                  // steps since the member table was written
+  std::vector<int64_t> base;      // each member's step when the table was written
   size_t off_desc = 0, off_items = 0, off_order = 0, off_mstart = 0, off_partials = 0,
-         off_out = 0, off_steps = 0, total = 0;
+         off_out = 0, off_bstep = 0, total = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_wpb = 0;
@@ -76,12 +82,14 @@ void make_lists(lbm_ctx* const* ctxs, int n, Lists* L) {
       const Plan& pl = ctxs[m]->pl;
       const int nwc = (int)pl.wallcols.size();
       const int segs = (pl.nx + 63) / 64;
-      const int lo = pass == 0 ? 0 : nwc, hi = pass == 0 ? nwc : (int)pl.active.size();
-      for (int slot = lo; slot < hi; slot++)
+      const int lo = pass == 0 ? 0 : nwc, hi = pass == 0 ? nwc : (int)pl.slots.size();
+      for (int slot = lo; slot < hi; slot++) {
+        const lbm::ColSlot& cs = pl.slots[slot];
         for (int sg = 0; sg < segs; sg++) {
           mine[m].push_back((int32_t)L->items.size());
-          L->items.push_back(WorkItem{m, slot, sg * 64, 0});
+          L->items.push_back(WorkItem{m, cs.col, cs.wallcol, cs.mask, sg * 64, 0, 0, 0});
         }
+      }
     }
   L->order.clear();
   L->mstart.assign(n + 1, 0);
@@ -119,13 +127,13 @@ void layout(lbm_batch* b, int n, int64_t nitems) {
   b->off_mstart = take((n + 1) * sizeof(int64_t));
   b->off_partials = take(nitems * 2 * sizeof(double));
   b->off_out = take(n * 2 * sizeof(double));
-  b->off_steps = take(n * sizeof(int64_t*));
+  b->off_bstep = take(sizeof(int64_t));
   b->total = off;
 }
 
 int64_t count_items(lbm_ctx* const* ctxs, int n) {
   int64_t t = 0;
-  for (int m = 0; m < n; m++) t += (int64_t)ctxs[m]->pl.active.size() * ((ctxs[m]->pl.nx + 63) / 64);
+  for (int m = 0; m < n; m++) t += (int64_t)ctxs[m]->pl.slots.size() * ((ctxs[m]->pl.nx + 63) / 64);
   return t;
 }
 
@@ -134,27 +142,62 @@ lbm_status launch_batch(lbm_batch* b, int64_t step_off, int wpb) {
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   int64_t nitems = b->nitems;
-  void* args[5] = {(void*)&md, (void*)&items, (void*)&nitems, (void*)&step_off, (void*)&wpb};
+  const int64_t* bstep = b->at<int64_t>(b->off_bstep);
+  void* args[6] = {(void*)&md,    (void*)&items,    (void*)&nitems,
+                   (void*)&bstep, (void*)&step_off, (void*)&wpb};
   const dim3 grid((unsigned)((nitems + wpb - 1) / wpb)), block(64 * wpb);
   BCHK(b, hipLaunchKernel(fn, grid, block, args, 0, b->stream));
   return LBM_OK;
 }
 
 lbm_status launch_bump(lbm_batch* b, int64_t v) {
-  const void* fn = lbm::batch_add_step_kernel_ptr();
-  int64_t* const* steps = b->at<int64_t* const>(b->off_steps);
-  int n = (int)b->m.size();
-  void* args[3] = {(void*)&steps, (void*)&n, (void*)&v};
-  BCHK(b, hipLaunchKernel(fn, dim3((n + 255) / 256), dim3(256), args, 0, b->stream));
+  const void* fn = lbm::add_step_kernel_ptr();
+  int64_t* d = b->at<int64_t>(b->off_bstep);
+  void* args[2] = {(void*)&d, (void*)&v};
+  BCHK(b, hipLaunchKernel(fn, dim3(1), dim3(64), args, 0, b->stream));
   return LBM_OK;
 }
 
+// the members' own device step bases are not advanced by batch steps
+constexpr int64_t kStale = INT64_MIN;
+
 void advance_members(lbm_batch* b, int64_t k) {
+  b->k += k;
   for (lbm_ctx* c : b->m) {
     c->step += k;
-    c->dstep_value += k;
+    c->dstep_value = kStale;
     if (k & 1) c->cur = 1 - c->cur;
   }
+}
+
+MemberDesc describe(const lbm_ctx* c, int64_t k) {
+  MemberDesc d;
+  std::memset(&d, 0, sizeof d);
+  d.a = c->args;
+  d.a.dstep = nullptr;
+  d.a.step_off = 0;
+  d.pop[0] = c->pop[0];
+  d.pop[1] = c->pop[1];
+  d.base_step = c->step - k;
+  d.cur_base = (int32_t)((c->cur + k) & 1);  // (cur_base + k) & 1 == cur
+  return d;
+}
+
+// A member stepped, restored or overwritten outside the batch no longer sits
+// at base + k: rewrite its table entry (after its own queued work).
+lbm_status resync(lbm_batch* b) {
+  for (size_t m = 0; m < b->m.size(); m++) {
+    lbm_ctx* c = b->m[m];
+    if (c->step == b->base[m] + b->k) continue;
+    lbm_status s = sync(c);
+    if (s != LBM_OK) return b->fail(s, "member stream failed");
+    const MemberDesc d = describe(c, b->k);
+    BCHK(b, hipMemcpyAsync(b->at<MemberDesc>(b->off_desc) + m, &d, sizeof d,
+                           hipMemcpyHostToDevice, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    b->base[m] = d.base_step;
+  }
+  return LBM_OK;
 }
 
 lbm_status build_graph(lbm_batch* b) {
@@ -171,13 +214,15 @@ lbm_status build_graph(lbm_batch* b) {
   const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
+  const int64_t* bstep = b->at<int64_t>(b->off_bstep);
   int64_t nitems = b->nitems;
   int wpb = b->wpb;
   hipGraphNode_t prev = nullptr;
   int64_t offs[kGraphSteps];
   for (int k = 0; k < kGraphSteps; k++) {
     offs[k] = k;
-    void* args[5] = {(void*)&md, (void*)&items, (void*)&nitems, (void*)&offs[k], (void*)&wpb};
+    void* args[6] = {(void*)&md,    (void*)&items,   (void*)&nitems,
+                     (void*)&bstep, (void*)&offs[k], (void*)&wpb};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
     kp.gridDim = dim3((unsigned)((nitems + wpb - 1) / wpb));
@@ -192,14 +237,13 @@ lbm_status build_graph(lbm_batch* b) {
     prev = node;
   }
   {
-    int64_t* const* steps = b->at<int64_t* const>(b->off_steps);
-    int n = (int)b->m.size();
+    int64_t* d = b->at<int64_t>(b->off_bstep);
     int64_t inc = kGraphSteps;
-    void* args[3] = {(void*)&steps, (void*)&n, (void*)&inc};
+    void* args[2] = {(void*)&d, (void*)&inc};
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(lbm::batch_add_step_kernel_ptr());
-    kp.gridDim = dim3((n + 255) / 256);
-    kp.blockDim = dim3(256);
+    kp.func = const_cast<void*>(lbm::add_step_kernel_ptr());
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
     kp.kernelParams = args;
     hipGraphNode_t node = nullptr;
     hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &kp);
@@ -259,24 +303,17 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   b->arena = static_cast<char*>(arena);
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<MemberDesc> desc(n);
-  std::vector<int64_t*> steps(n);
+  b->base.assign(n, 0);
   for (int m = 0; m < n; m++) {
     lbm_ctx* c = ctxs[m];
     if ((s = sync(c)) != LBM_OK) {
       delete b;
       return s;
     }
-    MemberDesc& d = desc[m];
-    std::memset(&d, 0, sizeof d);
-    d.a = c->args;
-    d.a.dstep = c->at<int64_t>(c->pl.off_step);
-    d.a.step_off = 0;
-    d.pop[0] = c->pop[0];
-    d.pop[1] = c->pop[1];
-    d.base_step = c->step;
-    d.cur_base = c->cur;
-    steps[m] = c->at<int64_t>(c->pl.off_step);
+    desc[m] = describe(c, 0);
+    b->base[m] = c->step;
   }
+  const int64_t zero = 0;
   lbm_status st = LBM_OK;
   do {
     if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_desc), desc.data(), n * sizeof(MemberDesc),
@@ -290,16 +327,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
     if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_mstart), L.mstart.data(),
                                     L.mstart.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                                     b->stream), "upload")) != LBM_OK) break;
-    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_steps), steps.data(), n * sizeof(int64_t*),
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_bstep), &zero, sizeof zero,
                                     hipMemcpyHostToDevice, b->stream), "upload")) != LBM_OK) break;
-    // every member's device step base must hold its current step
-    for (lbm_ctx* c : b->m)
-      if (c->dstep_value != c->step) {
-        if ((st = b->hip(lbm::launch_set_step(c->at<int64_t>(c->pl.off_step), c->step, b->stream),
-                         "launch_set_step")) != LBM_OK) break;
-        c->dstep_value = c->step;
-      }
-    if (st != LBM_OK) break;
     st = b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   } while (0);
   if (st != LBM_OK) {
@@ -325,6 +354,9 @@ lbm_status lbm_batch_items(const lbm_batch* b, int64_t* nitems) {
 
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
+  if (nsteps == 0) return LBM_OK;
+  lbm_status rs = resync(b);
+  if (rs != LBM_OK) return rs;
   while (nsteps >= kGraphSteps && b->graphs_ok) {
     if (!b->gexec || b->graph_wpb != b->wpb) {
       if (build_graph(b) != LBM_OK) {
@@ -350,9 +382,11 @@ lbm_status lbm_batch_invariants(lbm_batch* b, double* out) {
   if (!b || !out) return LBM_EINVAL;
   const int n = (int)b->m.size();
   double* dout = b->at<double>(b->off_out);
+  lbm_status rs = resync(b);
+  if (rs != LBM_OK) return rs;
   BCHK(b, lbm::launch_batch_moments(b->Q, b->prec, b->at<MemberDesc>(b->off_desc),
                                     b->at<WorkItem>(b->off_items), b->nitems,
-                                    b->at<double>(b->off_partials), b->at<int32_t>(b->off_order),
+                                    b->at<int64_t>(b->off_bstep), b->at<double>(b->off_partials), b->at<int32_t>(b->off_order),
                                     b->at<int64_t>(b->off_mstart), n, dout, b->bouz, b->stream));
   std::vector<double> h(2 * n);
   BCHK(b, hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -371,6 +405,8 @@ lbm_status lbm_batch_invariants(lbm_batch* b, double* out) {
 
 lbm_status lbm_batch_tune(lbm_batch* b, int* chosen) {
   if (!b) return LBM_EINVAL;
+  lbm_status rs = resync(b);
+  if (rs != LBM_OK) return rs;
   // time each candidate shape on launches whose results land in the buffers
   // the next step overwrites anyway (counters unchanged)
   static const int cand[4] = {1, 2, 4, 8};

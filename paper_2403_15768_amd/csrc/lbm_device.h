@@ -55,6 +55,15 @@ struct ColInfo {
   uint32_t mask;    // bit i: link i pulls from a solid point; kSolidColumn
 };
 
+// One fluid column as the kernels see it: everything a wave needs about its
+// column in one 16-byte record (one scalar load, no dependent lookups).
+struct ColSlot {
+  int32_t col;
+  int32_t wallcol;
+  uint32_t mask;
+  int32_t pad;
+};
+
 struct StepArgs {
   int nx, nxp, ny, nz;
   int64_t sI;         // elements between the x-lines of two directions (nxp)
@@ -63,8 +72,7 @@ struct StepArgs {
   int bx;             // threads per block along x
   int segs;           // blocks per column = ceil(nx / bx)
   int slab;           // z periodic
-  const int32_t* active;    // fluid column ids
-  const ColInfo* colinfo;   // per box column
+  const ColSlot* slots;     // fluid columns, wall columns first
   const void* rwall;        // [wallcol][nx] wall mixing weight r (arithmetic type)
   const void* bz;           // [wallcol][Q][2] interpolated bounce-back coefs (b, c) or null
   double rho0, omega;       // omega = 1/tau
@@ -89,10 +97,10 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 }
 
 // ------------------------------------------------------------------ batches
-// One member of a batch: its step arguments (a.dstep points at the member's
-// own step base), its two population buffers, and the buffer that held its
-// state at step base_step.  Buffer parity follows from the step:
-// src = pop[(cur_base + step - base_step) & 1].
+// One member of a batch: its step arguments, its two population buffers,
+// its step and current buffer when the batch was built.  With k the steps
+// the batch has taken since (one device counter for the whole batch), the
+// member is at step base_step + k and its state is in pop[(cur_base + k) & 1].
 struct MemberDesc {
   StepArgs a;
   const void* pop[2];
@@ -101,9 +109,12 @@ struct MemberDesc {
   int32_t pad;
 };
 
-// A batch work item: one 64-cell x-segment of one fluid column of one member.
+// A batch work item: one 64-cell x-segment of one fluid column of one
+// member, with that column's record inlined.
 struct WorkItem {
-  int32_t member, slot, x0, pad;
+  int32_t member, col, wallcol;
+  uint32_t mask;
+  int32_t x0, pad0, pad1, pad2;
 };
 
 // ------------------------------------------------------------------ storage

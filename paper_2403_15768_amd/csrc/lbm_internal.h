@@ -27,8 +27,8 @@ struct Plan {
   size_t ssize = 0, wsize = 0;  // storage bytes, wall-table bytes per value
   int nx = 0, nxp = 0, ny = 0, nz = 0;
   int64_t ncolbox = 0, sI = 0, sC = 0;  // layout g[col][i][x]: col * sC + i * sI + x
-  std::vector<int32_t> active;     // fluid column ids: wall columns, then interior ones
-  std::vector<ColInfo> colinfo;    // per box column
+  std::vector<lbm::ColSlot> slots;  // fluid columns: wall columns, then interior ones
+  std::vector<ColInfo> colinfo;     // per box column (host only)
   std::vector<int32_t> wallcols;   // column id of each wall column, increasing
   std::vector<double> linkq;       // [wallcol][Q] wall fraction (0: no wall link)
   std::vector<double> bzc;         // [wallcol][Q][2] interpolation coefficients b, c (TUBE)
@@ -38,7 +38,7 @@ struct Plan {
   bool bouz = false;
   // arena offsets
   size_t off_pop[2] = {0, 0}, pop_bytes = 0;
-  size_t off_active = 0, off_colinfo = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
+  size_t off_slots = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
          off_partials = 0, off_out = 0, off_flag = 0, off_step = 0, total = 0;
 };
 

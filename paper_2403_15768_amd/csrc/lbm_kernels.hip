@@ -15,7 +15,6 @@
 //  k_batch_step     k_step over the work list of a batch of channels, one
 //                   64-cell line segment per wave
 //  k_batch_moments, k_batch_reduce   per-member flux and mass of a batch
-//  k_batch_add_step advance every member's step base
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -34,16 +33,22 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   const int slot = blockIdx.x / a.segs;
   const int seg = blockIdx.x - slot * a.segs;
   const int x = seg * a.bx + threadIdx.x;
-  if (x >= a.nx) return;
-  const int col = uniform(gbl(a.active)[slot]);
+  if (x >= a.nxp) return;
+  // Lanes on the padding of an x-line (nx <= x < nxp) recompute cell nx - 1
+  // and store it into the padding, so every cache line of the output is
+  // written whole (a partly written line costs HBM a read-modify-write).
+  // Nothing reads the padding.
+  const int xc = x < a.nx ? x : a.nx - 1;
+  const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[slot];
+  const int col = uniform(cs.col);
   ColInfo info;
-  info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
-  info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
+  info.wallcol = uniform(cs.wallcol);
+  info.mask = (uint32_t)uniform((int)cs.mask);
   const int y = col % a.ny;
   const int z = col / a.ny;
   const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
   M df[L::Q];
-  gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
+  gather<L, S, M, M, BOUZ>(src, a, col, y, z, xc, info, df);
   collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
                          (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step);
 }
@@ -65,10 +70,11 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
   const int x = seg * a.bx + threadIdx.x;
   double jx_cell = 0.0, drho_cell = 0.0;
   if (x < a.nx) {
-    const int col = uniform(gbl(a.active)[slot]);
+    const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[slot];
+    const int col = uniform(cs.col);
     ColInfo info;
-    info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
-    info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
+    info.wallcol = uniform(cs.wallcol);
+    info.mask = (uint32_t)uniform((int)cs.mask);
     const int y = col % a.ny;
     const int z = col / a.ny;
     double df[L::Q];
@@ -270,31 +276,35 @@ __global__ void __launch_bounds__(256) k_convert(const A* __restrict__ in, B* __
 template <class L, typename S, typename M, bool BOUZ>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
-                                                    int64_t nitems, int64_t step_off, int wpb) {
+                                                    int64_t nitems, const int64_t* __restrict__ bstep,
+                                                    int64_t step_off, int wpb) {
   // wave index in a scalar register: the item and member are wave-uniform
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t it = (int64_t)blockIdx.x * wpb + wv;
   if (it >= nitems) return;
   const WorkItem item = items[it];
   const MemberDesc& d = md[item.member];
-  StepArgs a = d.a;
-  a.step_off = step_off;
+  const int64_t k = uniform64(*gbl(bstep)) + step_off;  // steps since the batch was built
+  const StepArgs& a = d.a;
   const int x = item.x0 + (int)(threadIdx.x & 63);
-  if (x >= a.nx) return;
-  const int64_t n = uniform64(*gbl(a.dstep)) + step_off;
-  const int par = (int)((d.cur_base + (n - d.base_step)) & 1);
-  const S* src = static_cast<const S*>(d.pop[par]);
-  S* dst = static_cast<S*>(const_cast<void*>(d.pop[par ^ 1]));
-  const int col = uniform(gbl(a.active)[item.slot]);
+  if (x >= a.nxp) return;
+  const int xc = x < a.nx ? x : a.nx - 1;  // padding lanes: as in k_step
+  // both pointers loaded up front, then selected: no load waits on the parity
+  const void* p0 = d.pop[0];
+  const void* p1 = d.pop[1];
+  const bool odd = ((d.cur_base + k) & 1) != 0;
+  const S* src = static_cast<const S*>(odd ? p1 : p0);
+  S* dst = static_cast<S*>(const_cast<void*>(odd ? p0 : p1));
+  const int col = item.col;
   ColInfo info;
-  info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
-  info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
+  info.wallcol = item.wallcol;
+  info.mask = item.mask;
   const int y = col % a.ny;
   const int z = col / a.ny;
   M df[L::Q];
-  gather<L, S, M, M, BOUZ>(src, a, col, y, z, x, info, df);
+  gather<L, S, M, M, BOUZ>(src, a, col, y, z, xc, info, df);
   collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, n);
+                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, d.base_step + k);
 }
 
 // per-item partial sums of (j_x, rho - rho0); one wave per item
@@ -302,6 +312,7 @@ template <class L, typename S, typename W, bool BOUZ>
 __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restrict__ md,
                                                        const WorkItem* __restrict__ items,
                                                        int64_t nitems,
+                                                       const int64_t* __restrict__ bstep,
                                                        double* __restrict__ partials) {
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t it = (int64_t)blockIdx.x * 4 + wv;
@@ -312,13 +323,12 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
   const int x = item.x0 + (int)(threadIdx.x & 63);
   double jx = 0.0, dr = 0.0;
   if (x < a.nx) {
-    const int64_t n = uniform64(*gbl(a.dstep));
-    const int par = (int)((d.cur_base + (n - d.base_step)) & 1);
+    const int par = (int)((d.cur_base + uniform64(*gbl(bstep))) & 1);
     const S* src = static_cast<const S*>(d.pop[par]);
-    const int col = uniform(gbl(a.active)[item.slot]);
+    const int col = item.col;
     ColInfo info;
-    info.wallcol = uniform(gbl(a.colinfo)[col].wallcol);
-    info.mask = (uint32_t)uniform((int)gbl(a.colinfo)[col].mask);
+    info.wallcol = item.wallcol;
+    info.mask = item.mask;
     double df[L::Q];
     gather<L, S, double, W, BOUZ>(src, a, col, col % a.ny, col / a.ny, x, info, df);
 #pragma unroll
@@ -365,11 +375,6 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__
   }
 }
 
-__global__ void k_batch_add_step(int64_t* const* __restrict__ steps, int n, int64_t v) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < n) *steps[m] += v;
-}
-
 // ------------------------------------------------------------ step base
 __global__ void k_set_step(int64_t* __restrict__ d, int64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *d = v;
@@ -400,31 +405,33 @@ const void* batch_step_kernel_ptr(int q, int prec, bool bouz) {
   if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz);
   return batch_kernel_t<D3Q19, _Float16, float>(bouz);
 }
-const void* batch_add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_batch_add_step); }
 
 template <class L, typename S, typename W>
 static hipError_t batch_moments_t(const MemberDesc* md, const WorkItem* items, int64_t nitems,
-                                  double* partials, bool bouz, hipStream_t st) {
+                                  const int64_t* bstep, double* partials, bool bouz,
+                                  hipStream_t st) {
   const dim3 grid((unsigned)((nitems + 3) / 4)), block(256);
   if (bouz)
-    hipLaunchKernelGGL((k_batch_moments<L, S, W, true>), grid, block, 0, st, md, items, nitems, partials);
+    hipLaunchKernelGGL((k_batch_moments<L, S, W, true>), grid, block, 0, st, md, items, nitems,
+                       bstep, partials);
   else
-    hipLaunchKernelGGL((k_batch_moments<L, S, W, false>), grid, block, 0, st, md, items, nitems, partials);
+    hipLaunchKernelGGL((k_batch_moments<L, S, W, false>), grid, block, 0, st, md, items, nitems,
+                       bstep, partials);
   return hipGetLastError();
 }
 hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,
-                                int64_t nitems, double* partials, const int32_t* order,
-                                const int64_t* mstart, int nmembers, double* out, bool bouz,
-                                hipStream_t st) {
+                                int64_t nitems, const int64_t* bstep, double* partials,
+                                const int32_t* order, const int64_t* mstart, int nmembers,
+                                double* out, bool bouz, hipStream_t st) {
   hipError_t e;
   if (q == 9)
-    e = prec == 0 ? batch_moments_t<D2Q9, double, double>(md, items, nitems, partials, bouz, st)
-      : prec == 1 ? batch_moments_t<D2Q9, float, double>(md, items, nitems, partials, bouz, st)
-                  : batch_moments_t<D2Q9, _Float16, float>(md, items, nitems, partials, bouz, st);
+    e = prec == 0 ? batch_moments_t<D2Q9, double, double>(md, items, nitems, bstep, partials, bouz, st)
+      : prec == 1 ? batch_moments_t<D2Q9, float, double>(md, items, nitems, bstep, partials, bouz, st)
+                  : batch_moments_t<D2Q9, _Float16, float>(md, items, nitems, bstep, partials, bouz, st);
   else
-    e = prec == 0 ? batch_moments_t<D3Q19, double, double>(md, items, nitems, partials, bouz, st)
-      : prec == 1 ? batch_moments_t<D3Q19, float, double>(md, items, nitems, partials, bouz, st)
-                  : batch_moments_t<D3Q19, _Float16, float>(md, items, nitems, partials, bouz, st);
+    e = prec == 0 ? batch_moments_t<D3Q19, double, double>(md, items, nitems, bstep, partials, bouz, st)
+      : prec == 1 ? batch_moments_t<D3Q19, float, double>(md, items, nitems, bstep, partials, bouz, st)
+                  : batch_moments_t<D3Q19, _Float16, float>(md, items, nitems, bstep, partials, bouz, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_reduce, dim3(nmembers), dim3(256), 0, st, partials, order, mstart, out);
   return hipGetLastError();

@@ -34,12 +34,12 @@ const void* add_step_kernel_ptr();  // k_add_step(int64_t* d, int64_t v)
 hipError_t launch_convert(int pin, const void* in, int pout, void* out, int64_t n, hipStream_t st);
 // batches
 const void* batch_step_kernel_ptr(int q, int prec, bool bouz);
-// k_batch_step(const MemberDesc*, const WorkItem*, int64_t nitems, int64_t step_off, int wpb)
-const void* batch_add_step_kernel_ptr();  // k_batch_add_step(int64_t* const*, int, int64_t)
+// k_batch_step(const MemberDesc*, const WorkItem*, int64_t nitems, const int64_t* bstep,
+//              int64_t step_off, int wpb)
 hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,
-                                int64_t nitems, double* partials, const int32_t* order,
-                                const int64_t* mstart, int nmembers, double* out, bool bouz,
-                                hipStream_t st);
+                                int64_t nitems, const int64_t* bstep, double* partials,
+                                const int32_t* order, const int64_t* mstart, int nmembers,
+                                double* out, bool bouz, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_set_r(int prec, const double* lambda, int64_t n, void* r, int* bad,
                         hipStream_t st);

@@ -122,6 +122,32 @@ def test_batch_tune_leaves_state(lbm):
         assert np.array_equal(c.get_state()[0], r.get_state()[0])
 
 
+def test_batch_members_stepped_outside(lbm):
+    """Members advanced or restored on their own between batch steps: the
+    batch picks up their current step and buffer, and stays bit-identical."""
+    say("batch with members stepped outside")
+    chans = make_ducts(lbm, SPECS, "f16s")
+    ref = make_ducts(lbm, SPECS, "f16s")
+    b = lbm.Batch(chans)
+    b.step(70)
+    chans[0].step(3)   # odd: parity flips
+    chans[2].step(64)  # through the channel's own graph
+    b.step(65)
+    saved = chans[3].get_state()
+    b.step(5)
+    chans[3].set_state(*saved)  # back 5 steps
+    b.step(5)
+    inv_b = b.invariants()
+    plan = [148, 145, 209, 140, 145]
+    for k, (c, r) in enumerate(zip(chans, ref)):
+        r.step(plan[k])
+        assert c.step_count == r.step_count == plan[k]
+        assert np.array_equal(c.get_state()[0], r.get_state()[0])
+        q, mass, dm = r.invariants()
+        assert abs(inv_b[k, 0] / q - 1) < 1e-13
+    b.close()
+
+
 def test_batch_rejects_mixed_members(lbm):
     a = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f32")
     c = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f64")
