@@ -74,7 +74,10 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   // FP64 arithmetic), float for F16S
   pl.wsize = p->precision == LBM_F16S ? 4 : 8;
   pl.nx = p->nx;
-  pl.nxp = (p->nx + 63) / 64 * 64;
+  // x-lines padded to whole 128-byte cache lines (32 floats or doubles, 64
+  // halves): the kernels write the padding too, so no line is written in part
+  const int pad = p->precision == LBM_F16S ? 64 : 32;
+  pl.nxp = (p->nx + pad - 1) / pad * pad;
   pl.ny = p->ny;
   pl.nz = p->nz;
   pl.ncolbox = (int64_t)p->ny * p->nz;
@@ -701,9 +704,8 @@ lbm_status lbm_transfer_state(lbm_ctx* dst, lbm_ctx* src) {
   lbm_status s = sync(src);
   if (s != LBM_OK) return s;
   const Plan &pd = dst->pl, &ps = src->pl;
-  const int64_t n = ps.ncolbox * ps.sC;  // same element count in both layouts
-  HIPCHK(dst, lbm::launch_convert(ps.prec, src->pop[src->cur], pd.prec, dst->pop[dst->cur], n,
-                                  dst->stream));
+  HIPCHK(dst, lbm::launch_convert(ps.prec, src->pop[src->cur], ps.nxp, pd.prec, dst->pop[dst->cur],
+                                  pd.nxp, ps.ncolbox * ps.Q, ps.nx, dst->stream));
   const size_t nw = (size_t)pd.nwall;
   if (nw) {
     HIPCHK(dst, hipMemcpyAsync(dst->at<double>(pd.off_lambda), src->at<double>(ps.off_lambda),

@@ -72,23 +72,59 @@ struct Lists {
   std::vector<int64_t> mstart;
 };
 
-// wall segments of every member first (they do more work), then the rest;
+// Interior columns of a member are cut into 32-cell chunks, two chunks per
+// wave, when the lanes of a wave can address both chunks from one base: the
+// storage lines are 32-element padded (not half precision), no periodic wrap
+// in z (slab), and every byte offset fits 32 bits.
+bool packs(const lbm_ctx* c) {
+  const Plan& pl = c->pl;
+  return pl.prec != LBM_F16S && c->p.geometry != LBM_SLAB && pl.pop_bytes < ((size_t)1 << 31);
+}
+
+// wall items of every member first (they do more work), then the rest;
 // `order` lists each member's items contiguously for the reductions
 void make_lists(lbm_ctx* const* ctxs, int n, Lists* L) {
   L->items.clear();
   std::vector<std::vector<int32_t>> mine(n);
+  auto push = [&](int m, const WorkItem& w) {
+    mine[m].push_back((int32_t)L->items.size());
+    L->items.push_back(w);
+  };
   for (int pass = 0; pass < 2; pass++)
     for (int m = 0; m < n; m++) {
       const Plan& pl = ctxs[m]->pl;
       const int nwc = (int)pl.wallcols.size();
       const int segs = (pl.nx + 63) / 64;
       const int lo = pass == 0 ? 0 : nwc, hi = pass == 0 ? nwc : (int)pl.slots.size();
+      if (pass == 1 && packs(ctxs[m])) {
+        // chunk sequence over the interior columns in slot order (increasing
+        // column id), paired in order: the second chunk's column is never lower
+        const int cpl = pl.nxp / 32;
+        WorkItem w{m, 0, -1, 0u, 0, -1, 0, 32};
+        bool half = false;
+        for (int slot = lo; slot < hi; slot++) {
+          const int col = pl.slots[slot].col;
+          for (int k = 0; k < cpl; k++) {
+            if (!half) {
+              w.col = col;
+              w.x0 = 32 * k;
+              w.colb = -1;
+              half = true;
+            } else {
+              w.colb = col;
+              w.x0b = 32 * k;
+              push(m, w);
+              half = false;
+            }
+          }
+        }
+        if (half) push(m, w);
+        continue;
+      }
       for (int slot = lo; slot < hi; slot++) {
         const lbm::ColSlot& cs = pl.slots[slot];
-        for (int sg = 0; sg < segs; sg++) {
-          mine[m].push_back((int32_t)L->items.size());
-          L->items.push_back(WorkItem{m, cs.col, cs.wallcol, cs.mask, sg * 64, 0, 0, 0});
-        }
+        for (int sg = 0; sg < segs; sg++)
+          push(m, WorkItem{m, cs.col, cs.wallcol, cs.mask, sg * 64, -1, 0, 64});
       }
     }
   L->order.clear();
@@ -133,7 +169,12 @@ void layout(lbm_batch* b, int n, int64_t nitems) {
 
 int64_t count_items(lbm_ctx* const* ctxs, int n) {
   int64_t t = 0;
-  for (int m = 0; m < n; m++) t += (int64_t)ctxs[m]->pl.slots.size() * ((ctxs[m]->pl.nx + 63) / 64);
+  for (int m = 0; m < n; m++) {
+    const Plan& pl = ctxs[m]->pl;
+    const int64_t nwc = (int64_t)pl.wallcols.size(), nin = (int64_t)pl.slots.size() - nwc;
+    const int64_t segs = (pl.nx + 63) / 64;
+    t += nwc * segs + (packs(ctxs[m]) ? (nin * (pl.nxp / 32) + 1) / 2 : nin * segs);
+  }
   return t;
 }
 

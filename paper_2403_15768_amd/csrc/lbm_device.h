@@ -109,12 +109,15 @@ struct MemberDesc {
   int32_t pad;
 };
 
-// A batch work item: one 64-cell x-segment of one fluid column of one
-// member, with that column's record inlined.
+// A batch work item: the 64 lanes of one wave over one member.  span 64:
+// cells x0 .. x0+63 of column col (any column, lanes at x >= nxp idle).
+// span 32 (interior columns only): lanes 0..31 take cells x0 .. x0+31 of
+// column col, lanes 32..63 cells x0b .. x0b+31 of column colb > col (colb < 0:
+// idle), so x-lines of any length fill whole waves up to a 32-cell chunk.
 struct WorkItem {
   int32_t member, col, wallcol;
   uint32_t mask;
-  int32_t x0, pad0, pad1, pad2;
+  int32_t x0, colb, x0b, span;
 };
 
 // ------------------------------------------------------------------ storage
@@ -249,9 +252,14 @@ __device__ __forceinline__ int src_col(const StepArgs& a, int i, int y, int z) {
 // Mixtures are evaluated as g + r (bb - g) and gb + b (gnb - gb) + c (gi - gb)
 // so that their weights sum to one exactly in the working precision (a
 // rounded 1 - r would multiply the wall populations by 1 + eps every step).
+//
+// dl (interior columns only) is added to every lane index: a lane working on
+// column col + k takes the lines of column col shifted by dl = k sC, which is
+// the same shift for every source column away from periodic wrap in z.
 template <class L, typename S, typename M, typename W, bool BOUZ>
 __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs& a, int col,
-                                       int y, int z, int x, ColInfo info, M* df) {
+                                       int y, int z, int x, ColInfo info, M* df,
+                                       unsigned dl = 0u) {
   const LBM_GLOBAL S* g = gbl(g0);
   const int64_t sI = a.sI, sC = a.sC;
   const unsigned ux = (unsigned)x;
@@ -262,7 +270,7 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
       const LBM_GLOBAL S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;  // uniform
-      df[i] = ld<S, M>(line, L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+      df[i] = ld<S, M>(line, dl + (L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux)));
     }
     return;
   }

@@ -259,20 +259,42 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 }
 
 // ------------------------------------------------------------ precision change
+// rows x-lines of nx values, nxp_in / nxp_out elements apart; the output's
+// padding is cleared
 template <typename A, typename B>
-__global__ void __launch_bounds__(256) k_convert(const A* __restrict__ in, B* __restrict__ out,
-                                                 int64_t n) {
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += st) {
-    const double v = dec<A, double>(in[k]);
-    if constexpr (sizeof(B) == 2)
-      out[k] = (B)(float)(v * kHalfScale);
-    else
-      out[k] = (B)v;
+__global__ void __launch_bounds__(256) k_convert(const A* __restrict__ in, int nxp_in,
+                                                 B* __restrict__ out, int nxp_out, int64_t rows,
+                                                 int nx) {
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const A* src = in + r * nxp_in;
+    B* dst = out + r * nxp_out;
+    for (int x = threadIdx.x; x < nxp_out; x += blockDim.x) {
+      const double v = x < nx ? dec<A, double>(src[x]) : 0.0;
+      if constexpr (sizeof(B) == 2)
+        dst[x] = (B)(float)(v * kHalfScale);
+      else
+        dst[x] = (B)v;
+    }
   }
 }
 
 // ------------------------------------------------------------ batches
+// The lane's cell of a batch item: column, x, and the index shift from the
+// item's first column; false for an idle lane.
+struct LaneCell {
+  int col, x;
+  unsigned dl;
+};
+__device__ __forceinline__ bool lane_cell(const WorkItem& item, const StepArgs& a, int lane,
+                                          LaneCell* c) {
+  const bool hi = lane >= item.span;
+  if (hi && item.colb < 0) return false;
+  c->col = hi ? item.colb : item.col;
+  c->x = hi ? item.x0b + (lane - 32) : item.x0 + lane;
+  c->dl = hi ? (unsigned)((int64_t)(item.colb - item.col) * a.sC) : 0u;
+  return c->x < a.nxp;
+}
+
 template <class L, typename S, typename M, bool BOUZ>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
@@ -286,25 +308,24 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   const MemberDesc& d = md[item.member];
   const int64_t k = uniform64(*gbl(bstep)) + step_off;  // steps since the batch was built
   const StepArgs& a = d.a;
-  const int x = item.x0 + (int)(threadIdx.x & 63);
-  if (x >= a.nxp) return;
-  const int xc = x < a.nx ? x : a.nx - 1;  // padding lanes: as in k_step
+  LaneCell c;
+  if (!lane_cell(item, a, (int)(threadIdx.x & 63), &c)) return;
+  const int xc = c.x < a.nx ? c.x : a.nx - 1;  // padding lanes: as in k_step
   // both pointers loaded up front, then selected: no load waits on the parity
   const void* p0 = d.pop[0];
   const void* p1 = d.pop[1];
   const bool odd = ((d.cur_base + k) & 1) != 0;
   const S* src = static_cast<const S*>(odd ? p1 : p0);
   S* dst = static_cast<S*>(const_cast<void*>(odd ? p0 : p1));
-  const int col = item.col;
   ColInfo info;
   info.wallcol = item.wallcol;
   info.mask = item.mask;
-  const int y = col % a.ny;
-  const int z = col / a.ny;
+  const int y = item.col % a.ny;
+  const int z = item.col / a.ny;
   M df[L::Q];
-  gather<L, S, M, M, BOUZ>(src, a, col, y, z, xc, info, df);
-  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, d.base_step + k);
+  gather<L, S, M, M, BOUZ>(src, a, item.col, y, z, xc, info, df, c.dl);
+  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)item.col * a.sC, c.dl + (unsigned)c.x,
+                         (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k);
 }
 
 // per-item partial sums of (j_x, rho - rho0); one wave per item
@@ -320,17 +341,17 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
   const WorkItem item = items[it];
   const MemberDesc& d = md[item.member];
   const StepArgs& a = d.a;
-  const int x = item.x0 + (int)(threadIdx.x & 63);
+  LaneCell c;
   double jx = 0.0, dr = 0.0;
-  if (x < a.nx) {
+  if (lane_cell(item, a, (int)(threadIdx.x & 63), &c) && c.x < a.nx) {
     const int par = (int)((d.cur_base + uniform64(*gbl(bstep))) & 1);
     const S* src = static_cast<const S*>(d.pop[par]);
-    const int col = item.col;
     ColInfo info;
     info.wallcol = item.wallcol;
     info.mask = item.mask;
     double df[L::Q];
-    gather<L, S, double, W, BOUZ>(src, a, col, col % a.ny, col / a.ny, x, info, df);
+    gather<L, S, double, W, BOUZ>(src, a, item.col, item.col % a.ny, item.col / a.ny, c.x, info,
+                                  df, c.dl);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
       dr += df[i];
@@ -438,20 +459,26 @@ hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const Wor
 }
 
 template <typename A>
-static hipError_t convert_from(const void* in, int pout, void* out, int64_t n, hipStream_t st) {
-  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384));
+static hipError_t convert_from(const void* in, int nxp_in, int pout, void* out, int nxp_out,
+                               int64_t rows, int nx, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, 16384));
+  const A* src = static_cast<const A*>(in);
   if (pout == 0)
-    hipLaunchKernelGGL((k_convert<A, double>), dim3(blocks), dim3(256), 0, st, (const A*)in, (double*)out, n);
+    hipLaunchKernelGGL((k_convert<A, double>), dim3(blocks), dim3(256), 0, st, src, nxp_in,
+                       (double*)out, nxp_out, rows, nx);
   else if (pout == 1)
-    hipLaunchKernelGGL((k_convert<A, float>), dim3(blocks), dim3(256), 0, st, (const A*)in, (float*)out, n);
+    hipLaunchKernelGGL((k_convert<A, float>), dim3(blocks), dim3(256), 0, st, src, nxp_in,
+                       (float*)out, nxp_out, rows, nx);
   else
-    hipLaunchKernelGGL((k_convert<A, _Float16>), dim3(blocks), dim3(256), 0, st, (const A*)in, (_Float16*)out, n);
+    hipLaunchKernelGGL((k_convert<A, _Float16>), dim3(blocks), dim3(256), 0, st, src, nxp_in,
+                       (_Float16*)out, nxp_out, rows, nx);
   return hipGetLastError();
 }
-hipError_t launch_convert(int pin, const void* in, int pout, void* out, int64_t n, hipStream_t st) {
-  if (pin == 0) return convert_from<double>(in, pout, out, n, st);
-  if (pin == 1) return convert_from<float>(in, pout, out, n, st);
-  return convert_from<_Float16>(in, pout, out, n, st);
+hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* out, int nxp_out,
+                          int64_t rows, int nx, hipStream_t st) {
+  if (pin == 0) return convert_from<double>(in, nxp_in, pout, out, nxp_out, rows, nx, st);
+  if (pin == 1) return convert_from<float>(in, nxp_in, pout, out, nxp_out, rows, nx, st);
+  return convert_from<_Float16>(in, nxp_in, pout, out, nxp_out, rows, nx, st);
 }
 
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {

@@ -30,8 +30,10 @@ hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, do
                            double* lambda, hipStream_t st);
 hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st);
 const void* add_step_kernel_ptr();  // k_add_step(int64_t* d, int64_t v)
-// elementwise storage-precision change of n populations (0 F64, 1 F32, 2 F16S)
-hipError_t launch_convert(int pin, const void* in, int pout, void* out, int64_t n, hipStream_t st);
+// storage-precision change (0 F64, 1 F32, 2 F16S) of `rows` x-lines of nx
+// populations, nxp_in / nxp_out elements apart
+hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* out, int nxp_out,
+                          int64_t rows, int nx, hipStream_t st);
 // batches
 const void* batch_step_kernel_ptr(int q, int prec, bool bouz);
 // k_batch_step(const MemberDesc*, const WorkItem*, int64_t nitems, const int64_t* bstep,

@@ -396,9 +396,10 @@ def test_f16s_storage_error_bounded(lbm):
     assert eu < 1e-2 and abs(qg / qo - 1) < 1e-2
 
 
-def test_transfer_state_across_precisions(lbm):
-    say("transfer")
-    nx, ny, nz = 40, 12, 10
+@pytest.mark.parametrize("nx", [40, 72])  # 72: the half and float x-lines are padded differently
+def test_transfer_state_across_precisions(lbm, nx):
+    say("transfer", nx)
+    ny, nz = 12, 10
     kw = dict(tau=0.75, force=(1e-6, 0, 0))
     H = lbm.Channel(19, lbm.DUCT, nx, ny, nz, precision="f16s", **kw)
     lam = inputs.duct_friction(H.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 12))
