@@ -16,6 +16,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a multiply-add is fused only within one source expression, so every
+    # kernel that runs the same update rounds it the same way (a channel
+    # stepped alone or in a batch stays bit-identical)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

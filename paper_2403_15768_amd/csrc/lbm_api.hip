@@ -119,13 +119,15 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
       } else {
         interior.push_back((int32_t)col);
       }
+      // pulls across the periodic z boundary take the general path
+      if (slab && pl.Q == 19 && (z == 0 || z == p->nz - 1)) ci.mask |= lbm::kWrapColumn;
       pl.colinfo[col] = ci;
     }
   // wall columns first: their blocks do more work, so they start early
   // instead of forming the tail of the grid
   for (int32_t col : pl.wallcols)
     pl.slots.push_back(lbm::ColSlot{col, pl.colinfo[col].wallcol, pl.colinfo[col].mask, 0});
-  for (int32_t col : interior) pl.slots.push_back(lbm::ColSlot{col, -1, 0u, 0});
+  for (int32_t col : interior) pl.slots.push_back(lbm::ColSlot{col, -1, pl.colinfo[col].mask, 0});
   const int64_t nwc = (int64_t)pl.wallcols.size();
   pl.linkq.assign(nwc * pl.Q, 0.0);
   if (pl.bouz) pl.bzc.assign(nwc * pl.Q * 2, 0.0);
@@ -181,6 +183,11 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
       const bool wall = ci.mask & (1u << i);
       if (!wall && !fluid_at(y - lat_c(pl.Q, i, 1), z - lat_c(pl.Q, i, 2))) {
         if (err) *err = "internal: fluid link to a solid column";
+        return LBM_EINVAL;
+      }
+      const int zs = z - lat_c(pl.Q, i, 2);
+      if (!wall && !(ci.mask & lbm::kWrapColumn) && (zs < 0 || zs >= p->nz)) {
+        if (err) *err = "internal: unflagged periodic pull";
         return LBM_EINVAL;
       }
       if (wall && pl.bouz && pl.bzc[((int64_t)ci.wallcol * pl.Q + i) * 2] != 0.0 &&
@@ -243,6 +250,8 @@ void fill_args(lbm_ctx* c) {
   a.sI = pl.sI;
   a.sC = pl.sC;
   a.nactive = (int)pl.slots.size();
+  a.nwallcols = (int)pl.wallcols.size();
+  a.rev = 0;
   a.bx = pl.bx;
   a.segs = pl.segs;
   a.slab = c->p.geometry == LBM_SLAB;
@@ -256,6 +265,10 @@ void fill_args(lbm_ctx* c) {
   a.dstep = nullptr;
   a.step_off = 0;
   a.seed = kSeed;
+  for (int i = 0; i < 19; i++)
+    a.nboff[i] = i < pl.Q ? (int64_t)i * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
+                                lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
+                          : 0;
 }
 
 template <typename W>
@@ -280,6 +293,7 @@ lbm_status upload_wall_r(lbm_ctx* c, const double* lambda_dev, int64_t n) {
 lbm_status lbm_host::launch_one_step(lbm_ctx* c) {
   StepArgs a = c->args;
   a.step_off = c->step;  // plain launch: the step travels as an argument
+  a.rev = c->cur;
   HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
                              c->pl.bouz, c->stream));
   c->cur = 1 - c->cur;
@@ -305,10 +319,11 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
     args[k] = c->args;
     args[k].dstep = dstep;
     args[k].step_off = k;
+    args[k].rev = (parity + k) & 1;
     void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&args[k]};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
-    kp.gridDim = dim3((unsigned)c->pl.nblocks);
+    kp.gridDim = dim3((unsigned)c->pl.slots.size(), (unsigned)c->pl.segs);
     kp.blockDim = dim3(c->pl.bx);
     kp.sharedMemBytes = 0;
     kp.kernelParams = kargs;

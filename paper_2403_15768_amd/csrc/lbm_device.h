@@ -49,10 +49,13 @@ struct D3Q19 {
 // and its wall links are the same for every x.
 
 constexpr uint32_t kSolidColumn = 0x80000000u;
+// a fluid column whose pulls wrap around the periodic z boundary (slab)
+constexpr uint32_t kWrapColumn = 0x40000000u;
+constexpr uint32_t kLinkBits = 0x000fffffu;
 
 struct ColInfo {
-  int32_t wallcol;  // index among wall columns, -1 for interior columns
-  uint32_t mask;    // bit i: link i pulls from a solid point; kSolidColumn
+  int32_t wallcol;  // index among wall columns, -1 for columns without wall links
+  uint32_t mask;    // bit i: link i pulls from a solid point; kWrapColumn; kSolidColumn
 };
 
 // One fluid column as the kernels see it: everything a wave needs about its
@@ -69,6 +72,8 @@ struct StepArgs {
   int64_t sI;         // elements between the x-lines of two directions (nxp)
   int64_t sC;         // elements between two columns (Q nxp)
   int nactive;        // number of fluid columns
+  int nwallcols;      // the first nwallcols of them have wall links
+  int rev;            // visit the other columns in reverse order (see k_step)
   int bx;             // threads per block along x
   int segs;           // blocks per column = ceil(nx / bx)
   int slab;           // z periodic
@@ -83,6 +88,9 @@ struct StepArgs {
   const int64_t* dstep;
   int64_t step_off;
   uint32_t seed;
+  // element offset, from the start of a column, of the x-line of g_i in the
+  // column the pull of link i reads: i sI - c_iy sC - c_iz ny sC (no wrap)
+  int64_t nboff[19];
 };
 
 // ------------------------------------------------------------------ uniformity
@@ -143,6 +151,13 @@ __device__ __forceinline__ const LBM_GLOBAL S* at(const LBM_GLOBAL S* line, unsi
 template <typename S>
 __device__ __forceinline__ LBM_GLOBAL S* at(LBM_GLOBAL S* line, unsigned i) {
   return (LBM_GLOBAL S*)((LBM_GLOBAL char*)line + i * (unsigned)sizeof(S));
+}
+// A wave-uniform line pointer pinned to scalar registers: without it the
+// compiler folds the lane offset into the base once and then forms every
+// store address with 64-bit vector arithmetic.
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T* sbase(LBM_GLOBAL T* p) {
+  return (LBM_GLOBAL T*)uniform64((int64_t)(uintptr_t)p);
 }
 template <typename S, typename M>
 __device__ __forceinline__ M ld(const LBM_GLOBAL S* line, unsigned i);  // defined after dec()
@@ -231,16 +246,18 @@ __device__ __forceinline__ M ld(const LBM_GLOBAL S* line, unsigned i) {
   return dec<S, M>(*at(line, i));
 }
 
-// source column of link i for the pull at column (y, z)
+// element offset, from the start of column (y, z), of the x-line of g_i in
+// the column the pull of link i reads (sZ = ny sC); with wrap, z is periodic
 template <class L>
-__device__ __forceinline__ int src_col(const StepArgs& a, int i, int y, int z) {
-  int ys = y - L::cy[i];
-  int zs = z - L::cz[i];
-  if (a.slab) {
-    if (zs < 0) zs += a.nz;
-    if (zs >= a.nz) zs -= a.nz;
+__device__ __forceinline__ int64_t src_off(const StepArgs& a, int i, int z, bool wrap) {
+  int64_t off = a.nboff[i];
+  if (L::cz[i] != 0 && wrap) {
+    const int64_t sZ = (int64_t)a.ny * a.sC;
+    const int zs = z - L::cz[i];
+    if (zs < 0) off += (int64_t)a.nz * sZ;
+    if (zs >= a.nz) off -= (int64_t)a.nz * sZ;
   }
-  return ys + a.ny * zs;
+  return off;
 }
 
 // Pull gather: df_i = g_i(x - c_i), periodic in x; a link whose upstream
@@ -258,19 +275,19 @@ __device__ __forceinline__ int src_col(const StepArgs& a, int i, int y, int z) {
 // the same shift for every source column away from periodic wrap in z.
 template <class L, typename S, typename M, typename W, bool BOUZ>
 __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs& a, int col,
-                                       int y, int z, int x, ColInfo info, M* df,
-                                       unsigned dl = 0u) {
+                                       int x, ColInfo info, M* df, unsigned dl = 0u) {
   const LBM_GLOBAL S* g = gbl(g0);
   const int64_t sI = a.sI, sC = a.sC;
   const unsigned ux = (unsigned)x;
   const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
   const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
   const uint32_t mask = info.mask;
+  const LBM_GLOBAL S* gown = g + (int64_t)col * sC;
   if (mask == 0u) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-      const LBM_GLOBAL S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;  // uniform
-      df[i] = ld<S, M>(line, dl + (L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux)));
+      const LBM_GLOBAL S* line = gown + a.nboff[i];  // uniform
+      df[i] = ld<S, M>(sbase(line), dl + (L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux)));
     }
     return;
   }
@@ -280,7 +297,8 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
   //          link the node behind it, g_opp(i)(x + c_i);
   //   ow[k]: this node's own g_k, for every k pointing into the wall (and
   //          for wall links that interpolate with g_i(x)).
-  const LBM_GLOBAL S* gown = g + (int64_t)col * sC;
+  const int z = col / a.ny;
+  const int y = col - z * a.ny;
   const LBM_GLOBAL W* cw =
       BOUZ ? gbl(static_cast<const W*>(a.bz)) + (int64_t)info.wallcol * L::Q * 2 : nullptr;
   S pv[L::Q], ow[L::Q];
@@ -288,15 +306,20 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
   for (int i = 0; i < L::Q; i++) {
     const bool wall = mask & (1u << i);
     if (!wall) {
-      const LBM_GLOBAL S* line = g + (int64_t)src_col<L>(a, i, y, z) * sC + i * sI;
-      pv[i] = *at(line, L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+      const LBM_GLOBAL S* line = gown + src_off<L>(a, i, z, (mask & kWrapColumn) != 0u);
+      pv[i] = *at(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
     } else if (BOUZ && cw[2 * i] != W(0)) {
       const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
       const LBM_GLOBAL S* line = g + (int64_t)nc * sC + L::opp[i] * sI;
-      pv[i] = *at(line, L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : ux));
+      pv[i] = *at(sbase(line), L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : ux));
     }
     if ((mask & (1u << L::opp[i])) || (BOUZ && wall && cw[2 * i + 1] != W(0)))
-      ow[i] = *at(gown + i * sI, ux);
+      ow[i] = *at(sbase(gown + i * sI), ux);
+  }
+  if ((mask & kLinkBits) == 0u) {  // a wrapping column without wall links
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) df[i] = dec<S, M>(pv[i]);
+    return;
   }
   const M r = static_cast<M>(gbl(static_cast<const W*>(a.rwall))[(int64_t)info.wallcol * a.nx + x]);
 #pragma unroll
@@ -369,9 +392,10 @@ __device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
 // cell the terms common to all directions are gathered first:
 //   C0 = omega (drho - 1.5 rho u.u) - 3 A u.F,      A = 1 - omega/2,
 //   U  = 4.5 omega rho u + 9 A F,  J = omega j + A F,
-// so that  df_i <- (1 - omega) df_i + w_i C0 + w_i (c.u)(c.U) + t_i (c.J).
-// Opposite directions are computed with exactly negated operands, so their
-// odd parts cancel exactly in the next step's moments.
+// so that  df_i <- (1 - omega) df_i + E_i + O_i  with the even part
+// E_i = w_i (C0 + (c.u)(c.U)) and the odd part O_i = t_i (c.J).  Opposite
+// directions share E and take O with its sign flipped, so each pair is
+// computed once and the odd parts cancel exactly in the next moments.
 template <class L, typename M, typename S>
 __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LBM_GLOBAL S* out_col,
                                               unsigned x, uint32_t cell, int64_t step) {
@@ -399,25 +423,29 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
   const M Ux = k45 * ux + a9 * Fx, Uy = k45 * uy + a9 * Fy, Uz = k45 * uz + a9 * Fz;
   const M Jx = om * jx + A * Fx, Jy = om * jy + A * Fy, Jz = om * jz + A * Fz;
   const M keep = M(1) - om;
+  // rounding bits: one 32-bit word for the rest population, then one per
+  // opposite pair (low half for the first direction, high half for its opposite)
   RoundBits rb(a.seed, step, Store<S, M>::kRandom ? cell : 0u);
-  uint32_t word = 0;
+  {
+    const uint32_t w0 = Store<S, M>::kRandom ? rb.next() : 0u;
+    const M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
+    *at(sbase(out_col), x) = Store<S, M>::enc(v, w0 & 0xffffu);
+  }
 #pragma unroll
-  for (int i = 0; i < L::Q; i++) {
+  for (int i = 1; i < L::Q; i++) {
+    const int o = L::opp[i];
+    if (o < i) continue;  // each pair once, from its first direction
     const M wi = static_cast<M>(L::w[i]);
-    M v = keep * df[i] + wi * C0;
-    if (i != 0) {
-      const M cu = cdot<L, M>(i, ux, uy, uz);
-      const M cU = cdot<L, M>(i, Ux, Uy, Uz);
-      const M cJ = cdot<L, M>(i, Jx, Jy, Jz);
-      v += wi * cu * cU;
-      v += lin_weight<L, M>(i) * cJ;
-    }
-    uint32_t bits = 0u;
-    if (Store<S, M>::kRandom) {
-      if ((i & 1) == 0) word = rb.next();
-      bits = (i & 1) ? (word >> 16) : (word & 0xffffu);
-    }
-    *at(out_col + i * a.sI, x) = Store<S, M>::enc(v, bits);
+    const M cu = cdot<L, M>(i, ux, uy, uz);
+    const M cU = cdot<L, M>(i, Ux, Uy, Uz);
+    const M cJ = cdot<L, M>(i, Jx, Jy, Jz);
+    const M E = (wi * cu) * cU + wi * C0;
+    const M O = lin_weight<L, M>(i) * cJ;
+    const M vi = (keep * df[i] + E) + O;
+    const M vo = (keep * df[o] + E) - O;
+    const uint32_t word = Store<S, M>::kRandom ? rb.next() : 0u;
+    *at(sbase(out_col + i * a.sI), x) = Store<S, M>::enc(vi, word & 0xffffu);
+    *at(sbase(out_col + o * a.sI), x) = Store<S, M>::enc(vo, word >> 16);
   }
 }
 

@@ -30,9 +30,14 @@ namespace lbm {
 template <class L, typename S, typename M, bool BOUZ>
 __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                               StepArgs a) {
-  const int slot = blockIdx.x / a.segs;
-  const int seg = blockIdx.x - slot * a.segs;
-  const int x = seg * a.bx + threadIdx.x;
+  // grid (fluid columns, segments per x-line).  Wall columns go first (their
+  // blocks do more work and would otherwise form the tail of the grid).  The
+  // rest are visited in one order when reading one buffer and in the reverse
+  // order when reading the other: a step then starts on the columns the
+  // previous step wrote last, which are still in the last-level cache.
+  int slot = blockIdx.x;
+  if (a.rev && slot >= a.nwallcols) slot = a.nactive - 1 - slot + a.nwallcols;
+  const int x = blockIdx.y * a.bx + threadIdx.x;
   if (x >= a.nxp) return;
   // Lanes on the padding of an x-line (nx <= x < nxp) recompute cell nx - 1
   // and store it into the padding, so every cache line of the output is
@@ -44,11 +49,9 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   ColInfo info;
   info.wallcol = uniform(cs.wallcol);
   info.mask = (uint32_t)uniform((int)cs.mask);
-  const int y = col % a.ny;
-  const int z = col / a.ny;
   const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
   M df[L::Q];
-  gather<L, S, M, M, BOUZ>(src, a, col, y, z, xc, info, df);
+  gather<L, S, M, M, BOUZ>(src, a, col, xc, info, df);
   collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
                          (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step);
 }
@@ -75,10 +78,8 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
     ColInfo info;
     info.wallcol = uniform(cs.wallcol);
     info.mask = (uint32_t)uniform((int)cs.mask);
-    const int y = col % a.ny;
-    const int z = col / a.ny;
     double df[L::Q];
-    gather<L, S, double, W, BOUZ>(src, a, col, y, z, x, info, df);
+    gather<L, S, double, W, BOUZ>(src, a, col, x, info, df);
     double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
@@ -320,10 +321,8 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   ColInfo info;
   info.wallcol = item.wallcol;
   info.mask = item.mask;
-  const int y = item.col % a.ny;
-  const int z = item.col / a.ny;
   M df[L::Q];
-  gather<L, S, M, M, BOUZ>(src, a, item.col, y, z, xc, info, df, c.dl);
+  gather<L, S, M, M, BOUZ>(src, a, item.col, xc, info, df, c.dl);
   collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)item.col * a.sC, c.dl + (unsigned)c.x,
                          (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k);
 }
@@ -350,8 +349,7 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
     info.wallcol = item.wallcol;
     info.mask = item.mask;
     double df[L::Q];
-    gather<L, S, double, W, BOUZ>(src, a, item.col, item.col % a.ny, item.col / a.ny, c.x, info,
-                                  df, c.dl);
+    gather<L, S, double, W, BOUZ>(src, a, item.col, c.x, info, df, c.dl);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
       dr += df[i];
@@ -492,7 +490,7 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 template <class L, typename S, typename M>
 static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, bool bouz,
                                 hipStream_t st) {
-  const dim3 grid((unsigned)((int64_t)a.nactive * a.segs)), block(a.bx);
+  const dim3 grid((unsigned)a.nactive, (unsigned)a.segs), block(a.bx);
   if (bouz)
     hipLaunchKernelGGL((k_step<L, S, M, true>), grid, block, 0, st, (const S*)src, (S*)dst, a);
   else
