@@ -192,16 +192,21 @@ lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
  * src; the copy runs on dst's stream and is complete on return. */
 lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
 
-/* ---- Batches (many channels, one kernel launch per step) -------------------
+/* ---- Batches (many channels, one kernel launch per step and group) --------
  * A batch groups n existing contexts with the same lattice, storage
  * precision and wall kind (TUBE or planar); sizes, tau, force and friction
- * may differ.  One launch per time step advances every member over a work
- * list of 64-cell x-segments (wall segments first); runs of 64 steps are
- * replayed from a captured hipGraph.  Members keep their own buffers,
- * parameters and step counters, and a member advanced in a batch is bit-for-
- * bit the same as the member advanced alone.  While a batch is alive, step
- * its members only through it; their lbm_get_*, lbm_invariants and
- * lbm_get_state calls stay valid between batch calls. */
+ * may differ.  One launch per time step advances a group of members over a
+ * work list of 64-lane items (wall segments first); runs of 64 steps are
+ * replayed from captured hipGraphs.  Members are cut, in order, into groups
+ * whose state fits the last-level cache (200 MiB by default, see
+ * lbm_batch_set_group_bytes); a call to lbm_batch_step runs each group 64
+ * steps at a time, one group after the other, so a group's populations stay
+ * cached between its steps.  Members keep their own buffers, parameters and
+ * step counters, and a member advanced in a batch is bit-for-bit the same as
+ * the member advanced alone.  Their lbm_get_*, lbm_invariants and
+ * lbm_get_state calls stay valid between batch calls; a member stepped,
+ * restored or transferred outside the batch is taken up at its current step
+ * by the next batch call. */
 typedef struct lbm_batch lbm_batch; /* opaque */
 /* Device bytes a batch of these contexts needs (descriptors, work list,
  * reduction partials). */
@@ -225,6 +230,12 @@ lbm_status lbm_batch_invariants(lbm_batch *b, double *out);
 lbm_status lbm_batch_tune(lbm_batch *b, int *chosen);
 /* Set the workgroup shape directly (1, 2, 4 or 8). */
 lbm_status lbm_batch_set_shape(lbm_batch *b, int waves_per_group);
+/* Largest state (both buffers of every member) of one group, in bytes; a
+ * member larger than that forms a group of its own; 0 puts every member in
+ * one group (all members advance step by step together).  Rewrites the work
+ * list; synchronous.  Results do not depend on the grouping. */
+lbm_status lbm_batch_set_group_bytes(lbm_batch *b, size_t bytes);
+lbm_status lbm_batch_groups(const lbm_batch *b, int *ngroups);
 const char *lbm_batch_last_error(const lbm_batch *b);
 
 /* Plain streaming device-to-device copy of `bytes` (a multiple of 16, both

@@ -1,16 +1,23 @@
-// lbm_batch.hip -- batches of channels advanced by one kernel launch per step.
+// lbm_batch.hip -- batches of channels advanced by one kernel launch per step
+// and group.
 //
 // A batch groups existing contexts (same lattice, storage precision and wall
-// kind; any sizes and parameters).  Its work list holds one item per 64-cell
-// x-segment of every fluid column of every member, wall segments first; one
-// wave updates one item, and every item carries its column's record so that
-// a wave's set-up is one chain of two scalar loads (item, member).  Members
-// keep their own buffers, parameters and step counters: a member's step
-// number decides which of its two buffers is current and which
-// stochastic-rounding bits it uses, so a channel advanced inside a batch is
-// bit-identical to the same channel advanced alone.  On the device the batch
-// keeps one counter, the steps taken since its member table was written; a
-// member's step is its base step plus that counter.
+// kind; any sizes and parameters).  Its work list holds, per wave, 64 lanes
+// of one member (a 64-cell x-segment, or two 32-cell chunks of interior
+// columns), and every item carries its column's record so that a wave's
+// set-up is one chain of two scalar loads (item, member).  Members keep their
+// own buffers, parameters and step counters: a member's step number decides
+// which of its two buffers is current and which stochastic-rounding bits it
+// uses, so a channel advanced inside a batch is bit-identical to the same
+// channel advanced alone.  On the device the batch keeps one counter, the
+// steps taken since its member table was written; a member's step is its base
+// step plus that counter.
+//
+// Members are independent, so they need not advance in lockstep: the batch
+// is cut into groups whose state fits the 256 MB last-level cache, and each
+// group runs a whole 64-step graph before the next group starts.  A group's
+// populations then stay in that cache from one step to the next instead of
+// streaming from HBM every step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,13 +39,18 @@ struct lbm_batch {
   int Q = 0, prec = 0;
   bool bouz = false;
   int64_t nitems = 0;
+  struct Group {
+    int64_t first, nwall, last;  // items [first, last), wall items [first, nwall)
+  };
+  std::vector<Group> groups;
+  size_t group_bytes = 0;
   int wpb = 4;  // waves (work items) per workgroup, set by lbm_batch_tune
   int64_t k = 0;                  // steps since the member table was written
   std::vector<int64_t> base;      // each member's step when the table was written
   size_t off_desc = 0, off_items = 0, off_order = 0, off_mstart = 0, off_partials = 0,
          off_out = 0, off_bstep = 0, total = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  std::vector<hipGraph_t> graph;  // per group: kGraphSteps steps
+  std::vector<hipGraphExec_t> gexec;
   int graph_wpb = 0;
   bool graphs_ok = true;
   std::string err;
@@ -68,9 +80,14 @@ namespace {
 
 struct Lists {
   std::vector<WorkItem> items;
+  std::vector<lbm_batch::Group> groups;
   std::vector<int32_t> order;
   std::vector<int64_t> mstart;
 };
+
+// Default group size: the state of a group (both buffers of every member)
+// stays well inside the 256 MB last-level cache.
+constexpr size_t kDefaultGroupBytes = (size_t)200 << 20;
 
 // Interior columns of a member are cut into 32-cell chunks, two chunks per
 // wave, when the lanes of a wave can address both chunks from one base: the
@@ -81,17 +98,28 @@ bool packs(const lbm_ctx* c) {
   return pl.prec != LBM_F16S && c->p.geometry != LBM_SLAB && pl.pop_bytes < ((size_t)1 << 31);
 }
 
+// Members in order, cut into groups of at most group_bytes of state (a
+// larger member forms a group of its own; 0: one group).  Within a group,
 // wall items of every member first (they do more work), then the rest;
-// `order` lists each member's items contiguously for the reductions
-void make_lists(lbm_ctx* const* ctxs, int n, Lists* L) {
+// `order` lists each member's items contiguously for the reductions.
+void make_lists(lbm_ctx* const* ctxs, int n, size_t group_bytes, Lists* L) {
   L->items.clear();
+  L->groups.clear();
   std::vector<std::vector<int32_t>> mine(n);
   auto push = [&](int m, const WorkItem& w) {
     mine[m].push_back((int32_t)L->items.size());
     L->items.push_back(w);
   };
-  for (int pass = 0; pass < 2; pass++)
-    for (int m = 0; m < n; m++) {
+  for (int m0 = 0; m0 < n;) {
+    int m1 = m0 + 1;
+    size_t bytes = 2 * ctxs[m0]->pl.pop_bytes;
+    while (group_bytes && m1 < n && bytes + 2 * ctxs[m1]->pl.pop_bytes <= group_bytes)
+      bytes += 2 * ctxs[m1++]->pl.pop_bytes;
+    if (!group_bytes) m1 = n;
+    lbm_batch::Group g{(int64_t)L->items.size(), 0, 0};
+  for (int pass = 0; pass < 2; pass++) {
+    if (pass == 1) g.nwall = (int64_t)L->items.size();
+    for (int m = m0; m < m1; m++) {
       const Plan& pl = ctxs[m]->pl;
       const int nwc = (int)pl.wallcols.size();
       const int segs = (pl.nx + 63) / 64;
@@ -127,6 +155,11 @@ void make_lists(lbm_ctx* const* ctxs, int n, Lists* L) {
           push(m, WorkItem{m, cs.col, cs.wallcol, cs.mask, sg * 64, -1, 0, 64});
       }
     }
+  }
+    g.last = (int64_t)L->items.size();
+    L->groups.push_back(g);
+    m0 = m1;
+  }
   L->order.clear();
   L->mstart.assign(n + 1, 0);
   for (int m = 0; m < n; m++) {
@@ -178,17 +211,27 @@ int64_t count_items(lbm_ctx* const* ctxs, int n) {
   return t;
 }
 
-lbm_status launch_batch(lbm_batch* b, int64_t step_off, int wpb) {
+// one step (step_off steps past the device counter) of group gi
+lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, int wpb) {
   const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
-  int64_t nitems = b->nitems;
+  lbm_batch::Group g = b->groups[gi];
   const int64_t* bstep = b->at<int64_t>(b->off_bstep);
-  void* args[6] = {(void*)&md,    (void*)&items,    (void*)&nitems,
-                   (void*)&bstep, (void*)&step_off, (void*)&wpb};
-  const dim3 grid((unsigned)((nitems + wpb - 1) / wpb)), block(64 * wpb);
+  void* args[8] = {(void*)&md,    (void*)&items,    (void*)&g.first, (void*)&g.nwall,
+                   (void*)&g.last, (void*)&bstep, (void*)&step_off, (void*)&wpb};
+  const dim3 grid((unsigned)((g.last - g.first + wpb - 1) / wpb)), block(64 * wpb);
   BCHK(b, hipLaunchKernel(fn, grid, block, args, 0, b->stream));
   return LBM_OK;
+}
+
+void drop_graphs(lbm_batch* b) {
+  for (hipGraphExec_t e : b->gexec)
+    if (e) (void)hipGraphExecDestroy(e);
+  for (hipGraph_t g : b->graph)
+    if (g) (void)hipGraphDestroy(g);
+  b->gexec.clear();
+  b->graph.clear();
 }
 
 lbm_status launch_bump(lbm_batch* b, int64_t v) {
@@ -241,32 +284,26 @@ lbm_status resync(lbm_batch* b) {
   return LBM_OK;
 }
 
-lbm_status build_graph(lbm_batch* b) {
-  if (b->gexec) {
-    (void)hipGraphExecDestroy(b->gexec);
-    b->gexec = nullptr;
-  }
-  if (b->graph) {
-    (void)hipGraphDestroy(b->graph);
-    b->graph = nullptr;
-  }
+// kGraphSteps steps of group gi, step k at (device counter + k); the
+// counter itself is advanced once all groups have run
+lbm_status build_graph(lbm_batch* b, size_t gi, hipGraph_t* gout, hipGraphExec_t* xout) {
   hipGraph_t g = nullptr;
   BCHK(b, hipGraphCreate(&g, 0));
   const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int64_t* bstep = b->at<int64_t>(b->off_bstep);
-  int64_t nitems = b->nitems;
+  lbm_batch::Group grp = b->groups[gi];
   int wpb = b->wpb;
   hipGraphNode_t prev = nullptr;
   int64_t offs[kGraphSteps];
   for (int k = 0; k < kGraphSteps; k++) {
     offs[k] = k;
-    void* args[6] = {(void*)&md,    (void*)&items,   (void*)&nitems,
-                     (void*)&bstep, (void*)&offs[k], (void*)&wpb};
+    void* args[8] = {(void*)&md,       (void*)&items, (void*)&grp.first, (void*)&grp.nwall,
+                     (void*)&grp.last, (void*)&bstep, (void*)&offs[k],   (void*)&wpb};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
-    kp.gridDim = dim3((unsigned)((nitems + wpb - 1) / wpb));
+    kp.gridDim = dim3((unsigned)((grp.last - grp.first + wpb - 1) / wpb));
     kp.blockDim = dim3(64 * wpb);
     kp.kernelParams = args;
     hipGraphNode_t node = nullptr;
@@ -277,31 +314,48 @@ lbm_status build_graph(lbm_batch* b) {
     }
     prev = node;
   }
-  {
-    int64_t* d = b->at<int64_t>(b->off_bstep);
-    int64_t inc = kGraphSteps;
-    void* args[2] = {(void*)&d, (void*)&inc};
-    hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(lbm::add_step_kernel_ptr());
-    kp.gridDim = dim3(1);
-    kp.blockDim = dim3(64);
-    kp.kernelParams = args;
-    hipGraphNode_t node = nullptr;
-    hipError_t e = hipGraphAddKernelNode(&node, g, &prev, 1, &kp);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return b->hip(e, "hipGraphAddKernelNode");
-    }
-  }
   hipGraphExec_t ex = nullptr;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
     return b->hip(e, "hipGraphInstantiate");
   }
-  b->graph = g;
-  b->gexec = ex;
+  *gout = g;
+  *xout = ex;
+  return LBM_OK;
+}
+
+lbm_status build_graphs(lbm_batch* b) {
+  drop_graphs(b);
+  for (size_t gi = 0; gi < b->groups.size(); gi++) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    lbm_status s = build_graph(b, gi, &g, &x);
+    if (s != LBM_OK) {
+      drop_graphs(b);
+      return s;
+    }
+    b->graph.push_back(g);
+    b->gexec.push_back(x);
+  }
   b->graph_wpb = b->wpb;
+  return LBM_OK;
+}
+
+// (re)write the work list for the current group size; synchronous
+lbm_status upload_lists(lbm_batch* b) {
+  Lists L;
+  make_lists(b->m.data(), (int)b->m.size(), b->group_bytes, &L);
+  if ((int64_t)L.items.size() != b->nitems) return b->fail(LBM_EINVAL, "internal: item count");
+  drop_graphs(b);
+  b->groups = L.groups;
+  BCHK(b, hipMemcpyAsync(b->at<void>(b->off_items), L.items.data(),
+                         L.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->at<void>(b->off_order), L.order.data(),
+                         L.order.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->at<void>(b->off_mstart), L.mstart.data(),
+                         L.mstart.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipStreamSynchronize(b->stream));
   return LBM_OK;
 }
 
@@ -333,8 +387,10 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   b->prec = ctxs[0]->p.precision;
   b->bouz = ctxs[0]->p.geometry == LBM_TUBE;
   Lists L;
-  make_lists(ctxs, n, &L);
+  b->group_bytes = kDefaultGroupBytes;
+  make_lists(ctxs, n, b->group_bytes, &L);
   b->nitems = (int64_t)L.items.size();
+  b->groups = L.groups;
   layout(b, n, b->nitems);
   if (arena_bytes < b->total || b->nitems >= ((int64_t)1 << 31)) {
     const lbm_status e = arena_bytes < b->total ? LBM_ENOMEM : LBM_EINVAL;
@@ -382,8 +438,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
 
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  drop_graphs(b);
   delete b;
 }
 
@@ -398,23 +453,31 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (nsteps == 0) return LBM_OK;
   lbm_status rs = resync(b);
   if (rs != LBM_OK) return rs;
+  // each group runs its kGraphSteps steps before the next group starts; the
+  // device counter advances once all groups have
   while (nsteps >= kGraphSteps && b->graphs_ok) {
-    if (!b->gexec || b->graph_wpb != b->wpb) {
-      if (build_graph(b) != LBM_OK) {
+    if (b->gexec.empty() || b->graph_wpb != b->wpb) {
+      if (build_graphs(b) != LBM_OK) {
         b->graphs_ok = false;  // fall back to plain launches
         (void)hipGetLastError();
         break;
       }
     }
-    BCHK(b, hipGraphLaunch(b->gexec, b->stream));
+    for (hipGraphExec_t x : b->gexec) BCHK(b, hipGraphLaunch(x, b->stream));
+    lbm_status s = launch_bump(b, kGraphSteps);
+    if (s != LBM_OK) return s;
     advance_members(b, kGraphSteps);
     nsteps -= kGraphSteps;
   }
-  for (; nsteps > 0; nsteps--) {
-    lbm_status s = launch_batch(b, 0, b->wpb);
+  if (nsteps > 0) {
+    for (size_t gi = 0; gi < b->groups.size(); gi++)
+      for (int64_t j = 0; j < nsteps; j++) {
+        lbm_status s = launch_batch(b, gi, j, b->wpb);
+        if (s != LBM_OK) return s;
+      }
+    lbm_status s = launch_bump(b, nsteps);
     if (s != LBM_OK) return s;
-    if ((s = launch_bump(b, 1)) != LBM_OK) return s;
-    advance_members(b, 1);
+    advance_members(b, nsteps);
   }
   return LBM_OK;
 }
@@ -459,10 +522,13 @@ lbm_status lbm_batch_tune(lbm_batch* b, int* chosen) {
   lbm_status s = LBM_OK;
   for (int k = 0; k < 4 && s == LBM_OK; k++) {
     const int w = cand[k];
-    for (int r = 0; r < 2 && s == LBM_OK; r++) s = launch_batch(b, 0, w);
+    const size_t ng = b->groups.size();
+    for (int r = 0; r < 2 && s == LBM_OK; r++)
+      for (size_t gi = 0; gi < ng && s == LBM_OK; gi++) s = launch_batch(b, gi, 0, w);
     if (s != LBM_OK) break;
     if ((s = b->hip(hipEventRecord(e0, b->stream), "hipEventRecord")) != LBM_OK) break;
-    for (int r = 0; r < 5 && s == LBM_OK; r++) s = launch_batch(b, 0, w);
+    for (int r = 0; r < 5 && s == LBM_OK; r++)
+      for (size_t gi = 0; gi < ng && s == LBM_OK; gi++) s = launch_batch(b, gi, 0, w);
     if (s != LBM_OK) break;
     if ((s = b->hip(hipEventRecord(e1, b->stream), "hipEventRecord")) != LBM_OK) break;
     if ((s = b->hip(hipEventSynchronize(e1), "hipEventSynchronize")) != LBM_OK) break;
@@ -486,6 +552,19 @@ lbm_status lbm_batch_set_shape(lbm_batch* b, int waves_per_group) {
               waves_per_group == 8))
     return LBM_EINVAL;
   b->wpb = waves_per_group;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_group_bytes(lbm_batch* b, size_t bytes) {
+  if (!b) return LBM_EINVAL;
+  if (bytes == b->group_bytes) return LBM_OK;
+  b->group_bytes = bytes;
+  return upload_lists(b);
+}
+
+lbm_status lbm_batch_groups(const lbm_batch* b, int* ngroups) {
+  if (!b || !ngroups) return LBM_EINVAL;
+  *ngroups = (int)b->groups.size();
   return LBM_OK;
 }
 

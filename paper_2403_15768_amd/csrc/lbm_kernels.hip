@@ -12,8 +12,8 @@
 //  k_set_r          lambda -> wall mixing weight r = 3 lambda / (1 + 3 lambda)
 //  k_copy           plain 16-byte streaming copy (measured bandwidth ceiling)
 //  k_set_step, k_add_step   device-resident step base read by graph-launched steps
-//  k_batch_step     k_step over the work list of a batch of channels, one
-//                   64-cell line segment per wave
+//  k_batch_step     k_step over the work list of a group of channels of a
+//                   batch, one 64-lane item per wave
 //  k_batch_moments, k_batch_reduce   per-member flux and mass of a batch
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -299,12 +299,17 @@ __device__ __forceinline__ bool lane_cell(const WorkItem& item, const StepArgs& 
 template <class L, typename S, typename M, bool BOUZ>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
-                                                    int64_t nitems, const int64_t* __restrict__ bstep,
+                                                    int64_t first, int64_t nwall, int64_t last,
+                                                    const int64_t* __restrict__ bstep,
                                                     int64_t step_off, int wpb) {
+  // items [first, last) of one group of members, wall items [first, nwall)
+  // first; on odd step_off the others are taken in reverse order, so that
+  // consecutive steps of a group meet its most recently written lines first
   // wave index in a scalar register: the item and member are wave-uniform
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t it = (int64_t)blockIdx.x * wpb + wv;
-  if (it >= nitems) return;
+  int64_t it = first + (int64_t)blockIdx.x * wpb + wv;
+  if (it >= last) return;
+  if ((step_off & 1) && it >= nwall) it = last - 1 - (it - nwall);
   const WorkItem item = items[it];
   const MemberDesc& d = md[item.member];
   const int64_t k = uniform64(*gbl(bstep)) + step_off;  // steps since the batch was built

@@ -61,7 +61,7 @@ EXPORTS = [
     "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error", "lbm_copy_probe",
     "lbm_transfer_state", "lbm_batch_footprint", "lbm_batch_create", "lbm_batch_destroy",
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
-    "lbm_batch_set_shape", "lbm_batch_last_error",
+    "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_last_error",
 ]
 
 _lib = None
@@ -109,6 +109,8 @@ def load() -> C.CDLL:
         "lbm_batch_invariants": [vp, dp],
         "lbm_batch_tune": [vp, C.POINTER(C.c_int)],
         "lbm_batch_set_shape": [vp, C.c_int],
+        "lbm_batch_set_group_bytes": [vp, sz],
+        "lbm_batch_groups": [vp, C.POINTER(C.c_int)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -401,6 +403,17 @@ class Batch:
     def set_shape(self, waves_per_group: int) -> None:
         self._ck(self._lib.lbm_batch_set_shape(self._h, int(waves_per_group)), "lbm_batch_set_shape")
         self.shape = int(waves_per_group)
+
+    def set_group_bytes(self, nbytes: int) -> None:
+        """Largest state of one group of members (0: a single group)."""
+        self._ck(self._lib.lbm_batch_set_group_bytes(self._h, int(nbytes)),
+                 "lbm_batch_set_group_bytes")
+
+    @property
+    def groups(self) -> int:
+        n = C.c_int()
+        self._ck(self._lib.lbm_batch_groups(self._h, C.byref(n)), "lbm_batch_groups")
+        return int(n.value)
 
 
 def copy_probe(src, dst, nbytes: int, stream) -> None:

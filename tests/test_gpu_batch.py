@@ -148,6 +148,40 @@ def test_batch_members_stepped_outside(lbm):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["f32", "f16s"])
+def test_batch_groups_do_not_change_results(lbm, precision):
+    """Members cut into several groups (each run 64 steps before the next)
+    give the same bits as one group stepped in lockstep, and as alone."""
+    say("batch groups", precision)
+    one = make_ducts(lbm, SPECS, precision)
+    many = make_ducts(lbm, SPECS, precision)
+    alone = make_ducts(lbm, SPECS, precision)
+    b1 = lbm.Batch(one)
+    b1.set_group_bytes(0)
+    assert b1.groups == 1
+    bn = lbm.Batch(many)
+    bn.set_group_bytes(1)  # every member its own group
+    assert bn.groups == len(SPECS)
+    for b in (b1, bn):
+        b.step(64 * 3 + 7)
+        b.step(5)
+    for c in alone:
+        c.step(204)
+    for a, x, y in zip(alone, one, many):
+        ref = a.get_state()[0]
+        assert np.array_equal(x.get_state()[0], ref)
+        assert np.array_equal(y.get_state()[0], ref)
+    i1, i2 = b1.invariants(), bn.invariants()
+    assert np.array_equal(i1, i2)
+    bn.set_group_bytes(3 * many[0].get_state()[0].nbytes)  # regroup mid-run
+    bn.step(70)
+    b1.step(70)
+    for x, y in zip(one, many):
+        assert np.array_equal(x.get_state()[0], y.get_state()[0])
+    b1.close()
+    bn.close()
+
+
 def test_batch_rejects_mixed_members(lbm):
     a = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f32")
     c = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f64")
