@@ -151,6 +151,44 @@ def test_tube_hagen_poiseuille_converges(R, tol):
     assert abs(q / (math.pi * g * R ** 4 / (8 * nu)) - 1) < tol
 
 
+def duct_flux_fourier(a, b, g, nu, nterms=400):
+    """Cross-section integral of the no-slip rectangular-duct Poiseuille
+    profile (width a in y, height b in z, walls at +-a/2, +-b/2):
+        u = 4 g a^2/(nu pi^3) sum_{n odd} (-1)^((n-1)/2)/n^3
+            [1 - cosh(n pi z/a)/cosh(n pi b/(2a))] cos(n pi y/a)."""
+    total = 0.0
+    for n in range(1, 2 * nterms, 2):
+        k = n * math.pi / a
+        sgn = (-1) ** ((n - 1) // 2)
+        amp = 4 * g * a * a / (nu * math.pi ** 3) * sgn / n ** 3
+        total += amp * (2 * sgn / k) * (b - 2 * math.tanh(k * b / 2) / k)
+    return total
+
+
+def test_duct_no_slip_converges_to_fourier_series():
+    # no-slip D3Q19 duct (half-way walls half a link outside the box, corners
+    # included): the steady flux per cross-section tends to the textbook
+    # Fourier-series integral at second order (error ratio ~4 per doubling);
+    # tau is the value where half-way bounce-back has no Poiseuille slip
+    tau, g = 0.5 + math.sqrt(3) / 4, 1e-6
+    nu = (tau - 0.5) / 3
+    errs = []
+    for ny, nz in ((8, 4), (16, 8), (32, 16)):
+        L = Lattice(19, DUCT, 2, ny, nz, tau=tau, force=(g, 0, 0))
+        L.set_friction(math.inf)
+        prev = None
+        for _ in range(60):
+            L.step(500)
+            q = L.invariants()[0]
+            if prev is not None and abs(q - prev) < 1e-12 * abs(q):
+                break
+            prev = q
+        errs.append(q / duct_flux_fourier(ny, nz, g, nu) - 1)
+    assert all(e > 0 for e in errs)
+    assert 3.3 < errs[0] / errs[1] < 4.5 and 3.3 < errs[1] / errs[2] < 4.5
+    assert errs[2] < 3e-3
+
+
 def test_channel_profile_symmetric_and_x_uniform():
     L = Lattice(9, SLAB, 64, 30, 1, tau=0.8, force=(1e-6, 0, 0))
     L.set_friction(0.025)
