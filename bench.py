@@ -173,7 +173,8 @@ def batch_workload(args):
     cells = sum(c.nx * c.ny * c.nz for c in specs)
     out = {"workload": "batch_256_ducts", "channels": len(specs), "cells": cells}
     fields, fluxes = {}, {}
-    for prec in ("f64", "f32", "f16s"):
+    precs = args.batch_precisions.split(",")
+    for prec in precs:
         log("batch:", prec)
         chs = [serve.open_channel(c, prec, serve.DuctQueries) for c in specs]
         b = lbm.Batch(chs)
@@ -194,32 +195,26 @@ def batch_workload(args):
         out[prec] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1),
                      "us_per_step": round(ms * 1e3 / n, 2),
                      "hbm_frac": round(bpu * cells * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "workgroup_items": shape}
+                     "workgroup_items": shape, "groups": b.groups}
         b.close()
         for ch in chs:
             ch.close()
         del chs
         torch.cuda.empty_cache()
-    for prec in ("f32", "f16s"):
+    for prec in [p for p in ("f32", "f16s") if p in precs and "f64" in precs]:
         fe = [float(np.max(np.abs(a - r)) / np.max(np.abs(r))) for a, r in zip(fields[prec], fields["f64"])]
         qe = np.abs(fluxes[prec] / fluxes["f64"] - 1)
         out[prec].update(field_err_max=float(np.max(fe)), field_err_median=float(np.median(fe)),
                          flux_err_max=float(np.max(qe)), flux_err_median=float(np.median(qe)))
-    # the FP64 reference against the oracle on the two smallest channels
-    import oracle
+    if not args.no_steady:
+        steady_comparison(specs, out)
+    print(json.dumps(out), flush=True)
 
-    small = sorted(range(len(specs)), key=lambda k: specs[k].nx * specs[k].ny * specs[k].nz)[:2]
-    errs = []
-    for k in small:
-        c = specs[k]
-        o = oracle.Lattice(19, oracle.DUCT, c.nx, c.ny, c.nz, tau=c.tau, force=(c.g, 0, 0))
-        o.set_friction(inputs.duct_friction(o.wall_coords(), c.nx, c.ny, c.nz,
-                                            inputs.rng_for("batch", c.seed_index)))
-        o.step(args.batch_steps)
-        uo = o.fields()[1]
-        errs.append(float(np.max(np.abs(fields["f64"][k] - uo)) / np.max(np.abs(uo))))
-    out["f64_vs_oracle_smallest"] = errs
-    # run to steady: FP32 storage vs mixed, same tolerance
+
+def steady_comparison(specs, out):
+    """Run to steady: FP32 storage vs mixed precision, same tolerance."""
+    from paper_2403_15768_amd import serve
+
     for mode in ("f32", "mixed"):
         log("batch: run to steady", mode)
         srv = serve.Server(mode=mode, hbm_budget=64 << 30, realtime=False, kind=serve.DuctQueries)
@@ -236,7 +231,6 @@ def batch_workload(args):
     out["steady_mixed_vs_f32_flux_diff_max"] = float(max(d))
     out["speedup_mixed_over_f32"] = round(out["steady_f32"]["makespan_s"] /
                                           out["steady_mixed"]["makespan_s"], 3)
-    print(json.dumps(out), flush=True)
 
 
 def serving_workload(args):
@@ -277,6 +271,10 @@ def main():
     ap.add_argument("--workload", default="duct", choices=["duct", "batch", "serving"],
                     help="duct: the headline line; batch / serving: their own JSON line")
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-precisions", default="f64,f32,f16s",
+                    help="storage precisions timed by --workload batch")
+    ap.add_argument("--no-steady", action="store_true",
+                    help="--workload batch: skip the run-to-steady comparison")
     ap.add_argument("--queries", type=int, default=500)
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--budget-gb", type=float, default=32.0)
