@@ -104,6 +104,41 @@ def test_batch_fp64_against_oracle(lbm):
         assert err < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_batch_slab_and_duct_members(lbm, precision):
+    """Planar members of both kinds in one batch: D3Q19 slabs (z periodic, so
+    the columns at the z boundary take the general path) beside ducts, bit-
+    identical to the same channels alone, and the FP64 slab against the oracle."""
+    say("batch slab + duct", precision)
+    shapes = [(lbm.SLAB, 40, 9, 6, 0.75), (lbm.DUCT, 37, 10, 8, 0.9), (lbm.SLAB, 100, 7, 3, 0.6),
+              (lbm.SLAB, 64, 12, 1, 0.8)]
+
+    def make():
+        out = []
+        for k, (geom, nx, ny, nz, tau) in enumerate(shapes):
+            ch = lbm.Channel(19, geom, nx, ny, nz, tau=tau, force=(1e-6, 0, 0), precision=precision)
+            lam = inputs.duct_friction(ch.wall_coords(), nx, ny, nz, inputs.rng_for("batch", 300 + k),
+                                       sigma=4.0)
+            ch.set_friction(lam)
+            out.append((ch, lam))
+        return out
+
+    alone, mixed = make(), make()
+    b = lbm.Batch([c for c, _ in mixed])
+    b.step(64 + 13)
+    for (a, _), (m, _) in zip(alone, mixed):
+        a.step(77)
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    if precision == "f64":
+        geom, nx, ny, nz, tau = shapes[0]
+        o = oracle.Lattice(19, oracle.SLAB, nx, ny, nz, tau=tau, force=(1e-6, 0, 0))
+        o.set_friction(mixed[0][1])
+        o.step(77)
+        ug, uo = mixed[0][0].field(1), o.fields()[1]
+        assert np.max(np.abs(ug - uo)) / np.max(np.abs(uo)) < 1e-12
+    b.close()
+
+
 def test_batch_tune_leaves_state(lbm):
     say("batch tune")
     chans = make_ducts(lbm, SPECS, "f32")
