@@ -74,10 +74,13 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   // FP64 arithmetic), float for F16S
   pl.wsize = p->precision == LBM_F16S ? 4 : 8;
   pl.nx = p->nx;
-  // x-lines padded to whole 128-byte cache lines (32 floats or doubles, 64
-  // halves): the kernels write the padding too, so no line is written in part
+  // x-lines of up to 128 cells are stored back to back (a column's Q lines
+  // are written by one workgroup, so the cache lines they share are
+  // completed in one L2); longer ones are padded to whole 128-byte cache
+  // lines (32 floats or doubles, 64 halves) and the kernels write the
+  // padding too, so no line is written in part by two workgroups
   const int pad = p->precision == LBM_F16S ? 64 : 32;
-  pl.nxp = (p->nx + pad - 1) / pad * pad;
+  pl.nxp = p->nx <= 128 ? p->nx : (p->nx + pad - 1) / pad * pad;
   pl.ny = p->ny;
   pl.nz = p->nz;
   pl.ncolbox = (int64_t)p->ny * p->nz;

@@ -47,7 +47,8 @@ struct lbm_batch {
   int wpb = 4;  // waves (work items) per workgroup, set by lbm_batch_tune
   int64_t k = 0;                  // steps since the member table was written
   std::vector<int64_t> base;      // each member's step when the table was written
-  size_t off_desc = 0, off_items = 0, off_order = 0, off_mstart = 0, off_partials = 0,
+  int64_t max_items = 0;  // capacity of the item arrays (largest list over the shapes)
+  size_t off_desc = 0, off_items = 0, off_cols = 0, off_order = 0, off_mstart = 0, off_partials = 0,
          off_out = 0, off_bstep = 0, total = 0;
   std::vector<hipGraph_t> graph;  // per group: kGraphSteps steps
   std::vector<hipGraphExec_t> gexec;
@@ -80,6 +81,7 @@ namespace {
 
 struct Lists {
   std::vector<WorkItem> items;
+  std::vector<int32_t> cols;  // column ids of the runs the items cover
   std::vector<lbm_batch::Group> groups;
   std::vector<int32_t> order;
   std::vector<int64_t> mstart;
@@ -89,27 +91,97 @@ struct Lists {
 // stays well inside the 256 MB last-level cache.
 constexpr size_t kDefaultGroupBytes = (size_t)200 << 20;
 
-// Interior columns of a member are cut into 32-cell chunks, two chunks per
-// wave, when the lanes of a wave can address both chunks from one base: the
-// storage lines are 32-element padded (not half precision), no periodic wrap
-// in z (slab), and every byte offset fits 32 bits.
+// The work list, in units of one workgroup (wpb items, one per wave; a
+// workgroup never shares a column with another, so the partly covered cache
+// lines at the ends of a column's x-lines are completed inside one L2):
+//  * general columns (wall links or periodic wrap): as many whole columns as
+//    fit in wpb waves, ceil(nxp/64) waves each; a longer column in segments
+//    of 64 wpb cells (its x-lines are then padded, so segments start on
+//    whole lines);
+//  * plain columns of a member whose lines fit 64-bit-free addressing: runs
+//    of k = floor(64 wpb / nxp) whole columns, their cells taken in order
+//    and 64 to a wave (a wave may span up to three columns);
+//  * unused waves of a workgroup get empty items (member -1).
+// cols[] holds the column ids of each run, items point into it.
 bool packs(const lbm_ctx* c) {
   const Plan& pl = c->pl;
-  return pl.prec != LBM_F16S && c->p.geometry != LBM_SLAB && pl.pop_bytes < ((size_t)1 << 31);
+  return pl.nxp >= 32 && pl.pop_bytes < ((size_t)1 << 31);
+}
+
+struct Builder {
+  Lists* L;
+  std::vector<std::vector<int32_t>>* mine;
+  int wpb;
+  int used = 0;  // items in the current workgroup
+  void push(const WorkItem& w) {
+    if (w.member >= 0) (*mine)[w.member].push_back((int32_t)L->items.size());
+    L->items.push_back(w);
+    used = (used + 1) % wpb;
+  }
+  void close_group() {  // pad the current workgroup with empty items
+    while (used != 0) push(WorkItem{-1, 0, 0, 0, 0, -1, 0u, 0});
+  }
+  // a run of columns (ids ascending) covering ncols * nxp cells
+  void run(int m, const std::vector<int32_t>& ids, int nxp, int32_t wallcol, uint32_t mask) {
+    const int32_t cbase = (int32_t)L->cols.size();
+    L->cols.insert(L->cols.end(), ids.begin(), ids.end());
+    const int64_t cells = (int64_t)ids.size() * nxp;
+    for (int64_t e0 = 0; e0 < cells; e0 += 64)
+      push(WorkItem{m, cbase, (int32_t)ids.size(), (int32_t)(e0 / nxp), (int32_t)(e0 % nxp), wallcol,
+                    mask, 0});
+  }
+};
+
+void member_items(Builder& B, lbm_ctx* c, int m, int pass) {
+  const Plan& pl = c->pl;
+  const int wpb = B.wpb, nxp = pl.nxp;
+  const int wpc = (nxp + 63) / 64;  // waves per column
+  std::vector<int32_t> ids;
+  if (pass == 1 && packs(c) && nxp <= 64 * wpb) {
+    const int k = std::max(1, 64 * wpb / nxp);
+    for (const lbm::ColSlot& cs : pl.slots) {
+      if (cs.mask != 0u) continue;
+      ids.push_back(cs.col);
+      if ((int)ids.size() == k) {
+        B.run(m, ids, nxp, -1, 0u);
+        B.close_group();
+        ids.clear();
+      }
+    }
+    if (!ids.empty()) {
+      B.run(m, ids, nxp, -1, 0u);
+      B.close_group();
+    }
+    return;
+  }
+  for (const lbm::ColSlot& cs : pl.slots) {
+    if ((pass == 0) != (cs.mask != 0u)) continue;
+    ids.assign(1, cs.col);
+    if (wpc > wpb) {  // long (padded) x-lines: segments of whole workgroups
+      const int32_t cbase = (int32_t)B.L->cols.size();
+      B.L->cols.push_back(cs.col);
+      B.close_group();
+      for (int x0 = 0; x0 < nxp; x0 += 64) B.push(WorkItem{m, cbase, 1, 0, x0, cs.wallcol, cs.mask, 0});
+      B.close_group();
+      continue;
+    }
+    if (B.used + wpc > wpb) B.close_group();
+    B.run(m, ids, nxp, cs.wallcol, cs.mask);
+  }
+  B.close_group();
 }
 
 // Members in order, cut into groups of at most group_bytes of state (a
 // larger member forms a group of its own; 0: one group).  Within a group,
-// wall items of every member first (they do more work), then the rest;
-// `order` lists each member's items contiguously for the reductions.
-void make_lists(lbm_ctx* const* ctxs, int n, size_t group_bytes, Lists* L) {
+// the general columns of every member first (they do more work), then the
+// plain ones; `order` lists each member's items contiguously for the
+// reductions.
+void make_lists(lbm_ctx* const* ctxs, int n, size_t group_bytes, int wpb, Lists* L) {
   L->items.clear();
+  L->cols.clear();
   L->groups.clear();
   std::vector<std::vector<int32_t>> mine(n);
-  auto push = [&](int m, const WorkItem& w) {
-    mine[m].push_back((int32_t)L->items.size());
-    L->items.push_back(w);
-  };
+  Builder B{L, &mine, wpb};
   for (int m0 = 0; m0 < n;) {
     int m1 = m0 + 1;
     size_t bytes = 2 * ctxs[m0]->pl.pop_bytes;
@@ -117,45 +189,9 @@ void make_lists(lbm_ctx* const* ctxs, int n, size_t group_bytes, Lists* L) {
       bytes += 2 * ctxs[m1++]->pl.pop_bytes;
     if (!group_bytes) m1 = n;
     lbm_batch::Group g{(int64_t)L->items.size(), 0, 0};
-  for (int pass = 0; pass < 2; pass++) {
-    if (pass == 1) g.nwall = (int64_t)L->items.size();
-    for (int m = m0; m < m1; m++) {
-      const Plan& pl = ctxs[m]->pl;
-      const int nwc = (int)pl.wallcols.size();
-      const int segs = (pl.nx + 63) / 64;
-      const int lo = pass == 0 ? 0 : nwc, hi = pass == 0 ? nwc : (int)pl.slots.size();
-      if (pass == 1 && packs(ctxs[m])) {
-        // chunk sequence over the interior columns in slot order (increasing
-        // column id), paired in order: the second chunk's column is never lower
-        const int cpl = pl.nxp / 32;
-        WorkItem w{m, 0, -1, 0u, 0, -1, 0, 32};
-        bool half = false;
-        for (int slot = lo; slot < hi; slot++) {
-          const int col = pl.slots[slot].col;
-          for (int k = 0; k < cpl; k++) {
-            if (!half) {
-              w.col = col;
-              w.x0 = 32 * k;
-              w.colb = -1;
-              half = true;
-            } else {
-              w.colb = col;
-              w.x0b = 32 * k;
-              push(m, w);
-              half = false;
-            }
-          }
-        }
-        if (half) push(m, w);
-        continue;
-      }
-      for (int slot = lo; slot < hi; slot++) {
-        const lbm::ColSlot& cs = pl.slots[slot];
-        for (int sg = 0; sg < segs; sg++)
-          push(m, WorkItem{m, cs.col, cs.wallcol, cs.mask, sg * 64, -1, 0, 64});
-      }
-    }
-  }
+    for (int m = m0; m < m1; m++) member_items(B, ctxs[m], m, 0);
+    g.nwall = (int64_t)L->items.size();
+    for (int m = m0; m < m1; m++) member_items(B, ctxs[m], m, 1);
     g.last = (int64_t)L->items.size();
     L->groups.push_back(g);
     m0 = m1;
@@ -183,7 +219,7 @@ lbm_status check_members(lbm_ctx* const* ctxs, int n) {
   return LBM_OK;
 }
 
-void layout(lbm_batch* b, int n, int64_t nitems) {
+void layout(lbm_batch* b, int n, int64_t nitems, int64_t ncols) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -192,6 +228,7 @@ void layout(lbm_batch* b, int n, int64_t nitems) {
   };
   b->off_desc = take(n * sizeof(MemberDesc));
   b->off_items = take(nitems * sizeof(WorkItem));
+  b->off_cols = take(ncols * sizeof(int32_t));
   b->off_order = take(nitems * sizeof(int32_t));
   b->off_mstart = take((n + 1) * sizeof(int64_t));
   b->off_partials = take(nitems * 2 * sizeof(double));
@@ -200,14 +237,24 @@ void layout(lbm_batch* b, int n, int64_t nitems) {
   b->total = off;
 }
 
-int64_t count_items(lbm_ctx* const* ctxs, int n) {
+// workgroup shapes (waves per workgroup) the autotuner tries
+constexpr int kShapes[3] = {2, 4, 8};
+
+// item capacity: the longest list over every shape (the length does not
+// depend on the grouping: each member's items are whole workgroups)
+int64_t max_items(lbm_ctx* const* ctxs, int n) {
   int64_t t = 0;
-  for (int m = 0; m < n; m++) {
-    const Plan& pl = ctxs[m]->pl;
-    const int64_t nwc = (int64_t)pl.wallcols.size(), nin = (int64_t)pl.slots.size() - nwc;
-    const int64_t segs = (pl.nx + 63) / 64;
-    t += nwc * segs + (packs(ctxs[m]) ? (nin * (pl.nxp / 32) + 1) / 2 : nin * segs);
+  for (int w : {1, 2, 4, 8}) {
+    Lists L;
+    make_lists(ctxs, n, 0, w, &L);
+    t = std::max<int64_t>(t, (int64_t)L.items.size());
   }
+  return t;
+}
+
+int64_t count_cols(lbm_ctx* const* ctxs, int n) {
+  int64_t t = 0;
+  for (int m = 0; m < n; m++) t += (int64_t)ctxs[m]->pl.slots.size();
   return t;
 }
 
@@ -216,9 +263,10 @@ lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, int wpb) {
   const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
+  const int32_t* cols = b->at<int32_t>(b->off_cols);
   lbm_batch::Group g = b->groups[gi];
   const int64_t* bstep = b->at<int64_t>(b->off_bstep);
-  void* args[8] = {(void*)&md,    (void*)&items,    (void*)&g.first, (void*)&g.nwall,
+  void* args[9] = {(void*)&md,     (void*)&items, (void*)&cols,     (void*)&g.first, (void*)&g.nwall,
                    (void*)&g.last, (void*)&bstep, (void*)&step_off, (void*)&wpb};
   const dim3 grid((unsigned)((g.last - g.first + wpb - 1) / wpb)), block(64 * wpb);
   BCHK(b, hipLaunchKernel(fn, grid, block, args, 0, b->stream));
@@ -292,6 +340,7 @@ lbm_status build_graph(lbm_batch* b, size_t gi, hipGraph_t* gout, hipGraphExec_t
   const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
+  const int32_t* cols = b->at<int32_t>(b->off_cols);
   const int64_t* bstep = b->at<int64_t>(b->off_bstep);
   lbm_batch::Group grp = b->groups[gi];
   int wpb = b->wpb;
@@ -299,8 +348,9 @@ lbm_status build_graph(lbm_batch* b, size_t gi, hipGraph_t* gout, hipGraphExec_t
   int64_t offs[kGraphSteps];
   for (int k = 0; k < kGraphSteps; k++) {
     offs[k] = k;
-    void* args[8] = {(void*)&md,       (void*)&items, (void*)&grp.first, (void*)&grp.nwall,
-                     (void*)&grp.last, (void*)&bstep, (void*)&offs[k],   (void*)&wpb};
+    void* args[9] = {(void*)&md,       (void*)&items,       (void*)&cols,
+                     (void*)&grp.first, (void*)&grp.nwall,  (void*)&grp.last,
+                     (void*)&bstep,     (void*)&offs[k],    (void*)&wpb};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
     kp.gridDim = dim3((unsigned)((grp.last - grp.first + wpb - 1) / wpb));
@@ -342,15 +392,19 @@ lbm_status build_graphs(lbm_batch* b) {
   return LBM_OK;
 }
 
-// (re)write the work list for the current group size; synchronous
+// (re)write the work list for the current group size and shape; synchronous
 lbm_status upload_lists(lbm_batch* b) {
   Lists L;
-  make_lists(b->m.data(), (int)b->m.size(), b->group_bytes, &L);
-  if ((int64_t)L.items.size() != b->nitems) return b->fail(LBM_EINVAL, "internal: item count");
+  make_lists(b->m.data(), (int)b->m.size(), b->group_bytes, b->wpb, &L);
+  if ((int64_t)L.items.size() > b->max_items) return b->fail(LBM_EINVAL, "internal: item count");
+  BCHK(b, hipStreamSynchronize(b->stream));  // no launch may still read the old list
   drop_graphs(b);
   b->groups = L.groups;
+  b->nitems = (int64_t)L.items.size();
   BCHK(b, hipMemcpyAsync(b->at<void>(b->off_items), L.items.data(),
                          L.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, b->stream));
+  BCHK(b, hipMemcpyAsync(b->at<void>(b->off_cols), L.cols.data(),
+                         L.cols.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
   BCHK(b, hipMemcpyAsync(b->at<void>(b->off_order), L.order.data(),
                          L.order.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
   BCHK(b, hipMemcpyAsync(b->at<void>(b->off_mstart), L.mstart.data(),
@@ -368,7 +422,7 @@ lbm_status lbm_batch_footprint(lbm_ctx* const* ctxs, int n, size_t* bytes) {
   lbm_status s = check_members(ctxs, n);
   if (s != LBM_OK) return s;
   lbm_batch tmp;
-  layout(&tmp, n, count_items(ctxs, n));
+  layout(&tmp, n, max_items(ctxs, n), count_cols(ctxs, n));
   *bytes = tmp.total;
   return LBM_OK;
 }
@@ -388,11 +442,12 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   b->bouz = ctxs[0]->p.geometry == LBM_TUBE;
   Lists L;
   b->group_bytes = kDefaultGroupBytes;
-  make_lists(ctxs, n, b->group_bytes, &L);
+  make_lists(ctxs, n, b->group_bytes, b->wpb, &L);
   b->nitems = (int64_t)L.items.size();
   b->groups = L.groups;
-  layout(b, n, b->nitems);
-  if (arena_bytes < b->total || b->nitems >= ((int64_t)1 << 31)) {
+  b->max_items = max_items(ctxs, n);
+  layout(b, n, b->max_items, count_cols(ctxs, n));
+  if (arena_bytes < b->total || b->max_items >= ((int64_t)1 << 31)) {
     const lbm_status e = arena_bytes < b->total ? LBM_ENOMEM : LBM_EINVAL;
     delete b;
     return e;
@@ -417,6 +472,9 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
                                     hipMemcpyHostToDevice, b->stream), "upload")) != LBM_OK) break;
     if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_items), L.items.data(),
                                     L.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                    b->stream), "upload")) != LBM_OK) break;
+    if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_cols), L.cols.data(),
+                                    L.cols.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                     b->stream), "upload")) != LBM_OK) break;
     if ((st = b->hip(hipMemcpyAsync(b->at<void>(b->off_order), L.order.data(),
                                     L.order.size() * sizeof(int32_t), hipMemcpyHostToDevice,
@@ -489,7 +547,8 @@ lbm_status lbm_batch_invariants(lbm_batch* b, double* out) {
   lbm_status rs = resync(b);
   if (rs != LBM_OK) return rs;
   BCHK(b, lbm::launch_batch_moments(b->Q, b->prec, b->at<MemberDesc>(b->off_desc),
-                                    b->at<WorkItem>(b->off_items), b->nitems,
+                                    b->at<WorkItem>(b->off_items), b->at<int32_t>(b->off_cols),
+                                    b->nitems,
                                     b->at<int64_t>(b->off_bstep), b->at<double>(b->off_partials), b->at<int32_t>(b->off_order),
                                     b->at<int64_t>(b->off_mstart), n, dout, b->bouz, b->stream));
   std::vector<double> h(2 * n);
@@ -511,17 +570,18 @@ lbm_status lbm_batch_tune(lbm_batch* b, int* chosen) {
   if (!b) return LBM_EINVAL;
   lbm_status rs = resync(b);
   if (rs != LBM_OK) return rs;
-  // time each candidate shape on launches whose results land in the buffers
-  // the next step overwrites anyway (counters unchanged)
-  static const int cand[4] = {1, 2, 4, 8};
+  // time each candidate shape (the work list is rebuilt for it) on launches
+  // whose results land in the buffers the next step overwrites anyway
+  // (state and counters unchanged)
   hipEvent_t e0, e1;
   BCHK(b, hipEventCreate(&e0));
   BCHK(b, hipEventCreate(&e1));
   float best = 1e30f;
   int pick = b->wpb;
   lbm_status s = LBM_OK;
-  for (int k = 0; k < 4 && s == LBM_OK; k++) {
-    const int w = cand[k];
+  for (int w : kShapes) {
+    b->wpb = w;
+    if ((s = upload_lists(b)) != LBM_OK) break;
     const size_t ng = b->groups.size();
     for (int r = 0; r < 2 && s == LBM_OK; r++)
       for (size_t gi = 0; gi < ng && s == LBM_OK; gi++) s = launch_batch(b, gi, 0, w);
@@ -541,8 +601,10 @@ lbm_status lbm_batch_tune(lbm_batch* b, int* chosen) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (s != LBM_OK) return s;
   b->wpb = pick;
+  lbm_status u = upload_lists(b);
+  if (s != LBM_OK) return s;
+  if (u != LBM_OK) return u;
   if (chosen) *chosen = pick;
   return LBM_OK;
 }
@@ -551,8 +613,9 @@ lbm_status lbm_batch_set_shape(lbm_batch* b, int waves_per_group) {
   if (!b || !(waves_per_group == 1 || waves_per_group == 2 || waves_per_group == 4 ||
               waves_per_group == 8))
     return LBM_EINVAL;
+  if (waves_per_group == b->wpb) return LBM_OK;
   b->wpb = waves_per_group;
-  return LBM_OK;
+  return upload_lists(b);
 }
 
 lbm_status lbm_batch_set_group_bytes(lbm_batch* b, size_t bytes) {

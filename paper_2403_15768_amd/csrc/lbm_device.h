@@ -117,15 +117,18 @@ struct MemberDesc {
   int32_t pad;
 };
 
-// A batch work item: the 64 lanes of one wave over one member.  span 64:
-// cells x0 .. x0+63 of column col (any column, lanes at x >= nxp idle).
-// span 32 (interior columns only): lanes 0..31 take cells x0 .. x0+31 of
-// column col, lanes 32..63 cells x0b .. x0b+31 of column colb > col (colb < 0:
-// idle), so x-lines of any length fill whole waves up to a 32-cell chunk.
+// A batch work item: the 64 lanes of one wave over one member.  The wave
+// covers cells xs .. xs+63 of the run of ncols columns whose ids are
+// cols[cbase], cols[cbase+1], ... starting in the run's column c0; lanes
+// past the end of a column continue in the next column of the run (runs of
+// plain columns only), lanes past the run (or past nxp for a single column)
+// are idle.  Items with member < 0 are empty.  wallcol and mask describe the
+// column of single-column items (mask 0 for plain columns).
 struct WorkItem {
-  int32_t member, col, wallcol;
+  int32_t member, cbase, ncols, c0, xs;
+  int32_t wallcol;
   uint32_t mask;
-  int32_t x0, colb, x0b, span;
+  int32_t pad;
 };
 
 // ------------------------------------------------------------------ storage

@@ -281,41 +281,69 @@ __global__ void __launch_bounds__(256) k_convert(const A* __restrict__ in, int n
 
 // ------------------------------------------------------------ batches
 // The lane's cell of a batch item: column, x, and the index shift from the
-// item's first column; false for an idle lane.
+// item's first column (colA); false for an idle lane.  colA..colC are the
+// item's first three run columns, loaded uniformly by the caller.
 struct LaneCell {
   int col, x;
   unsigned dl;
 };
-__device__ __forceinline__ bool lane_cell(const WorkItem& item, const StepArgs& a, int lane,
-                                          LaneCell* c) {
-  const bool hi = lane >= item.span;
-  if (hi && item.colb < 0) return false;
-  c->col = hi ? item.colb : item.col;
-  c->x = hi ? item.x0b + (lane - 32) : item.x0 + lane;
-  c->dl = hi ? (unsigned)((int64_t)(item.colb - item.col) * a.sC) : 0u;
-  return c->x < a.nxp;
+__device__ __forceinline__ bool lane_cell(const WorkItem& item, const StepArgs& a, int colA,
+                                          int colB, int colC, int lane, LaneCell* c) {
+  int x = item.xs + lane, j = 0;
+  if (item.ncols > 1) {
+    // nxp >= 32: 64 lanes cross at most two column ends
+    if (x >= a.nxp) {
+      x -= a.nxp;
+      j = 1;
+      if (x >= a.nxp) {
+        x -= a.nxp;
+        j = 2;
+      }
+    }
+    if (item.c0 + j >= item.ncols) return false;
+  } else if (x >= a.nxp) {
+    return false;
+  }
+  c->col = j == 0 ? colA : (j == 1 ? colB : colC);
+  c->x = x;
+  c->dl = (unsigned)((int64_t)(c->col - colA) * a.sC);
+  return true;
+}
+
+// the first three column ids of an item's run from its first column on
+__device__ __forceinline__ void run_cols(const int32_t* cols, const WorkItem& item, int* ca,
+                                         int* cb, int* cc) {
+  const LBM_GLOBAL int32_t* cl = gbl(cols) + item.cbase + item.c0;
+  *ca = uniform(cl[0]);
+  *cb = item.c0 + 1 < item.ncols ? uniform(cl[1]) : *ca;
+  *cc = item.c0 + 2 < item.ncols ? uniform(cl[2]) : *ca;
 }
 
 template <class L, typename S, typename M, bool BOUZ>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
+                                                    const int32_t* __restrict__ cols,
                                                     int64_t first, int64_t nwall, int64_t last,
                                                     const int64_t* __restrict__ bstep,
                                                     int64_t step_off, int wpb) {
-  // items [first, last) of one group of members, wall items [first, nwall)
-  // first; on odd step_off the others are taken in reverse order, so that
-  // consecutive steps of a group meet its most recently written lines first
-  // wave index in a scalar register: the item and member are wave-uniform
+  // items [first, last) of one group of members, general-path items
+  // [first, nwall) first; on odd step_off the others are taken in reverse
+  // order (whole workgroups: both ranges are multiples of wpb), so that
+  // consecutive steps of a group meet its most recently written lines first.
+  // The wave index is in a scalar register: item and member are wave-uniform.
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   int64_t it = first + (int64_t)blockIdx.x * wpb + wv;
   if (it >= last) return;
   if ((step_off & 1) && it >= nwall) it = last - 1 - (it - nwall);
   const WorkItem item = items[it];
+  if (item.member < 0) return;
   const MemberDesc& d = md[item.member];
   const int64_t k = uniform64(*gbl(bstep)) + step_off;  // steps since the batch was built
   const StepArgs& a = d.a;
+  int colA, colB, colC;
+  run_cols(cols, item, &colA, &colB, &colC);
   LaneCell c;
-  if (!lane_cell(item, a, (int)(threadIdx.x & 63), &c)) return;
+  if (!lane_cell(item, a, colA, colB, colC, (int)(threadIdx.x & 63), &c)) return;
   const int xc = c.x < a.nx ? c.x : a.nx - 1;  // padding lanes: as in k_step
   // both pointers loaded up front, then selected: no load waits on the parity
   const void* p0 = d.pop[0];
@@ -327,8 +355,8 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   info.wallcol = item.wallcol;
   info.mask = item.mask;
   M df[L::Q];
-  gather<L, S, M, M, BOUZ>(src, a, item.col, xc, info, df, c.dl);
-  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)item.col * a.sC, c.dl + (unsigned)c.x,
+  gather<L, S, M, M, BOUZ>(src, a, colA, xc, info, df, c.dl);
+  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)colA * a.sC, c.dl + (unsigned)c.x,
                          (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k);
 }
 
@@ -336,6 +364,7 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
 template <class L, typename S, typename W, bool BOUZ>
 __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restrict__ md,
                                                        const WorkItem* __restrict__ items,
+                                                       const int32_t* __restrict__ cols,
                                                        int64_t nitems,
                                                        const int64_t* __restrict__ bstep,
                                                        double* __restrict__ partials) {
@@ -343,18 +372,21 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
   const int64_t it = (int64_t)blockIdx.x * 4 + wv;
   if (it >= nitems) return;
   const WorkItem item = items[it];
+  if (item.member < 0) return;  // empty items are in no member's reduction
   const MemberDesc& d = md[item.member];
   const StepArgs& a = d.a;
+  int colA, colB, colC;
+  run_cols(cols, item, &colA, &colB, &colC);
   LaneCell c;
   double jx = 0.0, dr = 0.0;
-  if (lane_cell(item, a, (int)(threadIdx.x & 63), &c) && c.x < a.nx) {
+  if (lane_cell(item, a, colA, colB, colC, (int)(threadIdx.x & 63), &c) && c.x < a.nx) {
     const int par = (int)((d.cur_base + uniform64(*gbl(bstep))) & 1);
     const S* src = static_cast<const S*>(d.pop[par]);
     ColInfo info;
     info.wallcol = item.wallcol;
     info.mask = item.mask;
     double df[L::Q];
-    gather<L, S, double, W, BOUZ>(src, a, item.col, c.x, info, df, c.dl);
+    gather<L, S, double, W, BOUZ>(src, a, colA, c.x, info, df, c.dl);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
       dr += df[i];
@@ -431,31 +463,31 @@ const void* batch_step_kernel_ptr(int q, int prec, bool bouz) {
 }
 
 template <class L, typename S, typename W>
-static hipError_t batch_moments_t(const MemberDesc* md, const WorkItem* items, int64_t nitems,
-                                  const int64_t* bstep, double* partials, bool bouz,
-                                  hipStream_t st) {
+static hipError_t batch_moments_t(const MemberDesc* md, const WorkItem* items, const int32_t* cols,
+                                  int64_t nitems, const int64_t* bstep, double* partials,
+                                  bool bouz, hipStream_t st) {
   const dim3 grid((unsigned)((nitems + 3) / 4)), block(256);
   if (bouz)
-    hipLaunchKernelGGL((k_batch_moments<L, S, W, true>), grid, block, 0, st, md, items, nitems,
-                       bstep, partials);
+    hipLaunchKernelGGL((k_batch_moments<L, S, W, true>), grid, block, 0, st, md, items, cols,
+                       nitems, bstep, partials);
   else
-    hipLaunchKernelGGL((k_batch_moments<L, S, W, false>), grid, block, 0, st, md, items, nitems,
-                       bstep, partials);
+    hipLaunchKernelGGL((k_batch_moments<L, S, W, false>), grid, block, 0, st, md, items, cols,
+                       nitems, bstep, partials);
   return hipGetLastError();
 }
 hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,
-                                int64_t nitems, const int64_t* bstep, double* partials,
-                                const int32_t* order, const int64_t* mstart, int nmembers,
-                                double* out, bool bouz, hipStream_t st) {
+                                const int32_t* cols, int64_t nitems, const int64_t* bstep,
+                                double* partials, const int32_t* order, const int64_t* mstart,
+                                int nmembers, double* out, bool bouz, hipStream_t st) {
   hipError_t e;
+#define BM(L, S, W) batch_moments_t<L, S, W>(md, items, cols, nitems, bstep, partials, bouz, st)
   if (q == 9)
-    e = prec == 0 ? batch_moments_t<D2Q9, double, double>(md, items, nitems, bstep, partials, bouz, st)
-      : prec == 1 ? batch_moments_t<D2Q9, float, double>(md, items, nitems, bstep, partials, bouz, st)
-                  : batch_moments_t<D2Q9, _Float16, float>(md, items, nitems, bstep, partials, bouz, st);
+    e = prec == 0 ? BM(D2Q9, double, double) : prec == 1 ? BM(D2Q9, float, double)
+                                              : BM(D2Q9, _Float16, float);
   else
-    e = prec == 0 ? batch_moments_t<D3Q19, double, double>(md, items, nitems, bstep, partials, bouz, st)
-      : prec == 1 ? batch_moments_t<D3Q19, float, double>(md, items, nitems, bstep, partials, bouz, st)
-                  : batch_moments_t<D3Q19, _Float16, float>(md, items, nitems, bstep, partials, bouz, st);
+    e = prec == 0 ? BM(D3Q19, double, double) : prec == 1 ? BM(D3Q19, float, double)
+                                               : BM(D3Q19, _Float16, float);
+#undef BM
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_reduce, dim3(nmembers), dim3(256), 0, st, partials, order, mstart, out);
   return hipGetLastError();

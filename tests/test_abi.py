@@ -32,9 +32,15 @@ def test_footprint_host_logic():
     assert pops <= nb < pops * 1.05
     p64 = lbm.make_params(lbm.D3Q19, lbm.DUCT, 256, 128, 64, tau=0.7, precision="f64")
     assert lbm.footprint(p64) > 1.9 * nb
-    # padded x-lines: nx = 37 is stored as 64
+    # x-lines up to 128 cells stored back to back; longer ones padded to
+    # whole 128-byte lines (nx = 200 -> 224 floats, 256 halves)
     p = lbm.make_params(lbm.D3Q19, lbm.DUCT, 37, 5, 4, tau=0.7, precision="f32")
-    assert lbm.footprint(p) >= 2 * 19 * 64 * 20 * 4
+    pops = 2 * 19 * 37 * 20 * 4
+    assert pops <= lbm.footprint(p) < pops * 1.2
+    for prec, nxp, size in (("f32", 224, 4), ("f16s", 256, 2)):
+        p = lbm.make_params(lbm.D3Q19, lbm.DUCT, 200, 5, 4, tau=0.7, precision=prec)
+        pops = 2 * 19 * nxp * 20 * size
+        assert pops <= lbm.footprint(p) < pops * 1.2
 
 
 @pytest.mark.parametrize("kw", [
