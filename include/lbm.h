@@ -198,10 +198,13 @@ lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
  * may differ.  One launch per time step advances a group of members over a
  * work list of 64-lane items (wall segments first); runs of 64 steps are
  * replayed from captured hipGraphs.  Members are cut, in order, into groups
- * whose state fits the last-level cache (200 MiB by default, see
+ * whose state fits the last-level cache (128 MiB by default, see
  * lbm_batch_set_group_bytes); a call to lbm_batch_step runs each group 64
- * steps at a time, one group after the other, so a group's populations stay
- * cached between its steps.  Members keep their own buffers, parameters and
+ * steps at a time, so a group's populations stay cached between its steps.
+ * Groups are dealt round-robin to two streams (default, see
+ * lbm_batch_set_streams): the batch stream and internal streams the batch
+ * creates at the default priority, joined back into the batch stream before
+ * lbm_batch_step returns its work to that stream's order.  Members keep their own buffers, parameters and
  * step counters, and a member advanced in a batch is bit-for-bit the same as
  * the member advanced alone.  Their lbm_get_*, lbm_invariants and
  * lbm_get_state calls stay valid between batch calls; a member stepped,
@@ -236,6 +239,9 @@ lbm_status lbm_batch_set_shape(lbm_batch *b, int waves_per_group);
  * list; synchronous.  Results do not depend on the grouping. */
 lbm_status lbm_batch_set_group_bytes(lbm_batch *b, size_t bytes);
 lbm_status lbm_batch_groups(const lbm_batch *b, int *ngroups);
+/* Number of streams (1..4) the groups are dealt to; results do not depend
+ * on it. */
+lbm_status lbm_batch_set_streams(lbm_batch *b, int nstreams);
 const char *lbm_batch_last_error(const lbm_batch *b);
 
 /* Plain streaming device-to-device copy of `bytes` (a multiple of 16, both

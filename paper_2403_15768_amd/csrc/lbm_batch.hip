@@ -17,7 +17,10 @@
 // is cut into groups whose state fits the 256 MB last-level cache, and each
 // group runs a whole 64-step graph before the next group starts.  A group's
 // populations then stay in that cache from one step to the next instead of
-// streaming from HBM every step.
+// streaming from HBM every step.  Groups are dealt round-robin to two
+// streams (the batch's own and one of the batch's making, both at default
+// priority) so that one group's launch tails overlap another group's work;
+// the streams join before the device counter advances.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +34,8 @@
 using lbm::MemberDesc;
 using lbm::WorkItem;
 using namespace lbm_host;
+
+constexpr int kMaxStreams = 4;
 
 struct lbm_batch {
   std::vector<lbm_ctx*> m;
@@ -53,6 +58,9 @@ struct lbm_batch {
   std::vector<hipGraph_t> graph;  // per group: kGraphSteps steps
   std::vector<hipGraphExec_t> gexec;
   int graph_wpb = 0;
+  int nstreams = 2;                       // streams the groups are dealt to
+  hipStream_t side[kMaxStreams - 1] = {};  // streams 1.. (stream 0 is the batch stream)
+  hipEvent_t fork = nullptr, join[kMaxStreams - 1] = {};
   bool graphs_ok = true;
   std::string err;
 
@@ -87,9 +95,9 @@ struct Lists {
   std::vector<int64_t> mstart;
 };
 
-// Default group size: the state of a group (both buffers of every member)
-// stays well inside the 256 MB last-level cache.
-constexpr size_t kDefaultGroupBytes = (size_t)200 << 20;
+// Default group size: with two groups in flight at a time their state (both
+// buffers of every member) fills the 256 MB last-level cache.
+constexpr size_t kDefaultGroupBytes = (size_t)128 << 20;
 
 // The work list, in units of one workgroup (wpb items, one per wave; a
 // workgroup never shares a column with another, so the partly covered cache
@@ -259,7 +267,8 @@ int64_t count_cols(lbm_ctx* const* ctxs, int n) {
 }
 
 // one step (step_off steps past the device counter) of group gi
-lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, int wpb) {
+lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, int wpb,
+                        hipStream_t st = nullptr) {
   const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
@@ -269,8 +278,48 @@ lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, int wpb) {
   void* args[9] = {(void*)&md,     (void*)&items, (void*)&cols,     (void*)&g.first, (void*)&g.nwall,
                    (void*)&g.last, (void*)&bstep, (void*)&step_off, (void*)&wpb};
   const dim3 grid((unsigned)((g.last - g.first + wpb - 1) / wpb)), block(64 * wpb);
-  BCHK(b, hipLaunchKernel(fn, grid, block, args, 0, b->stream));
+  BCHK(b, hipLaunchKernel(fn, grid, block, args, 0, st ? st : b->stream));
   return LBM_OK;
+}
+
+hipStream_t group_stream(const lbm_batch* b, size_t gi) {
+  const int k = (int)(gi % (size_t)b->nstreams);
+  return k ? b->side[k - 1] : b->stream;
+}
+
+// the other streams start after the work queued so far on the batch stream
+lbm_status fork_streams(lbm_batch* b) {
+  if (b->nstreams < 2) return LBM_OK;
+  BCHK(b, hipEventRecord(b->fork, b->stream));
+  for (int k = 1; k < b->nstreams; k++) BCHK(b, hipStreamWaitEvent(b->side[k - 1], b->fork, 0));
+  return LBM_OK;
+}
+
+// the batch stream continues after everything queued on the others
+lbm_status join_streams(lbm_batch* b) {
+  for (int k = 1; k < b->nstreams; k++) {
+    BCHK(b, hipEventRecord(b->join[k - 1], b->side[k - 1]));
+    BCHK(b, hipStreamWaitEvent(b->stream, b->join[k - 1], 0));
+  }
+  return LBM_OK;
+}
+
+void drop_streams(lbm_batch* b) {
+  for (int k = 0; k < kMaxStreams - 1; k++) {
+    if (b->side[k]) {
+      (void)hipStreamSynchronize(b->side[k]);
+      (void)hipStreamDestroy(b->side[k]);
+      b->side[k] = nullptr;
+    }
+    if (b->join[k]) {
+      (void)hipEventDestroy(b->join[k]);
+      b->join[k] = nullptr;
+    }
+  }
+  if (b->fork) {
+    (void)hipEventDestroy(b->fork);
+    b->fork = nullptr;
+  }
 }
 
 void drop_graphs(lbm_batch* b) {
@@ -454,11 +503,22 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   }
   b->arena = static_cast<char*>(arena);
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // extra streams at the default priority, and the events that order them
+  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < kMaxStreams - 1; k++)
+    ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    drop_streams(b);
+    delete b;
+    return LBM_EDEVICE;
+  }
   std::vector<MemberDesc> desc(n);
   b->base.assign(n, 0);
   for (int m = 0; m < n; m++) {
     lbm_ctx* c = ctxs[m];
     if ((s = sync(c)) != LBM_OK) {
+      drop_streams(b);
       delete b;
       return s;
     }
@@ -487,6 +547,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
     st = b->hip(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   } while (0);
   if (st != LBM_OK) {
+    drop_streams(b);
     delete b;
     return st;
   }
@@ -497,6 +558,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
   drop_graphs(b);
+  drop_streams(b);
   delete b;
 }
 
@@ -521,19 +583,24 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
         break;
       }
     }
-    for (hipGraphExec_t x : b->gexec) BCHK(b, hipGraphLaunch(x, b->stream));
-    lbm_status s = launch_bump(b, kGraphSteps);
+    lbm_status s = fork_streams(b);
+    if (s != LBM_OK) return s;
+    for (size_t gi = 0; gi < b->gexec.size(); gi++)
+      BCHK(b, hipGraphLaunch(b->gexec[gi], group_stream(b, gi)));
+    if ((s = join_streams(b)) != LBM_OK) return s;
+    s = launch_bump(b, kGraphSteps);
     if (s != LBM_OK) return s;
     advance_members(b, kGraphSteps);
     nsteps -= kGraphSteps;
   }
   if (nsteps > 0) {
+    lbm_status s = fork_streams(b);
+    if (s != LBM_OK) return s;
     for (size_t gi = 0; gi < b->groups.size(); gi++)
-      for (int64_t j = 0; j < nsteps; j++) {
-        lbm_status s = launch_batch(b, gi, j, b->wpb);
-        if (s != LBM_OK) return s;
-      }
-    lbm_status s = launch_bump(b, nsteps);
+      for (int64_t j = 0; j < nsteps; j++)
+        if ((s = launch_batch(b, gi, j, b->wpb, group_stream(b, gi))) != LBM_OK) return s;
+    if ((s = join_streams(b)) != LBM_OK) return s;
+    s = launch_bump(b, nsteps);
     if (s != LBM_OK) return s;
     advance_members(b, nsteps);
   }
@@ -623,6 +690,12 @@ lbm_status lbm_batch_set_group_bytes(lbm_batch* b, size_t bytes) {
   if (bytes == b->group_bytes) return LBM_OK;
   b->group_bytes = bytes;
   return upload_lists(b);
+}
+
+lbm_status lbm_batch_set_streams(lbm_batch* b, int nstreams) {
+  if (!b || nstreams < 1 || nstreams > kMaxStreams) return LBM_EINVAL;
+  b->nstreams = nstreams;
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_groups(const lbm_batch* b, int* ngroups) {

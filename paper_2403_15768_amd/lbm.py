@@ -61,7 +61,8 @@ EXPORTS = [
     "lbm_set_state", "lbm_step_count", "lbm_sync", "lbm_last_error", "lbm_copy_probe",
     "lbm_transfer_state", "lbm_batch_footprint", "lbm_batch_create", "lbm_batch_destroy",
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
-    "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_last_error",
+    "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
+    "lbm_batch_last_error",
 ]
 
 _lib = None
@@ -111,6 +112,7 @@ def load() -> C.CDLL:
         "lbm_batch_set_shape": [vp, C.c_int],
         "lbm_batch_set_group_bytes": [vp, sz],
         "lbm_batch_groups": [vp, C.POINTER(C.c_int)],
+        "lbm_batch_set_streams": [vp, C.c_int],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -408,6 +410,10 @@ class Batch:
         """Largest state of one group of members (0: a single group)."""
         self._ck(self._lib.lbm_batch_set_group_bytes(self._h, int(nbytes)),
                  "lbm_batch_set_group_bytes")
+
+    def set_streams(self, n: int) -> None:
+        """Streams the groups are dealt to (1..4)."""
+        self._ck(self._lib.lbm_batch_set_streams(self._h, int(n)), "lbm_batch_set_streams")
 
     @property
     def groups(self) -> int:

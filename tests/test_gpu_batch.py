@@ -209,6 +209,8 @@ def test_batch_groups_do_not_change_results(lbm, precision):
     i1, i2 = b1.invariants(), bn.invariants()
     assert np.array_equal(i1, i2)
     bn.set_group_bytes(3 * many[0].get_state()[0].nbytes)  # regroup mid-run
+    bn.set_streams(3)
+    b1.set_streams(1)
     bn.step(70)
     b1.step(70)
     for x, y in zip(one, many):
