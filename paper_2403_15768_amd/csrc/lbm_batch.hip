@@ -184,10 +184,16 @@ void member_items(Builder& B, lbm_ctx* c, int m, int pass) {
 // the general columns of every member first (they do more work), then the
 // plain ones; `order` lists each member's items contiguously for the
 // reductions.
+int64_t count_items(lbm_ctx* const* ctxs, int n, int wpb);
+
 void make_lists(lbm_ctx* const* ctxs, int n, size_t group_bytes, int wpb, Lists* L) {
   L->items.clear();
   L->cols.clear();
   L->groups.clear();
+  int64_t ncol = 0;
+  for (int m = 0; m < n; m++) ncol += (int64_t)ctxs[m]->pl.slots.size();
+  L->cols.reserve(ncol);
+  L->items.reserve(count_items(ctxs, n, wpb));
   std::vector<std::vector<int32_t>> mine(n);
   Builder B{L, &mine, wpb};
   for (int m0 = 0; m0 < n;) {
@@ -248,15 +254,33 @@ void layout(lbm_batch* b, int n, int64_t nitems, int64_t ncols) {
 // workgroup shapes (waves per workgroup) the autotuner tries
 constexpr int kShapes[3] = {2, 4, 8};
 
+// items make_lists gives a member's pass, counted without building them
+int64_t member_count(const lbm_ctx* c, int wpb, int pass) {
+  const Plan& pl = c->pl;
+  const int64_t nxp = pl.nxp, wpc = (nxp + 63) / 64;
+  int64_t g = 0;
+  for (const lbm::ColSlot& cs : pl.slots) g += (pass == 0) == (cs.mask != 0u);
+  if (g == 0) return 0;
+  if (pass == 1 && packs(c) && nxp <= 64 * wpb) {
+    const int64_t k = std::max<int64_t>(1, 64 * wpb / nxp);
+    return (g + k - 1) / k * wpb;
+  }
+  if (wpc > wpb) return g * ((wpc + wpb - 1) / wpb) * wpb;
+  const int64_t kw = wpb / wpc;
+  return (g + kw - 1) / kw * wpb;
+}
+
+int64_t count_items(lbm_ctx* const* ctxs, int n, int wpb) {
+  int64_t t = 0;
+  for (int m = 0; m < n; m++) t += member_count(ctxs[m], wpb, 0) + member_count(ctxs[m], wpb, 1);
+  return t;
+}
+
 // item capacity: the longest list over every shape (the length does not
 // depend on the grouping: each member's items are whole workgroups)
 int64_t max_items(lbm_ctx* const* ctxs, int n) {
   int64_t t = 0;
-  for (int w : {1, 2, 4, 8}) {
-    Lists L;
-    make_lists(ctxs, n, 0, w, &L);
-    t = std::max<int64_t>(t, (int64_t)L.items.size());
-  }
+  for (int w : {1, 2, 4, 8}) t = std::max(t, count_items(ctxs, n, w));
   return t;
 }
 
@@ -445,7 +469,9 @@ lbm_status build_graphs(lbm_batch* b) {
 lbm_status upload_lists(lbm_batch* b) {
   Lists L;
   make_lists(b->m.data(), (int)b->m.size(), b->group_bytes, b->wpb, &L);
-  if ((int64_t)L.items.size() > b->max_items) return b->fail(LBM_EINVAL, "internal: item count");
+  if ((int64_t)L.items.size() != count_items(b->m.data(), (int)b->m.size(), b->wpb) ||
+      (int64_t)L.items.size() > b->max_items)
+    return b->fail(LBM_EINVAL, "internal: item count");
   BCHK(b, hipStreamSynchronize(b->stream));  // no launch may still read the old list
   drop_graphs(b);
   b->groups = L.groups;
@@ -496,6 +522,10 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   b->groups = L.groups;
   b->max_items = max_items(ctxs, n);
   layout(b, n, b->max_items, count_cols(ctxs, n));
+  if (b->nitems != count_items(ctxs, n, b->wpb)) {
+    delete b;
+    return LBM_EINVAL;  // internal: the counted and the built lists differ
+  }
   if (arena_bytes < b->total || b->max_items >= ((int64_t)1 << 31)) {
     const lbm_status e = arena_bytes < b->total ? LBM_ENOMEM : LBM_EINVAL;
     delete b;
