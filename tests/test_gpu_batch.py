@@ -219,6 +219,47 @@ def test_batch_groups_do_not_change_results(lbm, precision):
     bn.close()
 
 
+def test_batch_full_size_sampled(lbm):
+    """The 256-duct batch at full size (48 M cells), in the configuration the
+    benchmark times (default groups and streams): sampled members are bit-
+    identical to the same channels stepped alone, and the smallest one agrees
+    with the oracle (FP64 run of the same member)."""
+    say("batch full size")
+    specs = inputs.batch_channels(256)
+    chans = []
+    for k, c in enumerate(specs):
+        ch = lbm.Channel(19, lbm.DUCT, c.nx, c.ny, c.nz, tau=c.tau, force=(c.g, 0, 0), precision="f32")
+        ch.set_friction(inputs.duct_friction(ch.wall_coords(), c.nx, c.ny, c.nz,
+                                             inputs.rng_for("batch", c.seed_index)))
+        chans.append(ch)
+    b = lbm.Batch(chans)
+    assert b.groups > 1
+    b.step(64 + 9)
+    inv = b.invariants()
+    small = min(range(len(specs)), key=lambda k: specs[k].nx * specs[k].ny * specs[k].nz)
+    for k in sorted({0, 101, 255, small}):
+        c = specs[k]
+        a = lbm.Channel(19, lbm.DUCT, c.nx, c.ny, c.nz, tau=c.tau, force=(c.g, 0, 0), precision="f32")
+        a.set_friction(inputs.duct_friction(a.wall_coords(), c.nx, c.ny, c.nz,
+                                            inputs.rng_for("batch", c.seed_index)))
+        a.step(73)
+        assert np.array_equal(a.get_state()[0], chans[k].get_state()[0]), k
+        assert abs(inv[k, 0] / a.invariants()[0] - 1) < 1e-13
+        a.close()
+    c = specs[small]
+    o = oracle.Lattice(19, oracle.DUCT, c.nx, c.ny, c.nz, tau=c.tau, force=(c.g, 0, 0))
+    o.set_friction(inputs.duct_friction(o.wall_coords(), c.nx, c.ny, c.nz,
+                                        inputs.rng_for("batch", c.seed_index)))
+    o.step(73)
+    ug, uo = chans[small].field(1), o.fields()[1]
+    err = np.max(np.abs(ug - uo)) / np.max(np.abs(uo))
+    say("  smallest member vs oracle", err)
+    assert err < 1e-5
+    b.close()
+    for ch in chans:
+        ch.close()
+
+
 def test_batch_rejects_mixed_members(lbm):
     a = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f32")
     c = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f64")
