@@ -73,6 +73,11 @@ def load() -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime; it must be loaded before liblbm.so so
+    # that the library binds to that runtime (same soname) instead of pulling
+    # in a second one whose streams and allocations torch's would not know
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "(hipcc, gfx950); there is no CPU fallback")
