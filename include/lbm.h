@@ -196,23 +196,24 @@ lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
  * A batch groups n existing contexts with the same lattice, storage
  * precision and wall kind (TUBE or planar); sizes, tau, force and friction
  * may differ.  One launch per time step advances a group of members over a
- * work list of 64-lane items (wall segments first); runs of 64 steps are
- * replayed from captured hipGraphs.  Members are cut, in order, into groups
- * whose state fits the last-level cache (128 MiB by default, see
- * lbm_batch_set_group_bytes); a call to lbm_batch_step runs each group 64
- * steps at a time, so a group's populations stay cached between its steps.
- * Groups are dealt round-robin to two streams (default, see
- * lbm_batch_set_streams): the batch stream and internal streams the batch
- * creates at the default priority, joined back into the batch stream before
- * lbm_batch_step returns its work to that stream's order.  Members keep their own buffers, parameters and
- * step counters, and a member advanced in a batch is bit-for-bit the same as
- * the member advanced alone.  Their lbm_get_*, lbm_invariants and
- * lbm_get_state calls stay valid between batch calls; a member stepped,
- * restored or transferred outside the batch is taken up at its current step
- * by the next batch call. */
+ * work list of 64-lane items laid out in whole workgroups that never share a
+ * column (wall columns first); runs of 64 steps are replayed from captured
+ * hipGraphs.  Members are cut, in order, into groups whose state fits the
+ * last-level cache (128 MiB by default, see lbm_batch_set_group_bytes); a
+ * call to lbm_batch_step runs each group 64 steps at a time, so a group's
+ * populations stay cached between its steps.  Groups are dealt round-robin
+ * to two streams by default (see lbm_batch_set_streams): the batch stream
+ * and streams the batch creates at the default priority, which wait for the
+ * batch stream's earlier work and are joined back into it, so every call
+ * stays ordered on the batch stream.  Members keep their own buffers,
+ * parameters and step counters, and a member advanced in a batch is bit-for-
+ * bit the same as the member advanced alone.  Their lbm_get_*,
+ * lbm_invariants and lbm_get_state calls stay valid between batch calls; a
+ * member stepped, restored or transferred outside the batch is taken up at
+ * its current step by the next batch call.  Members must outlive the batch. */
 typedef struct lbm_batch lbm_batch; /* opaque */
-/* Device bytes a batch of these contexts needs (descriptors, work list,
- * reduction partials). */
+/* Device bytes a batch of these contexts needs (descriptors, work list for
+ * the longest workgroup shape, column ids, reduction partials). */
 lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
 /* arena: device, >= footprint bytes, 256-byte aligned, owned by the caller
  * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
@@ -226,12 +227,13 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 /* Per member m: out[3m] flux, out[3m+1] mass, out[3m+2] mass deviation, as
  * lbm_invariants.  Deterministic FP64 reductions.  Synchronous. */
 lbm_status lbm_batch_invariants(lbm_batch *b, double *out);
-/* Autotuner: time the candidate workgroup shapes (1, 2, 4 or 8 work items per
- * workgroup) on this batch and keep the fastest; *chosen may be NULL.  The
- * timed launches write only the buffers the next step overwrites: no state
- * or counter changes.  Synchronous. */
+/* Autotuner: time the candidate workgroup shapes (2, 4 or 8 waves per
+ * workgroup; the work list is rebuilt for each) on this batch and keep the
+ * fastest; *chosen may be NULL.  The timed launches write only the buffers
+ * the next step overwrites: no state or counter changes.  Synchronous. */
 lbm_status lbm_batch_tune(lbm_batch *b, int *chosen);
-/* Set the workgroup shape directly (1, 2, 4 or 8). */
+/* Set the workgroup shape directly (1, 2, 4 or 8 waves; 4 at creation);
+ * rebuilds the work list, synchronous. */
 lbm_status lbm_batch_set_shape(lbm_batch *b, int waves_per_group);
 /* Largest state (both buffers of every member) of one group, in bytes; a
  * member larger than that forms a group of its own; 0 puts every member in
