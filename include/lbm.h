@@ -210,7 +210,8 @@ lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
  * bit the same as the member advanced alone.  Their lbm_get_*,
  * lbm_invariants and lbm_get_state calls stay valid between batch calls; a
  * member stepped, restored or transferred outside the batch is taken up at
- * its current step by the next batch call.  Members must outlive the batch. */
+ * its current step by the next batch call (if its stream is not the batch
+ * stream, the caller orders the two).  Members must outlive the batch. */
 typedef struct lbm_batch lbm_batch; /* opaque */
 /* Device bytes a batch of these contexts needs (descriptors, work list for
  * the longest workgroup shape, column ids, reduction partials). */
