@@ -330,6 +330,7 @@ def main():
     ext["final_flux"] = q
     ext["mass_deviation"] = dm
 
+    arith = "f32" if args.precision == "f16s" else "f64"  # half storage computes in float
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
@@ -346,16 +347,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": arith,
         "data": "synthetic",
         "config": {"workload": f"duct_256x128x64_d3q19_{args.precision}storage",
                    "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
-                   "g": 1e-6, "storage": args.precision, "arithmetic": "f64",
+                   "g": 1e-6, "storage": args.precision, "arithmetic": arith,
                    "friction": "smooth random lambda(x,s): mean 0.05, std 0.02, corr. length 16",
                    "check_every": args.check_every},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step<D3Q19>",
+                     "traffic": traffic,
+                     "traffic_GBs": None if traffic is None else round(traffic / kern_s / 1e9, 1),
+                     "kernel": "k_step<D3Q19>",
                      "kernel_us": round(kern_s * 1e6, 3), "bytes_per_update": bpu},
         "cpu_baseline": cpu,
         "extras": ext,
