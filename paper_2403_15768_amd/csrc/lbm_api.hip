@@ -27,6 +27,9 @@ int lat_c(int Q, int i, int a) {
   return a == 0 ? lbm::D3Q19::cx[i] : (a == 1 ? lbm::D3Q19::cy[i] : lbm::D3Q19::cz[i]);
 }
 
+// storage row of direction i within a column
+int lat_row(int Q, int i) { return Q == 9 ? lbm::D2Q9::row[i] : lbm::D3Q19::row[i]; }
+
 // Positive root s of |P - s C|^2 = R^2 with P inside and P - C outside the
 // circle (the fraction of the link from the fluid node to the wall).
 double wall_fraction(double py, double pz, double cy, double cz, double R) {
@@ -269,7 +272,7 @@ void fill_args(lbm_ctx* c) {
   a.step_off = 0;
   a.seed = kSeed;
   for (int i = 0; i < 19; i++)
-    a.nboff[i] = i < pl.Q ? (int64_t)i * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
+    a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
                           : 0;
 }
@@ -664,7 +667,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
     for (int64_t col = 0; col < pl.ncolbox; col++) {
       const bool solid = pl.colinfo[col].mask & lbm::kSolidColumn;
       for (int x = 0; x < pl.nx; x++) {
-        const int64_t src = col * pl.sC + i * pl.sI + x;
+        const int64_t src = col * pl.sC + lat_row(pl.Q, i) * pl.sI + x;
         double v = 0.0;
         if (!solid) {
           if (pl.prec == LBM_F64) v = reinterpret_cast<const double*>(raw.data())[src];

@@ -24,6 +24,8 @@ struct D2Q9 {
   static constexpr int sig[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
   static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  // storage row of direction i within a column (see the layout note below)
+  static constexpr int row[9] = {0, 1, 3, 2, 6, 4, 5, 7, 8};
 };
 
 struct D3Q19 {
@@ -38,15 +40,22 @@ struct D3Q19 {
                                    1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  // storage row of direction i within a column (see the layout note below)
+  static constexpr int row[19] = {0, 1, 2, 3, 6, 9, 12, 4, 7, 8, 5, 10, 13, 14, 11, 15, 16, 17, 18};
 };
 
 // ------------------------------------------------------------------ layout
 // Populations live in a dense box of "columns" (y, z), col = y + ny z.  A
-// column holds its Q x-lines back to back, each padded to nxp elements:
-// g[col][i][x] (address col * sC + i * sI + x, sI = nxp, sC = Q nxp), so the
-// block that updates a column writes one contiguous Q * nxp run.  Every
-// geometry here is x-invariant: a column is entirely fluid or entirely solid
-// and its wall links are the same for every x.
+// column holds its Q x-lines back to back, each nxp elements long:
+// g[col][row(i)][x] (address col * sC + row(i) * sI + x, sI = nxp,
+// sC = Q nxp), so the block that updates a column writes one contiguous
+// Q * nxp run.  The rows are ordered by the column that pulls them: the
+// x-lines with the same (c_y, c_z) are adjacent (D3Q19: {0,1,2}, {3,7,10},
+// {4,8,9}, {5,11,14}, {6,12,13}, 15, 16, 17, 18), so one destination column
+// reads them as one contiguous run and, when x-lines are not padded to whole
+// cache lines, the lines they share are fetched once.  Every geometry here
+// is x-invariant: a column is entirely fluid or entirely solid and its wall
+// links are the same for every x.
 
 constexpr uint32_t kSolidColumn = 0x80000000u;
 // a fluid column whose pulls wrap around the periodic z boundary (slab)
@@ -89,7 +98,7 @@ struct StepArgs {
   int64_t step_off;
   uint32_t seed;
   // element offset, from the start of a column, of the x-line of g_i in the
-  // column the pull of link i reads: i sI - c_iy sC - c_iz ny sC (no wrap)
+  // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
 };
 
@@ -313,11 +322,11 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
       pv[i] = *at(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
     } else if (BOUZ && cw[2 * i] != W(0)) {
       const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
-      const LBM_GLOBAL S* line = g + (int64_t)nc * sC + L::opp[i] * sI;
+      const LBM_GLOBAL S* line = g + (int64_t)nc * sC + L::row[L::opp[i]] * sI;
       pv[i] = *at(sbase(line), L::cx[i] > 0 ? xp : (L::cx[i] < 0 ? xm : ux));
     }
     if ((mask & (1u << L::opp[i])) || (BOUZ && wall && cw[2 * i + 1] != W(0)))
-      ow[i] = *at(sbase(gown + i * sI), ux);
+      ow[i] = *at(sbase(gown + L::row[i] * sI), ux);
   }
   if ((mask & kLinkBits) == 0u) {  // a wrapping column without wall links
 #pragma unroll
@@ -432,6 +441,7 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
   {
     const uint32_t w0 = Store<S, M>::kRandom ? rb.next() : 0u;
     const M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
+    static_assert(L::row[0] == 0, "the rest population is the column's first row");
     *at(sbase(out_col), x) = Store<S, M>::enc(v, w0 & 0xffffu);
   }
 #pragma unroll
@@ -447,8 +457,8 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
     const M vi = (keep * df[i] + E) + O;
     const M vo = (keep * df[o] + E) - O;
     const uint32_t word = Store<S, M>::kRandom ? rb.next() : 0u;
-    *at(sbase(out_col + i * a.sI), x) = Store<S, M>::enc(vi, word & 0xffffu);
-    *at(sbase(out_col + o * a.sI), x) = Store<S, M>::enc(vo, word >> 16);
+    *at(sbase(out_col + L::row[i] * a.sI), x) = Store<S, M>::enc(vi, word & 0xffffu);
+    *at(sbase(out_col + L::row[o] * a.sI), x) = Store<S, M>::enc(vo, word >> 16);
   }
 }
 
