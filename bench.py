@@ -282,7 +282,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
+        print("bench.py runs on one GPU: the library has no multi-GPU path "
               "(the per-GPU kernel is measured at N = 1)", file=sys.stderr)
         sys.exit(2)
 

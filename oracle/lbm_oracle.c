@@ -35,8 +35,8 @@
  *  - Friction quadrature: a (q, omega) midpoint sum of the imaginary parts of
  *    a Drude solid response and a Lorentzian liquid response with a thermal
  *    factor; the paper states only that the Keldysh analysis yields linear
- *    friction coefficients (appendix, Eq. 26), the integrand is this build's
- *    synthetic stand-in.
+ *    friction coefficients (appendix, Eq. 26), so the integrand here is a
+ *    synthetic stand-in of that form.
  *
  * Step n -> n+1, for every fluid cell x (no blocking, no fusion):
  *   1. pull:   df_i = g_i(x - c_i), periodic in x (and z for the slab);

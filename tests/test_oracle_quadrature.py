@@ -1,6 +1,6 @@
 """Pins of the oracle's friction quadrature (no GPU).
 
-The integrand is this build's synthetic stand-in for the friction coefficients
+The integrand is a synthetic stand-in for the friction coefficients
 the paper's Keldysh analysis produces (appendix, Eq. 26): a q^3 e^{-2qd}
 weighted wavevector sum times a frequency sum of Im g_s Im g_l / sinh^2(w/2T).
 The pins reach it by other routes: complex response functions and the Bose
