@@ -199,7 +199,8 @@ lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
  * work list of 64-lane items laid out in whole workgroups that never share a
  * column (wall columns first); runs of 64 steps are replayed from captured
  * hipGraphs.  Members are cut, in order, into groups whose state fits the
- * last-level cache (128 MiB by default, see lbm_batch_set_group_bytes); a
+ * last-level cache (128 MiB by default, 96 MiB for F16S storage, see
+ * lbm_batch_set_group_bytes); a
  * call to lbm_batch_step runs each group 64 steps at a time, so a group's
  * populations stay cached between its steps.  Groups are dealt round-robin
  * to two streams by default (see lbm_batch_set_streams): the batch stream

@@ -96,8 +96,12 @@ struct Lists {
 };
 
 // Default group size: with two groups in flight at a time their state (both
-// buffers of every member) fills the 256 MB last-level cache.
-constexpr size_t kDefaultGroupBytes = (size_t)128 << 20;
+// buffers of every member) fills most of the 256 MB last-level cache.  Half
+// storage does best with somewhat smaller groups (measured on 256 uneven
+// ducts: 96 MiB 681 us/step against 719 with 128 MiB).
+size_t default_group_bytes(int precision) {
+  return precision == LBM_F16S ? (size_t)96 << 20 : (size_t)128 << 20;
+}
 
 // The work list, in units of one workgroup (wpb items, one per wave; a
 // workgroup never shares a column with another, so the partly covered cache
@@ -516,7 +520,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   b->prec = ctxs[0]->p.precision;
   b->bouz = ctxs[0]->p.geometry == LBM_TUBE;
   Lists L;
-  b->group_bytes = kDefaultGroupBytes;
+  b->group_bytes = default_group_bytes(b->prec);
   make_lists(ctxs, n, b->group_bytes, b->wpb, &L);
   b->nitems = (int64_t)L.items.size();
   b->groups = L.groups;
