@@ -260,6 +260,24 @@ def test_batch_full_size_sampled(lbm):
         ch.close()
 
 
+def test_batch_rejects_bad_settings(lbm):
+    chans = make_ducts(lbm, SPECS[:2], "f32")
+    b = lbm.Batch(chans)
+    for bad in (0, 3, 16):
+        with pytest.raises(lbm.LBMError):
+            b.set_shape(bad)
+    for bad in (0, 5):
+        with pytest.raises(lbm.LBMError):
+            b.set_streams(bad)
+    with pytest.raises(lbm.LBMError):
+        b.step(-1)
+    b.set_shape(8)
+    b.set_streams(4)
+    b.step(3)  # still usable
+    assert all(c.step_count == 3 for c in chans)
+    b.close()
+
+
 def test_batch_rejects_mixed_members(lbm):
     a = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f32")
     c = lbm.Channel(19, lbm.DUCT, 16, 6, 6, tau=0.7, precision="f64")
