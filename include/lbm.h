@@ -4,7 +4,7 @@
  * arXiv 2403.15768: water in a nanochannel (Sec. 2) as one lattice-Boltzmann
  * population set (Sec. 4), driven by a bulk pressure-gradient force (Eq. 2),
  * closed at the liquid/solid interface by a friction wall whose per-node
- * coefficient is the linear drag of Eq. 5 / Eq. 26, with periodic inlet and
+ * coefficient is the linear drag of Eq. 5 / Eq. 27, with periodic inlet and
  * outlet (Sec. 4.2).
  *
  * Conventions shared by every call:
@@ -20,7 +20,7 @@
  *    asynchronous; device errors are latched and returned by the next
  *    synchronising call (lbm_sync, lbm_invariants, lbm_flux, lbm_mass,
  *    lbm_get_*, lbm_run_to_steady).
- *  - Population order: D2Q9 uses the paper's numbering beside Eqs. 18-20
+ *  - Population order: D2Q9 uses the paper's numbering beside Eqs. 19-21
  *    (0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-));
  *    D3Q19: 0 rest, 1..6 = +x,-x,+y,-y,+z,-z, 7..18 = (+,+,0), (-,-,0),
  *    (+,-,0), (-,+,0), (+,0,+), (-,0,-), (+,0,-), (-,0,+), (0,+,+), (0,-,-),
@@ -100,7 +100,7 @@ typedef struct {
  *   P = Omega^2 q d (dispersion = 1) or Omega^2 (dispersion = 0).
  * Lattice friction of node k: lambda_k = lambda_target raw(Omega_k)/raw(omega0).
  * Stand-in for the friction coefficients of the Keldysh analysis (appendix,
- * Eq. 26), which the paper does not give in closed form. */
+ * Eq. 27), which the paper does not give in closed form. */
 typedef struct {
   double T, omega0, gamma_s, omega_l, gamma_l, a_l, d;
   int nq, nw;

@@ -13,7 +13,7 @@
  *  - Water as one lattice-Boltzmann population set (Sec. 4, "one set of
  *    discrete distributions per species"; Eqs. 1-2 are the continuity and
  *    momentum equations it reproduces, inertia kept).  Lattices: D2Q9 with the
- *    velocity numbering the paper gives beside Eqs. 18-20 (0 = rest, 1 = +x,
+ *    velocity numbering the paper gives beside Eqs. 19-21 (0 = rest, 1 = +x,
  *    2 = +y, 3 = -x, 4 = -y, 5 = (+,+), 6 = (-,+), 7 = (-,-), 8 = (+,-)), and
  *    D3Q19 (0 rest; 1..6 = +x,-x,+y,-y,+z,-z; then (+,+,0),(-,-,0),(+,-,0),
  *    (-,+,0),(+,0,+),(-,0,-),(+,0,-),(-,0,+),(0,+,+),(0,-,-),(0,+,-),(0,-,+)).
@@ -27,7 +27,7 @@
  *    its free-slip rule at the liquid/solid interface are mixed per wall node
  *    with weight r = 3 lambda / (1 + 3 lambda), lambda being the interfacial
  *    friction coefficient of the linear drag law (Eq. 5 and the appendix
- *    result F_kl = gamma_kl (u_k - u_l), Eq. 26) in lattice units.  The slip
+ *    result F_kl = gamma_kl (u_k - u_l), Eq. 27) in lattice units.  The slip
  *    half is the same-node transverse reversal (c_x, -c_y, -c_z).  Bounce-back
  *    is half-way on planar walls and Bouzidi-Firdaouss-Lallemand linear
  *    interpolation on the circular tube.  Inlet/outlet are periodic in x (the
@@ -35,7 +35,7 @@
  *  - Friction quadrature: a (q, omega) midpoint sum of the imaginary parts of
  *    a Drude solid response and a Lorentzian liquid response with a thermal
  *    factor; the paper states only that the Keldysh analysis yields linear
- *    friction coefficients (appendix, Eq. 26), so the integrand here is a
+ *    friction coefficients (appendix, Eq. 27), so the integrand here is a
  *    synthetic stand-in of that form.
  *
  * Step n -> n+1, for every fluid cell x (no blocking, no fusion):

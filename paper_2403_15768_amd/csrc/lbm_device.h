@@ -13,7 +13,7 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ lattices
-// D2Q9 in the paper's numbering (Sec. 4.2, beside Eqs. 18-20).
+// D2Q9 in the paper's numbering (Sec. 4.2, beside Eqs. 19-21).
 struct D2Q9 {
   static constexpr int Q = 9;
   static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};

@@ -1,7 +1,7 @@
 """Pins of the oracle's friction quadrature (no GPU).
 
 The integrand is a synthetic stand-in for the friction coefficients
-the paper's Keldysh analysis produces (appendix, Eq. 26): a q^3 e^{-2qd}
+the paper's Keldysh analysis produces (appendix, Eq. 27): a q^3 e^{-2qd}
 weighted wavevector sum times a frequency sum of Im g_s Im g_l / sinh^2(w/2T).
 The pins reach it by other routes: complex response functions and the Bose
 occupation identity 1/sinh^2(x/2) = 4 n (n + 1) (brute force on tiny grids),
