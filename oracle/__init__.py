@@ -100,6 +100,11 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_friction_raw.restype = C.c_double
     lib.ora_friction.argtypes = [sp, dp, lp, dp, dp]
     lib.ora_sizeof_real.restype = C.c_int
+    u64p = C.POINTER(C.c_uint64)
+    lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
+    lib.ora_set_thermal.restype = C.c_int
+    lib.ora_philox4x64.argtypes = [u64p, u64p, u64p]
+    lib.ora_thermal_normals.argtypes = [C.c_uint64, lp, lp, C.c_int, dp]
     _loaded[kind] = lib
     return lib
 
@@ -176,6 +181,12 @@ class Lattice:
                                                    (self.wall_count,)))
         if self._lib.ora_set_friction(self._h, _dptr(lam)) != 0:
             raise OracleError("friction must be >= 0 (inf allowed)")
+
+    def set_thermal(self, kT: float, mode: int = 2, seed: int = 0) -> None:
+        """Thermal fluctuations at lattice temperature kT (0 = off); mode 1 =
+        the stress source alone, 2 = every non-conserved direction."""
+        if self._lib.ora_set_thermal(self._h, float(kT), int(mode), int(seed)) != 0:
+            raise OracleError("kT must be finite and >= 0, mode 1 or 2")
 
     def step(self, n: int) -> None:
         self._lib.ora_step(self._h, int(n))
@@ -254,6 +265,25 @@ def friction(sp: Spectral, Omega, kind: str = "f64"):
     s = sp._c()
     _lib(kind).ora_friction(C.byref(s), _dptr(Om), len(Om), _dptr(raw), _dptr(lat))
     return raw, lat
+
+
+def philox4x64(ctr, key, kind: str = "f64") -> np.ndarray:
+    """Philox4x64-10 of one 256-bit counter under one 128-bit key."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint64))
+    assert c.shape == (4,) and k.shape == (2,)
+    out = np.zeros(4, dtype=np.uint64)
+    u64p = C.POINTER(C.c_uint64)
+    _lib(kind).ora_philox4x64(c.ctypes.data_as(u64p), k.ctypes.data_as(u64p),
+                              out.ctypes.data_as(u64p))
+    return out
+
+
+def thermal_normals(seed: int, cell: int, step: int, count: int, kind: str = "f64") -> np.ndarray:
+    """The first ``count`` standard normals the thermal noise of ``cell`` draws at ``step``."""
+    out = np.zeros(count)
+    _lib(kind).ora_thermal_normals(int(seed), int(cell), int(step), int(count), _dptr(out))
+    return out
 
 
 def sizeof_real(kind: str = "f64") -> int:

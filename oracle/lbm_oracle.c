@@ -48,11 +48,25 @@
  *                    + (1 - 1/(2 tau)) w_i [ 3 (c_i - u) + 9 (c_i.u) c_i ].F
  *   Reported rho, u "after n steps" are the moments of step 2 built from g(n).
  *
+ * Thermal fluctuations (optional, Sec. 3.2 Eq. 6 and Sec. 4 Eq. 17): the
+ * classical fluctuation-dissipation theorem fixes the random momentum flux,
+ * and the fluctuating LB equation adds it as a local source in the stress
+ * directions w_i (c_ia c_ib - c_s^2 delta_ab).  With a lattice temperature kT
+ * (lattice units, equipartition reads <rho u_a^2> = kT per site), step 4
+ * gains a zero-mean Gaussian term xi_i; see thermal_noise() below for the two
+ * forms (the paper's stress source alone, or every non-conserved direction).
+ * Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), a
+ * counter-based generator, keyed by the seed and counted by (cell, step,
+ * block), with Box-Muller (1958) normals.
+ *
  * Parity pins: exact discrete slip-Poiseuille and Couette profiles, exact
  * mass conservation, free-slip plug acceleration, Hagen-Poiseuille
  * convergence in the tube, long-double self-floor; quadrature pinned by
  * complex-arithmetic brute force on tiny grids, the f-sum rule, the closed
- * form of the q integral and an adaptive integrator (see tests/).
+ * form of the q integral and an adaptive integrator; thermal noise pinned by
+ * numpy's Philox4x64-10, the normal distribution, exact conservation, the
+ * paper's stress form and the stationarity of the equilibrium Gaussian
+ * measure (see tests/).
  */
 #include <math.h>
 #include <stdint.h>
@@ -108,6 +122,9 @@ typedef struct {
   real *qlink; /* per cell * 19: Bouzidi fraction of wall links (0 if none) */
   real *g, *gn;
   long step;
+  double kT;     /* lattice temperature; 0 = no fluctuations */
+  int noise;     /* 1 = stress directions only, 2 = all non-conserved */
+  uint64_t seed; /* key of the thermal random numbers */
 } ora_ctx;
 
 /* ---------------------------------------------------------------- lattice */
@@ -385,6 +402,140 @@ static void moments(const ora_ctx *o, const real *df, real *drho, real *rho,
   for (a = 0; a < 3; a++) u[a] = j[a] / *rho;
 }
 
+/* ------------------------------------------------ thermal fluctuations */
+
+/* kT >= 0 (0 switches the noise off); mode 1 or 2 when kT > 0. */
+int ora_set_thermal(ora_ctx *o, double kT, int mode, uint64_t seed) {
+  if (!(kT >= 0) || isinf(kT)) return ORA_EINVAL;
+  if (kT > 0 && mode != 1 && mode != 2) return ORA_EINVAL;
+  o->kT = kT;
+  o->noise = kT > 0 ? mode : 0;
+  o->seed = seed;
+  return ORA_OK;
+}
+
+/* Philox4x64 with 10 rounds: each round multiplies words 0 and 2 by two
+ * fixed odd constants, forms the new words from the high halves xor the
+ * other words xor the round key and from the low halves, and the key grows by
+ * two Weyl constants (golden ratio and sqrt(3) - 1, scaled to 64 bits)
+ * between rounds. */
+void ora_philox4x64(const uint64_t ctr[4], const uint64_t key[2],
+                    uint64_t out[4]) {
+  const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+  const uint64_t w0 = 0x9E3779B97F4A7C15ULL, w1 = 0xBB67AE8584CAA73BULL;
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  int r;
+  for (r = 0; r < 10; r++) {
+    unsigned __int128 p0 = (unsigned __int128)m0 * x0;
+    unsigned __int128 p1 = (unsigned __int128)m1 * x2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += w0;
+    k1 += w1;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* The first `count` standard normals of cell `cell` at step `step`.
+ * Block b of the counter (cell, step, b, 0) gives four 64-bit words; word w
+ * gives normals 8b + 2w and 8b + 2w + 1.  From the word's low and high 32-bit
+ * halves take the top 23 bits each, u = (k + 1/2) / 2^23 (exact in binary32
+ * as well, and never 0 or 1), and apply Box-Muller:
+ *   z = sqrt(-2 ln u_low) cos(2 pi u_high),  z' = sqrt(-2 ln u_low) sin(2 pi u_high).
+ * The largest |z| is sqrt(48 ln 2) = 5.77. */
+void ora_thermal_normals(uint64_t seed, long cell, long step, int count,
+                         double *z) {
+  int k;
+  uint64_t word[4] = {0, 0, 0, 0};
+  for (k = 0; k < count; k++) {
+    int b = k / 8, w = (k % 8) / 2;
+    double ul, uh, rad, ang;
+    if (k % 8 == 0) {
+      uint64_t ctr[4], key[2];
+      ctr[0] = (uint64_t)cell;
+      ctr[1] = (uint64_t)step;
+      ctr[2] = (uint64_t)b;
+      ctr[3] = 0;
+      key[0] = seed;
+      key[1] = 0;
+      ora_philox4x64(ctr, key, word);
+    }
+    ul = ((double)((uint32_t)word[w] >> 9) + 0.5) / 8388608.0;
+    uh = ((double)((uint32_t)(word[w] >> 32) >> 9) + 0.5) / 8388608.0;
+    rad = sqrt(-2.0 * log(ul));
+    ang = 2.0 * 3.14159265358979323846 * uh;
+    z[k] = k % 2 == 0 ? rad * cos(ang) : rad * sin(ang);
+  }
+}
+
+/* Thermal term xi_i added to the post-collision population of cell n.
+ *
+ * Every non-conserved direction relaxes by the factor gamma = 1 - 1/tau per
+ * step; a direction kept at variance mu (in the coordinates where the
+ * equilibrium covariance is mu w_i delta_ij) needs added noise of variance
+ * mu (1 - gamma^2): the fluctuation-dissipation balance of one linear
+ * relaxation step.  mu = rho0 kT / c_s^2 gives <j_a^2> = rho0 kT, i.e.
+ * equipartition.  A = sqrt(mu (1 - gamma^2)).
+ *
+ *  mode 1 (the paper's source, Eq. 17): xi_i = w_i / (2 c_s^4) P_ab
+ *    (c_ia c_ib - c_s^2 delta_ab), P symmetric Gaussian with
+ *    <P_ab P_cd> = A^2 c_s^4 (delta_ac delta_bd + delta_ad delta_bc):
+ *    P_aa = sqrt(2) c_s^2 A z, P_ab = c_s^2 A z (a < b), one normal each in
+ *    the order xx, yy, (zz,) xy, (xz, yz).
+ *  mode 2 (stress and kinetic directions): v_i = sqrt(w_i) z_i for every i,
+ *    then the mass and momentum parts are removed,
+ *    xi_i = A (v_i - w_i sum_k v_k - 3 w_i c_i . sum_k v_k c_k). */
+static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
+  const real cs2 = (real)1 / 3;
+  real gam = 1 - 1 / (real)o->p.tau;
+  real mu = (real)o->p.rho0 * (real)o->kT / cs2;
+  real A = sqrt((double)(mu * (1 - gam * gam)));
+  int d = o->q == 9 ? 2 : 3;
+  int i, a, b;
+  double z[19];
+  if (o->noise == 1) {
+    real P[3][3];
+    int k = 0;
+    ora_thermal_normals(o->seed, n, step, d * (d + 1) / 2, z);
+    for (a = 0; a < 3; a++)
+      for (b = 0; b < 3; b++) P[a][b] = 0;
+    for (a = 0; a < d; a++) P[a][a] = sqrt(2.0) * cs2 * A * (real)z[k++];
+    for (a = 0; a < d; a++)
+      for (b = a + 1; b < d; b++) {
+        P[a][b] = cs2 * A * (real)z[k++];
+        P[b][a] = P[a][b];
+      }
+    for (i = 0; i < o->q; i++) {
+      real s = 0;
+      for (a = 0; a < 3; a++)
+        for (b = 0; b < 3; b++)
+          s += P[a][b] * ((real)(o->c[i][a] * o->c[i][b]) - (a == b ? cs2 : 0));
+      xi[i] = o->w[i] / (2 * cs2 * cs2) * s;
+    }
+  } else {
+    real v[19], sv = 0, sc[3] = {0, 0, 0};
+    ora_thermal_normals(o->seed, n, step, o->q, z);
+    for (i = 0; i < o->q; i++) {
+      v[i] = sqrt((double)o->w[i]) * (real)z[i];
+      sv += v[i];
+      for (a = 0; a < 3; a++) sc[a] += v[i] * (real)o->c[i][a];
+    }
+    for (i = 0; i < o->q; i++) {
+      real cdot = 0;
+      for (a = 0; a < 3; a++) cdot += (real)o->c[i][a] * sc[a];
+      xi[i] = A * (v[i] - o->w[i] * sv - 3 * o->w[i] * cdot);
+    }
+  }
+}
+
 void ora_step(ora_ctx *o, long nsteps) {
   long s;
   int x, y, z, i, a;
@@ -396,8 +547,10 @@ void ora_step(ora_ctx *o, long nsteps) {
       for (y = 0; y < o->p.ny; y++)
         for (x = 0; x < o->p.nx; x++) {
           long n = cell(o, x, y, z);
-          real df[19], drho, rho, u[3], j[3], usq, uF;
+          real df[19], drho, rho, u[3], j[3], usq, uF, xi[19];
           if (!o->fluid[n]) continue;
+          for (i = 0; i < o->q; i++) xi[i] = 0;
+          if (o->noise) thermal_noise(o, n, o->step, xi);
           gather(o, o->g, x, y, z, df);
           moments(o, df, &drho, &rho, u, j);
           usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -412,7 +565,8 @@ void ora_step(ora_ctx *o, long nsteps) {
                   (drho + rho * (3 * cu + (real)4.5 * cu * cu -
                                          (real)1.5 * usq));
             src = (1 - 1 / (2 * tau)) * o->w[i] * (3 * (cF - uF) + 9 * cu * cF);
-            o->gn[(long)i * o->ncell + n] = df[i] - (df[i] - feq) / tau + src;
+            o->gn[(long)i * o->ncell + n] =
+                df[i] - (df[i] - feq) / tau + src + xi[i];
           }
         }
     {
