@@ -157,6 +157,19 @@ def extras(torch, lbm, inputs, args):
                            "hbm_frac_fluid_bytes": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
                                                          / HBM_PEAK_GBS, 4)}
     tb.close()
+    # the fluctuating update (thermal noise, kT = 1e-6) on the FP32 duct,
+    # both noise forms
+    for mode, name in ((1, "stress"), (2, "all")):
+        ch = make_duct(lbm, inputs, "f32")
+        ch.set_thermal(1e-6, mode, 1)
+        ch.step(200)
+        wall, kms = timed_run(torch, ch, 2000, 1000)
+        cells = ch.fluid_count
+        out[f"duct_f32_thermal_{name}"] = {
+            "mlups": round(cells * 2000 / wall / 1e6, 1),
+            "kernel_us": round(kms * 1e3 / 2000, 2),
+            "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
+        ch.close()
     return out
 
 
@@ -268,6 +281,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--thermal", type=int, default=0, choices=[0, 1, 2],
+                    help="duct with thermal noise (kT = 1e-6): 1 stress source, 2 every "
+                         "non-conserved direction")
     ap.add_argument("--workload", default="duct", choices=["duct", "batch", "serving"],
                     help="duct: the headline line; batch / serving: their own JSON line")
     ap.add_argument("--batch-steps", type=int, default=1000)
@@ -298,6 +314,8 @@ def main():
         return serving_workload(args)
     log("bench: duct 256x128x64", args.precision, "steps", args.steps)
     ch = make_duct(lbm, inputs, args.precision)
+    if args.thermal:
+        ch.set_thermal(1e-6, args.thermal, 1)
     cells = ch.fluid_count
     ch.step(args.warmup)
     ch.invariants()
@@ -313,7 +331,7 @@ def main():
     log(f"bench: {mlups:.1f} MLUPS, step kernel {kern_s * 1e6:.2f} us, {achieved:.0f} GB/s")
 
     traffic = None
-    if os.path.exists(COUNTERS) and args.precision == "f32":
+    if os.path.exists(COUNTERS) and args.precision == "f32" and not args.thermal:
         c = json.load(open(COUNTERS))
         if c.get("kernel_hash") == kernel_hash():
             traffic = c.get("bytes_per_launch")
@@ -349,16 +367,18 @@ def main():
         "vs_baseline": None,
         "dtype": arith,
         "data": "synthetic",
-        "config": {"workload": f"duct_256x128x64_d3q19_{args.precision}storage",
+        "config": {"workload": f"duct_256x128x64_d3q19_{args.precision}storage"
+                               + ("", "_thermal_stress", "_thermal_all")[args.thermal],
                    "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
                    "g": 1e-6, "storage": args.precision, "arithmetic": arith,
                    "friction": "smooth random lambda(x,s): mean 0.05, std 0.02, corr. length 16",
-                   "check_every": args.check_every},
+                   "check_every": args.check_every,
+                   "thermal": [None, "stress source, kT 1e-6", "all directions, kT 1e-6"][args.thermal]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_GBs": None if traffic is None else round(traffic / kern_s / 1e9, 1),
-                     "kernel": "k_step<D3Q19>",
+                     "kernel": "k_step<D3Q19>" if not args.thermal else f"k_step<D3Q19, noise {args.thermal}>",
                      "kernel_us": round(kern_s * 1e6, 3), "bytes_per_update": bpu},
         "cpu_baseline": cpu,
         "extras": ext,

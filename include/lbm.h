@@ -152,6 +152,31 @@ lbm_status lbm_set_friction_spectral(lbm_ctx *ctx, const lbm_spectral *sp,
  * raw(omega0)); either pointer may be NULL.  Host arrays. */
 lbm_status lbm_get_friction(lbm_ctx *ctx, double *lambda, double *raw);
 
+/* Thermal fluctuations (fluctuating LB).  Sec. 3.2, Eq. 6: the classical
+ * fluctuation-dissipation theorem fixes the random momentum flux; Sec. 4,
+ * Eq. 17: the fluctuating LB equation adds it as a local source along
+ * w_i (c_ia c_ib - c_s^2 delta_ab).  From the next step on, every fluid cell's
+ * post-collision populations gain a zero-mean Gaussian term xi_i:
+ *   LBM_NOISE_STRESS  the paper's source: a random symmetric tensor P with
+ *       <P_ab P_cd> = A^2 c_s^4 (d_ac d_bd + d_ad d_bc), xi_i = w_i/(2 c_s^4)
+ *       P:(c_i c_i - c_s^2 I);
+ *   LBM_NOISE_ALL     every non-conserved direction: xi = A times the part of
+ *       (sqrt(w_i) z_i) orthogonal to mass and momentum, z_i iid normals;
+ * A^2 = mu (1 - (1 - 1/tau)^2), mu = 3 rho0 kT.  LBM_NOISE_ALL holds the
+ * equilibrium populations at variance mu w_i, so that <rho u_a^2> = kT and
+ * <(rho - rho0)^2> = 3 rho0 kT per site at every wavelength; the stress
+ * source alone gives that only at long wavelengths (about 0.6 kT per site at
+ * tau = 0.7).  kT is in lattice units (0 switches the noise off; the mode is
+ * then ignored).  Random numbers: Philox4x64-10 (Salmon et al., SC'11) under
+ * key (seed, 0) with counter (x + nx (y + ny z), step, block, 0), each 64-bit
+ * word giving two Box-Muller normals from 23-bit uniforms (|z| <= 5.77), so a
+ * run is reproducible bit for bit and a restart from lbm_set_state continues
+ * the same sequence.  Mass is conserved exactly; momentum too where the walls
+ * conserve it.  kT < 0, NaN, Inf or an unknown mode -> LBM_EINVAL.
+ * Synchronous (finishes queued work). */
+typedef enum { LBM_NOISE_STRESS = 1, LBM_NOISE_ALL = 2 } lbm_noise;
+lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
+
 /* Advance nsteps >= 0 time steps (asynchronous). */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 /* Step in chunks of check_every until |Q(n) - Q(n - check_every)| <
@@ -173,6 +198,10 @@ lbm_status lbm_get_field(lbm_ctx *ctx, int which, double *host_out);
 /* Shifted post-collision populations g_i = f_i - w_i rho0 as doubles,
  * host_out: Q*nz*ny*nx ([i][z][y][x]), 0 on solid cells.  Synchronous. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *host_out);
+/* The inverse: replace the state by host_in (same layout; solid cells
+ * ignored), rounded to nearest in the storage precision, and set the step
+ * counter to step >= 0.  Synchronous. */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *host_in, int64_t step);
 
 /* Checkpoint: the populations in storage precision plus the step counter.
  * lbm_state_bytes gives the size; get/set are synchronous; set restores a
@@ -219,7 +248,9 @@ typedef struct lbm_batch lbm_batch; /* opaque */
 lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
 /* arena: device, >= footprint bytes, 256-byte aligned, owned by the caller
  * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
- * lattice, precision or wall kind, or one appears twice. */
+ * lattice, precision or wall kind, one appears twice, or one has thermal
+ * noise switched on (lbm_set_thermal; lbm_batch_step refuses such a member
+ * later too). */
 lbm_status lbm_batch_create(lbm_ctx *const *ctxs, int n, void *arena, size_t arena_bytes,
                             void *hip_stream, lbm_batch **out);
 void lbm_batch_destroy(lbm_batch *b);  /* members and arena untouched */

@@ -271,6 +271,9 @@ void fill_args(lbm_ctx* c) {
   a.dstep = nullptr;
   a.step_off = 0;
   a.seed = kSeed;
+  a.th_amp = 0.0;
+  a.th_mode = 0;
+  a.th_seed = 0;
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -313,7 +316,7 @@ namespace {
 lbm_status build_graph(lbm_ctx* c, int parity) {
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
-  const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz);
+  const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode);
   hipGraphNode_t prev = nullptr;
   // kernel arguments must outlive instantiation only; keep them on the stack
   const void* srcs[2] = {c->pop[parity], c->pop[1 - parity]};
@@ -597,6 +600,30 @@ lbm_status lbm_get_friction(lbm_ctx* c, double* lambda, double* raw) {
   return sync(c);
 }
 
+lbm_status lbm_set_thermal(lbm_ctx* c, double kT, int mode, uint64_t seed) {
+  if (!c) return LBM_EINVAL;
+  if (!(kT >= 0.0) || std::isinf(kT)) return c->fail(LBM_EINVAL, "kT must be finite and >= 0");
+  if (kT > 0.0 && mode != LBM_NOISE_STRESS && mode != LBM_NOISE_ALL)
+    return c->fail(LBM_EINVAL, "noise form must be LBM_NOISE_STRESS or LBM_NOISE_ALL");
+  // the step graphs hold the step arguments: finish queued work, rebuild later
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 2; k++) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+  // every non-conserved direction relaxes by gamma = 1 - 1/tau per step; the
+  // added variance mu (1 - gamma^2), mu = rho0 kT / c_s^2, holds it at mu w_i
+  const double gam = 1.0 - 1.0 / c->p.tau;
+  c->args.th_amp = kT > 0.0 ? std::sqrt(3.0 * c->p.rho0 * kT * (1.0 - gam * gam)) : 0.0;
+  c->args.th_mode = kT > 0.0 ? mode : 0;
+  c->args.th_seed = seed;
+  c->kT = kT;
+  return LBM_OK;
+}
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   return do_steps(c, nsteps);
@@ -678,6 +705,29 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
       }
     }
   return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) {
+  if (!c || !host_in || step < 0) return LBM_EINVAL;
+  const Plan& pl = c->pl;
+  std::vector<unsigned char> raw(pl.pop_bytes, 0);
+  for (int i = 0; i < pl.Q; i++)
+    for (int64_t col = 0; col < pl.ncolbox; col++) {
+      if (pl.colinfo[col].mask & lbm::kSolidColumn) continue;
+      for (int x = 0; x < pl.nxp; x++) {
+        // padding lanes take the value of cell nx - 1, as the step writes them
+        const int xs = x < pl.nx ? x : pl.nx - 1;
+        const double v = host_in[((int64_t)i * pl.ncolbox + col) * pl.nx + xs];
+        const int64_t dst = col * pl.sC + lat_row(pl.Q, i) * pl.sI + x;
+        if (pl.prec == LBM_F64) reinterpret_cast<double*>(raw.data())[dst] = v;
+        else if (pl.prec == LBM_F32) reinterpret_cast<float*>(raw.data())[dst] = (float)v;
+        else reinterpret_cast<_Float16*>(raw.data())[dst] = (_Float16)(float)(v * 4096.0);
+      }
+    }
+  HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], raw.data(), pl.pop_bytes, hipMemcpyHostToDevice, c->stream));
+  lbm_status s = sync(c);
+  if (s == LBM_OK) c->step = step;
+  return s;
 }
 
 lbm_status lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {

@@ -233,6 +233,7 @@ lbm_status check_members(lbm_ctx* const* ctxs, int n) {
     if (a.lattice != b.lattice || a.precision != b.precision ||
         (a.geometry == LBM_TUBE) != (b.geometry == LBM_TUBE))
       return LBM_EINVAL;
+    if (ctxs[m]->args.th_mode != 0) return LBM_EINVAL;  // the batch kernel has no noise
   }
   return LBM_OK;
 }
@@ -605,6 +606,11 @@ lbm_status lbm_batch_items(const lbm_batch* b, int64_t* nitems) {
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
+  for (lbm_ctx* c : b->m)
+    if (c->args.th_mode != 0) {
+      b->err = "a member has thermal noise switched on; batches step without it";
+      return LBM_EINVAL;
+    }
   lbm_status rs = resync(b);
   if (rs != LBM_OK) return rs;
   // each group runs its kGraphSteps steps before the next group starts; the

@@ -97,6 +97,11 @@ struct StepArgs {
   const int64_t* dstep;
   int64_t step_off;
   uint32_t seed;
+  // thermal fluctuations (see thermal_noise): amplitude A (0: none), form
+  // (1: stress source, 2: every non-conserved direction), random-number key
+  double th_amp;
+  int th_mode;
+  uint64_t th_seed;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
@@ -395,6 +400,130 @@ __device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
   return r;
 }
 
+// ------------------------------------------------------------------ thermal noise
+// Fluctuating LB (Sec. 3.2, Eq. 6: the classical fluctuation-dissipation
+// theorem for the random momentum flux; Sec. 4, Eq. 17: the fluctuating LB
+// equation adds it as a local source along w_i (c_ia c_ib - c_s^2 delta_ab)).
+//
+// Random numbers: Philox4x64 with ten rounds (Salmon, Moraes, Dror & Shaw,
+// SC'11), counter (cell, step, block, 0), key (seed, 0).  A round multiplies
+// words 0 and 2 by two odd 64-bit constants; the next words are the high
+// product halves xored with words 1 and 3 and the round key, and the low
+// halves; the key advances by two 64-bit Weyl increments.
+struct Philox4 {
+  uint64_t w[4];
+};
+__device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                 uint64_t k0, uint64_t k1) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    const uint64_t h0 = __umul64hi(kM0, x0), l0 = kM0 * x0;
+    const uint64_t h1 = __umul64hi(kM1, x2), l1 = kM1 * x2;
+    x0 = h1 ^ x1 ^ k0;
+    x1 = l1;
+    x2 = h0 ^ x3 ^ k1;
+    x3 = l0;
+    k0 += kW0;
+    k1 += kW1;
+  }
+  return Philox4{{x0, x1, x2, x3}};
+}
+
+// Two standard normals from one 64-bit word (Box-Muller): the top 23 bits of
+// each 32-bit half give u = (k + 1/2) 2^-23, exact in binary32 and never 0
+// or 1; z = sqrt(-2 ln u_lo) (cos, sin)(2 pi u_hi).  |z| <= sqrt(48 ln 2).
+__device__ __forceinline__ void normal_pair(uint64_t word, float* z0, float* z1) {
+  const float ul = (static_cast<float>(static_cast<uint32_t>(word) >> 9) + 0.5f) * 0x1p-23f;
+  const float uh = (static_cast<float>(static_cast<uint32_t>(word >> 32) >> 9) + 0.5f) * 0x1p-23f;
+  const float rad = sqrtf(-2.0f * logf(ul));
+  float sn, cs;
+  sincospif(2.0f * uh, &sn, &cs);
+  *z0 = rad * cs;
+  *z1 = rad * sn;
+}
+
+// sqrt(w_i) from the weight class (|c|^2 and the lattice)
+template <class L, typename M>
+__device__ __forceinline__ constexpr M sqrt_w(int i) {
+  return L::Q == 9 ? (i == 0 ? M(2.0 / 3) : (i < 5 ? M(1.0 / 3) : M(1.0 / 6)))
+                   : (i == 0 ? M(0.57735026918962576451) : (i < 7 ? M(0.23570226039551584147) : M(1.0 / 6)));
+}
+
+// Thermal term xi_i added to the post-collision population of a cell.  Each
+// non-conserved direction relaxes by gamma = 1 - omega per step; holding it at
+// the equilibrium variance mu w_i (mu = rho0 kT / c_s^2, which gives
+// <j_a^2> = rho0 kT) takes added variance mu (1 - gamma^2): A^2 (host side).
+// The normals z_k come in the order block k/8, word (k mod 8)/2, cos then sin.
+//  th_mode 1 (the stress source): P_aa = sqrt(2) c_s^2 A z, P_ab = c_s^2 A z
+//    (order xx, yy, [zz,] xy, [xz, yz]), xi_i = w_i/(2 c_s^4) P:(c_i c_i - c_s^2 I),
+//    i.e. xi_i = w_i [1.5 sqrt(2) A sum_a z_aa (c_ia^2 - 1/3) + 3 A sum_a<b z_ab c_ia c_ib];
+//  th_mode 2: v_i = sqrt(w_i) z_i for every i, mass and momentum removed:
+//    xi_i = A (v_i - w_i sum v - 3 w_i c_i . sum v c).
+template <class L, typename M, int MODE>
+__device__ __forceinline__ void thermal_noise(const StepArgs& a, uint32_t cell, int64_t step,
+                                              M* xi) {
+  static_assert(MODE == 1 || MODE == 2, "noise form");
+  const M A = static_cast<M>(a.th_amp);
+  const uint64_t key = a.th_seed;
+  if constexpr (MODE == 1) {
+    float z[6] = {0, 0, 0, 0, 0, 0};
+    const Philox4 r = philox4x64_10(cell, (uint64_t)step, 0, key, 0);
+    normal_pair(r.w[0], &z[0], &z[1]);
+    normal_pair(r.w[1], &z[2], &z[3]);
+    if (L::Q == 19) normal_pair(r.w[2], &z[4], &z[5]);
+    const M sd = M(2.12132034355964257320) * A, so = M(3) * A;
+    // 2-D: xx, yy, xy; 3-D: xx, yy, zz, xy, xz, yz
+    const M pxx = sd * z[0], pyy = sd * z[1];
+    const M pzz = L::Q == 19 ? sd * z[2] : M(0);
+    const M pxy = so * (L::Q == 19 ? z[3] : z[2]);
+    const M pxz = L::Q == 19 ? so * z[4] : M(0), pyz = L::Q == 19 ? so * z[5] : M(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      const M t = M(1) / M(3);
+      const M s = pxx * (M(L::cx[i] * L::cx[i]) - t) + pyy * (M(L::cy[i] * L::cy[i]) - t) +
+                  (L::Q == 19 ? pzz * (M(L::cz[i] * L::cz[i]) - t) : M(0)) +
+                  pxy * M(L::cx[i] * L::cy[i]) + pxz * M(L::cx[i] * L::cz[i]) +
+                  pyz * M(L::cy[i] * L::cz[i]);
+      xi[i] = static_cast<M>(L::w[i]) * s;
+    }
+    return;
+  } else {
+    float z[L::Q];
+    constexpr int kBlocks = (L::Q + 7) / 8;
+#pragma unroll
+    for (int b = 0; b < kBlocks; b++) {
+      const Philox4 r = philox4x64_10(cell, (uint64_t)step, (uint64_t)b, key, 0);
+#pragma unroll
+      for (int w = 0; w < 4; w++) {
+        const int k = 8 * b + 2 * w;
+        if (k >= L::Q) break;
+        float z0, z1;
+        normal_pair(r.w[w], &z0, &z1);
+        z[k] = z0;
+        if (k + 1 < L::Q) z[k + 1] = z1;
+      }
+    }
+    M v[L::Q], sv = 0, sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      v[i] = sqrt_w<L, M>(i) * static_cast<M>(z[i]);
+      sv += v[i];
+      if (L::cx[i]) sx += L::cx[i] > 0 ? v[i] : -v[i];
+      if (L::cy[i]) sy += L::cy[i] > 0 ? v[i] : -v[i];
+      if (L::cz[i]) sz += L::cz[i] > 0 ? v[i] : -v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      const M wi = static_cast<M>(L::w[i]);
+      const M cs = M(L::cx[i]) * sx + M(L::cy[i]) * sy + M(L::cz[i]) * sz;
+      xi[i] = A * (v[i] - wi * sv - M(3) * wi * cs);
+    }
+  }
+}
+
 // BGK relaxation with Guo forcing on shifted populations; each result is
 // stored as soon as it is computed (out_col: the column's base, uniform):
 //   rho = rho0 + sum df, j = rho u = sum df c + F/2,
@@ -408,9 +537,13 @@ __device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
 // E_i = w_i (C0 + (c.u)(c.U)) and the odd part O_i = t_i (c.J).  Opposite
 // directions share E and take O with its sign flipped, so each pair is
 // computed once and the odd parts cancel exactly in the next moments.
-template <class L, typename M, typename S>
+// With TH = 1 or 2, xi holds the cell's thermal term of that form
+// (thermal_noise), added to every result.
+template <class L, typename M, typename S, int TH = 0>
 __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LBM_GLOBAL S* out_col,
-                                              unsigned x, uint32_t cell, int64_t step) {
+                                              unsigned x, uint32_t cell, int64_t step,
+                                              const M* xi = nullptr) {
+  constexpr bool THERM = TH != 0;
   M drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
@@ -440,7 +573,8 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
   RoundBits rb(a.seed, step, Store<S, M>::kRandom ? cell : 0u);
   {
     const uint32_t w0 = Store<S, M>::kRandom ? rb.next() : 0u;
-    const M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
+    M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
+    if constexpr (THERM) v += xi[0];
     static_assert(L::row[0] == 0, "the rest population is the column's first row");
     *at(sbase(out_col), x) = Store<S, M>::enc(v, w0 & 0xffffu);
   }
@@ -454,8 +588,12 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
     const M cJ = cdot<L, M>(i, Jx, Jy, Jz);
     const M E = (wi * cu) * cU + wi * C0;
     const M O = lin_weight<L, M>(i) * cJ;
-    const M vi = (keep * df[i] + E) + O;
-    const M vo = (keep * df[o] + E) - O;
+    M vi = (keep * df[i] + E) + O;
+    M vo = (keep * df[o] + E) - O;
+    if constexpr (THERM) {
+      vi += xi[i];
+      vo += xi[o];
+    }
     const uint32_t word = Store<S, M>::kRandom ? rb.next() : 0u;
     *at(sbase(out_col + L::row[i] * a.sI), x) = Store<S, M>::enc(vi, word & 0xffffu);
     *at(sbase(out_col + L::row[o] * a.sI), x) = Store<S, M>::enc(vo, word >> 16);

@@ -59,6 +59,7 @@ struct lbm_ctx {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool graphs_ok = true;
   int64_t dstep_value = 0;  // value the device step base holds after enqueued work
+  double kT = 0.0;          // lattice temperature of the thermal noise (0: none)
 
   template <typename T>
   T* at(size_t off) const {

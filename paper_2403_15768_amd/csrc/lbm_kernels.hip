@@ -1,7 +1,8 @@
 // lbm_kernels.hip -- HIP kernels for gfx950 (MI355X) and their launchers.
 //
 //  k_step           fused pull stream + Navier-slip wall + BGK/Guo collide,
-//                   one thread per fluid cell, ping-pong buffers
+//                   one thread per fluid cell, ping-pong buffers; TH = 1, 2
+//                   adds thermal noise of that form (fluctuating LB)
 //  k_moments        moments of the current state (the populations the next
 //                   collision sees), per-block FP64 partials of the flux and
 //                   the mass deviation, optional dense field output
@@ -27,7 +28,7 @@
 namespace lbm {
 
 // ------------------------------------------------------------ stream-collide
-template <class L, typename S, typename M, bool BOUZ>
+template <class L, typename S, typename M, bool BOUZ, int TH>
 __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                               StepArgs a) {
   // grid (fluid columns, segments per x-line).  Wall columns go first (their
@@ -51,9 +52,14 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   info.mask = (uint32_t)uniform((int)cs.mask);
   const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
   M df[L::Q];
+  // the thermal term depends only on (cell, step): drawn before the gather,
+  // it holds fewer registers than while the gathered values are live
+  M xi[L::Q];
+  if constexpr (TH != 0)
+    thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
   gather<L, S, M, M, BOUZ>(src, a, col, xc, info, df);
-  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                         (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step);
+  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                                (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
 }
 
 // ------------------------------------------------------------ moments
@@ -526,15 +532,28 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
   return hipGetLastError();
 }
 
+// the step kernel for a wall kind and a noise form (0: none)
+template <class L, typename S, typename M>
+static const void* step_kernel_t(bool bouz, int th_mode) {
+  if (bouz) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 1>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 2>);
+    return reinterpret_cast<const void*>(&k_step<L, S, M, true, 0>);
+  }
+  if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 1>);
+  if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 2>);
+  return reinterpret_cast<const void*>(&k_step<L, S, M, false, 0>);
+}
+
 template <class L, typename S, typename M>
 static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, bool bouz,
                                 hipStream_t st) {
   const dim3 grid((unsigned)a.nactive, (unsigned)a.segs), block(a.bx);
-  if (bouz)
-    hipLaunchKernelGGL((k_step<L, S, M, true>), grid, block, 0, st, (const S*)src, (S*)dst, a);
-  else
-    hipLaunchKernelGGL((k_step<L, S, M, false>), grid, block, 0, st, (const S*)src, (S*)dst, a);
-  return hipGetLastError();
+  const S* s = static_cast<const S*>(src);
+  S* d = static_cast<S*>(dst);
+  StepArgs args = a;
+  void* kargs[3] = {(void*)&s, (void*)&d, (void*)&args};
+  return hipLaunchKernel(step_kernel_t<L, S, M>(bouz, a.th_mode), grid, block, kargs, 0, st);
 }
 
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
@@ -549,10 +568,8 @@ hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepAr
   return launch_step_t<D3Q19, _Float16, float>(src, dst, a, bouz, st);
 }
 
-const void* step_kernel_ptr(int q, int prec, bool bouz) {
-#define KP(L, S, M)                                                                       \
-  (bouz ? reinterpret_cast<const void*>(&k_step<L, S, M, true>)                           \
-        : reinterpret_cast<const void*>(&k_step<L, S, M, false>))
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode) {
+#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode)
   if (q == 9) {
     if (prec == 0) return KP(D2Q9, double, double);
     if (prec == 1) return KP(D2Q9, float, double);

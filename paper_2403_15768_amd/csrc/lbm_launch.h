@@ -21,7 +21,7 @@ struct SpecArgs {
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
                        hipStream_t st);
-const void* step_kernel_ptr(int q, int prec, bool bouz);
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode);
 hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, bool bouz,
                           int which, double* field, double* partials, hipStream_t st);
 hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,

@@ -62,8 +62,10 @@ EXPORTS = [
     "lbm_transfer_state", "lbm_batch_footprint", "lbm_batch_create", "lbm_batch_destroy",
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
-    "lbm_batch_last_error",
+    "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations",
 ]
+
+NOISE_STRESS, NOISE_ALL = 1, 2
 
 _lib = None
 
@@ -95,12 +97,14 @@ def load() -> C.CDLL:
         "lbm_set_friction_spectral": [vp, C.POINTER(Spectral), vp, sz, C.c_int],
         "lbm_get_friction": [vp, dp, dp],
         "lbm_step": [vp, i64],
+        "lbm_set_thermal": [vp, C.c_double, C.c_int, C.c_uint64],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_flux": [vp, dp],
         "lbm_mass": [vp, dp],
         "lbm_get_field": [vp, C.c_int, dp],
         "lbm_get_populations": [vp, dp],
+        "lbm_set_populations": [vp, dp, i64],
         "lbm_state_bytes": [vp, C.POINTER(sz)],
         "lbm_get_state": [vp, vp, sz, C.POINTER(i64)],
         "lbm_set_state": [vp, vp, sz, i64],
@@ -272,6 +276,13 @@ class Channel:
                  "lbm_get_friction")
         return (lam, r) if raw else lam
 
+    # ---- thermal fluctuations
+    def set_thermal(self, kT: float, mode: int = NOISE_ALL, seed: int = 0) -> None:
+        """Fluctuating update at lattice temperature kT (0 = off); mode
+        NOISE_STRESS (the stress source alone) or NOISE_ALL."""
+        self._ck(self._lib.lbm_set_thermal(self._h, float(kT), int(mode), int(seed)),
+                 "lbm_set_thermal")
+
     # ---- time stepping
     def step(self, n: int) -> None:
         self._ck(self._lib.lbm_step(self._h, int(n)), "lbm_step")
@@ -320,6 +331,13 @@ class Channel:
         out = np.zeros((self.q,) + self.shape)
         self._ck(self._lib.lbm_get_populations(self._h, _dptr(out)), "lbm_get_populations")
         return out
+
+    def set_populations(self, g: np.ndarray, step: int = 0) -> None:
+        """Replace the state by dense shifted populations [i][z][y][x]."""
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert g.shape == (self.q,) + self.shape
+        self._ck(self._lib.lbm_set_populations(self._h, _dptr(g), int(step)),
+                 "lbm_set_populations")
 
     def get_state(self):
         n = C.c_size_t()

@@ -1,0 +1,244 @@
+"""GPU parity of the fluctuating update (thermal noise) against the oracle.
+
+Both sides draw the same Philox4x64-10 numbers; the GPU evaluates the
+Box-Muller transform in binary32 (logf, sqrtf, sincospif, each within two
+units in the last place), the oracle in binary64.  A normal |z| <= 5.77 then
+differs by at most 5.77 * 6 * 2^-24 < 2.1e-6, and a thermal term
+xi_i = A * (combination of normals with coefficients summing to <= 4 in
+absolute value) by at most 1e-5 A.  Tolerances below follow from that:
+one step compares populations to 1e-5 A.  Over a run of n steps: the
+linearised update is non-expansive in the w-weighted 2-norm (streaming
+permutes, the collision contracts), so the injected errors add at most
+linearly; they come from independent draws and carry no mass or momentum,
+so they add as a random walk, sqrt(n) * 1e-5 A = 1e-4 A per population at
+n = 101, and at most 18 moving directions make a velocity error below
+2e-3 A.  The fields then are about A in size: the multi-step test uses
+3e-4 relative, between that bound with the collision's damping of the
+non-conserved directions (|1 - 1/tau| = 0.25 per step at tau = 0.8) and the
+measured 8e-8.  FP32 storage adds its stochastic rounding (2^-24 relative
+per population and step, a random walk: below 1e-5 relative over 101
+steps).  One step measured 1.3e-7 A.  Counter-based numbers make every run
+reproducible: graph and plain launches, restarts and repeated runs agree bit
+for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2403_15768_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+C9 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [-1, 0, 0], [0, -1, 0],
+               [1, 1, 0], [-1, 1, 0], [-1, -1, 0], [1, -1, 0]])
+C19 = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1],
+                [0, 0, -1], [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1],
+                [-1, 0, -1], [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1],
+                [0, -1, 1]])
+
+
+def weights(q):
+    c = C9 if q == 9 else C19
+    c2 = (c ** 2).sum(1)
+    if q == 9:
+        return np.where(c2 == 0, 4 / 9, np.where(c2 == 1, 1 / 9, 1 / 36))
+    return np.where(c2 == 0, 1 / 3, np.where(c2 == 1, 1 / 18, 1 / 36))
+
+
+def amplitude(kT, tau, rho0=1.0):
+    g = 1 - 1 / tau
+    return np.sqrt(3 * rho0 * kT * (1 - g * g))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_15768_amd import lbm as mod
+
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def equilibrium_sample(q, shape, mu, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((q,) + shape) * np.sqrt(mu * weights(q))[:, None, None, None]
+
+
+def build(lbm, case, precision, tau=0.8, g=1e-6):
+    """(GPU channel, oracle lattice) with the same seeded friction."""
+    if case == "d2q9":
+        args, kw = (9, lbm.SLAB, 64, 30, 1), {}
+    elif case == "duct":
+        args, kw = (19, lbm.DUCT, 40, 12, 10), {}
+    elif case == "slab":
+        args, kw = (19, lbm.SLAB, 33, 9, 6), {}
+    else:
+        R = 6
+        ny, nz, cy, cz = inputs.tube_box(R)
+        args, kw = (19, lbm.TUBE, 20, ny, nz), dict(tube_radius=float(R), tube_cy=cy, tube_cz=cz)
+    q, geom, nx, ny, nz = args
+    G = lbm.Channel(q, geom, nx, ny, nz, tau=tau, force=(g, 0, 0), precision=precision, **kw)
+    O = oracle.Lattice(q, geom, nx, ny, nz, tau=tau, force=(g, 0, 0), **kw)
+    rng = np.random.default_rng(123)
+    lam = rng.uniform(0.0, 0.2, size=G.wall_count)
+    G.set_friction(lam)
+    O.set_friction(lam)
+    return G, O
+
+
+CASES = ["d2q9", "duct", "slab", "tube"]
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("case", CASES)
+def test_one_step_noise_parity_fp64(lbm, case, mode):
+    say("thermal one step", case, mode)
+    kT, tau = 1e-6, 0.8
+    G, O = build(lbm, case, "f64", tau=tau)
+    A = amplitude(kT, tau)
+    g0 = equilibrium_sample(G.q, G.shape, 3 * kT, 7)
+    O.set_populations(g0, step=1234)
+    G.set_populations(g0, step=1234)
+    for L in (G, O):
+        L.set_thermal(kT, mode, 2024)
+    G.step(1)
+    O.step(1)
+    pg, po = G.populations(), O.get_populations()
+    fluid = O.fields()[0] != 0
+    d = np.abs(pg - po)[:, fluid]
+    say("  max |dg| / A", d.max() / A)
+    assert d.max() < 1e-5 * A
+    # the noise is really there: the step moves populations by about A
+    assert np.abs(pg - g0).max() > 0.5 * A
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("case", CASES)
+def test_fields_parity_over_graph_and_plain_steps(lbm, case, mode, precision):
+    # 101 steps: one 64-step graph replay, then 37 single launches
+    say("thermal fields", case, mode, precision)
+    kT, tau, n = 1e-6, 0.8, 101
+    G, O = build(lbm, case, precision, tau=tau)
+    for L in (G, O):
+        L.set_thermal(kT, mode, 77)
+    G.step(n)
+    O.step(n)
+    rg, ro = G.fields(), O.fields()
+    ref = max(np.abs(ro[k]).max() for k in (1, 2, 3))
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / ref
+    rerr = np.abs(rg[0] - ro[0]).max()
+    tol = 3e-4 if precision == "f64" else 3.1e-4
+    say(f"  rel u err {err:.3e} (tol {tol:.1e}), rho err {rerr:.3e}")
+    assert err < tol
+    assert rerr < tol * 3 * np.sqrt(kT)
+    if precision == "f64":
+        qg, qo = G.invariants(), O.invariants()
+        assert abs(qg[2] - qo[2]) < 1e-12 * O.fluid_count
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_graph_plain_repeat_and_restart_bitwise(lbm, precision):
+    say("thermal bitwise", precision)
+
+    def make():
+        G, _ = build(lbm, "duct", precision)
+        G.set_thermal(1e-6, 2, 5)
+        return G
+    A = make()
+    A.step(128)  # two graph replays
+    B = make()
+    for _ in range(128):
+        B.step(1)  # plain launches
+    sa, sb = A.get_state(), B.get_state()
+    assert sa[1] == sb[1] == 128 and np.array_equal(sa[0], sb[0])
+    C = make()
+    C.step(50)
+    buf, step = C.get_state()
+    D = make()
+    D.set_state(buf, step)
+    D.step(78)
+    assert np.array_equal(D.get_state()[0], sa[0])
+    E = make()
+    E.set_thermal(1e-6, 2, 6)  # another seed: another run
+    E.step(128)
+    assert not np.array_equal(E.get_state()[0], sa[0])
+
+
+def test_thermal_off_equals_never_on(lbm):
+    A, _ = build(lbm, "duct", "f64")
+    A.set_thermal(1e-6, 1, 3)
+    A.set_thermal(0.0, 0, 0)
+    A.step(70)
+    B, _ = build(lbm, "duct", "f64")
+    B.step(70)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+
+
+def test_thermal_settings_rejected(lbm):
+    G, _ = build(lbm, "duct", "f32")
+    for kT, mode in [(-1e-6, 2), (float("nan"), 2), (float("inf"), 1), (1e-6, 0), (1e-6, 3)]:
+        with pytest.raises(lbm.LBMError):
+            G.set_thermal(kT, mode, 0)
+    G.step(3)  # still usable
+
+
+def test_batch_refuses_thermal_members(lbm):
+    chs = [build(lbm, "duct", "f32")[0] for _ in range(2)]
+    chs[1].set_thermal(1e-6, 2, 0)
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch(chs)
+    chs[1].set_thermal(0.0, 0, 0)
+    b = lbm.Batch(chs)
+    chs[0].set_thermal(1e-6, 2, 0)  # switched on after the batch was built
+    with pytest.raises(lbm.LBMError):
+        b.step(4)
+
+
+# ---------------------------------------------- full-size properties (duct)
+def test_full_duct_equilibrium_stationary_fp32(lbm):
+    # 256 x 128 x 64 duct, FP32 storage as in the benchmark, free-slip walls,
+    # noise in every non-conserved direction: the equilibrium Gaussian
+    # measure stays put (40 M populations: standard error 0.02 %)
+    say("thermal full duct stationarity")
+    kT, tau, q = 1e-5, 0.7, 19
+    G = lbm.Channel(q, lbm.DUCT, 256, 128, 64, tau=tau, force=(0, 0, 0), precision="f32")
+    G.set_friction(0.0)
+    G.set_thermal(kT, 2, 11)
+    mu = 3 * kT
+    G.set_populations(equilibrium_sample(q, G.shape, mu, 3).astype(np.float64))
+    m0 = G.invariants()[2]
+    G.step(256)
+    g = G.populations().reshape(q, -1)
+    r = (g ** 2).mean(1) / (mu * weights(q))
+    rho, ux = G.field(0), G.field(1)
+    jx2 = np.mean((rho * ux) ** 2) / kT
+    say("  variance ratios", np.round(r, 4), "jx2/kT", jx2)
+    assert abs(r.mean() - 1) < 0.003
+    assert np.all(np.abs(r - 1) < 0.01)
+    assert abs(jx2 - 1) < 0.01
+    # stochastic rounding keeps the mass deviation unbiased: drift stays far
+    # below the thermal mass fluctuation sqrt(3 kT N)
+    assert abs(G.invariants()[2] - m0) < 1e-3 * np.sqrt(3 * kT * G.fluid_count)
+
+
+def test_full_duct_mass_and_axial_momentum_conserved_fp64(lbm):
+    say("thermal full duct conservation")
+    G = lbm.Channel(19, lbm.DUCT, 256, 128, 64, tau=0.7, force=(0, 0, 0), precision="f64")
+    G.set_friction(0.0)
+    G.set_thermal(1e-5, 1, 12)
+    G.step(10)
+    rho, ux = G.field(0), G.field(1)
+    m0, j0 = (rho - 1).sum(), (rho * ux).sum()
+    G.step(128)
+    rho, ux = G.field(0), G.field(1)
+    assert abs((rho - 1).sum() - m0) < 1e-9
+    assert abs((rho * ux).sum() - j0) < 1e-9
+    assert np.std(rho * ux) > 1e-3
