@@ -59,6 +59,7 @@ class _Spectral(C.Structure):
         ("d", C.c_double), ("nq", C.c_int), ("nw", C.c_int),
         ("q_max", C.c_double), ("w_max", C.c_double),
         ("lambda_target", C.c_double), ("dispersion", C.c_int),
+        ("coupling", C.c_int), ("v_l", C.c_double),
     ]
 
 
@@ -99,6 +100,7 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_friction_raw.argtypes = [sp, C.c_double]
     lib.ora_friction_raw.restype = C.c_double
     lib.ora_friction.argtypes = [sp, dp, lp, dp, dp]
+    lib.ora_response.argtypes = [sp, C.c_double, C.c_double, C.c_double, dp]
     lib.ora_sizeof_real.restype = C.c_int
     u64p = C.POINTER(C.c_uint64)
     lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
@@ -230,6 +232,8 @@ class Spectral:
     w_max: float | None = None
     lambda_target: float = 0.05
     dispersion: int = 1
+    coupling: int = 0
+    v_l: float = 0.0
 
     def _c(self) -> _Spectral:
         s = _Spectral()
@@ -239,6 +243,7 @@ class Spectral:
         s.q_max = self.q_max if self.q_max is not None else 10.0 / self.d
         s.w_max = self.w_max if self.w_max is not None else 20.0 * self.T
         s.lambda_target, s.dispersion = self.lambda_target, self.dispersion
+        s.coupling, s.v_l = self.coupling, self.v_l
         return s
 
 
@@ -250,6 +255,14 @@ def img_l(sp: Spectral, w: float, kind: str = "f64") -> float:
 def img_s(sp: Spectral, Omega: float, q: float, w: float, kind: str = "f64") -> float:
     s = sp._c()
     return _lib(kind).ora_img_s(C.byref(s), float(Omega), float(q), float(w))
+
+
+def response(sp: Spectral, Omega: float, q: float, w: float, kind: str = "f64"):
+    """Complex surface responses (g_s, g_l) at wavevector q and frequency w."""
+    s = sp._c()
+    out = np.zeros(4)
+    _lib(kind).ora_response(C.byref(s), float(Omega), float(q), float(w), _dptr(out))
+    return complex(out[0], out[1]), complex(out[2], out[3])
 
 
 def friction_raw(sp: Spectral, Omega: float, kind: str = "f64") -> float:

@@ -34,9 +34,11 @@
  *    first option of Sec. 4.2).
  *  - Friction quadrature: a (q, omega) midpoint sum of the imaginary parts of
  *    a Drude solid response and a Lorentzian liquid response with a thermal
- *    factor; the paper states only that the Keldysh analysis yields linear
- *    friction coefficients (appendix, Eq. 27), so the integrand here is a
- *    synthetic stand-in of that form.
+ *    factor, optionally divided by the coupling denominator
+ *    |1 - g_s g_l e^{-2qd}|^2 and with a q-dependent liquid mode; the paper
+ *    states only that the Keldysh analysis yields linear friction
+ *    coefficients (appendix, Eq. 27), so the spectra here are synthetic
+ *    stand-ins of that form.
  *
  * Step n -> n+1, for every fluid cell x (no blocking, no fusion):
  *   1. pull:   df_i = g_i(x - c_i), periodic in x (and z for the slab);
@@ -648,9 +650,11 @@ typedef struct {
   double q_max, w_max;
   double lambda_target;
   int dispersion; /* 1: omega_p^2 = Omega^2 q d ; 0: omega_p^2 = Omega^2 */
+  int coupling;   /* 1: divide by |1 - g_s g_l e^{-2qd}|^2 ; 0: leave it out */
+  double v_l;     /* liquid mode: omega_l(q)^2 = omega_l^2 + v_l^2 q^2 */
 } ora_spectral;
 
-/* imaginary part of the Lorentzian liquid response at frequency w */
+/* imaginary part of the Lorentzian liquid response at frequency w (q = 0) */
 double ora_img_l(const ora_spectral *s, double w) {
   real wl2 = (real)s->omega_l * (real)s->omega_l, ww = (real)w;
   real den = (wl2 - ww * ww) * (wl2 - ww * ww) +
@@ -669,9 +673,41 @@ double ora_img_s(const ora_spectral *s, double Omega, double q, double w) {
   return (double)(wp2 * (real)s->gamma_s * ww / den);
 }
 
+/* The complex surface responses at (q, w), each a damped oscillator
+ * A W / (W - w^2 - i gamma w):
+ *   solid  g_s: A = 1,   W = omega_p(q)^2 (as in ora_img_s), gamma_s;
+ *   liquid g_l: A = a_l, W = omega_l^2 + v_l^2 q^2, gamma_l.
+ * out = (Re g_s, Im g_s, Re g_l, Im g_l). */
+static void responses(const ora_spectral *s, real Omega, real q, real w,
+                      real out[4]) {
+  real Ws = Omega * Omega * (s->dispersion ? q * (real)s->d : (real)1);
+  real Wl = (real)s->omega_l * (real)s->omega_l +
+            (real)s->v_l * (real)s->v_l * q * q;
+  real ds = Ws - w * w, es = (real)s->gamma_s * w;
+  real dl = Wl - w * w, el = (real)s->gamma_l * w;
+  real ns = Ws / (ds * ds + es * es);
+  real nl = (real)s->a_l * Wl / (dl * dl + el * el);
+  /* A W / (d - i e) = A W (d + i e) / (d^2 + e^2) */
+  out[0] = ns * ds;
+  out[1] = ns * es;
+  out[2] = nl * dl;
+  out[3] = nl * el;
+}
+
+void ora_response(const ora_spectral *s, double Omega, double q, double w,
+                  double *out) {
+  real r[4];
+  int k;
+  responses(s, (real)Omega, (real)q, (real)w, r);
+  for (k = 0; k < 4; k++) out[k] = (double)r[k];
+}
+
 /* raw friction sum for one plasmon frequency Omega:
- *   C sum_a sum_b dq dw q^3 e^{-2 q d} Im g_s Im g_l / sinh^2(w / 2T),
- *   C = 1 / (8 pi^2 T), midpoint grids on (0, q_max) and (0, w_max). */
+ *   C sum_a sum_b dq dw q^3 e^{-2 q d} Im g_s Im g_l
+ *       / (sinh^2(w / 2T) |1 - g_s g_l e^{-2 q d}|^2),
+ *   C = 1 / (8 pi^2 T), midpoint grids on (0, q_max) and (0, w_max).
+ * The denominator (the two surfaces' repeated mutual screening) is 1 when
+ * coupling = 0; with v_l = 0 the liquid response does not depend on q. */
 double ora_friction_raw(const ora_spectral *s, double Omega) {
   real pi = (real)3.14159265358979323846264338327950288L;
   real C = 1 / (8 * pi * pi * (real)s->T);
@@ -680,20 +716,20 @@ double ora_friction_raw(const ora_spectral *s, double Omega) {
   int a, b;
   for (a = 0; a < s->nq; a++) {
     real q = ((real)a + (real)0.5) * dq;
-    real kq = q * q * q * R_EXP(-2 * q * (real)s->d);
+    real e = R_EXP(-2 * q * (real)s->d);
+    real kq = q * q * q * e;
     for (b = 0; b < s->nw; b++) {
       real w = ((real)b + (real)0.5) * dw;
       real sh = R_SINH(w / (2 * (real)s->T));
-      real wp2 = (real)Omega * (real)Omega *
-                 (s->dispersion ? q * (real)s->d : (real)1);
-      real ims = wp2 * (real)s->gamma_s * w /
-                 ((wp2 - w * w) * (wp2 - w * w) +
-                  (real)s->gamma_s * (real)s->gamma_s * w * w);
-      real wl2 = (real)s->omega_l * (real)s->omega_l;
-      real iml = (real)s->a_l * wl2 * (real)s->gamma_l * w /
-                 ((wl2 - w * w) * (wl2 - w * w) +
-                  (real)s->gamma_l * (real)s->gamma_l * w * w);
-      sum += dq * dw * kq * ims * iml / (sh * sh);
+      real g[4], den = 1;
+      responses(s, (real)Omega, q, w, g);
+      if (s->coupling) {
+        /* z = e g_s g_l ; |1 - z|^2 */
+        real zr = e * (g[0] * g[2] - g[1] * g[3]);
+        real zi = e * (g[0] * g[3] + g[1] * g[2]);
+        den = (1 - zr) * (1 - zr) + zi * zi;
+      }
+      sum += dq * dw * kq * g[1] * g[3] / (sh * sh * den);
     }
   }
   return (double)(C * sum);

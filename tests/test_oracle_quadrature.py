@@ -3,11 +3,15 @@
 The integrand is a synthetic stand-in for the friction coefficients
 the paper's Keldysh analysis produces (appendix, Eq. 27): a q^3 e^{-2qd}
 weighted wavevector sum times a frequency sum of Im g_s Im g_l / sinh^2(w/2T).
-The pins reach it by other routes: complex response functions and the Bose
-occupation identity 1/sinh^2(x/2) = 4 n (n + 1) (brute force on tiny grids),
-the f-sum rule of a damped oscillator, the closed form of the q integral and
-an adaptive integrator.
+The full form also divides by the screening denominator |1 - g_s g_l e^{-2qd}|^2
+and lets the liquid mode disperse with q.  The pins reach it by other
+routes: complex response functions and the Bose occupation identity
+1/sinh^2(x/2) = 4 n (n + 1) (brute force on tiny grids), the f-sum rule of a
+damped oscillator, Kramers-Kronig for the real parts, the closed form of the
+q integral (a double geometric series once screened), the weak-coupling
+limit and an adaptive integrator.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -20,7 +24,7 @@ from oracle import Spectral
 
 def brute_force(sp: Spectral, Omega: float) -> float:
     """Independent route: responses as Python complex numbers, thermal factor
-    from the Bose occupation number."""
+    from the Bose occupation number, screening as |1 - z|^2 of a complex z."""
     qmax = 10.0 / sp.d
     wmax = 20.0 * sp.T
     dq, dw = qmax / sp.nq, wmax / sp.nw
@@ -31,9 +35,12 @@ def brute_force(sp: Spectral, Omega: float) -> float:
         for b in range(sp.nw):
             w = (b + 0.5) * dw
             gs = wp2 / complex(wp2 - w * w, -sp.gamma_s * w)
-            gl = sp.a_l * sp.omega_l ** 2 / complex(sp.omega_l ** 2 - w * w, -sp.gamma_l * w)
+            wl2 = sp.omega_l ** 2 + sp.v_l ** 2 * q * q
+            gl = sp.a_l * wl2 / complex(wl2 - w * w, -sp.gamma_l * w)
             n = 1.0 / math.expm1(w / sp.T)
-            tot += dq * dw * q ** 3 * math.exp(-2 * q * sp.d) * gs.imag * gl.imag * 4 * n * (n + 1)
+            x = math.exp(-2 * q * sp.d)
+            screen = abs(1 - x * gs * gl) ** 2 if sp.coupling else 1.0
+            tot += dq * dw * q ** 3 * x * gs.imag * gl.imag * 4 * n * (n + 1) / screen
     return tot / (8 * math.pi ** 2 * sp.T)
 
 
@@ -43,11 +50,12 @@ def spec(**kw):
     return Spectral(**base)
 
 
+@pytest.mark.parametrize("full", [(0, 0.0), (1, 0.0), (1, 0.7)])
 @pytest.mark.parametrize("nq", [1, 2, 4])
 @pytest.mark.parametrize("nw", [1, 4, 16])
 @pytest.mark.parametrize("disp", [0, 1])
-def test_tiny_grid_brute_force(nq, nw, disp):
-    sp = spec(nq=nq, nw=nw, dispersion=disp)
+def test_tiny_grid_brute_force(nq, nw, disp, full):
+    sp = spec(nq=nq, nw=nw, dispersion=disp, coupling=full[0], v_l=full[1])
     for Om in (0.9, 1.7, 2.8):
         ref = brute_force(sp, Om)
         got = oracle.friction_raw(sp, Om)
@@ -150,6 +158,120 @@ def test_lattice_friction_normalisation_and_sign():
 
 def test_long_double_agrees():
     sp = spec(nq=128, nw=512)
+    a = oracle.friction_raw(sp, 1.9)
+    b = oracle.friction_raw(sp, 1.9, kind="f80")
+    assert abs(a / b - 1) < 1e-13
+
+
+# --------------------------------------------- coupled (screened) quadrature
+# The full form divides by |1 - g_s g_l e^{-2qd}|^2 (the two surfaces screen
+# each other repeatedly) and lets the liquid mode disperse,
+# omega_l(q)^2 = omega_l^2 + v_l^2 q^2.  It needs the complex responses; their
+# real parts are pinned by causality (Kramers-Kronig), the denominator by a
+# closed-form series of the q integral.
+
+@pytest.mark.parametrize("which", ["solid", "liquid"])
+def test_real_parts_by_kramers_kronig(which):
+    # Re g(w) = (1/pi) [PV int_0^inf Im g(u) / (u - w) du + int_0^inf Im g(u) / (u + w) du]
+    # for a causal response vanishing at infinity (Im g odd in w), and the
+    # static value g(0) = (2/pi) int_0^inf Im g(u) / u du
+    sp = spec(v_l=0.7)
+    Om, q = 1.9, 1.3
+    k = 0 if which == "solid" else 1
+    im = lambda u: oracle.response(sp, Om, q, u)[k].imag
+    W = 60.0
+    for w in (0.4, 1.1, 2.5, 3.7):
+        pv = integrate.quad(im, 0, W, weight="cauchy", wvar=w, limit=400, epsabs=0, epsrel=1e-11)[0]
+        pv += integrate.quad(lambda u: im(u) / (u - w), W, np.inf, limit=200, epsabs=0, epsrel=1e-11)[0]
+        plus = integrate.quad(lambda u: im(u) / (u + w), 0, np.inf, limit=400, epsabs=0, epsrel=1e-11)[0]
+        re = oracle.response(sp, Om, q, w)[k].real
+        assert abs((pv + plus) / math.pi - re) < 1e-8 * max(1.0, abs(re))
+    static = 2 / math.pi * integrate.quad(lambda u: im(u) / u, 0, np.inf, limit=400,
+                                           epsabs=0, epsrel=1e-11)[0]
+    assert static == pytest.approx(1.0 if which == "solid" else sp.a_l, rel=1e-8)
+
+
+def test_liquid_dispersion_shifts_the_mode():
+    # with v_l the liquid response at q is the q = 0 response of a mode at
+    # sqrt(omega_l^2 + v_l^2 q^2); v_l = 0 leaves it independent of q
+    sp = spec(v_l=0.8)
+    for q in (0.3, 1.0, 4.0):
+        shifted = spec(omega_l=math.sqrt(sp.omega_l ** 2 + 0.64 * q * q))
+        for w in (0.5, 2.0, 3.3):
+            got = oracle.response(sp, 1.7, q, w)[1].imag
+            assert got == pytest.approx(oracle.img_l(shifted, w), rel=1e-14)
+            assert oracle.response(spec(), 1.7, q, w)[1].imag == pytest.approx(
+                oracle.img_l(spec(), w), rel=1e-14)
+
+
+def q_series(G, d, Q, kmax=200):
+    # int_0^Q q^3 x / |1 - x G|^2 dq, x = e^{-2qd}, |G| < 1:
+    # 1/|1 - xG|^2 = sum_{m,n} G^m conj(G)^n x^{m+n}, each power integrated
+    # in closed form over the truncated range
+    tot = 0.0
+    for k in range(kmax):
+        s = sum(G ** m * np.conj(G) ** (k - m) for m in range(k + 1))
+        tot += s.real * q_integral_truncated(d * (1 + k), Q)
+    return tot
+
+
+def test_coupled_q_sum_equals_series_closed_form():
+    # one frequency point and no plasmon dispersion: the double sum is the
+    # frequency factor times a midpoint q sum of q^3 x / |1 - x G|^2, G = g_s g_l
+    T, Om, w0 = 1.05, 0.9, 1.2
+    sp = spec(T=T, dispersion=0, coupling=1, nw=1, w_max=2 * w0)
+    gs, gl = oracle.response(sp, Om, 1.0, w0)
+    G = gs * gl
+    assert 0.3 < abs(G) < 0.9
+    C = 1 / (8 * math.pi ** 2 * T)
+    pref = C * 2 * w0 * gs.imag * gl.imag / math.sinh(w0 / (2 * T)) ** 2
+    exact = q_series(G, 1.0, 10.0)
+    for nq, tol in ((128, 0.02), (256, 0.05)):
+        err = oracle.friction_raw(dataclasses.replace(sp, nq=nq), Om) / pref - exact
+        # midpoint rule: f'(0) = 0, so the leading error is
+        # (7 h^4 / 5760)(f'''(Q) - f'''(0)) with f'''(0) = 6 / |1 - G|^2
+        h = 10.0 / nq
+        predicted = -7 * h ** 4 / 5760 * 6 / abs(1 - G) ** 2
+        assert abs(err / predicted - 1) < tol
+    assert abs(err / exact) < 1e-7
+    # the same sum with the screening sign flipped is far off
+    assert abs(q_series(-G, 1.0, 10.0) / exact - 1) > 0.1
+
+
+def test_weak_coupling_limit():
+    # the denominator is 1 + O(a_l): the coupled result approaches the
+    # unscreened one linearly in the liquid's strength
+    dev = []
+    for a in (2e-3, 1e-3):
+        sp = spec(a_l=a, nq=64, nw=256)
+        dev.append(oracle.friction_raw(dataclasses.replace(sp, coupling=1), 1.7)
+                   / oracle.friction_raw(sp, 1.7) - 1)
+    assert abs(dev[1]) < 1e-2
+    assert 1.9 < dev[0] / dev[1] < 2.1
+
+
+@pytest.mark.parametrize("v_l", [0.0, 0.6])
+def test_coupled_refinement_against_adaptive_integrator(v_l):
+    sp = spec(T=1.1, coupling=1, v_l=v_l, nq=256, nw=1024)
+    Om, T = 2.2, 1.1
+
+    def integrand(w, q):
+        gs, gl = oracle.response(sp, Om, q, w)
+        x = math.exp(-2 * q)
+        return (q ** 3 * x * gs.imag * gl.imag
+                / (math.sinh(w / (2 * T)) ** 2 * abs(1 - x * gs * gl) ** 2))
+
+    ref = integrate.dblquad(integrand, 0, 10.0, 0, 20 * T, epsabs=0, epsrel=1e-11)[0]
+    ref /= 8 * math.pi ** 2 * T
+    e1 = oracle.friction_raw(sp, Om) / ref - 1
+    e2 = oracle.friction_raw(dataclasses.replace(sp, nq=512, nw=2048), Om) / ref - 1
+    # still fourth order: |1 - z|^2 is even in w (z(-w) = conj z(w))
+    assert abs(e1) < 1e-7
+    assert 14.0 < e1 / e2 < 18.0
+
+
+def test_coupled_long_double_agrees():
+    sp = spec(nq=128, nw=512, coupling=1, v_l=0.5)
     a = oracle.friction_raw(sp, 1.9)
     b = oracle.friction_raw(sp, 1.9, kind="f80")
     assert abs(a / b - 1) < 1e-13
