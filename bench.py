@@ -149,6 +149,17 @@ def extras(torch, lbm, inputs, args):
     n = tb.wall_count
     out["quadrature"] = {"nodes": n, "grid": [sp.nq, sp.nw], "s": round(qs, 4),
                          "gpoints_per_s": round((n + 1) * sp.nq * sp.nw / qs / 1e9, 2)}
+    # the screened form (|1 - g_s g_l e^{-2qd}|^2, dispersive liquid mode)
+    sp.coupling, sp.v_l = 1, 0.5
+    tb.set_friction_spectral(sp, om)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tb.set_friction_spectral(sp, om)
+    qs = time.perf_counter() - t0
+    out["quadrature_screened"] = {"nodes": n, "grid": [sp.nq, sp.nw], "s": round(qs, 4),
+                                  "gpoints_per_s": round((n + 1) * sp.nq * sp.nw / qs / 1e9, 2)}
+    sp.coupling, sp.v_l = 0, 0.0
+    tb.set_friction_spectral(sp, om)
     tb.step(200)
     wall, kms = timed_run(torch, tb, 2000, 1000)
     cells = tb.fluid_count

@@ -92,12 +92,17 @@ typedef struct {
 /* Synthetic surface-response spectra of the friction quadrature (units
  * hbar = k_B = 1, lengths in units of the gap d):
  *   raw(Omega) = C sum_a sum_b dq dw q_a^3 e^{-2 q_a d}
- *                  Im g_s(q_a, w_b; Omega) Im g_l(w_b) / sinh^2(w_b / 2T),
+ *                  Im g_s Im g_l / (sinh^2(w_b / 2T) S),
  *   C = 1/(8 pi^2 T), q_a = (a+1/2) dq, dq = q_max/nq, w_b = (b+1/2) dw,
- *   dw = w_max/nw,
- *   Im g_l(w) = a_l w_l^2 gamma_l w / ((w_l^2 - w^2)^2 + gamma_l^2 w^2),
- *   Im g_s(q,w;Omega) = P gamma_s w / ((P - w^2)^2 + gamma_s^2 w^2),
- *   P = Omega^2 q d (dispersion = 1) or Omega^2 (dispersion = 0).
+ *   dw = w_max/nw, responses at (q_a, w_b), each a damped oscillator
+ *   A W / (W - w^2 - i gamma w):
+ *   g_s: A = 1, W = P = Omega^2 q d (dispersion = 1) or Omega^2 (dispersion = 0),
+ *        gamma = gamma_s;
+ *   g_l: A = a_l, W = w_l^2 + v_l^2 q^2, gamma = gamma_l;
+ *   S = |1 - g_s g_l e^{-2 q d}|^2 (coupling = 1: the two surfaces screen
+ *       each other repeatedly) or 1 (coupling = 0).
+ * coupling must be 0 or 1, v_l finite and >= 0.  coupling = 0, v_l = 0 is
+ * the unscreened, non-dispersive form (a faster kernel).
  * Lattice friction of node k: lambda_k = lambda_target raw(Omega_k)/raw(omega0).
  * Stand-in for the friction coefficients of the Keldysh analysis (appendix,
  * Eq. 27), which the paper does not give in closed form. */
@@ -107,6 +112,8 @@ typedef struct {
   double q_max, w_max;
   double lambda_target;
   int dispersion;
+  int coupling;
+  double v_l;
 } lbm_spectral;
 
 typedef struct lbm_ctx lbm_ctx; /* opaque */

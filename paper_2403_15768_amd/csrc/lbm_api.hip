@@ -557,8 +557,9 @@ lbm_status lbm_set_friction_spectral(lbm_ctx* c, const lbm_spectral* sp, const d
   if (!(sp->T > 0) || !(sp->d > 0) || !(sp->gamma_s > 0) || !(sp->gamma_l > 0) ||
       !(sp->omega_l > 0) || !(sp->a_l > 0) || !(sp->q_max > 0) || !(sp->w_max > 0) ||
       !(sp->omega0 > 0) || sp->nq < 1 || sp->nw < 1 || !(sp->lambda_target >= 0) ||
+      (sp->coupling != 0 && sp->coupling != 1) || !(sp->v_l >= 0) ||
       !std::isfinite(sp->T + sp->d + sp->gamma_s + sp->gamma_l + sp->omega_l + sp->a_l +
-                     sp->q_max + sp->w_max + sp->omega0 + sp->lambda_target))
+                     sp->q_max + sp->w_max + sp->omega0 + sp->lambda_target + sp->v_l))
     return c->fail(LBM_EINVAL, "bad spectral parameters");
   std::vector<double> h;
   const double* hsrc = omega;
@@ -579,8 +580,9 @@ lbm_status lbm_set_friction_spectral(lbm_ctx* c, const lbm_spectral* sp, const d
   if (n)
     HIPCHK(c, hipMemcpyAsync(dl, omega, n * sizeof(double),
                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-  lbm::SpecArgs a{sp->T,  sp->omega0, sp->gamma_s, sp->omega_l, sp->gamma_l, sp->a_l, sp->d,
-                  sp->nq, sp->nw,     sp->q_max,   sp->w_max,   sp->lambda_target, sp->dispersion};
+  lbm::SpecArgs a{sp->T,  sp->omega0, sp->gamma_s, sp->omega_l,       sp->gamma_l,
+                  sp->a_l, sp->d,      sp->nq,      sp->nw,            sp->q_max,
+                  sp->w_max, sp->lambda_target, sp->dispersion, sp->coupling, sp->v_l};
   HIPCHK(c, lbm::launch_friction(a, dl, (int64_t)n, draw, dl, c->stream));
   c->have_raw = true;
   return upload_wall_r(c, dl, (int64_t)n);

@@ -9,6 +9,8 @@
 //  k_reduce_final   fixed-order FP64 sum of the per-block partials
 //  k_friction_raw   (q, omega) friction quadrature, omega table tiled
 //                   through LDS, FP64 sums, wavefront + block reduction
+//  k_friction_full  the same with the screening denominator |1 - g_s g_l e^{-2qd}|^2
+//                   and a dispersive liquid mode (complex responses)
 //  k_friction_lat   normalisation lambda_k = lambda_target raw_k / raw_ref
 //  k_set_r          lambda -> wall mixing weight r = 3 lambda / (1 + 3 lambda)
 //  k_copy           plain 16-byte streaming copy (measured bandwidth ceiling)
@@ -214,6 +216,116 @@ __global__ void __launch_bounds__(kQuadThreads) k_friction_raw(SpecArgs s,
         for (int j = 0; j < kQuadNodes; j++) {
           const double dd = P[j] - e.s;
           S[j] += e.v / (dd * dd + e.t);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kQuadNodes; j++) acc[j] += kq * P[j] * S[j];
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < kQuadNodes; j++) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) red[j][wv] = v;
+  }
+  __syncthreads();
+  if (tid < kQuadNodes) {
+    const int64_t k = k0 + tid;
+    if (k <= n) {
+      double t = 0;
+      for (int w = 0; w < kQuadThreads / 64; w++) t += red[tid][w];
+      const double C = 1.0 / (8.0 * M_PI * M_PI * s.T);
+      raw[k] = C * dq * dw * t;
+    }
+  }
+}
+
+// The screened form: complex responses g_s = P (d_s + i gamma_s w) / D,
+// d_s = P - w^2, D = d_s^2 + gamma_s^2 w^2, and g_l = a_l W (d_l + i gamma_l w)
+// / (d_l^2 + gamma_l^2 w^2), W = omega_l^2 + v_l^2 q^2, d_l = W - w^2; with
+// z = e^{-2qd} g_s g_l = (e P / D)(a + i b), a = d_s Re g_l - gamma_s w Im g_l,
+// b = d_s Im g_l + gamma_s w Re g_l, the term
+//   q^3 e^{-2qd} Im g_s Im g_l / (sinh^2 |1 - z|^2)
+//   = q^3 e^{-2qd} P (gamma_s w / sinh^2) Im g_l D / ((D - e P a)^2 + (e P b)^2)
+// takes one divide (SCREEN = false: the unscreened term with a dispersive
+// liquid, q^3 e^{-2qd} P (gamma_s w / sinh^2) Im g_l / D).
+constexpr int kFullTile = 512;
+
+struct OmegaEntryFull {
+  double w2, gw, t, v, glw, gl2w2, pad0, pad1;  // w^2, gamma_s w, gamma_s^2 w^2,
+                                                // gamma_s w / sinh^2, gamma_l w, (gamma_l w)^2
+};
+
+template <bool SCREEN>
+__global__ void __launch_bounds__(kQuadThreads) k_friction_full(SpecArgs s,
+                                                                const double* __restrict__ omega,
+                                                                int64_t n,
+                                                                double* __restrict__ raw) {
+  __shared__ OmegaEntryFull tab[kFullTile];
+  __shared__ double red[kQuadNodes][kQuadThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kQuadNodes;
+  double om2[kQuadNodes];
+#pragma unroll
+  for (int j = 0; j < kQuadNodes; j++) {
+    const int64_t k = k0 + j;
+    const double o = k < n ? omega[k] : s.omega0;  // k >= n: reference (k == n) or padding
+    om2[j] = o * o;
+  }
+  const double dq = s.q_max / s.nq, dw = s.w_max / s.nw;
+  double acc[kQuadNodes];
+#pragma unroll
+  for (int j = 0; j < kQuadNodes; j++) acc[j] = 0.0;
+
+  for (int b0 = 0; b0 < s.nw; b0 += kFullTile) {
+    const int nb = min(kFullTile, s.nw - b0);
+    __syncthreads();
+    for (int b = tid; b < nb; b += kQuadThreads) {
+      const double w = ((double)(b0 + b) + 0.5) * dw;
+      const double sh = sinh(w / (2.0 * s.T));
+      OmegaEntryFull e;
+      e.w2 = w * w;
+      e.gw = s.gamma_s * w;
+      e.t = e.gw * e.gw;
+      e.v = e.gw / (sh * sh);
+      e.glw = s.gamma_l * w;
+      e.gl2w2 = e.glw * e.glw;
+      e.pad0 = e.pad1 = 0.0;
+      tab[b] = e;
+    }
+    __syncthreads();
+    for (int ai = tid; ai < s.nq; ai += kQuadThreads) {
+      const double q = ((double)ai + 0.5) * dq;
+      const double ex = exp(-2.0 * q * s.d);
+      const double kq = q * q * q * ex;
+      const double qd = s.dispersion ? q * s.d : 1.0;
+      const double Wl = s.omega_l * s.omega_l + s.v_l * s.v_l * q * q;
+      const double Al = s.a_l * Wl;
+      double P[kQuadNodes], eP[kQuadNodes], S[kQuadNodes];
+#pragma unroll
+      for (int j = 0; j < kQuadNodes; j++) {
+        P[j] = om2[j] * qd;
+        eP[j] = ex * P[j];
+        S[j] = 0.0;
+      }
+      for (int b = 0; b < nb; b++) {
+        const OmegaEntryFull e = tab[b];  // same b for every lane: LDS broadcast
+        const double dl = Wl - e.w2;
+        const double inv = Al / (dl * dl + e.gl2w2);
+        const double Rl = inv * dl, Il = inv * e.glw;
+        const double vI = e.v * Il;
+        const double c1 = e.gw * Il, c2 = e.gw * Rl;
+#pragma unroll
+        for (int j = 0; j < kQuadNodes; j++) {
+          const double dd = P[j] - e.w2;
+          const double D = dd * dd + e.t;
+          if constexpr (SCREEN) {
+            const double a = dd * Rl - c1, bb = dd * Il + c2;
+            const double A = D - eP[j] * a, B = eP[j] * bb;
+            S[j] += vI * D / (A * A + B * B);
+          } else {
+            S[j] += vI / D;
+          }
         }
       }
 #pragma unroll
@@ -616,7 +728,14 @@ hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, do
                            double* lambda, hipStream_t st) {
   const int64_t nodes = n + 1;
   const unsigned blocks = (unsigned)((nodes + kQuadNodes - 1) / kQuadNodes);
-  hipLaunchKernelGGL(k_friction_raw, dim3(blocks), dim3(kQuadThreads), 0, st, s, omega, n, raw);
+  if (s.coupling)
+    hipLaunchKernelGGL(k_friction_full<true>, dim3(blocks), dim3(kQuadThreads), 0, st, s, omega, n,
+                       raw);
+  else if (s.v_l != 0.0)
+    hipLaunchKernelGGL(k_friction_full<false>, dim3(blocks), dim3(kQuadThreads), 0, st, s, omega,
+                       n, raw);
+  else
+    hipLaunchKernelGGL(k_friction_raw, dim3(blocks), dim3(kQuadThreads), 0, st, s, omega, n, raw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (n > 0)

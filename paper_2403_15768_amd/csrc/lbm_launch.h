@@ -16,6 +16,8 @@ struct SpecArgs {
   double q_max, w_max;
   double lambda_target;
   int dispersion;
+  int coupling;  // 1: screening denominator
+  double v_l;    // liquid mode dispersion
 };
 
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S

@@ -49,6 +49,7 @@ class Spectral(C.Structure):
         ("d", C.c_double), ("nq", C.c_int), ("nw", C.c_int),
         ("q_max", C.c_double), ("w_max", C.c_double),
         ("lambda_target", C.c_double), ("dispersion", C.c_int),
+        ("coupling", C.c_int), ("v_l", C.c_double),
     ]
 
 
@@ -177,6 +178,8 @@ def make_spectral(sp) -> Spectral:
     s.q_max = getattr(sp, "q_max", None) or 10.0 / sp.d
     s.w_max = getattr(sp, "w_max", None) or 20.0 * sp.T
     s.dispersion = int(getattr(sp, "dispersion", 1))
+    s.coupling = int(getattr(sp, "coupling", 0))
+    s.v_l = float(getattr(sp, "v_l", 0.0))
     return s
 
 

@@ -257,6 +257,62 @@ def test_quadrature_grids(lbm, nq, nw, disp):
     assert np.max(np.abs(lam_g / lam_o - 1)) < 1e-13
 
 
+@pytest.mark.parametrize("nq,nw,disp,coupling,v_l", [
+    (1, 1, 1, 1, 0.0), (2, 4, 0, 1, 0.5), (4, 16, 1, 0, 0.7), (7, 1500, 1, 1, 0.3),
+    (300, 64, 1, 1, 0.0), (256, 1024, 1, 1, 0.4)])
+def test_screened_quadrature_grids(lbm, nq, nw, disp, coupling, v_l):
+    # the screening denominator and the dispersive liquid mode (complex
+    # responses): same sums as the oracle up to summation order
+    say("screened quadrature", nq, nw, disp, coupling, v_l)
+    G = lbm.Channel(19, lbm.DUCT, 3, 4, 4, tau=0.7, precision="f64")
+    sp = small_spectral(nq=nq, nw=nw, seed=9)
+    sp.dispersion, sp.coupling, sp.v_l = disp, coupling, v_l
+    om = np.linspace(0.3, 4.0, G.wall_count)
+    G.set_friction_spectral(sp, om)
+    lam_g, raw_g = G.get_friction(raw=True)
+    raw_o, lam_o = oracle.friction(oracle_spectral(sp, dispersion=disp, coupling=coupling,
+                                                   v_l=v_l), om)
+    assert np.max(np.abs(raw_g[:-1] / raw_o - 1)) < 1e-12
+    assert np.max(np.abs(lam_g / lam_o - 1)) < 1e-12
+    if coupling and nq >= 32:  # the screening changes the result (a one-point
+        # grid samples q = q_max / 2, where e^{-2qd} leaves it negligible)
+        raw_u, _ = oracle.friction(oracle_spectral(sp, dispersion=disp, v_l=v_l), om)
+        assert np.max(np.abs(raw_u / raw_o - 1)) > 1e-3
+
+
+def test_screened_quadrature_full_tube_sampled(lbm):
+    # the R = 32 tube (129,024 wall nodes, 256 x 1024 points): eight nodes
+    # and the reference recomputed one by one by the oracle
+    say("screened quadrature, full tube")
+    R, nx = 32, 512
+    kw, ny, nz = tube_kw(R)
+    G = lbm.Channel(19, lbm.TUBE, nx, ny, nz, tau=0.8, precision="f32", **kw)
+    sp = inputs.draw_spectral(inputs.rng_for("tube", 0))
+    sp.coupling, sp.v_l = 1, 0.5
+    om = inputs.tube_plasmon_frequencies(G.wall_coords(), nx, R, kw["tube_cy"], kw["tube_cz"],
+                                         sp.omega0, inputs.rng_for("tube", 1))
+    G.set_friction_spectral(sp, om)
+    lam_g, raw_g = G.get_friction(raw=True)
+    osp = oracle_spectral(sp, coupling=1, v_l=0.5)
+    pick = np.random.default_rng(4).choice(G.wall_count, 8, replace=False)
+    for k in pick:
+        ref = oracle.friction_raw(osp, om[k])
+        assert abs(raw_g[k] / ref - 1) < 1e-12
+    assert abs(raw_g[-1] / oracle.friction_raw(osp, sp.omega0) - 1) < 1e-12
+    assert np.all(lam_g > 0)
+
+
+def test_screened_spectral_settings_rejected(lbm):
+    G = lbm.Channel(19, lbm.DUCT, 3, 4, 4, tau=0.7, precision="f64")
+    om = np.full(G.wall_count, 1.5)
+    for coupling, v_l in [(2, 0.0), (-1, 0.0), (1, -0.1), (1, float("nan")), (0, float("inf"))]:
+        sp = small_spectral()
+        sp.coupling, sp.v_l = coupling, v_l
+        with pytest.raises(lbm.LBMError):
+            G.set_friction_spectral(sp, om)
+    G.step(2)
+
+
 # ------------------------------------------------------------------ edge cases
 @pytest.mark.parametrize("case", ["nx1", "ragged37", "ragged100", "ny1_d2q9", "slab_d3q19",
                                   "tube_r3", "nx600"])
