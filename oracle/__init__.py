@@ -101,6 +101,9 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_friction_raw.restype = C.c_double
     lib.ora_friction.argtypes = [sp, dp, lp, dp, dp]
     lib.ora_response.argtypes = [sp, C.c_double, C.c_double, C.c_double, dp]
+    lib.ora_set_electrons.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.ora_set_electrons.restype = C.c_int
+    lib.ora_get_electrons.argtypes = [vp, dp, dp]
     lib.ora_sizeof_real.restype = C.c_int
     u64p = C.POINTER(C.c_uint64)
     lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
@@ -189,6 +192,22 @@ class Lattice:
         the stress source alone, 2 = every non-conserved direction."""
         if self._lib.ora_set_thermal(self._h, float(kT), int(mode), int(seed)) != 0:
             raise OracleError("kT must be finite and >= 0, mode 1 or 2")
+
+    def set_electrons(self, tau_e: float, rho_e0: float, gamma_e: float,
+                      force_e: float = 0.0) -> None:
+        """Electron sheets on the two slab walls, coupled to the water by the
+        relative-velocity wall drag (state reset to rest)."""
+        if self._lib.ora_set_electrons(self._h, float(tau_e), float(rho_e0), float(gamma_e),
+                                       float(force_e)) != 0:
+            raise OracleError("electron sheets need a SLAB without moving wall, tau_e > 1/2, "
+                              "rho_e0 > 0, gamma_e >= 0")
+
+    def electrons(self):
+        """(u_e of the last step [sheet][z][x], shifted populations [i][sheet][z][x])."""
+        ue = np.zeros((2, self.nz, self.nx))
+        pops = np.zeros((3, 2, self.nz, self.nx))
+        self._lib.ora_get_electrons(self._h, _dptr(ue), _dptr(pops))
+        return ue, pops
 
     def step(self, n: int) -> None:
         self._lib.ora_step(self._h, int(n))

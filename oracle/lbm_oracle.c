@@ -57,6 +57,9 @@
  * (lattice units, equipartition reads <rho u_a^2> = kT per site), step 4
  * gains a zero-mean Gaussian term xi_i; see thermal_noise() below for the two
  * forms (the paper's stress source alone, or every non-conserved direction).
+ * Electron wind (optional, SLAB): the solid's electrons as a second
+ * population set on one sheet per wall, coupled to the water by the
+ * relative-velocity drag (Sec. 3.3, Eq. 5, Eq. 27); see electron_step().
  * Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), a
  * counter-based generator, keyed by the seed and counted by (cell, step,
  * block), with Box-Muller (1958) normals.
@@ -68,7 +71,8 @@
  * form of the q integral and an adaptive integrator; thermal noise pinned by
  * numpy's Philox4x64-10, the normal distribution, exact conservation, the
  * paper's stress form and the stationarity of the equilibrium Gaussian
- * measure (see tests/).
+ * measure; electron wind pinned by exact per-step momentum bookkeeping and
+ * exact coupled steady states (see tests/).
  */
 #include <math.h>
 #include <stdint.h>
@@ -127,6 +131,12 @@ typedef struct {
   double kT;     /* lattice temperature; 0 = no fluctuations */
   int noise;     /* 1 = stress directions only, 2 = all non-conserved */
   uint64_t seed; /* key of the thermal random numbers */
+  /* electron sheets (SLAB only): one solid row below y = 0 (sheet 0) and
+   * one above y = ny - 1 (sheet 1), electron lines along x, D1Q3 */
+  int elec;
+  double tau_e, rho_e0, gamma_e, force_e;
+  real *e, *en; /* shifted populations [i][sheet][z][x], i = 0, +x, -x */
+  real *ue;     /* electron velocity of the last step, [sheet][z][x] */
 } ora_ctx;
 
 /* ---------------------------------------------------------------- lattice */
@@ -180,6 +190,11 @@ static void set_lattice(ora_ctx *o) {
 
 static long cell(const ora_ctx *o, int x, int y, int z) {
   return (long)x + (long)o->p.nx * ((long)y + (long)o->p.ny * (long)z);
+}
+
+/* electron sheet node: sheet b (0 below y = 0, 1 above y = ny - 1), z, x */
+static long sheet_node(const ora_ctx *o, int b, int z, int x) {
+  return ((long)b * o->p.nz + z) * o->p.nx + x;
 }
 
 /* Is the lattice point (x, y, z) -- already wrapped in the periodic
@@ -277,6 +292,9 @@ int ora_create(const ora_params *p, ora_ctx **out) {
 
 void ora_destroy(ora_ctx *o) {
   if (!o) return;
+  free(o->e);
+  free(o->en);
+  free(o->ue);
   free(o->fluid);
   free(o->wall_id);
   free(o->r);
@@ -368,6 +386,13 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
      * population and this node's own outgoing population i */
     bb = g[(long)ib * o->ncell + n] / (2 * qv) +
          (2 * qv - 1) / (2 * qv) * g[(long)i * o->ncell + n];
+  }
+  if (o->elec && o->c[i][0] != 0) {
+    /* the wall moves with the electrons of the solid point x - c_i */
+    int xs = ((x - o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
+    int zs = ((z - o->c[i][2]) % o->p.nz + o->p.nz) % o->p.nz;
+    bb += 6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
+          o->ue[sheet_node(o, sy < 0 ? 0 : 1, zs, xs)];
   }
   return o->r[n] * bb + (1 - o->r[n]) * g[(long)o->sig[i] * o->ncell + n];
 }
@@ -538,6 +563,111 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
   }
 }
 
+/* ------------------------------------------------------ electron wind */
+
+/* The solid's electrons as a second population set (Sec. 3.3, Sec. 4: one
+ * set of distributions per species), coupled to the water by the
+ * relative-velocity drag of Eq. 5 / Eq. 27 (F_kl = -F_lk): the bounce-back
+ * half of the wall rule reflects off a wall moving with the electrons, and
+ * the electrons take back exactly the axial momentum the water gains there.
+ *
+ * Each SLAB wall carries one sheet of electron lines along x (the flow axis;
+ * transverse transport in the sheet is not modelled), D1Q3 (c = 0, +1, -1,
+ * w = 2/3, 1/6, 1/6), periodic in x; BGK with tau_e around rho_e0, Guo
+ * forcing with F = force_e (the field drive) + F_wall - gamma_e rho u_e
+ * (drag on the lattice, Eq. 13's F^{fr,eC}).  The interface rules of
+ * Eqs. 22-24 keep the electrons in the solid: here they never leave their
+ * line.  Requires wall_velocity_top == 0.  Off after creation. */
+int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
+                      double force_e) {
+  long n = 2L * o->p.nz * o->p.nx;
+  if (o->p.geometry != ORA_SLAB || o->p.wall_velocity_top != 0.0)
+    return ORA_EINVAL;
+  if (!(tau_e > 0.5) || !(rho_e0 > 0) || !(gamma_e >= 0) || !isfinite(force_e) ||
+      !isfinite(tau_e) || !isfinite(rho_e0) || !isfinite(gamma_e))
+    return ORA_EINVAL;
+  if (!o->e) {
+    o->e = (real *)calloc(3 * n, sizeof(real));
+    o->en = (real *)calloc(3 * n, sizeof(real));
+    o->ue = (real *)calloc(n, sizeof(real));
+    if (!o->e || !o->en || !o->ue) return ORA_ENOMEM;
+  }
+  memset(o->e, 0, 3 * n * sizeof(real));
+  memset(o->ue, 0, n * sizeof(real));
+  o->elec = 1;
+  o->tau_e = tau_e;
+  o->rho_e0 = rho_e0;
+  o->gamma_e = gamma_e;
+  o->force_e = force_e;
+  return ORA_OK;
+}
+
+/* One electron step from the water state g (both at step n).  Per sheet
+ * node s, the water links that leave s and land on a fluid node x_f = s + c_k
+ * with c_kx != 0 carry the axial exchange: the water at x_f gains
+ *   r(x_f) (2 g_opp(k)(x_f) + 6 w_k rho0 c_kx u_e(s)) c_kx
+ * (its wall rule; the free-slip half exchanges no axial momentum), so
+ *   F_wall(s) = F0 - K u_e,  F0 = -sum 2 r g_opp(k) c_kx,  K = 6 rho0 sum r w_k.
+ * With the drag and Guo's half-force the velocity solves
+ *   rho u = j + (force_e + F0 - K u - gamma rho u) / 2. */
+static void electron_step(ora_ctx *o) {
+  const int cd[3] = {0, 1, -1};
+  const real wd[3] = {(real)2 / 3, (real)1 / 6, (real)1 / 6};
+  int b, z, x, i, k;
+  real tau = (real)o->tau_e, gam = (real)o->gamma_e;
+  long n = 2L * o->p.nz * o->p.nx;
+  for (b = 0; b < 2; b++)
+    for (z = 0; z < o->p.nz; z++)
+      for (x = 0; x < o->p.nx; x++) {
+        long s = sheet_node(o, b, z, x);
+        real de[3], drho = 0, j = 0, rho, u, F0 = 0, K = 0, F;
+        int yf = b == 0 ? 0 : o->p.ny - 1, cy = b == 0 ? 1 : -1;
+        for (i = 0; i < 3; i++) {
+          int xs = ((x - cd[i]) % o->p.nx + o->p.nx) % o->p.nx;
+          de[i] = o->e[(long)i * n + sheet_node(o, b, z, xs)];
+          drho += de[i];
+          j += de[i] * (real)cd[i];
+        }
+        rho = (real)o->rho_e0 + drho;
+        for (k = 0; k < o->q; k++) {
+          long cf;
+          int xf;
+          if (o->c[k][1] != cy || o->c[k][0] == 0) continue;
+          xf = ((x + o->c[k][0]) % o->p.nx + o->p.nx) % o->p.nx;
+          cf = cell(o, xf, yf, ((z + o->c[k][2]) % o->p.nz + o->p.nz) % o->p.nz);
+          F0 -= 2 * o->r[cf] * o->g[(long)o->opp[k] * o->ncell + cf] * (real)o->c[k][0];
+          K += 6 * (real)o->p.rho0 * o->r[cf] * o->w[k];
+        }
+        u = (j + ((real)o->force_e + F0) / 2) / (rho * (1 + gam / 2) + K / 2);
+        F = (real)o->force_e + F0 - K * u - gam * rho * u;
+        for (i = 0; i < 3; i++) {
+          real c = (real)cd[i];
+          real eq = wd[i] * (drho + rho * (3 * c * u + (real)4.5 * c * c * u * u -
+                                           (real)1.5 * u * u));
+          real src = (1 - 1 / (2 * tau)) * wd[i] * (3 * (c - u) + 9 * c * u * c) * F;
+          o->en[(long)i * n + s] = de[i] - (de[i] - eq) / tau + src;
+        }
+        o->ue[s] = u;
+      }
+  {
+    real *t = o->e;
+    o->e = o->en;
+    o->en = t;
+  }
+}
+
+/* electron velocity of the last step and the shifted populations
+ * [i][sheet][z][x] of the current state (either may be NULL) */
+void ora_get_electrons(const ora_ctx *o, double *ue, double *pops) {
+  long k, n = 2L * o->p.nz * o->p.nx;
+  if (!o->e) return;
+  for (k = 0; k < n; k++) {
+    if (ue) ue[k] = (double)o->ue[k];
+  }
+  if (pops)
+    for (k = 0; k < 3 * n; k++) pops[k] = (double)o->e[k];
+}
+
 void ora_step(ora_ctx *o, long nsteps) {
   long s;
   int x, y, z, i, a;
@@ -545,6 +675,7 @@ void ora_step(ora_ctx *o, long nsteps) {
   real F[3];
   for (a = 0; a < 3; a++) F[a] = (real)o->p.force[a];
   for (s = 0; s < nsteps; s++) {
+    if (o->elec) electron_step(o); /* reads g at step n, sets u_e of step n */
     for (z = 0; z < o->p.nz; z++)
       for (y = 0; y < o->p.ny; y++)
         for (x = 0; x < o->p.nx; x++) {

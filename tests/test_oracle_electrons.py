@@ -1,0 +1,131 @@
+"""Pins of the oracle's electron wind (no GPU).
+
+The solid's electrons form a second population set (Sec. 3.3; Sec. 4: one set
+of distributions per species) coupled to the water by the relative-velocity
+drag of Eq. 5 / Eq. 27 (F_kl = -F_lk).  Pins:
+
+* exact momentum bookkeeping: over any single step, water plus electron axial
+  momentum changes by exactly the external forces minus the electrons' drag
+  on the lattice -- a wrong sign or weight in the reaction force breaks it;
+* exact steady states: total momentum balance fixes the electron velocity
+  U_e = (F_h N_h + F_e N_e) / (gamma rho_e0 N_e), and the water is the exact
+  discrete slip-Poiseuille profile shifted by U_e (a wall moving with the
+  electrons) -- pressure-driven water dragging the electrons along, the field
+  drive ("electron wind") pulling the water, and the two opposed;
+* electron mass conserved line by line; settings outside the model rejected.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import SLAB, Lattice
+from test_oracle_lb import poiseuille_exact
+
+C9X = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+C19X = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0])
+
+
+def axial_momentum(L, q):
+    """(water sum g_i c_ix over the box, electron sum e_i c_i) of the current
+    state; solid cells hold zeros."""
+    cx = C9X if q == 9 else C19X
+    g = L.get_populations()
+    _, pops = L.electrons()
+    return float(np.tensordot(cx, g, axes=(0, 0)).sum()), float((pops[1] - pops[2]).sum())
+
+
+@pytest.mark.parametrize("q,shape", [(9, (16, 12, 1)), (19, (10, 8, 5))])
+def test_momentum_balance_is_exact_every_step(q, shape):
+    nx, ny, nz = shape
+    fh, fe, gam, rho_e = 2e-6, -1.5e-6, 0.03, 0.7
+    L = Lattice(q, SLAB, nx, ny, nz, tau=0.75, force=(fh, 0, 0))
+    rng = np.random.default_rng(2)
+    L.set_friction(rng.uniform(0.0, 0.3, L.wall_count))
+    L.set_electrons(0.85, rho_e, gam, fe)
+    L.step(37)  # a transient state
+    for _ in range(3):
+        w0, e0 = axial_momentum(L, q)
+        _, pops = L.electrons()
+        # electron density each node sees in the next step (pulled along x)
+        rho = rho_e + pops[0] + np.roll(pops[1], 1, axis=-1) + np.roll(pops[2], -1, axis=-1)
+        L.step(1)
+        w1, e1 = axial_momentum(L, q)
+        ue, _ = L.electrons()
+        expect = fh * L.fluid_count + fe * 2 * nx * nz - gam * float((rho * ue).sum())
+        assert abs((w1 + e1) - (w0 + e0) - expect) < 1e-15 * (abs(w0) + abs(e0) + 1e-3)
+        # and the exchange is not trivially zero: each side alone is off
+        assert abs((w1 - w0) - fh * L.fluid_count) > 1e-9
+
+
+@pytest.mark.parametrize("fh,fe", [(1e-6, 0.0), (0.0, 2e-6), (1e-6, -3e-6)])
+def test_steady_state_d2q9_exact(fh, fe):
+    H, tau, lam = 30, 0.8, 0.05
+    rho_e, gam = 2.0, 0.2
+    L = Lattice(9, SLAB, 4, H, 1, tau=tau, force=(fh, 0, 0))
+    L.set_friction(lam)
+    L.set_electrons(0.9, rho_e, gam, fe)
+    L.step(45000)  # slowest coupled mode decays over ~1,200 steps
+    Ue = (fh * H + fe * 2) / (gam * rho_e * 2)
+    ue, pops = L.electrons()
+    assert np.abs(ue / Ue - 1).max() < 1e-10
+    rho, ux, uy, _ = L.fields()
+    exp = (poiseuille_exact(H, tau, fh, lam) if fh else np.zeros(H)) + Ue
+    for x in range(4):
+        assert np.abs(ux[0, :, x] - exp).max() < 1e-10 * np.abs(exp).max()
+    assert np.abs(uy).max() < 1e-15
+    # the sign of the coupling: water dragged along by field-driven electrons
+    if fh == 0.0:
+        assert ux.min() > 0
+
+
+def test_steady_state_d3q19_slab_exact():
+    H, nz, tau, lam, fh = 16, 3, 0.7, 0.1, 1e-6
+    rho_e, gam, fe = 1.5, 0.08, 5e-7
+    L = Lattice(19, SLAB, 2, H, nz, tau=tau, force=(fh, 0, 0))
+    L.set_friction(lam)
+    L.set_electrons(0.8, rho_e, gam, fe)
+    L.step(30000)
+    Ue = (fh * H * nz + fe * 2 * nz) / (gam * rho_e * 2 * nz)
+    ue, _ = L.electrons()
+    assert np.abs(ue / Ue - 1).max() < 1e-10
+    _, ux, _, uz = L.fields()
+    exp = poiseuille_exact(H, tau, fh, lam) + Ue
+    assert np.abs(ux[:, :, :] - exp[None, :, None]).max() < 1e-10 * exp.max()
+    assert np.abs(uz).max() < 1e-15
+
+
+def test_electron_mass_conserved_per_line():
+    L = Lattice(9, SLAB, 20, 10, 1, tau=0.7, force=(1e-6, 0, 0))
+    L.set_friction(np.random.default_rng(1).uniform(0, 0.2, L.wall_count))
+    L.set_electrons(1.1, 0.4, 0.02, 1e-6)
+    L.step(500)
+    _, pops = L.electrons()
+    assert np.abs(pops.sum(axis=(0, 3))).max() < 1e-16
+
+
+def test_immovable_electrons_give_walls_at_rest():
+    # the heavier the sheets, the less they move: the water then approaches
+    # the flow between walls at rest, the difference falling as 1 / rho_e0
+    def run(rho_e):
+        L = Lattice(9, SLAB, 12, 8, 1, tau=0.8, force=(1e-6, 0, 0))
+        L.set_friction(0.07)
+        if rho_e:
+            L.set_electrons(0.9, rho_e, 1.0, 0.0)
+        L.step(400)
+        return L.fields()[1]
+    rest = run(0)
+    d = [np.abs(run(r) - rest).max() / np.abs(rest).max() for r in (1e3, 1e6)]
+    assert 1e-6 < d[0] < 1e-4
+    assert abs(d[1] / d[0] * 1e3 - 1) < 0.01
+
+
+def test_electron_settings_rejected():
+    for geom, kw in [(oracle.DUCT, {}), (SLAB, {"wall_velocity_top": 1e-3})]:
+        L = Lattice(19, geom, 4, 4, 4, tau=0.8, **kw)
+        with pytest.raises(oracle.OracleError):
+            L.set_electrons(0.8, 1.0, 0.1, 0.0)
+    L = Lattice(9, SLAB, 4, 4, 1, tau=0.8)
+    for args in [(0.5, 1.0, 0.1, 0.0), (0.8, 0.0, 0.1, 0.0), (0.8, 1.0, -0.1, 0.0),
+                 (0.8, 1.0, 0.1, float("nan"))]:
+        with pytest.raises(oracle.OracleError):
+            L.set_electrons(*args)
