@@ -168,6 +168,22 @@ def extras(torch, lbm, inputs, args):
                            "hbm_frac_fluid_bytes": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
                                                          / HBM_PEAK_GBS, 4)}
     tb.close()
+    # the slab with electron sheets on both walls (electron wind): water step
+    # plus the sheets' step, against the same slab without them
+    nx, ny, nz = DUCT
+    for name, elec in (("slab_f32", False), ("slab_f32_electrons", True)):
+        ch = lbm.Channel(lbm.D3Q19, lbm.SLAB, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
+                         precision="f32")
+        ch.set_friction(0.05)
+        if elec:
+            ch.set_electrons(0.9, 1.0, 0.05, 1e-6)
+        ch.step(200)
+        wall, kms = timed_run(torch, ch, 2000, 1000)
+        cells = ch.fluid_count
+        out[name] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                     "step_us": round(kms * 1e3 / 2000, 2),
+                     "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
+        ch.close()
     # the fluctuating update (thermal noise, kT = 1e-6) on the FP32 duct,
     # both noise forms
     for mode, name in ((1, "stress"), (2, "all")):

@@ -204,6 +204,20 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     }
   }
 
+  if (p->geometry == LBM_SLAB) {
+    pl.nsheet = 2LL * pl.nz * pl.nx;
+    pl.sheet_wc.assign(2 * (size_t)pl.nz, -1);
+    for (int b = 0; b < 2; b++)
+      for (int z = 0; z < pl.nz; z++) {
+        const int64_t col = (int64_t)(b == 0 ? 0 : pl.ny - 1) + (int64_t)pl.ny * z;
+        pl.sheet_wc[(size_t)b * pl.nz + z] = pl.colinfo[col].wallcol;
+        if (pl.colinfo[col].wallcol < 0) {
+          if (err) *err = "internal: slab wall row without wall links";
+          return LBM_EINVAL;
+        }
+      }
+  }
+
   size_t off = 0;
   pl.pop_bytes = (size_t)pl.ncolbox * pl.sC * pl.ssize;
   auto take = [&](size_t bytes) {
@@ -222,6 +236,10 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_out = take(4 * sizeof(double));
   pl.off_flag = take(4 * sizeof(int));
   pl.off_step = take(sizeof(int64_t));
+  pl.off_e[0] = take((size_t)pl.nsheet * 3 * sizeof(double));
+  pl.off_e[1] = take((size_t)pl.nsheet * 3 * sizeof(double));
+  pl.off_ue = take((size_t)pl.nsheet * sizeof(double));
+  pl.off_swc = take(pl.sheet_wc.size() * sizeof(int32_t));
   pl.total = off;
   return LBM_OK;
 }
@@ -274,6 +292,7 @@ void fill_args(lbm_ctx* c) {
   a.th_amp = 0.0;
   a.th_mode = 0;
   a.th_seed = 0;
+  a.ue = nullptr;
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -303,6 +322,11 @@ lbm_status lbm_host::launch_one_step(lbm_ctx* c) {
   StepArgs a = c->args;
   a.step_off = c->step;  // plain launch: the step travels as an argument
   a.rev = c->cur;
+  if (c->elec)  // the electrons of step n first: the water step reads their velocity
+    HIPCHK(c, lbm::launch_electron_step(c->pl.Q, c->pl.prec, c->pop[c->cur],
+                                        c->at<double>(c->pl.off_e[c->cur]),
+                                        c->at<double>(c->pl.off_e[1 - c->cur]),
+                                        c->at<double>(c->pl.off_ue), c->ea, c->stream));
   HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
                              c->pl.bouz, c->stream));
   c->cur = 1 - c->cur;
@@ -316,7 +340,13 @@ namespace {
 lbm_status build_graph(lbm_ctx* c, int parity) {
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
-  const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode);
+  const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode,
+                                        c->elec);
+  const void* fe = c->elec ? lbm::electron_kernel_ptr(c->pl.Q, c->pl.prec) : nullptr;
+  const double* esrc[2] = {c->at<double>(c->pl.off_e[parity]), c->at<double>(c->pl.off_e[1 - parity])};
+  double* edst[2] = {c->at<double>(c->pl.off_e[1 - parity]), c->at<double>(c->pl.off_e[parity])};
+  double* uep = c->at<double>(c->pl.off_ue);
+  lbm::ElecArgs eargs = c->ea;
   hipGraphNode_t prev = nullptr;
   // kernel arguments must outlive instantiation only; keep them on the stack
   const void* srcs[2] = {c->pop[parity], c->pop[1 - parity]};
@@ -329,6 +359,22 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
     args[k].dstep = dstep;
     args[k].step_off = k;
     args[k].rev = (parity + k) & 1;
+    if (fe) {  // the electron step of step k, before the water step that reads u_e
+      void* eargv[5] = {(void*)&srcs[k & 1], (void*)&esrc[k & 1], (void*)&edst[k & 1], (void*)&uep,
+                        (void*)&eargs};
+      hipKernelNodeParams ep{};
+      ep.func = const_cast<void*>(fe);
+      ep.gridDim = dim3((unsigned)((c->pl.nsheet + 255) / 256));
+      ep.blockDim = dim3(256);
+      ep.kernelParams = eargv;
+      hipGraphNode_t enode = nullptr;
+      hipError_t e = hipGraphAddKernelNode(&enode, g, prev ? &prev : nullptr, prev ? 1 : 0, &ep);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return c->hip(e, "hipGraphAddKernelNode");
+      }
+      prev = enode;
+    }
     void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&args[k]};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
@@ -459,6 +505,9 @@ lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void
   do {
     if ((st = c->hip(hipMemsetAsync(c->arena, 0, pl.total, c->stream), "hipMemsetAsync")) != LBM_OK) break;
     if ((st = upload(c, pl.off_slots, pl.slots.data(), pl.slots.size() * sizeof(lbm::ColSlot))) != LBM_OK) break;
+    if (!pl.sheet_wc.empty() &&
+        (st = upload(c, pl.off_swc, pl.sheet_wc.data(), pl.sheet_wc.size() * sizeof(int32_t))) != LBM_OK)
+      break;
     std::vector<double> inf(pl.nwall, INFINITY);
     std::vector<double> ones(pl.nwall, 1.0);
     if ((st = upload(c, pl.off_lambda, inf.data(), inf.size() * sizeof(double))) != LBM_OK) break;
@@ -624,6 +673,64 @@ lbm_status lbm_set_thermal(lbm_ctx* c, double kT, int mode, uint64_t seed) {
   c->args.th_seed = seed;
   c->kT = kT;
   return LBM_OK;
+}
+
+lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gamma_e,
+                             double force_e) {
+  if (!c) return LBM_EINVAL;
+  const bool on = tau_e != 0.0;
+  if (on) {
+    if (c->p.geometry != LBM_SLAB || c->p.wall_velocity_top != 0.0)
+      return c->fail(LBM_EINVAL, "electron sheets need a SLAB without a moving wall");
+    if (!(tau_e > 0.5) || !(rho_e0 > 0.0) || !(gamma_e >= 0.0) || !std::isfinite(tau_e) ||
+        !std::isfinite(rho_e0) || !std::isfinite(gamma_e) || !std::isfinite(force_e))
+      return c->fail(LBM_EINVAL, "need tau_e > 1/2, rho_e0 > 0, gamma_e >= 0, finite values");
+  }
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 2; k++) {  // the step graphs hold the kernels and their arguments
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+  c->elec = on;
+  c->args.ue = on ? c->at<double>(c->pl.off_ue) : nullptr;
+  if (!on) return LBM_OK;
+  const Plan& pl = c->pl;
+  lbm::ElecArgs& ea = c->ea;
+  ea.nx = pl.nx;
+  ea.ny = pl.ny;
+  ea.nz = pl.nz;
+  ea.sI = pl.sI;
+  ea.sC = pl.sC;
+  ea.rwall = c->at<void>(pl.off_r);
+  ea.swc = c->at<int32_t>(pl.off_swc);
+  ea.rho0 = c->p.rho0;
+  ea.omega_e = 1.0 / tau_e;
+  ea.rho_e0 = rho_e0;
+  ea.gamma_e = gamma_e;
+  ea.force_e = force_e;
+  // electrons at rest
+  for (int k = 0; k < 2; k++)
+    HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_e[k]), 0, (size_t)pl.nsheet * 3 * sizeof(double),
+                             c->stream));
+  HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_ue), 0, (size_t)pl.nsheet * sizeof(double), c->stream));
+  return sync(c);
+}
+
+lbm_status lbm_get_electrons(lbm_ctx* c, double* ue, double* pops) {
+  if (!c) return LBM_EINVAL;
+  if (!c->elec) return c->fail(LBM_ESTATE, "electron sheets are off");
+  const Plan& pl = c->pl;
+  if (ue)
+    HIPCHK(c, hipMemcpyAsync(ue, c->at<double>(pl.off_ue), (size_t)pl.nsheet * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  if (pops)
+    HIPCHK(c, hipMemcpyAsync(pops, c->at<double>(pl.off_e[c->cur]),
+                             (size_t)pl.nsheet * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  return sync(c);
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {

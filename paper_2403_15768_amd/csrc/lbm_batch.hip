@@ -233,7 +233,8 @@ lbm_status check_members(lbm_ctx* const* ctxs, int n) {
     if (a.lattice != b.lattice || a.precision != b.precision ||
         (a.geometry == LBM_TUBE) != (b.geometry == LBM_TUBE))
       return LBM_EINVAL;
-    if (ctxs[m]->args.th_mode != 0) return LBM_EINVAL;  // the batch kernel has no noise
+    // the batch kernel has no noise and no electron sheets
+    if (ctxs[m]->args.th_mode != 0 || ctxs[m]->elec) return LBM_EINVAL;
   }
   return LBM_OK;
 }
@@ -607,8 +608,9 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
   for (lbm_ctx* c : b->m)
-    if (c->args.th_mode != 0) {
-      b->err = "a member has thermal noise switched on; batches step without it";
+    if (c->args.th_mode != 0 || c->elec) {
+      b->err = "a member has thermal noise or electron sheets switched on; batches step "
+               "without them";
       return LBM_EINVAL;
     }
   lbm_status rs = resync(b);

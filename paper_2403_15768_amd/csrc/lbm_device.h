@@ -102,6 +102,9 @@ struct StepArgs {
   double th_amp;
   int th_mode;
   uint64_t th_seed;
+  // electron sheets (slab walls): x velocity of each sheet node in the step
+  // being taken, [sheet][z][x] (sheet 0 below y = 0, 1 above y = ny - 1)
+  const double* ue;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
@@ -290,7 +293,12 @@ __device__ __forceinline__ int64_t src_off(const StepArgs& a, int i, int z, bool
 // dl (interior columns only) is added to every lane index: a lane working on
 // column col + k takes the lines of column col shifted by dl = k sC, which is
 // the same shift for every source column away from periodic wrap in z.
-template <class L, typename S, typename M, typename W, bool BOUZ>
+//
+// With ELEC (slab walls with electron sheets) the bounce-back half reflects
+// off a wall moving with the electrons of the solid point x - c_i:
+//   BB_i = g_opp(i)(x) + 6 w_i rho0 c_ix u_e(x - c_i)
+// (wall links with c_ix != 0 have c_iz = 0 in a slab).
+template <class L, typename S, typename M, typename W, bool BOUZ, bool ELEC = false>
 __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs& a, int col,
                                        int x, ColInfo info, M* df, unsigned dl = 0u) {
   const LBM_GLOBAL S* g = gbl(g0);
@@ -351,6 +359,11 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
       continue;
     }
     M bb = gb;
+    if (ELEC && L::cx[i] != 0) {
+      const int64_t sn = ((int64_t)(L::cy[i] > 0 ? 0 : 1) * a.nz + z) * a.nx +
+                         (L::cx[i] > 0 ? xm : xp);
+      bb += static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i]) * static_cast<M>(gbl(a.ue)[sn]);
+    }
     if (BOUZ) {
       const M cb = static_cast<M>(cw[2 * i]), cc = static_cast<M>(cw[2 * i + 1]);
       if (cb != M(0)) bb += cb * (dec<S, M>(pv[i]) - gb);

@@ -36,10 +36,13 @@ struct Plan {
   int bx = 0, segs = 0;
   int64_t nblocks = 0;
   bool bouz = false;
+  int64_t nsheet = 0;               // electron sheet nodes (SLAB: 2 nz nx; else 0)
+  std::vector<int32_t> sheet_wc;    // [sheet][z]: wall column next to the sheet
   // arena offsets
   size_t off_pop[2] = {0, 0}, pop_bytes = 0;
   size_t off_slots = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
          off_partials = 0, off_out = 0, off_flag = 0, off_step = 0, total = 0;
+  size_t off_e[2] = {0, 0}, off_ue = 0, off_swc = 0;  // electron sheets
 };
 
 }  // namespace lbm_host
@@ -60,6 +63,8 @@ struct lbm_ctx {
   bool graphs_ok = true;
   int64_t dstep_value = 0;  // value the device step base holds after enqueued work
   double kT = 0.0;          // lattice temperature of the thermal noise (0: none)
+  bool elec = false;        // electron sheets on (SLAB)
+  lbm::ElecArgs ea{};
 
   template <typename T>
   T* at(size_t off) const {

@@ -30,7 +30,7 @@
 namespace lbm {
 
 // ------------------------------------------------------------ stream-collide
-template <class L, typename S, typename M, bool BOUZ, int TH>
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC = false>
 __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                               StepArgs a) {
   // grid (fluid columns, segments per x-line).  Wall columns go first (their
@@ -59,9 +59,64 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   M xi[L::Q];
   if constexpr (TH != 0)
     thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
-  gather<L, S, M, M, BOUZ>(src, a, col, xc, info, df);
+  gather<L, S, M, M, BOUZ, ELEC>(src, a, col, xc, info, df);
   collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
                                 (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+}
+
+// ------------------------------------------------------------ electron sheets
+// One electron step per sheet node (lines along x, D1Q3: c = 0, +1, -1,
+// w = 2/3, 1/6, 1/6, shifted populations [i][sheet][z][x] in double):
+//   pull along the line (periodic); the water links from this node to the
+//   fluid row (c_ky towards the water, c_kx != 0) give the axial force the
+//   water's wall rule takes from the sheet, F_wall = F0 - K u,
+//     F0 = -sum 2 r g_opp(k)(x + c_kx) c_kx,  K = 6 rho0 sum r w_k;
+//   with the field force and the drag -gamma rho u, Guo's half-force makes
+//     rho u = j + (force + F0 - K u - gamma rho u) / 2
+//   linear in u; then BGK + Guo with F = force + F0 - K u - gamma rho u.
+template <class L, typename S, typename W>
+__global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
+                                                       const double* __restrict__ es,
+                                                       double* __restrict__ ed,
+                                                       double* __restrict__ ue, ElecArgs ea) {
+  const int64_t n = 2LL * ea.nz * ea.nx;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t bz = s / ea.nx;  // sheet * nz + z
+  const int x = (int)(s - bz * ea.nx);
+  const int b = (int)(bz / ea.nz), z = (int)(bz - (int64_t)b * ea.nz);
+  const int64_t line = bz * ea.nx;
+  const int xm = x == 0 ? ea.nx - 1 : x - 1, xp = x == ea.nx - 1 ? 0 : x + 1;
+  const double d0 = es[s], d1 = es[n + line + xm], d2 = es[2 * n + line + xp];
+  const double drho = d0 + d1 + d2, j = d1 - d2;
+  const double rho = ea.rho_e0 + drho;
+  const int cy = b == 0 ? 1 : -1;
+  const int64_t col = (int64_t)(b == 0 ? 0 : ea.ny - 1) + (int64_t)ea.ny * z;
+  const LBM_GLOBAL W* rw = gbl(static_cast<const W*>(ea.rwall)) + (int64_t)ea.swc[bz] * ea.nx;
+  double F0 = 0.0, K = 0.0;
+#pragma unroll
+  for (int k = 0; k < L::Q; k++) {
+    if (L::cx[k] == 0 || L::cy[k] == 0) continue;
+    if (L::cy[k] != cy) continue;
+    const int xf = L::cx[k] > 0 ? xp : xm;
+    const double r = static_cast<double>(rw[xf]);
+    const double go = dec<S, double>(gbl(g)[col * ea.sC + L::row[L::opp[k]] * ea.sI + xf]);
+    F0 -= 2.0 * r * go * L::cx[k];
+    K += 6.0 * ea.rho0 * r * L::w[k];
+  }
+  const double gam = ea.gamma_e;
+  const double u = (j + 0.5 * (ea.force_e + F0)) / (rho * (1.0 + 0.5 * gam) + 0.5 * K);
+  const double F = ea.force_e + F0 - K * u - gam * rho * u;
+  const double om = ea.omega_e, A = 1.0 - 0.5 * om;
+  const double d[3] = {d0, d1, d2};
+  const double c[3] = {0.0, 1.0, -1.0}, w[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    const double eq = w[i] * (drho + rho * (3.0 * c[i] * u + 4.5 * c[i] * c[i] * u * u - 1.5 * u * u));
+    const double src = A * w[i] * (3.0 * (c[i] - u) + 9.0 * c[i] * u * c[i]) * F;
+    ed[i * n + s] = d[i] - om * (d[i] - eq) + src;
+  }
+  ue[s] = u;
 }
 
 // ------------------------------------------------------------ moments
@@ -71,7 +126,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <class L, typename S, typename W, bool BOUZ>
+template <class L, typename S, typename W, bool BOUZ, bool ELEC = false>
 __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, StepArgs a,
                                                  int which, double* __restrict__ field,
                                                  double* __restrict__ partials) {
@@ -87,7 +142,8 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
     info.wallcol = uniform(cs.wallcol);
     info.mask = (uint32_t)uniform((int)cs.mask);
     double df[L::Q];
-    gather<L, S, double, W, BOUZ>(src, a, col, x, info, df);
+    // with electron sheets the wall moves with u_e of the last step
+    gather<L, S, double, W, BOUZ, ELEC>(src, a, col, x, info, df);
     double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
@@ -646,7 +702,12 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 
 // the step kernel for a wall kind and a noise form (0: none)
 template <class L, typename S, typename M>
-static const void* step_kernel_t(bool bouz, int th_mode) {
+static const void* step_kernel_t(bool bouz, int th_mode, bool elec) {
+  if (elec) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 1, true>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 2, true>);
+    return reinterpret_cast<const void*>(&k_step<L, S, M, false, 0, true>);
+  }
   if (bouz) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 1>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 2>);
@@ -665,7 +726,8 @@ static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, b
   S* d = static_cast<S*>(dst);
   StepArgs args = a;
   void* kargs[3] = {(void*)&s, (void*)&d, (void*)&args};
-  return hipLaunchKernel(step_kernel_t<L, S, M>(bouz, a.th_mode), grid, block, kargs, 0, st);
+  return hipLaunchKernel(step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr), grid, block,
+                         kargs, 0, st);
 }
 
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
@@ -680,8 +742,8 @@ hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepAr
   return launch_step_t<D3Q19, _Float16, float>(src, dst, a, bouz, st);
 }
 
-const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode) {
-#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode)
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec) {
+#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec)
   if (q == 9) {
     if (prec == 0) return KP(D2Q9, double, double);
     if (prec == 1) return KP(D2Q9, float, double);
@@ -693,6 +755,27 @@ const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode) {
 #undef KP
 }
 
+const void* electron_kernel_ptr(int q, int prec) {
+  if (q == 9) {
+    if (prec == 0) return reinterpret_cast<const void*>(&k_electron_step<D2Q9, double, double>);
+    if (prec == 1) return reinterpret_cast<const void*>(&k_electron_step<D2Q9, float, double>);
+    return reinterpret_cast<const void*>(&k_electron_step<D2Q9, _Float16, float>);
+  }
+  if (prec == 0) return reinterpret_cast<const void*>(&k_electron_step<D3Q19, double, double>);
+  if (prec == 1) return reinterpret_cast<const void*>(&k_electron_step<D3Q19, float, double>);
+  return reinterpret_cast<const void*>(&k_electron_step<D3Q19, _Float16, float>);
+}
+
+hipError_t launch_electron_step(int q, int prec, const void* g, const double* e_src,
+                                double* e_dst, double* ue, const ElecArgs& ea, hipStream_t st) {
+  const int64_t n = 2LL * ea.nz * ea.nx;
+  if (n <= 0 || (n + 255) / 256 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  ElecArgs args = ea;
+  void* kargs[5] = {(void*)&g, (void*)&e_src, (void*)&e_dst, (void*)&ue, (void*)&args};
+  return hipLaunchKernel(electron_kernel_ptr(q, prec), dim3((unsigned)((n + 255) / 256)), dim3(256),
+                         kargs, 0, st);
+}
+
 template <class L, typename S, typename W>
 static hipError_t launch_moments_t(const void* src, const StepArgs& a, bool bouz, int which,
                                    double* field, double* partials, hipStream_t st) {
@@ -700,6 +783,9 @@ static hipError_t launch_moments_t(const void* src, const StepArgs& a, bool bouz
   if (bouz)
     hipLaunchKernelGGL((k_moments<L, S, W, true>), grid, block, 0, st, (const S*)src, a, which,
                        field, partials);
+  else if (a.ue)
+    hipLaunchKernelGGL((k_moments<L, S, W, false, true>), grid, block, 0, st, (const S*)src, a,
+                       which, field, partials);
   else
     hipLaunchKernelGGL((k_moments<L, S, W, false>), grid, block, 0, st, (const S*)src, a, which,
                        field, partials);

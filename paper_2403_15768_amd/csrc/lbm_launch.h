@@ -20,10 +20,25 @@ struct SpecArgs {
   double v_l;    // liquid mode dispersion
 };
 
+// Electron sheets of a slab (one per wall, lines along x, D1Q3)
+struct ElecArgs {
+  int nx, ny, nz;
+  int64_t sI, sC;        // water layout
+  const void* rwall;     // water wall weights r [wallcol][nx] (double, float for F16S)
+  const int32_t* swc;    // [sheet][z]: wall column of the water row next to the sheet
+  double rho0;           // water reference density
+  double omega_e, rho_e0, gamma_e, force_e;
+};
+
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
-                       hipStream_t st);
-const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode);
+                       hipStream_t st);  // a.ue != nullptr: the electron-sheet walls
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec);
+// one electron step from the water state g (step n): e_src -> e_dst, u_e of
+// step n -> ue; the water step of step n then reads ue
+hipError_t launch_electron_step(int q, int prec, const void* g, const double* e_src,
+                                double* e_dst, double* ue, const ElecArgs& ea, hipStream_t st);
+const void* electron_kernel_ptr(int q, int prec);
 hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, bool bouz,
                           int which, double* field, double* partials, hipStream_t st);
 hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,

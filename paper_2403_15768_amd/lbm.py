@@ -63,7 +63,8 @@ EXPORTS = [
     "lbm_transfer_state", "lbm_batch_footprint", "lbm_batch_create", "lbm_batch_destroy",
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
-    "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations",
+    "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
+    "lbm_get_electrons",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -99,6 +100,8 @@ def load() -> C.CDLL:
         "lbm_get_friction": [vp, dp, dp],
         "lbm_step": [vp, i64],
         "lbm_set_thermal": [vp, C.c_double, C.c_int, C.c_uint64],
+        "lbm_set_electrons": [vp, C.c_double, C.c_double, C.c_double, C.c_double],
+        "lbm_get_electrons": [vp, dp, dp],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_flux": [vp, dp],
@@ -285,6 +288,22 @@ class Channel:
         NOISE_STRESS (the stress source alone) or NOISE_ALL."""
         self._ck(self._lib.lbm_set_thermal(self._h, float(kT), int(mode), int(seed)),
                  "lbm_set_thermal")
+
+    # ---- electron sheets (slab walls)
+    def set_electrons(self, tau_e: float, rho_e0: float = 1.0, gamma_e: float = 0.0,
+                      force_e: float = 0.0) -> None:
+        """Electron sheets on both slab walls (tau_e = 0: off); resets them to rest."""
+        self._ck(self._lib.lbm_set_electrons(self._h, float(tau_e), float(rho_e0),
+                                             float(gamma_e), float(force_e)),
+                 "lbm_set_electrons")
+
+    def electrons(self):
+        """(u_e of the last step [sheet][z][x], populations [i][sheet][z][x])."""
+        ue = np.zeros((2, self.nz, self.nx))
+        pops = np.zeros((3, 2, self.nz, self.nx))
+        self._ck(self._lib.lbm_get_electrons(self._h, _dptr(ue), _dptr(pops)),
+                 "lbm_get_electrons")
+        return ue, pops
 
     # ---- time stepping
     def step(self, n: int) -> None:

@@ -1,0 +1,149 @@
+"""GPU parity of the electron wind (electron sheets on slab walls) against the
+oracle, through the C ABI.
+
+Tolerances: FP64 water fields and electron state within 1e-12 relative of the
+oracle (same arithmetic, summation order aside); FP32 water storage within
+1e-5 of the largest axial velocity (its stochastic rounding, as for the plain
+channel).  Exact properties at full size: the one-step axial momentum
+bookkeeping of water plus electrons.  Closed form: the coupled steady state.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from test_oracle_lb import poiseuille_exact
+
+pytestmark = pytest.mark.gpu
+
+C9X = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+C19X = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0])
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_15768_amd import lbm as mod
+
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+CASES = {"d2q9": (9, 64, 30, 1), "d3q19": (19, 37, 9, 6)}
+ELEC = (0.85, 0.7, 0.03, -1.5e-6)  # tau_e, rho_e0, gamma_e, force_e
+
+
+def build(lbm, case, precision, fh=2e-6):
+    q, nx, ny, nz = CASES[case]
+    G = lbm.Channel(q, lbm.SLAB, nx, ny, nz, tau=0.75, force=(fh, 0, 0), precision=precision)
+    O = oracle.Lattice(q, oracle.SLAB, nx, ny, nz, tau=0.75, force=(fh, 0, 0))
+    lam = np.random.default_rng(8).uniform(0.0, 0.3, G.wall_count)
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.set_electrons(*ELEC)
+    O.set_electrons(*ELEC)
+    return G, O
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_parity_over_graph_and_plain_steps(lbm, case, precision):
+    say("electrons parity", case, precision)
+    G, O = build(lbm, case, precision)
+    n = 101  # one 64-step graph replay, then single launches
+    G.step(n)
+    O.step(n)
+    rg, ro = G.fields(), O.fields()
+    ref = np.abs(ro[1]).max()
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / ref
+    ueg, pg = G.electrons()
+    ueo, po = O.electrons()
+    eerr = np.abs(ueg - ueo).max() / np.abs(ueo).max()
+    perr = np.abs(pg - po).max() / np.abs(po).max()
+    say(f"  water {err:.2e}  u_e {eerr:.2e}  electron pops {perr:.2e}")
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert err < tol and eerr < tol and perr < tol
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_graph_and_plain_launches_bitwise(lbm, precision):
+    say("electrons bitwise", precision)
+    A, _ = build(lbm, "d3q19", precision)
+    B, _ = build(lbm, "d3q19", precision)
+    A.step(128)
+    for _ in range(128):
+        B.step(1)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+    ua, pa = A.electrons()
+    ub, pb = B.electrons()
+    assert np.array_equal(ua, ub) and np.array_equal(pa, pb)
+
+
+def test_coupled_steady_state_closed_form(lbm):
+    # pressure-driven water dragging the electrons, opposed by a field drive
+    say("electrons steady state")
+    H, tau, lam, fh, fe = 30, 0.8, 0.05, 1e-6, -3e-6
+    rho_e, gam = 2.0, 0.2
+    G = lbm.Channel(9, lbm.SLAB, 4, H, 1, tau=tau, force=(fh, 0, 0), precision="f64")
+    G.set_friction(lam)
+    G.set_electrons(0.9, rho_e, gam, fe)
+    G.step(45056)
+    Ue = (fh * H + fe * 2) / (gam * rho_e * 2)
+    ue, _ = G.electrons()
+    assert np.abs(ue / Ue - 1).max() < 1e-10
+    _, ux, uy, _ = G.fields()
+    exp = poiseuille_exact(H, tau, fh, lam) + Ue
+    assert np.abs(ux[0] - exp[:, None]).max() < 1e-10 * np.abs(exp).max()
+
+
+def test_full_slab_momentum_bookkeeping_fp64(lbm):
+    # 256 x 128 x 64 slab: over one step water plus electrons change axial
+    # momentum by exactly the forces minus the lattice drag
+    say("electrons full slab momentum")
+    nx, ny, nz, fh = 256, 128, 64, 2e-6
+    tau_e, rho_e, gam, fe = ELEC
+    G = lbm.Channel(19, lbm.SLAB, nx, ny, nz, tau=0.7, force=(fh, 0, 0), precision="f64")
+    G.set_friction(np.random.default_rng(3).uniform(0.0, 0.2, G.wall_count))
+    G.set_electrons(tau_e, rho_e, gam, fe)
+    G.step(200)
+
+    def totals():
+        g = G.populations()
+        _, p = G.electrons()
+        return float(np.tensordot(C19X, g, axes=(0, 0)).sum()), float((p[1] - p[2]).sum()), p
+    w0, e0, p = totals()
+    rho = rho_e + p[0] + np.roll(p[1], 1, axis=-1) + np.roll(p[2], -1, axis=-1)
+    G.step(1)
+    w1, e1, _ = totals()
+    ue, _ = G.electrons()
+    expect = fh * G.fluid_count + fe * 2 * nx * nz - gam * float((rho * ue).sum())
+    say(f"  residual {(w1 + e1) - (w0 + e0) - expect:.3e} of {abs(w0):.3e}")
+    assert abs((w1 + e1) - (w0 + e0) - expect) < 1e-12 * abs(w0)
+    assert abs((w1 - w0) - fh * G.fluid_count) > 1e-6 * abs(fh * G.fluid_count)
+
+
+def test_electron_settings_and_batches(lbm):
+    D = lbm.Channel(19, lbm.DUCT, 8, 4, 4, tau=0.8, precision="f64")
+    with pytest.raises(lbm.LBMError):
+        D.set_electrons(*ELEC)
+    S = lbm.Channel(9, lbm.SLAB, 8, 4, 1, tau=0.8, precision="f64")
+    for args in [(0.5, 1.0, 0.1, 0.0), (0.8, 0.0, 0.1, 0.0), (0.8, 1.0, -0.1, 0.0),
+                 (0.8, 1.0, 0.1, float("nan"))]:
+        with pytest.raises(lbm.LBMError):
+            S.set_electrons(*args)
+    with pytest.raises(lbm.LBMError):
+        S.electrons()  # off
+    S.set_electrons(*ELEC)
+    T = lbm.Channel(9, lbm.SLAB, 8, 4, 1, tau=0.8, precision="f64")
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([S, T])
+    S.set_electrons(0.0)  # off again: an ordinary slab
+    S.step(70)
+    T.step(70)
+    assert np.array_equal(S.get_state()[0], T.get_state()[0])
