@@ -311,7 +311,9 @@ def main():
     ap.add_argument("--thermal", type=int, default=0, choices=[0, 1, 2],
                     help="duct with thermal noise (kT = 1e-6): 1 stress source, 2 every "
                          "non-conserved direction")
-    ap.add_argument("--workload", default="duct", choices=["duct", "batch", "serving"],
+    ap.add_argument("--electrons", action="store_true",
+                    help="with --workload slab: electron sheets on both walls")
+    ap.add_argument("--workload", default="duct", choices=["duct", "slab", "batch", "serving"],
                     help="duct: the headline line; batch / serving: their own JSON line")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-precisions", default="f64,f32,f16s",
@@ -339,8 +341,17 @@ def main():
         return batch_workload(args)
     if args.workload == "serving":
         return serving_workload(args)
-    log("bench: duct 256x128x64", args.precision, "steps", args.steps)
-    ch = make_duct(lbm, inputs, args.precision)
+    slab = args.workload == "slab"
+    log("bench:", "slab" if slab else "duct", "256x128x64", args.precision, "steps", args.steps)
+    if slab:  # walls on y only (z periodic), uniform friction, optional electron sheets
+        nx, ny, nz = DUCT
+        ch = lbm.Channel(lbm.D3Q19, lbm.SLAB, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
+                         precision=args.precision)
+        ch.set_friction(0.05)
+        if args.electrons:
+            ch.set_electrons(0.9, 1.0, 0.05, 1e-6)
+    else:
+        ch = make_duct(lbm, inputs, args.precision)
     if args.thermal:
         ch.set_thermal(1e-6, args.thermal, 1)
     cells = ch.fluid_count
@@ -358,7 +369,7 @@ def main():
     log(f"bench: {mlups:.1f} MLUPS, step kernel {kern_s * 1e6:.2f} us, {achieved:.0f} GB/s")
 
     traffic = None
-    if os.path.exists(COUNTERS) and args.precision == "f32" and not args.thermal:
+    if os.path.exists(COUNTERS) and args.precision == "f32" and not args.thermal and not slab:
         c = json.load(open(COUNTERS))
         if c.get("kernel_hash") == kernel_hash():
             traffic = c.get("bytes_per_launch")
@@ -394,18 +405,25 @@ def main():
         "vs_baseline": None,
         "dtype": arith,
         "data": "synthetic",
-        "config": {"workload": f"duct_256x128x64_d3q19_{args.precision}storage"
-                               + ("", "_thermal_stress", "_thermal_all")[args.thermal],
+        "config": {"workload": f"{'slab' if slab else 'duct'}_256x128x64_d3q19_{args.precision}storage"
+                               + ("", "_thermal_stress", "_thermal_all")[args.thermal]
+                               + ("_electrons" if slab and args.electrons else ""),
                    "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
                    "g": 1e-6, "storage": args.precision, "arithmetic": arith,
-                   "friction": "smooth random lambda(x,s): mean 0.05, std 0.02, corr. length 16",
+                   "friction": ("uniform lambda 0.05" if slab else
+                                "smooth random lambda(x,s): mean 0.05, std 0.02, corr. length 16"),
+                   "electrons": ("sheets on both walls: tau_e 0.9, rho_e0 1, gamma_e 0.05, "
+                                 "force_e 1e-6") if slab and args.electrons else None,
                    "check_every": args.check_every,
                    "thermal": [None, "stress source, kT 1e-6", "all directions, kT 1e-6"][args.thermal]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_GBs": None if traffic is None else round(traffic / kern_s / 1e9, 1),
-                     "kernel": "k_step<D3Q19>" if not args.thermal else f"k_step<D3Q19, noise {args.thermal}>",
+                     "kernel": ("k_step<D3Q19>" if not args.thermal else
+                                f"k_step<D3Q19, noise {args.thermal}>")
+                               + (" + k_electron_step (time per step covers both)"
+                                  if slab and args.electrons else ""),
                      "kernel_us": round(kern_s * 1e6, 3), "bytes_per_update": bpu},
         "cpu_baseline": cpu,
         "extras": ext,
