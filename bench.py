@@ -298,6 +298,39 @@ def serving_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def permeability_workload(args):
+    """Sec. 5.1: steady permeability enhancement of x-periodic nanotubes
+    against radius and carrier density (plasmon frequency), friction from the
+    quadrature; continuum Navier slip predicts 1 + 4 nu / (lambda R)."""
+    import numpy as np
+
+    from paper_2403_15768_amd import permeability
+
+    radii, scales = [4, 6, 8, 12, 16, 24, 32], [0.5, 1.0, 2.0]
+    t0 = time.perf_counter()
+    res = permeability.sweep(radii, scales, precision=args.precision)
+    dt = time.perf_counter() - t0
+    nu = (0.8 - 0.5) / 3
+    rows = [{"R": r.radius, "omega_scale": r.omega_scale, "lambda": round(r.lam, 6),
+             "enhancement": round(r.enhancement, 5),
+             "slip_length_fit_over_nu_lambda": round(r.slip_length_fit() * r.lam / nu, 4),
+             "steps": r.steps} for r in res]
+    slopes = {}
+    for s in scales:
+        e = np.array([r.enhancement for r in res if r.omega_scale == s])
+        slopes[str(s)] = round(float(np.polyfit(np.log(radii), np.log(e - 1), 1)[0]), 4)
+    rec = {"metric": "nanotube permeability enhancement vs radius (Sec. 5.1)",
+           "value": round(len(res) / dt, 3), "unit": "tubes solved per s (each also with no-slip walls)",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64" if args.precision != "f16s" else "f32",
+           "data": "synthetic",
+           "config": {"workload": "tube_permeability_sweep", "radii": radii,
+                      "omega_scales": scales, "nx": 16, "tau": 0.8, "g": 1e-6,
+                      "storage": args.precision, "steady": "flux change < 1e-9 per 500 steps"},
+           "loglog_slope_of_enhancement_minus_1": slopes, "tubes": rows,
+           "wall_s": round(dt, 3)}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,7 +346,8 @@ def main():
                          "non-conserved direction")
     ap.add_argument("--electrons", action="store_true",
                     help="with --workload slab: electron sheets on both walls")
-    ap.add_argument("--workload", default="duct", choices=["duct", "slab", "batch", "serving"],
+    ap.add_argument("--workload", default="duct",
+                    choices=["duct", "slab", "batch", "serving", "permeability"],
                     help="duct: the headline line; batch / serving: their own JSON line")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-precisions", default="f64,f32,f16s",
@@ -341,6 +375,10 @@ def main():
         return batch_workload(args)
     if args.workload == "serving":
         return serving_workload(args)
+    if args.workload == "permeability":
+        if args.precision == "f32" and "--precision" not in sys.argv:
+            args.precision = "f64"
+        return permeability_workload(args)
     slab = args.workload == "slab"
     log("bench:", "slab" if slab else "duct", "256x128x64", args.precision, "steps", args.steps)
     if slab:  # walls on y only (z periodic), uniform friction, optional electron sheets
