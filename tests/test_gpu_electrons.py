@@ -4,7 +4,8 @@ oracle, through the C ABI.
 Tolerances: FP64 water fields and electron state within 1e-12 relative of the
 oracle (same arithmetic, summation order aside); FP32 water storage within
 1e-5 of the largest axial velocity (its stochastic rounding, as for the plain
-channel).  Exact properties at full size: the one-step axial momentum
+channel); half storage within 2e-3 (its field error, ~4e-4); with thermal
+noise 3e-4 (the noise's binary32 Box-Muller, as in the thermal tests).  Exact properties at full size: the one-step axial momentum
 bookkeeping of water plus electrons.  Closed form: the coupled steady state.
 """
 import numpy as np
@@ -147,3 +148,36 @@ def test_electron_settings_and_batches(lbm):
     S.step(70)
     T.step(70)
     assert np.array_equal(S.get_state()[0], T.get_state()[0])
+
+
+def test_electrons_with_thermal_noise_fp64(lbm):
+    # both extensions at once: the sheets' walls and the fluctuating update
+    say("electrons + thermal noise")
+    G, O = build(lbm, "d3q19", "f64")
+    for L in (G, O):
+        L.set_thermal(1e-7, 2, 31)
+    G.step(101)
+    O.step(101)
+    rg, ro = G.fields(), O.fields()
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / np.abs(ro[1]).max()
+    ueg, _ = G.electrons()
+    ueo, _ = O.electrons()
+    say(f"  water {err:.2e}  u_e {np.abs(ueg - ueo).max() / np.abs(ueo).max():.2e}")
+    # the thermal term's binary32 Box-Muller (see the thermal parity tests)
+    assert err < 3e-4
+    assert np.abs(ueg - ueo).max() < 3e-4 * np.abs(ueo).max()
+
+
+def test_half_storage_electrons_track_the_oracle(lbm):
+    # half-precision water storage (float arithmetic) with the double sheets:
+    # the sheets follow the oracle within the water's half-storage error
+    # (fields within about 4e-4 of the oracle after 1000 steps on a duct)
+    say("electrons half storage")
+    G, O = build(lbm, "d2q9", "f16s")
+    G.step(300)
+    O.step(300)
+    ueg, _ = G.electrons()
+    ueo, _ = O.electrons()
+    e = np.abs(ueg - ueo).max() / np.abs(ueo).max()
+    say(f"  u_e {e:.2e}")
+    assert e < 2e-3
