@@ -211,12 +211,16 @@ def batch_workload(args):
 
     specs = inputs.batch_channels(256)
     cells = sum(c.nx * c.ny * c.nz for c in specs)
-    out = {"workload": "batch_256_ducts", "channels": len(specs), "cells": cells}
+    out = {"workload": "batch_256_ducts" + ("", "_thermal_stress", "_thermal_all")[args.thermal],
+           "channels": len(specs), "cells": cells}
     fields, fluxes = {}, {}
     precs = args.batch_precisions.split(",")
     for prec in precs:
         log("batch:", prec)
         chs = [serve.open_channel(c, prec, serve.DuctQueries) for c in specs]
+        if args.thermal:  # the fluctuating update, each channel its own seed
+            for k, ch in enumerate(chs):
+                ch.set_thermal(1e-6, args.thermal, k)
         b = lbm.Batch(chs)
         shape = b.tune()
         b.step(64)
@@ -342,8 +346,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--thermal", type=int, default=0, choices=[0, 1, 2],
-                    help="duct with thermal noise (kT = 1e-6): 1 stress source, 2 every "
-                         "non-conserved direction")
+                    help="thermal noise (kT = 1e-6) on the duct or the batch: 1 stress "
+                         "source, 2 every non-conserved direction")
     ap.add_argument("--electrons", action="store_true",
                     help="with --workload slab: electron sheets on both walls")
     ap.add_argument("--workload", default="duct",

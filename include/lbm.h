@@ -289,9 +289,12 @@ typedef struct lbm_batch lbm_batch; /* opaque */
 lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
 /* arena: device, >= footprint bytes, 256-byte aligned, owned by the caller
  * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
- * lattice, precision or wall kind, one appears twice, or one has thermal
- * noise switched on (lbm_set_thermal; lbm_batch_step refuses such a member
- * later too). */
+ * lattice, precision, wall kind or thermal-noise form (lbm_set_thermal: one
+ * form for the whole batch, each member its own kT and seed), one appears
+ * twice, or one has electron sheets.  lbm_batch_step refuses a member whose
+ * noise form changed or whose sheets were switched on after the batch was
+ * built, and takes up a changed kT or seed.  Batched members draw the same
+ * thermal numbers as alone: results agree bit for bit. */
 lbm_status lbm_batch_create(lbm_ctx *const *ctxs, int n, void *arena, size_t arena_bytes,
                             void *hip_stream, lbm_batch **out);
 void lbm_batch_destroy(lbm_batch *b);  /* members and arena untouched */

@@ -43,6 +43,7 @@ struct lbm_batch {
   char* arena = nullptr;
   int Q = 0, prec = 0;
   bool bouz = false;
+  int th = 0;  // every member's thermal-noise form (0: none)
   int64_t nitems = 0;
   struct Group {
     int64_t first, nwall, last;  // items [first, last), wall items [first, nwall)
@@ -52,6 +53,8 @@ struct lbm_batch {
   int wpb = 4;  // waves (work items) per workgroup, set by lbm_batch_tune
   int64_t k = 0;                  // steps since the member table was written
   std::vector<int64_t> base;      // each member's step when the table was written
+  std::vector<double> th_amp;     // each member's noise amplitude and key in the table
+  std::vector<uint64_t> th_seed;
   int64_t max_items = 0;  // capacity of the item arrays (largest list over the shapes)
   size_t off_desc = 0, off_items = 0, off_cols = 0, off_order = 0, off_mstart = 0, off_partials = 0,
          off_out = 0, off_bstep = 0, total = 0;
@@ -233,8 +236,9 @@ lbm_status check_members(lbm_ctx* const* ctxs, int n) {
     if (a.lattice != b.lattice || a.precision != b.precision ||
         (a.geometry == LBM_TUBE) != (b.geometry == LBM_TUBE))
       return LBM_EINVAL;
-    // the batch kernel has no noise and no electron sheets
-    if (ctxs[m]->args.th_mode != 0 || ctxs[m]->elec) return LBM_EINVAL;
+    // one noise form for the whole batch (each member its own kT and seed);
+    // the batch kernel has no electron sheets
+    if (ctxs[m]->args.th_mode != ctxs[0]->args.th_mode || ctxs[m]->elec) return LBM_EINVAL;
   }
   return LBM_OK;
 }
@@ -299,7 +303,7 @@ int64_t count_cols(lbm_ctx* const* ctxs, int n) {
 // one step (step_off steps past the device counter) of group gi
 lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, int wpb,
                         hipStream_t st = nullptr) {
-  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int32_t* cols = b->at<int32_t>(b->off_cols);
@@ -399,7 +403,9 @@ MemberDesc describe(const lbm_ctx* c, int64_t k) {
 lbm_status resync(lbm_batch* b) {
   for (size_t m = 0; m < b->m.size(); m++) {
     lbm_ctx* c = b->m[m];
-    if (c->step == b->base[m] + b->k) continue;
+    if (c->step == b->base[m] + b->k && c->args.th_amp == b->th_amp[m] &&
+        c->args.th_seed == b->th_seed[m])
+      continue;
     lbm_status s = sync(c);
     if (s != LBM_OK) return b->fail(s, "member stream failed");
     const MemberDesc d = describe(c, b->k);
@@ -407,6 +413,8 @@ lbm_status resync(lbm_batch* b) {
                            hipMemcpyHostToDevice, b->stream));
     BCHK(b, hipStreamSynchronize(b->stream));
     b->base[m] = d.base_step;
+    b->th_amp[m] = c->args.th_amp;
+    b->th_seed[m] = c->args.th_seed;
   }
   return LBM_OK;
 }
@@ -416,7 +424,7 @@ lbm_status resync(lbm_batch* b) {
 lbm_status build_graph(lbm_batch* b, size_t gi, hipGraph_t* gout, hipGraphExec_t* xout) {
   hipGraph_t g = nullptr;
   BCHK(b, hipGraphCreate(&g, 0));
-  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz);
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int32_t* cols = b->at<int32_t>(b->off_cols);
@@ -551,6 +559,9 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   }
   std::vector<MemberDesc> desc(n);
   b->base.assign(n, 0);
+  b->th_amp.assign(n, 0.0);
+  b->th_seed.assign(n, 0);
+  b->th = ctxs[0]->args.th_mode;
   for (int m = 0; m < n; m++) {
     lbm_ctx* c = ctxs[m];
     if ((s = sync(c)) != LBM_OK) {
@@ -560,6 +571,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
     }
     desc[m] = describe(c, 0);
     b->base[m] = c->step;
+    b->th_amp[m] = c->args.th_amp;
+    b->th_seed[m] = c->args.th_seed;
   }
   const int64_t zero = 0;
   lbm_status st = LBM_OK;
@@ -608,9 +621,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
   for (lbm_ctx* c : b->m)
-    if (c->args.th_mode != 0 || c->elec) {
-      b->err = "a member has thermal noise or electron sheets switched on; batches step "
-               "without them";
+    if (c->args.th_mode != b->th || c->elec) {
+      b->err = "a member's noise form changed or its electron sheets are on; rebuild the batch";
       return LBM_EINVAL;
     }
   lbm_status rs = resync(b);

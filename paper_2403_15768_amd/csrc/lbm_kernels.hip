@@ -494,7 +494,7 @@ __device__ __forceinline__ void run_cols(const int32_t* cols, const WorkItem& it
   *cc = item.c0 + 2 < item.ncols ? uniform(cl[2]) : *ca;
 }
 
-template <class L, typename S, typename M, bool BOUZ>
+template <class L, typename S, typename M, bool BOUZ, int TH = 0>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ cols,
@@ -530,9 +530,16 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   info.wallcol = item.wallcol;
   info.mask = item.mask;
   M df[L::Q];
+  // thermal term of the member's cell and step (each member its own kT and
+  // seed), drawn before the gather as in k_step
+  M xi[L::Q];
+  if constexpr (TH != 0)
+    thermal_noise<L, M, TH>(a, (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
+                            xi);
   gather<L, S, M, M, BOUZ>(src, a, colA, xc, info, df, c.dl);
-  collide_store<L, M, S>(df, a, gbl(dst) + (int64_t)colA * a.sC, c.dl + (unsigned)c.x,
-                         (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k);
+  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)colA * a.sC, c.dl + (unsigned)c.x,
+                             (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
+                             xi);
 }
 
 // per-item partial sums of (j_x, rho - rho0); one wave per item
@@ -622,19 +629,25 @@ hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st) {
 const void* add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_add_step); }
 
 template <class L, typename S, typename M>
-static const void* batch_kernel_t(bool bouz) {
-  return bouz ? reinterpret_cast<const void*>(&k_batch_step<L, S, M, true>)
-              : reinterpret_cast<const void*>(&k_batch_step<L, S, M, false>);
-}
-const void* batch_step_kernel_ptr(int q, int prec, bool bouz) {
-  if (q == 9) {
-    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz);
-    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz);
-    return batch_kernel_t<D2Q9, _Float16, float>(bouz);
+static const void* batch_kernel_t(bool bouz, int th) {
+  if (bouz) {
+    if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 1>);
+    if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 2>);
+    return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 0>);
   }
-  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz);
-  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz);
-  return batch_kernel_t<D3Q19, _Float16, float>(bouz);
+  if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 1>);
+  if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 2>);
+  return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 0>);
+}
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th) {
+  if (q == 9) {
+    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz, th);
+    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz, th);
+    return batch_kernel_t<D2Q9, _Float16, float>(bouz, th);
+  }
+  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz, th);
+  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz, th);
+  return batch_kernel_t<D3Q19, _Float16, float>(bouz, th);
 }
 
 template <class L, typename S, typename W>

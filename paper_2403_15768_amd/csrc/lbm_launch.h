@@ -52,7 +52,7 @@ const void* add_step_kernel_ptr();  // k_add_step(int64_t* d, int64_t v)
 hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* out, int nxp_out,
                           int64_t rows, int nx, hipStream_t st);
 // batches
-const void* batch_step_kernel_ptr(int q, int prec, bool bouz);
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th);  // th: noise form
 // k_batch_step(const MemberDesc*, const WorkItem*, const int32_t* cols, int64_t first,
 //              int64_t nwall, int64_t last, const int64_t* bstep, int64_t step_off, int wpb)
 hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,

@@ -190,16 +190,59 @@ def test_thermal_settings_rejected(lbm):
     G.step(3)  # still usable
 
 
-def test_batch_refuses_thermal_members(lbm):
-    chs = [build(lbm, "duct", "f32")[0] for _ in range(2)]
-    chs[1].set_thermal(1e-6, 2, 0)
+SPECS = [(37, 12, 9, 0.65, 2e-6), (64, 10, 14, 0.9, 1e-6), (100, 8, 8, 1.1, 1.5e-6),
+         (33, 9, 11, 0.6, 1.2e-6)]
+
+
+def thermal_ducts(lbm, precision, mode):
+    out = []
+    for k, (nx, ny, nz, tau, g) in enumerate(SPECS):
+        ch = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=tau, force=(g, 0, 0), precision=precision)
+        ch.set_friction(inputs.duct_friction(ch.wall_coords(), nx, ny, nz,
+                                             inputs.rng_for("batch", 300 + k), sigma=6.0))
+        ch.set_thermal(1e-6 * (k + 1), mode, 1000 + k)  # each its own kT and seed
+        out.append(ch)
+    return out
+
+
+@pytest.mark.parametrize("precision,mode", [("f32", 1), ("f64", 2), ("f16s", 1)])
+def test_batch_of_thermal_channels_bit_identical_to_alone(lbm, precision, mode):
+    # the batch kernel draws each member's own noise (its cell, its step, its
+    # kT and seed): batched and alone runs agree bit for bit, also after a
+    # member's kT changes between batch steps
+    say("thermal batch vs alone", precision, mode)
+    alone = thermal_ducts(lbm, precision, mode)
+    mixed = thermal_ducts(lbm, precision, mode)
+    for a, m in zip(alone, mixed):
+        a.step(11)
+        m.step(11)
+    b = lbm.Batch(mixed)
+    b.step(100)
+    for a in alone:
+        a.step(100)
+    alone[2].set_thermal(5e-6, mode, 77)
+    mixed[2].set_thermal(5e-6, mode, 77)
+    b.step(70)
+    for a in alone:
+        a.step(70)
+    for a, m in zip(alone, mixed):
+        assert m.step_count == a.step_count == 181
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    b.close()
+
+
+def test_batch_noise_form_rules(lbm):
+    chs = thermal_ducts(lbm, "f32", 1)
+    chs[1].set_thermal(1e-6, 2, 0)  # another form: refused
     with pytest.raises(lbm.LBMError):
         lbm.Batch(chs)
-    chs[1].set_thermal(0.0, 0, 0)
+    chs[1].set_thermal(1e-6, 1, 0)
     b = lbm.Batch(chs)
-    chs[0].set_thermal(1e-6, 2, 0)  # switched on after the batch was built
+    chs[0].set_thermal(0.0, 0, 0)  # the form changed after the batch was built
     with pytest.raises(lbm.LBMError):
         b.step(4)
+    chs[0].set_thermal(1e-6, 1, 0)
+    b.step(4)
 
 
 # ---------------------------------------------- full-size properties (duct)
