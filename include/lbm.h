@@ -241,7 +241,9 @@ lbm_status lbm_get_field(lbm_ctx *ctx, int which, double *host_out);
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *host_out);
 /* The inverse: replace the state by host_in (same layout; solid cells
  * ignored), rounded to nearest in the storage precision, and set the step
- * counter to step >= 0.  Synchronous. */
+ * counter to step >= 0.  A NaN, or a value the storage cannot hold (half:
+ * |g| > 65504 / 2^12), is rejected with LBM_EINVAL and the state left
+ * unchanged.  Synchronous. */
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *host_in, int64_t step);
 
 /* Checkpoint: the populations in storage precision plus the step counter.

@@ -819,6 +819,19 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
 lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) {
   if (!c || !host_in || step < 0) return LBM_EINVAL;
   const Plan& pl = c->pl;
+  // largest |g| each storage holds (half: scaled by 2^12 below 65504)
+  const double vmax = pl.prec == LBM_F64 ? 1.7976931348623157e308
+                      : pl.prec == LBM_F32 ? 3.4028234663852886e38 : 65504.0 / 4096.0;
+  for (int i = 0; i < pl.Q; i++)
+    for (int64_t col = 0; col < pl.ncolbox; col++) {
+      if (pl.colinfo[col].mask & lbm::kSolidColumn) continue;
+      for (int x = 0; x < pl.nx; x++) {
+        const double v = host_in[((int64_t)i * pl.ncolbox + col) * pl.nx + x];
+        if (!(std::fabs(v) <= vmax))
+          return c->fail(LBM_EINVAL, "population %d at column %lld, x %d is %g: NaN or beyond "
+                                     "the storage range", i, (long long)col, x, v);
+      }
+    }
   std::vector<unsigned char> raw(pl.pop_bytes, 0);
   for (int i = 0; i < pl.Q; i++)
     for (int64_t col = 0; col < pl.ncolbox; col++) {

@@ -182,6 +182,19 @@ def test_thermal_off_equals_never_on(lbm):
     assert np.array_equal(A.get_state()[0], B.get_state()[0])
 
 
+def test_set_populations_rejects_bad_values(lbm):
+    G, _ = build(lbm, "duct", "f16s")
+    G.step(3)
+    before = G.get_state()
+    for bad in (np.nan, 20.0):  # half storage holds |g| <= 65504 / 4096 = 16
+        g = np.zeros((G.q,) + G.shape)
+        g[3, 2, 5, 7] = bad
+        with pytest.raises(lbm.LBMError):
+            G.set_populations(g)
+    after = G.get_state()
+    assert after[1] == before[1] and np.array_equal(after[0], before[0])
+
+
 def test_thermal_settings_rejected(lbm):
     G, _ = build(lbm, "duct", "f32")
     for kT, mode in [(-1e-6, 2), (float("nan"), 2), (float("inf"), 1), (1e-6, 0), (1e-6, 3)]:
