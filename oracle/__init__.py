@@ -104,6 +104,8 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_set_electrons.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
     lib.ora_set_electrons.restype = C.c_int
     lib.ora_get_electrons.argtypes = [vp, dp, dp]
+    lib.ora_shell_count.argtypes = [vp]
+    lib.ora_shell_count.restype = lp
     lib.ora_sizeof_real.restype = C.c_int
     u64p = C.POINTER(C.c_uint64)
     lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
@@ -195,17 +197,24 @@ class Lattice:
 
     def set_electrons(self, tau_e: float, rho_e0: float, gamma_e: float,
                       force_e: float = 0.0) -> None:
-        """Electron sheets on the two slab walls, coupled to the water by the
-        relative-velocity wall drag (state reset to rest)."""
+        """Electron lines in the solid columns next to the water (slab and duct
+        walls), coupled to the water by the relative-velocity wall drag
+        (state reset to rest)."""
         if self._lib.ora_set_electrons(self._h, float(tau_e), float(rho_e0), float(gamma_e),
                                        float(force_e)) != 0:
-            raise OracleError("electron sheets need a SLAB without moving wall, tau_e > 1/2, "
-                              "rho_e0 > 0, gamma_e >= 0")
+            raise OracleError("electron sheets need a SLAB or DUCT without moving wall, "
+                              "tau_e > 1/2, rho_e0 > 0, gamma_e >= 0")
+
+    @property
+    def shell_count(self) -> int:
+        return int(self._lib.ora_shell_count(self._h))
 
     def electrons(self):
-        """(u_e of the last step [sheet][z][x], shifted populations [i][sheet][z][x])."""
-        ue = np.zeros((2, self.nz, self.nx))
-        pops = np.zeros((3, 2, self.nz, self.nx))
+        """(u_e of the last step [shell][x], shifted populations [i][shell][x]);
+        shells: y = -1 (by z), y = ny (by z), then for a duct z = -1 (by y),
+        z = nz (by y)."""
+        ue = np.zeros((self.shell_count, self.nx))
+        pops = np.zeros((3, self.shell_count, self.nx))
         self._lib.ora_get_electrons(self._h, _dptr(ue), _dptr(pops))
         return ue, pops
 

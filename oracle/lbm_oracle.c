@@ -131,12 +131,12 @@ typedef struct {
   double kT;     /* lattice temperature; 0 = no fluctuations */
   int noise;     /* 1 = stress directions only, 2 = all non-conserved */
   uint64_t seed; /* key of the thermal random numbers */
-  /* electron sheets (SLAB only): one solid row below y = 0 (sheet 0) and
-   * one above y = ny - 1 (sheet 1), electron lines along x, D1Q3 */
+  /* electron shells (SLAB and DUCT): the solid columns next to the water,
+   * each with an electron line along x, D1Q3 (see shell_of) */
   int elec;
   double tau_e, rho_e0, gamma_e, force_e;
-  real *e, *en; /* shifted populations [i][sheet][z][x], i = 0, +x, -x */
-  real *ue;     /* electron velocity of the last step, [sheet][z][x] */
+  real *e, *en; /* shifted populations [i][shell][x], i = 0, +x, -x */
+  real *ue;     /* electron velocity of the last step, [shell][x] */
 } ora_ctx;
 
 /* ---------------------------------------------------------------- lattice */
@@ -192,9 +192,35 @@ static long cell(const ora_ctx *o, int x, int y, int z) {
   return (long)x + (long)o->p.nx * ((long)y + (long)o->p.ny * (long)z);
 }
 
-/* electron sheet node: sheet b (0 below y = 0, 1 above y = ny - 1), z, x */
-static long sheet_node(const ora_ctx *o, int b, int z, int x) {
-  return ((long)b * o->p.nz + z) * o->p.nx + x;
+/* Electron shells: the solid columns next to the water that carry an
+ * electron line along x.  Numbering: y = -1 (z = 0..nz-1), then y = ny,
+ * then (DUCT only) z = -1 (y = 0..ny-1), then z = nz.  -1 if (ys, zs) is
+ * none of them. */
+static long nshell(const ora_ctx *o) {
+  return 2L * o->p.nz + (o->p.geometry == ORA_DUCT ? 2L * o->p.ny : 0);
+}
+static long shell_of(const ora_ctx *o, int ys, int zs) {
+  if (zs >= 0 && zs < o->p.nz) {
+    if (ys == -1) return zs;
+    if (ys == o->p.ny) return o->p.nz + zs;
+  }
+  if (o->p.geometry == ORA_DUCT && ys >= 0 && ys < o->p.ny) {
+    if (zs == -1) return 2L * o->p.nz + ys;
+    if (zs == o->p.nz) return 2L * o->p.nz + o->p.ny + ys;
+  }
+  return -1;
+}
+/* the shell's solid column (ys, zs) */
+static void shell_column(const ora_ctx *o, long s, int *ys, int *zs) {
+  long nz = o->p.nz, ny = o->p.ny;
+  if (s < 2 * nz) {
+    *ys = s < nz ? -1 : (int)ny;
+    *zs = (int)(s % nz);
+  } else {
+    s -= 2 * nz;
+    *zs = s < ny ? -1 : (int)nz;
+    *ys = (int)(s % ny);
+  }
 }
 
 /* Is the lattice point (x, y, z) -- already wrapped in the periodic
@@ -390,9 +416,10 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
   if (o->elec && o->c[i][0] != 0) {
     /* the wall moves with the electrons of the solid point x - c_i */
     int xs = ((x - o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
-    int zs = ((z - o->c[i][2]) % o->p.nz + o->p.nz) % o->p.nz;
+    int zs = z - o->c[i][2];
+    if (o->p.geometry == ORA_SLAB) zs = (zs % o->p.nz + o->p.nz) % o->p.nz;
     bb += 6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
-          o->ue[sheet_node(o, sy < 0 ? 0 : 1, zs, xs)];
+          o->ue[shell_of(o, sy, zs) * o->p.nx + xs];
   }
   return o->r[n] * bb + (1 - o->r[n]) * g[(long)o->sig[i] * o->ncell + n];
 }
@@ -571,7 +598,8 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
  * half of the wall rule reflects off a wall moving with the electrons, and
  * the electrons take back exactly the axial momentum the water gains there.
  *
- * Each SLAB wall carries one sheet of electron lines along x (the flow axis;
+ * Every solid column next to the water on a SLAB or DUCT wall (the shells,
+ * see shell_of) carries one electron line along x (the flow axis;
  * transverse transport in the sheet is not modelled), D1Q3 (c = 0, +1, -1,
  * w = 2/3, 1/6, 1/6), periodic in x; BGK with tau_e around rho_e0, Guo
  * forcing with F = force_e (the field drive) + F_wall - gamma_e rho u_e
@@ -580,9 +608,8 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
  * line.  Requires wall_velocity_top == 0.  Off after creation. */
 int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
                       double force_e) {
-  long n = 2L * o->p.nz * o->p.nx;
-  if (o->p.geometry != ORA_SLAB || o->p.wall_velocity_top != 0.0)
-    return ORA_EINVAL;
+  long n = nshell(o) * o->p.nx;
+  if (o->p.geometry == ORA_TUBE || o->p.wall_velocity_top != 0.0) return ORA_EINVAL;
   if (!(tau_e > 0.5) || !(rho_e0 > 0) || !(gamma_e >= 0) || !isfinite(force_e) ||
       !isfinite(tau_e) || !isfinite(rho_e0) || !isfinite(gamma_e))
     return ORA_EINVAL;
@@ -602,9 +629,10 @@ int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
   return ORA_OK;
 }
 
-/* One electron step from the water state g (both at step n).  Per sheet
+/* One electron step from the water state g (both at step n).  Per shell
  * node s, the water links that leave s and land on a fluid node x_f = s + c_k
- * with c_kx != 0 carry the axial exchange: the water at x_f gains
+ * with c_kx != 0 carry the axial exchange (one fluid column per shell, two
+ * directions): the water at x_f gains
  *   r(x_f) (2 g_opp(k)(x_f) + 6 w_k rho0 c_kx u_e(s)) c_kx
  * (its wall rule; the free-slip half exchanges no axial momentum), so
  *   F_wall(s) = F0 - K u_e,  F0 = -sum 2 r g_opp(k) c_kx,  K = 6 rho0 sum r w_k.
@@ -613,42 +641,46 @@ int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
 static void electron_step(ora_ctx *o) {
   const int cd[3] = {0, 1, -1};
   const real wd[3] = {(real)2 / 3, (real)1 / 6, (real)1 / 6};
-  int b, z, x, i, k;
+  int x, i, k, ys, zs;
+  long sh;
   real tau = (real)o->tau_e, gam = (real)o->gamma_e;
-  long n = 2L * o->p.nz * o->p.nx;
-  for (b = 0; b < 2; b++)
-    for (z = 0; z < o->p.nz; z++)
-      for (x = 0; x < o->p.nx; x++) {
-        long s = sheet_node(o, b, z, x);
-        real de[3], drho = 0, j = 0, rho, u, F0 = 0, K = 0, F;
-        int yf = b == 0 ? 0 : o->p.ny - 1, cy = b == 0 ? 1 : -1;
-        for (i = 0; i < 3; i++) {
-          int xs = ((x - cd[i]) % o->p.nx + o->p.nx) % o->p.nx;
-          de[i] = o->e[(long)i * n + sheet_node(o, b, z, xs)];
-          drho += de[i];
-          j += de[i] * (real)cd[i];
-        }
-        rho = (real)o->rho_e0 + drho;
-        for (k = 0; k < o->q; k++) {
-          long cf;
-          int xf;
-          if (o->c[k][1] != cy || o->c[k][0] == 0) continue;
-          xf = ((x + o->c[k][0]) % o->p.nx + o->p.nx) % o->p.nx;
-          cf = cell(o, xf, yf, ((z + o->c[k][2]) % o->p.nz + o->p.nz) % o->p.nz);
-          F0 -= 2 * o->r[cf] * o->g[(long)o->opp[k] * o->ncell + cf] * (real)o->c[k][0];
-          K += 6 * (real)o->p.rho0 * o->r[cf] * o->w[k];
-        }
-        u = (j + ((real)o->force_e + F0) / 2) / (rho * (1 + gam / 2) + K / 2);
-        F = (real)o->force_e + F0 - K * u - gam * rho * u;
-        for (i = 0; i < 3; i++) {
-          real c = (real)cd[i];
-          real eq = wd[i] * (drho + rho * (3 * c * u + (real)4.5 * c * c * u * u -
-                                           (real)1.5 * u * u));
-          real src = (1 - 1 / (2 * tau)) * wd[i] * (3 * (c - u) + 9 * c * u * c) * F;
-          o->en[(long)i * n + s] = de[i] - (de[i] - eq) / tau + src;
-        }
-        o->ue[s] = u;
+  long n = nshell(o) * o->p.nx;
+  for (sh = 0; sh < nshell(o); sh++) {
+    shell_column(o, sh, &ys, &zs);
+    for (x = 0; x < o->p.nx; x++) {
+      long s = sh * o->p.nx + x;
+      real de[3], drho = 0, j = 0, rho, u, F0 = 0, K = 0, F;
+      for (i = 0; i < 3; i++) {
+        int xs = ((x - cd[i]) % o->p.nx + o->p.nx) % o->p.nx;
+        de[i] = o->e[(long)i * n + sh * o->p.nx + xs];
+        drho += de[i];
+        j += de[i] * (real)cd[i];
       }
+      rho = (real)o->rho_e0 + drho;
+      for (k = 0; k < o->q; k++) {
+        long cf;
+        int xf, yf = ys + o->c[k][1], zf = zs + o->c[k][2];
+        if (o->c[k][0] == 0) continue;
+        if (o->p.geometry == ORA_SLAB) zf = (zf % o->p.nz + o->p.nz) % o->p.nz;
+        if (yf < 0 || yf >= o->p.ny || zf < 0 || zf >= o->p.nz) continue;
+        xf = ((x + o->c[k][0]) % o->p.nx + o->p.nx) % o->p.nx;
+        cf = cell(o, xf, yf, zf);
+        if (!o->fluid[cf]) continue;
+        F0 -= 2 * o->r[cf] * o->g[(long)o->opp[k] * o->ncell + cf] * (real)o->c[k][0];
+        K += 6 * (real)o->p.rho0 * o->r[cf] * o->w[k];
+      }
+      u = (j + ((real)o->force_e + F0) / 2) / (rho * (1 + gam / 2) + K / 2);
+      F = (real)o->force_e + F0 - K * u - gam * rho * u;
+      for (i = 0; i < 3; i++) {
+        real c = (real)cd[i];
+        real eq = wd[i] * (drho + rho * (3 * c * u + (real)4.5 * c * c * u * u -
+                                         (real)1.5 * u * u));
+        real src = (1 - 1 / (2 * tau)) * wd[i] * (3 * (c - u) + 9 * c * u * c) * F;
+        o->en[(long)i * n + s] = de[i] - (de[i] - eq) / tau + src;
+      }
+      o->ue[s] = u;
+    }
+  }
   {
     real *t = o->e;
     o->e = o->en;
@@ -656,10 +688,12 @@ static void electron_step(ora_ctx *o) {
   }
 }
 
-/* electron velocity of the last step and the shifted populations
- * [i][sheet][z][x] of the current state (either may be NULL) */
+/* electron velocity of the last step [shell][x] and the shifted populations
+ * [i][shell][x] of the current state (either may be NULL) */
+long ora_shell_count(const ora_ctx *o) { return nshell(o); }
+
 void ora_get_electrons(const ora_ctx *o, double *ue, double *pops) {
-  long k, n = 2L * o->p.nz * o->p.nx;
+  long k, n = nshell(o) * o->p.nx;
   if (!o->e) return;
   for (k = 0; k < n; k++) {
     if (ue) ue[k] = (double)o->ue[k];
