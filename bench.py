@@ -184,6 +184,17 @@ def extras(torch, lbm, inputs, args):
                      "step_us": round(kms * 1e3 / 2000, 2),
                      "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
         ch.close()
+    # the benchmark duct with electron lines on all four walls
+    ch = make_duct(lbm, inputs, "f32")
+    ch.set_electrons(0.9, 1.0, 0.05, 1e-6)
+    ch.step(200)
+    wall, kms = timed_run(torch, ch, 2000, 1000)
+    cells = ch.fluid_count
+    out["duct_f32_electrons"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                                 "step_us": round(kms * 1e3 / 2000, 2),
+                                 "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
+                                                   / HBM_PEAK_GBS, 4)}
+    ch.close()
     # the fluctuating update (thermal noise, kT = 1e-6) on the FP32 duct,
     # both noise forms
     for mode, name in ((1, "stress"), (2, "all")):

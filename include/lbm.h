@@ -184,12 +184,13 @@ lbm_status lbm_get_friction(lbm_ctx *ctx, double *lambda, double *raw);
 typedef enum { LBM_NOISE_STRESS = 1, LBM_NOISE_ALL = 2 } lbm_noise;
 lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
 
-/* Electron wind (SLAB only).  Sec. 3.3 describes the electrons of the solid
+/* Electron wind (SLAB and DUCT).  Sec. 3.3 describes the electrons of the solid
  * as a fluid dragged by, and dragging, the water; Sec. 4 gives each species
  * its own set of distributions; Eq. 5 / Eq. 27 make the interfacial force a
  * drag on the relative velocity, equal and opposite for the two species.
- * Each slab wall carries one sheet of electron lines along x, one solid row
- * outside the water (sheet 0 below y = 0, sheet 1 above y = ny - 1): D1Q3
+ * Every solid column next to the water (a "shell") carries one electron line
+ * along x -- shells y = -1 and y = ny (by z), then for a duct z = -1 and
+ * z = nz (by y), nshell = 2 nz (+ 2 ny for a duct): D1Q3
  * populations (c = 0, +1, -1; w = 2/3, 1/6, 1/6; stored as deviations from
  * w_i rho_e0, double), BGK with tau_e, Guo forcing with
  *   F = force_e (a field drive along x) + F_wall - gamma_e rho_e u_e
@@ -201,11 +202,13 @@ lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
  * there (the free-slip half exchanges none), so water plus electrons change
  * axial momentum only by the external forces and the lattice drag.  Each
  * step runs the electrons first (from the water state of that step), then
- * the water with that u_e.  At steady state the sheets move at
- *   U_e = (F_x N_fluid + force_e N_sheet) / (gamma_e rho_e0 N_sheet)
- * and the water is the slip-Poiseuille profile shifted by U_e.
- * Requires wall_velocity_top == 0, tau_e > 1/2, rho_e0 > 0, gamma_e >= 0,
- * finite values (else LBM_EINVAL); tau_e == 0 switches the sheets off.
+ * the water with that u_e.  At steady state the lines' drag takes exactly
+ * what the forces put in, gamma_e sum rho_e u_e = F_x N_fluid + force_e
+ * N_lines; in a slab the sheets then move at one U_e and the water is the
+ * slip-Poiseuille profile shifted by it.
+ * Requires a SLAB or DUCT (a TUBE gives LBM_EINVAL), wall_velocity_top == 0,
+ * tau_e > 1/2, rho_e0 > 0, gamma_e >= 0, finite values (else LBM_EINVAL);
+ * tau_e == 0 switches the sheets off.
  * Fields, flux and mass (the moments the next collision would see) take
  * the wall velocity from the last step's u_e.
  * Switching on resets the electrons to rest.  The electron state is not part
@@ -213,8 +216,8 @@ lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
  * channels with sheets.  Synchronous. */
 lbm_status lbm_set_electrons(lbm_ctx *ctx, double tau_e, double rho_e0,
                              double gamma_e, double force_e);
-/* u_e of the last step (2 * nz * nx doubles, [sheet][z][x]) and the current
- * electron populations (3 * 2 * nz * nx, [i][sheet][z][x]); host arrays,
+/* u_e of the last step (nshell * nx doubles, [shell][x]) and the current
+ * electron populations (3 * nshell * nx, [i][shell][x]); host arrays,
  * either may be NULL.  LBM_ESTATE if the sheets are off.  Synchronous. */
 lbm_status lbm_get_electrons(lbm_ctx *ctx, double *ue, double *pops);
 

@@ -204,18 +204,27 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     }
   }
 
-  if (p->geometry == LBM_SLAB) {
-    pl.nsheet = 2LL * pl.nz * pl.nx;
-    pl.sheet_wc.assign(2 * (size_t)pl.nz, -1);
-    for (int b = 0; b < 2; b++)
-      for (int z = 0; z < pl.nz; z++) {
-        const int64_t col = (int64_t)(b == 0 ? 0 : pl.ny - 1) + (int64_t)pl.ny * z;
-        pl.sheet_wc[(size_t)b * pl.nz + z] = pl.colinfo[col].wallcol;
-        if (pl.colinfo[col].wallcol < 0) {
-          if (err) *err = "internal: slab wall row without wall links";
-          return LBM_EINVAL;
-        }
+  if (p->geometry != LBM_TUBE) {
+    // electron shells: the solid columns next to the water, y = -1 and y = ny
+    // (by z), then for a duct z = -1 and z = nz (by y); each couples to one
+    // fluid column, whose wall column is recorded
+    const int64_t nshell = 2LL * pl.nz + (p->geometry == LBM_DUCT ? 2LL * pl.ny : 0);
+    pl.nsheet = nshell * pl.nx;
+    pl.sheet_wc.assign((size_t)nshell, -1);
+    for (int64_t sh = 0; sh < nshell; sh++) {
+      int64_t col;
+      if (sh < 2LL * pl.nz)
+        col = (sh < pl.nz ? 0 : pl.ny - 1) + (int64_t)pl.ny * (sh % pl.nz);
+      else {
+        const int64_t t = sh - 2LL * pl.nz;
+        col = t % pl.ny + (int64_t)pl.ny * (t < pl.ny ? 0 : pl.nz - 1);
       }
+      pl.sheet_wc[(size_t)sh] = pl.colinfo[col].wallcol;
+      if (pl.colinfo[col].wallcol < 0) {
+        if (err) *err = "internal: wall row without wall links";
+        return LBM_EINVAL;
+      }
+    }
   }
 
   size_t off = 0;
@@ -680,8 +689,8 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   if (!c) return LBM_EINVAL;
   const bool on = tau_e != 0.0;
   if (on) {
-    if (c->p.geometry != LBM_SLAB || c->p.wall_velocity_top != 0.0)
-      return c->fail(LBM_EINVAL, "electron sheets need a SLAB without a moving wall");
+    if (c->p.geometry == LBM_TUBE || c->p.wall_velocity_top != 0.0)
+      return c->fail(LBM_EINVAL, "electron sheets need a SLAB or DUCT without a moving wall");
     if (!(tau_e > 0.5) || !(rho_e0 > 0.0) || !(gamma_e >= 0.0) || !std::isfinite(tau_e) ||
         !std::isfinite(rho_e0) || !std::isfinite(gamma_e) || !std::isfinite(force_e))
       return c->fail(LBM_EINVAL, "need tau_e > 1/2, rho_e0 > 0, gamma_e >= 0, finite values");
@@ -704,6 +713,7 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   ea.nz = pl.nz;
   ea.sI = pl.sI;
   ea.sC = pl.sC;
+  ea.nshell = (int)(pl.nsheet / pl.nx);
   ea.rwall = c->at<void>(pl.off_r);
   ea.swc = c->at<int32_t>(pl.off_swc);
   ea.rho0 = c->p.rho0;

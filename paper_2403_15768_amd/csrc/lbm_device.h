@@ -102,8 +102,9 @@ struct StepArgs {
   double th_amp;
   int th_mode;
   uint64_t th_seed;
-  // electron sheets (slab walls): x velocity of each sheet node in the step
-  // being taken, [sheet][z][x] (sheet 0 below y = 0, 1 above y = ny - 1)
+  // electron shells (slab and duct walls): x velocity of each shell node in
+  // the step being taken, [shell][x]; shells y = -1, y = ny (by z), then for
+  // a duct z = -1, z = nz (by y)
   const double* ue;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
@@ -294,10 +295,10 @@ __device__ __forceinline__ int64_t src_off(const StepArgs& a, int i, int z, bool
 // column col + k takes the lines of column col shifted by dl = k sC, which is
 // the same shift for every source column away from periodic wrap in z.
 //
-// With ELEC (slab walls with electron sheets) the bounce-back half reflects
-// off a wall moving with the electrons of the solid point x - c_i:
+// With ELEC (slab or duct walls with electron shells) the bounce-back half
+// reflects off a wall moving with the electrons of the solid point x - c_i:
 //   BB_i = g_opp(i)(x) + 6 w_i rho0 c_ix u_e(x - c_i)
-// (wall links with c_ix != 0 have c_iz = 0 in a slab).
+// (a wall link with c_ix != 0 crosses a y wall or a z wall, never both).
 template <class L, typename S, typename M, typename W, bool BOUZ, bool ELEC = false>
 __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs& a, int col,
                                        int x, ColInfo info, M* df, unsigned dl = 0u) {
@@ -360,8 +361,9 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
     }
     M bb = gb;
     if (ELEC && L::cx[i] != 0) {
-      const int64_t sn = ((int64_t)(L::cy[i] > 0 ? 0 : 1) * a.nz + z) * a.nx +
-                         (L::cx[i] > 0 ? xm : xp);
+      const int64_t shell = L::cy[i] != 0 ? (int64_t)(L::cy[i] > 0 ? 0 : a.nz) + z
+                                          : 2LL * a.nz + (L::cz[i] > 0 ? 0 : a.ny) + y;
+      const int64_t sn = shell * a.nx + (L::cx[i] > 0 ? xm : xp);
       bb += static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i]) * static_cast<M>(gbl(a.ue)[sn]);
     }
     if (BOUZ) {

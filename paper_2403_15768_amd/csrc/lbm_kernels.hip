@@ -65,10 +65,10 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
 }
 
 // ------------------------------------------------------------ electron sheets
-// One electron step per sheet node (lines along x, D1Q3: c = 0, +1, -1,
-// w = 2/3, 1/6, 1/6, shifted populations [i][sheet][z][x] in double):
+// One electron step per shell node (lines along x, D1Q3: c = 0, +1, -1,
+// w = 2/3, 1/6, 1/6, shifted populations [i][shell][x] in double):
 //   pull along the line (periodic); the water links from this node to the
-//   fluid row (c_ky towards the water, c_kx != 0) give the axial force the
+//   fluid column next to it (c_kx != 0) give the axial force the
 //   water's wall rule takes from the sheet, F_wall = F0 - K u,
 //     F0 = -sum 2 r g_opp(k)(x + c_kx) c_kx,  K = 6 rho0 sum r w_k;
 //   with the field force and the drag -gamma rho u, Guo's half-force makes
@@ -79,25 +79,37 @@ __global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
                                                        const double* __restrict__ es,
                                                        double* __restrict__ ed,
                                                        double* __restrict__ ue, ElecArgs ea) {
-  const int64_t n = 2LL * ea.nz * ea.nx;
+  const int64_t n = (int64_t)ea.nshell * ea.nx;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const int64_t bz = s / ea.nx;  // sheet * nz + z
-  const int x = (int)(s - bz * ea.nx);
-  const int b = (int)(bz / ea.nz), z = (int)(bz - (int64_t)b * ea.nz);
-  const int64_t line = bz * ea.nx;
+  const int64_t sh = s / ea.nx;  // shell
+  const int x = (int)(s - sh * ea.nx);
+  const int64_t line = sh * ea.nx;
   const int xm = x == 0 ? ea.nx - 1 : x - 1, xp = x == ea.nx - 1 ? 0 : x + 1;
   const double d0 = es[s], d1 = es[n + line + xm], d2 = es[2 * n + line + xp];
   const double drho = d0 + d1 + d2, j = d1 - d2;
   const double rho = ea.rho_e0 + drho;
-  const int cy = b == 0 ? 1 : -1;
-  const int64_t col = (int64_t)(b == 0 ? 0 : ea.ny - 1) + (int64_t)ea.ny * z;
-  const LBM_GLOBAL W* rw = gbl(static_cast<const W*>(ea.rwall)) + (int64_t)ea.swc[bz] * ea.nx;
+  // the fluid column next to the shell and the (c_y, c_z) of the links to it
+  int cy, cz;
+  int64_t col;
+  if (sh < 2LL * ea.nz) {
+    const bool low = sh < ea.nz;
+    cy = low ? 1 : -1;
+    cz = 0;
+    col = (low ? 0 : ea.ny - 1) + (int64_t)ea.ny * (sh % ea.nz);
+  } else {
+    const int64_t t = sh - 2LL * ea.nz;
+    const bool low = t < ea.ny;
+    cy = 0;
+    cz = low ? 1 : -1;
+    col = t % ea.ny + (int64_t)ea.ny * (low ? 0 : ea.nz - 1);
+  }
+  const LBM_GLOBAL W* rw = gbl(static_cast<const W*>(ea.rwall)) + (int64_t)ea.swc[sh] * ea.nx;
   double F0 = 0.0, K = 0.0;
 #pragma unroll
   for (int k = 0; k < L::Q; k++) {
-    if (L::cx[k] == 0 || L::cy[k] == 0) continue;
-    if (L::cy[k] != cy) continue;
+    if (L::cx[k] == 0 || (L::cy[k] == 0 && L::cz[k] == 0)) continue;
+    if (L::cy[k] != cy || L::cz[k] != cz) continue;
     const int xf = L::cx[k] > 0 ? xp : xm;
     const double r = static_cast<double>(rw[xf]);
     const double go = dec<S, double>(gbl(g)[col * ea.sC + L::row[L::opp[k]] * ea.sI + xf]);
@@ -781,7 +793,7 @@ const void* electron_kernel_ptr(int q, int prec) {
 
 hipError_t launch_electron_step(int q, int prec, const void* g, const double* e_src,
                                 double* e_dst, double* ue, const ElecArgs& ea, hipStream_t st) {
-  const int64_t n = 2LL * ea.nz * ea.nx;
+  const int64_t n = (int64_t)ea.nshell * ea.nx;
   if (n <= 0 || (n + 255) / 256 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   ElecArgs args = ea;
   void* kargs[5] = {(void*)&g, (void*)&e_src, (void*)&e_dst, (void*)&ue, (void*)&args};

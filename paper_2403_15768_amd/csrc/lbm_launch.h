@@ -20,12 +20,14 @@ struct SpecArgs {
   double v_l;    // liquid mode dispersion
 };
 
-// Electron sheets of a slab (one per wall, lines along x, D1Q3)
+// Electron shells (the solid columns next to the water of a slab or duct,
+// one line along x each, D1Q3): y = -1 and y = ny (by z), then for a duct
+// z = -1 and z = nz (by y)
 struct ElecArgs {
-  int nx, ny, nz;
+  int nx, ny, nz, nshell;
   int64_t sI, sC;        // water layout
   const void* rwall;     // water wall weights r [wallcol][nx] (double, float for F16S)
-  const int32_t* swc;    // [sheet][z]: wall column of the water row next to the sheet
+  const int32_t* swc;    // [shell]: wall column of the fluid column next to the shell
   double rho0;           // water reference density
   double omega_e, rho_e0, gamma_e, force_e;
 };

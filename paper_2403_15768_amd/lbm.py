@@ -292,15 +292,21 @@ class Channel:
     # ---- electron sheets (slab walls)
     def set_electrons(self, tau_e: float, rho_e0: float = 1.0, gamma_e: float = 0.0,
                       force_e: float = 0.0) -> None:
-        """Electron sheets on both slab walls (tau_e = 0: off); resets them to rest."""
+        """Electron lines in the solid next to every slab or duct wall (tau_e = 0:
+        off); resets them to rest."""
         self._ck(self._lib.lbm_set_electrons(self._h, float(tau_e), float(rho_e0),
                                              float(gamma_e), float(force_e)),
                  "lbm_set_electrons")
 
+    @property
+    def shell_count(self) -> int:
+        """Electron lines: y = -1, y = ny (by z), then for a duct z = -1, z = nz (by y)."""
+        return 2 * self.nz + (2 * self.ny if self.params.geometry == DUCT else 0)
+
     def electrons(self):
-        """(u_e of the last step [sheet][z][x], populations [i][sheet][z][x])."""
-        ue = np.zeros((2, self.nz, self.nx))
-        pops = np.zeros((3, 2, self.nz, self.nx))
+        """(u_e of the last step [shell][x], populations [i][shell][x])."""
+        ue = np.zeros((self.shell_count, self.nx))
+        pops = np.zeros((3, self.shell_count, self.nx))
         self._ck(self._lib.lbm_get_electrons(self._h, _dptr(ue), _dptr(pops)),
                  "lbm_get_electrons")
         return ue, pops

@@ -36,14 +36,16 @@ def say(*a):
     print(*a, flush=True)
 
 
-CASES = {"d2q9": (9, 64, 30, 1), "d3q19": (19, 37, 9, 6)}
+CASES = {"d2q9": (9, 64, 30, 1), "d3q19": (19, 37, 9, 6), "duct": (19, 33, 10, 7)}
 ELEC = (0.85, 0.7, 0.03, -1.5e-6)  # tau_e, rho_e0, gamma_e, force_e
 
 
 def build(lbm, case, precision, fh=2e-6):
     q, nx, ny, nz = CASES[case]
-    G = lbm.Channel(q, lbm.SLAB, nx, ny, nz, tau=0.75, force=(fh, 0, 0), precision=precision)
-    O = oracle.Lattice(q, oracle.SLAB, nx, ny, nz, tau=0.75, force=(fh, 0, 0))
+    geom = "DUCT" if case == "duct" else "SLAB"
+    G = lbm.Channel(q, getattr(lbm, geom), nx, ny, nz, tau=0.75, force=(fh, 0, 0),
+                    precision=precision)
+    O = oracle.Lattice(q, getattr(oracle, geom), nx, ny, nz, tau=0.75, force=(fh, 0, 0))
     lam = np.random.default_rng(8).uniform(0.0, 0.3, G.wall_count)
     G.set_friction(lam)
     O.set_friction(lam)
@@ -72,11 +74,12 @@ def test_parity_over_graph_and_plain_steps(lbm, case, precision):
     assert err < tol and eerr < tol and perr < tol
 
 
+@pytest.mark.parametrize("case", ["d3q19", "duct"])
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
-def test_graph_and_plain_launches_bitwise(lbm, precision):
-    say("electrons bitwise", precision)
-    A, _ = build(lbm, "d3q19", precision)
-    B, _ = build(lbm, "d3q19", precision)
+def test_graph_and_plain_launches_bitwise(lbm, precision, case):
+    say("electrons bitwise", precision, case)
+    A, _ = build(lbm, case, precision)
+    B, _ = build(lbm, case, precision)
     A.step(128)
     for _ in range(128):
         B.step(1)
@@ -103,13 +106,15 @@ def test_coupled_steady_state_closed_form(lbm):
     assert np.abs(ux[0] - exp[:, None]).max() < 1e-10 * np.abs(exp).max()
 
 
-def test_full_slab_momentum_bookkeeping_fp64(lbm):
-    # 256 x 128 x 64 slab: over one step water plus electrons change axial
-    # momentum by exactly the forces minus the lattice drag
-    say("electrons full slab momentum")
+@pytest.mark.parametrize("geom", ["SLAB", "DUCT"])
+def test_full_size_momentum_bookkeeping_fp64(lbm, geom):
+    # 256 x 128 x 64 slab and duct: over one step water plus electrons change
+    # axial momentum by exactly the forces minus the lattice drag
+    say("electrons full size momentum", geom)
     nx, ny, nz, fh = 256, 128, 64, 2e-6
     tau_e, rho_e, gam, fe = ELEC
-    G = lbm.Channel(19, lbm.SLAB, nx, ny, nz, tau=0.7, force=(fh, 0, 0), precision="f64")
+    G = lbm.Channel(19, getattr(lbm, geom), nx, ny, nz, tau=0.7, force=(fh, 0, 0),
+                    precision="f64")
     G.set_friction(np.random.default_rng(3).uniform(0.0, 0.2, G.wall_count))
     G.set_electrons(tau_e, rho_e, gam, fe)
     G.step(200)
@@ -123,14 +128,15 @@ def test_full_slab_momentum_bookkeeping_fp64(lbm):
     G.step(1)
     w1, e1, _ = totals()
     ue, _ = G.electrons()
-    expect = fh * G.fluid_count + fe * 2 * nx * nz - gam * float((rho * ue).sum())
+    expect = fh * G.fluid_count + fe * G.shell_count * nx - gam * float((rho * ue).sum())
     say(f"  residual {(w1 + e1) - (w0 + e0) - expect:.3e} of {abs(w0):.3e}")
     assert abs((w1 + e1) - (w0 + e0) - expect) < 1e-12 * abs(w0)
     assert abs((w1 - w0) - fh * G.fluid_count) > 1e-6 * abs(fh * G.fluid_count)
 
 
 def test_electron_settings_and_batches(lbm):
-    D = lbm.Channel(19, lbm.DUCT, 8, 4, 4, tau=0.8, precision="f64")
+    D = lbm.Channel(19, lbm.TUBE, 8, 12, 12, tau=0.8, precision="f64", tube_radius=3.0,
+                    tube_cy=5.5, tube_cz=5.5)
     with pytest.raises(lbm.LBMError):
         D.set_electrons(*ELEC)
     S = lbm.Channel(9, lbm.SLAB, 8, 4, 1, tau=0.8, precision="f64")
