@@ -428,6 +428,19 @@ __device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
 struct Philox4 {
   uint64_t w[4];
 };
+
+// 64 x 64 -> 128-bit product from four 32 x 32 + 64 multiply-adds: with
+// m = m1 2^32 + m0, v = v1 2^32 + v0, the middle sums cannot overflow
+// ((2^32 - 1)^2 + 2 (2^32 - 1) = 2^64 - 1)
+__device__ __forceinline__ void mulhilo64(uint64_t m, uint64_t v, uint64_t* hi, uint64_t* lo) {
+  const uint32_t m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+  const uint32_t v0 = (uint32_t)v, v1 = (uint32_t)(v >> 32);
+  const uint64_t p00 = (uint64_t)m0 * v0;
+  const uint64_t t = (uint64_t)m1 * v0 + (p00 >> 32);
+  const uint64_t u = (uint64_t)m0 * v1 + (uint32_t)t;
+  *hi = (uint64_t)m1 * v1 + (t >> 32) + (u >> 32);
+  *lo = (u << 32) | (uint32_t)p00;
+}
 __device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
                                                  uint64_t k0, uint64_t k1) {
   constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
@@ -435,8 +448,9 @@ __device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint6
   uint64_t x0 = c0, x1 = c1, x2 = c2, x3 = 0;
 #pragma unroll
   for (int r = 0; r < 10; r++) {
-    const uint64_t h0 = __umul64hi(kM0, x0), l0 = kM0 * x0;
-    const uint64_t h1 = __umul64hi(kM1, x2), l1 = kM1 * x2;
+    uint64_t h0, l0, h1, l1;
+    mulhilo64(kM0, x0, &h0, &l0);
+    mulhilo64(kM1, x2, &h1, &l1);
     x0 = h1 ^ x1 ^ k0;
     x1 = l1;
     x2 = h0 ^ x3 ^ k1;
@@ -450,14 +464,16 @@ __device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint6
 // Two standard normals from one 64-bit word (Box-Muller): the top 23 bits of
 // each 32-bit half give u = (k + 1/2) 2^-23, exact in binary32 and never 0
 // or 1; z = sqrt(-2 ln u_lo) (cos, sin)(2 pi u_hi).  |z| <= sqrt(48 ln 2).
+// Over all 2^23 such u the hardware log2 gives the radius within 5.3e-7 and
+// the hardware sin / cos (argument in revolutions) are within 1.3e-7 of
+// binary64 (measured), so |dz| < 1.3e-6.
 __device__ __forceinline__ void normal_pair(uint64_t word, float* z0, float* z1) {
   const float ul = (static_cast<float>(static_cast<uint32_t>(word) >> 9) + 0.5f) * 0x1p-23f;
   const float uh = (static_cast<float>(static_cast<uint32_t>(word >> 32) >> 9) + 0.5f) * 0x1p-23f;
-  const float rad = sqrtf(-2.0f * logf(ul));
-  float sn, cs;
-  sincospif(2.0f * uh, &sn, &cs);
-  *z0 = rad * cs;
-  *z1 = rad * sn;
+  // hardware log2 and sin / cos of 2 pi t (argument in revolutions)
+  const float rad = sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(ul));
+  *z0 = rad * __builtin_amdgcn_cosf(uh);
+  *z1 = rad * __builtin_amdgcn_sinf(uh);
 }
 
 // sqrt(w_i) from the weight class (|c|^2 and the lattice)
