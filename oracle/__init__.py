@@ -25,7 +25,7 @@ _LIBS = {
     "f80": os.path.join(_HERE, "liblbm_oracle_ld.so"),
 }
 
-SLAB, DUCT, TUBE = 0, 1, 2
+SLAB, DUCT, TUBE, MASKED = 0, 1, 2, 3
 
 
 def build(verbose: bool = False) -> None:
@@ -49,6 +49,7 @@ class _Params(C.Structure):
         ("tau", C.c_double), ("rho0", C.c_double),
         ("force", C.c_double * 3),
         ("wall_velocity_top", C.c_double),
+        ("solid", C.c_void_p),
     ]
 
 
@@ -130,14 +131,16 @@ class Lattice:
 
     geometry: SLAB (walls on y, periodic z), DUCT (walls on y and z) or TUBE
     (circular cross-section of ``tube_radius`` centred at (tube_cy, tube_cz) in
-    the box).  For SLAB/DUCT the box is all fluid and the walls lie half a link
+    the box) or MASKED (a slab whose solid points in the (x, y) plane are
+    ``solid``, shaped (ny, nx), the same for every z: corrugated or stepped
+    walls).  For SLAB/DUCT the box is all fluid and the walls lie half a link
     outside it.  ``kind`` = "f64" or "f80" (long double).
     """
 
     def __init__(self, lattice: int, geometry: int, nx: int, ny: int, nz: int,
                  tau: float, force=(0.0, 0.0, 0.0), rho0: float = 1.0,
                  tube_radius: float = 0.0, tube_cy: float = 0.0, tube_cz: float = 0.0,
-                 wall_velocity_top: float = 0.0, kind: str = "f64"):
+                 wall_velocity_top: float = 0.0, kind: str = "f64", solid=None):
         self._lib = _lib(kind)
         p = _Params()
         p.lattice, p.precision, p.geometry = lattice, 0, geometry
@@ -146,6 +149,11 @@ class Lattice:
         p.tau, p.rho0 = tau, rho0
         p.force = (C.c_double * 3)(*force)
         p.wall_velocity_top = wall_velocity_top
+        mask = None
+        if solid is not None:
+            mask = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
+            assert mask.shape == (ny, nx)
+            p.solid = mask.ctypes.data
         h = C.c_void_p()
         rc = self._lib.ora_create(C.byref(p), C.byref(h))
         if rc != 0:

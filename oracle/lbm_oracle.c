@@ -31,7 +31,10 @@
  *    half is the same-node transverse reversal (c_x, -c_y, -c_z).  Bounce-back
  *    is half-way on planar walls and Bouzidi-Firdaouss-Lallemand linear
  *    interpolation on the circular tube.  Inlet/outlet are periodic in x (the
- *    first option of Sec. 4.2).
+ *    first option of Sec. 4.2).  Walls that vary along x (a solid mask in
+ *    the (x, y) plane: corrugated, wrinkled or stepped walls) take the slip
+ *    half from a pairing of the node's wall links (pair_slip_links) that
+ *    keeps mass exact.
  *  - Friction quadrature: a (q, omega) midpoint sum of the imaginary parts of
  *    a Drude solid response and a Lorentzian liquid response with a thermal
  *    factor, optionally divided by the coupling denominator
@@ -97,19 +100,22 @@ typedef double real;
 #define ORA_EINVAL -1
 #define ORA_ENOMEM -2
 
-enum { ORA_SLAB = 0, ORA_DUCT = 1, ORA_TUBE = 2 };
+enum { ORA_SLAB = 0, ORA_DUCT = 1, ORA_TUBE = 2, ORA_MASKED = 3 };
 
 /* Same field order as the GPU library's parameter struct, but declared here
  * independently: only the layout of plain numbers is common. */
 typedef struct {
   int lattice;  /* 9 or 19 */
   int precision; /* ignored by the oracle (always real) */
-  int geometry; /* ORA_SLAB / ORA_DUCT / ORA_TUBE */
+  int geometry; /* ORA_SLAB / ORA_DUCT / ORA_TUBE / ORA_MASKED */
   int nx, ny, nz;
   double tube_radius, tube_cy, tube_cz;
   double tau, rho0;
   double force[3];
   double wall_velocity_top; /* moving top wall (y = ny - 1/2), slab/duct only */
+  /* ORA_MASKED: solid points of the (x, y) plane, nx*ny bytes, x fastest,
+   * nonzero = solid, the same for every z; read at creation only */
+  const unsigned char *solid;
 } ora_params;
 
 typedef struct {
@@ -126,6 +132,8 @@ typedef struct {
   long nfluid;
   real *r;     /* per cell (wall nodes only) */
   real *qlink; /* per cell * 19: Bouzidi fraction of wall links (0 if none) */
+  unsigned char *mask;  /* ORA_MASKED: copy of the (x, y) solid mask */
+  signed char *partner; /* ORA_MASKED: per cell * 19, slip partner of wall link i */
   real *g, *gn;
   long step;
   double kT;     /* lattice temperature; 0 = no fluctuations */
@@ -226,8 +234,8 @@ static void shell_column(const ora_ctx *o, long s, int *ys, int *zs) {
 /* Is the lattice point (x, y, z) -- already wrapped in the periodic
  * directions -- a solid point? */
 static int is_solid(const ora_ctx *o, int x, int y, int z) {
-  (void)x;
   if (y < 0 || y >= o->p.ny || z < 0 || z >= o->p.nz) return 1;
+  if (o->p.geometry == ORA_MASKED) return o->mask[(long)x + (long)o->p.nx * y] != 0;
   if (o->p.geometry == ORA_TUBE) {
     double dy = (double)y - o->p.tube_cy, dz = (double)z - o->p.tube_cz;
     return !(dy * dy + dz * dz < o->p.tube_radius * o->p.tube_radius);
@@ -241,7 +249,8 @@ static void upstream(const ora_ctx *o, int x, int y, int z, int i, int *sx,
   *sx = ((x - o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
   *sy = y - o->c[i][1];
   *sz = z - o->c[i][2];
-  if (o->p.geometry == ORA_SLAB) *sz = ((*sz) % o->p.nz + o->p.nz) % o->p.nz;
+  if (o->p.geometry == ORA_SLAB || o->p.geometry == ORA_MASKED)
+    *sz = ((*sz) % o->p.nz + o->p.nz) % o->p.nz;
 }
 
 /* Bouzidi fraction: distance from the fluid node P to the circular wall
@@ -256,6 +265,60 @@ static real bouzidi_q(const ora_ctx *o, int y, int z, int i) {
   return (-b + R_SQRT(b * b - 4 * a * cc)) / (2 * a);
 }
 
+/* Slip partners on a masked wall (corrugated or stepped walls, Sec. 4.2 and
+ * the wall-design remark of Sec. 5.1).  At a wall node the links whose
+ * upstream point is solid (set J) and the links pointing into the solid (set
+ * K = the opposites of J) have equal counts.  The slip half of the wall rule
+ * hands each j in J the node's own population of one link k in K; when every
+ * k is handed out exactly once, the weights r and 1 - r of every into-wall
+ * population sum to one and mass is conserved exactly.  The pairing below
+ * picks, in this order of preference and each time over j in increasing
+ * direction index, among the links of K not yet handed out:
+ *   1. the reflection about a wall normal to y, (c_x, -c_y, -c_z) -- the
+ *      transverse reversal of the planar walls, so flat stretches of the
+ *      mask behave exactly as the slab;
+ *   2. the reflection about a wall normal to x, (-c_x, c_y, -c_z) -- step
+ *      faces, where the slip keeps the flow along the face;
+ *   3. the opposite -c_j (plain bounce-back);
+ *   4. the lowest-numbered link of K still free.
+ * Each pass maps distinct j to distinct k, so passes 1-3 commute with the
+ * mirror images x -> -x and y -> -y of the geometry. */
+static int find_dir(const ora_ctx *o, int cx, int cy, int cz) {
+  int k;
+  for (k = 0; k < o->q; k++)
+    if (o->c[k][0] == cx && o->c[k][1] == cy && o->c[k][2] == cz) return k;
+  return -1;
+}
+static void pair_slip_links(ora_ctx *o, int x, int y, int z, signed char *pt) {
+  int inJ[19], inK[19], taken[19], i, pass, k;
+  for (i = 0; i < 19; i++) {
+    inJ[i] = inK[i] = taken[i] = 0;
+    pt[i] = -1;
+  }
+  for (i = 1; i < o->q; i++) {
+    int sx, sy, sz;
+    upstream(o, x, y, z, i, &sx, &sy, &sz);
+    if (is_solid(o, sx, sy, sz)) {
+      inJ[i] = 1;
+      inK[o->opp[i]] = 1;
+    }
+  }
+  for (pass = 1; pass <= 4; pass++)
+    for (i = 1; i < o->q; i++) {
+      if (!inJ[i] || pt[i] >= 0) continue;
+      if (pass == 1) k = find_dir(o, o->c[i][0], -o->c[i][1], -o->c[i][2]);
+      else if (pass == 2) k = find_dir(o, -o->c[i][0], o->c[i][1], -o->c[i][2]);
+      else if (pass == 3) k = o->opp[i];
+      else
+        for (k = 1; k < o->q && !(inK[k] && !taken[k]); k++) {
+        }
+      if (k >= 0 && k < o->q && inK[k] && !taken[k]) {
+        pt[i] = (signed char)k;
+        taken[k] = 1;
+      }
+    }
+}
+
 /* ------------------------------------------------------------- life cycle */
 
 void ora_destroy(ora_ctx *o);
@@ -265,11 +328,15 @@ int ora_create(const ora_params *p, ora_ctx **out) {
   int x, y, z, i;
   *out = NULL;
   if (!(p->lattice == 9 || p->lattice == 19)) return ORA_EINVAL;
-  if (p->geometry < 0 || p->geometry > 2) return ORA_EINVAL;
+  if (p->geometry < 0 || p->geometry > 3) return ORA_EINVAL;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return ORA_EINVAL;
-  if (p->lattice == 9 && (p->nz != 1 || p->geometry != ORA_SLAB)) return ORA_EINVAL;
+  if (p->lattice == 9 &&
+      (p->nz != 1 || (p->geometry != ORA_SLAB && p->geometry != ORA_MASKED)))
+    return ORA_EINVAL;
   if (!(p->tau > 0.5)) return ORA_EINVAL;
-  if (p->wall_velocity_top != 0.0 && p->geometry == ORA_TUBE) return ORA_EINVAL;
+  if (p->wall_velocity_top != 0.0 && (p->geometry == ORA_TUBE || p->geometry == ORA_MASKED))
+    return ORA_EINVAL;
+  if (p->geometry == ORA_MASKED && !p->solid) return ORA_EINVAL;
   o = (ora_ctx *)calloc(1, sizeof(ora_ctx));
   if (!o) return ORA_ENOMEM;
   o->p = *p;
@@ -281,7 +348,14 @@ int ora_create(const ora_params *p, ora_ctx **out) {
   o->qlink = (real *)calloc(o->ncell * 19, sizeof(real));
   o->g = (real *)calloc(o->ncell * o->q, sizeof(real));
   o->gn = (real *)calloc(o->ncell * o->q, sizeof(real));
-  if (!o->fluid || !o->wall_id || !o->r || !o->qlink || !o->g || !o->gn) {
+  if (p->geometry == ORA_MASKED) {
+    o->mask = (unsigned char *)malloc((size_t)p->nx * p->ny);
+    o->partner = (signed char *)malloc((size_t)o->ncell * 19);
+    if (o->mask) memcpy(o->mask, p->solid, (size_t)p->nx * p->ny);
+  }
+  o->p.solid = NULL; /* the caller's array is not kept */
+  if (!o->fluid || !o->wall_id || !o->r || !o->qlink || !o->g || !o->gn ||
+      (p->geometry == ORA_MASKED && (!o->mask || !o->partner))) {
     ora_destroy(o);
     return ORA_ENOMEM;
   }
@@ -311,7 +385,12 @@ int ora_create(const ora_params *p, ora_ctx **out) {
           o->wall_id[n] = o->nwall++;
           o->r[n] = 1; /* default: no-slip bounce-back */
         }
+        if (p->geometry == ORA_MASKED) pair_slip_links(o, x, y, z, o->partner + n * 19);
       }
+  if (p->geometry == ORA_MASKED && o->nfluid == 0) {
+    ora_destroy(o);
+    return ORA_EINVAL;
+  }
   *out = o;
   return ORA_OK;
 }
@@ -325,6 +404,8 @@ void ora_destroy(ora_ctx *o) {
   free(o->wall_id);
   free(o->r);
   free(o->qlink);
+  free(o->mask);
+  free(o->partner);
   free(o->g);
   free(o->gn);
   free(o);
@@ -421,6 +502,8 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
     bb += 6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
           o->ue[shell_of(o, sy, zs) * o->p.nx + xs];
   }
+  if (o->p.geometry == ORA_MASKED)
+    return o->r[n] * bb + (1 - o->r[n]) * g[(long)o->partner[n * 19 + i] * o->ncell + n];
   return o->r[n] * bb + (1 - o->r[n]) * g[(long)o->sig[i] * o->ncell + n];
 }
 
@@ -609,7 +692,8 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
 int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
                       double force_e) {
   long n = nshell(o) * o->p.nx;
-  if (o->p.geometry == ORA_TUBE || o->p.wall_velocity_top != 0.0) return ORA_EINVAL;
+  if (o->p.geometry == ORA_TUBE || o->p.geometry == ORA_MASKED || o->p.wall_velocity_top != 0.0)
+    return ORA_EINVAL;
   if (!(tau_e > 0.5) || !(rho_e0 > 0) || !(gamma_e >= 0) || !isfinite(force_e) ||
       !isfinite(tau_e) || !isfinite(rho_e0) || !isfinite(gamma_e))
     return ORA_EINVAL;

@@ -23,6 +23,7 @@ DRIVER = r"""
 typedef struct {
   int lattice, precision, geometry, nx, ny, nz;
   double tube_radius, tube_cy, tube_cz, tau, rho0, force[3], wall_velocity_top;
+  const unsigned char *solid;
 } P;
 typedef struct {
   double T, omega0, gamma_s, omega_l, gamma_l, a_l, d;
@@ -50,7 +51,16 @@ void ora_set_populations(ora_ctx *, const double *, long);
 void ora_friction(const S *, const double *, long, double *, double *);
 
 static int run(int q, int geom, int nx, int ny, int nz, double R, int mode, int elec) {
-  P p = {q, 0, geom, nx, ny, nz, R, (ny - 1) / 2.0, (nz - 1) / 2.0, 0.8, 1.0, {1e-6, 0, 0}, 0};
+  P p = {q, 0, geom, nx, ny, nz, R, (ny - 1) / 2.0, (nz - 1) / 2.0, 0.8, 1.0, {1e-6, 0, 0}, 0, 0};
+  unsigned char *mask = calloc((size_t)nx * ny, 1);
+  if (geom == 3) { /* corrugated floor, a step in the ceiling, a post */
+    for (int x = 0; x < nx; x++) {
+      for (int y = 0; y < 1 + (x % 3); y++) mask[x + nx * y] = 1;
+      if (x >= nx / 2) mask[x + nx * (ny - 1)] = 1;
+    }
+    mask[nx / 3 + nx * (ny / 2)] = 1;
+    p.solid = mask;
+  }
   ora_ctx *o;
   if (ora_create(&p, &o)) return 1;
   long nw = ora_wall_count(o), nc = (long)nx * ny * nz;
@@ -74,7 +84,7 @@ static int run(int q, int geom, int nx, int ny, int nz, double R, int mode, int 
   ora_step(o, 3);
   if (elec) ora_get_electrons(o, ue, pe);
   if (!isfinite(inv[0]) || !isfinite(inv[1])) return 5;
-  free(lam); free(xyz); free(links); free(f); free(g); free(ue); free(pe);
+  free(lam); free(xyz); free(links); free(f); free(g); free(ue); free(pe); free(mask);
   ora_destroy(o);
   return 0;
 }
@@ -86,6 +96,8 @@ int main(void) {
   rc |= run(19, 0, 7, 5, 4, 0, 1, 1);
   rc |= run(19, 1, 9, 5, 6, 0, 2, 0);
   rc |= run(19, 2, 5, 14, 14, 5.0, 1, 0);
+  rc |= run(9, 3, 13, 9, 1, 0, 1, 0);
+  rc |= run(19, 3, 8, 10, 3, 0, 2, 0);
   for (int c = 0; c < 2; c++) {
     S s = {1.0, 2.0, 0.5, 3.0, 1.0, 0.5, 1.0, 9, 17, 10.0, 20.0, 0.05, 1, c, 0.4 * c};
     double om[3] = {1.5, 2.0, 2.5}, raw[3], lat[3];
