@@ -67,13 +67,27 @@ typedef enum { LBM_D2Q9 = 9, LBM_D3Q19 = 19 } lbm_lattice;
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_precision;
 
 /* SLAB: walls half a link below y = 0 and above y = ny-1, z periodic (D2Q9
- *       requires SLAB with nz = 1).
+ *       requires SLAB or MASKED with nz = 1).
  * DUCT: walls on both y and both z faces, half a link outside the box.
  * TUBE: circular wall of radius tube_radius around the x axis through
  *       (tube_cy, tube_cz); cells with (y-cy)^2 + (z-cz)^2 < R^2 are fluid;
  *       interpolated (Bouzidi) bounce-back at the curved wall.
+ * MASKED: walls that vary along x -- corrugated, wrinkled or stepped walls,
+ *       posts -- the design freedom of Sec. 5.1: the SLAB box with the
+ *       points of the (x, y) plane flagged in `solid` solid for every z
+ *       (z periodic).  Half-way bounce-back on every wall link; the slip
+ *       half of the wall rule takes, for each wall link i of a node, the
+ *       node's own population of one link k pointing into the solid, chosen
+ *       so that each such k serves exactly one i (mass stays exact): by
+ *       preference, over i in increasing direction index among the k still
+ *       free, the reflection (c_x, -c_y, -c_z) about a y-normal wall (the
+ *       SLAB's transverse reversal: an x-uniform mask is the SLAB exactly),
+ *       then (-c_x, c_y, -c_z) about an x-normal step face, then -c_i, then
+ *       the lowest-numbered free k.  Wall nodes are numbered as in every
+ *       geometry (increasing x + nx (y + ny z)).  No moving wall, no
+ *       electron sheets, no batches.
  * x is periodic in every geometry (inlet/outlet option 1 of Sec. 4.2). */
-typedef enum { LBM_SLAB = 0, LBM_DUCT = 1, LBM_TUBE = 2 } lbm_geometry;
+typedef enum { LBM_SLAB = 0, LBM_DUCT = 1, LBM_TUBE = 2, LBM_MASKED = 3 } lbm_geometry;
 
 typedef struct {
   int lattice;   /* lbm_lattice */
@@ -87,6 +101,10 @@ typedef struct {
   double wall_velocity_top; /* != 0: the y = ny-1/2 wall of SLAB/DUCT moves
                                along x at this speed as a no-slip wall
                                (Couette check); 0 otherwise */
+  const uint8_t *solid;     /* MASKED only: nx * ny bytes, host, index
+                               x + nx y, nonzero = solid; read by
+                               lbm_footprint / lbm_create only (not kept);
+                               ignored by the other geometries */
 } lbm_params;
 
 /* Synthetic surface-response spectra of the friction quadrature (units
@@ -206,7 +224,7 @@ lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
  * what the forces put in, gamma_e sum rho_e u_e = F_x N_fluid + force_e
  * N_lines; in a slab the sheets then move at one U_e and the water is the
  * slip-Poiseuille profile shifted by it.
- * Requires a SLAB or DUCT (a TUBE gives LBM_EINVAL), wall_velocity_top == 0,
+ * Requires a SLAB or DUCT (a TUBE or MASKED gives LBM_EINVAL), wall_velocity_top == 0,
  * tau_e > 1/2, rho_e0 > 0, gamma_e >= 0, finite values (else LBM_EINVAL);
  * tau_e == 0 switches the sheets off.
  * Fields, flux and mass (the moments the next collision would see) take
@@ -296,7 +314,7 @@ lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
  * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
  * lattice, precision, wall kind or thermal-noise form (lbm_set_thermal: one
  * form for the whole batch, each member its own kT and seed), one appears
- * twice, or one has electron sheets.  lbm_batch_step refuses a member whose
+ * twice, or one has electron sheets or MASKED walls.  lbm_batch_step refuses a member whose
  * noise form changed or whose sheets were switched on after the batch was
  * built, and takes up a changed kT or seed.  Batched members draw the same
  * thermal numbers as alone: results agree bit for bit. */

@@ -29,6 +29,45 @@ int lat_c(int Q, int i, int a) {
 
 // storage row of direction i within a column
 int lat_row(int Q, int i) { return Q == 9 ? lbm::D2Q9::row[i] : lbm::D3Q19::row[i]; }
+int lat_opp(int Q, int i) { return Q == 9 ? lbm::D2Q9::opp[i] : lbm::D3Q19::opp[i]; }
+int lat_dir(int Q, int cx, int cy, int cz) {
+  for (int k = 0; k < Q; k++)
+    if (lat_c(Q, k, 0) == cx && lat_c(Q, k, 1) == cy && lat_c(Q, k, 2) == cz) return k;
+  return -1;
+}
+
+// Slip partners at one node of a masked wall.  from_solid[i]: link i pulls
+// from a solid point (set J); the links pointing into the solid are their
+// opposites (set K, as many).  Each i in J gets one k in K and each k serves
+// one i, so the wall rule's weights r and 1 - r of every into-wall population
+// sum to one (exact mass).  Candidates in order of preference, each pass over
+// i in increasing index and among the k not yet taken: the reflection about a
+// y-normal wall (c_x, -c_y, -c_z), about an x-normal face (-c_x, c_y, -c_z),
+// the opposite, the lowest free k.  Within a pass distinct i have distinct
+// candidates, so the result does not depend on the order inside a pass.
+void slip_partners(int Q, const bool* from_solid, int* partner) {
+  bool into[19] = {}, taken[19] = {};
+  for (int i = 0; i < Q; i++) {
+    partner[i] = -1;
+    if (from_solid[i]) into[lat_opp(Q, i)] = true;
+  }
+  for (int pass = 0; pass < 4; pass++)
+    for (int i = 1; i < Q; i++) {
+      if (!from_solid[i] || partner[i] >= 0) continue;
+      const int cx = lat_c(Q, i, 0), cy = lat_c(Q, i, 1), cz = lat_c(Q, i, 2);
+      int k = -1;
+      if (pass == 0) k = lat_dir(Q, cx, -cy, -cz);
+      else if (pass == 1) k = lat_dir(Q, -cx, cy, -cz);
+      else if (pass == 2) k = lat_opp(Q, i);
+      else
+        for (int t = 1; t < Q && k < 0; t++)
+          if (into[t] && !taken[t]) k = t;
+      if (k > 0 && into[k] && !taken[k]) {
+        partner[i] = k;
+        taken[k] = true;
+      }
+    }
+}
 
 // Positive root s of |P - s C|^2 = R^2 with P inside and P - C outside the
 // circle (the fraction of the link from the fluid node to the wall).
@@ -48,18 +87,19 @@ lbm_status validate(const lbm_params* p, std::string* err) {
   if (!p) return fail("null parameters");
   if (p->lattice != 9 && p->lattice != 19) return fail("lattice must be 9 or 19");
   if (p->precision < 0 || p->precision > 2) return fail("bad precision");
-  if (p->geometry < 0 || p->geometry > 2) return fail("bad geometry");
+  if (p->geometry < 0 || p->geometry > 3) return fail("bad geometry");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail("sizes must be >= 1");
   if ((int64_t)p->ny * p->nz > (int64_t)1 << 28 || p->nx > (1 << 24)) return fail("box too large");
-  if (p->lattice == 9 && (p->nz != 1 || p->geometry != LBM_SLAB))
-    return fail("D2Q9 needs SLAB geometry with nz = 1");
+  if (p->lattice == 9 && (p->nz != 1 || (p->geometry != LBM_SLAB && p->geometry != LBM_MASKED)))
+    return fail("D2Q9 needs SLAB or MASKED geometry with nz = 1");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail("tau must be finite and > 0.5");
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail("rho0 must be finite and > 0");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(p->force[a])) return fail("force must be finite");
   if (!std::isfinite(p->wall_velocity_top)) return fail("wall velocity must be finite");
-  if (p->wall_velocity_top != 0.0 && p->geometry == LBM_TUBE)
+  if (p->wall_velocity_top != 0.0 && (p->geometry == LBM_TUBE || p->geometry == LBM_MASKED))
     return fail("moving top wall needs SLAB or DUCT");
+  if (p->geometry == LBM_MASKED && !p->solid) return fail("MASKED needs a solid mask");
   if (p->geometry == LBM_TUBE &&
       (!(p->tube_radius > 0.0) || !std::isfinite(p->tube_cy) || !std::isfinite(p->tube_cz)))
     return fail("tube needs radius > 0 and a finite centre");
@@ -90,9 +130,22 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.sI = pl.nxp;
   pl.sC = (int64_t)pl.Q * pl.nxp;
   pl.bouz = p->geometry == LBM_TUBE;
-  const bool slab = p->geometry == LBM_SLAB;
+  pl.masked = p->geometry == LBM_MASKED;
+  // z periodic
+  const bool slab = p->geometry == LBM_SLAB || pl.masked;
 
   std::vector<unsigned char> fluid(pl.ncolbox, 1);
+  if (pl.masked) {
+    // a column (y, z) holds storage when some x of its row is fluid
+    pl.solid.assign((size_t)p->nx * p->ny, 0);
+    for (int64_t k = 0; k < (int64_t)p->nx * p->ny; k++) pl.solid[k] = p->solid[k] != 0;
+    for (int z = 0; z < p->nz; z++)
+      for (int y = 0; y < p->ny; y++) {
+        bool any = false;
+        for (int x = 0; x < p->nx && !any; x++) any = !pl.solid[x + (int64_t)p->nx * y];
+        fluid[y + (int64_t)p->ny * z] = any ? 1 : 0;
+      }
+  }
   if (p->geometry == LBM_TUBE) {
     const double R2 = p->tube_radius * p->tube_radius;
     for (int z = 0; z < p->nz; z++)
@@ -116,7 +169,8 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
       const int64_t col = y + (int64_t)p->ny * z;
       if (!fluid[col]) continue;
       uint32_t mask = 0;
-      for (int i = 1; i < pl.Q; i++)
+      // masked walls: no column-wide wall links (the kernel classifies cells)
+      for (int i = 1; i < pl.Q && !pl.masked; i++)
         if (!fluid_at(y - lat_c(pl.Q, i, 1), z - lat_c(pl.Q, i, 2))) mask |= 1u << i;
       ColInfo ci{-1, mask};
       if (mask) {
@@ -172,6 +226,49 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   }
   pl.nfluid = (int64_t)pl.slots.size() * pl.nx;
   pl.nwall = nwc * pl.nx;
+  if (pl.masked) {
+    // classify the points of the (x, y) plane; 2-D wall nodes in increasing
+    // x + nx y, so that node (k, z) of the 3-D numbering is z nw2d + k
+    const int nx = p->nx, ny = p->ny;
+    auto solid_at = [&](int x, int y) {
+      if (y < 0 || y >= ny) return true;
+      x = ((x % nx) + nx) % nx;
+      return pl.solid[x + (int64_t)nx * y] != 0;
+    };
+    pl.cellw.assign((size_t)nx * ny, lbm::kCellSolid);
+    pl.ptab.clear();
+    pl.w2d.clear();
+    int64_t nf2 = 0;
+    for (int y = 0; y < ny; y++)
+      for (int x = 0; x < nx; x++) {
+        if (solid_at(x, y)) continue;
+        nf2++;
+        bool from_solid[19] = {};
+        bool wall = false;
+        for (int i = 1; i < pl.Q; i++) {
+          from_solid[i] = solid_at(x - lat_c(pl.Q, i, 0), y - lat_c(pl.Q, i, 1));
+          wall = wall || from_solid[i];
+        }
+        if (!wall) {
+          pl.cellw[x + (int64_t)nx * y] = lbm::kCellInterior;
+          continue;
+        }
+        int partner[19];
+        slip_partners(pl.Q, from_solid, partner);
+        for (int i = 0; i < pl.Q; i++) {
+          if (from_solid[i] && partner[i] < 0) {
+            if (err) *err = "internal: unpaired wall link";
+            return LBM_EINVAL;
+          }
+          pl.ptab.push_back(from_solid[i] ? (uint8_t)lat_row(pl.Q, partner[i]) : lbm::kNoLink);
+        }
+        pl.cellw[x + (int64_t)nx * y] = (int32_t)pl.w2d.size();
+        pl.w2d.push_back((int32_t)(x + nx * y));
+      }
+    pl.nw2d = (int64_t)pl.w2d.size();
+    pl.nfluid = nf2 * pl.nz;
+    pl.nwall = pl.nw2d * pl.nz;
+  }
   pl.bx = std::min((pl.nx + 63) / 64 * 64, 512);
   pl.segs = (pl.nx + pl.bx - 1) / pl.bx;
   pl.nblocks = (int64_t)pl.slots.size() * pl.segs;
@@ -181,7 +278,9 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   }
 
   // every load the step kernel issues must land on a fluid column of the box
+  // (masked walls: on a fluid point, by the classification above)
   for (const lbm::ColSlot& cs : pl.slots) {
+    if (pl.masked) break;
     const int col = cs.col;
     const int y = col % p->ny, z = col / p->ny;
     const ColInfo ci{cs.wallcol, cs.mask};
@@ -204,7 +303,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     }
   }
 
-  if (p->geometry != LBM_TUBE) {
+  if (p->geometry == LBM_SLAB || p->geometry == LBM_DUCT) {
     // electron shells: the solid columns next to the water, y = -1 and y = ny
     // (by z), then for a duct z = -1 and z = nz (by y); each couples to one
     // fluid column, whose wall column is recorded
@@ -249,6 +348,8 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_e[1] = take((size_t)pl.nsheet * 3 * sizeof(double));
   pl.off_ue = take((size_t)pl.nsheet * sizeof(double));
   pl.off_swc = take(pl.sheet_wc.size() * sizeof(int32_t));
+  pl.off_cellw = take(pl.cellw.size() * sizeof(int32_t));
+  pl.off_ptab = take(pl.ptab.size());
   pl.total = off;
   return LBM_OK;
 }
@@ -302,6 +403,9 @@ void fill_args(lbm_ctx* c) {
   a.th_mode = 0;
   a.th_seed = 0;
   a.ue = nullptr;
+  a.cellw = pl.masked ? c->at<int32_t>(pl.off_cellw) : nullptr;
+  a.ptab = pl.masked ? c->at<uint8_t>(pl.off_ptab) : nullptr;
+  a.nw2d = pl.nw2d;
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -350,7 +454,7 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
   const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode,
-                                        c->elec);
+                                        c->elec, c->pl.masked);
   const void* fe = c->elec ? lbm::electron_kernel_ptr(c->pl.Q, c->pl.prec) : nullptr;
   const double* esrc[2] = {c->at<double>(c->pl.off_e[parity]), c->at<double>(c->pl.off_e[1 - parity])};
   double* edst[2] = {c->at<double>(c->pl.off_e[1 - parity]), c->at<double>(c->pl.off_e[parity])};
@@ -517,6 +621,10 @@ lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void
     if (!pl.sheet_wc.empty() &&
         (st = upload(c, pl.off_swc, pl.sheet_wc.data(), pl.sheet_wc.size() * sizeof(int32_t))) != LBM_OK)
       break;
+    if (pl.masked &&
+        ((st = upload(c, pl.off_cellw, pl.cellw.data(), pl.cellw.size() * sizeof(int32_t))) != LBM_OK ||
+         (st = upload(c, pl.off_ptab, pl.ptab.data(), pl.ptab.size())) != LBM_OK))
+      break;
     std::vector<double> inf(pl.nwall, INFINITY);
     std::vector<double> ones(pl.nwall, 1.0);
     if ((st = upload(c, pl.off_lambda, inf.data(), inf.size() * sizeof(double))) != LBM_OK) break;
@@ -564,6 +672,15 @@ lbm_status lbm_wall_coords(const lbm_ctx* c, int32_t* xyz) {
   if (!c || (!xyz && c->pl.nwall)) return LBM_EINVAL;
   const Plan& pl = c->pl;
   int64_t k = 0;
+  if (pl.masked) {
+    for (int z = 0; z < pl.nz; z++)
+      for (int64_t w = 0; w < pl.nw2d; w++, k++) {
+        xyz[3 * k] = pl.w2d[w] % pl.nx;
+        xyz[3 * k + 1] = pl.w2d[w] / pl.nx;
+        xyz[3 * k + 2] = z;
+      }
+    return LBM_OK;
+  }
   for (size_t w = 0; w < pl.wallcols.size(); w++) {
     const int col = pl.wallcols[w];
     for (int x = 0; x < pl.nx; x++, k++) {
@@ -579,6 +696,13 @@ lbm_status lbm_wall_links(const lbm_ctx* c, double* links) {
   if (!c || (!links && c->pl.nwall)) return LBM_EINVAL;
   const Plan& pl = c->pl;
   int64_t k = 0;
+  if (pl.masked) {  // half-way bounce-back on every wall link
+    for (int z = 0; z < pl.nz; z++)
+      for (int64_t w = 0; w < pl.nw2d; w++, k++)
+        for (int i = 0; i < pl.Q; i++)
+          links[k * pl.Q + i] = pl.ptab[w * pl.Q + i] != lbm::kNoLink ? 0.5 : 0.0;
+    return LBM_OK;
+  }
   for (size_t w = 0; w < pl.wallcols.size(); w++)
     for (int x = 0; x < pl.nx; x++, k++)
       for (int i = 0; i < pl.Q; i++) links[k * pl.Q + i] = pl.linkq[w * pl.Q + i];
@@ -689,7 +813,7 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   if (!c) return LBM_EINVAL;
   const bool on = tau_e != 0.0;
   if (on) {
-    if (c->p.geometry == LBM_TUBE || c->p.wall_velocity_top != 0.0)
+    if ((c->p.geometry != LBM_SLAB && c->p.geometry != LBM_DUCT) || c->p.wall_velocity_top != 0.0)
       return c->fail(LBM_EINVAL, "electron sheets need a SLAB or DUCT without a moving wall");
     if (!(tau_e > 0.5) || !(rho_e0 > 0.0) || !(gamma_e >= 0.0) || !std::isfinite(tau_e) ||
         !std::isfinite(rho_e0) || !std::isfinite(gamma_e) || !std::isfinite(force_e))
@@ -812,10 +936,11 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* host_out) {
   for (int i = 0; i < pl.Q; i++)
     for (int64_t col = 0; col < pl.ncolbox; col++) {
       const bool solid = pl.colinfo[col].mask & lbm::kSolidColumn;
+      const int y = (int)(col % pl.ny);
       for (int x = 0; x < pl.nx; x++) {
         const int64_t src = col * pl.sC + lat_row(pl.Q, i) * pl.sI + x;
         double v = 0.0;
-        if (!solid) {
+        if (!solid && !(pl.masked && pl.solid[x + (int64_t)pl.nx * y])) {
           if (pl.prec == LBM_F64) v = reinterpret_cast<const double*>(raw.data())[src];
           else if (pl.prec == LBM_F32) v = reinterpret_cast<const float*>(raw.data())[src];
           else v = (double)(float)reinterpret_cast<const _Float16*>(raw.data())[src] / 4096.0;
@@ -836,6 +961,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) 
     for (int64_t col = 0; col < pl.ncolbox; col++) {
       if (pl.colinfo[col].mask & lbm::kSolidColumn) continue;
       for (int x = 0; x < pl.nx; x++) {
+        if (pl.masked && pl.solid[x + (int64_t)pl.nx * (col % pl.ny)]) continue;
         const double v = host_in[((int64_t)i * pl.ncolbox + col) * pl.nx + x];
         if (!(std::fabs(v) <= vmax))
           return c->fail(LBM_EINVAL, "population %d at column %lld, x %d is %g: NaN or beyond "
@@ -849,7 +975,10 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) 
       for (int x = 0; x < pl.nxp; x++) {
         // padding lanes take the value of cell nx - 1, as the step writes them
         const int xs = x < pl.nx ? x : pl.nx - 1;
-        const double v = host_in[((int64_t)i * pl.ncolbox + col) * pl.nx + xs];
+        // solid points of masked walls hold zero (nothing reads them)
+        const double v = pl.masked && pl.solid[xs + (int64_t)pl.nx * (col % pl.ny)]
+                             ? 0.0
+                             : host_in[((int64_t)i * pl.ncolbox + col) * pl.nx + xs];
         const int64_t dst = col * pl.sC + lat_row(pl.Q, i) * pl.sI + x;
         if (pl.prec == LBM_F64) reinterpret_cast<double*>(raw.data())[dst] = v;
         else if (pl.prec == LBM_F32) reinterpret_cast<float*>(raw.data())[dst] = (float)v;

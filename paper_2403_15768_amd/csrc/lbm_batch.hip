@@ -237,8 +237,9 @@ lbm_status check_members(lbm_ctx* const* ctxs, int n) {
         (a.geometry == LBM_TUBE) != (b.geometry == LBM_TUBE))
       return LBM_EINVAL;
     // one noise form for the whole batch (each member its own kT and seed);
-    // the batch kernel has no electron sheets
-    if (ctxs[m]->args.th_mode != ctxs[0]->args.th_mode || ctxs[m]->elec) return LBM_EINVAL;
+    // the batch kernel has no electron sheets and no masked walls
+    if (ctxs[m]->args.th_mode != ctxs[0]->args.th_mode || ctxs[m]->elec || ctxs[m]->pl.masked)
+      return LBM_EINVAL;
   }
   return LBM_OK;
 }

@@ -61,6 +61,11 @@ constexpr uint32_t kSolidColumn = 0x80000000u;
 // a fluid column whose pulls wrap around the periodic z boundary (slab)
 constexpr uint32_t kWrapColumn = 0x40000000u;
 constexpr uint32_t kLinkBits = 0x000fffffu;
+// masked walls: cell classes of the (x, y) plane (>= 0: 2-D wall-node index)
+// and the partner-table entry of a link whose upstream point is fluid
+constexpr int32_t kCellInterior = -1;
+constexpr int32_t kCellSolid = -2;
+constexpr uint8_t kNoLink = 0xff;
 
 struct ColInfo {
   int32_t wallcol;  // index among wall columns, -1 for columns without wall links
@@ -106,6 +111,14 @@ struct StepArgs {
   // the step being taken, [shell][x]; shells y = -1, y = ny (by z), then for
   // a duct z = -1, z = nz (by y)
   const double* ue;
+  // masked walls (walls that vary along x; null for the other geometries):
+  // cellw[x + nx y] is the class of the point (kCellSolid, kCellInterior or
+  // the 2-D wall-node index k), ptab[k Q + i] the storage row of the slip
+  // partner of wall link i (kNoLink if the link pulls from a fluid point),
+  // and the wall weight of node (k, z) is rwall[z nw2d + k]
+  const int32_t* cellw;
+  const uint8_t* ptab;
+  int64_t nw2d;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
@@ -373,6 +386,47 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
     }
     const M gs = dec<S, M>(ow[L::sig[i]]);
     df[i] = gs + r * (bb - gs);
+  }
+}
+
+// Pull gather on masked walls (walls that vary along x).  cw is the class of
+// the cell's point of the (x, y) plane: kCellInterior pulls every link; a
+// wall node (cw >= 0) takes, for each link i whose upstream point is solid,
+//   df_i = r BB_i + (1 - r) g_p(i)(x),   BB_i = g_opp(i)(x) (half-way),
+// with p(i) its slip partner (the table holds p's storage row), evaluated as
+// g + r (bb - g) like the column-wide rule.  z is periodic.  The class varies
+// along x, so lanes of one wave may take different branches.
+template <class L, typename S, typename M, typename W>
+__device__ __forceinline__ void gather_masked(const S* __restrict__ g0, const StepArgs& a,
+                                              int col, int z, int x, int cw, M* df) {
+  const LBM_GLOBAL S* g = gbl(g0);
+  const int64_t sI = a.sI;
+  const unsigned ux = (unsigned)x;
+  const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
+  const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
+  const bool wrap = L::Q == 19 && (z == 0 || z == a.nz - 1);
+  const LBM_GLOBAL S* gown = g + (int64_t)col * a.sC;
+  if (cw < 0) {
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      const LBM_GLOBAL S* line = gown + src_off<L>(a, i, z, wrap);
+      df[i] = ld<S, M>(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+    }
+    return;
+  }
+  const LBM_GLOBAL uint8_t* pt = gbl(a.ptab) + (int64_t)cw * L::Q;
+  const M r = static_cast<M>(gbl(static_cast<const W*>(a.rwall))[(int64_t)z * a.nw2d + cw]);
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    const unsigned prow = pt[i];
+    if (prow == kNoLink) {
+      const LBM_GLOBAL S* line = gown + src_off<L>(a, i, z, wrap);
+      df[i] = ld<S, M>(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+    } else {
+      const M bb = ld<S, M>(sbase(gown + L::row[L::opp[i]] * sI), ux);
+      const M gs = ld<S, M>(gown + (int64_t)prow * sI, ux);
+      df[i] = gs + r * (bb - gs);
+    }
   }
 }
 

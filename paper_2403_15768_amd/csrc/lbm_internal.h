@@ -36,6 +36,17 @@ struct Plan {
   int bx = 0, segs = 0;
   int64_t nblocks = 0;
   bool bouz = false;
+  // MASKED: per point of the (x, y) plane its 2-D wall-node index, or
+  // kCellInterior / kCellSolid; per 2-D wall node and link the storage row of
+  // the slip partner (kNoLink: the upstream point is fluid); the 2-D wall
+  // nodes' x + nx y in increasing order
+  bool masked = false;
+  std::vector<unsigned char> solid;  // [x + nx y]
+  std::vector<int32_t> cellw;
+  std::vector<uint8_t> ptab;
+  std::vector<int32_t> w2d;
+  int64_t nw2d = 0;
+  size_t off_cellw = 0, off_ptab = 0;
   int64_t nsheet = 0;               // electron sheet nodes (SLAB: 2 nz nx; else 0)
   std::vector<int32_t> sheet_wc;    // [sheet][z]: wall column next to the sheet
   // arena offsets

@@ -64,6 +64,34 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
                                 (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
 }
 
+// Masked walls: the same update on every fluid point of the columns that
+// hold one; the class of each point (solid, interior, wall node) comes from
+// a table of the (x, y) plane, so a wave may hold all three.  Solid points
+// are neither computed nor stored (nothing reads them); columns are visited
+// in one order or the reverse, as above.
+template <class L, typename S, typename M, int TH>
+__global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
+                                                     S* __restrict__ dst, StepArgs a) {
+  int slot = blockIdx.x;
+  if (a.rev) slot = a.nactive - 1 - slot;
+  const int x = blockIdx.y * a.bx + threadIdx.x;
+  if (x >= a.nxp) return;
+  const int xc = x < a.nx ? x : a.nx - 1;  // padding lanes: cell nx - 1 again
+  const int col = uniform(gbl(a.slots)[slot].col);
+  const int z = col / a.ny;
+  const int y = col - z * a.ny;
+  const int cw = gbl(a.cellw)[xc + (int64_t)a.nx * y];
+  if (cw == kCellSolid) return;
+  const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
+  M df[L::Q];
+  M xi[L::Q];
+  if constexpr (TH != 0)
+    thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+  gather_masked<L, S, M, M>(src, a, col, z, xc, cw, df);
+  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                             (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+}
+
 // ------------------------------------------------------------ electron sheets
 // One electron step per shell node (lines along x, D1Q3: c = 0, +1, -1,
 // w = 2/3, 1/6, 1/6, shifted populations [i][shell][x] in double):
@@ -138,7 +166,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <class L, typename S, typename W, bool BOUZ, bool ELEC = false>
+template <class L, typename S, typename W, bool BOUZ, bool ELEC = false, bool MASKED = false>
 __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, StepArgs a,
                                                  int which, double* __restrict__ field,
                                                  double* __restrict__ partials) {
@@ -147,15 +175,21 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
   const int seg = blockIdx.x - slot * a.segs;
   const int x = seg * a.bx + threadIdx.x;
   double jx_cell = 0.0, drho_cell = 0.0;
-  if (x < a.nx) {
-    const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[slot];
-    const int col = uniform(cs.col);
-    ColInfo info;
-    info.wallcol = uniform(cs.wallcol);
-    info.mask = (uint32_t)uniform((int)cs.mask);
+  const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[slot];
+  const int col = uniform(cs.col);
+  // masked walls: solid points contribute nothing (their field stays zero)
+  const int cw = MASKED && x < a.nx ? gbl(a.cellw)[x + (int64_t)a.nx * (col % a.ny)] : 0;
+  if (x < a.nx && !(MASKED && cw == kCellSolid)) {
     double df[L::Q];
-    // with electron sheets the wall moves with u_e of the last step
-    gather<L, S, double, W, BOUZ, ELEC>(src, a, col, x, info, df);
+    if constexpr (MASKED) {
+      gather_masked<L, S, double, W>(src, a, col, col / a.ny, x, cw, df);
+    } else {
+      ColInfo info;
+      info.wallcol = uniform(cs.wallcol);
+      info.mask = (uint32_t)uniform((int)cs.mask);
+      // with electron sheets the wall moves with u_e of the last step
+      gather<L, S, double, W, BOUZ, ELEC>(src, a, col, x, info, df);
+    }
     double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
@@ -727,7 +761,12 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 
 // the step kernel for a wall kind and a noise form (0: none)
 template <class L, typename S, typename M>
-static const void* step_kernel_t(bool bouz, int th_mode, bool elec) {
+static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked) {
+  if (masked) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 1>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 2>);
+    return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 0>);
+  }
   if (elec) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 1, true>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 2, true>);
@@ -751,8 +790,9 @@ static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, b
   S* d = static_cast<S*>(dst);
   StepArgs args = a;
   void* kargs[3] = {(void*)&s, (void*)&d, (void*)&args};
-  return hipLaunchKernel(step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr), grid, block,
-                         kargs, 0, st);
+  return hipLaunchKernel(
+      step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr, a.cellw != nullptr), grid, block,
+      kargs, 0, st);
 }
 
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
@@ -767,8 +807,8 @@ hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepAr
   return launch_step_t<D3Q19, _Float16, float>(src, dst, a, bouz, st);
 }
 
-const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec) {
-#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec)
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec, bool masked) {
+#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec, masked)
   if (q == 9) {
     if (prec == 0) return KP(D2Q9, double, double);
     if (prec == 1) return KP(D2Q9, float, double);
@@ -805,7 +845,10 @@ template <class L, typename S, typename W>
 static hipError_t launch_moments_t(const void* src, const StepArgs& a, bool bouz, int which,
                                    double* field, double* partials, hipStream_t st) {
   const dim3 grid((unsigned)((int64_t)a.nactive * a.segs)), block(a.bx);
-  if (bouz)
+  if (a.cellw)
+    hipLaunchKernelGGL((k_moments<L, S, W, false, false, true>), grid, block, 0, st,
+                       (const S*)src, a, which, field, partials);
+  else if (bouz)
     hipLaunchKernelGGL((k_moments<L, S, W, true>), grid, block, 0, st, (const S*)src, a, which,
                        field, partials);
   else if (a.ue)

@@ -34,8 +34,9 @@ struct ElecArgs {
 
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
-                       hipStream_t st);  // a.ue != nullptr: the electron-sheet walls
-const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec);
+                       hipStream_t st);  // a.ue: electron-sheet walls; a.cellw: masked walls
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec,
+                            bool masked);
 // one electron step from the water state g (step n): e_src -> e_dst, u_e of
 // step n -> ue; the water step of step n then reads ue
 hipError_t launch_electron_step(int q, int prec, const void* g, const double* e_src,

@@ -18,6 +18,10 @@ lattice spacing of 1 nm):
   g 1e-6, per-wall-node friction from the spectral quadrature.
 * ``batch``      256 ducts with sizes uniform in [32,128] x [32,64] x [32,64].
 * ``serving``    Poisson arrivals (50/s) of tube queries with radius 8..32.
+* ``corrugated`` D3Q19 slab 256 x 128 x 64 whose two walls are wrinkled
+  (Sec. 5.1: the wall's shape as a design parameter): staircase sinusoids of
+  amplitude 4 cells and wavelength 64 along x, random phases, friction as the
+  duct's smooth random field.
 """
 from __future__ import annotations
 
@@ -27,7 +31,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 SEED_BASE = 240315768
-WORKLOAD_ID = {"channel2d": 1, "duct": 2, "tube": 3, "batch": 4, "serving": 5}
+WORKLOAD_ID = {"channel2d": 1, "duct": 2, "tube": 3, "batch": 4, "serving": 5,
+               "corrugated": 6}
 
 
 def rng_for(workload: str, index: int = 0) -> np.random.Generator:
@@ -101,6 +106,27 @@ class SpectralDraw:
     @property
     def w_max(self) -> float:
         return 20.0 * self.T
+
+
+def corrugated_mask(nx: int, ny: int, rng: np.random.Generator, amp: float = 4.0,
+                    wavelength: float = 64.0, base: int = 4, post: bool = False) -> np.ndarray:
+    """Solid points, shaped (ny, nx), of a slab with wrinkled walls: the
+    bottom wall fills y < lo(x), the top one y >= ny - hi(x), each
+    round(base + amp sin(2 pi x / wavelength + phase)) with a random phase
+    (base >= amp keeps both >= 0).  post: a free-standing 3 x 3 post in the
+    middle of the channel as well."""
+    x = np.arange(nx)
+    ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+    lo = np.round(base + amp * np.sin(2.0 * math.pi * x / wavelength + ph[0])).astype(int)
+    hi = np.round(base + amp * np.sin(2.0 * math.pi * x / wavelength + ph[1])).astype(int)
+    solid = np.zeros((ny, nx), dtype=bool)
+    for i in range(nx):
+        solid[: max(lo[i], 0), i] = True
+        solid[ny - max(hi[i], 0):, i] = True
+    if post:
+        cx, cy = nx // 2, ny // 2
+        solid[cy - 1:cy + 2, cx - 1:cx + 2] = True
+    return solid
 
 
 def draw_spectral(rng: np.random.Generator, nq: int = 256, nw: int = 1024) -> SpectralDraw:

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 D2Q9, D3Q19 = 9, 19
 F64, F32, F16S = 0, 1, 2
-SLAB, DUCT, TUBE = 0, 1, 2
+SLAB, DUCT, TUBE, MASKED = 0, 1, 2, 3
 PRECISION = {"f64": F64, "f32": F32, "f16s": F16S}
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
@@ -39,6 +39,7 @@ class Params(C.Structure):
         ("tau", C.c_double), ("rho0", C.c_double),
         ("force", C.c_double * 3),
         ("wall_velocity_top", C.c_double),
+        ("solid", C.c_void_p),
     ]
 
 
@@ -151,7 +152,10 @@ def _dptr(a: np.ndarray):
 def make_params(lattice: int, geometry: int, nx: int, ny: int, nz: int, tau: float,
                 force=(0.0, 0.0, 0.0), precision="f32", rho0: float = 1.0,
                 tube_radius: float = 0.0, tube_cy: float = 0.0, tube_cz: float = 0.0,
-                wall_velocity_top: float = 0.0) -> Params:
+                wall_velocity_top: float = 0.0, solid=None) -> Params:
+    """Creation parameters.  ``solid`` (MASKED only): the solid points of the
+    (x, y) plane, array-like shaped (ny, nx), nonzero = solid; the Params
+    object keeps its own copy alive."""
     p = Params()
     p.lattice, p.geometry = lattice, geometry
     p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -160,6 +164,12 @@ def make_params(lattice: int, geometry: int, nx: int, ny: int, nz: int, tau: flo
     p.tau, p.rho0 = tau, rho0
     p.force = (C.c_double * 3)(*force)
     p.wall_velocity_top = wall_velocity_top
+    if solid is not None:
+        mask = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
+        if mask.shape != (ny, nx):
+            raise ValueError(f"solid mask must be shaped (ny, nx) = {(ny, nx)}")
+        p._solid = mask
+        p.solid = mask.ctypes.data
     return p
 
 
@@ -192,12 +202,13 @@ class Channel:
     def __init__(self, lattice: int, geometry: int, nx: int, ny: int, nz: int, tau: float,
                  force=(0.0, 0.0, 0.0), precision="f32", rho0: float = 1.0,
                  tube_radius: float = 0.0, tube_cy: float = 0.0, tube_cz: float = 0.0,
-                 wall_velocity_top: float = 0.0, device: str = "cuda", stream=None):
+                 wall_velocity_top: float = 0.0, device: str = "cuda", stream=None,
+                 solid=None):
         import torch  # device memory and streams only
 
         self._lib = load()
         self.params = make_params(lattice, geometry, nx, ny, nz, tau, force, precision, rho0,
-                                  tube_radius, tube_cy, tube_cz, wall_velocity_top)
+                                  tube_radius, tube_cy, tube_cz, wall_velocity_top, solid)
         self.nbytes = footprint(self.params)
         dev = torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=dev)

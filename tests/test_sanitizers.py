@@ -112,16 +112,22 @@ int main(void) {
 
 HOST_DRIVER = r"""
 #include <stdio.h>
+#include <stdlib.h>
 #include "lbm.h"
 int main(void) {
   int bad = 0;
-  for (int geom = 0; geom < 3; geom++)
+  for (int geom = 0; geom < 4; geom++)
     for (int q = 9; q <= 19; q += 10)
       for (int prec = 0; prec < 3; prec++)
         for (int nx = 1; nx <= 300; nx += 37)
           for (int ny = 1; ny <= 40; ny += 13) {
-            if (q == 9 && geom != LBM_SLAB) continue;
+            if (q == 9 && geom != LBM_SLAB && geom != LBM_MASKED) continue;
             lbm_params p = {0};
+            uint8_t *mask = (uint8_t *)calloc((size_t)nx * (ny + 9), 1);
+            for (int x = 0; x < nx; x++) /* steps on the floor, a post */
+              for (int y = 0; y < (x / 5) % 3 && y < ny; y++) mask[x + nx * y] = 1;
+            if (ny > 4) mask[nx / 2 + nx * (ny / 2)] = 1;
+            p.solid = mask;
             p.lattice = q; p.precision = prec; p.geometry = geom;
             p.nx = nx; p.ny = geom == LBM_TUBE ? 2 * (ny / 2) + 9 : ny;
             p.nz = q == 9 ? 1 : (geom == LBM_TUBE ? p.ny : ny / 2 + 1);
@@ -130,6 +136,7 @@ int main(void) {
             size_t b = 0;
             lbm_status s = lbm_footprint(&p, &b);
             if (s == LBM_OK && b == 0) bad++;
+            free(mask);
           }
   lbm_params p = {0};
   p.lattice = 19; p.tau = 0.4;  /* rejected parameters */
