@@ -56,6 +56,18 @@ def make_duct(lbm, inputs, precision):
     return ch
 
 
+def make_corrugated(lbm, inputs, precision):
+    """The 256 x 128 x 64 slab with wrinkled walls (amplitude 4, wavelength 64
+    along x) and the duct's smooth random friction field."""
+    nx, ny, nz = DUCT
+    solid = inputs.corrugated_mask(nx, ny, inputs.rng_for("corrugated", 0))
+    ch = lbm.Channel(lbm.D3Q19, lbm.MASKED, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
+                     precision=precision, solid=solid)
+    lam = inputs.duct_friction(ch.wall_coords(), nx, ny, nz, inputs.rng_for("corrugated", 1))
+    ch.set_friction(lam)
+    return ch
+
+
 def timed_run(torch, ch, steps, check_every):
     """Run `steps` steps with an FP64 flux/mass check every `check_every`.
     Returns wall seconds and the summed HIP-event time of the step chunks
@@ -184,6 +196,16 @@ def extras(torch, lbm, inputs, args):
                      "step_us": round(kms * 1e3 / 2000, 2),
                      "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
         ch.close()
+    # walls that vary along x: the wrinkled slab (masked walls)
+    ch = make_corrugated(lbm, inputs, "f32")
+    ch.step(200)
+    wall, kms = timed_run(torch, ch, 2000, 1000)
+    cells = ch.fluid_count
+    out["corrugated_f32"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                             "kernel_us": round(kms * 1e3 / 2000, 2),
+                             "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
+                                               / HBM_PEAK_GBS, 4)}
+    ch.close()
     # the benchmark duct with electron lines on all four walls
     ch = make_duct(lbm, inputs, "f32")
     ch.set_electrons(0.9, 1.0, 0.05, 1e-6)
@@ -362,7 +384,7 @@ def main():
     ap.add_argument("--electrons", action="store_true",
                     help="with --workload slab: electron sheets on both walls")
     ap.add_argument("--workload", default="duct",
-                    choices=["duct", "slab", "batch", "serving", "permeability"],
+                    choices=["duct", "slab", "corrugated", "batch", "serving", "permeability"],
                     help="duct: the headline line; batch / serving: their own JSON line")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-precisions", default="f64,f32,f16s",
@@ -395,7 +417,8 @@ def main():
             args.precision = "f64"
         return permeability_workload(args)
     slab = args.workload == "slab"
-    log("bench:", "slab" if slab else "duct", "256x128x64", args.precision, "steps", args.steps)
+    corr = args.workload == "corrugated"
+    log("bench:", args.workload, "256x128x64", args.precision, "steps", args.steps)
     if slab:  # walls on y only (z periodic), uniform friction, optional electron sheets
         nx, ny, nz = DUCT
         ch = lbm.Channel(lbm.D3Q19, lbm.SLAB, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
@@ -403,6 +426,8 @@ def main():
         ch.set_friction(0.05)
         if args.electrons:
             ch.set_electrons(0.9, 1.0, 0.05, 1e-6)
+    elif corr:
+        ch = make_corrugated(lbm, inputs, args.precision)
     else:
         ch = make_duct(lbm, inputs, args.precision)
     if args.thermal:
@@ -422,7 +447,8 @@ def main():
     log(f"bench: {mlups:.1f} MLUPS, step kernel {kern_s * 1e6:.2f} us, {achieved:.0f} GB/s")
 
     traffic = None
-    if os.path.exists(COUNTERS) and args.precision == "f32" and not args.thermal and not slab:
+    if (os.path.exists(COUNTERS) and args.precision == "f32" and not args.thermal
+            and args.workload == "duct"):
         c = json.load(open(COUNTERS))
         if c.get("kernel_hash") == kernel_hash():
             traffic = c.get("bytes_per_launch")
@@ -458,13 +484,15 @@ def main():
         "vs_baseline": None,
         "dtype": arith,
         "data": "synthetic",
-        "config": {"workload": f"{'slab' if slab else 'duct'}_256x128x64_d3q19_{args.precision}storage"
+        "config": {"workload": f"{args.workload}_256x128x64_d3q19_{args.precision}storage"
                                + ("", "_thermal_stress", "_thermal_all")[args.thermal]
                                + ("_electrons" if slab and args.electrons else ""),
                    "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
                    "g": 1e-6, "storage": args.precision, "arithmetic": arith,
                    "friction": ("uniform lambda 0.05" if slab else
                                 "smooth random lambda(x,s): mean 0.05, std 0.02, corr. length 16"),
+                   "walls": ("wrinkled: staircase sinusoids, amplitude 4, wavelength 64"
+                             if corr else "planar"),
                    "electrons": ("sheets on both walls: tau_e 0.9, rho_e0 1, gamma_e 0.05, "
                                  "force_e 1e-6") if slab and args.electrons else None,
                    "check_every": args.check_every,
@@ -473,7 +501,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_GBs": None if traffic is None else round(traffic / kern_s / 1e9, 1),
-                     "kernel": ("k_step<D3Q19>" if not args.thermal else
+                     "kernel": ("k_step_masked<D3Q19>" if corr else
+                                "k_step<D3Q19>" if not args.thermal else
                                 f"k_step<D3Q19, noise {args.thermal}>")
                                + (" + k_electron_step (time per step covers both)"
                                   if slab and args.electrons else ""),

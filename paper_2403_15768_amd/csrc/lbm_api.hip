@@ -236,6 +236,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
       return pl.solid[x + (int64_t)nx * y] != 0;
     };
     pl.cellw.assign((size_t)nx * ny, lbm::kCellSolid);
+    pl.pstride = (pl.Q + 3) / 4 * 4;  // whole 32-bit words per node
     pl.ptab.clear();
     pl.w2d.clear();
     int64_t nf2 = 0;
@@ -255,12 +256,13 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
         }
         int partner[19];
         slip_partners(pl.Q, from_solid, partner);
-        for (int i = 0; i < pl.Q; i++) {
-          if (from_solid[i] && partner[i] < 0) {
+        for (int i = 0; i < pl.pstride; i++) {
+          if (i < pl.Q && from_solid[i] && partner[i] < 0) {
             if (err) *err = "internal: unpaired wall link";
             return LBM_EINVAL;
           }
-          pl.ptab.push_back(from_solid[i] ? (uint8_t)lat_row(pl.Q, partner[i]) : lbm::kNoLink);
+          pl.ptab.push_back(i < pl.Q && from_solid[i] ? (uint8_t)lat_row(pl.Q, partner[i])
+                                                      : lbm::kNoLink);
         }
         pl.cellw[x + (int64_t)nx * y] = (int32_t)pl.w2d.size();
         pl.w2d.push_back((int32_t)(x + nx * y));
@@ -268,6 +270,20 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     pl.nw2d = (int64_t)pl.w2d.size();
     pl.nfluid = nf2 * pl.nz;
     pl.nwall = pl.nw2d * pl.nz;
+    // columns whose row holds a wall node first, flagged (mask 1): only their
+    // blocks classify points; every other column is wholly interior (a row
+    // with both fluid and solid points has wall nodes)
+    std::vector<char> wallrow(ny, 0);
+    for (int32_t w : pl.w2d) wallrow[w / nx] = 1;
+    std::vector<lbm::ColSlot> first, rest;
+    for (lbm::ColSlot cs : pl.slots) {
+      const int y = cs.col % ny;
+      cs.mask = wallrow[y] ? 1u : 0u;
+      (wallrow[y] ? first : rest).push_back(cs);
+    }
+    pl.nwallslots = (int64_t)first.size();
+    pl.slots = first;
+    pl.slots.insert(pl.slots.end(), rest.begin(), rest.end());
   }
   pl.bx = std::min((pl.nx + 63) / 64 * 64, 512);
   pl.segs = (pl.nx + pl.bx - 1) / pl.bx;
@@ -384,7 +400,7 @@ void fill_args(lbm_ctx* c) {
   a.sI = pl.sI;
   a.sC = pl.sC;
   a.nactive = (int)pl.slots.size();
-  a.nwallcols = (int)pl.wallcols.size();
+  a.nwallcols = pl.masked ? (int)pl.nwallslots : (int)pl.wallcols.size();
   a.rev = 0;
   a.bx = pl.bx;
   a.segs = pl.segs;
@@ -700,7 +716,7 @@ lbm_status lbm_wall_links(const lbm_ctx* c, double* links) {
     for (int z = 0; z < pl.nz; z++)
       for (int64_t w = 0; w < pl.nw2d; w++, k++)
         for (int i = 0; i < pl.Q; i++)
-          links[k * pl.Q + i] = pl.ptab[w * pl.Q + i] != lbm::kNoLink ? 0.5 : 0.0;
+          links[k * pl.Q + i] = pl.ptab[w * pl.pstride + i] != lbm::kNoLink ? 0.5 : 0.0;
     return LBM_OK;
   }
   for (size_t w = 0; w < pl.wallcols.size(); w++)

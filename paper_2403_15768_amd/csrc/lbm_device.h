@@ -389,43 +389,78 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
   }
 }
 
-// Pull gather on masked walls (walls that vary along x).  cw is the class of
-// the cell's point of the (x, y) plane: kCellInterior pulls every link; a
-// wall node (cw >= 0) takes, for each link i whose upstream point is solid,
+// Masked walls (walls that vary along x).  The class of each point of the
+// (x, y) plane (cellw) is kCellSolid, kCellInterior or its 2-D wall-node
+// index k; a wall node's partner table holds, per link i, the storage row of
+// i's slip partner (kNoLink where the upstream point is fluid), padded to
+// whole 32-bit words.
+template <class L>
+constexpr int ptab_words() {
+  return (L::Q + 3) / 4;
+}
+
+// Pulls only: a column none of whose points is a wall node (all of them
+// interior; the block's branch is uniform).  z is periodic.
+template <class L, typename S, typename M>
+__device__ __forceinline__ void gather_masked_interior(const S* __restrict__ g0, const StepArgs& a,
+                                                       int col, int z, int x, M* df) {
+  const LBM_GLOBAL S* gown = gbl(g0) + (int64_t)col * a.sC;
+  const unsigned ux = (unsigned)x;
+  const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
+  const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
+  const bool wrap = L::Q == 19 && (z == 0 || z == a.nz - 1);
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    const LBM_GLOBAL S* line = gown + src_off<L>(a, i, z, wrap);
+    df[i] = ld<S, M>(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+  }
+}
+
+// Any non-solid point (cw >= 0: a wall node, kCellInterior otherwise).  A
+// link whose upstream point is solid takes
 //   df_i = r BB_i + (1 - r) g_p(i)(x),   BB_i = g_opp(i)(x) (half-way),
-// with p(i) its slip partner (the table holds p's storage row), evaluated as
-// g + r (bb - g) like the column-wide rule.  z is periodic.  The class varies
-// along x, so lanes of one wave may take different branches.
+// p(i) its slip partner, evaluated as g + r (bb - g) like the column-wide
+// rule.  Lanes of one wave may be wall nodes or not: every lane issues one
+// load per link (its pull, or its partner's own population) and wall lanes
+// one more (the bounced population), all before any is combined.
 template <class L, typename S, typename M, typename W>
 __device__ __forceinline__ void gather_masked(const S* __restrict__ g0, const StepArgs& a,
                                               int col, int z, int x, int cw, M* df) {
-  const LBM_GLOBAL S* g = gbl(g0);
+  const LBM_GLOBAL S* gown = gbl(g0) + (int64_t)col * a.sC;
   const int64_t sI = a.sI;
   const unsigned ux = (unsigned)x;
   const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
   const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
   const bool wrap = L::Q == 19 && (z == 0 || z == a.nz - 1);
-  const LBM_GLOBAL S* gown = g + (int64_t)col * a.sC;
-  if (cw < 0) {
+  const bool wall = cw >= 0;
+  constexpr int kWords = ptab_words<L>();
+  uint32_t pw[kWords];
+  const LBM_GLOBAL uint32_t* pt =
+      reinterpret_cast<const LBM_GLOBAL uint32_t*>(gbl(a.ptab)) + (int64_t)(wall ? cw : 0) * kWords;
 #pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-      const LBM_GLOBAL S* line = gown + src_off<L>(a, i, z, wrap);
-      df[i] = ld<S, M>(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
-    }
-    return;
-  }
-  const LBM_GLOBAL uint8_t* pt = gbl(a.ptab) + (int64_t)cw * L::Q;
-  const M r = static_cast<M>(gbl(static_cast<const W*>(a.rwall))[(int64_t)z * a.nw2d + cw]);
+  for (int w = 0; w < kWords; w++) pw[w] = wall ? pt[w] : 0xffffffffu;
+  const M r = wall ? static_cast<M>(gbl(static_cast<const W*>(a.rwall))[(int64_t)z * a.nw2d + cw])
+                   : M(0);
+  S A[L::Q], B[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
-    const unsigned prow = pt[i];
-    if (prow == kNoLink) {
-      const LBM_GLOBAL S* line = gown + src_off<L>(a, i, z, wrap);
-      df[i] = ld<S, M>(sbase(line), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
-    } else {
-      const M bb = ld<S, M>(sbase(gown + L::row[L::opp[i]] * sI), ux);
-      const M gs = ld<S, M>(gown + (int64_t)prow * sI, ux);
+    const unsigned prow = (pw[i >> 2] >> (8 * (i & 3))) & 0xffu;
+    const bool wl = prow != kNoLink;
+    const LBM_GLOBAL S* pull =
+        at(gown + src_off<L>(a, i, z, wrap), L::cx[i] > 0 ? xm : (L::cx[i] < 0 ? xp : ux));
+    const LBM_GLOBAL S* own = at(gown + (int64_t)(wl ? prow : 0u) * sI, ux);
+    A[i] = *(wl ? own : pull);
+    if (wl) B[i] = *at(gown + L::row[L::opp[i]] * sI, ux);
+  }
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    const unsigned prow = (pw[i >> 2] >> (8 * (i & 3))) & 0xffu;
+    const M gs = dec<S, M>(A[i]);
+    if (prow != kNoLink) {
+      const M bb = dec<S, M>(B[i]);
       df[i] = gs + r * (bb - gs);
+    } else {
+      df[i] = gs;
     }
   }
 }

@@ -46,6 +46,8 @@ struct Plan {
   std::vector<uint8_t> ptab;
   std::vector<int32_t> w2d;
   int64_t nw2d = 0;
+  int pstride = 0;         // partner-table bytes per 2-D wall node (whole words)
+  int64_t nwallslots = 0;  // leading slots whose columns hold wall nodes
   size_t off_cellw = 0, off_ptab = 0;
   int64_t nsheet = 0;               // electron sheet nodes (SLAB: 2 nz nx; else 0)
   std::vector<int32_t> sheet_wc;    // [sheet][z]: wall column next to the sheet

@@ -65,29 +65,35 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
 }
 
 // Masked walls: the same update on every fluid point of the columns that
-// hold one; the class of each point (solid, interior, wall node) comes from
-// a table of the (x, y) plane, so a wave may hold all three.  Solid points
-// are neither computed nor stored (nothing reads them); columns are visited
-// in one order or the reverse, as above.
+// hold one.  Columns with wall nodes come first (slot mask != 0); there the
+// class of each point (solid, interior, wall node) comes from a table of the
+// (x, y) plane, so a wave may hold all three, and solid points are neither
+// computed nor stored (nothing reads them).  The other columns are wholly
+// interior and only pull.  Their order alternates as in k_step.
 template <class L, typename S, typename M, int TH>
 __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
                                                      S* __restrict__ dst, StepArgs a) {
   int slot = blockIdx.x;
-  if (a.rev) slot = a.nactive - 1 - slot;
+  if (a.rev && slot >= a.nwallcols) slot = a.nactive - 1 - slot + a.nwallcols;
   const int x = blockIdx.y * a.bx + threadIdx.x;
   if (x >= a.nxp) return;
   const int xc = x < a.nx ? x : a.nx - 1;  // padding lanes: cell nx - 1 again
-  const int col = uniform(gbl(a.slots)[slot].col);
+  const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[slot];
+  const int col = uniform(cs.col);
+  const bool wallcol = uniform((int)cs.mask) != 0;
   const int z = col / a.ny;
   const int y = col - z * a.ny;
-  const int cw = gbl(a.cellw)[xc + (int64_t)a.nx * y];
+  const int cw = wallcol ? gbl(a.cellw)[xc + (int64_t)a.nx * y] : kCellInterior;
   if (cw == kCellSolid) return;
   const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
   M df[L::Q];
   M xi[L::Q];
   if constexpr (TH != 0)
     thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
-  gather_masked<L, S, M, M>(src, a, col, z, xc, cw, df);
+  if (wallcol)
+    gather_masked<L, S, M, M>(src, a, col, z, xc, cw, df);
+  else
+    gather_masked_interior<L, S, M>(src, a, col, z, xc, df);
   collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
                              (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
 }
