@@ -108,6 +108,8 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_shell_count.argtypes = [vp]
     lib.ora_shell_count.restype = lp
     lib.ora_sizeof_real.restype = C.c_int
+    lib.ora_set_open_ends.argtypes = [vp, C.c_int, C.c_double, C.c_double]
+    lib.ora_set_open_ends.restype = C.c_int
     u64p = C.POINTER(C.c_uint64)
     lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
     lib.ora_set_thermal.restype = C.c_int
@@ -212,6 +214,14 @@ class Lattice:
                                        float(force_e)) != 0:
             raise OracleError("electron sheets need a SLAB or DUCT without moving wall, "
                               "tau_e > 1/2, rho_e0 > 0, gamma_e >= 0")
+
+    def set_open_ends(self, rho_in: float, rho_out: float, open_: bool = True) -> None:
+        """Open x ends (Neumann-like inlet and outlet at densities rho_in,
+        rho_out); open_=False restores periodic x."""
+        if self._lib.ora_set_open_ends(self._h, int(bool(open_)), float(rho_in),
+                                       float(rho_out)) != 0:
+            raise OracleError("open ends need a SLAB or DUCT without electron sheets, nx >= 2 "
+                              "and finite densities > 0")
 
     @property
     def shell_count(self) -> int:

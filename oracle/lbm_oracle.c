@@ -31,7 +31,9 @@
  *    half is the same-node transverse reversal (c_x, -c_y, -c_z).  Bounce-back
  *    is half-way on planar walls and Bouzidi-Firdaouss-Lallemand linear
  *    interpolation on the circular tube.  Inlet/outlet are periodic in x (the
- *    first option of Sec. 4.2).  Walls that vary along x (a solid mask in
+ *    first option of Sec. 4.2), or open (its Neumann-like option: ghost
+ *    nodes rebuilt from the boundary node at a prescribed density, see
+ *    open_ghost).  Walls that vary along x (a solid mask in
  *    the (x, y) plane: corrugated, wrinkled or stepped walls) take the slip
  *    half from a pairing of the node's wall links (pair_slip_links) that
  *    keeps mass exact.
@@ -138,6 +140,9 @@ typedef struct {
   long step;
   double kT;     /* lattice temperature; 0 = no fluctuations */
   int noise;     /* 1 = stress directions only, 2 = all non-conserved */
+  /* open x ends (Neumann-like inlet and outlet): prescribed densities */
+  int open;
+  double rho_in, rho_out;
   uint64_t seed; /* key of the thermal random numbers */
   /* electron shells (SLAB and DUCT): the solid columns next to the water,
    * each with an electron line along x, D1Q3 (see shell_of) */
@@ -507,15 +512,58 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
   return o->r[n] * bb + (1 - o->r[n]) * g[(long)o->sig[i] * o->ncell + n];
 }
 
+/* Open x ends (the Neumann-like option for inlet and outlet, Sec. 4.2).
+ * A link that pulls from beyond the box in x (x - c_i outside 0..nx-1) reads
+ * a ghost node just outside the end.  The ghost copies the populations of
+ * its neighbour inside the box, the boundary node b in the ghost's own
+ * column (zero normal gradient of velocity and of the non-equilibrium part),
+ * moved along the local equilibrium to the density prescribed at that end:
+ *   ghost_i = g_i(b) + w_i (rho_bc - rho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2
+ *                                             - 1.5 u_b.u_b),
+ * with rho_b = rho0 + sum_k g_k(b) and u_b = sum_k g_k(b) c_k / rho_b the
+ * moments of b's stored populations.  rho_bc is rho_in at x = -1 and rho_out
+ * at x = nx; the pressure c_s^2 rho_bc is the drive. */
+int ora_set_open_ends(ora_ctx *o, int open, double rho_in, double rho_out) {
+  if (open && (o->p.geometry == ORA_TUBE || o->p.geometry == ORA_MASKED || o->elec ||
+               o->p.nx < 2 || !(rho_in > 0) || !(rho_out > 0) || !isfinite(rho_in) ||
+               !isfinite(rho_out)))
+    return ORA_EINVAL;
+  o->open = open ? 1 : 0;
+  o->rho_in = rho_in;
+  o->rho_out = rho_out;
+  return ORA_OK;
+}
+
+static real open_ghost(const ora_ctx *o, const real *g, int xb, int yb, int zb,
+                       int i, double rho_bc) {
+  long nb = cell(o, xb, yb, zb);
+  real drho = 0, j[3] = {0, 0, 0}, rho, u[3], cu, usq;
+  int k, a;
+  for (k = 0; k < o->q; k++) {
+    real v = g[(long)k * o->ncell + nb];
+    drho += v;
+    for (a = 0; a < 3; a++) j[a] += (real)o->c[k][a] * v;
+  }
+  rho = (real)o->p.rho0 + drho;
+  for (a = 0; a < 3; a++) u[a] = j[a] / rho;
+  cu = (real)o->c[i][0] * u[0] + (real)o->c[i][1] * u[1] + (real)o->c[i][2] * u[2];
+  usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return g[(long)i * o->ncell + nb] +
+         o->w[i] * (((real)rho_bc - (real)o->p.rho0) - drho) *
+             (1 + 3 * cu + (real)4.5 * cu * cu - (real)1.5 * usq);
+}
+
 /* steps 1 and 2: gather the populations a collision at (x,y,z) sees */
 static void gather(const ora_ctx *o, const real *g, int x, int y, int z,
                    real *df) {
   int i;
   for (i = 0; i < o->q; i++) {
-    int sx, sy, sz;
+    int sx, sy, sz, xr = x - o->c[i][0];
     upstream(o, x, y, z, i, &sx, &sy, &sz);
     if (is_solid(o, sx, sy, sz))
       df[i] = wall_value(o, g, x, y, z, i, sy);
+    else if (o->open && (xr < 0 || xr >= o->p.nx))
+      df[i] = open_ghost(o, g, x, sy, sz, i, xr < 0 ? o->rho_in : o->rho_out);
     else
       df[i] = g[(long)i * o->ncell + cell(o, sx, sy, sz)];
   }
@@ -692,7 +740,8 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
 int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
                       double force_e) {
   long n = nshell(o) * o->p.nx;
-  if (o->p.geometry == ORA_TUBE || o->p.geometry == ORA_MASKED || o->p.wall_velocity_top != 0.0)
+  if (o->p.geometry == ORA_TUBE || o->p.geometry == ORA_MASKED || o->p.wall_velocity_top != 0.0 ||
+      o->open)
     return ORA_EINVAL;
   if (!(tau_e > 0.5) || !(rho_e0 > 0) || !(gamma_e >= 0) || !isfinite(force_e) ||
       !isfinite(tau_e) || !isfinite(rho_e0) || !isfinite(gamma_e))

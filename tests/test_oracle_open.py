@@ -1,0 +1,130 @@
+"""Pins of the oracle's open x ends (the Neumann-like inlet and outlet option
+of Sec. 4.2): ghost nodes beyond each end copy their neighbour inside the box,
+moved along the local equilibrium to a prescribed density.
+
+What fixes it independently of the oracle's own open-end code:
+  - with equal densities at both ends and a body force, an x-uniform flow is
+    a fixed point, so the open channel must reproduce the periodic one (whose
+    profile is pinned by the exact discrete slip-Poiseuille solution);
+  - a pressure drop rho_in - rho_out with no body force holds the density
+    linear inside the box with slope -(rho_in - rho_out)/(nx + 1) (the ghost
+    planes sit at x = -1 and x = nx), and drives the same flow as the body
+    force F = c_s^2 (rho_in - rho_out)/(nx + 1): exactly the discrete
+    Poiseuille profile between no-slip walls, up to compressibility terms of
+    second order in the density drop;
+  - in a duct, the pressure-driven flux equals the body-force-driven flux of
+    the periodic duct to the same order.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from test_oracle_lb import poiseuille_exact
+
+
+def run_steady(L, chunk=1000, tol=1e-11, max_chunks=200):
+    prev = None
+    for _ in range(max_chunks):
+        L.step(chunk)
+        q = L.invariants()[0]
+        if prev is not None and abs(q - prev) < tol * abs(q):
+            return q
+        prev = q
+    raise AssertionError("not converged")
+
+
+@pytest.mark.parametrize("q,geom,shape", [(9, oracle.SLAB, (40, 12, 1)),
+                                          (19, oracle.DUCT, (9, 8, 6)),
+                                          (19, oracle.SLAB, (7, 9, 4))])
+def test_equal_densities_reproduce_the_periodic_channel(q, geom, shape):
+    # slab: the periodic flow keeps rho = rho0 at every node, so the ghosts
+    # equal the periodic neighbours to rounding; in a duct the corners hold
+    # density deviations of second order in the velocity, which the open
+    # ends pin to rho0 at the ghosts: agreement to that order only
+    nx, ny, nz = shape
+    A = oracle.Lattice(q, geom, nx, ny, nz, tau=0.8, force=(1e-5, 0, 0))
+    B = oracle.Lattice(q, geom, nx, ny, nz, tau=0.8, force=(1e-5, 0, 0))
+    B.set_open_ends(1.0, 1.0)
+    # one friction value per wall (a friction varying across the section
+    # would stir up density deviations of second order, as in the duct)
+    xyz = A.wall_coords()
+    lam = np.where(xyz[:, 1] == 0, 0.05, 0.12)
+    A.set_friction(lam)
+    B.set_friction(lam)
+    A.step(800)
+    B.step(800)
+    ra, rb = A.fields(), B.fields()
+    ref = np.abs(ra[1]).max()
+    assert ref > 1e-4
+    tol = 1e-13 if geom == oracle.SLAB else 1e-5
+    assert max(np.abs(ra[k] - rb[k]).max() for k in (1, 2, 3)) < tol * ref
+    assert np.abs(ra[0] - rb[0]).max() < (1e-15 if geom == oracle.SLAB else 1e-7)
+
+
+@pytest.mark.parametrize("nx,drho", [(64, 1e-6), (33, 1e-6), (64, 1e-4)])
+def test_pressure_driven_poiseuille_exact(nx, drho):
+    ny, tau = 16, 0.8
+    L = oracle.Lattice(9, oracle.SLAB, nx, ny, 1, tau=tau)
+    L.set_friction(math.inf)
+    L.set_open_ends(1.0 + drho / 2, 1.0 - drho / 2)
+    q = run_steady(L)
+    rho, ux, uy, _ = L.fields()
+    # density linear inside with the ghost planes at x = -1 and x = nx
+    slope, icpt = np.polyfit(np.arange(nx), rho[0].mean(axis=0), 1)
+    assert abs(slope / (-drho / (nx + 1)) - 1) < 1e-6
+    assert abs((icpt - slope) - (1.0 + drho / 2)) < 1e-3 * drho
+    # the flow of the equivalent body force
+    G = drho / 3.0 / (nx + 1)
+    ue = poiseuille_exact(ny, tau, G, math.inf)
+    tol = 1e-8 if drho <= 1e-6 else 2e-6
+    assert abs(q / ue.sum() - 1) < tol
+    assert np.abs(ux[0, :, nx // 2] / ue - 1).max() < 50 * tol
+    assert np.abs(uy).max() < 1e-3 * ue.max()
+
+
+def test_pressure_drop_matches_body_force_in_a_duct():
+    nx, ny, nz, tau, drho = 24, 10, 8, 0.7, 1e-6
+    P = oracle.Lattice(19, oracle.DUCT, nx, ny, nz, tau=tau)
+    P.set_friction(math.inf)
+    P.set_open_ends(1.0 + drho / 2, 1.0 - drho / 2)
+    B = oracle.Lattice(19, oracle.DUCT, 2, ny, nz, tau=tau, force=(drho / 3 / (nx + 1), 0, 0))
+    B.set_friction(math.inf)
+    qp = run_steady(P, chunk=500)
+    qb = run_steady(B, chunk=500)
+    assert abs(qp / qb - 1) < 1e-7
+
+
+def test_slip_walls_under_a_pressure_drop():
+    # Navier-slip walls: the pressure drop and the equivalent body force give
+    # fluxes within 1 % (the wall rule's slip half sees the density gradient
+    # of the pressure-driven flow); both well above the no-slip flux
+    nx, ny, tau, drho, lam = 64, 16, 0.8, 1e-6, 0.05
+    L = oracle.Lattice(9, oracle.SLAB, nx, ny, 1, tau=tau)
+    L.set_friction(lam)
+    L.set_open_ends(1.0 + drho / 2, 1.0 - drho / 2)
+    q = run_steady(L)
+    G = drho / 3.0 / (nx + 1)
+    qs = poiseuille_exact(ny, tau, G, lam).sum()
+    q0 = poiseuille_exact(ny, tau, G, math.inf).sum()
+    assert abs(q / qs - 1) < 0.01
+    assert q > 1.5 * q0
+
+
+def test_open_ends_rejections():
+    T = oracle.Lattice(19, oracle.TUBE, 4, 12, 12, tau=0.8, tube_radius=4.0, tube_cy=5.5,
+                       tube_cz=5.5)
+    with pytest.raises(oracle.OracleError):
+        T.set_open_ends(1.0, 1.0)
+    S = oracle.Lattice(9, oracle.SLAB, 1, 6, 1, tau=0.8)
+    with pytest.raises(oracle.OracleError):  # nx = 1
+        S.set_open_ends(1.0, 1.0)
+    S = oracle.Lattice(9, oracle.SLAB, 8, 6, 1, tau=0.8)
+    for bad in [(0.0, 1.0), (1.0, float("nan")), (1.0, -1.0)]:
+        with pytest.raises(oracle.OracleError):
+            S.set_open_ends(*bad)
+    S.set_electrons(0.9, 1.0, 0.1)
+    with pytest.raises(oracle.OracleError):
+        S.set_open_ends(1.0, 1.0)
+    S.set_open_ends(1.0, 1.0, open_=False)  # closing is always allowed

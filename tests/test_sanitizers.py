@@ -1,7 +1,8 @@
 """Host sanitizers (no GPU): the oracle built with AddressSanitizer and
 UndefinedBehaviorSanitizer (gcc) and driven through every entry point -- the
-three geometries and both lattices, friction, thermal noise of both forms,
-electron sheets, the plain and the screened quadrature, population get/set --
+four geometries and both lattices, friction, thermal noise of both forms,
+electron sheets, open ends, masked walls, the plain and the screened
+quadrature, population get/set --
 must run without a single report.  The library's host-side planning
 (geometry classification, wall tables, arena layout) is exercised the same
 way through lbm_footprint, with the sanitizers on the host pass of the
@@ -42,6 +43,7 @@ void ora_wall_links(const ora_ctx *, double *);
 int ora_set_friction(ora_ctx *, const double *);
 int ora_set_thermal(ora_ctx *, double, int, uint64_t);
 int ora_set_electrons(ora_ctx *, double, double, double, double);
+int ora_set_open_ends(ora_ctx *, int, double, double);
 void ora_get_electrons(const ora_ctx *, double *, double *);
 void ora_step(ora_ctx *, long);
 void ora_fields(const ora_ctx *, double *, double *, double *, double *);
@@ -76,6 +78,7 @@ static int run(int q, int geom, int nx, int ny, int nz, double R, int mode, int 
   if (ora_set_friction(o, lam)) return 2;
   if (mode && ora_set_thermal(o, 1e-6, mode, 9)) return 3;
   if (elec && ora_set_electrons(o, 0.9, 1.0, 0.05, 1e-6)) return 4;
+  if (!elec && geom <= 1 && ora_set_open_ends(o, 1, 1.0001, 0.9999)) return 6;
   ora_step(o, 7);
   ora_fields(o, f, f + nc, f + 2 * nc, f + 3 * nc);
   ora_invariants(o, inv);
@@ -95,6 +98,7 @@ int main(void) {
   rc |= run(9, 0, 12, 6, 1, 0, 2, 1);
   rc |= run(19, 0, 7, 5, 4, 0, 1, 1);
   rc |= run(19, 1, 9, 5, 6, 0, 2, 0);
+  rc |= run(19, 0, 6, 5, 3, 0, 0, 0);
   rc |= run(19, 2, 5, 14, 14, 5.0, 1, 0);
   rc |= run(9, 3, 13, 9, 1, 0, 1, 0);
   rc |= run(19, 3, 8, 10, 3, 0, 2, 0);
