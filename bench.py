@@ -196,6 +196,19 @@ def extras(torch, lbm, inputs, args):
                      "step_us": round(kms * 1e3 / 2000, 2),
                      "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
         ch.close()
+    # open x ends (Neumann-like inlet and outlet): the benchmark duct with a
+    # density drop besides its body force; the step kernel plus the kernel
+    # that recomputes the end nodes with the ghost pulls
+    ch = make_duct(lbm, inputs, "f32")
+    ch.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
+    ch.step(200)
+    wall, kms = timed_run(torch, ch, 2000, 1000)
+    cells = ch.fluid_count
+    out["duct_f32_open_ends"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                                 "step_us": round(kms * 1e3 / 2000, 2),
+                                 "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
+                                                   / HBM_PEAK_GBS, 4)}
+    ch.close()
     # walls that vary along x: the wrinkled slab (masked walls)
     ch = make_corrugated(lbm, inputs, "f32")
     ch.step(200)

@@ -86,7 +86,8 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_precision;
  *       the lowest-numbered free k.  Wall nodes are numbered as in every
  *       geometry (increasing x + nx (y + ny z)).  No moving wall, no
  *       electron sheets, no batches.
- * x is periodic in every geometry (inlet/outlet option 1 of Sec. 4.2). */
+ * x is periodic in every geometry (inlet/outlet option 1 of Sec. 4.2) unless
+ * lbm_set_open_ends opens it (option 2). */
 typedef enum { LBM_SLAB = 0, LBM_DUCT = 1, LBM_TUBE = 2, LBM_MASKED = 3 } lbm_geometry;
 
 typedef struct {
@@ -202,6 +203,26 @@ lbm_status lbm_get_friction(lbm_ctx *ctx, double *lambda, double *raw);
 typedef enum { LBM_NOISE_STRESS = 1, LBM_NOISE_ALL = 2 } lbm_noise;
 lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
 
+/* Open x ends: the Neumann-like inlet and outlet of Sec. 4.2 (the option the
+ * paper sets beside periodic ends) in place of periodic x.  From the next
+ * step on, a fluid link of the first (last) node of an x-line that would
+ * pull from x = -1 (x = nx) reads a ghost node instead.  The ghost copies the
+ * populations of its neighbour inside the box -- the boundary node b in the
+ * ghost's own column -- moved along the local equilibrium to the density
+ * prescribed at that end (zero normal gradient of velocity and of the
+ * non-equilibrium part; Dirichlet density, i.e. pressure c_s^2 rho):
+ *   ghost_i = g_i(b) + w_i (rho_bc - rho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2
+ *                                             - 1.5 u_b.u_b),
+ * rho_b = rho0 + sum_k g_k(b), u_b = sum_k g_k(b) c_k / rho_b, rho_bc =
+ * rho_in at x = -1 and rho_out at x = nx.  A pressure drop rho_in > rho_out
+ * then drives the flow of the body force c_s^2 (rho_in - rho_out) / (nx + 1).
+ * Fields, flux and mass take the ghosts too; mass is no longer conserved.
+ * open = 0 restores periodic x (the densities are then ignored).  Requires
+ * a SLAB or DUCT, nx >= 2, no electron sheets, finite densities > 0 (else
+ * LBM_EINVAL); batches refuse such channels.  Synchronous (finishes queued
+ * work). */
+lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_out);
+
 /* Electron wind (SLAB and DUCT).  Sec. 3.3 describes the electrons of the solid
  * as a fluid dragged by, and dragging, the water; Sec. 4 gives each species
  * its own set of distributions; Eq. 5 / Eq. 27 make the interfacial force a
@@ -314,7 +335,7 @@ lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
  * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
  * lattice, precision, wall kind or thermal-noise form (lbm_set_thermal: one
  * form for the whole batch, each member its own kT and seed), one appears
- * twice, or one has electron sheets or MASKED walls.  lbm_batch_step refuses a member whose
+ * twice, or one has electron sheets, MASKED walls or open ends.  lbm_batch_step refuses a member whose
  * noise form changed or whose sheets were switched on after the batch was
  * built, and takes up a changed kT or seed.  Batched members draw the same
  * thermal numbers as alone: results agree bit for bit. */

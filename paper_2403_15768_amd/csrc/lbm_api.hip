@@ -422,6 +422,9 @@ void fill_args(lbm_ctx* c) {
   a.cellw = pl.masked ? c->at<int32_t>(pl.off_cellw) : nullptr;
   a.ptab = pl.masked ? c->at<uint8_t>(pl.off_ptab) : nullptr;
   a.nw2d = pl.nw2d;
+  a.open = 0;
+  a.drho_in = 0.0;
+  a.drho_out = 0.0;
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -458,6 +461,9 @@ lbm_status lbm_host::launch_one_step(lbm_ctx* c) {
                                         c->at<double>(c->pl.off_ue), c->ea, c->stream));
   HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
                              c->pl.bouz, c->stream));
+  if (a.open)  // the end nodes again, with the ghost pulls
+    HIPCHK(c, lbm::launch_open_ends(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
+                                    c->stream));
   c->cur = 1 - c->cur;
   c->step++;
   return LBM_OK;
@@ -472,6 +478,7 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode,
                                         c->elec, c->pl.masked);
   const void* fe = c->elec ? lbm::electron_kernel_ptr(c->pl.Q, c->pl.prec) : nullptr;
+  const void* fo = c->args.open ? lbm::open_kernel_ptr(c->pl.Q, c->pl.prec, c->args.th_mode) : nullptr;
   const double* esrc[2] = {c->at<double>(c->pl.off_e[parity]), c->at<double>(c->pl.off_e[1 - parity])};
   double* edst[2] = {c->at<double>(c->pl.off_e[1 - parity]), c->at<double>(c->pl.off_e[parity])};
   double* uep = c->at<double>(c->pl.off_ue);
@@ -519,6 +526,20 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
       return c->hip(e, "hipGraphAddKernelNode");
     }
     prev = node;
+    if (fo) {  // the end nodes of step k again, with the ghost pulls
+      hipKernelNodeParams op{};
+      op.func = const_cast<void*>(fo);
+      op.gridDim = dim3((unsigned)c->pl.slots.size());
+      op.blockDim = dim3(64);
+      op.kernelParams = kargs;
+      hipGraphNode_t onode = nullptr;
+      e = hipGraphAddKernelNode(&onode, g, &prev, 1, &op);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return c->hip(e, "hipGraphAddKernelNode");
+      }
+      prev = onode;
+    }
   }
   {
     int64_t inc = kGraphSteps;
@@ -824,6 +845,30 @@ lbm_status lbm_set_thermal(lbm_ctx* c, double kT, int mode, uint64_t seed) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_open_ends(lbm_ctx* c, int open, double rho_in, double rho_out) {
+  if (!c) return LBM_EINVAL;
+  if (open) {
+    if (c->p.geometry != LBM_SLAB && c->p.geometry != LBM_DUCT)
+      return c->fail(LBM_EINVAL, "open ends need a SLAB or DUCT");
+    if (c->elec) return c->fail(LBM_EINVAL, "open ends need the electron sheets off");
+    if (c->pl.nx < 2) return c->fail(LBM_EINVAL, "open ends need nx >= 2");
+    if (!(rho_in > 0.0) || !(rho_out > 0.0) || !std::isfinite(rho_in) || !std::isfinite(rho_out))
+      return c->fail(LBM_EINVAL, "densities must be finite and > 0");
+  }
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 2; k++) {  // the step graphs hold the kernels and their arguments
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+  c->args.open = open ? 1 : 0;
+  c->args.drho_in = open ? rho_in - c->p.rho0 : 0.0;
+  c->args.drho_out = open ? rho_out - c->p.rho0 : 0.0;
+  return LBM_OK;
+}
+
 lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gamma_e,
                              double force_e) {
   if (!c) return LBM_EINVAL;
@@ -831,6 +876,7 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   if (on) {
     if ((c->p.geometry != LBM_SLAB && c->p.geometry != LBM_DUCT) || c->p.wall_velocity_top != 0.0)
       return c->fail(LBM_EINVAL, "electron sheets need a SLAB or DUCT without a moving wall");
+    if (c->args.open) return c->fail(LBM_EINVAL, "electron sheets need periodic x ends");
     if (!(tau_e > 0.5) || !(rho_e0 > 0.0) || !(gamma_e >= 0.0) || !std::isfinite(tau_e) ||
         !std::isfinite(rho_e0) || !std::isfinite(gamma_e) || !std::isfinite(force_e))
       return c->fail(LBM_EINVAL, "need tau_e > 1/2, rho_e0 > 0, gamma_e >= 0, finite values");

@@ -237,8 +237,9 @@ lbm_status check_members(lbm_ctx* const* ctxs, int n) {
         (a.geometry == LBM_TUBE) != (b.geometry == LBM_TUBE))
       return LBM_EINVAL;
     // one noise form for the whole batch (each member its own kT and seed);
-    // the batch kernel has no electron sheets and no masked walls
-    if (ctxs[m]->args.th_mode != ctxs[0]->args.th_mode || ctxs[m]->elec || ctxs[m]->pl.masked)
+    // the batch kernel has no electron sheets, masked walls or open ends
+    if (ctxs[m]->args.th_mode != ctxs[0]->args.th_mode || ctxs[m]->elec || ctxs[m]->pl.masked ||
+        ctxs[m]->args.open)
       return LBM_EINVAL;
   }
   return LBM_OK;
@@ -622,8 +623,9 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
   for (lbm_ctx* c : b->m)
-    if (c->args.th_mode != b->th || c->elec) {
-      b->err = "a member's noise form changed or its electron sheets are on; rebuild the batch";
+    if (c->args.th_mode != b->th || c->elec || c->args.open) {
+      b->err = "a member's noise form changed or its electron sheets or open ends are on; "
+               "rebuild the batch";
       return LBM_EINVAL;
     }
   lbm_status rs = resync(b);

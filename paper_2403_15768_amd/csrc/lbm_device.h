@@ -119,6 +119,10 @@ struct StepArgs {
   const int32_t* cellw;
   const uint8_t* ptab;
   int64_t nw2d;
+  // open x ends (0: periodic): prescribed density deviations rho - rho0 of
+  // the ghost planes x = -1 (inlet) and x = nx (outlet)
+  int open;
+  double drho_in, drho_out;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
@@ -502,6 +506,50 @@ __device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
     r = any ? r + t : t;
   }
   return r;
+}
+
+// Open x ends: a fluid link of the first (last) node of an x-line that
+// pulls from x = -1 (x = nx) reads a ghost.  The ghost copies the boundary
+// node b of its own column (the column the pull reads, at the same x),
+// moved along the local equilibrium to the prescribed density:
+//   ghost_i = g_i(b) + w_i (drho_bc - drho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2
+//                                               - 1.5 u_b.u_b),
+// drho_b = sum_k g_k(b), u_b = sum_k g_k(b) c_k / (rho0 + drho_b).  Replaces
+// df_i of those links after the periodic gather (which read x = nx - 1 or 0);
+// x is the lane's cell, the column is uniform.
+template <class L, typename S, typename M>
+__device__ __forceinline__ void open_patch(const S* __restrict__ g0, const StepArgs& a, int col,
+                                           int x, uint32_t mask, M* df) {
+  const bool in = x == 0, out = x == a.nx - 1;
+  if (!in && !out) return;
+  const LBM_GLOBAL S* gown = gbl(g0) + (int64_t)col * a.sC;
+  const int z = col / a.ny;
+  const bool wrap = (mask & kWrapColumn) != 0u;
+  const unsigned ux = (unsigned)x;
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    if (L::cx[i] == 0 || (mask & (1u << i))) continue;
+    if (!((L::cx[i] > 0 && in) || (L::cx[i] < 0 && out))) continue;
+    // the source column of link i
+    const LBM_GLOBAL S* cb = gown + src_off<L>(a, i, z, wrap) - L::row[i] * a.sI;
+    M drho = 0, jx = 0, jy = 0, jz = 0, gi = 0;
+#pragma unroll
+    for (int k = 0; k < L::Q; k++) {
+      const M v = ld<S, M>(sbase(cb + L::row[k] * a.sI), ux);
+      drho += v;
+      if (L::cx[k]) jx += L::cx[k] > 0 ? v : -v;
+      if (L::cy[k]) jy += L::cy[k] > 0 ? v : -v;
+      if (L::cz[k]) jz += L::cz[k] > 0 ? v : -v;
+      if (k == i) gi = v;
+    }
+    const M rho = static_cast<M>(a.rho0) + drho;
+    const M ux_ = jx / rho, uy_ = jy / rho, uz_ = jz / rho;
+    const M cu = cdot<L, M>(i, ux_, uy_, uz_);
+    const M usq = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
+    const M dbc = static_cast<M>(in ? a.drho_in : a.drho_out);
+    df[i] = gi + static_cast<M>(L::w[i]) * (dbc - drho) *
+                     (M(1) + M(3) * cu + M(4.5) * cu * cu - M(1.5) * usq);
+  }
 }
 
 // ------------------------------------------------------------------ thermal noise

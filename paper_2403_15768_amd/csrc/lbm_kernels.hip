@@ -98,6 +98,33 @@ __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
                              (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
 }
 
+// Open x ends: after k_step (which treats x as periodic) this kernel
+// recomputes the first and last node of every fluid x-line with the ghost
+// pulls (open_patch) and overwrites them.  One wave per column: lane 0 takes
+// x = 0, lane 1 x = nx - 1 (nx >= 2); both read the source buffer only, like
+// k_step, so the result is that of one update with open ends.
+template <class L, typename S, typename M, int TH>
+__global__ void __launch_bounds__(64) k_open_ends(const S* __restrict__ src, S* __restrict__ dst,
+                                                  StepArgs a) {
+  const int lane = threadIdx.x;
+  if (lane > 1) return;
+  const int x = lane == 0 ? 0 : a.nx - 1;
+  const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[blockIdx.x];
+  const int col = uniform(cs.col);
+  ColInfo info;
+  info.wallcol = uniform(cs.wallcol);
+  info.mask = (uint32_t)uniform((int)cs.mask);
+  const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
+  M df[L::Q];
+  M xi[L::Q];
+  if constexpr (TH != 0)
+    thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+  gather<L, S, M, M, false, false>(src, a, col, x, info, df);
+  open_patch<L, S, M>(src, a, col, x, info.mask, df);
+  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                             (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+}
+
 // ------------------------------------------------------------ electron sheets
 // One electron step per shell node (lines along x, D1Q3: c = 0, +1, -1,
 // w = 2/3, 1/6, 1/6, shifted populations [i][shell][x] in double):
@@ -195,6 +222,7 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
       info.mask = (uint32_t)uniform((int)cs.mask);
       // with electron sheets the wall moves with u_e of the last step
       gather<L, S, double, W, BOUZ, ELEC>(src, a, col, x, info, df);
+      if (a.open) open_patch<L, S, double>(src, a, col, x, info.mask, df);
     }
     double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -824,6 +852,33 @@ const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec, 
   if (prec == 1) return KP(D3Q19, float, double);
   return KP(D3Q19, _Float16, float);
 #undef KP
+}
+
+template <class L, typename S, typename M>
+static const void* open_kernel_t(int th) {
+  if (th == 1) return reinterpret_cast<const void*>(&k_open_ends<L, S, M, 1>);
+  if (th == 2) return reinterpret_cast<const void*>(&k_open_ends<L, S, M, 2>);
+  return reinterpret_cast<const void*>(&k_open_ends<L, S, M, 0>);
+}
+
+const void* open_kernel_ptr(int q, int prec, int th_mode) {
+  if (q == 9) {
+    if (prec == 0) return open_kernel_t<D2Q9, double, double>(th_mode);
+    if (prec == 1) return open_kernel_t<D2Q9, float, double>(th_mode);
+    return open_kernel_t<D2Q9, _Float16, float>(th_mode);
+  }
+  if (prec == 0) return open_kernel_t<D3Q19, double, double>(th_mode);
+  if (prec == 1) return open_kernel_t<D3Q19, float, double>(th_mode);
+  return open_kernel_t<D3Q19, _Float16, float>(th_mode);
+}
+
+hipError_t launch_open_ends(int q, int prec, const void* src, void* dst, const StepArgs& a,
+                            hipStream_t st) {
+  if (a.nactive <= 0 || a.nx < 2) return hipErrorInvalidValue;
+  StepArgs args = a;
+  void* kargs[3] = {(void*)&src, (void*)&dst, (void*)&args};
+  return hipLaunchKernel(open_kernel_ptr(q, prec, a.th_mode), dim3((unsigned)a.nactive), dim3(64),
+                         kargs, 0, st);
 }
 
 const void* electron_kernel_ptr(int q, int prec) {

@@ -65,7 +65,7 @@ EXPORTS = [
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
-    "lbm_get_electrons",
+    "lbm_get_electrons", "lbm_set_open_ends",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -103,6 +103,7 @@ def load() -> C.CDLL:
         "lbm_set_thermal": [vp, C.c_double, C.c_int, C.c_uint64],
         "lbm_set_electrons": [vp, C.c_double, C.c_double, C.c_double, C.c_double],
         "lbm_get_electrons": [vp, dp, dp],
+        "lbm_set_open_ends": [vp, C.c_int, C.c_double, C.c_double],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_flux": [vp, dp],
@@ -299,6 +300,13 @@ class Channel:
         NOISE_STRESS (the stress source alone) or NOISE_ALL."""
         self._ck(self._lib.lbm_set_thermal(self._h, float(kT), int(mode), int(seed)),
                  "lbm_set_thermal")
+
+    # ---- open x ends
+    def set_open_ends(self, rho_in: float, rho_out: float, open_: bool = True) -> None:
+        """Neumann-like inlet and outlet at densities rho_in and rho_out in
+        place of periodic x (open_=False: periodic again)."""
+        self._ck(self._lib.lbm_set_open_ends(self._h, int(bool(open_)), float(rho_in),
+                                             float(rho_out)), "lbm_set_open_ends")
 
     # ---- electron sheets (slab walls)
     def set_electrons(self, tau_e: float, rho_e0: float = 1.0, gamma_e: float = 0.0,

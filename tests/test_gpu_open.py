@@ -1,0 +1,167 @@
+"""GPU parity of open x ends (the Neumann-like inlet and outlet) against the
+oracle, through the C ABI.
+
+Tolerances as for the periodic channels: FP64 within 1e-12 relative of the
+oracle, FP32 storage within 1e-5 of the largest axial velocity, thermal noise
+within 3e-4 (binary32 Box-Muller).  Closed form: the pressure-driven
+Poiseuille profile of the equivalent body force.  Exact: graph replays equal
+plain launches bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from test_oracle_lb import poiseuille_exact
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_15768_amd import lbm as mod
+
+    mod.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# several 64-lane tiles and ragged tails; D3Q19 slabs wrap in z
+CASES = {"d2q9": (9, "SLAB", 150, 20, 1), "d3q19": (19, "SLAB", 70, 12, 5),
+         "duct": (19, "DUCT", 37, 10, 8), "duct_long": (19, "DUCT", 200, 6, 5)}
+
+
+def build(lbm, case, precision, rho=(1.0 + 2e-5, 1.0 - 1e-5), force=(1e-6, 0, 0)):
+    q, geom, nx, ny, nz = CASES[case]
+    G = lbm.Channel(q, getattr(lbm, geom), nx, ny, nz, tau=0.72, force=force, precision=precision)
+    O = oracle.Lattice(q, getattr(oracle, geom), nx, ny, nz, tau=0.72, force=force)
+    lam = np.random.default_rng(3).uniform(0.0, 0.3, G.wall_count)
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.set_open_ends(*rho)
+    O.set_open_ends(*rho)
+    return G, O
+
+
+def errs(G, O):
+    rg, ro = G.fields(), O.fields()
+    ref = np.abs(ro[1]).max()
+    return (max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / ref,
+            np.abs(rg[0] - ro[0]).max())
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_parity_over_graph_and_plain_steps(lbm, case, precision):
+    say("open ends parity", case, precision)
+    G, O = build(lbm, case, precision)
+    n = 229  # three 64-step graph replays, then single launches
+    G.step(n)
+    O.step(n)
+    eu, er = errs(G, O)
+    qg, mg, _ = G.invariants()
+    qo, mo, _ = O.invariants()
+    say(f"  u {eu:.2e}  rho {er:.2e}  flux {abs(qg / qo - 1):.2e}  mass {abs(mg / mo - 1):.2e}")
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert eu < tol and abs(qg / qo - 1) < tol
+    assert er < (1e-14 if precision == "f64" else 1e-6)
+    assert abs(mg / mo - 1) < (1e-14 if precision == "f64" else 1e-8)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_graph_and_plain_launches_bitwise(lbm, precision):
+    say("open ends graph = plain", precision)
+    A, _ = build(lbm, "duct", precision)
+    B, _ = build(lbm, "duct", precision)
+    A.step(128)
+    for _ in range(128):
+        B.step(1)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+
+
+def test_open_ends_with_thermal_noise(lbm):
+    say("open ends + thermal")
+    G, O = build(lbm, "d3q19", "f64")
+    for L in (G, O):
+        L.set_thermal(1e-7, 2, 5)
+    G.step(101)
+    O.step(101)
+    eu, _ = errs(G, O)
+    say(f"  u {eu:.2e}")
+    assert eu < 3e-4
+
+
+def test_pressure_driven_poiseuille_closed_form(lbm):
+    # no body force, a density drop: the discrete Poiseuille profile of the
+    # body force c_s^2 (rho_in - rho_out) / (nx + 1)
+    say("open ends Poiseuille")
+    nx, ny, tau, drho = 64, 16, 0.8, 1e-6
+    G = lbm.Channel(9, lbm.SLAB, nx, ny, 1, tau=tau, precision="f64")
+    G.set_friction(math.inf)
+    G.set_open_ends(1.0 + drho / 2, 1.0 - drho / 2)
+    G.step(20032)
+    rho, ux, _, _ = G.fields()
+    ue = poiseuille_exact(ny, tau, drho / 3.0 / (nx + 1), math.inf)
+    q = G.invariants()[0]
+    say(f"  flux {q / ue.sum() - 1:.2e}")
+    assert abs(q / ue.sum() - 1) < 1e-8
+    slope = np.polyfit(np.arange(nx), rho[0].mean(axis=0), 1)[0]
+    assert abs(slope / (-drho / (nx + 1)) - 1) < 1e-6
+
+
+def test_full_size_duct_open_ends_fp64(lbm):
+    say("open ends full size duct")
+    nx, ny, nz = 256, 128, 64
+    G = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0, 0), precision="f64")
+    O = oracle.Lattice(19, oracle.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0, 0))
+    lam = np.random.default_rng(9).uniform(0.0, 0.1, G.wall_count)
+    for L in (G, O):
+        L.set_friction(lam)
+        L.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
+    G.step(3)
+    O.step(3)
+    eu, er = errs(G, O)
+    say(f"  u {eu:.2e} rho {er:.2e}")
+    assert eu < 1e-12 and er < 1e-14
+
+
+def test_open_ends_settings(lbm):
+    T = lbm.Channel(19, lbm.TUBE, 8, 12, 12, tau=0.8, precision="f64", tube_radius=4.0,
+                    tube_cy=5.5, tube_cz=5.5)
+    with pytest.raises(lbm.LBMError):
+        T.set_open_ends(1.0, 1.0)
+    M = lbm.Channel(9, lbm.MASKED, 8, 6, 1, tau=0.8, precision="f64", solid=np.zeros((6, 8)))
+    with pytest.raises(lbm.LBMError):
+        M.set_open_ends(1.0, 1.0)
+    S1 = lbm.Channel(9, lbm.SLAB, 1, 6, 1, tau=0.8, precision="f64")
+    with pytest.raises(lbm.LBMError):
+        S1.set_open_ends(1.0, 1.0)
+    S = lbm.Channel(9, lbm.SLAB, 8, 6, 1, tau=0.8, precision="f64", force=(1e-5, 0, 0))
+    for bad in [(0.0, 1.0), (1.0, float("nan")), (1.0, -1.0), (float("inf"), 1.0)]:
+        with pytest.raises(lbm.LBMError):
+            S.set_open_ends(*bad)
+    S.set_electrons(0.9, 1.0, 0.1, 0.0)
+    with pytest.raises(lbm.LBMError):
+        S.set_open_ends(1.0, 1.0)
+    S.set_electrons(0.0)
+    S.set_open_ends(1.0, 0.999)
+    with pytest.raises(lbm.LBMError):
+        S.set_electrons(0.9, 1.0, 0.1, 0.0)
+    R = lbm.Channel(9, lbm.SLAB, 8, 6, 1, tau=0.8, precision="f64", force=(1e-5, 0, 0))
+    with pytest.raises(lbm.LBMError):
+        lbm.Batch([R, S])
+    # closing again gives back the periodic channel
+    S.set_open_ends(1.0, 1.0, open_=False)
+    S2 = lbm.Channel(9, lbm.SLAB, 8, 6, 1, tau=0.8, precision="f64", force=(1e-5, 0, 0))
+    S.set_state(S2.get_state()[0], 0)
+    S.step(70)
+    S2.step(70)
+    assert np.array_equal(S.get_state()[0], S2.get_state()[0])
