@@ -394,6 +394,9 @@ def main():
     ap.add_argument("--thermal", type=int, default=0, choices=[0, 1, 2],
                     help="thermal noise (kT = 1e-6) on the duct or the batch: 1 stress "
                          "source, 2 every non-conserved direction")
+    ap.add_argument("--open-ends", action="store_true",
+                    help="duct or slab: Neumann-like inlet and outlet (densities 1 +- 1e-5) "
+                         "in place of periodic x")
     ap.add_argument("--electrons", action="store_true",
                     help="with --workload slab: electron sheets on both walls")
     ap.add_argument("--workload", default="duct",
@@ -445,6 +448,8 @@ def main():
         ch = make_duct(lbm, inputs, args.precision)
     if args.thermal:
         ch.set_thermal(1e-6, args.thermal, 1)
+    if args.open_ends:
+        ch.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
     cells = ch.fluid_count
     ch.step(args.warmup)
     ch.invariants()
@@ -461,7 +466,7 @@ def main():
 
     traffic = None
     if (os.path.exists(COUNTERS) and args.precision == "f32" and not args.thermal
-            and args.workload == "duct"):
+            and args.workload == "duct" and not args.open_ends):
         c = json.load(open(COUNTERS))
         if c.get("kernel_hash") == kernel_hash():
             traffic = c.get("bytes_per_launch")
@@ -499,7 +504,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}_256x128x64_d3q19_{args.precision}storage"
                                + ("", "_thermal_stress", "_thermal_all")[args.thermal]
-                               + ("_electrons" if slab and args.electrons else ""),
+                               + ("_electrons" if slab and args.electrons else "")
+                               + ("_open_ends" if args.open_ends else ""),
                    "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
                    "g": 1e-6, "storage": args.precision, "arithmetic": arith,
                    "friction": ("uniform lambda 0.05" if slab else
@@ -518,7 +524,9 @@ def main():
                                 "k_step<D3Q19>" if not args.thermal else
                                 f"k_step<D3Q19, noise {args.thermal}>")
                                + (" + k_electron_step (time per step covers both)"
-                                  if slab and args.electrons else ""),
+                                  if slab and args.electrons else "")
+                               + (" + k_open_ends (time per step covers both)"
+                                  if args.open_ends else ""),
                      "kernel_us": round(kern_s * 1e6, 3), "bytes_per_update": bpu},
         "cpu_baseline": cpu,
         "extras": ext,

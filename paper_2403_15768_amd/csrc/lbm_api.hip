@@ -365,6 +365,8 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_ue = take((size_t)pl.nsheet * sizeof(double));
   pl.off_swc = take(pl.sheet_wc.size() * sizeof(int32_t));
   pl.off_cellw = take(pl.cellw.size() * sizeof(int32_t));
+  // open ends: per population buffer, [side][column][4] records of the end nodes
+  pl.off_bmom = take((size_t)2 * 2 * pl.ncolbox * 4 * sizeof(double));
   pl.off_ptab = take(pl.ptab.size());
   pl.total = off;
   return LBM_OK;
@@ -425,6 +427,8 @@ void fill_args(lbm_ctx* c) {
   a.open = 0;
   a.drho_in = 0.0;
   a.drho_out = 0.0;
+  a.bmom = nullptr;  // set per launch (open ends)
+  a.bmom_out = nullptr;
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -450,6 +454,25 @@ lbm_status upload_wall_r(lbm_ctx* c, const double* lambda_dev, int64_t n) {
 
 }  // namespace
 
+namespace {
+
+double* bmom_buf(lbm_ctx* c, int b) {
+  return c->at<double>(c->pl.off_bmom) + (size_t)b * 2 * c->pl.ncolbox * 4;
+}
+
+// Open ends: the step kernels leave the end-node records of the buffer they
+// write; after the state was set from outside, rebuild them for the current
+// buffer once.
+lbm_status ensure_end_records(lbm_ctx* c) {
+  if (c->bmom_ok) return LBM_OK;
+  HIPCHK(c, lbm::launch_open_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args,
+                                     bmom_buf(c, c->cur), c->stream));
+  c->bmom_ok = true;
+  return LBM_OK;
+}
+
+}  // namespace
+
 lbm_status lbm_host::launch_one_step(lbm_ctx* c) {
   StepArgs a = c->args;
   a.step_off = c->step;  // plain launch: the step travels as an argument
@@ -459,11 +482,14 @@ lbm_status lbm_host::launch_one_step(lbm_ctx* c) {
                                         c->at<double>(c->pl.off_e[c->cur]),
                                         c->at<double>(c->pl.off_e[1 - c->cur]),
                                         c->at<double>(c->pl.off_ue), c->ea, c->stream));
+  if (a.open) {  // the ghosts read the end-node records of the buffer the step reads
+    lbm_status s = ensure_end_records(c);
+    if (s != LBM_OK) return s;
+    a.bmom = bmom_buf(c, c->cur);
+    a.bmom_out = bmom_buf(c, 1 - c->cur);
+  }
   HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
                              c->pl.bouz, c->stream));
-  if (a.open)  // the end nodes again, with the ghost pulls
-    HIPCHK(c, lbm::launch_open_ends(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
-                                    c->stream));
   c->cur = 1 - c->cur;
   c->step++;
   return LBM_OK;
@@ -476,9 +502,9 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
   const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode,
-                                        c->elec, c->pl.masked);
+                                        c->elec, c->pl.masked, c->args.open != 0);
   const void* fe = c->elec ? lbm::electron_kernel_ptr(c->pl.Q, c->pl.prec) : nullptr;
-  const void* fo = c->args.open ? lbm::open_kernel_ptr(c->pl.Q, c->pl.prec, c->args.th_mode) : nullptr;
+  double* bm[2] = {bmom_buf(c, parity), bmom_buf(c, 1 - parity)};
   const double* esrc[2] = {c->at<double>(c->pl.off_e[parity]), c->at<double>(c->pl.off_e[1 - parity])};
   double* edst[2] = {c->at<double>(c->pl.off_e[1 - parity]), c->at<double>(c->pl.off_e[parity])};
   double* uep = c->at<double>(c->pl.off_ue);
@@ -511,6 +537,10 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
       }
       prev = enode;
     }
+    if (args[k].open) {  // end-node records: read those of the source buffer
+      args[k].bmom = bm[k & 1];
+      args[k].bmom_out = bm[(k + 1) & 1];
+    }
     void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&args[k]};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
@@ -526,20 +556,6 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
       return c->hip(e, "hipGraphAddKernelNode");
     }
     prev = node;
-    if (fo) {  // the end nodes of step k again, with the ghost pulls
-      hipKernelNodeParams op{};
-      op.func = const_cast<void*>(fo);
-      op.gridDim = dim3((unsigned)c->pl.slots.size());
-      op.blockDim = dim3(64);
-      op.kernelParams = kargs;
-      hipGraphNode_t onode = nullptr;
-      e = hipGraphAddKernelNode(&onode, g, &prev, 1, &op);
-      if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return c->hip(e, "hipGraphAddKernelNode");
-      }
-      prev = onode;
-    }
   }
   {
     int64_t inc = kGraphSteps;
@@ -581,6 +597,10 @@ lbm_status do_steps(lbm_ctx* c, int64_t n) {
     if (c->dstep_value != c->step) {
       HIPCHK(c, lbm::launch_set_step(c->at<int64_t>(c->pl.off_step), c->step, c->stream));
       c->dstep_value = c->step;
+    }
+    if (c->args.open) {
+      lbm_status s = ensure_end_records(c);
+      if (s != LBM_OK) return s;
     }
     HIPCHK(c, hipGraphLaunch(c->gexec[c->cur], c->stream));
     c->step += kGraphSteps;  // even count: buffer parity unchanged
@@ -866,6 +886,7 @@ lbm_status lbm_set_open_ends(lbm_ctx* c, int open, double rho_in, double rho_out
   c->args.open = open ? 1 : 0;
   c->args.drho_in = open ? rho_in - c->p.rho0 : 0.0;
   c->args.drho_out = open ? rho_out - c->p.rho0 : 0.0;
+  c->bmom_ok = false;
   return LBM_OK;
 }
 
@@ -1050,6 +1071,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) 
   HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], raw.data(), pl.pop_bytes, hipMemcpyHostToDevice, c->stream));
   lbm_status s = sync(c);
   if (s == LBM_OK) c->step = step;
+  c->bmom_ok = false;
   return s;
 }
 
@@ -1072,6 +1094,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* host_buf, size_t bytes, int64_t
   HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], host_buf, bytes, hipMemcpyHostToDevice, c->stream));
   lbm_status s = sync(c);
   if (s == LBM_OK) c->step = step;
+  c->bmom_ok = false;
   return s;
 }
 
@@ -1095,6 +1118,8 @@ lbm_status lbm_transfer_state(lbm_ctx* dst, lbm_ctx* src) {
       a.nz != b.nz || a.tube_radius != b.tube_radius || a.tube_cy != b.tube_cy ||
       a.tube_cz != b.tube_cz)
     return dst->fail(LBM_EINVAL, "transfer needs the same lattice and geometry");
+  if (dst->pl.masked && dst->pl.solid != src->pl.solid)
+    return dst->fail(LBM_EINVAL, "transfer needs the same solid mask");
   lbm_status s = sync(src);
   if (s != LBM_OK) return s;
   const Plan &pd = dst->pl, &ps = src->pl;
@@ -1109,6 +1134,7 @@ lbm_status lbm_transfer_state(lbm_ctx* dst, lbm_ctx* src) {
   }
   dst->have_raw = src->have_raw;
   dst->step = src->step;
+  dst->bmom_ok = false;
   s = upload_wall_r(dst, dst->at<double>(pd.off_lambda), (int64_t)nw);
   return s;
 }

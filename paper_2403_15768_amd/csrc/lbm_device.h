@@ -120,9 +120,14 @@ struct StepArgs {
   const uint8_t* ptab;
   int64_t nw2d;
   // open x ends (0: periodic): prescribed density deviations rho - rho0 of
-  // the ghost planes x = -1 (inlet) and x = nx (outlet)
+  // the ghost planes x = -1 (inlet) and x = nx (outlet); records
+  // (sum g, u_x, u_y, u_z) of the stored populations of the first and the
+  // last node of every column, [side][column][4], of the buffer the step
+  // reads (bmom) and of the one it writes (bmom_out)
   int open;
   double drho_in, drho_out;
+  const double* bmom;
+  double* bmom_out;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
@@ -316,14 +321,19 @@ __device__ __forceinline__ int64_t src_off(const StepArgs& a, int i, int z, bool
 // reflects off a wall moving with the electrons of the solid point x - c_i:
 //   BB_i = g_opp(i)(x) + 6 w_i rho0 c_ix u_e(x - c_i)
 // (a wall link with c_ix != 0 crosses a y wall or a z wall, never both).
-template <class L, typename S, typename M, typename W, bool BOUZ, bool ELEC = false>
+//
+// With OPEN (open x ends) the pulls of the first and last node that would
+// wrap around x read the node itself instead (x - c_i clamped into the box):
+// the ghost's own population g_i(b); open_correct adds the rest of the ghost.
+template <class L, typename S, typename M, typename W, bool BOUZ, bool ELEC = false,
+          bool OPEN = false>
 __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs& a, int col,
                                        int x, ColInfo info, M* df, unsigned dl = 0u) {
   const LBM_GLOBAL S* g = gbl(g0);
   const int64_t sI = a.sI, sC = a.sC;
   const unsigned ux = (unsigned)x;
-  const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
-  const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
+  const unsigned xm = (x == 0) ? (OPEN ? 0u : (unsigned)a.nx - 1u) : ux - 1u;
+  const unsigned xp = (x == a.nx - 1) ? (OPEN ? ux : 0u) : ux + 1u;
   const uint32_t mask = info.mask;
   const LBM_GLOBAL S* gown = g + (int64_t)col * sC;
   if (mask == 0u) {
@@ -552,6 +562,64 @@ __device__ __forceinline__ void open_patch(const S* __restrict__ g0, const StepA
   }
 }
 
+// Record of one end node for the open-end ghosts: drho = sum_k g_k and
+// u = sum_k g_k c_k / (rho0 + drho) of its stored populations (gc: the
+// column's base, x its cell), written to o[0..3].  Summed in the order the
+// step kernel's collide_store<REC> sums what it stores (rest, then each
+// opposite pair), so that a state set from outside continues bit for bit.
+template <class L, typename S, typename M>
+__device__ __forceinline__ void end_record(const LBM_GLOBAL S* gc, const StepArgs& a, unsigned x,
+                                           LBM_GLOBAL double* o) {
+  M r0 = ld<S, M>(gc, x), jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 1; i < L::Q; i++) {
+    const int op = L::opp[i];
+    if (op < i) continue;
+    const M di = ld<S, M>(gc + L::row[i] * a.sI, x), d_o = ld<S, M>(gc + L::row[op] * a.sI, x);
+    const M dd = di - d_o;
+    r0 += di + d_o;
+    if (L::cx[i]) jx += L::cx[i] > 0 ? dd : -dd;
+    if (L::cy[i]) jy += L::cy[i] > 0 ? dd : -dd;
+    if (L::cz[i]) jz += L::cz[i] > 0 ? dd : -dd;
+  }
+  const M rho = static_cast<M>(a.rho0) + r0;
+  o[0] = static_cast<double>(r0);
+  o[1] = static_cast<double>(jx / rho);
+  o[2] = static_cast<double>(jy / rho);
+  o[3] = static_cast<double>(jz / rho);
+}
+
+// The rest of the ghost for the step kernel (whose OPEN gather already
+// read g_i(b)): for the first (last) node of an x-line, each fluid link that
+// would pull from x = -1 (x = nx) gains
+//   w_i (drho_bc - drho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2 - 1.5 u_b.u_b)
+// from b's record (a.bmom).  Lanes inside the line return at once.
+template <class L, typename M>
+__device__ __forceinline__ void open_correct(const StepArgs& a, int col, int x, uint32_t mask,
+                                             M* df) {
+  const bool in = x == 0, out = x == a.nx - 1;
+  if (!in && !out) return;
+  const int z = col / a.ny;
+  const int y = col - z * a.ny;
+  const LBM_GLOBAL double* bm = gbl(a.bmom) + (out ? (int64_t)a.ny * a.nz * 4 : 0);
+  const M dbc = static_cast<M>(in ? a.drho_in : a.drho_out);
+#pragma unroll
+  for (int i = 0; i < L::Q; i++) {
+    if (L::cx[i] == 0 || (mask & (1u << i))) continue;
+    if (!((L::cx[i] > 0 && in) || (L::cx[i] < 0 && out))) continue;
+    int zb = z - L::cz[i];
+    if (zb < 0) zb += a.nz;  // z periodic (slab; a duct never pulls across z)
+    if (zb >= a.nz) zb -= a.nz;
+    const LBM_GLOBAL double* r = bm + ((int64_t)(y - L::cy[i]) + (int64_t)a.ny * zb) * 4;
+    const M drho = static_cast<M>(r[0]);
+    const M ux_ = static_cast<M>(r[1]), uy_ = static_cast<M>(r[2]), uz_ = static_cast<M>(r[3]);
+    const M cu = cdot<L, M>(i, ux_, uy_, uz_);
+    const M usq = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
+    df[i] += static_cast<M>(L::w[i]) * (dbc - drho) *
+             (M(1) + M(3) * cu + M(4.5) * cu * cu - M(1.5) * usq);
+  }
+}
+
 // ------------------------------------------------------------------ thermal noise
 // Fluctuating LB (Sec. 3.2, Eq. 6: the classical fluctuation-dissipation
 // theorem for the random momentum flux; Sec. 4, Eq. 17: the fluctuating LB
@@ -707,10 +775,13 @@ __device__ __forceinline__ void thermal_noise(const StepArgs& a, uint32_t cell, 
 // computed once and the odd parts cancel exactly in the next moments.
 // With TH = 1 or 2, xi holds the cell's thermal term of that form
 // (thermal_noise), added to every result.
-template <class L, typename M, typename S, int TH = 0>
+//
+// With REC the moments of the values as stored (decoded back: sum g,
+// sum g c) are summed into rec[0..3] (the open ends' end-node records).
+template <class L, typename M, typename S, int TH = 0, bool REC = false>
 __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LBM_GLOBAL S* out_col,
                                               unsigned x, uint32_t cell, int64_t step,
-                                              const M* xi = nullptr) {
+                                              const M* xi = nullptr, M* rec = nullptr) {
   constexpr bool THERM = TH != 0;
   M drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -744,7 +815,12 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
     M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
     if constexpr (THERM) v += xi[0];
     static_assert(L::row[0] == 0, "the rest population is the column's first row");
-    *at(sbase(out_col), x) = Store<S, M>::enc(v, w0 & 0xffffu);
+    const S e = Store<S, M>::enc(v, w0 & 0xffffu);
+    *at(sbase(out_col), x) = e;
+    if constexpr (REC) {
+      rec[0] = dec<S, M>(e);
+      rec[1] = rec[2] = rec[3] = M(0);
+    }
   }
 #pragma unroll
   for (int i = 1; i < L::Q; i++) {
@@ -763,8 +839,17 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
       vo += xi[o];
     }
     const uint32_t word = Store<S, M>::kRandom ? rb.next() : 0u;
-    *at(sbase(out_col + L::row[i] * a.sI), x) = Store<S, M>::enc(vi, word & 0xffffu);
-    *at(sbase(out_col + L::row[o] * a.sI), x) = Store<S, M>::enc(vo, word >> 16);
+    const S ei = Store<S, M>::enc(vi, word & 0xffffu);
+    const S eo = Store<S, M>::enc(vo, word >> 16);
+    *at(sbase(out_col + L::row[i] * a.sI), x) = ei;
+    *at(sbase(out_col + L::row[o] * a.sI), x) = eo;
+    if constexpr (REC) {  // c_o = -c_i
+      const M di = dec<S, M>(ei), dd = di - dec<S, M>(eo);
+      rec[0] += di + dec<S, M>(eo);
+      if (L::cx[i]) rec[1] += L::cx[i] > 0 ? dd : -dd;
+      if (L::cy[i]) rec[2] += L::cy[i] > 0 ? dd : -dd;
+      if (L::cz[i]) rec[3] += L::cz[i] > 0 ? dd : -dd;
+    }
   }
 }
 

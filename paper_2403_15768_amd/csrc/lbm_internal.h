@@ -49,6 +49,7 @@ struct Plan {
   int pstride = 0;         // partner-table bytes per 2-D wall node (whole words)
   int64_t nwallslots = 0;  // leading slots whose columns hold wall nodes
   size_t off_cellw = 0, off_ptab = 0;
+  size_t off_bmom = 0;  // open ends: [side][column][4] moments of the end nodes
   int64_t nsheet = 0;               // electron sheet nodes (SLAB: 2 nz nx; else 0)
   std::vector<int32_t> sheet_wc;    // [sheet][z]: wall column next to the sheet
   // arena offsets
@@ -77,6 +78,7 @@ struct lbm_ctx {
   int64_t dstep_value = 0;  // value the device step base holds after enqueued work
   double kT = 0.0;          // lattice temperature of the thermal noise (0: none)
   bool elec = false;        // electron sheets on (SLAB)
+  bool bmom_ok = false;     // open ends: end-node records of pop[cur] are current
   lbm::ElecArgs ea{};
 
   template <typename T>

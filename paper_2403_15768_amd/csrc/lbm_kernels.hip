@@ -30,9 +30,9 @@
 namespace lbm {
 
 // ------------------------------------------------------------ stream-collide
-template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC = false>
-__global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
-                                              StepArgs a) {
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN>
+__device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restrict__ dst,
+                                           const StepArgs& a) {
   // grid (fluid columns, segments per x-line).  Wall columns go first (their
   // blocks do more work and would otherwise form the tail of the grid).  The
   // rest are visited in one order when reading one buffer and in the reverse
@@ -59,9 +59,38 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
   M xi[L::Q];
   if constexpr (TH != 0)
     thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
-  gather<L, S, M, M, BOUZ, ELEC>(src, a, col, xc, info, df);
-  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                                (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+  gather<L, S, M, M, BOUZ, ELEC, OPEN>(src, a, col, xc, info, df);
+  if constexpr (OPEN) open_correct<L, M>(a, col, xc, info.mask, df);
+  M rec[4];
+  collide_store<L, M, S, TH, OPEN>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                                   (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi, rec);
+  // open ends: the end nodes leave the record of what they stored (the same
+  // sums end_record forms) for the ghosts of the next step
+  if constexpr (OPEN)
+    if (x == xc && (x == 0 || x == a.nx - 1)) {
+      LBM_GLOBAL double* o =
+          gbl(a.bmom_out) + ((x == 0 ? 0 : (int64_t)a.ny * a.nz) + col) * 4;
+      const M rho = static_cast<M>(a.rho0) + rec[0];
+      o[0] = static_cast<double>(rec[0]);
+      o[1] = static_cast<double>(rec[1] / rho);
+      o[2] = static_cast<double>(rec[2] / rho);
+      o[3] = static_cast<double>(rec[3] / rho);
+    }
+}
+
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC = false>
+__global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
+                                              StepArgs a) {
+  step_cells<L, S, M, BOUZ, TH, ELEC, false>(src, dst, a);
+}
+
+// Open x ends: the same update with the ghost pulls at both ends of every
+// x-line (the end-node records hold a few more registers: four waves per
+// SIMD instead of five; asking for five makes the compiler spill)
+template <class L, typename S, typename M, int TH>
+__global__ void __launch_bounds__(512) k_step_open(const S* __restrict__ src,
+                                                      S* __restrict__ dst, StepArgs a) {
+  step_cells<L, S, M, false, TH, false, true>(src, dst, a);
 }
 
 // Masked walls: the same update on every fluid point of the columns that
@@ -98,31 +127,19 @@ __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
                              (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
 }
 
-// Open x ends: after k_step (which treats x as periodic) this kernel
-// recomputes the first and last node of every fluid x-line with the ghost
-// pulls (open_patch) and overwrites them.  One wave per column: lane 0 takes
-// x = 0, lane 1 x = nx - 1 (nx >= 2); both read the source buffer only, like
-// k_step, so the result is that of one update with open ends.
-template <class L, typename S, typename M, int TH>
-__global__ void __launch_bounds__(64) k_open_ends(const S* __restrict__ src, S* __restrict__ dst,
-                                                  StepArgs a) {
-  const int lane = threadIdx.x;
-  if (lane > 1) return;
-  const int x = lane == 0 ? 0 : a.nx - 1;
-  const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[blockIdx.x];
-  const int col = uniform(cs.col);
-  ColInfo info;
-  info.wallcol = uniform(cs.wallcol);
-  info.mask = (uint32_t)uniform((int)cs.mask);
-  const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
-  M df[L::Q];
-  M xi[L::Q];
-  if constexpr (TH != 0)
-    thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
-  gather<L, S, M, M, false, false>(src, a, col, x, info, df);
-  open_patch<L, S, M>(src, a, col, x, info.mask, df);
-  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                             (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+// Open x ends: the records (sum g, u) of the first and last node of every
+// fluid column of src ([side][column][4]) where no step has left them (after
+// the state was set from outside).  One lane per (column, side).
+template <class L, typename S, typename M>
+__global__ void __launch_bounds__(256) k_open_moments(const S* __restrict__ src, StepArgs a,
+                                                      double* __restrict__ bmom) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * (int64_t)a.nactive) return;
+  const int side = (int)(t & 1);
+  const int col = gbl(a.slots)[t >> 1].col;
+  const unsigned x = side ? (unsigned)a.nx - 1u : 0u;
+  end_record<L, S, M>(gbl(src) + (int64_t)col * a.sC, a, x,
+                      gbl(bmom) + ((int64_t)side * a.ny * a.nz + col) * 4);
 }
 
 // ------------------------------------------------------------ electron sheets
@@ -795,7 +812,12 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 
 // the step kernel for a wall kind and a noise form (0: none)
 template <class L, typename S, typename M>
-static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked) {
+static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked, bool open) {
+  if (open) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, 1>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, 2>);
+    return reinterpret_cast<const void*>(&k_step_open<L, S, M, 0>);
+  }
   if (masked) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 1>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 2>);
@@ -825,8 +847,8 @@ static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, b
   StepArgs args = a;
   void* kargs[3] = {(void*)&s, (void*)&d, (void*)&args};
   return hipLaunchKernel(
-      step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr, a.cellw != nullptr), grid, block,
-      kargs, 0, st);
+      step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr, a.cellw != nullptr, a.open != 0),
+      grid, block, kargs, 0, st);
 }
 
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
@@ -841,8 +863,9 @@ hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepAr
   return launch_step_t<D3Q19, _Float16, float>(src, dst, a, bouz, st);
 }
 
-const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec, bool masked) {
-#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec, masked)
+const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec, bool masked,
+                            bool open) {
+#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec, masked, open)
   if (q == 9) {
     if (prec == 0) return KP(D2Q9, double, double);
     if (prec == 1) return KP(D2Q9, float, double);
@@ -854,31 +877,25 @@ const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec, 
 #undef KP
 }
 
-template <class L, typename S, typename M>
-static const void* open_kernel_t(int th) {
-  if (th == 1) return reinterpret_cast<const void*>(&k_open_ends<L, S, M, 1>);
-  if (th == 2) return reinterpret_cast<const void*>(&k_open_ends<L, S, M, 2>);
-  return reinterpret_cast<const void*>(&k_open_ends<L, S, M, 0>);
-}
-
-const void* open_kernel_ptr(int q, int prec, int th_mode) {
+const void* open_moments_kernel_ptr(int q, int prec) {
   if (q == 9) {
-    if (prec == 0) return open_kernel_t<D2Q9, double, double>(th_mode);
-    if (prec == 1) return open_kernel_t<D2Q9, float, double>(th_mode);
-    return open_kernel_t<D2Q9, _Float16, float>(th_mode);
+    if (prec == 0) return reinterpret_cast<const void*>(&k_open_moments<D2Q9, double, double>);
+    if (prec == 1) return reinterpret_cast<const void*>(&k_open_moments<D2Q9, float, double>);
+    return reinterpret_cast<const void*>(&k_open_moments<D2Q9, _Float16, float>);
   }
-  if (prec == 0) return open_kernel_t<D3Q19, double, double>(th_mode);
-  if (prec == 1) return open_kernel_t<D3Q19, float, double>(th_mode);
-  return open_kernel_t<D3Q19, _Float16, float>(th_mode);
+  if (prec == 0) return reinterpret_cast<const void*>(&k_open_moments<D3Q19, double, double>);
+  if (prec == 1) return reinterpret_cast<const void*>(&k_open_moments<D3Q19, float, double>);
+  return reinterpret_cast<const void*>(&k_open_moments<D3Q19, _Float16, float>);
 }
 
-hipError_t launch_open_ends(int q, int prec, const void* src, void* dst, const StepArgs& a,
-                            hipStream_t st) {
-  if (a.nactive <= 0 || a.nx < 2) return hipErrorInvalidValue;
+hipError_t launch_open_moments(int q, int prec, const void* src, const StepArgs& a, double* bmom,
+                               hipStream_t st) {
+  const int64_t n = 2 * (int64_t)a.nactive;
+  if (n <= 0 || (n + 255) / 256 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   StepArgs args = a;
-  void* kargs[3] = {(void*)&src, (void*)&dst, (void*)&args};
-  return hipLaunchKernel(open_kernel_ptr(q, prec, a.th_mode), dim3((unsigned)a.nactive), dim3(64),
-                         kargs, 0, st);
+  void* kargs[3] = {(void*)&src, (void*)&args, (void*)&bmom};
+  return hipLaunchKernel(open_moments_kernel_ptr(q, prec), dim3((unsigned)((n + 255) / 256)),
+                         dim3(256), kargs, 0, st);
 }
 
 const void* electron_kernel_ptr(int q, int prec) {

@@ -36,17 +36,17 @@ struct ElecArgs {
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
                        hipStream_t st);  // a.ue: electron-sheet walls; a.cellw: masked walls
 const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec,
-                            bool masked);
+                            bool masked, bool open);
 // one electron step from the water state g (step n): e_src -> e_dst, u_e of
 // step n -> ue; the water step of step n then reads ue
 hipError_t launch_electron_step(int q, int prec, const void* g, const double* e_src,
                                 double* e_dst, double* ue, const ElecArgs& ea, hipStream_t st);
 const void* electron_kernel_ptr(int q, int prec);
-// open x ends: recompute the first and last node of every x-line with the
-// ghost pulls, after the step kernel of the same step (src -> dst)
-hipError_t launch_open_ends(int q, int prec, const void* src, void* dst, const StepArgs& a,
-                            hipStream_t st);
-const void* open_kernel_ptr(int q, int prec, int th_mode);
+// open x ends: the moments of the first and last node of every column of
+// src ([side][column][4] doubles), before the step that reads src
+hipError_t launch_open_moments(int q, int prec, const void* src, const StepArgs& a, double* bmom,
+                               hipStream_t st);
+const void* open_moments_kernel_ptr(int q, int prec);  // (src, StepArgs, bmom)
 hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, bool bouz,
                           int which, double* field, double* partials, hipStream_t st);
 hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,
