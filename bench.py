@@ -196,6 +196,35 @@ def extras(torch, lbm, inputs, args):
                      "step_us": round(kms * 1e3 / 2000, 2),
                      "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
         ch.close()
+    # one rank's share of the duct split into 8 x-slabs (32 x 128 x 64, x
+    # periodic in place of the halo exchange): the channel kernel (one
+    # workgroup per 32-cell x-line) and the batch kernel (64-lane waves
+    # packed across x-lines), as a sharded run would step it
+    for name, batched in (("duct_share_32x128x64_f32", False),
+                          ("duct_share_32x128x64_f32_batch_kernel", True)):
+        ch = lbm.Channel(lbm.D3Q19, lbm.DUCT, 32, 128, 64, tau=0.7, force=(1e-6, 0.0, 0.0),
+                         precision="f32")
+        ch.set_friction(0.05)
+        cells = ch.fluid_count
+        if batched:
+            b = lbm.Batch([ch])
+            b.tune()
+            b.step(64)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(b.stream)
+            b.step(2048)
+            e1.record(b.stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 2048
+            b.close()
+        else:
+            ch.step(200)
+            _, kms = timed_run(torch, ch, 2048, 1024)
+            us = kms * 1e3 / 2048
+        out[name] = {"mlups": round(cells / us, 1), "step_us": round(us, 2),
+                     "hbm_frac": round(152 * cells / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        ch.close()
     # open x ends (Neumann-like inlet and outlet): the benchmark duct with a
     # density drop besides its body force; the step kernel plus the kernel
     # that recomputes the end nodes with the ghost pulls
