@@ -109,6 +109,8 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_shell_count.restype = lp
     lib.ora_sizeof_real.restype = C.c_int
     lib.ora_set_open_ends.argtypes = [vp, C.c_int, C.c_double, C.c_double]
+    lib.ora_set_noise_closure.argtypes = [vp, dp, C.c_int, C.c_int, dp, dp]
+    lib.ora_set_noise_closure.restype = C.c_int
     lib.ora_set_open_ends.restype = C.c_int
     u64p = C.POINTER(C.c_uint64)
     lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
@@ -214,6 +216,22 @@ class Lattice:
                                        float(force_e)) != 0:
             raise OracleError("electron sheets need a SLAB or DUCT without moving wall, "
                               "tau_e > 1/2, rho_e0 > 0, gamma_e >= 0")
+
+    def set_noise_closure(self, gamma=None, wx=None, wt=None) -> None:
+        """One-point closure of the quantum noise: gamma shaped (6, nr, ns) (the
+        correlator of the components xx, yy, zz, xy, xz, yz at lags r, s),
+        weights wx (nr) and wt (ns); None restores the classical noise."""
+        if gamma is None:
+            rc = self._lib.ora_set_noise_closure(self._h, None, 0, 0, None, None)
+        else:
+            g = np.ascontiguousarray(gamma, dtype=np.float64)
+            a = np.ascontiguousarray(wx, dtype=np.float64)
+            b = np.ascontiguousarray(wt, dtype=np.float64)
+            assert g.shape == (6, a.size, b.size)
+            rc = self._lib.ora_set_noise_closure(self._h, _dptr(g), a.size, b.size, _dptr(a),
+                                                 _dptr(b))
+        if rc != 0:
+            raise OracleError("closure factors must be finite and >= 0")
 
     def set_open_ends(self, rho_in: float, rho_out: float, open_: bool = True) -> None:
         """Open x ends (Neumann-like inlet and outlet at densities rho_in,

@@ -144,6 +144,10 @@ typedef struct {
   int open;
   double rho_in, rho_out;
   uint64_t seed; /* key of the thermal random numbers */
+  /* one-point closure of the quantum noise: square roots of the factors
+   * m_c by which the stress components' variances are scaled, in the order
+   * xx, yy, zz, xy, xz, yz (1 = classical) */
+  real qfac[6];
   /* electron shells (SLAB and DUCT): the solid columns next to the water,
    * each with an electron line along x, D1Q3 (see shell_of) */
   int elec;
@@ -345,6 +349,7 @@ int ora_create(const ora_params *p, ora_ctx **out) {
   o = (ora_ctx *)calloc(1, sizeof(ora_ctx));
   if (!o) return ORA_ENOMEM;
   o->p = *p;
+  for (i = 0; i < 6; i++) o->qfac[i] = 1;
   set_lattice(o);
   o->ncell = (long)p->nx * p->ny * p->nz;
   o->fluid = (unsigned char *)calloc(o->ncell, 1);
@@ -599,6 +604,37 @@ int ora_set_thermal(ora_ctx *o, double kT, int mode, uint64_t seed) {
   return ORA_OK;
 }
 
+/* One-point closure of the quantum fluctuations (Sec. 4, Eq. 18): the
+ * two-point quantum correlator (Eq. 16), whose lag dependence Gamma_ab the
+ * Keldysh analysis would supply, is averaged over spatial lags r and time
+ * lags s with weights W_x(r), W_t(s) into a one-point tensor,
+ *   m_ab = sum_r sum_s W_x(r) W_t(s) Gamma_ab(r, s),
+ * which here scales the variance of each component of the random stress of
+ * the stress-source noise (Eq. 17): P_ab -> sqrt(m_ab) P_ab.  gamma holds
+ * Gamma for the six components xx, yy, zz, xy, xz, yz, each an nr x ns table
+ * (component-major, then r, then s); a 2-D lattice ignores zz, xz, yz.  Every
+ * m must come out finite and >= 0.  gamma == NULL restores the classical
+ * noise (m = 1). */
+int ora_set_noise_closure(ora_ctx *o, const double *gamma, int nr, int ns,
+                          const double *wx, const double *wt) {
+  real m[6];
+  int c, r, t;
+  if (!gamma) {
+    for (c = 0; c < 6; c++) o->qfac[c] = 1;
+    return ORA_OK;
+  }
+  if (nr < 1 || ns < 1 || !wx || !wt) return ORA_EINVAL;
+  for (c = 0; c < 6; c++) {
+    m[c] = 0;
+    for (r = 0; r < nr; r++)
+      for (t = 0; t < ns; t++)
+        m[c] += (real)wx[r] * (real)wt[t] * (real)gamma[((long)c * nr + r) * ns + t];
+    if (!(m[c] >= 0) || !R_ISFINITE(m[c])) return ORA_EINVAL;
+  }
+  for (c = 0; c < 6; c++) o->qfac[c] = R_SQRT(m[c]);
+  return ORA_OK;
+}
+
 /* Philox4x64 with 10 rounds: each round multiplies words 0 and 2 by two
  * fixed odd constants, forms the new words from the high halves xor the
  * other words xor the round key and from the low halves, and the key grows by
@@ -692,10 +728,11 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
     ora_thermal_normals(o->seed, n, step, d * (d + 1) / 2, z);
     for (a = 0; a < 3; a++)
       for (b = 0; b < 3; b++) P[a][b] = 0;
-    for (a = 0; a < d; a++) P[a][a] = sqrt(2.0) * cs2 * A * (real)z[k++];
+    for (a = 0; a < d; a++) P[a][a] = sqrt(2.0) * cs2 * A * o->qfac[a] * (real)z[k++];
     for (a = 0; a < d; a++)
       for (b = a + 1; b < d; b++) {
-        P[a][b] = cs2 * A * (real)z[k++];
+        /* xy -> 3, xz -> 4, yz -> 5 */
+        P[a][b] = cs2 * A * o->qfac[a == 0 ? 2 + b : 5] * (real)z[k++];
         P[b][a] = P[a][b];
       }
     for (i = 0; i < o->q; i++) {

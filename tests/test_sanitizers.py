@@ -44,6 +44,7 @@ int ora_set_friction(ora_ctx *, const double *);
 int ora_set_thermal(ora_ctx *, double, int, uint64_t);
 int ora_set_electrons(ora_ctx *, double, double, double, double);
 int ora_set_open_ends(ora_ctx *, int, double, double);
+int ora_set_noise_closure(ora_ctx *, const double *, int, int, const double *, const double *);
 void ora_get_electrons(const ora_ctx *, double *, double *);
 void ora_step(ora_ctx *, long);
 void ora_fields(const ora_ctx *, double *, double *, double *, double *);
@@ -77,6 +78,11 @@ static int run(int q, int geom, int nx, int ny, int nz, double R, int mode, int 
   ora_wall_links(o, links);
   if (ora_set_friction(o, lam)) return 2;
   if (mode && ora_set_thermal(o, 1e-6, mode, 9)) return 3;
+  if (mode == 1) {
+    double gam[6 * 2 * 3], wx[2] = {0.3, 0.7}, wt[3] = {0.2, 0.5, 0.3};
+    for (int k = 0; k < 36; k++) gam[k] = 0.5 + 0.1 * (k % 5);
+    if (ora_set_noise_closure(o, gam, 2, 3, wx, wt)) return 7;
+  }
   if (elec && ora_set_electrons(o, 0.9, 1.0, 0.05, 1e-6)) return 4;
   if (!elec && geom <= 1 && ora_set_open_ends(o, 1, 1.0001, 0.9999)) return 6;
   ora_step(o, 7);
