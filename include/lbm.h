@@ -203,6 +203,24 @@ lbm_status lbm_get_friction(lbm_ctx *ctx, double *lambda, double *raw);
 typedef enum { LBM_NOISE_STRESS = 1, LBM_NOISE_ALL = 2 } lbm_noise;
 lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
 
+/* One-point closure of the quantum fluctuations (Sec. 4, Eq. 18): the
+ * two-point quantum correlator of the fluctuating forces (Eq. 16), whose lag
+ * dependence Gamma_ab the Keldysh analysis would supply, averaged over
+ * spatial lags r and time lags s into a one-point tensor
+ *   m_ab = sum_r sum_s W_x(r) W_t(s) Gamma_ab(r, s),
+ * which scales the variance of each component of the random stress of the
+ * stress-source noise (LBM_NOISE_STRESS): P_ab -> sqrt(m_ab) P_ab, the same
+ * Philox normals as the classical noise.  gamma: host, 6 * nr * ns doubles,
+ * the components xx, yy, zz, xy, xz, yz in that order, each an nr x ns table
+ * indexed [r][s]; wx (nr) and wt (ns) the weights.  A 2-D lattice ignores
+ * zz, xz and yz.  Every m_ab must be finite and >= 0 (else LBM_EINVAL); a
+ * unit correlator with weights summing to one gives the classical noise bit
+ * for bit; gamma == NULL restores it.  Takes effect with the stress-source
+ * noise (lbm_set_thermal); kept across lbm_set_thermal calls.  Batches carry
+ * each member's factors.  Synchronous (finishes queued work). */
+lbm_status lbm_set_noise_closure(lbm_ctx *ctx, const double *gamma, int nr, int ns,
+                                 const double *wx, const double *wt);
+
 /* Open x ends: the Neumann-like inlet and outlet of Sec. 4.2 (the option the
  * paper sets beside periodic ends) in place of periodic x.  From the next
  * step on, a fluid link of the first (last) node of an x-line that would

@@ -420,6 +420,7 @@ void fill_args(lbm_ctx* c) {
   a.th_amp = 0.0;
   a.th_mode = 0;
   a.th_seed = 0;
+  for (int k = 0; k < 6; k++) a.th_fac[k] = 1.0;
   a.ue = nullptr;
   a.cellw = pl.masked ? c->at<int32_t>(pl.off_cellw) : nullptr;
   a.ptab = pl.masked ? c->at<uint8_t>(pl.off_ptab) : nullptr;
@@ -862,6 +863,34 @@ lbm_status lbm_set_thermal(lbm_ctx* c, double kT, int mode, uint64_t seed) {
   c->args.th_mode = kT > 0.0 ? mode : 0;
   c->args.th_seed = seed;
   c->kT = kT;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_noise_closure(lbm_ctx* c, const double* gamma, int nr, int ns,
+                                 const double* wx, const double* wt) {
+  if (!c) return LBM_EINVAL;
+  double fac[6] = {1, 1, 1, 1, 1, 1};
+  if (gamma) {
+    if (nr < 1 || ns < 1 || !wx || !wt) return c->fail(LBM_EINVAL, "need nr, ns >= 1 and weights");
+    for (int k = 0; k < 6; k++) {
+      // the lag average of component k: sum_r sum_s W_x(r) W_t(s) Gamma_k(r, s)
+      double m = 0.0;
+      for (int r = 0; r < nr; r++)
+        for (int t = 0; t < ns; t++) m += wx[r] * wt[t] * gamma[((int64_t)k * nr + r) * ns + t];
+      if (!(m >= 0.0) || !std::isfinite(m))
+        return c->fail(LBM_EINVAL, "closure factor %d is %g: must be finite and >= 0", k, m);
+      fac[k] = std::sqrt(m);
+    }
+  }
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 2; k++) {  // the step graphs hold the step arguments
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+  for (int k = 0; k < 6; k++) c->args.th_fac[k] = fac[k];
   return LBM_OK;
 }
 

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -55,6 +56,7 @@ struct lbm_batch {
   std::vector<int64_t> base;      // each member's step when the table was written
   std::vector<double> th_amp;     // each member's noise amplitude and key in the table
   std::vector<uint64_t> th_seed;
+  std::vector<std::array<double, 6>> th_fac;  // and noise-closure factors
   int64_t max_items = 0;  // capacity of the item arrays (largest list over the shapes)
   size_t off_desc = 0, off_items = 0, off_cols = 0, off_order = 0, off_mstart = 0, off_partials = 0,
          off_out = 0, off_bstep = 0, total = 0;
@@ -406,7 +408,8 @@ lbm_status resync(lbm_batch* b) {
   for (size_t m = 0; m < b->m.size(); m++) {
     lbm_ctx* c = b->m[m];
     if (c->step == b->base[m] + b->k && c->args.th_amp == b->th_amp[m] &&
-        c->args.th_seed == b->th_seed[m])
+        c->args.th_seed == b->th_seed[m] &&
+        std::equal(b->th_fac[m].begin(), b->th_fac[m].end(), c->args.th_fac))
       continue;
     lbm_status s = sync(c);
     if (s != LBM_OK) return b->fail(s, "member stream failed");
@@ -417,6 +420,7 @@ lbm_status resync(lbm_batch* b) {
     b->base[m] = d.base_step;
     b->th_amp[m] = c->args.th_amp;
     b->th_seed[m] = c->args.th_seed;
+    std::copy(c->args.th_fac, c->args.th_fac + 6, b->th_fac[m].begin());
   }
   return LBM_OK;
 }
@@ -563,6 +567,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   b->base.assign(n, 0);
   b->th_amp.assign(n, 0.0);
   b->th_seed.assign(n, 0);
+  b->th_fac.assign(n, std::array<double, 6>{});
   b->th = ctxs[0]->args.th_mode;
   for (int m = 0; m < n; m++) {
     lbm_ctx* c = ctxs[m];
@@ -575,6 +580,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
     b->base[m] = c->step;
     b->th_amp[m] = c->args.th_amp;
     b->th_seed[m] = c->args.th_seed;
+    std::copy(c->args.th_fac, c->args.th_fac + 6, b->th_fac[m].begin());
   }
   const int64_t zero = 0;
   lbm_status st = LBM_OK;

@@ -107,6 +107,9 @@ struct StepArgs {
   double th_amp;
   int th_mode;
   uint64_t th_seed;
+  // one-point closure of the quantum noise (form 1): factors on the random
+  // stress components xx, yy, zz, xy, xz, yz (1: classical)
+  double th_fac[6];
   // electron shells (slab and duct walls): x velocity of each shell node in
   // the step being taken, [shell][x]; shells y = -1, y = ny (by z), then for
   // a duct z = -1, z = nz (by y)
@@ -711,11 +714,14 @@ __device__ __forceinline__ void thermal_noise(const StepArgs& a, uint32_t cell, 
     normal_pair(r.w[1], &z[2], &z[3]);
     if (L::Q == 19) normal_pair(r.w[2], &z[4], &z[5]);
     const M sd = M(2.12132034355964257320) * A, so = M(3) * A;
-    // 2-D: xx, yy, xy; 3-D: xx, yy, zz, xy, xz, yz
-    const M pxx = sd * z[0], pyy = sd * z[1];
-    const M pzz = L::Q == 19 ? sd * z[2] : M(0);
-    const M pxy = so * (L::Q == 19 ? z[3] : z[2]);
-    const M pxz = L::Q == 19 ? so * z[4] : M(0), pyz = L::Q == 19 ? so * z[5] : M(0);
+    // 2-D: xx, yy, xy; 3-D: xx, yy, zz, xy, xz, yz; each component scaled by
+    // its closure factor (exactly 1 for the classical noise)
+    const M pxx = (sd * static_cast<M>(a.th_fac[0])) * z[0];
+    const M pyy = (sd * static_cast<M>(a.th_fac[1])) * z[1];
+    const M pzz = L::Q == 19 ? (sd * static_cast<M>(a.th_fac[2])) * z[2] : M(0);
+    const M pxy = (so * static_cast<M>(a.th_fac[3])) * (L::Q == 19 ? z[3] : z[2]);
+    const M pxz = L::Q == 19 ? (so * static_cast<M>(a.th_fac[4])) * z[4] : M(0);
+    const M pyz = L::Q == 19 ? (so * static_cast<M>(a.th_fac[5])) * z[5] : M(0);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
       const M t = M(1) / M(3);

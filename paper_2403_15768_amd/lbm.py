@@ -65,7 +65,7 @@ EXPORTS = [
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
-    "lbm_get_electrons", "lbm_set_open_ends",
+    "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -104,6 +104,7 @@ def load() -> C.CDLL:
         "lbm_set_electrons": [vp, C.c_double, C.c_double, C.c_double, C.c_double],
         "lbm_get_electrons": [vp, dp, dp],
         "lbm_set_open_ends": [vp, C.c_int, C.c_double, C.c_double],
+        "lbm_set_noise_closure": [vp, dp, C.c_int, C.c_int, dp, dp],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_flux": [vp, dp],
@@ -300,6 +301,23 @@ class Channel:
         NOISE_STRESS (the stress source alone) or NOISE_ALL."""
         self._ck(self._lib.lbm_set_thermal(self._h, float(kT), int(mode), int(seed)),
                  "lbm_set_thermal")
+
+    def set_noise_closure(self, gamma=None, wx=None, wt=None) -> None:
+        """One-point closure of the quantum noise (stress-source form): gamma
+        shaped (6, nr, ns) for the components xx, yy, zz, xy, xz, yz at lags
+        (r, s), weights wx (nr) and wt (ns); None: the classical noise."""
+        if gamma is None:
+            rc = self._lib.lbm_set_noise_closure(self._h, None, 0, 0, None, None)
+        else:
+            g = np.ascontiguousarray(gamma, dtype=np.float64)
+            a = np.ascontiguousarray(wx, dtype=np.float64)
+            b = np.ascontiguousarray(wt, dtype=np.float64)
+            if g.shape != (6, a.size, b.size):
+                raise ValueError("gamma must be shaped (6, len(wx), len(wt))")
+            dpt = C.POINTER(C.c_double)
+            rc = self._lib.lbm_set_noise_closure(self._h, g.ctypes.data_as(dpt), a.size, b.size,
+                                                 a.ctypes.data_as(dpt), b.ctypes.data_as(dpt))
+        self._ck(rc, "lbm_set_noise_closure")
 
     # ---- open x ends
     def set_open_ends(self, rho_in: float, rho_out: float, open_: bool = True) -> None:

@@ -300,3 +300,83 @@ def test_full_duct_mass_and_axial_momentum_conserved_fp64(lbm):
     assert abs((rho - 1).sum() - m0) < 1e-9
     assert abs((rho * ux).sum() - j0) < 1e-9
     assert np.std(rho * ux) > 1e-3
+
+
+def closure_tables(seed=9):
+    # a one-point closure of the quantum noise: separable correlator tables
+    # on 3 spatial and 4 time lags, every component its own factor
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.2, 3.0, (6, 3))
+    g = rng.uniform(0.1, 1.0, 4)
+    return f[:, :, None] * g[None, None, :], rng.uniform(0.1, 1.0, 3), rng.uniform(0.1, 1.0, 4)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_noise_closure_one_step_parity_fp64(lbm, case):
+    say("noise closure one step", case)
+    kT, tau = 1e-6, 0.8
+    G, O = build(lbm, case, "f64", tau=tau)
+    A = amplitude(kT, tau)
+    g0 = equilibrium_sample(G.q, G.shape, 3 * kT, 8)
+    O.set_populations(g0, step=99)
+    G.set_populations(g0, step=99)
+    gam, wx, wt = closure_tables()
+    for L in (G, O):
+        L.set_thermal(kT, 1, 7)
+        L.set_noise_closure(gam, wx, wt)
+    G.step(1)
+    O.step(1)
+    pg, po = G.populations(), O.get_populations()
+    fluid = O.fields()[0] != 0
+    d = np.abs(pg - po)[:, fluid]
+    say("  max |dg| / A", d.max() / A)
+    # the factors sqrt(m) reach 3.6 here: the classical bound 1e-5 A scaled
+    assert d.max() < 3.6e-5 * A
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_noise_closure_fields_and_unit_closure(lbm, precision):
+    say("noise closure fields", precision)
+    G, O = build(lbm, "duct", precision)
+    gam, wx, wt = closure_tables(3)
+    for L in (G, O):
+        L.set_thermal(1e-7, 1, 21)
+        L.set_noise_closure(gam, wx, wt)
+    G.step(101)
+    O.step(101)
+    rg, ro = G.fields(), O.fields()
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / np.abs(ro[1]).max()
+    say(f"  fields {err:.2e}")
+    assert err < 3e-4
+    # a unit correlator with weights summing to one is the classical noise
+    A, _ = build(lbm, "slab", precision)
+    B, _ = build(lbm, "slab", precision)
+    for L in (A, B):
+        L.set_thermal(1e-6, 1, 5)
+    B.set_noise_closure(np.ones((6, 2, 2)), [0.25, 0.75], [0.5, 0.5])
+    A.step(70)
+    B.step(70)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+    with pytest.raises(lbm.LBMError):
+        B.set_noise_closure(-np.ones((6, 1, 1)), [1.0], [1.0])
+
+
+def test_batch_carries_the_noise_closure(lbm):
+    say("noise closure in a batch")
+    alone = thermal_ducts(lbm, "f32", 1)
+    mixed = thermal_ducts(lbm, "f32", 1)
+    gam, wx, wt = closure_tables(4)
+    for chs in (alone, mixed):
+        chs[1].set_noise_closure(gam, wx, wt)
+    b = lbm.Batch(mixed)
+    b.step(64)
+    for a in alone:
+        a.step(64)
+    for chs in (alone, mixed):  # changed between batch steps
+        chs[2].set_noise_closure(gam[:, ::-1], wx[::-1], wt)
+    b.step(70)
+    for a in alone:
+        a.step(70)
+    for a, m in zip(alone, mixed):
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    b.close()
