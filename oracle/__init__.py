@@ -111,6 +111,9 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_set_open_ends.argtypes = [vp, C.c_int, C.c_double, C.c_double]
     lib.ora_set_noise_closure.argtypes = [vp, dp, C.c_int, C.c_int, dp, dp]
     lib.ora_set_noise_closure.restype = C.c_int
+    lib.ora_set_phonons.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+    lib.ora_set_phonons.restype = C.c_int
+    lib.ora_get_phonons.argtypes = [vp, dp, dp]
     lib.ora_set_open_ends.restype = C.c_int
     u64p = C.POINTER(C.c_uint64)
     lib.ora_set_thermal.argtypes = [vp, C.c_double, C.c_int, C.c_uint64]
@@ -240,6 +243,21 @@ class Lattice:
                                        float(rho_out)) != 0:
             raise OracleError("open ends need a SLAB or DUCT without electron sheets, nx >= 2 "
                               "and finite densities > 0")
+
+    def set_phonons(self, tau_p: float, rho_p0: float = 1.0, gamma_pc: float = 0.0,
+                    gamma_ep: float = 0.0) -> None:
+        """Phonon lines beside the electron lines (tau_p = 0: off); reset to rest."""
+        if self._lib.ora_set_phonons(self._h, float(tau_p), float(rho_p0), float(gamma_pc),
+                                     float(gamma_ep)) != 0:
+            raise OracleError("phonons need the electron lines on, tau_p > 1/2, rho_p0 > 0, "
+                              "gamma_pc, gamma_ep >= 0")
+
+    def phonons(self):
+        """(u_p of the last step [shell][x], populations [i][shell][x])."""
+        up = np.zeros((self.shell_count, self.nx))
+        pops = np.zeros((3, self.shell_count, self.nx))
+        self._lib.ora_get_phonons(self._h, _dptr(up), _dptr(pops))
+        return up, pops
 
     @property
     def shell_count(self) -> int:

@@ -154,6 +154,10 @@ typedef struct {
   double tau_e, rho_e0, gamma_e, force_e;
   real *e, *en; /* shifted populations [i][shell][x], i = 0, +x, -x */
   real *ue;     /* electron velocity of the last step, [shell][x] */
+  /* phonon lines beside the electron lines (Sec. 3.4), same layout */
+  int phon;
+  double tau_p, rho_p0, gamma_pc, gamma_ep;
+  real *ph, *phn, *up;
 } ora_ctx;
 
 /* ---------------------------------------------------------------- lattice */
@@ -410,6 +414,9 @@ void ora_destroy(ora_ctx *o) {
   free(o->e);
   free(o->en);
   free(o->ue);
+  free(o->ph);
+  free(o->phn);
+  free(o->up);
   free(o->fluid);
   free(o->wall_id);
   free(o->r);
@@ -792,6 +799,7 @@ int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
   memset(o->e, 0, 3 * n * sizeof(real));
   memset(o->ue, 0, n * sizeof(real));
   o->elec = 1;
+  o->phon = 0; /* switching the electrons on resets them without phonons */
   o->tau_e = tau_e;
   o->rho_e0 = rho_e0;
   o->gamma_e = gamma_e;
@@ -839,8 +847,43 @@ static void electron_step(ora_ctx *o) {
         F0 -= 2 * o->r[cf] * o->g[(long)o->opp[k] * o->ncell + cf] * (real)o->c[k][0];
         K += 6 * (real)o->p.rho0 * o->r[cf] * o->w[k];
       }
-      u = (j + ((real)o->force_e + F0) / 2) / (rho * (1 + gam / 2) + K / 2);
-      F = (real)o->force_e + F0 - K * u - gam * rho * u;
+      if (!o->phon) {
+        u = (j + ((real)o->force_e + F0) / 2) / (rho * (1 + gam / 2) + K / 2);
+        F = (real)o->force_e + F0 - K * u - gam * rho * u;
+      } else {
+        /* phonons: the electron-phonon drag -G (u - u_p) on the electrons and
+         * +G (u - u_p) on the phonons (Sec. 3.4; equal and opposite, Eq. 27),
+         * G = gamma_ep rho, and the crystal drag -gamma_pc rho_p u_p on the
+         * phonons; with Guo's half-forces both velocities solve
+         *   rho u     = j   + (force_e + F0 - K u - gam rho u - G (u - u_p)) / 2
+         *   rho_p u_p = j_p + (-gamma_pc rho_p u_p + G (u - u_p)) / 2 */
+        const real taup = (real)o->tau_p, gp = (real)o->gamma_pc;
+        real dp[3], drp = 0, jp = 0, rp, G, a11, a22, b1, det, Fp, upv;
+        for (i = 0; i < 3; i++) {
+          int xs = ((x - cd[i]) % o->p.nx + o->p.nx) % o->p.nx;
+          dp[i] = o->ph[(long)i * n + sh * o->p.nx + xs];
+          drp += dp[i];
+          jp += dp[i] * (real)cd[i];
+        }
+        rp = (real)o->rho_p0 + drp;
+        G = (real)o->gamma_ep * rho;
+        a11 = rho * (1 + gam / 2) + K / 2 + G / 2;
+        a22 = rp * (1 + gp / 2) + G / 2;
+        b1 = j + ((real)o->force_e + F0) / 2;
+        det = a11 * a22 - G * G / 4;
+        u = (b1 * a22 + G / 2 * jp) / det;
+        upv = (a11 * jp + G / 2 * b1) / det;
+        F = (real)o->force_e + F0 - K * u - gam * rho * u - G * (u - upv);
+        Fp = -gp * rp * upv + G * (u - upv);
+        for (i = 0; i < 3; i++) {
+          real c = (real)cd[i];
+          real eq = wd[i] * (drp + rp * (3 * c * upv + (real)4.5 * c * c * upv * upv -
+                                        (real)1.5 * upv * upv));
+          real src = (1 - 1 / (2 * taup)) * wd[i] * (3 * (c - upv) + 9 * c * upv * c) * Fp;
+          o->phn[(long)i * n + s] = dp[i] - (dp[i] - eq) / taup + src;
+        }
+        o->up[s] = upv;
+      }
       for (i = 0; i < 3; i++) {
         real c = (real)cd[i];
         real eq = wd[i] * (drho + rho * (3 * c * u + (real)4.5 * c * c * u * u -
@@ -856,6 +899,52 @@ static void electron_step(ora_ctx *o) {
     o->e = o->en;
     o->en = t;
   }
+  if (o->phon) {
+    real *t = o->ph;
+    o->ph = o->phn;
+    o->phn = t;
+  }
+}
+
+/* Phonon lines (Sec. 3.4): a third population set, one D1Q3 line beside
+ * every electron line, BGK with tau_p around rho_p0, driven only by the
+ * electron-phonon drag of Sec. 3.4 (equal and opposite on the two, Eq. 27;
+ * coefficient gamma_ep rho_e) and damped by the crystal, -gamma_pc rho_p u_p;
+ * they do not touch the water.  Requires the electron lines on; resets the
+ * phonons to rest; tau_p == 0 switches them off. */
+int ora_set_phonons(ora_ctx *o, double tau_p, double rho_p0, double gamma_pc, double gamma_ep) {
+  long n = nshell(o) * o->p.nx;
+  if (tau_p == 0) {
+    o->phon = 0;
+    return ORA_OK;
+  }
+  if (!o->elec || !(tau_p > 0.5) || !(rho_p0 > 0) || !(gamma_pc >= 0) || !(gamma_ep >= 0) ||
+      !isfinite(tau_p) || !isfinite(rho_p0) || !isfinite(gamma_pc) || !isfinite(gamma_ep))
+    return ORA_EINVAL;
+  if (!o->ph) {
+    o->ph = (real *)calloc(3 * n, sizeof(real));
+    o->phn = (real *)calloc(3 * n, sizeof(real));
+    o->up = (real *)calloc(n, sizeof(real));
+    if (!o->ph || !o->phn || !o->up) return ORA_ENOMEM;
+  }
+  memset(o->ph, 0, 3 * n * sizeof(real));
+  memset(o->up, 0, n * sizeof(real));
+  o->phon = 1;
+  o->tau_p = tau_p;
+  o->rho_p0 = rho_p0;
+  o->gamma_pc = gamma_pc;
+  o->gamma_ep = gamma_ep;
+  return ORA_OK;
+}
+
+/* phonon velocity of the last step [shell][x] and populations [i][shell][x] */
+void ora_get_phonons(const ora_ctx *o, double *up, double *pops) {
+  long k, n = nshell(o) * o->p.nx;
+  if (!o->phon) return;
+  for (k = 0; k < n; k++)
+    if (up) up[k] = (double)o->up[k];
+  if (pops)
+    for (k = 0; k < 3 * n; k++) pops[k] = (double)o->ph[k];
 }
 
 /* electron velocity of the last step [shell][x] and the shifted populations

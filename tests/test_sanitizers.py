@@ -1,7 +1,7 @@
 """Host sanitizers (no GPU): the oracle built with AddressSanitizer and
 UndefinedBehaviorSanitizer (gcc) and driven through every entry point -- the
 four geometries and both lattices, friction, thermal noise of both forms,
-electron sheets, open ends, masked walls, the plain and the screened
+electron sheets and phonons, open ends, masked walls, the plain and the screened
 quadrature, population get/set --
 must run without a single report.  The library's host-side planning
 (geometry classification, wall tables, arena layout) is exercised the same
@@ -45,6 +45,8 @@ int ora_set_thermal(ora_ctx *, double, int, uint64_t);
 int ora_set_electrons(ora_ctx *, double, double, double, double);
 int ora_set_open_ends(ora_ctx *, int, double, double);
 int ora_set_noise_closure(ora_ctx *, const double *, int, int, const double *, const double *);
+int ora_set_phonons(ora_ctx *, double, double, double, double);
+void ora_get_phonons(const ora_ctx *, double *, double *);
 void ora_get_electrons(const ora_ctx *, double *, double *);
 void ora_step(ora_ctx *, long);
 void ora_fields(const ora_ctx *, double *, double *, double *, double *);
@@ -84,6 +86,7 @@ static int run(int q, int geom, int nx, int ny, int nz, double R, int mode, int 
     if (ora_set_noise_closure(o, gam, 2, 3, wx, wt)) return 7;
   }
   if (elec && ora_set_electrons(o, 0.9, 1.0, 0.05, 1e-6)) return 4;
+  if (elec && ora_set_phonons(o, 0.8, 1.2, 0.02, 0.1)) return 8;
   if (!elec && geom <= 1 && ora_set_open_ends(o, 1, 1.0001, 0.9999)) return 6;
   ora_step(o, 7);
   ora_fields(o, f, f + nc, f + 2 * nc, f + 3 * nc);
@@ -92,6 +95,7 @@ static int run(int q, int geom, int nx, int ny, int nz, double R, int mode, int 
   ora_set_populations(o, g, 7);
   ora_step(o, 3);
   if (elec) ora_get_electrons(o, ue, pe);
+  if (elec) ora_get_phonons(o, ue, pe);
   if (!isfinite(inv[0]) || !isfinite(inv[1])) return 5;
   free(lam); free(xyz); free(links); free(f); free(g); free(ue); free(pe); free(mask);
   ora_destroy(o);
