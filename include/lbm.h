@@ -278,6 +278,25 @@ lbm_status lbm_set_electrons(lbm_ctx *ctx, double tau_e, double rho_e0,
  * either may be NULL.  LBM_ESTATE if the sheets are off.  Synchronous. */
 lbm_status lbm_get_electrons(lbm_ctx *ctx, double *ue, double *pops);
 
+/* Phonon lines (Sec. 3.4): a third population set, one D1Q3 line beside every
+ * electron line, BGK with tau_p around rho_p0.  The electron-phonon drag acts
+ * equal and opposite on the two (Eq. 27): -G (u_e - u_p) on the electrons and
+ * +G (u_e - u_p) on the phonons, G = gamma_ep rho_e at the node; the crystal
+ * damps the phonons, -gamma_pc rho_p u_p.  Phonons do not touch the water.
+ * With Guo's half-forces both velocities come from one 2 x 2 solve per node,
+ * in the electron step.  Water, electrons and phonons then change axial
+ * momentum only by the external forces and the two crystal drags; at steady
+ * state U_p = G U_e / (G + gamma_pc rho_p0).  Requires the electron lines
+ * on (else LBM_EINVAL); tau_p > 1/2, rho_p0 > 0, gamma_pc, gamma_ep >= 0,
+ * finite; tau_p == 0 switches them off; lbm_set_electrons switches them off.
+ * Resets the phonons to rest.  Synchronous. */
+lbm_status lbm_set_phonons(lbm_ctx *ctx, double tau_p, double rho_p0, double gamma_pc,
+                           double gamma_ep);
+/* u_p of the last step (nshell * nx doubles) and the current phonon
+ * populations (3 * nshell * nx, [i][shell][x]); host arrays, either may be
+ * NULL.  LBM_ESTATE if the phonons are off.  Synchronous. */
+lbm_status lbm_get_phonons(lbm_ctx *ctx, double *up, double *pops);
+
 /* Advance nsteps >= 0 time steps (asynchronous). */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 /* Step in chunks of check_every until |Q(n) - Q(n - check_every)| <

@@ -360,9 +360,10 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_out = take(4 * sizeof(double));
   pl.off_flag = take(4 * sizeof(int));
   pl.off_step = take(sizeof(int64_t));
-  pl.off_e[0] = take((size_t)pl.nsheet * 3 * sizeof(double));
-  pl.off_e[1] = take((size_t)pl.nsheet * 3 * sizeof(double));
-  pl.off_ue = take((size_t)pl.nsheet * sizeof(double));
+  // electron lines: rows 0..2 electrons, 3..5 phonons; velocities u_e then u_p
+  pl.off_e[0] = take((size_t)pl.nsheet * 6 * sizeof(double));
+  pl.off_e[1] = take((size_t)pl.nsheet * 6 * sizeof(double));
+  pl.off_ue = take((size_t)pl.nsheet * 2 * sizeof(double));
   pl.off_swc = take(pl.sheet_wc.size() * sizeof(int32_t));
   pl.off_cellw = take(pl.cellw.size() * sizeof(int32_t));
   // open ends: per population buffer, [side][column][4] records of the end nodes
@@ -957,11 +958,62 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   ea.rho_e0 = rho_e0;
   ea.gamma_e = gamma_e;
   ea.force_e = force_e;
+  ea.phon = 0;  // switching the electrons on resets them without phonons
   // electrons at rest
   for (int k = 0; k < 2; k++)
-    HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_e[k]), 0, (size_t)pl.nsheet * 3 * sizeof(double),
+    HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_e[k]), 0, (size_t)pl.nsheet * 6 * sizeof(double),
                              c->stream));
-  HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_ue), 0, (size_t)pl.nsheet * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_ue), 0, (size_t)pl.nsheet * 2 * sizeof(double),
+                           c->stream));
+  return sync(c);
+}
+
+lbm_status lbm_set_phonons(lbm_ctx* c, double tau_p, double rho_p0, double gamma_pc,
+                           double gamma_ep) {
+  if (!c) return LBM_EINVAL;
+  const bool on = tau_p != 0.0;
+  if (on) {
+    if (!c->elec) return c->fail(LBM_EINVAL, "phonon lines need the electron lines on");
+    if (!(tau_p > 0.5) || !(rho_p0 > 0.0) || !(gamma_pc >= 0.0) || !(gamma_ep >= 0.0) ||
+        !std::isfinite(tau_p) || !std::isfinite(rho_p0) || !std::isfinite(gamma_pc) ||
+        !std::isfinite(gamma_ep))
+      return c->fail(LBM_EINVAL, "need tau_p > 1/2, rho_p0 > 0, gamma_pc, gamma_ep >= 0, finite");
+  }
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  for (int k = 0; k < 2; k++) {  // the step graphs hold the electron arguments
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+  lbm::ElecArgs& ea = c->ea;
+  ea.phon = on ? 1 : 0;
+  if (!on) return LBM_OK;
+  ea.omega_p = 1.0 / tau_p;
+  ea.rho_p0 = rho_p0;
+  ea.gamma_pc = gamma_pc;
+  ea.gamma_ep = gamma_ep;
+  const Plan& pl = c->pl;
+  for (int k = 0; k < 2; k++)  // phonons at rest
+    HIPCHK(c, hipMemsetAsync(c->at<double>(pl.off_e[k]) + 3 * pl.nsheet, 0,
+                             (size_t)pl.nsheet * 3 * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->at<double>(pl.off_ue) + pl.nsheet, 0, (size_t)pl.nsheet * sizeof(double),
+                           c->stream));
+  return sync(c);
+}
+
+lbm_status lbm_get_phonons(lbm_ctx* c, double* up, double* pops) {
+  if (!c) return LBM_EINVAL;
+  if (!c->elec || !c->ea.phon) return c->fail(LBM_ESTATE, "phonon lines are off");
+  const Plan& pl = c->pl;
+  if (up)
+    HIPCHK(c, hipMemcpyAsync(up, c->at<double>(pl.off_ue) + pl.nsheet,
+                             (size_t)pl.nsheet * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (pops)
+    HIPCHK(c, hipMemcpyAsync(pops, c->at<double>(pl.off_e[c->cur]) + 3 * pl.nsheet,
+                             (size_t)pl.nsheet * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
   return sync(c);
 }
 

@@ -195,11 +195,40 @@ __global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
     K += 6.0 * ea.rho0 * r * L::w[k];
   }
   const double gam = ea.gamma_e;
-  const double u = (j + 0.5 * (ea.force_e + F0)) / (rho * (1.0 + 0.5 * gam) + 0.5 * K);
-  const double F = ea.force_e + F0 - K * u - gam * rho * u;
+  const double c[3] = {0.0, 1.0, -1.0}, w[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
+  double u, F;
+  if (!ea.phon) {
+    u = (j + 0.5 * (ea.force_e + F0)) / (rho * (1.0 + 0.5 * gam) + 0.5 * K);
+    F = ea.force_e + F0 - K * u - gam * rho * u;
+  } else {
+    // phonon line beside it: the electron-phonon drag G (u - u_p), G =
+    // gamma_ep rho, on both (opposite signs) and the crystal drag on the
+    // phonons; with the half-forces a 2 x 2 linear system in (u, u_p)
+    const double p0 = es[3 * n + s], p1 = es[4 * n + line + xm], p2 = es[5 * n + line + xp];
+    const double drp = p0 + p1 + p2, jp = p1 - p2;
+    const double rp = ea.rho_p0 + drp, gp = ea.gamma_pc;
+    const double G = ea.gamma_ep * rho;
+    const double a11 = rho * (1.0 + 0.5 * gam) + 0.5 * K + 0.5 * G;
+    const double a22 = rp * (1.0 + 0.5 * gp) + 0.5 * G;
+    const double b1 = j + 0.5 * (ea.force_e + F0);
+    const double det = a11 * a22 - 0.25 * G * G;
+    u = (b1 * a22 + 0.5 * G * jp) / det;
+    const double up = (a11 * jp + 0.5 * G * b1) / det;
+    F = ea.force_e + F0 - K * u - gam * rho * u - G * (u - up);
+    const double Fp = -gp * rp * up + G * (u - up);
+    const double omp = ea.omega_p, Ap = 1.0 - 0.5 * omp;
+    const double dp[3] = {p0, p1, p2};
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const double eq =
+          w[i] * (drp + rp * (3.0 * c[i] * up + 4.5 * c[i] * c[i] * up * up - 1.5 * up * up));
+      const double src = Ap * w[i] * (3.0 * (c[i] - up) + 9.0 * c[i] * up * c[i]) * Fp;
+      ed[(3 + i) * n + s] = dp[i] - omp * (dp[i] - eq) + src;
+    }
+    ue[n + s] = up;
+  }
   const double om = ea.omega_e, A = 1.0 - 0.5 * om;
   const double d[3] = {d0, d1, d2};
-  const double c[3] = {0.0, 1.0, -1.0}, w[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     const double eq = w[i] * (drho + rho * (3.0 * c[i] * u + 4.5 * c[i] * c[i] * u * u - 1.5 * u * u));

@@ -30,6 +30,11 @@ struct ElecArgs {
   const int32_t* swc;    // [shell]: wall column of the fluid column next to the shell
   double rho0;           // water reference density
   double omega_e, rho_e0, gamma_e, force_e;
+  // phonon lines beside the electron lines (rows 3..5 of the state, their
+  // velocity after the electrons'): on/off, 1/tau_p, rho_p0, crystal drag,
+  // electron-phonon drag coefficient
+  int phon;
+  double omega_p, rho_p0, gamma_pc, gamma_ep;
 };
 
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S

@@ -65,7 +65,8 @@ EXPORTS = [
     "lbm_batch_items", "lbm_batch_step", "lbm_batch_invariants", "lbm_batch_tune",
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
-    "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure",
+    "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure", "lbm_set_phonons",
+    "lbm_get_phonons",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -103,6 +104,8 @@ def load() -> C.CDLL:
         "lbm_set_thermal": [vp, C.c_double, C.c_int, C.c_uint64],
         "lbm_set_electrons": [vp, C.c_double, C.c_double, C.c_double, C.c_double],
         "lbm_get_electrons": [vp, dp, dp],
+        "lbm_set_phonons": [vp, C.c_double, C.c_double, C.c_double, C.c_double],
+        "lbm_get_phonons": [vp, dp, dp],
         "lbm_set_open_ends": [vp, C.c_int, C.c_double, C.c_double],
         "lbm_set_noise_closure": [vp, dp, C.c_int, C.c_int, dp, dp],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
@@ -347,6 +350,22 @@ class Channel:
         self._ck(self._lib.lbm_get_electrons(self._h, _dptr(ue), _dptr(pops)),
                  "lbm_get_electrons")
         return ue, pops
+
+    def set_phonons(self, tau_p: float, rho_p0: float = 1.0, gamma_pc: float = 0.0,
+                    gamma_ep: float = 0.0) -> None:
+        """Phonon lines beside the electron lines (tau_p = 0: off); reset to rest."""
+        self._ck(self._lib.lbm_set_phonons(self._h, float(tau_p), float(rho_p0),
+                                           float(gamma_pc), float(gamma_ep)), "lbm_set_phonons")
+
+    def phonons(self):
+        """(u_p of the last step [shell][x], phonon populations [i][shell][x])."""
+        ns = self.shell_count
+        up = np.zeros((ns, self.nx))
+        pops = np.zeros((3, ns, self.nx))
+        dpt = C.POINTER(C.c_double)
+        self._ck(self._lib.lbm_get_phonons(self._h, up.ctypes.data_as(dpt),
+                                           pops.ctypes.data_as(dpt)), "lbm_get_phonons")
+        return up, pops
 
     # ---- time stepping
     def step(self, n: int) -> None:

@@ -34,9 +34,10 @@ def test_footprint_host_logic():
     assert lbm.footprint(p64) > 1.9 * nb
     # x-lines up to 128 cells stored back to back; longer ones padded to
     # whole 128-byte lines (nx = 200 -> 224 floats, 256 halves); a duct also
-    # reserves its electron lines: (2 nz + 2 ny) shells x nx x 7 doubles
+    # reserves its electron and phonon lines: (2 nz + 2 ny) shells x nx x 14
+    # doubles (two buffers of 6 rows, two velocities)
     def electrons(nx, ny, nz):
-        return (2 * nz + 2 * ny) * nx * 7 * 8
+        return (2 * nz + 2 * ny) * nx * 14 * 8
     p = lbm.make_params(lbm.D3Q19, lbm.DUCT, 37, 5, 4, tau=0.7, precision="f32")
     pops = 2 * 19 * 37 * 20 * 4
     assert pops + electrons(37, 5, 4) <= lbm.footprint(p) < pops * 1.2 + electrons(37, 5, 4)

@@ -187,3 +187,110 @@ def test_half_storage_electrons_track_the_oracle(lbm):
     e = np.abs(ueg - ueo).max() / np.abs(ueo).max()
     say(f"  u_e {e:.2e}")
     assert e < 2e-3
+
+
+PHON = (0.7, 1.3, 0.02, 0.08)  # tau_p, rho_p0, gamma_pc, gamma_ep
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_phonon_parity_over_graph_and_plain_steps(lbm, case, precision):
+    say("phonons parity", case, precision)
+    G, O = build(lbm, case, precision)
+    for L in (G, O):
+        L.set_phonons(*PHON)
+    n = 101
+    G.step(n)
+    O.step(n)
+    rg, ro = G.fields(), O.fields()
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / np.abs(ro[1]).max()
+    ueg, _ = G.electrons()
+    ueo, _ = O.electrons()
+    upg, ppg = G.phonons()
+    upo, ppo = O.phonons()
+    eu = np.abs(ueg - ueo).max() / np.abs(ueo).max()
+    ep = np.abs(upg - upo).max() / np.abs(upo).max()
+    epp = np.abs(ppg - ppo).max() / np.abs(ppo).max()
+    say(f"  water {err:.2e}  u_e {eu:.2e}  u_p {ep:.2e}  phonon pops {epp:.2e}")
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert err < tol and eu < tol and ep < tol and epp < tol
+
+
+def test_phonons_graph_and_plain_launches_bitwise(lbm):
+    say("phonons bitwise")
+    A, _ = build(lbm, "duct", "f32")
+    B, _ = build(lbm, "duct", "f32")
+    for L in (A, B):
+        L.set_phonons(*PHON)
+    A.step(128)
+    for _ in range(128):
+        B.step(1)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+    assert np.array_equal(A.phonons()[1], B.phonons()[1])
+
+
+def test_phonons_steady_state_closed_form(lbm):
+    say("phonons steady state")
+    H, tau, lam, fh, fe = 30, 0.8, 0.05, 1e-6, 0.0
+    rho_e, gam, rho_p, gpc, gep = 2.0, 0.2, 1.5, 0.1, 0.3
+    G = lbm.Channel(9, lbm.SLAB, 4, H, 1, tau=tau, force=(fh, 0, 0), precision="f64")
+    G.set_friction(lam)
+    G.set_electrons(0.9, rho_e, gam, fe)
+    G.set_phonons(0.8, rho_p, gpc, gep)
+    G.step(45056)
+    Gc = gep * rho_e
+    kappa = Gc / (Gc + gpc * rho_p)
+    Ue = (fh * H + fe * 2) / (2 * (gam * rho_e + gpc * rho_p * kappa))
+    ue, _ = G.electrons()
+    up, _ = G.phonons()
+    assert np.abs(ue / Ue - 1).max() < 1e-10
+    assert np.abs(up / (kappa * Ue) - 1).max() < 1e-10
+
+
+def test_phonons_full_size_momentum_bookkeeping_fp64(lbm):
+    say("phonons full size momentum")
+    nx, ny, nz, fh = 256, 128, 64, 2e-6
+    tau_e, rho_e, gam, fe = ELEC
+    tau_p, rho_p, gpc, gep = PHON
+    G = lbm.Channel(19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(fh, 0, 0), precision="f64")
+    G.set_friction(np.random.default_rng(3).uniform(0.0, 0.2, G.wall_count))
+    G.set_electrons(tau_e, rho_e, gam, fe)
+    G.set_phonons(tau_p, rho_p, gpc, gep)
+    G.step(200)
+
+    def totals():
+        g = G.populations()
+        _, pe = G.electrons()
+        _, pp = G.phonons()
+        return (float(np.tensordot(C19X, g, axes=(0, 0)).sum()), float((pe[1] - pe[2]).sum()),
+                float((pp[1] - pp[2]).sum()), pe, pp)
+    w0, e0, p0, pe, pp = totals()
+    re = rho_e + pe[0] + np.roll(pe[1], 1, axis=-1) + np.roll(pe[2], -1, axis=-1)
+    rp = rho_p + pp[0] + np.roll(pp[1], 1, axis=-1) + np.roll(pp[2], -1, axis=-1)
+    G.step(1)
+    w1, e1, p1, _, _ = totals()
+    ue, _ = G.electrons()
+    up, _ = G.phonons()
+    expect = (fh * G.fluid_count + fe * G.shell_count * nx - gam * float((re * ue).sum())
+              - gpc * float((rp * up).sum()))
+    res = (w1 + e1 + p1) - (w0 + e0 + p0) - expect
+    say(f"  residual {res:.3e} of {abs(w0):.3e}")
+    assert abs(res) < 1e-12 * abs(w0)
+    assert abs(p1 - p0) > 1e-12 * abs(w0)
+
+
+def test_phonon_settings(lbm):
+    S = lbm.Channel(9, lbm.SLAB, 8, 4, 1, tau=0.8, precision="f64")
+    with pytest.raises(lbm.LBMError):  # electrons off
+        S.set_phonons(*PHON)
+    S.set_electrons(*ELEC)
+    with pytest.raises(lbm.LBMError):
+        S.phonons()  # off
+    for bad in [(0.5, 1.0, 0.1, 0.1), (0.8, 0.0, 0.1, 0.1), (0.8, 1.0, -0.1, 0.1),
+                (0.8, 1.0, 0.1, float("nan"))]:
+        with pytest.raises(lbm.LBMError):
+            S.set_phonons(*bad)
+    S.set_phonons(*PHON)
+    S.set_electrons(*ELEC)  # switches the phonons off
+    with pytest.raises(lbm.LBMError):
+        S.phonons()
