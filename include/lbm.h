@@ -204,7 +204,7 @@ typedef enum { LBM_NOISE_STRESS = 1, LBM_NOISE_ALL = 2 } lbm_noise;
 lbm_status lbm_set_thermal(lbm_ctx *ctx, double kT, int mode, uint64_t seed);
 
 /* One-point closure of the quantum fluctuations (Sec. 4, Eq. 18): the
- * two-point quantum correlator of the fluctuating forces (Eq. 16), whose lag
+ * two-point quantum correlator of the fluctuating forces (Eq. 7), whose lag
  * dependence Gamma_ab the Keldysh analysis would supply, averaged over
  * spatial lags r and time lags s into a one-point tensor
  *   m_ab = sum_r sum_s W_x(r) W_t(s) Gamma_ab(r, s),

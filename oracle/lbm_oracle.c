@@ -612,7 +612,7 @@ int ora_set_thermal(ora_ctx *o, double kT, int mode, uint64_t seed) {
 }
 
 /* One-point closure of the quantum fluctuations (Sec. 4, Eq. 18): the
- * two-point quantum correlator (Eq. 16), whose lag dependence Gamma_ab the
+ * two-point quantum correlator (Eq. 7), whose lag dependence Gamma_ab the
  * Keldysh analysis would supply, is averaged over spatial lags r and time
  * lags s with weights W_x(r), W_t(s) into a one-point tensor,
  *   m_ab = sum_r sum_s W_x(r) W_t(s) Gamma_ab(r, s),
