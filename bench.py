@@ -258,6 +258,14 @@ def extras(torch, lbm, inputs, args):
                                  "step_us": round(kms * 1e3 / 2000, 2),
                                  "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
                                                    / HBM_PEAK_GBS, 4)}
+    # with phonon lines beside the electron lines (solved in the same kernel)
+    ch.set_phonons(0.7, 1.3, 0.02, 0.08)
+    ch.step(200)
+    wall, kms = timed_run(torch, ch, 2000, 1000)
+    out["duct_f32_electrons_phonons"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                                         "step_us": round(kms * 1e3 / 2000, 2),
+                                         "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000)
+                                                           / 1e9 / HBM_PEAK_GBS, 4)}
     ch.close()
     # the fluctuating update (thermal noise, kT = 1e-6) on the FP32 duct,
     # both noise forms

@@ -186,3 +186,26 @@ def test_masked_rejections(lbm):
     S = lbm.Channel(9, lbm.SLAB, 8, 6, 1, tau=0.8, precision="f64")
     with pytest.raises(lbm.LBMError):
         lbm.Batch([S, M])
+
+
+@pytest.mark.parametrize("q,nx,ny,nz", [(9, 1, 9, 1), (19, 1, 8, 3), (19, 5, 9, 1), (9, 300, 12, 1)])
+def test_degenerate_and_long_masks_fp64(lbm, q, nx, ny, nz):
+    # a one-cell-long box (every step face wraps onto itself), a one-layer
+    # D3Q19 box, and a long x-line (padded, several segments) with steps
+    say("masked edge", q, nx, ny, nz)
+    solid = np.zeros((ny, nx), dtype=bool)
+    solid[:2, ::2] = True
+    solid[ny - 1, : max(1, nx // 3)] = True
+    if nx > 2:
+        solid[ny // 2, nx // 2] = True
+    kw = dict(tau=0.8, force=(2e-6, 1e-7, 0))
+    G = lbm.Channel(q, lbm.MASKED, nx, ny, nz, precision="f64", solid=solid, **kw)
+    O = oracle.Lattice(q, oracle.MASKED, nx, ny, nz, solid=solid, **kw)
+    lam = np.random.default_rng(2).uniform(0.0, 0.5, G.wall_count)
+    G.set_friction(lam)
+    O.set_friction(lam)
+    G.step(130)
+    O.step(130)
+    eu, er = field_err(G, O)
+    assert eu < 1e-12 and er < 1e-14
+    assert abs(G.invariants()[2]) < 1e-13 * G.fluid_count

@@ -180,3 +180,20 @@ def test_restart_with_open_ends_bitwise(lbm, precision):
     A.step(131)
     B.step(131)
     assert np.array_equal(A.get_state()[0], B.get_state()[0])
+
+
+@pytest.mark.parametrize("nx", [2, 3])
+@pytest.mark.parametrize("q,geom,ny,nz", [(9, "SLAB", 7, 1), (19, "DUCT", 5, 4)])
+def test_shortest_open_channels_fp64(lbm, nx, q, geom, ny, nz):
+    # the degenerate lengths: both ends in one or two cells
+    say("open ends short", nx, q, geom)
+    kw = dict(tau=0.8, force=(1e-6, 0, 0))
+    G = lbm.Channel(q, getattr(lbm, geom), nx, ny, nz, precision="f64", **kw)
+    O = oracle.Lattice(q, getattr(oracle, geom), nx, ny, nz, **kw)
+    for L in (G, O):
+        L.set_friction(0.04)
+        L.set_open_ends(1.0 + 3e-6, 1.0 - 2e-6)
+    G.step(150)
+    O.step(150)
+    eu, er = errs(G, O)
+    assert eu < 1e-12 and er < 1e-14
