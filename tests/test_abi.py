@@ -3,6 +3,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2403_15768_amd import lbm
@@ -67,3 +68,26 @@ def test_tube_footprint_counts_box():
     p = lbm.make_params(lbm.D3Q19, lbm.TUBE, 512, 72, 72, tau=0.8, tube_radius=32,
                         tube_cy=35.5, tube_cz=35.5)
     assert lbm.footprint(p) >= 2 * 19 * 512 * 72 * 72 * 4
+
+
+def test_masked_footprint_host_logic():
+    # walls that vary along x: the plan reserves the class table of the
+    # (x, y) plane and the partner tables; a mask is required, an all-solid
+    # mask and a moving wall are refused
+    nx, ny, nz = 40, 12, 3
+    solid = np.zeros((ny, nx), dtype=bool)
+    solid[:2, 10:20] = True
+    p = lbm.make_params(lbm.D3Q19, lbm.MASKED, nx, ny, nz, tau=0.8, precision="f32", solid=solid)
+    pops = 2 * 19 * nx * ny * nz * 4
+    nb = lbm.footprint(p)
+    assert pops + nx * ny * 4 <= nb < pops * 1.3 + 200_000
+    p2 = lbm.make_params(lbm.D2Q9, lbm.MASKED, nx, ny, 1, tau=0.8, precision="f64", solid=solid)
+    assert lbm.footprint(p2) >= 2 * 9 * nx * ny * 8
+    lib = lbm.load()
+    n = C.c_size_t()
+    for bad in (dict(solid=None), dict(solid=np.ones((ny, nx))),
+                dict(solid=solid, wall_velocity_top=1e-3)):
+        q = lbm.make_params(lbm.D3Q19, lbm.MASKED, nx, ny, nz, tau=0.8, precision="f32", **bad)
+        assert lib.lbm_footprint(C.byref(q), C.byref(n)) == -1
+    with pytest.raises(ValueError):
+        lbm.make_params(lbm.D3Q19, lbm.MASKED, nx, ny, nz, tau=0.8, solid=np.zeros((nx, ny)))
