@@ -415,6 +415,18 @@ def permeability_workload(args):
                       "storage": args.precision, "steady": "flux change < 1e-9 per 500 steps"},
            "loglog_slope_of_enhancement_minus_1": slopes, "tubes": rows,
            "wall_s": round(dt, 3)}
+    # the wall's shape (same section): wrinkled walls against flat ones
+    t0 = time.perf_counter()
+    wr = permeability.wrinkle_sweep([1.0, 2.0, 4.0], [float("inf"), 0.05],
+                                    precision=args.precision)
+    rec["wrinkles"] = {"config": {"lattice": "D2Q9", "nx": 128, "mean_gap": 24,
+                                  "wavelength": 64, "tau": 0.8, "g": 1e-6},
+                       "wall_s": round(time.perf_counter() - t0, 3),
+                       "rows": [{"amplitude": w.amplitude, "meander": w.meander,
+                                 "no_slip": bool(np.isinf(w.lam)),
+                                 "lambda": None if np.isinf(w.lam) else w.lam,
+                                 "flux_over_flat": round(w.relative, 5),
+                                 "steps": w.steps} for w in wr]}
     print(json.dumps(rec), flush=True)
 
 

@@ -108,15 +108,18 @@ class SpectralDraw:
         return 20.0 * self.T
 
 
-def corrugated_mask(nx: int, ny: int, rng: np.random.Generator, amp: float = 4.0,
-                    wavelength: float = 64.0, base: int = 4, post: bool = False) -> np.ndarray:
+def corrugated_mask(nx: int, ny: int, rng: np.random.Generator | None, amp: float = 4.0,
+                    wavelength: float = 64.0, base: int = 4, post: bool = False,
+                    phases=None) -> np.ndarray:
     """Solid points, shaped (ny, nx), of a slab with wrinkled walls: the
     bottom wall fills y < lo(x), the top one y >= ny - hi(x), each
-    round(base + amp sin(2 pi x / wavelength + phase)) with a random phase
-    (base >= amp keeps both >= 0).  post: a free-standing 3 x 3 post in the
-    middle of the channel as well."""
+    round(base + amp sin(2 pi x / wavelength + phase)) with a random phase, or
+    the two given phases (base >= amp keeps both >= 0; top phase = bottom
+    phase + pi gives a meander of constant gap, equal phases a gap that
+    narrows and widens).  post: a free-standing 3 x 3 post in the middle of
+    the channel as well."""
     x = np.arange(nx)
-    ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+    ph = np.asarray(phases, dtype=float) if phases is not None else rng.uniform(0.0, 2.0 * math.pi, 2)
     lo = np.round(base + amp * np.sin(2.0 * math.pi * x / wavelength + ph[0])).astype(int)
     hi = np.round(base + amp * np.sin(2.0 * math.pi * x / wavelength + ph[1])).astype(int)
     solid = np.zeros((ny, nx), dtype=bool)

@@ -13,6 +13,12 @@ continuum answer is
 
 so the enhancement falls like 1 / R.  Every number comes from the library's
 kernels; this module only sets the channels up and collects the results.
+
+The same section names nano-corrugations and wrinkles of the graphene walls
+as the next design parameter: ``wrinkle_sweep`` runs channels whose two walls
+are wrinkled along x (masked walls), as a meander of constant gap or as a
+gap that narrows and widens, against the flat channel of the same mean gap,
+with no-slip or Navier-slip walls.
 """
 from __future__ import annotations
 
@@ -68,4 +74,54 @@ def sweep(radii, omega_scales, spectral=None, nx: int = 16, tau: float = 0.8,
             n = ch.run_to_steady(rel_tol=rel_tol, check_every=check_every, max_steps=max_steps)
             out.append(TubeResult(R, float(s), lam, ch.flux(), q0, int(n)))
             ch.close()
+    return out
+
+
+@dataclass
+class WrinkleResult:
+    amplitude: float       # wrinkle amplitude (cells)
+    meander: bool          # True: constant gap; False: the gap narrows and widens
+    lam: float             # wall friction (lattice units; inf = no slip)
+    flux: float            # steady flux, wrinkled walls
+    flux_flat: float       # steady flux, flat walls of the same mean gap
+    steps: int
+
+    @property
+    def relative(self) -> float:
+        return self.flux / self.flux_flat
+
+
+def _wrinkled(nx: int, ny: int, amp: float, wavelength: float, base: int, meander: bool,
+              tau: float, g: float, precision: str):
+    solid = inputs.corrugated_mask(nx, ny, None, amp=amp, wavelength=wavelength, base=base,
+                                   phases=(0.0, np.pi if meander else 0.0))
+    return lbm.Channel(lbm.D2Q9, lbm.MASKED, nx, ny, 1, tau=tau, force=(g, 0.0, 0.0),
+                       precision=precision, solid=solid)
+
+
+def wrinkle_sweep(amplitudes, lams, gap: int = 24, nx: int = 128, wavelength: float = 64.0,
+                  meanders=(True, False), tau: float = 0.8, g: float = 1e-6,
+                  precision: str = "f64", rel_tol: float = 1e-9, check_every: int = 500,
+                  max_steps: int = 2_000_000) -> list[WrinkleResult]:
+    """Steady flux of D2Q9 channels of mean gap ``gap`` whose walls carry
+    wrinkles of the given amplitudes (cells, <= 4) and wavelength, relative to
+    the flat channel with the same walls' friction."""
+    base = 4
+    ny = gap + 2 * base
+    out = []
+    for lam in lams:
+        flat = _wrinkled(nx, ny, 0.0, wavelength, base, True, tau, g, precision)
+        flat.set_friction(lam)
+        flat.run_to_steady(rel_tol=rel_tol, check_every=check_every, max_steps=max_steps)
+        q0 = flat.flux()
+        flat.close()
+        for meander in meanders:
+            for a in amplitudes:
+                ch = _wrinkled(nx, ny, a, wavelength, base, meander, tau, g, precision)
+                ch.set_friction(lam)
+                n = ch.run_to_steady(rel_tol=rel_tol, check_every=check_every,
+                                     max_steps=max_steps)
+                out.append(WrinkleResult(float(a), bool(meander), float(lam), ch.flux(), q0,
+                                         int(n)))
+                ch.close()
     return out

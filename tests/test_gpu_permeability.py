@@ -78,3 +78,52 @@ def test_enhancement_falls_like_inverse_radius(mods):
     for R in radii:
         assert (by[(R, 2.0)].lam < by[(R, 1.0)].lam) == (by[(R, 2.0)].enhancement
                                                            > by[(R, 1.0)].enhancement)
+
+
+def oracle_wrinkled_flux(nx, gap, amp, wavelength, meander, lam, tau=0.8, g=1e-6, tol=1e-10):
+    base = 4
+    solid = inputs.corrugated_mask(nx, gap + 2 * base, None, amp=amp, wavelength=wavelength,
+                                   base=base, phases=(0.0, np.pi if meander else 0.0))
+    O = oracle.Lattice(9, oracle.MASKED, nx, gap + 2 * base, 1, tau=tau, force=(g, 0, 0),
+                       solid=solid)
+    O.set_friction(lam)
+    q_old = None
+    for _ in range(400):
+        O.step(500)
+        q = O.invariants()[0]
+        if q_old is not None and abs(q - q_old) < tol * abs(q):
+            return q
+        q_old = q
+    raise AssertionError("oracle did not reach steady state")
+
+
+def test_wrinkled_channel_flux_matches_oracle(mods):
+    # the wall-shape sweep of Sec. 5.1 (masked walls): one wrinkled slip
+    # channel and its flat reference, both to a 1e-10 steady state
+    lbm, perm = mods
+    print("wrinkle sweep parity", flush=True)
+    res = perm.wrinkle_sweep([2.0], [0.05], gap=24, nx=64, wavelength=32.0, meanders=(True,),
+                             precision="f64", rel_tol=1e-10)
+    r = res[0]
+    q_flat = oracle_wrinkled_flux(64, 24, 0.0, 32.0, True, 0.05)
+    q_wr = oracle_wrinkled_flux(64, 24, 2.0, 32.0, True, 0.05)
+    print(f"  flat {r.flux_flat / q_flat - 1:.2e}  wrinkled {r.flux / q_wr - 1:.2e}", flush=True)
+    assert abs(r.flux_flat / q_flat - 1) < 1e-8
+    assert abs(r.flux / q_wr - 1) < 1e-8
+
+
+def test_wrinkles_reduce_the_flux_more_with_slip(mods):
+    # deeper wrinkles carry less water; slip walls lose more to them than
+    # no-slip walls (each step of the staircase blocks part of the slip
+    # flow), in the meander and in the narrowing-and-widening gap
+    lbm, perm = mods
+    print("wrinkle sweep physics", flush=True)
+    res = perm.wrinkle_sweep([1.0, 2.0, 4.0], [float("inf"), 0.05], precision="f64")
+    rel = {(r.meander, r.lam, r.amplitude): r.relative for r in res}
+    for meander in (True, False):
+        for lam in (float("inf"), 0.05):
+            seq = [rel[(meander, lam, a)] for a in (1.0, 2.0, 4.0)]
+            print(f"  meander {meander} lambda {lam}: {seq}", flush=True)
+            assert 1.0 > seq[0] > seq[1] > seq[2] > 0.2
+        for a in (1.0, 2.0, 4.0):
+            assert rel[(meander, 0.05, a)] < rel[(meander, float("inf"), a)]
