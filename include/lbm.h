@@ -84,8 +84,9 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 } lbm_precision;
  *       SLAB's transverse reversal: an x-uniform mask is the SLAB exactly),
  *       then (-c_x, c_y, -c_z) about an x-normal step face, then -c_i, then
  *       the lowest-numbered free k.  Wall nodes are numbered as in every
- *       geometry (increasing x + nx (y + ny z)).  No moving wall, no
- *       electron sheets, no batches.
+ *       geometry (increasing x + nx (y + ny z)).  Thermal noise works as
+ *       everywhere; no moving wall, electron sheets, open ends or batches
+ *       (LBM_EINVAL).
  * x is periodic in every geometry (inlet/outlet option 1 of Sec. 4.2) unless
  * lbm_set_open_ends opens it (option 2). */
 typedef enum { LBM_SLAB = 0, LBM_DUCT = 1, LBM_TUBE = 2, LBM_MASKED = 3 } lbm_geometry;
