@@ -452,6 +452,8 @@ def main():
     ap.add_argument("--open-ends", action="store_true",
                     help="duct or slab: Neumann-like inlet and outlet (densities 1 +- 1e-5) "
                          "in place of periodic x")
+    ap.add_argument("--phonons", action="store_true",
+                    help="slab with --electrons: phonon lines beside the electron lines")
     ap.add_argument("--electrons", action="store_true",
                     help="with --workload slab: electron sheets on both walls")
     ap.add_argument("--workload", default="duct",
@@ -497,6 +499,8 @@ def main():
         ch.set_friction(0.05)
         if args.electrons:
             ch.set_electrons(0.9, 1.0, 0.05, 1e-6)
+            if args.phonons:
+                ch.set_phonons(0.7, 1.3, 0.02, 0.08)
     elif corr:
         ch = make_corrugated(lbm, inputs, args.precision)
     else:
@@ -561,6 +565,7 @@ def main():
         "config": {"workload": f"{args.workload}_256x128x64_d3q19_{args.precision}storage"
                                + ("", "_thermal_stress", "_thermal_all")[args.thermal]
                                + ("_electrons" if slab and args.electrons else "")
+                               + ("_phonons" if slab and args.electrons and args.phonons else "")
                                + ("_open_ends" if args.open_ends else ""),
                    "lattice": "D3Q19", "box": list(DUCT), "fluid_cells": cells, "tau": 0.7,
                    "g": 1e-6, "storage": args.precision, "arithmetic": arith,
@@ -569,7 +574,10 @@ def main():
                    "walls": ("wrinkled: staircase sinusoids, amplitude 4, wavelength 64"
                              if corr else "planar"),
                    "electrons": ("sheets on both walls: tau_e 0.9, rho_e0 1, gamma_e 0.05, "
-                                 "force_e 1e-6") if slab and args.electrons else None,
+                                 "force_e 1e-6"
+                                 + ("; phonon lines: tau_p 0.7, rho_p0 1.3, gamma_pc 0.02, "
+                                    "gamma_ep 0.08" if args.phonons else ""))
+                                if slab and args.electrons else None,
                    "check_every": args.check_every,
                    "thermal": [None, "stress source, kT 1e-6", "all directions, kT 1e-6"][args.thermal]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
