@@ -294,3 +294,21 @@ def test_phonon_settings(lbm):
     S.set_electrons(*ELEC)  # switches the phonons off
     with pytest.raises(lbm.LBMError):
         S.phonons()
+
+
+def test_phonons_with_half_storage_water(lbm):
+    # half-storage water (float arithmetic) with double electron and phonon
+    # lines: the lines follow the oracle within the water's half-storage error
+    say("phonons half storage")
+    G, O = build(lbm, "d2q9", "f16s")
+    for L in (G, O):
+        L.set_phonons(*PHON)
+    G.step(300)
+    O.step(300)
+    upg, _ = G.phonons()
+    upo, _ = O.phonons()
+    ueg, _ = G.electrons()
+    ueo, _ = O.electrons()
+    e = max(np.abs(upg - upo).max() / np.abs(upo).max(), np.abs(ueg - ueo).max() / np.abs(ueo).max())
+    say(f"  u_e, u_p {e:.2e}")
+    assert e < 2e-3
