@@ -197,3 +197,16 @@ def test_shortest_open_channels_fp64(lbm, nx, q, geom, ny, nz):
     O.step(150)
     eu, er = errs(G, O)
     assert eu < 1e-12 and er < 1e-14
+
+
+def test_open_ends_half_storage_tracks_the_oracle(lbm):
+    # half storage (float arithmetic): within its field error, as for the
+    # periodic channels
+    say("open ends f16s")
+    G, O = build(lbm, "duct", "f16s")
+    G.step(500)
+    O.step(500)
+    eu, _ = errs(G, O)
+    qg, qo = G.invariants()[0], O.invariants()[0]
+    say(f"  u {eu:.2e}  flux {abs(qg / qo - 1):.2e}")
+    assert eu < 1e-2 and abs(qg / qo - 1) < 1e-2
