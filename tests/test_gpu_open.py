@@ -210,3 +210,23 @@ def test_open_ends_half_storage_tracks_the_oracle(lbm):
     qg, qo = G.invariants()[0], O.invariants()[0]
     say(f"  u {eu:.2e}  flux {abs(qg / qo - 1):.2e}")
     assert eu < 1e-2 and abs(qg / qo - 1) < 1e-2
+
+
+def test_couette_with_open_ends_matches_periodic_fp64(lbm):
+    # a moving top wall with equal end densities: the x-uniform Couette flow
+    # is a fixed point of the open ends, so the open channel must reproduce
+    # the periodic one (itself pinned by the exact Couette profile)
+    say("open ends Couette")
+    nx, ny, U = 24, 12, 1e-3
+    kw = dict(tau=0.9, precision="f64", wall_velocity_top=U)
+    A = lbm.Channel(9, lbm.SLAB, nx, ny, 1, **kw)
+    B = lbm.Channel(9, lbm.SLAB, nx, ny, 1, **kw)
+    for L in (A, B):
+        L.set_friction(0.1)
+    B.set_open_ends(1.0, 1.0)
+    A.step(6000)
+    B.step(6000)
+    ua, ub = A.field(1), B.field(1)
+    err = np.abs(ua - ub).max() / np.abs(ua).max()
+    say(f"  {err:.2e}")
+    assert np.abs(ua).max() > 1e-4 and err < 1e-12
