@@ -209,3 +209,28 @@ def test_degenerate_and_long_masks_fp64(lbm, q, nx, ny, nz):
     eu, er = field_err(G, O)
     assert eu < 1e-12 and er < 1e-14
     assert abs(G.invariants()[2]) < 1e-13 * G.fluid_count
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_mirror_symmetric_wrinkles_give_a_symmetric_flow(lbm, precision):
+    # a mask and a friction field symmetric under y -> ny - 1 - y: the flow
+    # is mirror-symmetric (the slip pairing commutes with the mirror); FP32
+    # storage within its stochastic rounding
+    say("masked mirror", precision)
+    nx, ny, nz = 96, 21, 4
+    half = inputs.corrugated_mask(nx, ny, None, amp=2.0, wavelength=32.0, base=2,
+                                  phases=(0.3, 0.0))
+    half[ny // 2:] = False
+    solid = half | half[::-1]
+    G = lbm.Channel(19, lbm.MASKED, nx, ny, nz, tau=0.75, force=(2e-6, 0, 0),
+                    precision=precision, solid=solid)
+    xyz = G.wall_coords()
+    d = np.minimum(xyz[:, 1], ny - 1 - xyz[:, 1])
+    G.set_friction(0.05 + 0.03 * d + 0.01 * np.sin(xyz[:, 0]))
+    G.step(400)
+    _, ux, uy, _ = G.fields()
+    ref = np.abs(ux).max()
+    tol = 1e-12 if precision == "f64" else 2e-5
+    assert np.abs(ux - ux[:, ::-1, :]).max() < tol * ref
+    assert np.abs(uy + uy[:, ::-1, :]).max() < tol * ref
+    assert np.abs(uy).max() > 1e-3 * ref
