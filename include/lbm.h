@@ -196,8 +196,9 @@ lbm_status lbm_get_friction(lbm_ctx *ctx, double *lambda, double *raw);
  * tau = 0.7).  kT is in lattice units (0 switches the noise off; the mode is
  * then ignored).  Random numbers: Philox4x64-10 (Salmon et al., SC'11) under
  * key (seed, 0) with counter (x + nx (y + ny z), step, block, 0), each 64-bit
- * word giving two Box-Muller normals from 23-bit uniforms (|z| <= 5.77), so a
- * run is reproducible bit for bit and a restart from lbm_set_state continues
+ * word giving two Box-Muller normals from 23-bit uniforms (|z| <= 5.77),
+ * transformed in binary64 with F64 storage and in binary32 (hardware log2,
+ * sin, cos) with F32 and F16S storage, so a run is reproducible bit for bit and a restart from lbm_set_state continues
  * the same sequence.  Mass is conserved exactly; momentum too where the walls
  * conserve it.  kT < 0, NaN, Inf or an unknown mode -> LBM_EINVAL.
  * Synchronous (finishes queued work). */

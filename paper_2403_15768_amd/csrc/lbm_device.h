@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbm {
 
 // ------------------------------------------------------------------ lattices
@@ -672,9 +674,10 @@ __device__ __forceinline__ Philox4 philox4x64_10(uint64_t c0, uint64_t c1, uint6
 // Two standard normals from one 64-bit word (Box-Muller): the top 23 bits of
 // each 32-bit half give u = (k + 1/2) 2^-23, exact in binary32 and never 0
 // or 1; z = sqrt(-2 ln u_lo) (cos, sin)(2 pi u_hi).  |z| <= sqrt(48 ln 2).
-// Over all 2^23 such u the hardware log2 gives the radius within 5.3e-7 and
-// the hardware sin / cos (argument in revolutions) are within 1.3e-7 of
-// binary64 (measured), so |dz| < 1.3e-6.
+// Binary32 form (float and half storage): over all 2^23 such u the hardware
+// log2 gives the radius within 5.3e-7 and the hardware sin / cos (argument
+// in revolutions) are within 1.3e-7 of binary64 (measured), so
+// |dz| < 1.3e-6.
 __device__ __forceinline__ void normal_pair(uint64_t word, float* z0, float* z1) {
   const float ul = (static_cast<float>(static_cast<uint32_t>(word) >> 9) + 0.5f) * 0x1p-23f;
   const float uh = (static_cast<float>(static_cast<uint32_t>(word >> 32) >> 9) + 0.5f) * 0x1p-23f;
@@ -683,6 +686,23 @@ __device__ __forceinline__ void normal_pair(uint64_t word, float* z0, float* z1)
   *z0 = rad * __builtin_amdgcn_cosf(uh);
   *z1 = rad * __builtin_amdgcn_sinf(uh);
 }
+// Binary64 form (double storage, the reference precision): the same
+// uniforms, the transform in double with the device library's log, sqrt and
+// sincos (each within an ulp or two), so a normal agrees with a binary64
+// evaluation of the same formula to a few units in the last place.
+__device__ __forceinline__ void normal_pair(uint64_t word, double* z0, double* z1) {
+  const double ul = (static_cast<double>(static_cast<uint32_t>(word) >> 9) + 0.5) * 0x1p-23;
+  const double uh = (static_cast<double>(static_cast<uint32_t>(word >> 32) >> 9) + 0.5) * 0x1p-23;
+  const double rad = sqrt(-2.0 * log(ul));
+  double sn, cs;
+  sincos(6.28318530717958647692 * uh, &sn, &cs);
+  *z0 = rad * cs;
+  *z1 = rad * sn;
+}
+
+// the type the thermal normals of a storage type are drawn in
+template <typename S>
+using NormalT = typename std::conditional<sizeof(S) == 8, double, float>::type;
 
 // sqrt(w_i) from the weight class (|c|^2 and the lattice)
 template <class L, typename M>
@@ -701,14 +721,16 @@ __device__ __forceinline__ constexpr M sqrt_w(int i) {
 //    i.e. xi_i = w_i [1.5 sqrt(2) A sum_a z_aa (c_ia^2 - 1/3) + 3 A sum_a<b z_ab c_ia c_ib];
 //  th_mode 2: v_i = sqrt(w_i) z_i for every i, mass and momentum removed:
 //    xi_i = A (v_i - w_i sum v - 3 w_i c_i . sum v c).
-template <class L, typename M, int MODE>
+// Z is the type the normals are drawn in: double for double storage,
+// float (the hardware transcendentals) for float and half storage.
+template <class L, typename M, int MODE, typename Z = float>
 __device__ __forceinline__ void thermal_noise(const StepArgs& a, uint32_t cell, int64_t step,
                                               M* xi) {
   static_assert(MODE == 1 || MODE == 2, "noise form");
   const M A = static_cast<M>(a.th_amp);
   const uint64_t key = a.th_seed;
   if constexpr (MODE == 1) {
-    float z[6] = {0, 0, 0, 0, 0, 0};
+    Z z[6] = {0, 0, 0, 0, 0, 0};
     const Philox4 r = philox4x64_10(cell, (uint64_t)step, 0, key, 0);
     normal_pair(r.w[0], &z[0], &z[1]);
     normal_pair(r.w[1], &z[2], &z[3]);
@@ -733,7 +755,7 @@ __device__ __forceinline__ void thermal_noise(const StepArgs& a, uint32_t cell, 
     }
     return;
   } else {
-    float z[L::Q];
+    Z z[L::Q];
     constexpr int kBlocks = (L::Q + 7) / 8;
 #pragma unroll
     for (int b = 0; b < kBlocks; b++) {
@@ -742,7 +764,7 @@ __device__ __forceinline__ void thermal_noise(const StepArgs& a, uint32_t cell, 
       for (int w = 0; w < 4; w++) {
         const int k = 8 * b + 2 * w;
         if (k >= L::Q) break;
-        float z0, z1;
+        Z z0, z1;
         normal_pair(r.w[w], &z0, &z1);
         z[k] = z0;
         if (k + 1 < L::Q) z[k + 1] = z1;

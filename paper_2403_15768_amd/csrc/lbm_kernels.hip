@@ -58,7 +58,7 @@ __device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restr
   // it holds fewer registers than while the gathered values are live
   M xi[L::Q];
   if constexpr (TH != 0)
-    thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+    thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
   gather<L, S, M, M, BOUZ, ELEC, OPEN>(src, a, col, xc, info, df);
   if constexpr (OPEN) open_correct<L, M>(a, col, xc, info.mask, df);
   M rec[4];
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
   M df[L::Q];
   M xi[L::Q];
   if constexpr (TH != 0)
-    thermal_noise<L, M, TH>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+    thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
   if (wallcol)
     gather_masked<L, S, M, M>(src, a, col, z, xc, cw, df);
   else
@@ -660,7 +660,7 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   // seed), drawn before the gather as in k_step
   M xi[L::Q];
   if constexpr (TH != 0)
-    thermal_noise<L, M, TH>(a, (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
+    thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
                             xi);
   gather<L, S, M, M, BOUZ>(src, a, colA, xc, info, df, c.dl);
   collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)colA * a.sC, c.dl + (unsigned)c.x,

@@ -4,8 +4,9 @@ oracle, through the C ABI.
 Tolerances: FP64 water fields and electron state within 1e-12 relative of the
 oracle (same arithmetic, summation order aside); FP32 water storage within
 1e-5 of the largest axial velocity (its stochastic rounding, as for the plain
-channel); half storage within 2e-3 (its field error, ~4e-4); with thermal
-noise 3e-4 (the noise's binary32 Box-Muller, as in the thermal tests).  Exact properties at full size: the one-step axial momentum
+channel); half storage within about 3x its measured error; with thermal
+noise and double storage 1e-12 (both sides draw the normals in binary64).
+Exact properties at full size: the one-step axial momentum
 bookkeeping of water plus electrons.  Closed form: the coupled steady state.
 """
 import numpy as np
@@ -169,9 +170,9 @@ def test_electrons_with_thermal_noise_fp64(lbm):
     ueg, _ = G.electrons()
     ueo, _ = O.electrons()
     say(f"  water {err:.2e}  u_e {np.abs(ueg - ueo).max() / np.abs(ueo).max():.2e}")
-    # the thermal term's binary32 Box-Muller (see the thermal parity tests)
-    assert err < 3e-4
-    assert np.abs(ueg - ueo).max() < 3e-4 * np.abs(ueo).max()
+    # binary64 normals on both sides (see the thermal parity tests)
+    assert err < 1e-12
+    assert np.abs(ueg - ueo).max() < 1e-12 * np.abs(ueo).max()
 
 
 def test_half_storage_electrons_track_the_oracle(lbm):
@@ -186,7 +187,7 @@ def test_half_storage_electrons_track_the_oracle(lbm):
     ueo, _ = O.electrons()
     e = np.abs(ueg - ueo).max() / np.abs(ueo).max()
     say(f"  u_e {e:.2e}")
-    assert e < 2e-3
+    assert e < 1.6e-3  # measured 5.4e-4
 
 
 PHON = (0.7, 1.3, 0.02, 0.08)  # tau_p, rho_p0, gamma_pc, gamma_ep
@@ -311,4 +312,4 @@ def test_phonons_with_half_storage_water(lbm):
     ueo, _ = O.electrons()
     e = max(np.abs(upg - upo).max() / np.abs(upo).max(), np.abs(ueg - ueo).max() / np.abs(ueo).max())
     say(f"  u_e, u_p {e:.2e}")
-    assert e < 2e-3
+    assert e < 1.8e-3  # measured 5.8e-4

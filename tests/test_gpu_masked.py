@@ -3,8 +3,9 @@ or stepped walls, posts) against the oracle, through the C ABI.
 
 Tolerances as for the other geometries: FP64 within 1e-12 relative of the
 oracle, FP32 storage within 1e-5 of the largest axial velocity (stochastic
-rounding), half storage within 1e-2 (its field error), thermal noise within
-3e-4 (the binary32 Box-Muller of the GPU path).  Exact properties: wall
+rounding), half storage within about 3x its measured field and flux error,
+thermal noise with double storage within 1e-12 (both sides draw the normals
+in binary64).  Exact properties: wall
 classification and link tables bit for bit, mass to rounding at full size, an
 empty mask is the slab bit for bit, graph replays equal plain launches bit for
 bit.
@@ -101,7 +102,8 @@ def test_half_storage_tracks_the_oracle(lbm):
     eu, _ = field_err(G, O)
     qg, qo = G.invariants()[0], O.invariants()[0]
     say(f"  u {eu:.2e}  flux {abs(qg / qo - 1):.2e}")
-    assert eu < 1e-2 and abs(qg / qo - 1) < 1e-2
+    # measured 3.8e-4 (field) and 1.28e-5 (flux) after 500 steps
+    assert eu < 1.2e-3 and abs(qg / qo - 1) < 4e-5
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -142,7 +144,7 @@ def test_thermal_noise_on_masked_walls(lbm, mode):
     O.step(101)
     eu, _ = field_err(G, O)
     say(f"  u {eu:.2e}")
-    assert eu < 3e-4
+    assert eu < 1e-12
     # mass stays exact with the noise too
     assert abs(G.invariants()[2]) < 1e-12 * G.fluid_count
 

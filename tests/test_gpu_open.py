@@ -3,7 +3,8 @@ oracle, through the C ABI.
 
 Tolerances as for the periodic channels: FP64 within 1e-12 relative of the
 oracle, FP32 storage within 1e-5 of the largest axial velocity, thermal noise
-within 3e-4 (binary32 Box-Muller).  Closed form: the pressure-driven
+with double storage within 1e-12 (binary64 normals on both sides), half
+storage within about 3x its measured error.  Closed form: the pressure-driven
 Poiseuille profile of the equivalent body force.  Exact: graph replays equal
 plain launches bit for bit.
 """
@@ -96,7 +97,7 @@ def test_open_ends_with_thermal_noise(lbm):
     O.step(101)
     eu, _ = errs(G, O)
     say(f"  u {eu:.2e}")
-    assert eu < 3e-4
+    assert eu < 1e-12  # binary64 normals with double storage
 
 
 def test_pressure_driven_poiseuille_closed_form(lbm):
@@ -201,7 +202,8 @@ def test_shortest_open_channels_fp64(lbm, nx, q, geom, ny, nz):
 
 def test_open_ends_half_storage_tracks_the_oracle(lbm):
     # half storage (float arithmetic): within its field error, as for the
-    # periodic channels
+    # periodic channels; measured 4.0e-4 (field) and 1.05e-5 (flux), held to
+    # about 3x that
     say("open ends f16s")
     G, O = build(lbm, "duct", "f16s")
     G.step(500)
@@ -209,7 +211,7 @@ def test_open_ends_half_storage_tracks_the_oracle(lbm):
     eu, _ = errs(G, O)
     qg, qo = G.invariants()[0], O.invariants()[0]
     say(f"  u {eu:.2e}  flux {abs(qg / qo - 1):.2e}")
-    assert eu < 1e-2 and abs(qg / qo - 1) < 1e-2
+    assert eu < 1.2e-3 and abs(qg / qo - 1) < 3.2e-5
 
 
 def test_couette_with_open_ends_matches_periodic_fp64(lbm):

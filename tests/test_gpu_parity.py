@@ -437,7 +437,8 @@ def test_fp32_storage_at_steady_state_closed_form(lbm):
 
 def test_f16s_storage_error_bounded(lbm):
     # half-precision deviations: the error against the FP64 oracle is
-    # reported; bounded here at 1e-2 of the axial velocity
+    # reported; measured 3.6e-4 of the axial velocity and 3.4e-6 of the flux
+    # after 1000 steps, held to about 3x that
     say("f16s replica")
     nx, ny, nz = 48, 24, 12
     G, O = pair(lbm, 19, lbm.DUCT, nx, ny, nz, 0.7, 1e-6, "f16s")
@@ -449,7 +450,7 @@ def test_f16s_storage_error_bounded(lbm):
     eu, _ = vel_err(G, O)
     qg, qo = G.invariants()[0], O.invariants()[0]
     say("  f16s u err", eu, "flux err", abs(qg / qo - 1))
-    assert eu < 1e-2 and abs(qg / qo - 1) < 1e-2
+    assert eu < 1.1e-3 and abs(qg / qo - 1) < 1e-5
 
 
 @pytest.mark.parametrize("nx", [40, 72])  # 72: the half and float x-lines are padded differently

@@ -1,27 +1,26 @@
 """GPU parity of the fluctuating update (thermal noise) against the oracle.
 
-Both sides draw the same Philox4x64-10 numbers; the GPU evaluates the
-Box-Muller transform in binary32 (the hardware log2 and sin / cos, sqrtf),
-the oracle in binary64.  Over every uniform the generator can produce the
-GPU's radius sqrt(-2 ln u) is within 5.3e-7 and its cos / sin within 1.3e-7
-of binary64 (measured on the GPU over all 2^23 values), so a normal
-|z| <= 5.77 differs by at most 5.77 * 1.3e-7 + 5.3e-7 < 2.1e-6, and a thermal term
-xi_i = A * (combination of normals with coefficients summing to <= 4 in
-absolute value) by at most 1e-5 A.  Tolerances below follow from that:
-one step compares populations to 1e-5 A.  Over a run of n steps: the
-linearised update is non-expansive in the w-weighted 2-norm (streaming
-permutes, the collision contracts), so the injected errors add at most
-linearly; they come from independent draws and carry no mass or momentum,
-so they add as a random walk, sqrt(n) * 1e-5 A = 1e-4 A per population at
-n = 101, and at most 18 moving directions make a velocity error below
-2e-3 A.  The fields then are about A in size: the multi-step test uses
-3e-4 relative, between that bound with the collision's damping of the
-non-conserved directions (|1 - 1/tau| = 0.25 per step at tau = 0.8) and the
-measured 8e-8.  FP32 storage adds its stochastic rounding (2^-24 relative
-per population and step, a random walk: below 1e-5 relative over 101
-steps).  One step measured 1.3e-7 A.  Counter-based numbers make every run
-reproducible: graph and plain launches, restarts and repeated runs agree bit
-for bit.
+Both sides draw the same Philox4x64-10 numbers.  With double storage (the
+reference precision) the GPU evaluates the Box-Muller transform in binary64
+(the device library's log, sqrt and sincos), as the oracle does with the C
+library's: a normal then differs by a few units in the last place, a
+thermal term by < 1e-15 A, and the FP64 bars are the FP64 bar of the whole
+path, 1e-12 (one step, relative to the amplitude A; fields relative to their
+largest component).
+
+With float and half storage the GPU evaluates Box-Muller in binary32 (the
+hardware log2 and sin / cos, sqrtf).  Over every uniform the generator can
+produce the GPU's radius sqrt(-2 ln u) is within 5.3e-7 and its cos / sin
+within 1.3e-7 of binary64 (measured on the GPU over all 2^23 values), so a
+normal |z| <= 5.77 differs by at most 5.77 * 1.3e-7 + 5.3e-7 < 2.1e-6, and a
+thermal term xi_i = A * (combination of normals with coefficients summing
+to <= 4 in absolute value) by at most 1e-5 A.  Over a run of n steps the
+linearised update is non-expansive in the w-weighted 2-norm, so the
+injected errors add at most as a random walk: a worst case of 3e-4 of the
+fields at n = 101.  The FP32 bar of the path (1e-5 on velocity fields) is
+what the float-storage runs are held to; the seeded runs here measure
+about 1e-7.  Counter-based numbers make every run reproducible: graph and
+plain launches, restarts and repeated runs agree bit for bit.
 """
 import numpy as np
 import pytest
@@ -116,7 +115,7 @@ def test_one_step_noise_parity_fp64(lbm, case, mode):
     fluid = O.fields()[0] != 0
     d = np.abs(pg - po)[:, fluid]
     say("  max |dg| / A", d.max() / A)
-    assert d.max() < 1e-5 * A
+    assert d.max() < 1e-12 * A
     # the noise is really there: the step moves populations by about A
     assert np.abs(pg - g0).max() > 0.5 * A
 
@@ -137,7 +136,7 @@ def test_fields_parity_over_graph_and_plain_steps(lbm, case, mode, precision):
     ref = max(np.abs(ro[k]).max() for k in (1, 2, 3))
     err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / ref
     rerr = np.abs(rg[0] - ro[0]).max()
-    tol = 3e-4 if precision == "f64" else 3.1e-4
+    tol = 1e-12 if precision == "f64" else 1e-5
     say(f"  rel u err {err:.3e} (tol {tol:.1e}), rho err {rerr:.3e}")
     assert err < tol
     assert rerr < tol * 3 * np.sqrt(kT)
@@ -330,8 +329,8 @@ def test_noise_closure_one_step_parity_fp64(lbm, case):
     fluid = O.fields()[0] != 0
     d = np.abs(pg - po)[:, fluid]
     say("  max |dg| / A", d.max() / A)
-    # the factors sqrt(m) reach 3.6 here: the classical bound 1e-5 A scaled
-    assert d.max() < 3.6e-5 * A
+    # the factors sqrt(m) reach 3.6 here
+    assert d.max() < 1e-12 * A
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -347,7 +346,7 @@ def test_noise_closure_fields_and_unit_closure(lbm, precision):
     rg, ro = G.fields(), O.fields()
     err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / np.abs(ro[1]).max()
     say(f"  fields {err:.2e}")
-    assert err < 3e-4
+    assert err < (1e-12 if precision == "f64" else 1e-5)
     # a unit correlator with weights summing to one is the classical noise
     A, _ = build(lbm, "slab", precision)
     B, _ = build(lbm, "slab", precision)
