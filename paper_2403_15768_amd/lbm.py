@@ -228,10 +228,13 @@ class Channel:
         self.shape = (nz, ny, nx)
 
     def close(self) -> None:
+        """Destroy the context and release its device arena (to torch's
+        caching allocator)."""
         h = getattr(self, "_h", None)
         if h:
             self._lib.lbm_destroy(h)
             self._h = None
+        self.arena = None
 
     def __del__(self):
         self.close()
@@ -472,10 +475,13 @@ class Batch:
             self.tune()
 
     def close(self) -> None:
+        """Destroy the batch (members untouched) and release its arena."""
         h = getattr(self, "_h", None)
         if h:
             self._lib.lbm_batch_destroy(h)
             self._h = None
+        self.arena = None
+        self.channels = []
 
     def __del__(self):
         self.close()

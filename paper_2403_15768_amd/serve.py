@@ -50,6 +50,8 @@ class Result:
     steps_half: int
     flux: float
     status: str  # "ok", "not_converged", "diverged"
+    # the final u_x field [z][y][x], kept only when the server is asked to
+    ux: np.ndarray | None = field(default=None, repr=False, compare=False)
 
     @property
     def latency_s(self) -> float:
@@ -123,7 +125,8 @@ def open_channel(q, precision: str, kind=TubeQueries) -> lbm.Channel:
 class Server:
     def __init__(self, mode: str = "f32", hbm_budget: int = 32 << 30, check_every: int = 1000,
                  rel_tol: float = 1e-8, switch_tol: float = 1e-5, max_steps: int = 500_000,
-                 tune: bool = True, realtime: bool = True, log=None, kind=TubeQueries):
+                 tune: bool = True, realtime: bool = True, log=None, kind=TubeQueries,
+                 keep_fields: bool = False):
         assert mode in ("f32", "mixed")
         self.kind = kind
         self.mode = mode
@@ -135,6 +138,7 @@ class Server:
         self.tune = tune
         self.realtime = realtime
         self.log = log
+        self.keep_fields = keep_fields
         self.shape = None  # workgroup shape chosen by the autotuner
         self._serial = 0
         self.stats = {"batch_rebuilds": 0, "chunks": 0, "max_active": 0, "lattice_updates": 0}
@@ -265,7 +269,8 @@ class Server:
                                       arrival_s=getattr(s.query, "arrival_s", 0.0),
                                       admitted_s=s.admitted_s,
                                       done_s=t_done, steps=steps,
-                                      steps_half=s.steps_half, flux=q, status=status))
+                                      steps_half=s.steps_half, flux=q, status=status,
+                                      ux=s.ch.field(1) if self.keep_fields else None))
                 s.ch.close()
                 self._say(f"done q{s.query.qid} steps={steps} "
                           f"half={s.steps_half} t={t_done:.2f}s active={len(active)}")
@@ -318,7 +323,9 @@ def main(argv=None):
     print(json.dumps(summ), flush=True)
     if args.out:
         with open(args.out, "w") as f:
-            json.dump({"summary": summ, "results": [asdict(r) for r in res]}, f)
+            json.dump({"summary": summ,
+                       "results": [{k: v for k, v in asdict(r).items() if k != "ux"} for r in res]},
+                      f)
 
 
 if __name__ == "__main__":

@@ -65,26 +65,76 @@ def test_batch_bit_identical_to_alone(lbm, precision):
     b.close()
 
 
-def test_batch_tubes_f16s_bit_identical(lbm):
-    say("batch tubes f16s")
+TUBES = ((6, 40, 0), (9, 70, 1), (4, 64, 2))  # radius, nx, seed
+
+
+def tube_spectral(seed):
+    return inputs.draw_spectral(inputs.rng_for("serving", 10 + seed), nq=16, nw=64)
+
+
+def tube_omega(coords, nx, R, cy, cz, sp, seed):
+    return inputs.tube_plasmon_frequencies(coords, nx, R, cy, cz, sp.omega0,
+                                           inputs.rng_for("serving", 20 + seed), sigma=4.0)
+
+
+@pytest.mark.parametrize("precision", ["f16s", "f32", "f64"])
+def test_batch_tubes_bit_identical(lbm, precision):
+    # tubes (interpolated bounce-back) in a batch: the batch kernel's BOUZ
+    # path against the channel kernel, bit for bit, in every storage
+    say("batch tubes", precision)
     chans = []
-    for R, nx, seed in ((6, 40, 0), (9, 70, 1), (4, 64, 2)):
+    for R, nx, seed in TUBES:
         ny, nz, cy, cz = inputs.tube_box(R)
         pair = []
         for _ in range(2):
-            ch = lbm.Channel(19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), precision="f16s",
-                             tube_radius=float(R), tube_cy=cy, tube_cz=cz)
-            sp = inputs.draw_spectral(inputs.rng_for("serving", 10 + seed), nq=16, nw=64)
-            om = inputs.tube_plasmon_frequencies(ch.wall_coords(), nx, R, cy, cz, sp.omega0,
-                                                 inputs.rng_for("serving", 20 + seed), sigma=4.0)
-            ch.set_friction_spectral(sp, om)
+            ch = lbm.Channel(19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0),
+                             precision=precision, tube_radius=float(R), tube_cy=cy, tube_cz=cz)
+            sp = tube_spectral(seed)
+            ch.set_friction_spectral(sp, tube_omega(ch.wall_coords(), nx, R, cy, cz, sp, seed))
             pair.append(ch)
         chans.append(pair)
+    for p in chans:  # join the batch at an odd step
+        p[0].step(3)
+        p[1].step(3)
     b = lbm.Batch([p[1] for p in chans])
     b.step(100)
     for p in chans:
         p[0].step(100)
+        assert p[0].step_count == p[1].step_count == 103
         assert np.array_equal(p[0].get_state()[0], p[1].get_state()[0])
+    b.close()
+
+
+def test_batch_tubes_fp64_against_oracle(lbm):
+    # the batched tubes against the oracle, friction from the oracle's own
+    # quadrature of the same spectra
+    say("batch tubes fp64 vs oracle")
+    chans, oras = [], []
+    for R, nx, seed in TUBES:
+        ny, nz, cy, cz = inputs.tube_box(R)
+        kw = dict(tube_radius=float(R), tube_cy=cy, tube_cz=cz)
+        ch = lbm.Channel(19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), precision="f64",
+                         **kw)
+        sp = tube_spectral(seed)
+        om = tube_omega(ch.wall_coords(), nx, R, cy, cz, sp, seed)
+        ch.set_friction_spectral(sp, om)
+        o = oracle.Lattice(19, oracle.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), **kw)
+        _, lam = oracle.friction(oracle.Spectral(T=sp.T, omega0=sp.omega0, gamma_s=sp.gamma_s,
+                                                 omega_l=sp.omega_l, gamma_l=sp.gamma_l,
+                                                 a_l=sp.a_l, d=sp.d, nq=sp.nq, nw=sp.nw,
+                                                 lambda_target=sp.lambda_target), om)
+        o.set_friction(lam)
+        chans.append(ch)
+        oras.append(o)
+    b = lbm.Batch(chans)
+    b.step(300)
+    for ch, o in zip(chans, oras):
+        o.step(300)
+        ug, uo = ch.field(1), o.fields()[1]
+        err = np.max(np.abs(ug - uo)) / np.max(np.abs(uo))
+        say("  err", err)
+        assert err < 1e-12
+    b.close()
 
 
 def test_batch_fp64_against_oracle(lbm):

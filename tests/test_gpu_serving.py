@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import oracle
 from paper_2403_15768_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -67,3 +68,48 @@ def test_realtime_trace_latencies(serve):
     res = srv.run(trace)
     s = serve.summarize(res, 0.0)
     assert s["converged"] == 4 and s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def oracle_tube(q):
+    """The oracle's tube for a served query: same geometry, the friction from
+    the oracle's own quadrature of the query's spectra at the same per-node
+    plasmon frequencies."""
+    from paper_2403_15768_amd import serve
+
+    kw = serve.tube_params(q)
+    o = oracle.Lattice(19, oracle.TUBE, kw["nx"], kw["ny"], kw["nz"], tau=q.tau,
+                       force=(q.g, 0, 0), tube_radius=kw["tube_radius"],
+                       tube_cy=kw["tube_cy"], tube_cz=kw["tube_cz"])
+    om = inputs.tube_plasmon_frequencies(o.wall_coords(), kw["nx"], q.radius, kw["tube_cy"],
+                                         kw["tube_cz"], q.spectral.omega0,
+                                         inputs.rng_for("serving", 1000 + q.qid))
+    sp = q.spectral
+    _, lam = oracle.friction(oracle.Spectral(T=sp.T, omega0=sp.omega0, gamma_s=sp.gamma_s,
+                                             omega_l=sp.omega_l, gamma_l=sp.gamma_l, a_l=sp.a_l,
+                                             d=sp.d, nq=sp.nq, nw=sp.nw,
+                                             lambda_target=sp.lambda_target), om)
+    o.set_friction(lam)
+    return o
+
+
+@pytest.mark.parametrize("mode", ["f32", "mixed"])
+def test_served_result_matches_the_oracle(serve, mode):
+    # a served query (in a mix of four, FP32 storage or half storage handed
+    # to FP32) against the oracle stepped the query's own number of steps:
+    # flux and axial velocity field within the FP32 bar, 1e-5
+    trace = inputs.serving_trace(4, rate_per_s=200.0, nx=32, radius_range=(3, 4))
+    srv = serve.Server(mode=mode, hbm_budget=8 << 30, check_every=500, realtime=False,
+                       tune=False, keep_fields=True)
+    res = {r.qid: r for r in srv.run(trace)}
+    q = trace[1]
+    r = res[q.qid]
+    assert r.status == "ok" and (r.steps_half > 0) == (mode == "mixed")
+    o = oracle_tube(q)
+    o.step(r.steps)
+    qo = o.invariants()[0]
+    uo = o.fields()[1]
+    ferr = abs(r.flux / qo - 1)
+    uerr = np.max(np.abs(r.ux - uo)) / np.max(np.abs(uo))
+    print(f"served q{q.qid} R={q.radius} steps={r.steps} half={r.steps_half}: "
+          f"flux err {ferr:.2e}, u err {uerr:.2e}", flush=True)
+    assert ferr < 1e-5 and uerr < 1e-5
