@@ -9,8 +9,13 @@ kernel and the CPU oracle timed on the same workload.
 
 A "step" is one lattice time step of the whole duct; every ``--check-every``
 steps the flux and mass are reduced in FP64 and brought to the host, as the
-run-to-steady loop does.  Per-query set-up (geometry, friction field -> wall
-weights, rest state) happens before the timed region.
+run-to-steady loop does (the last step of each chunk sums them as it goes).
+Per-query set-up (geometry, friction field -> wall weights, rest state)
+happens before the timed region.
+
+The same line carries the rest of the metric: the 256-duct batch run to
+steady (solves/s, p50 / p99 time-to-steady) and short serving traces of
+nanotube queries, each in FP32 storage and in mixed precision.
 
 Prints ONE JSON line.
 """
@@ -75,9 +80,11 @@ def make_corrugated(lbm, inputs, precision):
 
 
 def timed_run(torch, ch, steps, check_every):
-    """Run `steps` steps with an FP64 flux/mass check every `check_every`.
-    Returns wall seconds and the summed HIP-event time of the step chunks
-    (events on the stream the kernels run on)."""
+    """Run `steps` steps with an FP64 flux/mass check every `check_every`
+    (the last step of each chunk also sums the flux and mass of the state it
+    reads; the reduction then finishes and the host reads it, as the
+    run-to-steady loop does).  Returns wall seconds and the summed HIP-event
+    time of the step chunks (events on the stream the kernels run on)."""
     stream = ch.stream
     ev = []
     torch.cuda.synchronize()
@@ -88,10 +95,10 @@ def timed_run(torch, ch, steps, check_every):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        ch.step(k)
+        ch.step_checked(k)
         b.record(stream)
         ev.append((a, b, k))
-        ch.invariants()  # synchronising FP64 reduction + host check
+        ch.checked_invariants()  # finishes the FP64 reduction, host check
         done += k
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -121,9 +128,14 @@ def copy_ceiling(torch, lbm, nbytes, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(steps):
-    import numpy as np
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
+
+def cpu_baseline(steps):
     import oracle
     from paper_2403_15768_amd import inputs
 
@@ -134,9 +146,9 @@ def cpu_baseline(steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     return {"value": round(o.fluid_count * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
+            "host_cores": host_cores(), "kind": "oracle",
             "sample": f"{steps} steps of the 256x128x64 duct (D3Q19, FP64, single-threaded "
-                      f"scalar C), {dt:.1f} s"}
+                      f"scalar C: one of the host's {host_cores()} cores), {dt:.1f} s"}
 
 
 def extras(torch, lbm, inputs, args):
@@ -289,19 +301,16 @@ def extras(torch, lbm, inputs, args):
     return out
 
 
-def batch_workload(args):
+def batch_throughput(args, specs):
     """256 uneven ducts in one batch: throughput and per-channel error after
-    1000 steps for FP64 / FP32 / half storage, then run-to-steady solves/s for
-    FP32 storage against mixed precision (half storage handed to FP32)."""
+    1000 steps for FP64 / FP32 / half storage."""
     import numpy as np
     import torch
 
-    from paper_2403_15768_amd import inputs, lbm, serve
+    from paper_2403_15768_amd import lbm, serve
 
-    specs = inputs.batch_channels(256)
     cells = sum(c.nx * c.ny * c.nz for c in specs)
-    out = {"workload": "batch_256_ducts" + ("", "_thermal_stress", "_thermal_all")[args.thermal],
-           "channels": len(specs), "cells": cells}
+    out = {}
     fields, fluxes = {}, {}
     precs = args.batch_precisions.split(",")
     for prec in precs:
@@ -335,20 +344,24 @@ def batch_workload(args):
         del chs
         torch.cuda.empty_cache()
     for prec in [p for p in ("f32", "f16s") if p in precs and "f64" in precs]:
-        fe = [float(np.max(np.abs(a - r)) / np.max(np.abs(r))) for a, r in zip(fields[prec], fields["f64"])]
+        fe = [float(np.max(np.abs(a - r)) / np.max(np.abs(r)))
+              for a, r in zip(fields[prec], fields["f64"])]
         qe = np.abs(fluxes[prec] / fluxes["f64"] - 1)
         out[prec].update(field_err_max=float(np.max(fe)), field_err_median=float(np.median(fe)),
                          flux_err_max=float(np.max(qe)), flux_err_median=float(np.median(qe)))
-    if not args.no_steady:
-        steady_comparison(specs, out)
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def steady_comparison(specs, out):
-    """Run to steady: FP32 storage vs mixed precision, same tolerance."""
+def batch_steady(specs, modes=("f32", "mixed")):
+    """Run every channel of the batch to steady (flux change < 1e-8 per
+    check), FP32 storage against mixed precision at the same tolerance:
+    solves/s, p50 / p99 time-to-steady and the spread of the final fluxes.
+    The mixed-precision solve ends in FP32 storage, so both modes meet the
+    same accuracy; the 'FP32' path stores float and computes in double."""
     from paper_2403_15768_amd import serve
 
-    for mode in ("f32", "mixed"):
+    out, flux = {}, {}
+    for mode in modes:
         log("batch: run to steady", mode)
         srv = serve.Server(mode=mode, hbm_budget=64 << 30, realtime=False, kind=serve.DuctQueries)
         t0 = time.perf_counter()
@@ -357,28 +370,42 @@ def steady_comparison(specs, out):
         sm = serve.summarize(res, wall)
         sm["lattice_updates"] = srv.stats["lattice_updates"]
         sm["glups"] = round(srv.stats["lattice_updates"] / wall / 1e9, 2)
-        out["steady_" + mode] = sm
-        out["steady_" + mode + "_flux"] = {r.qid: r.flux for r in res}
-    fa, fb = out.pop("steady_f32_flux"), out.pop("steady_mixed_flux")
-    d = [abs(fb[k] / fa[k] - 1) for k in fa]
-    out["steady_mixed_vs_f32_flux_diff_max"] = float(max(d))
-    out["speedup_mixed_over_f32"] = round(out["steady_f32"]["makespan_s"] /
-                                          out["steady_mixed"]["makespan_s"], 3)
+        sm["batch_rebuilds"] = srv.stats["batch_rebuilds"]
+        out[mode] = sm
+        flux[mode] = {r.qid: r.flux for r in res}
+    if "f32" in flux and "mixed" in flux:
+        fa, fb = flux["f32"], flux["mixed"]
+        out["mixed_vs_f32_flux_diff_max"] = float(max(abs(fb[k] / fa[k] - 1) for k in fa))
+        out["speedup_mixed_over_f32"] = round(out["f32"]["makespan_s"] /
+                                              out["mixed"]["makespan_s"], 3)
+    return out
 
 
-def serving_workload(args):
-    """Poisson-arriving nanotube queries (radius 8..32), continuous batching,
-    FP32 storage against mixed precision on the same trace."""
+def batch_workload(args):
+    """The batch line of its own: throughput and errors after 1000 steps,
+    then run-to-steady solves/s."""
+    from paper_2403_15768_amd import inputs
+
+    specs = inputs.batch_channels(256)
+    out = {"workload": "batch_256_ducts" + ("", "_thermal_stress", "_thermal_all")[args.thermal],
+           "channels": len(specs), "cells": sum(c.nx * c.ny * c.nz for c in specs)}
+    out.update(batch_throughput(args, specs))
+    if not args.no_steady:
+        out["steady"] = batch_steady(specs)
+    print(json.dumps(out), flush=True)
+
+
+def serving_run(trace, modes=("f32", "mixed"), budget_gb=32.0):
+    """One Poisson trace of nanotube queries through the continuous-batching
+    server, FP32 storage against mixed precision."""
     import torch
 
-    from paper_2403_15768_amd import inputs, lbm, serve
+    from paper_2403_15768_amd import serve
 
-    trace = inputs.serving_trace(args.queries, args.rate)
-    out = {"workload": "serving_tubes", "queries": len(trace), "rate_per_s": args.rate,
-           "radius": [8, 32], "box": "512 x (2R+8)^2"}
-    for mode in ("f32", "mixed"):
-        log("serving:", mode)
-        srv = serve.Server(mode=mode, hbm_budget=int(args.budget_gb * (1 << 30)), realtime=True)
+    out = {}
+    for mode in modes:
+        log(f"serving: {mode}, {len(trace)} queries")
+        srv = serve.Server(mode=mode, hbm_budget=int(budget_gb * (1 << 30)), realtime=True)
         t0 = time.perf_counter()
         res = srv.run(trace)
         wall = time.perf_counter() - t0
@@ -387,8 +414,44 @@ def serving_workload(args):
                   glups=round(srv.stats["lattice_updates"] / wall / 1e9, 2))
         out[mode] = sm
         torch.cuda.empty_cache()
-    out["speedup_mixed_over_f32"] = round(out["f32"]["makespan_s"] / out["mixed"]["makespan_s"], 3)
+    if "f32" in out and "mixed" in out:
+        out["speedup_mixed_over_f32"] = round(out["f32"]["makespan_s"] /
+                                              out["mixed"]["makespan_s"], 3)
+    return out
+
+
+def serving_workload(args):
+    """Poisson-arriving nanotube queries (radius 8..32), continuous batching,
+    FP32 storage against mixed precision on the same trace."""
+    from paper_2403_15768_amd import inputs
+
+    trace = inputs.serving_trace(args.queries, args.rate)
+    out = {"workload": "serving_tubes", "queries": len(trace), "rate_per_s": args.rate,
+           "radius": [8, 32], "box": "512 x (2R+8)^2"}
+    out.update(serving_run(trace, budget_gb=args.budget_gb))
     print(json.dumps(out), flush=True)
+
+
+def whole_metric(args):
+    """The rest of the headline metric, bounded to a few minutes: the 256-duct
+    batch run to steady (solves/s, p50 / p99 time-to-steady, FP32 storage
+    against mixed precision) and two short serving traces of nanotube queries
+    (radius 8..32), one at the 50/s arrival rate (oversubscribed: one GPU
+    serves about 2 such queries per second) and one at 2/s."""
+    from paper_2403_15768_amd import inputs
+
+    specs = inputs.batch_channels(256)
+    out = {"batch_steady": {"workload": "batch_256_ducts", "channels": len(specs),
+                            "cells": sum(c.nx * c.ny * c.nz for c in specs)}}
+    out["batch_steady"].update(batch_steady(specs))
+    out["serving"] = {}
+    for rate in (50.0, 2.0):
+        trace = inputs.serving_trace(args.serving_queries, rate)
+        key = f"rate_{rate:g}_per_s"
+        out["serving"][key] = {"queries": len(trace), "radius": [8, 32],
+                               "box": "512 x (2R+8)^2", "budget_gb": args.budget_gb}
+        out["serving"][key].update(serving_run(trace, budget_gb=args.budget_gb))
+    return out
 
 
 def permeability_workload(args):
@@ -443,7 +506,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--check-every", type=int, default=1000)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16s"])
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--thermal", type=int, default=0, choices=[0, 1, 2],
@@ -467,6 +530,10 @@ def main():
     ap.add_argument("--queries", type=int, default=500)
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--serving-queries", type=int, default=40,
+                    help="queries per serving trace in the headline line")
+    ap.add_argument("--no-whole-metric", action="store_true",
+                    help="headline line without the batch run-to-steady and serving parts")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -544,6 +611,10 @@ def main():
     ext["mass_deviation"] = dm
 
     arith = "f32" if args.precision == "f16s" else "f64"  # half storage computes in float
+    whole = None
+    if (args.workload == "duct" and not args.no_whole_metric and not args.thermal
+            and not args.open_ends):
+        whole = whole_metric(args)
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
@@ -595,6 +666,8 @@ def main():
         "cpu_baseline": cpu,
         "extras": ext,
     }
+    if whole:
+        rec.update(whole)
     print(json.dumps(rec), flush=True)
 
 

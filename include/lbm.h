@@ -299,13 +299,36 @@ lbm_status lbm_set_phonons(lbm_ctx *ctx, double tau_p, double rho_p0, double gam
  * NULL.  LBM_ESTATE if the phonons are off.  Synchronous. */
 lbm_status lbm_get_phonons(lbm_ctx *ctx, double *up, double *pops);
 
-/* Advance nsteps >= 0 time steps (asynchronous). */
+/* Advance nsteps >= 0 time steps (asynchronous).  One step is the LB update
+ * of Sec. 4 for the water: pull streaming, the wall rule at the liquid/solid
+ * links (Sec. 4.2; Navier-slip friction of Eq. 5 / Eq. 27), BGK collision
+ * with the bulk force of Eq. 2 as a Guo source; plus the species and noise
+ * switched on by the lbm_set_* calls below. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
-/* Step in chunks of check_every until |Q(n) - Q(n - check_every)| <
- * rel_tol |Q(n)| (Q = flux), or max_steps (LBM_ENOTCONV) or a NaN/Inf
- * (LBM_EDIVERGED).  steps_taken may be NULL.  Synchronous. */
+/* Run to the steady state the paper's permeability questions ask for (the
+ * steady flux through the channel, Sec. 5.1): step in chunks of
+ * check_every until |Q(a) - Q(b)| < rel_tol |Q(a)| for the fluxes Q of two
+ * states check_every steps apart, or max_steps (LBM_ENOTCONV) or a NaN/Inf
+ * (LBM_EDIVERGED).  Each chunk's last step reduces the flux of the state it
+ * reads (lbm_step_checked), so the flux compared is that of one step before
+ * each chunk's end (the first chunk's against the starting state).
+ * steps_taken may be NULL.  Synchronous. */
 lbm_status lbm_run_to_steady(lbm_ctx *ctx, double rel_tol, int64_t check_every,
                              int64_t max_steps, int64_t *steps_taken);
+/* Advance nsteps >= 1 steps like lbm_step, the last of which also sums in
+ * FP64, per block, the flux and mass of the populations its collision sees:
+ * the invariants of the state one step before the end (asynchronous).  For
+ * planar and tube walls without noise, electron lines, masked walls or open
+ * ends the sums are fused into that step (no extra pass over the state) and
+ * equal lbm_invariants' bit for bit with F64 and F32 storage; otherwise a
+ * separate moments pass runs before the last step. */
+lbm_status lbm_step_checked(lbm_ctx *ctx, int64_t nsteps);
+/* Finish the reduction of the last lbm_step_checked: out as lbm_invariants
+ * for the state at step *at_step (may be NULL), the step before that call's
+ * end.  LBM_ESTATE if no checked step ran since the context's last
+ * reduction pass or state change (lbm_invariants, lbm_get_field,
+ * lbm_set_state, ...).  Synchronous; may be called again (same result). */
+lbm_status lbm_checked_invariants(lbm_ctx *ctx, double out[3], int64_t *at_step);
 
 /* Invariants of the current state (the moments the next collision sees):
  * out[0] = flux Q = (1/nx) sum_fluid rho u_x, out[1] = mass M = sum_fluid rho,

@@ -431,6 +431,7 @@ void fill_args(lbm_ctx* c) {
   a.drho_out = 0.0;
   a.bmom = nullptr;  // set per launch (open ends)
   a.bmom_out = nullptr;
+  a.partials = nullptr;  // set for a checked step only
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -475,10 +476,18 @@ lbm_status ensure_end_records(lbm_ctx* c) {
 
 }  // namespace
 
-lbm_status lbm_host::launch_one_step(lbm_ctx* c) {
+lbm_status lbm_host::launch_one_step(lbm_ctx* c, bool check) {
   StepArgs a = c->args;
   a.step_off = c->step;  // plain launch: the step travels as an argument
   a.rev = c->cur;
+  if (check) {  // the step also leaves the invariants' partials of its input state
+    a.partials = c->at<double>(c->pl.off_partials);
+    HIPCHK(c, lbm::launch_step_checked(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
+                                       c->pl.bouz, c->stream));
+    c->cur = 1 - c->cur;
+    c->step++;
+    return LBM_OK;
+  }
   if (c->elec)  // the electrons of step n first: the water step reads their velocity
     HIPCHK(c, lbm::launch_electron_step(c->pl.Q, c->pl.prec, c->pop[c->cur],
                                         c->at<double>(c->pl.off_e[c->cur]),
@@ -616,11 +625,11 @@ lbm_status do_steps(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
-lbm_status invariants(lbm_ctx* c, double out[3]) {
+// The per-block partials in the arena -> (flux, mass, mass deviation):
+// fixed-order reduction, copy to the host, synchronise.
+lbm_status reduce_partials(lbm_ctx* c, double out[3]) {
   double* partials = c->at<double>(c->pl.off_partials);
   double* dout = c->at<double>(c->pl.off_out);
-  HIPCHK(c, lbm::launch_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args, c->pl.bouz, -1,
-                                nullptr, partials, c->stream));
   HIPCHK(c, lbm::launch_reduce_final(partials, c->pl.nblocks, dout, c->stream));
   double h[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -631,6 +640,34 @@ lbm_status invariants(lbm_ctx* c, double out[3]) {
   out[2] = h[1];
   if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
     return c->fail(LBM_EDIVERGED, "flux or mass is not finite");
+  return LBM_OK;
+}
+
+// the moments of the current state into the per-block partials (asynchronous)
+lbm_status moments_partials(lbm_ctx* c) {
+  HIPCHK(c, lbm::launch_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args, c->pl.bouz, -1,
+                                nullptr, c->at<double>(c->pl.off_partials), c->stream));
+  return LBM_OK;
+}
+
+lbm_status invariants(lbm_ctx* c, double out[3]) {
+  c->checked_step = -1;  // the partials are about to hold the current state's
+  lbm_status s = moments_partials(c);
+  if (s != LBM_OK) return s;
+  return reduce_partials(c, out);
+}
+
+// nsteps >= 1 steps; the partials are left holding the invariants of the
+// state before the last step (fused into that step where the step kernel
+// can: planar or tube walls without noise, sheets, mask or open ends).
+lbm_status steps_checked(lbm_ctx* c, int64_t nsteps) {
+  lbm_status s = do_steps(c, nsteps - 1);
+  if (s != LBM_OK) return s;
+  c->checked_step = -1;
+  const bool fused = !c->elec && !c->args.open && !c->pl.masked && c->args.th_mode == 0;
+  if (!fused && (s = moments_partials(c)) != LBM_OK) return s;
+  if ((s = launch_one_step(c, fused)) != LBM_OK) return s;
+  c->checked_step = c->step - 1;
   return LBM_OK;
 }
 
@@ -1045,16 +1082,34 @@ lbm_status lbm_run_to_steady(lbm_ctx* c, double rel_tol, int64_t check_every, in
   if (s != LBM_OK) return s;
   double prev = inv[0];
   int64_t taken = 0;
+  // each chunk's last step also reduces the flux of the state it reads, so a
+  // check costs no extra pass over the populations: the flux compared is
+  // that of the step before each chunk's end (check_every steps apart, the
+  // first chunk's one step fewer from the starting state)
   while (taken < max_steps) {
     const int64_t k = std::min(check_every, max_steps - taken);
-    if ((s = do_steps(c, k)) != LBM_OK) return s;
+    if ((s = steps_checked(c, k)) != LBM_OK) return s;
     taken += k;
     if (steps_taken) *steps_taken = taken;
-    if ((s = invariants(c, inv)) != LBM_OK) return s;
+    if ((s = reduce_partials(c, inv)) != LBM_OK) return s;
     if (std::fabs(inv[0] - prev) < rel_tol * std::fabs(inv[0])) return LBM_OK;
     prev = inv[0];
   }
   return c->fail(LBM_ENOTCONV, "no steady state after %lld steps", (long long)taken);
+}
+
+lbm_status lbm_step_checked(lbm_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 1) return LBM_EINVAL;
+  return steps_checked(c, nsteps);
+}
+
+lbm_status lbm_checked_invariants(lbm_ctx* c, double out[3], int64_t* at_step) {
+  if (!c || !out) return LBM_EINVAL;
+  if (c->checked_step < 0) return c->fail(LBM_ESTATE, "no checked step since the last reduction");
+  const int64_t at = c->checked_step;
+  lbm_status s = reduce_partials(c, out);
+  if (s == LBM_OK && at_step) *at_step = at;
+  return s;
 }
 
 lbm_status lbm_invariants(lbm_ctx* c, double out[3]) {
@@ -1084,6 +1139,7 @@ lbm_status lbm_get_field(lbm_ctx* c, int which, double* host_out) {
   double* scratch = static_cast<double*>(c->pop[1 - c->cur]);
   const size_t bytes = (size_t)c->pl.ncolbox * c->pl.nx * sizeof(double);
   HIPCHK(c, hipMemsetAsync(scratch, 0, bytes, c->stream));
+  c->checked_step = -1;  // the moments kernel writes the partials too
   HIPCHK(c, lbm::launch_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args, c->pl.bouz, which,
                                 scratch, c->at<double>(c->pl.off_partials), c->stream));
   HIPCHK(c, hipMemcpyAsync(host_out, scratch, bytes, hipMemcpyDeviceToHost, c->stream));
@@ -1153,6 +1209,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) 
   lbm_status s = sync(c);
   if (s == LBM_OK) c->step = step;
   c->bmom_ok = false;
+  c->checked_step = -1;
   return s;
 }
 
@@ -1176,6 +1233,7 @@ lbm_status lbm_set_state(lbm_ctx* c, const void* host_buf, size_t bytes, int64_t
   lbm_status s = sync(c);
   if (s == LBM_OK) c->step = step;
   c->bmom_ok = false;
+  c->checked_step = -1;
   return s;
 }
 
@@ -1216,6 +1274,7 @@ lbm_status lbm_transfer_state(lbm_ctx* dst, lbm_ctx* src) {
   dst->have_raw = src->have_raw;
   dst->step = src->step;
   dst->bmom_ok = false;
+  dst->checked_step = -1;
   s = upload_wall_r(dst, dst->at<double>(pd.off_lambda), (int64_t)nw);
   return s;
 }

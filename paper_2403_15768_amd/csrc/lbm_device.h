@@ -133,6 +133,10 @@ struct StepArgs {
   double drho_in, drho_out;
   const double* bmom;
   double* bmom_out;
+  // a checked step (the last step of a chunk of run-to-steady): per-block
+  // FP64 sums (j_x, rho - rho0) of the populations the step's collision
+  // sees, [slot * segs + segment][2]; null otherwise
+  double* partials;
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];

@@ -79,6 +79,7 @@ struct lbm_ctx {
   double kT = 0.0;          // lattice temperature of the thermal noise (0: none)
   bool elec = false;        // electron sheets on (SLAB)
   bool bmom_ok = false;     // open ends: end-node records of pop[cur] are current
+  int64_t checked_step = -1;  // step whose invariants' partials the arena holds (-1: none)
   lbm::ElecArgs ea{};
 
   template <typename T>
@@ -109,5 +110,7 @@ struct lbm_ctx {
 
 namespace lbm_host {
 lbm_status sync(lbm_ctx* c);
-lbm_status launch_one_step(lbm_ctx* c);
+// one plain step launch; check: the step also leaves the per-block partials
+// of the invariants of the state it reads (see lbm_step_checked)
+lbm_status launch_one_step(lbm_ctx* c, bool check = false);
 }  // namespace lbm_host

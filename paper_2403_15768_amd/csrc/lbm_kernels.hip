@@ -30,18 +30,14 @@
 namespace lbm {
 
 // ------------------------------------------------------------ stream-collide
-template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN>
-__device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restrict__ dst,
-                                           const StepArgs& a) {
-  // grid (fluid columns, segments per x-line).  Wall columns go first (their
-  // blocks do more work and would otherwise form the tail of the grid).  The
-  // rest are visited in one order when reading one buffer and in the reverse
-  // order when reading the other: a step then starts on the columns the
-  // previous step wrote last, which are still in the last-level cache.
-  int slot = blockIdx.x;
-  if (a.rev && slot >= a.nwallcols) slot = a.nactive - 1 - slot + a.nwallcols;
-  const int x = blockIdx.y * a.bx + threadIdx.x;
-  if (x >= a.nxp) return;
+// One lane's cell of the step kernel (x < nxp).  With CHECK the lane also
+// returns, in FP64, j_x (with the half-force) and rho - rho0 of the
+// populations its collision sees, as k_moments forms them (0 on padding
+// lanes).
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN, bool CHECK>
+__device__ __forceinline__ void step_cell(const S* __restrict__ src, S* __restrict__ dst,
+                                          const StepArgs& a, int slot, int x, double* jx_c,
+                                          double* dr_c) {
   // Lanes on the padding of an x-line (nx <= x < nxp) recompute cell nx - 1
   // and store it into the padding, so every cache line of the output is
   // written whole (a partly written line costs HBM a read-modify-write).
@@ -61,6 +57,18 @@ __device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restr
     thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
   gather<L, S, M, M, BOUZ, ELEC, OPEN>(src, a, col, xc, info, df);
   if constexpr (OPEN) open_correct<L, M>(a, col, xc, info.mask, df);
+  if constexpr (CHECK) {
+    if (x < a.nx) {
+      double dr = 0, jx = 0;
+#pragma unroll
+      for (int i = 0; i < L::Q; i++) {
+        dr += static_cast<double>(df[i]);
+        jx += L::cx[i] * static_cast<double>(df[i]);
+      }
+      *jx_c = jx + a.F[0] / 2;
+      *dr_c = dr;
+    }
+  }
   M rec[4];
   collide_store<L, M, S, TH, OPEN>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
                                    (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi, rec);
@@ -78,10 +86,69 @@ __device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restr
     }
 }
 
-template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC = false>
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Per-block partial sums (s0, s1) over a block of the step or moments grid:
+// a fixed butterfly within each wave, then the waves in order (deterministic).
+__device__ __forceinline__ void block_partials(double s0, double s1, double* __restrict__ out) {
+  __shared__ double red[2][8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) {
+    red[0][wv] = s0;
+    red[1][wv] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    double t0 = 0, t1 = 0;
+    for (int k = 0; k < nw; k++) {
+      t0 += red[0][k];
+      t1 += red[1][k];
+    }
+    out[0] = t0;
+    out[1] = t1;
+  }
+}
+
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN,
+          bool CHECK = false>
+__device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restrict__ dst,
+                                           const StepArgs& a) {
+  // grid (fluid columns, segments per x-line).  Wall columns go first (their
+  // blocks do more work and would otherwise form the tail of the grid).  The
+  // rest are visited in one order when reading one buffer and in the reverse
+  // order when reading the other: a step then starts on the columns the
+  // previous step wrote last, which are still in the last-level cache.
+  int slot = blockIdx.x;
+  if (a.rev && slot >= a.nwallcols) slot = a.nactive - 1 - slot + a.nwallcols;
+  const int x = blockIdx.y * a.bx + threadIdx.x;
+  if constexpr (CHECK) {
+    // a checked step (the last of a chunk) also sums the flux and mass
+    // deviation of the populations its collision sees -- the invariants of
+    // the state before the step -- per block, indexed like k_moments' blocks
+    // (slot, segment), so the two agree bit for bit where the arithmetic is
+    // double
+    double jx_c = 0.0, dr_c = 0.0;
+    if (x < a.nxp)
+      step_cell<L, S, M, BOUZ, TH, ELEC, OPEN, true>(src, dst, a, slot, x, &jx_c, &dr_c);
+    block_partials(jx_c, dr_c, a.partials + 2 * ((int64_t)slot * a.segs + blockIdx.y));
+    return;
+  }
+  if (x >= a.nxp) return;
+  step_cell<L, S, M, BOUZ, TH, ELEC, OPEN, false>(src, dst, a, slot, x, nullptr, nullptr);
+}
+
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC = false,
+          bool CHECK = false>
 __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                               StepArgs a) {
-  step_cells<L, S, M, BOUZ, TH, ELEC, false>(src, dst, a);
+  step_cells<L, S, M, BOUZ, TH, ELEC, false, CHECK>(src, dst, a);
 }
 
 // Open x ends: the same update with the ghost pulls at both ends of every
@@ -239,17 +306,11 @@ __global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
 }
 
 // ------------------------------------------------------------ moments
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <class L, typename S, typename W, bool BOUZ, bool ELEC = false, bool MASKED = false>
 __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, StepArgs a,
                                                  int which, double* __restrict__ field,
                                                  double* __restrict__ partials) {
-  __shared__ double red[2][8];
   const int slot = blockIdx.x / a.segs;
   const int seg = blockIdx.x - slot * a.segs;
   const int x = seg * a.bx + threadIdx.x;
@@ -289,47 +350,43 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
       field[(int64_t)col * a.nx + x] = v;
     }
   }
-  // deterministic block reduction: fixed butterfly within a wave, waves in order
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double s0 = wave_sum(jx_cell), s1 = wave_sum(drho_cell);
-  if (lane == 0) {
-    red[0][wv] = s0;
-    red[1][wv] = s1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) >> 6;
-    double t0 = 0, t1 = 0;
-    for (int k = 0; k < nw; k++) {
-      t0 += red[0][k];
-      t1 += red[1][k];
-    }
-    partials[2 * (int64_t)blockIdx.x] = t0;
-    partials[2 * (int64_t)blockIdx.x + 1] = t1;
-  }
+  // deterministic block reduction (the checked step kernel forms the same)
+  block_partials(jx_cell, drho_cell, partials + 2 * (int64_t)blockIdx.x);
 }
 
-__global__ void __launch_bounds__(256) k_reduce_final(const double* __restrict__ partials,
-                                                      int64_t nblocks, double* __restrict__ out) {
-  __shared__ double red[2][256];
+// Fixed-order FP64 sum of the (j_x, rho - rho0) partials of nblocks blocks:
+// thread t adds blocks t, t + 1024, ... in order (loads unrolled so that
+// several are in flight), then a fixed butterfly in each wave and the 16
+// waves in order.
+constexpr int kReduceThreads = 1024;
+__global__ void __launch_bounds__(kReduceThreads) k_reduce_final(const double* __restrict__ partials,
+                                                                 int64_t nblocks,
+                                                                 double* __restrict__ out) {
+  __shared__ double red[2][kReduceThreads / 64];
+  const double2* p2 = reinterpret_cast<const double2*>(partials);
   double t0 = 0, t1 = 0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
-    t0 += partials[2 * b];
-    t1 += partials[2 * b + 1];
+#pragma unroll 8
+  for (int64_t b = threadIdx.x; b < nblocks; b += kReduceThreads) {
+    const double2 v = p2[b];
+    t0 += v.x;
+    t1 += v.y;
   }
-  red[0][threadIdx.x] = t0;
-  red[1][threadIdx.x] = t1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  t0 = wave_sum(t0);
+  t1 = wave_sum(t1);
+  if (lane == 0) {
+    red[0][wv] = t0;
+    red[1][wv] = t1;
+  }
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    out[0] = red[0][0];
-    out[1] = red[1][0];
+    double s0 = 0, s1 = 0;
+    for (int k = 0; k < kReduceThreads / 64; k++) {
+      s0 += red[0][k];
+      s1 += red[1][k];
+    }
+    out[0] = s0;
+    out[1] = s1;
   }
 }
 
@@ -880,6 +937,33 @@ static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, b
       grid, block, kargs, 0, st);
 }
 
+// the checked step: planar or tube walls, no noise, sheets, mask or open ends
+template <class L, typename S, typename M>
+static hipError_t launch_step_checked_t(const void* src, void* dst, const StepArgs& a, bool bouz,
+                                        hipStream_t st) {
+  const dim3 grid((unsigned)a.nactive, (unsigned)a.segs), block(a.bx);
+  const S* s = static_cast<const S*>(src);
+  S* d = static_cast<S*>(dst);
+  StepArgs args = a;
+  void* kargs[3] = {(void*)&s, (void*)&d, (void*)&args};
+  const void* fn = bouz ? reinterpret_cast<const void*>(&k_step<L, S, M, true, 0, false, true>)
+                        : reinterpret_cast<const void*>(&k_step<L, S, M, false, 0, false, true>);
+  return hipLaunchKernel(fn, grid, block, kargs, 0, st);
+}
+
+hipError_t launch_step_checked(int q, int prec, const void* src, void* dst, const StepArgs& a,
+                               bool bouz, hipStream_t st) {
+  if (!a.partials || a.th_mode != 0 || a.ue || a.cellw || a.open) return hipErrorInvalidValue;
+  if (q == 9) {
+    if (prec == 0) return launch_step_checked_t<D2Q9, double, double>(src, dst, a, bouz, st);
+    if (prec == 1) return launch_step_checked_t<D2Q9, float, double>(src, dst, a, bouz, st);
+    return launch_step_checked_t<D2Q9, _Float16, float>(src, dst, a, bouz, st);
+  }
+  if (prec == 0) return launch_step_checked_t<D3Q19, double, double>(src, dst, a, bouz, st);
+  if (prec == 1) return launch_step_checked_t<D3Q19, float, double>(src, dst, a, bouz, st);
+  return launch_step_checked_t<D3Q19, _Float16, float>(src, dst, a, bouz, st);
+}
+
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
                        hipStream_t st) {
   if (q == 9) {
@@ -981,7 +1065,7 @@ hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, b
 
 hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, partials, nblocks, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, st, partials, nblocks, out);
   return hipGetLastError();
 }
 

@@ -40,6 +40,11 @@ struct ElecArgs {
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
                        hipStream_t st);  // a.ue: electron-sheet walls; a.cellw: masked walls
+// one step that also leaves the per-block FP64 (j_x, rho - rho0) partials of
+// the populations its collision sees in a.partials (k_moments' blocks and
+// order); planar or tube walls without noise, sheets, mask or open ends
+hipError_t launch_step_checked(int q, int prec, const void* src, void* dst, const StepArgs& a,
+                               bool bouz, hipStream_t st);
 const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec,
                             bool masked, bool open);
 // one electron step from the water state g (step n): e_src -> e_dst, u_e of

@@ -66,7 +66,7 @@ EXPORTS = [
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
     "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure", "lbm_set_phonons",
-    "lbm_get_phonons",
+    "lbm_get_phonons", "lbm_step_checked", "lbm_checked_invariants",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -109,6 +109,8 @@ def load() -> C.CDLL:
         "lbm_set_open_ends": [vp, C.c_int, C.c_double, C.c_double],
         "lbm_set_noise_closure": [vp, dp, C.c_int, C.c_int, dp, dp],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
+        "lbm_step_checked": [vp, i64],
+        "lbm_checked_invariants": [vp, dp, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_flux": [vp, dp],
         "lbm_mass": [vp, dp],
@@ -373,6 +375,20 @@ class Channel:
     # ---- time stepping
     def step(self, n: int) -> None:
         self._ck(self._lib.lbm_step(self._h, int(n)), "lbm_step")
+
+    def step_checked(self, n: int) -> None:
+        """n >= 1 steps; the last also reduces the invariants of the state it
+        reads (asynchronous; collect them with checked_invariants)."""
+        self._ck(self._lib.lbm_step_checked(self._h, int(n)), "lbm_step_checked")
+
+    def checked_invariants(self):
+        """(flux, mass, mass deviation, step) of the last step_checked's
+        reduction: the state one step before that call's end."""
+        out = np.zeros(3)
+        at = C.c_int64()
+        self._ck(self._lib.lbm_checked_invariants(self._h, _dptr(out), C.byref(at)),
+                 "lbm_checked_invariants")
+        return float(out[0]), float(out[1]), float(out[2]), int(at.value)
 
     def run_to_steady(self, rel_tol: float = 1e-8, check_every: int = 1000,
                       max_steps: int = 10 ** 7) -> int:

@@ -473,3 +473,54 @@ def test_transfer_state_across_precisions(lbm, nx):
     F.step(130)
     F2.step(130)
     assert np.array_equal(F.get_state()[0], F2.get_state()[0])
+
+
+# ------------------------------------------------------------------ checked steps
+@pytest.mark.parametrize("case", ["duct_f64", "duct_f32", "tube_f32", "d2q9_f64", "duct_f16s",
+                                  "duct_f32_thermal", "slab_f64_electrons"])
+def test_checked_step_equals_invariants_before_the_last_step(lbm, case):
+    # a checked step's fused FP64 sums are the invariants of the state it
+    # reads: bit for bit where the arithmetic is double, and within the
+    # float arithmetic's rounding for half storage; the cases that cannot
+    # fuse (noise, electron lines) take a separate moments pass, exactly
+    say("checked step", case)
+    geom, prec = case.split("_")[0], case.split("_")[1]
+    kw = {}
+    if geom == "duct":
+        args = (19, lbm.DUCT, 48, 20, 12)
+    elif geom == "tube":
+        kw, ny, nz = tube_kw(7)
+        args = (19, lbm.TUBE, 40, ny, nz)
+    elif geom == "slab":
+        args = (19, lbm.SLAB, 33, 9, 6)
+    else:
+        args = (9, lbm.SLAB, 64, 30, 1)
+
+    def make():
+        G = lbm.Channel(*args, tau=0.75, force=(1e-5, 0, 0), precision=prec, **kw)
+        G.set_friction(np.random.default_rng(4).uniform(0.0, 0.2, G.wall_count))
+        if case.endswith("thermal"):
+            G.set_thermal(1e-7, 2, 3)
+        if case.endswith("electrons"):
+            G.set_electrons(0.9, 1.0, 0.05, 1e-6)
+        return G
+
+    A, B = make(), make()
+    for n in (1, 70, 129):
+        A.step(n - 1)
+        ref = A.invariants()
+        A.step(1)
+        B.step_checked(n)
+        q, m, dm, at = B.checked_invariants()
+        assert at == A.step_count - 1 == B.step_count - 1
+        assert np.array_equal(A.get_state()[0], B.get_state()[0])  # same steps
+        if prec == "f16s":
+            assert abs(q / ref[0] - 1) < 1e-6 and abs(dm - ref[2]) < 1e-9 * B.fluid_count
+        else:
+            assert (q, m, dm) == ref
+        assert B.checked_invariants()[:3] == (q, m, dm)  # may be read again
+    B.invariants()  # a reduction pass of its own: the checked sums are gone
+    with pytest.raises(lbm.LBMError):
+        B.checked_invariants()
+    with pytest.raises(lbm.LBMError):
+        B.step_checked(0)
