@@ -174,6 +174,25 @@ lbm_status lbm_set_friction(lbm_ctx *ctx, const double *lambda, size_t n,
 lbm_status lbm_set_friction_spectral(lbm_ctx *ctx, const lbm_spectral *sp,
                                      const double *omega, size_t n,
                                      int on_device);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * friction quadrature of lbm_set_friction_spectral without a context.
+ * omega: device, n plasmon frequencies (finite, >= 0; not checked here: a
+ * bad value gives a NaN lambda); lambda: device, n doubles out, the lattice
+ * friction lambda_target raw(Omega_k) / raw(omega0), bit for bit what
+ * lbm_set_friction_spectral computes for the same spectra and frequencies
+ * (lambda may alias omega).  Both arrays are owned by the caller.
+ * hip_stream: a hipStream_t (NULL = default stream); asynchronous, no
+ * synchronisation, no allocation, no memset, so it may be captured.  The raw
+ * quadrature sums live in a fixed device array of LBM_STATIC_MAX_NODES + 1
+ * doubles (8 MiB) per GPU, held until the process ends and shared by every
+ * call on that GPU: calls that overlap on one GPU (on different streams
+ * without ordering) race.  n > LBM_STATIC_MAX_NODES or invalid spectral
+ * parameters -> LBM_EINVAL; a failed launch -> LBM_EDEVICE. */
+#define LBM_STATIC_MAX_NODES ((size_t)1 << 20)
+lbm_status lbm_friction_quadrature_static(const lbm_spectral *sp, const double *omega, size_t n,
+                                          double *lambda, void *hip_stream);
+
 /* Current friction: lambda (lattice units) and, after a spectral set, the raw
  * quadrature sums (raw has wall_count + 1 entries, the last being
  * raw(omega0)); either pointer may be NULL.  Host arrays. */

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_kernels.hip"]
+SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_kernels.hip", "lbm_static.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -832,13 +832,7 @@ lbm_status lbm_set_friction_spectral(lbm_ctx* c, const lbm_spectral* sp, const d
                                      size_t n, int on_device) {
   if (!c || !sp) return LBM_EINVAL;
   if (n != (size_t)c->pl.nwall) return c->fail(LBM_EINVAL, "expected %lld plasmon frequencies", (long long)c->pl.nwall);
-  if (!(sp->T > 0) || !(sp->d > 0) || !(sp->gamma_s > 0) || !(sp->gamma_l > 0) ||
-      !(sp->omega_l > 0) || !(sp->a_l > 0) || !(sp->q_max > 0) || !(sp->w_max > 0) ||
-      !(sp->omega0 > 0) || sp->nq < 1 || sp->nw < 1 || !(sp->lambda_target >= 0) ||
-      (sp->coupling != 0 && sp->coupling != 1) || !(sp->v_l >= 0) ||
-      !std::isfinite(sp->T + sp->d + sp->gamma_s + sp->gamma_l + sp->omega_l + sp->a_l +
-                     sp->q_max + sp->w_max + sp->omega0 + sp->lambda_target + sp->v_l))
-    return c->fail(LBM_EINVAL, "bad spectral parameters");
+  if (!spectral_valid(sp)) return c->fail(LBM_EINVAL, "bad spectral parameters");
   std::vector<double> h;
   const double* hsrc = omega;
   if (n && !omega) return c->fail(LBM_EINVAL, "null omega array");
@@ -858,10 +852,7 @@ lbm_status lbm_set_friction_spectral(lbm_ctx* c, const lbm_spectral* sp, const d
   if (n)
     HIPCHK(c, hipMemcpyAsync(dl, omega, n * sizeof(double),
                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-  lbm::SpecArgs a{sp->T,  sp->omega0, sp->gamma_s, sp->omega_l,       sp->gamma_l,
-                  sp->a_l, sp->d,      sp->nq,      sp->nw,            sp->q_max,
-                  sp->w_max, sp->lambda_target, sp->dispersion, sp->coupling, sp->v_l};
-  HIPCHK(c, lbm::launch_friction(a, dl, (int64_t)n, draw, dl, c->stream));
+  HIPCHK(c, lbm::launch_friction(spec_args(sp), dl, (int64_t)n, draw, dl, c->stream));
   c->have_raw = true;
   return upload_wall_r(c, dl, (int64_t)n);
 }

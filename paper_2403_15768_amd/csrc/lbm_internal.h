@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
@@ -109,6 +110,21 @@ struct lbm_ctx {
 
 
 namespace lbm_host {
+// the spectral parameters the quadrature accepts (finite, positive scales,
+// coupling 0 or 1, v_l >= 0)
+inline bool spectral_valid(const lbm_spectral* sp) {
+  return sp && sp->T > 0 && sp->d > 0 && sp->gamma_s > 0 && sp->gamma_l > 0 && sp->omega_l > 0 &&
+         sp->a_l > 0 && sp->q_max > 0 && sp->w_max > 0 && sp->omega0 > 0 && sp->nq >= 1 &&
+         sp->nw >= 1 && sp->lambda_target >= 0 && (sp->coupling == 0 || sp->coupling == 1) &&
+         sp->v_l >= 0 &&
+         std::isfinite(sp->T + sp->d + sp->gamma_s + sp->gamma_l + sp->omega_l + sp->a_l +
+                       sp->q_max + sp->w_max + sp->omega0 + sp->lambda_target + sp->v_l);
+}
+inline lbm::SpecArgs spec_args(const lbm_spectral* sp) {
+  return lbm::SpecArgs{sp->T,     sp->omega0, sp->gamma_s,       sp->omega_l,    sp->gamma_l,
+                       sp->a_l,   sp->d,      sp->nq,            sp->nw,         sp->q_max,
+                       sp->w_max, sp->lambda_target, sp->dispersion, sp->coupling, sp->v_l};
+}
 lbm_status sync(lbm_ctx* c);
 // one plain step launch; check: the step also leaves the per-block partials
 // of the invariants of the state it reads (see lbm_step_checked)

@@ -67,6 +67,7 @@ EXPORTS = [
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
     "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure", "lbm_set_phonons",
     "lbm_get_phonons", "lbm_step_checked", "lbm_checked_invariants",
+    "lbm_friction_quadrature_static",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -110,6 +111,7 @@ def load() -> C.CDLL:
         "lbm_set_noise_closure": [vp, dp, C.c_int, C.c_int, dp, dp],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
         "lbm_step_checked": [vp, i64],
+        "lbm_friction_quadrature_static": [C.POINTER(Spectral), vp, sz, vp, vp],
         "lbm_checked_invariants": [vp, dp, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_flux": [vp, dp],
