@@ -388,59 +388,121 @@ lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
 lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
 
 /* ---- Batches (many channels, one kernel launch per step and group) --------
- * A batch groups n existing contexts with the same lattice, storage
- * precision and wall kind (TUBE or planar); sizes, tau, force and friction
- * may differ.  One launch per time step advances a group of members over a
- * work list of 64-lane items laid out in whole workgroups that never share a
- * column (wall columns first); runs of 64 steps are replayed from captured
- * hipGraphs.  Members are cut, in order, into groups whose state fits the
- * last-level cache (128 MiB by default, 96 MiB for F16S storage, see
- * lbm_batch_set_group_bytes); a
- * call to lbm_batch_step runs each group 64 steps at a time, so a group's
- * populations stay cached between its steps.  Groups are dealt round-robin
- * to two streams by default (see lbm_batch_set_streams): the batch stream
- * and streams the batch creates at the default priority, which wait for the
- * batch stream's earlier work and are joined back into it, so every call
- * stays ordered on the batch stream.  Members keep their own buffers,
- * parameters and step counters, and a member advanced in a batch is bit-for-
- * bit the same as the member advanced alone.  Their lbm_get_*,
- * lbm_invariants and lbm_get_state calls stay valid between batch calls; a
- * member stepped, restored or transferred outside the batch is taken up at
- * its current step by the next batch call (if its stream is not the batch
- * stream, the caller orders the two).  Members must outlive the batch. */
+ * The batching the configurations of many uneven channels and of the
+ * serving loop ask for (the design queries of Sec. 5.1: permeability against
+ * radius and carrier density, one independent channel each).  A batch holds
+ * contexts with the same lattice, storage precision, wall kind (TUBE or
+ * planar) and thermal-noise form in member slots; sizes, tau, force,
+ * friction, kT and noise seed may differ.  One launch per time step
+ * advances a group of members over a work list of 64-lane items laid out in
+ * whole workgroups that never share a column (wall columns first); runs of
+ * 64 steps are replayed from captured hipGraphs.  Members are cut into
+ * groups whose state fits the last-level cache (128 MiB by default, 96 MiB
+ * for F16S storage, see lbm_batch_set_group_bytes); a call to lbm_batch_step
+ * runs each group 64 steps at a time, so a group's populations stay cached
+ * between its steps.  Groups are dealt round-robin to two streams by default
+ * (see lbm_batch_set_streams): the batch stream and streams the batch
+ * creates at the default priority, which wait for the batch stream's earlier
+ * work and are joined back into it, so every call stays ordered on the batch
+ * stream.  Members keep their own buffers, parameters and step counters,
+ * and a member advanced in a batch is bit-for-bit the same as the member
+ * advanced alone.  Their lbm_get_*, lbm_invariants and lbm_get_state calls
+ * stay valid between batch calls; a member stepped, restored or transferred
+ * outside the batch is taken up at its current step by the next batch call
+ * (if its stream is not the batch stream, the caller orders the two).
+ * Members join (lbm_batch_add) and leave (lbm_batch_remove) while the batch
+ * runs: only the groups they touch get new work lists and graphs.  Members
+ * must outlive their membership.  Batches refuse members with electron
+ * lines, MASKED walls or open ends (LBM_EINVAL); lbm_batch_step refuses a
+ * member whose noise form changed or whose sheets or open ends were switched
+ * on after it joined, and takes up a changed kT, seed or noise closure. */
 typedef struct lbm_batch lbm_batch; /* opaque */
-/* Device bytes a batch of these contexts needs (descriptors, work list for
- * the longest workgroup shape, column ids, reduction partials). */
+
+/* Capacity of a batch made empty (lbm_batch_create_spec): the kind of its
+ * members and the most members, work items and fluid columns it holds at
+ * once (lbm_batch_member_cost gives a context's items and columns). */
+typedef struct {
+  int lattice;     /* lbm_lattice */
+  int precision;   /* lbm_precision */
+  int tube;        /* 1: TUBE members (interpolated walls), 0: SLAB / DUCT */
+  int noise;       /* thermal-noise form of every member: 0 none, LBM_NOISE_* */
+  int max_members;
+  int64_t max_items, max_columns;
+} lbm_batch_spec;
+/* Work items (the most over every workgroup shape) and fluid columns a
+ * context takes up in a batch; either pointer may be NULL. */
+lbm_status lbm_batch_member_cost(const lbm_ctx *ctx, int64_t *items, int64_t *columns);
+/* Device bytes of a batch of this capacity (member table, work list, column
+ * ids, the reduction's per-item partials). */
+lbm_status lbm_batch_spec_footprint(const lbm_batch_spec *spec, size_t *bytes);
+/* An empty batch of that capacity.  arena: device, >= footprint bytes,
+ * 256-byte aligned, owned by the caller (borrowed, never freed).
+ * Synchronous. */
+lbm_status lbm_batch_create_spec(const lbm_batch_spec *spec, void *arena, size_t arena_bytes,
+                                 void *hip_stream, lbm_batch **out);
+/* Device bytes a batch of exactly these contexts needs. */
 lbm_status lbm_batch_footprint(lbm_ctx *const *ctxs, int n, size_t *bytes);
-/* arena: device, >= footprint bytes, 256-byte aligned, owned by the caller
- * (borrowed, never freed).  Synchronous.  LBM_EINVAL if the members differ in
- * lattice, precision, wall kind or thermal-noise form (lbm_set_thermal: one
- * form for the whole batch, each member its own kT and seed), one appears
- * twice, or one has electron sheets, MASKED walls or open ends.  lbm_batch_step refuses a member whose
- * noise form changed or whose sheets were switched on after the batch was
- * built, and takes up a changed kT or seed.  Batched members draw the same
- * thermal numbers as alone: results agree bit for bit. */
+/* A batch of these n contexts in slots 0..n-1 (capacity for exactly them).
+ * Synchronous.  LBM_EINVAL if the members differ in kind (see above) or one
+ * appears twice. */
 lbm_status lbm_batch_create(lbm_ctx *const *ctxs, int n, void *arena, size_t arena_bytes,
                             void *hip_stream, lbm_batch **out);
 void lbm_batch_destroy(lbm_batch *b);  /* members and arena untouched */
+/* Take ctx in, at its current step and state, into the lowest free slot
+ * (*slot, may be NULL): it joins the first group with room for its state or
+ * a new group, whose work list and graph are rebuilt; the other groups keep
+ * theirs.  Synchronous (waits for the batch's queued steps).  LBM_EINVAL: a
+ * member already, or of another kind; LBM_ENOMEM: no free slot or no room in
+ * the work list (nothing changed). */
+lbm_status lbm_batch_add(lbm_batch *b, lbm_ctx *ctx, int *slot);
+/* Let ctx leave after the batch's queued steps (synchronous); its slot is
+ * free again, its group's work list is rebuilt.  LBM_EINVAL if not a
+ * member.  The context is untouched and may be stepped alone or join again. */
+lbm_status lbm_batch_remove(lbm_batch *b, lbm_ctx *ctx);
+/* Members now, and slots in use (the highest taken slot + 1); either may be
+ * NULL. */
+lbm_status lbm_batch_size(const lbm_batch *b, int *members, int *slots);
 lbm_status lbm_batch_items(const lbm_batch *b, int64_t *nitems);
 /* Advance every member nsteps steps (asynchronous, on the batch stream). */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
-/* Per member m: out[3m] flux, out[3m+1] mass, out[3m+2] mass deviation, as
- * lbm_invariants.  Deterministic FP64 reductions.  Synchronous. */
+/* Per slot s < slots: out[3s] flux, out[3s+1] mass, out[3s+2] mass
+ * deviation, as lbm_invariants (NaN for a free slot).  Deterministic FP64
+ * reductions.  Synchronous. */
 lbm_status lbm_batch_invariants(lbm_batch *b, double *out);
-/* Autotuner: time the candidate workgroup shapes (2, 4 or 8 waves per
- * workgroup; the work list is rebuilt for each) on this batch and keep the
- * fastest; *chosen may be NULL.  The timed launches write only the buffers
- * the next step overwrites: no state or counter changes.  Synchronous. */
-lbm_status lbm_batch_tune(lbm_batch *b, int *chosen);
+
+/* Autotuner settings: workgroup shape (waves per workgroup), group size in
+ * bytes of state, streams; the timed step of the chosen setting and of the
+ * default one (4 waves, default group size, 2 streams), in microseconds. */
+typedef struct {
+  int waves_per_group;
+  size_t group_bytes;
+  int streams;
+  double us_per_step;          /* 0 when not timed (taken from the cache) */
+  double us_per_step_default;  /* 0 when not timed */
+  int cached;                  /* 1: taken from the process-wide cache */
+  int64_t repacks;             /* lbm_batch_settings: times every group was laid out anew */
+} lbm_batch_tuning;
+#define LBM_TUNE_RETIME 1
+/* Autotuner: for this kind of batch (lattice, storage, wall kind, noise
+ * form, and a size bucket: log2 of its fluid cells and of its members) take
+ * the setting a previous search chose in this process, else search: every
+ * combination of 2, 4 or 8 waves per workgroup, groups of 64, 96, 128 or
+ * 192 MiB of state and 1, 2 or 3 streams is laid out and timed on this
+ * batch, the fastest kept and cached.  flags LBM_TUNE_RETIME: search even if
+ * cached.  The timed launches write only the buffers the next step
+ * overwrites: no state or counter changes, and no setting changes results.
+ * *chosen may be NULL.  Synchronous. */
+lbm_status lbm_batch_tune(lbm_batch *b, int flags, lbm_batch_tuning *chosen);
+/* The current setting (us_* and cached zero). */
+lbm_status lbm_batch_settings(const lbm_batch *b, lbm_batch_tuning *now);
 /* Set the workgroup shape directly (1, 2, 4 or 8 waves; 4 at creation);
  * rebuilds the work list, synchronous. */
 lbm_status lbm_batch_set_shape(lbm_batch *b, int waves_per_group);
 /* Largest state (both buffers of every member) of one group, in bytes; a
  * member larger than that forms a group of its own; 0 puts every member in
- * one group (all members advance step by step together).  Rewrites the work
- * list; synchronous.  Results do not depend on the grouping. */
+ * one group (all members advance step by step together).  Regroups the
+ * members in slot order and rewrites the work list; synchronous.  Results do
+ * not depend on the grouping. */
 lbm_status lbm_batch_set_group_bytes(lbm_batch *b, size_t bytes);
 lbm_status lbm_batch_groups(const lbm_batch *b, int *ngroups);
 /* Number of streams (1..4) the groups are dealt to; results do not depend

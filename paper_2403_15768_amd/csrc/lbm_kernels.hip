@@ -725,17 +725,19 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
                              xi);
 }
 
-// per-item partial sums of (j_x, rho - rho0); one wave per item
+// per-item partial sums of (j_x, rho - rho0) of items [first, first + count);
+// one wave per item, partials at the item's index
 template <class L, typename S, typename W, bool BOUZ>
 __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restrict__ md,
                                                        const WorkItem* __restrict__ items,
                                                        const int32_t* __restrict__ cols,
-                                                       int64_t nitems,
+                                                       int64_t first, int64_t count,
                                                        const int64_t* __restrict__ bstep,
                                                        double* __restrict__ partials) {
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t it = (int64_t)blockIdx.x * 4 + wv;
-  if (it >= nitems) return;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wv;
+  if (j >= count) return;
+  const int64_t it = first + j;
   const WorkItem item = items[it];
   if (item.member < 0) return;  // empty items are in no member's reduction
   const MemberDesc& d = md[item.member];
@@ -767,15 +769,18 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
   }
 }
 
-// one block per member: its items' partials in the member-sorted order
+// one block per member slot m: the partials of its items, listed in
+// order[mstart[m] .. mstart[m] + mcount[m]) (a free slot has none: zeros)
 __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__ partials,
                                                       const int32_t* __restrict__ order,
                                                       const int64_t* __restrict__ mstart,
+                                                      const int64_t* __restrict__ mcount,
                                                       double* __restrict__ out) {
   __shared__ double red[2][256];
   const int m = blockIdx.x;
   double t0 = 0, t1 = 0;
-  for (int64_t k = mstart[m] + threadIdx.x; k < mstart[m + 1]; k += 256) {
+  const int64_t k0 = mstart[m], k1 = mstart[m] + mcount[m];
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
     const int64_t it = order[k];
     t0 += partials[2 * it];
     t1 += partials[2 * it + 1];
@@ -835,32 +840,37 @@ const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th) {
 
 template <class L, typename S, typename W>
 static hipError_t batch_moments_t(const MemberDesc* md, const WorkItem* items, const int32_t* cols,
-                                  int64_t nitems, const int64_t* bstep, double* partials,
-                                  bool bouz, hipStream_t st) {
-  const dim3 grid((unsigned)((nitems + 3) / 4)), block(256);
+                                  int64_t first, int64_t count, const int64_t* bstep,
+                                  double* partials, bool bouz, hipStream_t st) {
+  const dim3 grid((unsigned)((count + 3) / 4)), block(256);
   if (bouz)
     hipLaunchKernelGGL((k_batch_moments<L, S, W, true>), grid, block, 0, st, md, items, cols,
-                       nitems, bstep, partials);
+                       first, count, bstep, partials);
   else
     hipLaunchKernelGGL((k_batch_moments<L, S, W, false>), grid, block, 0, st, md, items, cols,
-                       nitems, bstep, partials);
+                       first, count, bstep, partials);
   return hipGetLastError();
 }
 hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,
-                                const int32_t* cols, int64_t nitems, const int64_t* bstep,
-                                double* partials, const int32_t* order, const int64_t* mstart,
-                                int nmembers, double* out, bool bouz, hipStream_t st) {
-  hipError_t e;
-#define BM(L, S, W) batch_moments_t<L, S, W>(md, items, cols, nitems, bstep, partials, bouz, st)
+                                const int32_t* cols, int64_t first, int64_t count,
+                                const int64_t* bstep, double* partials, bool bouz,
+                                hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if ((count + 3) / 4 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+#define BM(L, S, W) \
+  batch_moments_t<L, S, W>(md, items, cols, first, count, bstep, partials, bouz, st)
   if (q == 9)
-    e = prec == 0 ? BM(D2Q9, double, double) : prec == 1 ? BM(D2Q9, float, double)
-                                              : BM(D2Q9, _Float16, float);
-  else
-    e = prec == 0 ? BM(D3Q19, double, double) : prec == 1 ? BM(D3Q19, float, double)
-                                               : BM(D3Q19, _Float16, float);
+    return prec == 0 ? BM(D2Q9, double, double) : prec == 1 ? BM(D2Q9, float, double)
+                                                 : BM(D2Q9, _Float16, float);
+  return prec == 0 ? BM(D3Q19, double, double) : prec == 1 ? BM(D3Q19, float, double)
+                                                : BM(D3Q19, _Float16, float);
 #undef BM
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_reduce, dim3(nmembers), dim3(256), 0, st, partials, order, mstart, out);
+}
+hipError_t launch_batch_reduce(const double* partials, const int32_t* order, const int64_t* mstart,
+                               const int64_t* mcount, int nslots, double* out, hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_reduce, dim3(nslots), dim3(256), 0, st, partials, order, mstart,
+                     mcount, out);
   return hipGetLastError();
 }
 

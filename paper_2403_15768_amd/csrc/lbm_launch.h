@@ -73,10 +73,15 @@ hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* o
 const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th);  // th: noise form
 // k_batch_step(const MemberDesc*, const WorkItem*, const int32_t* cols, int64_t first,
 //              int64_t nwall, int64_t last, const int64_t* bstep, int64_t step_off, int wpb)
+// per-item partials of the flux and mass of items [first, first + count)
 hipError_t launch_batch_moments(int q, int prec, const MemberDesc* md, const WorkItem* items,
-                                const int32_t* cols, int64_t nitems, const int64_t* bstep,
-                                double* partials, const int32_t* order, const int64_t* mstart,
-                                int nmembers, double* out, bool bouz, hipStream_t st);
+                                const int32_t* cols, int64_t first, int64_t count,
+                                const int64_t* bstep, double* partials, bool bouz,
+                                hipStream_t st);
+// per member slot m < nslots: out[2m..2m+1] = sum of the partials of the
+// items order[mstart[m] .. mstart[m] + mcount[m])
+hipError_t launch_batch_reduce(const double* partials, const int32_t* order, const int64_t* mstart,
+                               const int64_t* mcount, int nslots, double* out, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st);
 hipError_t launch_set_r(int prec, const double* lambda, int64_t n, void* r, int* bad,
                         hipStream_t st);

@@ -67,7 +67,9 @@ EXPORTS = [
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
     "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure", "lbm_set_phonons",
     "lbm_get_phonons", "lbm_step_checked", "lbm_checked_invariants",
-    "lbm_friction_quadrature_static",
+    "lbm_friction_quadrature_static", "lbm_batch_member_cost", "lbm_batch_spec_footprint",
+    "lbm_batch_create_spec", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
+    "lbm_batch_settings",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -131,7 +133,14 @@ def load() -> C.CDLL:
         "lbm_batch_items": [vp, C.POINTER(i64)],
         "lbm_batch_step": [vp, i64],
         "lbm_batch_invariants": [vp, dp],
-        "lbm_batch_tune": [vp, C.POINTER(C.c_int)],
+        "lbm_batch_tune": [vp, C.c_int, vp],
+        "lbm_batch_settings": [vp, vp],
+        "lbm_batch_member_cost": [vp, C.POINTER(i64), C.POINTER(i64)],
+        "lbm_batch_spec_footprint": [vp, C.POINTER(sz)],
+        "lbm_batch_create_spec": [vp, vp, sz, vp, C.POINTER(vp)],
+        "lbm_batch_add": [vp, vp, C.POINTER(C.c_int)],
+        "lbm_batch_remove": [vp, vp],
+        "lbm_batch_size": [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
         "lbm_batch_set_shape": [vp, C.c_int],
         "lbm_batch_set_group_bytes": [vp, sz],
         "lbm_batch_groups": [vp, C.POINTER(C.c_int)],
@@ -464,8 +473,37 @@ class Channel:
                                          int(step)), "lbm_set_state")
 
 
+class BatchSpec(C.Structure):
+    _fields_ = [("lattice", C.c_int), ("precision", C.c_int), ("tube", C.c_int),
+                ("noise", C.c_int), ("max_members", C.c_int), ("max_items", C.c_int64),
+                ("max_columns", C.c_int64)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("waves_per_group", C.c_int), ("group_bytes", C.c_size_t), ("streams", C.c_int),
+                ("us_per_step", C.c_double), ("us_per_step_default", C.c_double),
+                ("cached", C.c_int), ("repacks", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def member_cost(ch: "Channel"):
+    """(work items, fluid columns) a channel takes up in a batch."""
+    items, cols = C.c_int64(), C.c_int64()
+    rc = load().lbm_batch_member_cost(ch._h, C.byref(items), C.byref(cols))
+    if rc != 0:
+        raise LBMError(rc, "lbm_batch_member_cost")
+    return int(items.value), int(cols.value)
+
+
 class Batch:
-    """Many channels advanced by one kernel launch per step (lbm_batch_*)."""
+    """Many channels advanced by one kernel launch per step (lbm_batch_*).
+
+    ``Batch(channels)`` holds exactly those channels; ``Batch.empty(...)``
+    makes a batch of a given capacity that channels join (``add``) and leave
+    (``remove``) while it runs.  ``channels`` lists the members by slot
+    (None for a free slot)."""
 
     def __init__(self, channels, stream=None, tune: bool = False):
         import torch
@@ -474,7 +512,6 @@ class Batch:
         self.channels = list(channels)
         n = len(self.channels)
         arr = (C.c_void_p * n)(*[ch._h.value for ch in self.channels])
-        self._arr = arr
         nb = C.c_size_t()
         rc = self._lib.lbm_batch_footprint(arr, n, C.byref(nb))
         if rc != 0:
@@ -489,8 +526,39 @@ class Batch:
             raise LBMError(rc, "lbm_batch_create failed")
         self._h = h
         self.shape = None
+        self.tuning = None
         if tune:
             self.tune()
+
+    @classmethod
+    def empty(cls, lattice: int, precision, tube: bool, max_members: int, max_items: int,
+              max_columns: int, noise: int = 0, stream=None, device: str = "cuda") -> "Batch":
+        """An empty batch of this kind and capacity (see lbm_batch_create_spec)."""
+        import torch
+
+        self = cls.__new__(cls)
+        self._lib = load()
+        sp = BatchSpec()
+        sp.lattice, sp.tube, sp.noise = int(lattice), int(bool(tube)), int(noise)
+        sp.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        sp.max_members, sp.max_items, sp.max_columns = int(max_members), int(max_items), int(max_columns)
+        nb = C.c_size_t()
+        rc = self._lib.lbm_batch_spec_footprint(C.byref(sp), C.byref(nb))
+        if rc != 0:
+            raise LBMError(rc, "lbm_batch_spec_footprint rejected the capacity")
+        self.arena = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=torch.device(device))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        h = C.c_void_p()
+        rc = self._lib.lbm_batch_create_spec(C.byref(sp), C.c_void_p(self.arena.data_ptr()),
+                                             nb.value, C.c_void_p(self.stream.cuda_stream),
+                                             C.byref(h))
+        if rc != 0:
+            raise LBMError(rc, "lbm_batch_create_spec failed")
+        self._h = h
+        self.channels = []
+        self.shape = None
+        self.tuning = None
+        return self
 
     def close(self) -> None:
         """Destroy the batch (members untouched) and release its arena."""
@@ -508,6 +576,30 @@ class Batch:
         if rc != 0:
             raise LBMError(rc, f"{what}: {self._lib.lbm_batch_last_error(self._h).decode()}")
 
+    def add(self, ch: "Channel") -> int:
+        """Channel ch joins at its current step; returns its slot."""
+        s = C.c_int()
+        self._ck(self._lib.lbm_batch_add(self._h, ch._h, C.byref(s)), "lbm_batch_add")
+        k = int(s.value)
+        while len(self.channels) <= k:
+            self.channels.append(None)
+        self.channels[k] = ch
+        return k
+
+    def remove(self, ch: "Channel") -> None:
+        """Channel ch leaves after the queued steps; it stays usable alone."""
+        self._ck(self._lib.lbm_batch_remove(self._h, ch._h), "lbm_batch_remove")
+        k = self.channels.index(ch)
+        self.channels[k] = None
+        while self.channels and self.channels[-1] is None:
+            self.channels.pop()
+
+    @property
+    def members(self) -> int:
+        n = C.c_int()
+        self._ck(self._lib.lbm_batch_size(self._h, C.byref(n), None), "lbm_batch_size")
+        return int(n.value)
+
     @property
     def items(self) -> int:
         n = C.c_int64()
@@ -518,20 +610,32 @@ class Batch:
         self._ck(self._lib.lbm_batch_step(self._h, int(n)), "lbm_batch_step")
 
     def invariants(self, raise_on_divergence: bool = True) -> np.ndarray:
-        """(n, 3): flux, mass, mass deviation per member.  With
-        raise_on_divergence=False a member whose flux or mass is not finite
-        shows up as NaN/Inf in its row instead of raising."""
-        out = np.zeros(3 * len(self.channels))
+        """(slots, 3): flux, mass, mass deviation per slot (NaN rows for free
+        slots).  With raise_on_divergence=False a member whose flux or mass is
+        not finite shows up as NaN/Inf in its row instead of raising."""
+        ns = C.c_int()
+        self._ck(self._lib.lbm_batch_size(self._h, None, C.byref(ns)), "lbm_batch_size")
+        out = np.zeros(3 * max(int(ns.value), 1))
         rc = self._lib.lbm_batch_invariants(self._h, _dptr(out))
         if rc != 0 and not (rc == -5 and not raise_on_divergence):
             self._ck(rc, "lbm_batch_invariants")
-        return out.reshape(-1, 3)
+        return out[: 3 * int(ns.value)].reshape(-1, 3)
 
-    def tune(self) -> int:
-        w = C.c_int()
-        self._ck(self._lib.lbm_batch_tune(self._h, C.byref(w)), "lbm_batch_tune")
-        self.shape = int(w.value)
+    def tune(self, retime: bool = False) -> int:
+        """Autotune workgroup shape, group size and streams (cached per kind
+        and size of batch); returns the workgroup shape, the full choice in
+        ``self.tuning``."""
+        t = Tuning()
+        self._ck(self._lib.lbm_batch_tune(self._h, 1 if retime else 0, C.byref(t)),
+                 "lbm_batch_tune")
+        self.tuning = t.as_dict()
+        self.shape = int(t.waves_per_group)
         return self.shape
+
+    def settings(self) -> dict:
+        t = Tuning()
+        self._ck(self._lib.lbm_batch_settings(self._h, C.byref(t)), "lbm_batch_settings")
+        return t.as_dict()
 
     def set_shape(self, waves_per_group: int) -> None:
         self._ck(self._lib.lbm_batch_set_shape(self._h, int(waves_per_group)), "lbm_batch_set_shape")

@@ -5,20 +5,27 @@ pressure-gradient force and the spectral parameters of its wall friction
 (paper Sec. 5.1: permeability of carbon nanotubes against diameter and
 charge-carrier density).  The server
 
-* admits arrived queries while their device footprint fits the HBM budget
-  (each admitted query owns a context whose state stays resident on the GPU);
+* admits arrived queries, first come first served, while their device
+  footprint fits the HBM budget (each admitted query owns a context whose
+  state stays resident on the GPU);
 * computes each query's wall friction with the GPU quadrature once;
-* advances every active query together through one batch (one kernel launch
-  per step, graph-replayed) in chunks of ``check_every`` steps;
-* retires a query when its flux changes by less than ``rel_tol`` relative over
-  ``check_every`` steps of its own step counter, and frees its memory.
+* advances every active query in rounds of 64 steps (one graph replay per
+  group of a batch), and between rounds lets queries join and leave the
+  running batch (lbm_batch_add / lbm_batch_remove: only the groups they
+  touch get new work lists, the batch itself is never rebuilt);
+* checks each query on its own step counter every ``check_every`` steps (a
+  multiple of 64) and retires it when its flux changed by less than
+  ``rel_tol`` relative over that interval, freeing its memory.
 
 ``mode="f32"`` runs every query in FP32 storage (FP64 arithmetic).
 ``mode="mixed"`` runs a query first with half-precision storage (FP32
 arithmetic) until its flux change per check falls below ``switch_tol`` or
 stops shrinking, then hands its state to an FP32 context
-(``lbm_transfer_state``) which converges to the same ``rel_tol``: both modes
-end at the same accuracy.
+(``lbm_transfer_state``) which joins the FP32 batch and converges to the same
+``rel_tol``: both modes end at the same accuracy.
+
+A query's trajectory depends only on its own parameters and step counter,
+so its result is the same alone and in any mix, bit for bit.
 
 Scheduling, admission and bookkeeping are host logic here; every numerical
 step runs in the library's kernels.
@@ -68,7 +75,6 @@ class _Slot:
     prev_q: float | None = None
     prev_rel: float | None = None
     steps_half: int = 0
-    uid: int = 0  # serial number of the context currently serving the query
 
 
 def tube_params(q: inputs.Query):
@@ -122,12 +128,17 @@ def open_channel(q, precision: str, kind=TubeQueries) -> lbm.Channel:
     return ch
 
 
+ROUND = 64  # steps per round: one graph replay per batch group
+
+
 class Server:
-    def __init__(self, mode: str = "f32", hbm_budget: int = 32 << 30, check_every: int = 1000,
+    def __init__(self, mode: str = "f32", hbm_budget: int = 32 << 30, check_every: int = 1024,
                  rel_tol: float = 1e-8, switch_tol: float = 1e-5, max_steps: int = 500_000,
                  tune: bool = True, realtime: bool = True, log=None, kind=TubeQueries,
-                 keep_fields: bool = False):
+                 keep_fields: bool = False, max_members: int = 2048):
         assert mode in ("f32", "mixed")
+        if check_every % ROUND:
+            raise ValueError(f"check_every must be a multiple of {ROUND}")
         self.kind = kind
         self.mode = mode
         self.budget = int(hbm_budget)
@@ -139,9 +150,11 @@ class Server:
         self.realtime = realtime
         self.log = log
         self.keep_fields = keep_fields
+        self.max_members = int(max_members)
         self.shape = None  # workgroup shape chosen by the autotuner
-        self._serial = 0
-        self.stats = {"batch_rebuilds": 0, "chunks": 0, "max_active": 0, "lattice_updates": 0}
+        self.tuning = {}   # per phase: the autotuner's choice
+        self.stats = {"batch_rebuilds": 0, "rounds": 0, "joins": 0, "leaves": 0,
+                      "max_active": 0, "lattice_updates": 0, "batch_bytes": 0}
 
     # ------------------------------------------------------------- helpers
     def _say(self, *a):
@@ -162,25 +175,98 @@ class Server:
     def _admit(self, q, now) -> _Slot:
         ch = self._open(q, "f16s" if self.mode == "mixed" else "f32")
         self.kind.set_friction(ch, q)
-        self._serial += 1
         return _Slot(query=q, ch=ch, phase="half" if self.mode == "mixed" else "f32",
-                     admitted_s=now, reserved=self._reserve(q), uid=self._serial)
+                     admitted_s=now, reserved=self._reserve(q))
+
+    # the batches: one per phase, of a capacity for what the budget can hold
+    def _capacity(self, phase: str, need_items: int = 0, need_cols: int = 0) -> dict:
+        bytes_per_cell = 2 * 19 * (2 if phase == "half" else 4)
+        cells = self.budget // bytes_per_cell
+        return dict(max_members=self.max_members,
+                    max_items=max(2 * need_items, cells // 24 + 4096),
+                    max_columns=max(2 * need_cols, cells // 32 + 1024))
+
+    def _join(self, phase: str, s: _Slot) -> None:
+        b = self._batches.get(phase)
+        it, co = lbm.member_cost(s.ch)
+        load = self._load.setdefault(phase, [0, 0])
+        if b is not None and (load[0] + it > b.cap["max_items"] or
+                              load[1] + co > b.cap["max_columns"]):
+            # out of room (more than the budget estimate held): a bigger batch
+            # takes the members over
+            members = [c for c in b.channels if c is not None]
+            cap = self._capacity(phase, load[0] + it, load[1] + co)
+            nb = self._new_batch(phase, cap)
+            for c in members:
+                b.remove(c)
+                nb.add(c)
+            self._drop_batch(b)
+            self.stats["batch_rebuilds"] += 1
+            b = nb
+        if b is None:
+            b = self._new_batch(phase, self._capacity(phase))
+        b.add(s.ch)
+        load[0] += it
+        load[1] += co
+        self.stats["joins"] += 1
+
+    def _leave(self, phase: str, s: _Slot) -> None:
+        b = self._batches[phase]
+        b.remove(s.ch)
+        it, co = lbm.member_cost(s.ch)
+        self._load[phase][0] -= it
+        self._load[phase][1] -= co
+        self.stats["leaves"] += 1
+
+    def _new_batch(self, phase: str, cap: dict) -> lbm.Batch:
+        prec = "f16s" if phase == "half" else "f32"
+        kw = self.kind.params(self._any_query)
+        b = lbm.Batch.empty(kw["lattice"], prec, kw["geometry"] == lbm.TUBE, **cap)
+        b.cap = cap
+        b.tuned = False
+        self._batches[phase] = b
+        self._batch_bytes += b.arena.numel()
+        self.stats["batch_bytes"] = max(self.stats["batch_bytes"], self._batch_bytes)
+        return b
+
+    def _drop_batch(self, b) -> None:
+        self._batch_bytes -= b.arena.numel()
+        b.close()
 
     def _hand_off(self, s: _Slot) -> None:
+        self._leave("half", s)
         f32 = self._open(s.query, "f32")
         f32.transfer_from(s.ch)
         s.ch.close()
         s.ch = f32
         s.phase = "f32"
         s.steps_half = f32.step_count
-        self._serial += 1
-        s.uid = self._serial
+        self._join("f32", s)
+
+    def _maybe_tune(self, phase: str, b: lbm.Batch, waiting: int) -> None:
+        # once per phase, when the batch holds a representative mix (or all
+        # that will come at once)
+        if not self.tune or b.tuned or (b.members < 4 and waiting):
+            return
+        b.tune()
+        b.tuned = True
+        self.tuning[phase] = b.tuning
+        if phase == ("half" if self.mode == "mixed" else "f32"):
+            self.shape = b.shape
 
     # ------------------------------------------------------------- the loop
-    def run(self, trace: list[inputs.Query]) -> list[Result]:
+    def run(self, trace: list) -> list[Result]:
+        import torch
+
         trace = sorted(trace, key=lambda q: getattr(q, "arrival_s", 0.0))
         if not self.realtime:  # saturation: every query is there at t = 0
             trace = [dataclasses.replace(q, arrival_s=0.0) for q in trace]
+        if not trace:
+            return []
+        self._any_query = trace[0]
+        self._batches: dict = {}
+        self._load: dict = {}
+        self._batch_bytes = 0
         clock = time.perf_counter
         t0 = clock()
         now = lambda: clock() - t0
@@ -189,19 +275,23 @@ class Server:
         active: list[_Slot] = []
         used = 0
         results: list[Result] = []
-        batches: dict = {}
-        members: dict = {}
+        # at most two rounds queued ahead of the GPU, so that a query joins
+        # within a round or two of its admission
+        events = [None, None]
         while i < n or waiting or active:
             t = now()
             while i < n and getattr(trace[i], "arrival_s", 0.0) <= t:
                 waiting.append(trace[i])
                 i += 1
-            # admission by device footprint, first come first served
-            while waiting and used + self._reserve(waiting[0]) <= self.budget:
+            # admission by device footprint (the batches' own arenas counted),
+            # first come first served
+            while waiting and (used + self._batch_bytes + self._reserve(waiting[0])
+                               <= self.budget):
                 q = waiting.popleft()
                 s = self._admit(q, now())
                 used += s.reserved
                 active.append(s)
+                self._join(s.phase, s)
             if waiting and not active:
                 raise RuntimeError(f"query {waiting[0].qid} does not fit the HBM budget")
             if not active:
@@ -209,60 +299,50 @@ class Server:
                     time.sleep(max(0.0, min(0.05, trace[i].arrival_s - now())))
                 continue
             self.stats["max_active"] = max(self.stats["max_active"], len(active))
-            # one chunk of check_every steps for every active query, per phase
-            stepped: dict = {}
-            for phase in ("half", "f32"):
-                group = [s for s in active if s.phase == phase]
-                stepped[phase] = group
-                if not group:
-                    batches.pop(phase, None)
-                    members.pop(phase, None)
-                    continue
-                ids = [s.uid for s in group]
-                if members.get(phase) != ids:
-                    old = batches.pop(phase, None)
-                    if old is not None:
-                        old.close()
-                    b = lbm.Batch([s.ch for s in group])
-                    if self.shape is None and self.tune:
-                        self.shape = b.tune()
-                    elif self.shape is not None:
-                        b.set_shape(self.shape)
-                    batches[phase], members[phase] = b, ids
-                    self.stats["batch_rebuilds"] += 1
-                batches[phase].step(self.check_every)
-                self.stats["lattice_updates"] += self.check_every * sum(s.ch.fluid_count for s in group)
-            self.stats["chunks"] += 1
-            # convergence on each query's own step counter
+            # one round for every active query
+            for phase, b in self._batches.items():
+                if b.members:
+                    self._maybe_tune(phase, b, len(waiting) + (n - i))
+                    b.step(ROUND)
+            self.stats["rounds"] += 1
+            self.stats["lattice_updates"] += ROUND * sum(s.ch.fluid_count for s in active)
+            ev = torch.cuda.Event()
+            ev.record()
+            if events[0] is not None:
+                events[0].synchronize()
+            events = [events[1], ev]
+            # checks, on each query's own step counter
+            due = [s for s in active if s.ch.step_count % self.check_every == 0]
+            if not due:
+                continue
             retire: list[tuple[_Slot, str, float]] = []
-            for phase in ("half", "f32"):
-                group = stepped[phase]  # as stepped: hand-offs below move slots to "f32"
-                if not group:
+            for s in due:
+                try:
+                    q = s.ch.invariants()[0]
+                except lbm.LBMError:
+                    q = math.nan
+                steps = s.ch.step_count
+                if not math.isfinite(q):
+                    retire.append((s, "diverged", q))
                     continue
-                inv = batches[phase].invariants(raise_on_divergence=False)
-                for k, s in enumerate(group):
-                    q = float(inv[k, 0])
-                    steps = s.ch.step_count
-                    if not math.isfinite(q):
-                        retire.append((s, "diverged", q))
-                        continue
-                    rel = abs(q - s.prev_q) / abs(q) if s.prev_q is not None and q != 0 else math.inf
-                    if phase == "f32" and rel < self.rel_tol:
-                        retire.append((s, "ok", q))
-                    elif steps >= self.max_steps:
-                        retire.append((s, "not_converged", q))
-                    elif phase == "half" and (rel < self.switch_tol or (
-                            rel < 1e-4 and s.prev_rel is not None and rel > 0.7 * s.prev_rel)):
-                        s.prev_rel = rel
-                        s.prev_q = q
-                        self._hand_off(s)
-                        continue
+                rel = abs(q - s.prev_q) / abs(q) if s.prev_q is not None and q != 0 else math.inf
+                if s.phase == "f32" and rel < self.rel_tol:
+                    retire.append((s, "ok", q))
+                elif steps >= self.max_steps:
+                    retire.append((s, "not_converged", q))
+                elif s.phase == "half" and (rel < self.switch_tol or (
+                        rel < 1e-4 and s.prev_rel is not None and rel > 0.7 * s.prev_rel)):
                     s.prev_rel = rel
                     s.prev_q = q
+                    self._hand_off(s)
+                    continue
+                s.prev_rel = rel
+                s.prev_q = q
             t_done = now()
             for s, status, q in retire:
                 active.remove(s)
                 used -= s.reserved
+                self._leave(s.phase, s)
                 steps = s.ch.step_count
                 results.append(Result(qid=s.query.qid, radius=getattr(s.query, "radius", 0),
                                       tau=s.query.tau,
@@ -274,8 +354,10 @@ class Server:
                 s.ch.close()
                 self._say(f"done q{s.query.qid} steps={steps} "
                           f"half={s.steps_half} t={t_done:.2f}s active={len(active)}")
-        for b in batches.values():
-            b.close()
+        torch.cuda.synchronize()
+        for b in list(self._batches.values()):
+            self._drop_batch(b)
+        self._batches = {}
         return sorted(results, key=lambda r: r.qid)
 
 
@@ -302,7 +384,7 @@ def main(argv=None):
     ap.add_argument("--rmin", type=int, default=8)
     ap.add_argument("--rmax", type=int, default=32)
     ap.add_argument("--nx", type=int, default=512)
-    ap.add_argument("--check-every", type=int, default=1000)
+    ap.add_argument("--check-every", type=int, default=1024)
     ap.add_argument("--out", default=None)
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args(argv)

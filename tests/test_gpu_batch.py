@@ -335,3 +335,119 @@ def test_batch_rejects_mixed_members(lbm):
         lbm.Batch([a, c])
     with pytest.raises(lbm.LBMError):
         lbm.Batch([a, a])
+
+
+# ---------------------------------------------- members joining and leaving
+def capacity_for(lbm, chans, members=None, slack=1):
+    items = cols = 0
+    for ch in chans:
+        i, c = lbm.member_cost(ch)
+        items, cols = items + i, cols + c
+    return dict(max_members=members or len(chans), max_items=slack * items,
+                max_columns=slack * cols)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16s"])
+def test_members_join_and_leave_bit_identical_to_alone(lbm, precision):
+    # members join a running batch at different steps and leave again; each
+    # is bit for bit the channel stepped alone the same number of steps, and
+    # the batch's reductions match each member's own
+    say("batch add / remove", precision)
+    alone = make_ducts(lbm, SPECS, precision)
+    mixed = make_ducts(lbm, SPECS, precision)
+    cap = capacity_for(lbm, mixed, members=4, slack=2)
+    b = lbm.Batch.empty(19, precision, False, **cap)
+    steps = [0] * len(SPECS)
+
+    def run(n, active):
+        b.step(n)
+        for k in active:
+            steps[k] += n
+
+    assert b.add(mixed[0]) == 0
+    assert b.add(mixed[1]) == 1
+    run(70, [0, 1])
+    mixed[2].step(5)  # joins with a history (another buffer parity)
+    steps[2] += 5
+    assert b.add(mixed[2]) == 2
+    run(64, [0, 1, 2])
+    b.remove(mixed[1])  # leaves from the middle: its slot is free again
+    assert b.members == 2 and b.channels[1] is None
+    assert b.add(mixed[3]) == 1
+    assert b.add(mixed[4]) == 3
+    with pytest.raises(lbm.LBMError):
+        b.add(mixed[1])  # four slots, all taken
+    run(131, [0, 2, 3, 4])
+    inv = b.invariants()
+    for k, slot in ((0, 0), (2, 2), (3, 1), (4, 3)):
+        assert abs(inv[slot, 0] / mixed[k].invariants()[0] - 1) < 1e-13
+    b.remove(mixed[0])
+    mixed[1].step(3)  # stepped alone meanwhile, then back in
+    steps[1] += 3
+    assert b.add(mixed[1]) == 0
+    run(64, [1, 2, 3, 4])
+    for a, m, n in zip(alone, mixed, steps):
+        a.step(n)
+        assert m.step_count == a.step_count == n
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    with pytest.raises(lbm.LBMError):
+        b.remove(mixed[0])  # not a member any more
+    with pytest.raises(lbm.LBMError):
+        b.add(mixed[2])  # a member already
+    b.close()
+
+
+def test_join_and_leave_across_groups_and_repacks(lbm):
+    # small groups (one member each) and a work list with little room: joins
+    # and leaves move groups to fresh regions and repack the list; results
+    # stay bit for bit those of the channels alone
+    say("batch groups + repack")
+    specs = SPECS * 2
+    alone = make_ducts(lbm, specs, "f32")
+    mixed = make_ducts(lbm, specs, "f32")
+    cap = capacity_for(lbm, mixed)
+    b = lbm.Batch.empty(19, "f32", False, **cap)
+    b.set_group_bytes(2 * mixed[0].get_state()[0].nbytes + 1)
+    for ch in mixed[:6]:
+        b.add(ch)
+    b.step(64)
+    for k in (1, 4):
+        b.remove(mixed[k])
+    for ch in mixed[6:]:
+        b.add(ch)
+    b.step(65)
+    b.add(mixed[1])
+    b.step(64)
+    assert b.settings()["repacks"] >= 1
+    n = {0: 193, 2: 193, 3: 193, 5: 193, 4: 64, 1: 128, 6: 129, 7: 129, 8: 129, 9: 129}
+    for k, (a, m) in enumerate(zip(alone, mixed)):
+        a.step(n[k])
+        assert np.array_equal(a.get_state()[0], m.get_state()[0]), k
+    b.close()
+
+
+def test_tuning_is_cached_and_never_changes_results(lbm):
+    say("batch autotuner")
+    alone = make_ducts(lbm, SPECS, "f32")
+    mixed = make_ducts(lbm, SPECS, "f32")
+    b = lbm.Batch(mixed)
+    b.tune(retime=True)
+    t = b.tuning
+    assert t["waves_per_group"] in (2, 4, 8) and t["streams"] in (1, 2, 3)
+    assert t["us_per_step"] > 0 and t["us_per_step"] <= t["us_per_step_default"] * 1.05
+    assert t["cached"] == 0
+    b.step(100)
+    for a in alone:
+        a.step(100)
+    for a, m in zip(alone, mixed):
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    # the same kind and size of batch: the cached choice, no timing
+    again = make_ducts(lbm, SPECS, "f32")
+    b2 = lbm.Batch(again)
+    b2.tune()
+    assert b2.tuning["cached"] == 1
+    s = b2.settings()
+    assert (s["waves_per_group"], s["group_bytes"], s["streams"]) == \
+        (t["waves_per_group"], t["group_bytes"], t["streams"])
+    b.close()
+    b2.close()

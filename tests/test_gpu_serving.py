@@ -26,11 +26,14 @@ def small_trace(n=6):
 
 def test_each_result_same_alone_and_in_the_mix(serve):
     trace = small_trace()
-    srv = serve.Server(mode="f32", hbm_budget=8 << 30, check_every=500, realtime=False, tune=False)
+    srv = serve.Server(mode="f32", hbm_budget=8 << 30, check_every=512, realtime=False, tune=False)
     mix = {r.qid: r for r in srv.run(trace)}
     assert all(r.status == "ok" for r in mix.values())
+    # queries joined and left the running batch: it was never rebuilt
+    assert srv.stats["batch_rebuilds"] == 0
+    assert srv.stats["joins"] == srv.stats["leaves"] == len(trace)
     for q in trace[:3]:
-        alone = serve.Server(mode="f32", hbm_budget=8 << 30, check_every=500, realtime=False,
+        alone = serve.Server(mode="f32", hbm_budget=8 << 30, check_every=512, realtime=False,
                              tune=False).run([q])[0]
         assert alone.steps == mix[q.qid].steps
         assert alone.flux == mix[q.qid].flux  # bit for bit
@@ -38,15 +41,17 @@ def test_each_result_same_alone_and_in_the_mix(serve):
 
 def test_mixed_precision_reaches_the_same_flux(serve):
     trace = small_trace()
-    f32 = {r.qid: r for r in serve.Server(mode="f32", hbm_budget=8 << 30, check_every=500,
+    f32 = {r.qid: r for r in serve.Server(mode="f32", hbm_budget=8 << 30, check_every=512,
                                           realtime=False, tune=False).run(trace)}
-    mixed = serve.Server(mode="mixed", hbm_budget=8 << 30, check_every=500, realtime=False, tune=False)
+    mixed = serve.Server(mode="mixed", hbm_budget=8 << 30, check_every=512, realtime=False, tune=False)
     res = mixed.run(trace)
+    assert mixed.stats["batch_rebuilds"] == 0
+    assert mixed.stats["joins"] == 2 * len(trace)  # the half batch, then the FP32 one
     for r in res:
         assert r.status == "ok" and r.steps_half > 0
         assert abs(r.flux / f32[r.qid].flux - 1) < 1e-5, (r.qid, r.flux, f32[r.qid].flux)
     # same query alone in mixed mode: same result
-    alone = serve.Server(mode="mixed", hbm_budget=8 << 30, check_every=500, realtime=False,
+    alone = serve.Server(mode="mixed", hbm_budget=8 << 30, check_every=512, realtime=False,
                          tune=False).run([trace[2]])[0]
     mixed_map = {r.qid: r for r in res}
     assert alone.flux == mixed_map[trace[2].qid].flux and alone.steps == mixed_map[trace[2].qid].steps
@@ -55,7 +60,7 @@ def test_mixed_precision_reaches_the_same_flux(serve):
 def test_admission_respects_the_budget(serve):
     trace = small_trace(5)
     one = max(serve.footprint(q, "f32") for q in trace)
-    srv = serve.Server(mode="f32", hbm_budget=2 * one + 1, check_every=500, realtime=False, tune=True)
+    srv = serve.Server(mode="f32", hbm_budget=2 * one + 1, check_every=512, realtime=False, tune=True)
     res = srv.run(trace)
     assert srv.stats["max_active"] <= 2
     assert all(r.status == "ok" for r in res) and len(res) == 5
@@ -64,7 +69,7 @@ def test_admission_respects_the_budget(serve):
 
 def test_realtime_trace_latencies(serve):
     trace = small_trace(4)
-    srv = serve.Server(mode="f32", hbm_budget=8 << 30, check_every=500, realtime=True, tune=False)
+    srv = serve.Server(mode="f32", hbm_budget=8 << 30, check_every=512, realtime=True, tune=False)
     res = srv.run(trace)
     s = serve.summarize(res, 0.0)
     assert s["converged"] == 4 and s["p99_latency_s"] >= s["p50_latency_s"] > 0
@@ -98,7 +103,7 @@ def test_served_result_matches_the_oracle(serve, mode):
     # to FP32) against the oracle stepped the query's own number of steps:
     # flux and axial velocity field within the FP32 bar, 1e-5
     trace = inputs.serving_trace(4, rate_per_s=200.0, nx=32, radius_range=(3, 4))
-    srv = serve.Server(mode=mode, hbm_budget=8 << 30, check_every=500, realtime=False,
+    srv = serve.Server(mode=mode, hbm_budget=8 << 30, check_every=512, realtime=False,
                        tune=False, keep_fields=True)
     res = {r.qid: r for r in srv.run(trace)}
     q = trace[1]
