@@ -334,10 +334,15 @@ def batch_throughput(args, specs):
         fluxes[prec] = inv[:, 0].copy()
         fields[prec] = [ch.field(1) for ch in chs]
         bpu = BYTES_PER_UPDATE[prec]
+        t = b.tuning
         out[prec] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1),
                      "us_per_step": round(ms * 1e3 / n, 2),
                      "hbm_frac": round(bpu * cells * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "workgroup_items": shape, "groups": b.groups}
+                     "groups": b.groups,
+                     "tuned": {"waves_per_group": shape, "group_mib": t["group_bytes"] >> 20,
+                               "streams": t["streams"], "us_per_step": round(t["us_per_step"], 2),
+                               "us_per_step_default_setting":
+                                   round(t["us_per_step_default"], 2)}}
         b.close()
         for ch in chs:
             ch.close()
@@ -371,6 +376,13 @@ def batch_steady(specs, modes=("f32", "mixed")):
         sm["lattice_updates"] = srv.stats["lattice_updates"]
         sm["glups"] = round(srv.stats["lattice_updates"] / wall / 1e9, 2)
         sm["batch_rebuilds"] = srv.stats["batch_rebuilds"]
+        sm["joins"] = srv.stats["joins"]
+        sm["rounds"] = srv.stats["rounds"]
+        sm["host_wait_s"] = round(srv.stats["host_wait_s"], 3)
+        sm["check_s"] = round(srv.stats["check_s"], 3)
+        sm["tuning"] = {k: {"waves_per_group": v["waves_per_group"],
+                            "group_mib": v["group_bytes"] >> 20, "streams": v["streams"]}
+                        for k, v in srv.tuning.items()}
         out[mode] = sm
         flux[mode] = {r.qid: r.flux for r in res}
     if "f32" in flux and "mixed" in flux:
@@ -389,7 +401,8 @@ def batch_workload(args):
     specs = inputs.batch_channels(256)
     out = {"workload": "batch_256_ducts" + ("", "_thermal_stress", "_thermal_all")[args.thermal],
            "channels": len(specs), "cells": sum(c.nx * c.ny * c.nz for c in specs)}
-    out.update(batch_throughput(args, specs))
+    if args.batch_precisions:
+        out.update(batch_throughput(args, specs))
     if not args.no_steady:
         out["steady"] = batch_steady(specs)
     print(json.dumps(out), flush=True)
@@ -411,6 +424,7 @@ def serving_run(trace, modes=("f32", "mixed"), budget_gb=32.0):
         wall = time.perf_counter() - t0
         sm = serve.summarize(res, wall)
         sm.update(max_active=srv.stats["max_active"], batch_rebuilds=srv.stats["batch_rebuilds"],
+                  joins=srv.stats["joins"], rounds=srv.stats["rounds"],
                   glups=round(srv.stats["lattice_updates"] / wall / 1e9, 2))
         out[mode] = sm
         torch.cuda.empty_cache()

@@ -354,6 +354,15 @@ lbm_status lbm_checked_invariants(lbm_ctx *ctx, double out[3], int64_t *at_step)
  * out[2] = sum_fluid (rho - rho0).  Deterministic FP64 reductions.
  * Synchronous. */
 lbm_status lbm_invariants(lbm_ctx *ctx, double out[3]);
+/* The same invariants, enqueued: host_out[0..2] (flux, mass, mass deviation)
+ * are written when the context's stream reaches this point (the caller
+ * waits for the stream or an event recorded after the call before reading
+ * them; NaN/Inf are not flagged).  host_out: page-locked host memory
+ * (hipHostMalloc or a pinned allocation of the caller's), 3 doubles, owned by
+ * the caller and valid until then; with pageable memory the copy, and the
+ * call, wait for the stream.  Asynchronous: a serving loop checks many
+ * channels without draining the queue once per channel. */
+lbm_status lbm_invariants_async(lbm_ctx *ctx, double *host_out);
 lbm_status lbm_flux(lbm_ctx *ctx, double *q);
 lbm_status lbm_mass(lbm_ctx *ctx, double *m);
 /* which: 0 rho, 1 u_x, 2 u_y, 3 u_z; host_out: nz*ny*nx doubles, 0 on solid

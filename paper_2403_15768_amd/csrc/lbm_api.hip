@@ -357,7 +357,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_lambda = take((size_t)pl.nwall * sizeof(double));
   pl.off_raw = take((size_t)(pl.nwall + 1) * sizeof(double));
   pl.off_partials = take((size_t)pl.nblocks * 2 * sizeof(double));
-  pl.off_out = take(4 * sizeof(double));
+  pl.off_out = take(8 * sizeof(double));
   pl.off_flag = take(4 * sizeof(int));
   pl.off_step = take(sizeof(int64_t));
   // electron lines: rows 0..2 electrons, 3..5 phonons; velocities u_e then u_p
@@ -625,19 +625,23 @@ lbm_status do_steps(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
+// the fixed-order reduction of the per-block partials in the arena; the
+// device out slot then holds (sums, flux, mass, mass deviation)
+lbm_status launch_reduce(lbm_ctx* c) {
+  HIPCHK(c, lbm::launch_reduce_final(c->at<double>(c->pl.off_partials), c->pl.nblocks,
+                                     c->at<double>(c->pl.off_out), c->pl.nx,
+                                     (double)c->pl.nfluid * c->p.rho0, c->stream));
+  return LBM_OK;
+}
+
 // The per-block partials in the arena -> (flux, mass, mass deviation):
 // fixed-order reduction, copy to the host, synchronise.
 lbm_status reduce_partials(lbm_ctx* c, double out[3]) {
-  double* partials = c->at<double>(c->pl.off_partials);
-  double* dout = c->at<double>(c->pl.off_out);
-  HIPCHK(c, lbm::launch_reduce_final(partials, c->pl.nblocks, dout, c->stream));
-  double h[2] = {0, 0};
-  HIPCHK(c, hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, c->stream));
-  lbm_status s = sync(c);
+  lbm_status s = launch_reduce(c);
   if (s != LBM_OK) return s;
-  out[0] = h[0] / c->pl.nx;
-  out[1] = (double)c->pl.nfluid * c->p.rho0 + h[1];
-  out[2] = h[1];
+  HIPCHK(c, hipMemcpyAsync(out, c->at<double>(c->pl.off_out) + 2, 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  if ((s = sync(c)) != LBM_OK) return s;
   if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
     return c->fail(LBM_EDIVERGED, "flux or mass is not finite");
   return LBM_OK;
@@ -1087,6 +1091,17 @@ lbm_status lbm_run_to_steady(lbm_ctx* c, double rel_tol, int64_t check_every, in
     prev = inv[0];
   }
   return c->fail(LBM_ENOTCONV, "no steady state after %lld steps", (long long)taken);
+}
+
+lbm_status lbm_invariants_async(lbm_ctx* c, double* host_out) {
+  if (!c || !host_out) return LBM_EINVAL;
+  c->checked_step = -1;  // the partials are about to hold the current state's
+  lbm_status s = moments_partials(c);
+  if (s == LBM_OK) s = launch_reduce(c);
+  if (s != LBM_OK) return s;
+  HIPCHK(c, hipMemcpyAsync(host_out, c->at<double>(c->pl.off_out) + 2, 3 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  return LBM_OK;
 }
 
 lbm_status lbm_step_checked(lbm_ctx* c, int64_t nsteps) {

@@ -696,21 +696,23 @@ TuneKey tune_key(const lbm_batch* b) {
 }
 
 // Time `reps` steps of every group with the current shape, grouping and
-// stream count: launches whose results land in the buffers the next step
-// overwrites anyway (state and counters unchanged).  Returns microseconds
-// per step.
+// stream count, each group taking kTuneRun steps in a row as it does inside
+// its graph (so that what a group keeps in the last-level cache from one of
+// its steps to the next counts): launches whose results land in the buffers
+// the next step overwrites anyway (state and counters unchanged).  Returns
+// microseconds per step.
+constexpr int kTuneRun = 8;
 lbm_status time_steps(lbm_batch* b, int reps, hipEvent_t e0, hipEvent_t e1, double* us) {
   auto round = [&]() -> lbm_status {
     lbm_status s = fork_streams(b);
     if (s != LBM_OK) return s;
     for (size_t gi = 0; gi < b->groups.size(); gi++)
-      if ((s = launch_batch(b, gi, 0, group_stream(b, gi))) != LBM_OK) return s;
+      for (int j = 0; j < kTuneRun; j++)
+        if ((s = launch_batch(b, gi, 0, group_stream(b, gi))) != LBM_OK) return s;
     return join_streams(b);
   };
-  for (int r = 0; r < 2; r++) {
-    lbm_status s = round();
-    if (s != LBM_OK) return s;
-  }
+  lbm_status s0 = round();  // warm
+  if (s0 != LBM_OK) return s0;
   BCHK(b, hipEventRecord(e0, b->stream));
   for (int r = 0; r < reps; r++) {
     lbm_status s = round();
@@ -720,7 +722,7 @@ lbm_status time_steps(lbm_batch* b, int reps, hipEvent_t e0, hipEvent_t e1, doub
   BCHK(b, hipEventSynchronize(e1));
   float ms = 0;
   BCHK(b, hipEventElapsedTime(&ms, e0, e1));
-  *us = 1e3 * ms / reps;
+  *us = 1e3 * ms / (reps * kTuneRun);
   return LBM_OK;
 }
 
@@ -914,6 +916,22 @@ lbm_status lbm_batch_remove(lbm_batch* b, lbm_ctx* c) {
     return update_groups(b, {});
   }
   b->gof[s] = -1;
+  // a group that lost members merges into another one with room for them,
+  // so that members leaving do not leave many small groups (each a launch
+  // of little work) behind
+  for (size_t gj = 0; gj < b->groups.size(); gj++) {
+    if (gj == gi || !b->group_bytes ||
+        b->groups[gj].bytes + b->groups[gi].bytes > b->group_bytes)
+      continue;
+    lbm_batch::Group& src = b->groups[gi];
+    lbm_batch::Group& dst = b->groups[gj];
+    dst.slots.insert(dst.slots.end(), src.slots.begin(), src.slots.end());
+    dst.bytes += src.bytes;
+    drop_graph(src);
+    b->groups.erase(b->groups.begin() + (long)gi);
+    recompute_gof(b);
+    return update_groups(b, {gj > gi ? gj - 1 : gj});
+  }
   return update_groups(b, {gi});
 }
 
@@ -1066,7 +1084,7 @@ lbm_status lbm_batch_tune(lbm_batch* b, int flags, lbm_batch_tuning* chosen) {
       for (int ns : nst) {
         if ((s = apply_setting(b, w, gb, ns)) != LBM_OK) break;
         double us = 0;
-        if ((s = time_steps(b, 5, e0, e1, &us)) != LBM_OK) break;
+        if ((s = time_steps(b, 2, e0, e1, &us)) != LBM_OK) break;
         if (w == 4 && gb == dflt && ns == 2) at_default = us;
         if (us < best) {
           best = us;

@@ -357,11 +357,13 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
 // Fixed-order FP64 sum of the (j_x, rho - rho0) partials of nblocks blocks:
 // thread t adds blocks t, t + 1024, ... in order (loads unrolled so that
 // several are in flight), then a fixed butterfly in each wave and the 16
-// waves in order.
+// waves in order.  out: the two sums, then the invariants they give, flux
+// = sum j_x / nx, mass = nfluid rho0 + sum (rho - rho0), mass deviation.
 constexpr int kReduceThreads = 1024;
 __global__ void __launch_bounds__(kReduceThreads) k_reduce_final(const double* __restrict__ partials,
                                                                  int64_t nblocks,
-                                                                 double* __restrict__ out) {
+                                                                 double* __restrict__ out, int nx,
+                                                                 double mass0) {
   __shared__ double red[2][kReduceThreads / 64];
   const double2* p2 = reinterpret_cast<const double2*>(partials);
   double t0 = 0, t1 = 0;
@@ -387,6 +389,9 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce_final(const double* _
     }
     out[0] = s0;
     out[1] = s1;
+    out[2] = s0 / nx;
+    out[3] = mass0 + s1;
+    out[4] = s1;
   }
 }
 
@@ -1073,9 +1078,10 @@ hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, b
   return launch_moments_t<D3Q19, _Float16, float>(src, a, bouz, which, field, partials, st);
 }
 
-hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, st, partials, nblocks, out);
+hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out, int nx,
+                               double mass0, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, st, partials, nblocks, out,
+                     nx, mass0);
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ EXPORTS = [
     "lbm_get_phonons", "lbm_step_checked", "lbm_checked_invariants",
     "lbm_friction_quadrature_static", "lbm_batch_member_cost", "lbm_batch_spec_footprint",
     "lbm_batch_create_spec", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
-    "lbm_batch_settings",
+    "lbm_batch_settings", "lbm_invariants_async",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -116,6 +116,7 @@ def load() -> C.CDLL:
         "lbm_friction_quadrature_static": [C.POINTER(Spectral), vp, sz, vp, vp],
         "lbm_checked_invariants": [vp, dp, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
+        "lbm_invariants_async": [vp, vp],
         "lbm_flux": [vp, dp],
         "lbm_mass": [vp, dp],
         "lbm_get_field": [vp, C.c_int, dp],
@@ -422,6 +423,14 @@ class Channel:
         out = np.zeros(3)
         self._ck(self._lib.lbm_invariants(self._h, _dptr(out)), "lbm_invariants")
         return float(out[0]), float(out[1]), float(out[2])
+
+    def invariants_async(self, out) -> None:
+        """Enqueue the invariants (flux, mass, mass deviation) into ``out``, a
+        pinned CPU float64 torch tensor of 3 elements, written when the
+        stream reaches this point."""
+        assert out.dtype.itemsize == 8 and out.numel() >= 3 and out.is_pinned()
+        self._ck(self._lib.lbm_invariants_async(self._h, C.c_void_p(out.data_ptr())),
+                 "lbm_invariants_async")
 
     def flux(self) -> float:
         q = C.c_double()

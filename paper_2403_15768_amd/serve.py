@@ -75,6 +75,8 @@ class _Slot:
     prev_q: float | None = None
     prev_rel: float | None = None
     steps_half: int = 0
+    steps: int = 0  # the context's step counter, kept on the host side
+    cells: int = 0  # fluid cells
 
 
 def tube_params(q: inputs.Query):
@@ -137,8 +139,8 @@ class Server:
                  tune: bool = True, realtime: bool = True, log=None, kind=TubeQueries,
                  keep_fields: bool = False, max_members: int = 2048):
         assert mode in ("f32", "mixed")
-        if check_every % ROUND:
-            raise ValueError(f"check_every must be a multiple of {ROUND}")
+        if check_every % ROUND or check_every < 2 * ROUND:
+            raise ValueError(f"check_every must be a multiple of {ROUND}, at least {2 * ROUND}")
         self.kind = kind
         self.mode = mode
         self.budget = int(hbm_budget)
@@ -154,7 +156,8 @@ class Server:
         self.shape = None  # workgroup shape chosen by the autotuner
         self.tuning = {}   # per phase: the autotuner's choice
         self.stats = {"batch_rebuilds": 0, "rounds": 0, "joins": 0, "leaves": 0,
-                      "max_active": 0, "lattice_updates": 0, "batch_bytes": 0}
+                      "max_active": 0, "lattice_updates": 0, "batch_bytes": 0,
+                      "host_wait_s": 0.0, "check_s": 0.0}
 
     # ------------------------------------------------------------- helpers
     def _say(self, *a):
@@ -175,8 +178,10 @@ class Server:
     def _admit(self, q, now) -> _Slot:
         ch = self._open(q, "f16s" if self.mode == "mixed" else "f32")
         self.kind.set_friction(ch, q)
-        return _Slot(query=q, ch=ch, phase="half" if self.mode == "mixed" else "f32",
-                     admitted_s=now, reserved=self._reserve(q))
+        s = _Slot(query=q, ch=ch, phase="half" if self.mode == "mixed" else "f32",
+                  admitted_s=now, reserved=self._reserve(q), steps=ch.step_count,
+                  cells=ch.fluid_count)
+        return s
 
     # the batches: one per phase, of a capacity for what the budget can hold
     def _capacity(self, phase: str, need_items: int = 0, need_cols: int = 0) -> dict:
@@ -275,9 +280,15 @@ class Server:
         active: list[_Slot] = []
         used = 0
         results: list[Result] = []
-        # at most two rounds queued ahead of the GPU, so that a query joins
-        # within a round or two of its admission
-        events = [None, None]
+        # The checks after a round are enqueued with it (flux and mass into
+        # pinned host rows) and read one round later, after the next round
+        # has been queued: the GPU never waits for the host's bookkeeping.  A
+        # query's decision therefore lands one round after its check, alone
+        # or in any mix alike.  At most two rounds are queued ahead of the
+        # GPU, so that a query joins within a round or two of its admission.
+        ring = torch.empty((4 * self.max_members, 3), dtype=torch.float64, pin_memory=True)
+        next_row = 0
+        pending = None  # (event, [(slot, row, steps at the check)])
         while i < n or waiting or active:
             t = now()
             while i < n and getattr(trace[i], "arrival_s", 0.0) <= t:
@@ -305,31 +316,38 @@ class Server:
                     self._maybe_tune(phase, b, len(waiting) + (n - i))
                     b.step(ROUND)
             self.stats["rounds"] += 1
-            self.stats["lattice_updates"] += ROUND * sum(s.ch.fluid_count for s in active)
+            self.stats["lattice_updates"] += ROUND * sum(s.cells for s in active)
+            # checks on each query's own step counter, enqueued behind the round
+            enq = []
+            for s in active:
+                s.steps += ROUND
+                if s.steps % self.check_every == 0:
+                    row = ring[next_row]
+                    next_row = (next_row + 1) % ring.shape[0]
+                    s.ch.invariants_async(row)
+                    enq.append((s, row, s.steps))
             ev = torch.cuda.Event()
             ev.record()
-            if events[0] is not None:
-                events[0].synchronize()
-            events = [events[1], ev]
-            # checks, on each query's own step counter
-            due = [s for s in active if s.ch.step_count % self.check_every == 0]
-            if not due:
+            done, pending = pending, (ev, enq)
+            if done is None:
                 continue
-            retire: list[tuple[_Slot, str, float]] = []
-            for s in due:
-                try:
-                    q = s.ch.invariants()[0]
-                except lbm.LBMError:
-                    q = math.nan
-                steps = s.ch.step_count
+            t_w = clock()
+            done[0].synchronize()
+            self.stats["host_wait_s"] += clock() - t_w
+            if not done[1]:
+                continue
+            t_c = clock()
+            retire: list[tuple[_Slot, str]] = []
+            for s, row, steps in done[1]:
+                q = float(row[0])
                 if not math.isfinite(q):
-                    retire.append((s, "diverged", q))
+                    retire.append((s, "diverged"))
                     continue
                 rel = abs(q - s.prev_q) / abs(q) if s.prev_q is not None and q != 0 else math.inf
                 if s.phase == "f32" and rel < self.rel_tol:
-                    retire.append((s, "ok", q))
+                    retire.append((s, "ok"))
                 elif steps >= self.max_steps:
-                    retire.append((s, "not_converged", q))
+                    retire.append((s, "not_converged"))
                 elif s.phase == "half" and (rel < self.switch_tol or (
                         rel < 1e-4 and s.prev_rel is not None and rel > 0.7 * s.prev_rel)):
                     s.prev_rel = rel
@@ -339,10 +357,14 @@ class Server:
                 s.prev_rel = rel
                 s.prev_q = q
             t_done = now()
-            for s, status, q in retire:
+            for s, status in retire:
                 active.remove(s)
                 used -= s.reserved
-                self._leave(s.phase, s)
+                self._leave(s.phase, s)  # after the queued round: the final state
+                try:
+                    q = s.ch.invariants()[0]
+                except lbm.LBMError:
+                    q = math.nan
                 steps = s.ch.step_count
                 results.append(Result(qid=s.query.qid, radius=getattr(s.query, "radius", 0),
                                       tau=s.query.tau,
@@ -354,6 +376,7 @@ class Server:
                 s.ch.close()
                 self._say(f"done q{s.query.qid} steps={steps} "
                           f"half={s.steps_half} t={t_done:.2f}s active={len(active)}")
+            self.stats["check_s"] += clock() - t_c
         torch.cuda.synchronize()
         for b in list(self._batches.values()):
             self._drop_batch(b)
