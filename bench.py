@@ -591,10 +591,15 @@ def main():
     if args.open_ends:
         ch.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
     cells = ch.fluid_count
+    # the step kernel's block width from the autotuner (searched here, once)
+    block, _ = ch.tune(retime=True)
     ch.step(args.warmup)
     ch.invariants()
     wall, kernel_ms = timed_run(torch, ch, args.steps, args.check_every)
     q, m, dm = ch.invariants()
+    # the same kernel at the default block width, for the tuner's gain
+    ch.set_block(0)
+    _, kms_default = timed_run(torch, ch, 1000, 1000)
     ch.close()
     del ch
 
@@ -623,6 +628,8 @@ def main():
     ext["frac_of_copy_same_footprint"] = round(achieved / copy_gbs, 4)
     ext["final_flux"] = q
     ext["mass_deviation"] = dm
+    ext["step_block_width"] = {"tuned": block, "kernel_us_tuned": round(kern_s * 1e6, 3),
+                               "kernel_us_default_width": round(kms_default * 1e3 / 1000, 3)}
 
     arith = "f32" if args.precision == "f16s" else "f64"  # half storage computes in float
     whole = None

@@ -318,6 +318,26 @@ lbm_status lbm_set_phonons(lbm_ctx *ctx, double tau_p, double rho_p0, double gam
  * NULL.  LBM_ESTATE if the phonons are off.  Synchronous. */
 lbm_status lbm_get_phonons(lbm_ctx *ctx, double *up, double *pops);
 
+/* Autotuner of the channel kernels: the block width (threads per workgroup
+ * along an x-line: 64, 128, 256 or 512, no wider than the x-line) of the
+ * step kernel of this kind of channel (lattice, storage, geometry, noise
+ * form, electron lines, open ends, and a size bucket: log2 of nx and of the
+ * fluid columns).  Takes the width a previous search chose in this process,
+ * else times every allowed width on this channel (launches that write only
+ * the buffer the next step overwrites: no state, counter or electron line
+ * changes) and keeps and caches the fastest; flags LBM_TUNE_RETIME searches
+ * even if cached.  *bx and *us (the chosen width's step time in
+ * microseconds, 0 when taken from the cache) may be NULL.  Results never
+ * depend on the width: the step's arithmetic is per cell, and the
+ * reductions (invariants, checked steps) keep the default blocks.
+ * Synchronous. */
+#define LBM_TUNE_RETIME 1
+lbm_status lbm_tune(lbm_ctx *ctx, int flags, int *bx, double *us);
+/* Set the step kernel's block width directly (as lbm_tune; 0: the default,
+ * min(nx rounded up to 64, 512)); LBM_EINVAL for a width not allowed.
+ * Synchronous. */
+lbm_status lbm_set_block(lbm_ctx *ctx, int bx);
+
 /* Advance nsteps >= 0 time steps (asynchronous).  One step is the LB update
  * of Sec. 4 for the water: pull streaming, the wall rule at the liquid/solid
  * links (Sec. 4.2; Navier-slip friction of Eq. 5 / Eq. 27), BGK collision
@@ -491,7 +511,6 @@ typedef struct {
   int cached;                  /* 1: taken from the process-wide cache */
   int64_t repacks;             /* lbm_batch_settings: times every group was laid out anew */
 } lbm_batch_tuning;
-#define LBM_TUNE_RETIME 1
 /* Autotuner: for this kind of batch (lattice, storage, wall kind, noise
  * form, and a size bucket: log2 of its fluid cells and of its members) take
  * the setting a previous search chose in this process, else search: every

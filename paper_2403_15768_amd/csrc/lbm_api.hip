@@ -10,7 +10,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -488,6 +491,9 @@ lbm_status lbm_host::launch_one_step(lbm_ctx* c, bool check) {
     c->step++;
     return LBM_OK;
   }
+  a = step_args(c);
+  a.step_off = c->step;
+  a.rev = c->cur;
   if (c->elec)  // the electrons of step n first: the water step reads their velocity
     HIPCHK(c, lbm::launch_electron_step(c->pl.Q, c->pl.prec, c->pop[c->cur],
                                         c->at<double>(c->pl.off_e[c->cur]),
@@ -527,8 +533,9 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   // node k runs step (*d_step + k); a last node advances *d_step
   StepArgs args[kGraphSteps];
   int64_t* dstep = c->at<int64_t>(c->pl.off_step);
+  const StepArgs base = step_args(c);
   for (int k = 0; k < kGraphSteps; k++) {
-    args[k] = c->args;
+    args[k] = base;
     args[k].dstep = dstep;
     args[k].step_off = k;
     args[k].rev = (parity + k) & 1;
@@ -555,8 +562,8 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
     void* kargs[3] = {(void*)&srcs[k & 1], (void*)&dsts[k & 1], (void*)&args[k]};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void*>(fn);
-    kp.gridDim = dim3((unsigned)c->pl.slots.size(), (unsigned)c->pl.segs);
-    kp.blockDim = dim3(c->pl.bx);
+    kp.gridDim = dim3((unsigned)c->pl.slots.size(), (unsigned)base.segs);
+    kp.blockDim = dim3(base.bx);
     kp.sharedMemBytes = 0;
     kp.kernelParams = kargs;
     kp.extra = nullptr;
@@ -1101,6 +1108,136 @@ lbm_status lbm_invariants_async(lbm_ctx* c, double* host_out) {
   if (s != LBM_OK) return s;
   HIPCHK(c, hipMemcpyAsync(host_out, c->at<double>(c->pl.off_out) + 2, 3 * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void drop_step_graphs(lbm_ctx* c) {
+  for (int k = 0; k < 2; k++) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+}
+
+// Block widths the step kernels may take: whole waves, at most 512 threads,
+// no wider than the x-line (rounded up to a wave).
+bool block_ok(const lbm_ctx* c, int bx) {
+  return bx >= 64 && bx <= 512 && bx % 64 == 0 && bx <= (c->pl.nxp + 63) / 64 * 64;
+}
+
+// The autotuner's choices per kind of channel: lattice, storage, geometry,
+// noise form, electron lines, open ends, and size bucket (log2 of nx and of
+// the fluid columns).  Shared by every context of the process.
+struct StepKey {
+  int Q, prec, geom, th, elec, open, nx_log2, cols_log2;
+  bool operator<(const StepKey& o) const {
+    const int a[8] = {Q, prec, geom, th, elec, open, nx_log2, cols_log2};
+    const int b[8] = {o.Q, o.prec, o.geom, o.th, o.elec, o.open, o.nx_log2, o.cols_log2};
+    return std::lexicographical_compare(a, a + 8, b, b + 8);
+  }
+};
+std::mutex g_step_mu;
+std::map<StepKey, int> g_step_tune;
+
+int log2i(int64_t v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    r++;
+  }
+  return r;
+}
+
+// Time reps launches of the water step kernel with block width bx, each
+// reading the current buffer and writing the other (which the next real
+// step overwrites: state, counters and electron lines unchanged).
+lbm_status time_step_kernel(lbm_ctx* c, int bx, int reps, hipEvent_t e0, hipEvent_t e1,
+                            double* us) {
+  const int saved = c->step_bx;
+  c->step_bx = bx;
+  StepArgs a = step_args(c);
+  c->step_bx = saved;
+  a.step_off = c->step;
+  a.rev = c->cur;
+  if (a.open) {
+    lbm_status s = ensure_end_records(c);
+    if (s != LBM_OK) return s;
+    a.bmom = bmom_buf(c, c->cur);
+    a.bmom_out = bmom_buf(c, 1 - c->cur);
+  }
+  for (int r = 0; r < reps + 2; r++) {
+    if (r == 2) HIPCHK(c, hipEventRecord(e0, c->stream));
+    HIPCHK(c, lbm::launch_step(c->pl.Q, c->pl.prec, c->pop[c->cur], c->pop[1 - c->cur], a,
+                               c->pl.bouz, c->stream));
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  *us = 1e3 * ms / reps;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_set_block(lbm_ctx* c, int bx) {
+  if (!c) return LBM_EINVAL;
+  if (bx != 0 && !block_ok(c, bx)) return c->fail(LBM_EINVAL, "block width %d not allowed", bx);
+  lbm_status s = sync(c);
+  if (s != LBM_OK) return s;
+  if ((bx ? bx : c->pl.bx) != (c->step_bx ? c->step_bx : c->pl.bx)) drop_step_graphs(c);
+  c->step_bx = bx;
+  return LBM_OK;
+}
+
+lbm_status lbm_tune(lbm_ctx* c, int flags, int* bx_out, double* us_out) {
+  if (!c) return LBM_EINVAL;
+  const StepKey key{c->pl.Q, c->pl.prec, c->p.geometry, c->args.th_mode, c->elec ? 1 : 0,
+                    c->args.open ? 1 : 0, log2i(c->pl.nx), log2i((int64_t)c->pl.slots.size())};
+  int pick = 0;
+  double best = 0.0;
+  if (!(flags & LBM_TUNE_RETIME)) {
+    std::lock_guard<std::mutex> lock(g_step_mu);
+    auto it = g_step_tune.find(key);
+    if (it != g_step_tune.end()) pick = it->second;
+  }
+  if (!pick || !block_ok(c, pick)) {
+    lbm_status s = sync(c);
+    if (s != LBM_OK) return s;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return c->fail(LBM_EDEVICE, "hipEventCreate failed");
+    }
+    best = 1e300;
+    pick = c->pl.bx;
+    for (int bx : {64, 128, 256, 512}) {
+      if (!block_ok(c, bx)) continue;
+      double us = 0;
+      if ((s = time_step_kernel(c, bx, 10, e0, e1, &us)) != LBM_OK) break;
+      if (us < best) {
+        best = us;
+        pick = bx;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != LBM_OK) return s;
+    std::lock_guard<std::mutex> lock(g_step_mu);
+    g_step_tune[key] = pick;
+  }
+  lbm_status s = lbm_set_block(c, pick == c->pl.bx ? 0 : pick);
+  if (s != LBM_OK) return s;
+  if (bx_out) *bx_out = pick;
+  if (us_out) *us_out = best;
   return LBM_OK;
 }
 

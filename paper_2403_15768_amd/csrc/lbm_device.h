@@ -43,7 +43,7 @@ struct D3Q19 {
                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   // storage row of direction i within a column (see the layout note below)
-  static constexpr int row[19] = {0, 1, 2, 3, 6, 9, 12, 4, 7, 8, 5, 10, 13, 14, 11, 15, 16, 17, 18};
+  static constexpr int row[19] = {8, 9, 10, 11, 5, 15, 1, 12, 6, 7, 13, 16, 2, 3, 17, 18, 0, 4, 14};
 };
 
 // ------------------------------------------------------------------ layout
@@ -52,12 +52,17 @@ struct D3Q19 {
 // g[col][row(i)][x] (address col * sC + row(i) * sI + x, sI = nxp,
 // sC = Q nxp), so the block that updates a column writes one contiguous
 // Q * nxp run.  The rows are ordered by the column that pulls them: the
-// x-lines with the same (c_y, c_z) are adjacent (D3Q19: {0,1,2}, {3,7,10},
-// {4,8,9}, {5,11,14}, {6,12,13}, 15, 16, 17, 18), so one destination column
+// x-lines with the same (c_y, c_z) are adjacent, so one destination column
 // reads them as one contiguous run and, when x-lines are not padded to whole
-// cache lines, the lines they share are fetched once.  Every geometry here
-// is x-invariant: a column is entirely fluid or entirely solid and its wall
-// links are the same for every x.
+// cache lines, the lines they share are fetched once.  The runs themselves
+// go by destination, z-1 before z before z+1 and within each y-1, y, y+1
+// (D3Q19: 16, {6,12,13}, 17, {4,8,9}, {0,1,2}, {3,7,10}, 18, {5,11,14}, 15;
+// D2Q9: {0,1,3}, {2,5,6}, {4,7,8}): a cache line that two runs share is
+// then mostly wanted by two destinations next to each other in y, which
+// the same workgroup (or the next) updates, so the line is used whole while
+// it is in that L2.  Every geometry here is x-invariant: a column is
+// entirely fluid or entirely solid and its wall links are the same for
+// every x.
 
 constexpr uint32_t kSolidColumn = 0x80000000u;
 // a fluid column whose pulls wrap around the periodic z boundary (slab)
@@ -579,7 +584,7 @@ __device__ __forceinline__ void open_patch(const S* __restrict__ g0, const StepA
 template <class L, typename S, typename M>
 __device__ __forceinline__ void end_record(const LBM_GLOBAL S* gc, const StepArgs& a, unsigned x,
                                            LBM_GLOBAL double* o) {
-  M r0 = ld<S, M>(gc, x), jx = 0, jy = 0, jz = 0;
+  M r0 = ld<S, M>(gc + L::row[0] * a.sI, x), jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 1; i < L::Q; i++) {
     const int op = L::opp[i];
@@ -846,9 +851,8 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
     const uint32_t w0 = Store<S, M>::kRandom ? rb.next() : 0u;
     M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
     if constexpr (THERM) v += xi[0];
-    static_assert(L::row[0] == 0, "the rest population is the column's first row");
     const S e = Store<S, M>::enc(v, w0 & 0xffffu);
-    *at(sbase(out_col), x) = e;
+    *at(sbase(out_col + L::row[0] * a.sI), x) = e;
     if constexpr (REC) {
       rec[0] = dec<S, M>(e);
       rec[1] = rec[2] = rec[3] = M(0);

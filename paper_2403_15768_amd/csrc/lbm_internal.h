@@ -81,6 +81,7 @@ struct lbm_ctx {
   bool elec = false;        // electron sheets on (SLAB)
   bool bmom_ok = false;     // open ends: end-node records of pop[cur] are current
   int64_t checked_step = -1;  // step whose invariants' partials the arena holds (-1: none)
+  int step_bx = 0;  // threads per block of the plain step launches (0: the plan's default)
   lbm::ElecArgs ea{};
 
   template <typename T>
@@ -129,4 +130,15 @@ lbm_status sync(lbm_ctx* c);
 // one plain step launch; check: the step also leaves the per-block partials
 // of the invariants of the state it reads (see lbm_step_checked)
 lbm_status launch_one_step(lbm_ctx* c, bool check = false);
+// the step arguments of the plain (unchecked) step launches: the context's,
+// with the block width the autotuner chose (the moments kernel and the
+// checked step keep the plan's, so that reductions do not depend on it)
+inline lbm::StepArgs step_args(const lbm_ctx* c) {
+  lbm::StepArgs a = c->args;
+  if (c->step_bx > 0) {
+    a.bx = c->step_bx;
+    a.segs = (c->pl.nxp + c->step_bx - 1) / c->step_bx;
+  }
+  return a;
+}
 }  // namespace lbm_host

@@ -69,7 +69,7 @@ EXPORTS = [
     "lbm_get_phonons", "lbm_step_checked", "lbm_checked_invariants",
     "lbm_friction_quadrature_static", "lbm_batch_member_cost", "lbm_batch_spec_footprint",
     "lbm_batch_create_spec", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
-    "lbm_batch_settings", "lbm_invariants_async",
+    "lbm_batch_settings", "lbm_invariants_async", "lbm_tune", "lbm_set_block",
 ]
 
 NOISE_STRESS, NOISE_ALL = 1, 2
@@ -117,6 +117,8 @@ def load() -> C.CDLL:
         "lbm_checked_invariants": [vp, dp, C.POINTER(i64)],
         "lbm_invariants": [vp, dp],
         "lbm_invariants_async": [vp, vp],
+        "lbm_tune": [vp, C.c_int, C.POINTER(C.c_int), dp],
+        "lbm_set_block": [vp, C.c_int],
         "lbm_flux": [vp, dp],
         "lbm_mass": [vp, dp],
         "lbm_get_field": [vp, C.c_int, dp],
@@ -383,6 +385,19 @@ class Channel:
         self._ck(self._lib.lbm_get_phonons(self._h, up.ctypes.data_as(dpt),
                                            pops.ctypes.data_as(dpt)), "lbm_get_phonons")
         return up, pops
+
+    # ---- kernel shape
+    def tune(self, retime: bool = False):
+        """Autotune the step kernel's block width (cached per kind and size of
+        channel); returns (width, microseconds per step or 0 if cached)."""
+        bx, us = C.c_int(), C.c_double()
+        self._ck(self._lib.lbm_tune(self._h, 1 if retime else 0, C.byref(bx), C.byref(us)),
+                 "lbm_tune")
+        return int(bx.value), float(us.value)
+
+    def set_block(self, bx: int) -> None:
+        """Step kernel block width (64, 128, 256, 512; 0 = default)."""
+        self._ck(self._lib.lbm_set_block(self._h, int(bx)), "lbm_set_block")
 
     # ---- time stepping
     def step(self, n: int) -> None:

@@ -524,3 +524,58 @@ def test_checked_step_equals_invariants_before_the_last_step(lbm, case):
         B.checked_invariants()
     with pytest.raises(lbm.LBMError):
         B.step_checked(0)
+
+
+# ------------------------------------------------------------------ block width
+@pytest.mark.parametrize("case", ["duct_f32", "tube_f64", "slab_f16s_thermal", "masked_f32",
+                                  "open_f64", "electrons_f32"])
+def test_block_width_never_changes_results(lbm, case):
+    # the step kernel's block width (set directly, or chosen by the
+    # autotuner) changes which threads update which cells, not one bit of
+    # the result; reductions keep the default blocks
+    say("block width", case)
+    geom, prec = case.split("_")[0], case.split("_")[1]
+    kw = {}
+
+    def make():
+        if geom == "duct" or geom == "open":
+            G = lbm.Channel(19, lbm.DUCT, 200, 10, 8, tau=0.7, force=(1e-5, 0, 0), precision=prec)
+        elif geom == "tube":
+            k, ny, nz = tube_kw(6)
+            G = lbm.Channel(19, lbm.TUBE, 150, ny, nz, tau=0.8, force=(1e-5, 0, 0),
+                            precision=prec, **k)
+        elif geom == "masked":
+            solid = inputs.corrugated_mask(300, 20, inputs.rng_for("corrugated", 5), amp=3,
+                                           base=3)
+            G = lbm.Channel(19, lbm.MASKED, 300, 20, 4, tau=0.7, force=(1e-5, 0, 0),
+                            precision=prec, solid=solid)
+        else:  # slab (with noise or electron lines)
+            G = lbm.Channel(19, lbm.SLAB, 130, 9, 6, tau=0.7, force=(1e-5, 0, 0), precision=prec)
+        G.set_friction(np.random.default_rng(9).uniform(0.0, 0.2, G.wall_count))
+        if case.endswith("thermal"):
+            G.set_thermal(1e-7, 2, 4)
+        if geom == "open":
+            G.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
+        if geom == "electrons":
+            G.set_electrons(0.9, 1.0, 0.05, 1e-6)
+        return G
+
+    ref = make()
+    ref.step(70)
+    ref.step_checked(3)
+    qr = ref.checked_invariants()
+    widths = [w for w in (64, 128, 256, 512) if w <= (ref.nx + 63) // 64 * 64]
+    for bx in widths + ["tuned"]:
+        G = make()
+        if bx == "tuned":
+            w, us = G.tune(retime=True)
+            assert w in widths and us > 0
+            assert G.tune()[1] == 0.0  # the cached choice
+        else:
+            G.set_block(bx)
+        G.step(70)
+        G.step_checked(3)
+        assert np.array_equal(G.get_state()[0], ref.get_state()[0]), bx
+        assert G.checked_invariants() == qr
+    with pytest.raises(lbm.LBMError):
+        ref.set_block(96)
