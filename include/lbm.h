@@ -138,8 +138,10 @@ typedef struct {
 
 typedef struct lbm_ctx lbm_ctx; /* opaque */
 
-/* Device bytes lbm_create() needs for these parameters (LBM_EINVAL on bad
- * parameters). */
+/* Device bytes lbm_create() needs for a channel (the nanochannel of Sec. 2:
+ * its box, wall geometry and lattice) -- populations, wall tables,
+ * reduction partials; for admission by footprint.  LBM_EINVAL on bad
+ * parameters. */
 lbm_status lbm_footprint(const lbm_params *p, size_t *bytes);
 
 /* Set up a channel: classify cells and wall links (Sec. 4.2 boundary sites),
@@ -151,13 +153,16 @@ lbm_status lbm_create(const lbm_params *p, void *arena, size_t arena_bytes,
                       void *hip_stream, lbm_ctx **out);
 void lbm_destroy(lbm_ctx *ctx); /* never frees the arena */
 
+/* Fluid cells, and wall nodes: the fluid sites next to the liquid/solid
+ * interface, where the boundary rules of Sec. 4.2 apply (a site with a
+ * link whose upstream point is solid). */
 lbm_status lbm_fluid_count(const lbm_ctx *ctx, size_t *n);
 lbm_status lbm_wall_count(const lbm_ctx *ctx, size_t *n);
 /* xyz: host, 3*wall_count int32 (x, y, z) per wall node, canonical order */
 lbm_status lbm_wall_coords(const lbm_ctx *ctx, int32_t *xyz);
 /* links: host, wall_count * Q doubles: fraction q in (0, 1] of the link from
  * the node to the wall along -c_i for every wall link (0.5 on planar walls),
- * 0 where the upstream point is fluid. */
+ * 0 where the upstream point is fluid (the interface links of Sec. 4.2). */
 lbm_status lbm_wall_links(const lbm_ctx *ctx, double *links);
 
 /* Friction per wall node, lattice units, canonical order: lambda >= 0,
@@ -170,7 +175,11 @@ lbm_status lbm_set_friction(lbm_ctx *ctx, const double *lambda, size_t n,
                             int on_device);
 /* Run the friction quadrature on the GPU for every wall node (Omega: the
  * node's plasmon frequency, canonical order, n = wall_count) and set the wall
- * from the result.  Host or device Omega.  Synchronous. */
+ * from the result: the linear friction coefficient of the Keldysh analysis
+ * (appendix, Eq. 27) as a (q, omega) sum over the two surfaces' response
+ * spectra (lbm_spectral above), the plasmon frequency standing for the
+ * charge-carrier density of Sec. 5.1.  Host or device Omega (finite, >= 0,
+ * else LBM_EINVAL); bad spectral parameters -> LBM_EINVAL.  Synchronous. */
 lbm_status lbm_set_friction_spectral(lbm_ctx *ctx, const lbm_spectral *sp,
                                      const double *omega, size_t n,
                                      int on_device);
@@ -289,9 +298,10 @@ lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_o
  * tau_e == 0 switches the sheets off.
  * Fields, flux and mass (the moments the next collision would see) take
  * the wall velocity from the last step's u_e.
- * Switching on resets the electrons to rest.  The electron state is not part
- * of lbm_get_state / lbm_set_state / lbm_transfer_state, and batches refuse
- * channels with sheets.  Synchronous. */
+ * Switching on resets the electrons to rest.  The electron and phonon lines
+ * are part of the checkpoint (lbm_get_state / lbm_set_state) while they are
+ * on; lbm_transfer_state copies the water only, and batches refuse channels
+ * with sheets.  Synchronous. */
 lbm_status lbm_set_electrons(lbm_ctx *ctx, double tau_e, double rho_e0,
                              double gamma_e, double force_e);
 /* u_e of the last step (nshell * nx doubles, [shell][x]) and the current
@@ -370,9 +380,12 @@ lbm_status lbm_step_checked(lbm_ctx *ctx, int64_t nsteps);
 lbm_status lbm_checked_invariants(lbm_ctx *ctx, double out[3], int64_t *at_step);
 
 /* Invariants of the current state (the moments the next collision sees):
- * out[0] = flux Q = (1/nx) sum_fluid rho u_x, out[1] = mass M = sum_fluid rho,
- * out[2] = sum_fluid (rho - rho0).  Deterministic FP64 reductions.
- * Synchronous. */
+ * out[0] = flux Q = (1/nx) sum_fluid rho u_x -- the mass flow through a
+ * cross-section, the permeability measure of Sec. 5.1 --, out[1] = mass
+ * M = sum_fluid rho (conserved by Eq. 1 with periodic ends and planar
+ * walls), out[2] = sum_fluid (rho - rho0).  Deterministic FP64 reductions.
+ * lbm_flux and lbm_mass return out[0] and out[1].  NaN/Inf ->
+ * LBM_EDIVERGED.  Synchronous. */
 lbm_status lbm_invariants(lbm_ctx *ctx, double out[3]);
 /* The same invariants, enqueued: host_out[0..2] (flux, mass, mass deviation)
  * are written when the context's stream reaches this point (the caller
@@ -385,11 +398,14 @@ lbm_status lbm_invariants(lbm_ctx *ctx, double out[3]);
 lbm_status lbm_invariants_async(lbm_ctx *ctx, double *host_out);
 lbm_status lbm_flux(lbm_ctx *ctx, double *q);
 lbm_status lbm_mass(lbm_ctx *ctx, double *m);
-/* which: 0 rho, 1 u_x, 2 u_y, 3 u_z; host_out: nz*ny*nx doubles, 0 on solid
- * cells.  Synchronous. */
+/* The hydrodynamic fields of Eqs. 1-2 as the LB moments of Sec. 4 (the
+ * populations the next collision sees, with Guo's half-force): which: 0 rho,
+ * 1 u_x, 2 u_y, 3 u_z; host_out: nz*ny*nx doubles, 0 on solid cells.
+ * Synchronous. */
 lbm_status lbm_get_field(lbm_ctx *ctx, int which, double *host_out);
-/* Shifted post-collision populations g_i = f_i - w_i rho0 as doubles,
- * host_out: Q*nz*ny*nx ([i][z][y][x]), 0 on solid cells.  Synchronous. */
+/* The distribution functions of Sec. 4 as shifted post-collision
+ * populations g_i = f_i - w_i rho0, doubles, host_out: Q*nz*ny*nx
+ * ([i][z][y][x]), 0 on solid cells.  Synchronous. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, double *host_out);
 /* The inverse: replace the state by host_in (same layout; solid cells
  * ignored), rounded to nearest in the storage precision, and set the step
@@ -398,22 +414,29 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, double *host_out);
  * unchanged.  Synchronous. */
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *host_in, int64_t step);
 
-/* Checkpoint: the populations in storage precision plus the step counter.
- * lbm_state_bytes gives the size; get/set are synchronous; set restores a
- * state bit for bit. */
+/* Checkpoint: the populations in storage precision plus the step counter;
+ * with electron lines on (lbm_set_electrons) also the electron and phonon
+ * populations and their velocities of the last step, so that a restored run
+ * continues the same run.  lbm_state_bytes gives the size for the context's
+ * current settings (LBM_EINVAL on a size mismatch, e.g. a state taken with
+ * the lines on restored with them off); get/set are synchronous; set
+ * restores a state bit for bit. */
 lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 lbm_status lbm_get_state(lbm_ctx *ctx, void *host_buf, size_t bytes,
                          int64_t *step);
 lbm_status lbm_set_state(lbm_ctx *ctx, const void *host_buf, size_t bytes,
                          int64_t step);
 
+/* Time steps taken (the context's own counter: it selects the buffer and
+ * the counter-based random bits of each step). */
 lbm_status lbm_step_count(const lbm_ctx *ctx, int64_t *step);
 
 /* Copy the state of src into dst: populations (converted to dst's storage
  * precision, round to nearest), step counter and friction.  Both contexts
  * must have the same lattice, geometry and box; their precisions may differ
- * (e.g. a half-precision run handed to a float context to finish).  Waits for
- * src; the copy runs on dst's stream and is complete on return. */
+ * (e.g. a half-precision run handed to a float context to finish: the
+ * mixed-precision solve; the paper fixes no precision).  Waits for src; the
+ * copy runs on dst's stream and is complete on return. */
 lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
 
 /* ---- Batches (many channels, one kernel launch per step and group) --------

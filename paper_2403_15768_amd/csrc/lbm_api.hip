@@ -1356,23 +1356,64 @@ lbm_status lbm_set_populations(lbm_ctx* c, const double* host_in, int64_t step) 
   return s;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The checkpoint: the water populations in storage precision, then, with
+// electron lines on, their populations (electron and phonon rows of the
+// current buffer) and the velocities of the last step, u_e then u_p.
+size_t line_bytes(const lbm_ctx* c) {
+  return c->elec ? (size_t)c->pl.nsheet * (6 + 2) * sizeof(double) : 0;
+}
+size_t state_bytes(const lbm_ctx* c) { return c->pl.pop_bytes + line_bytes(c); }
+
+}  // namespace
+
+extern "C" {
+
 lbm_status lbm_state_bytes(const lbm_ctx* c, size_t* bytes) {
   if (!c || !bytes) return LBM_EINVAL;
-  *bytes = c->pl.pop_bytes;
+  *bytes = state_bytes(c);
   return LBM_OK;
 }
 
 lbm_status lbm_get_state(lbm_ctx* c, void* host_buf, size_t bytes, int64_t* step) {
-  if (!c || !host_buf || bytes != c->pl.pop_bytes) return LBM_EINVAL;
-  HIPCHK(c, hipMemcpyAsync(host_buf, c->pop[c->cur], bytes, hipMemcpyDeviceToHost, c->stream));
+  if (!c || !host_buf) return LBM_EINVAL;
+  if (bytes != state_bytes(c))
+    return c->fail(LBM_EINVAL, "state holds %zu bytes", state_bytes(c));
+  char* h = static_cast<char*>(host_buf);
+  const Plan& pl = c->pl;
+  HIPCHK(c, hipMemcpyAsync(h, c->pop[c->cur], pl.pop_bytes, hipMemcpyDeviceToHost, c->stream));
+  if (c->elec) {
+    const size_t eb = (size_t)pl.nsheet * 6 * sizeof(double);
+    HIPCHK(c, hipMemcpyAsync(h + pl.pop_bytes, c->at<double>(pl.off_e[c->cur]), eb,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h + pl.pop_bytes + eb, c->at<double>(pl.off_ue),
+                             (size_t)pl.nsheet * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
   lbm_status s = sync(c);
   if (s == LBM_OK && step) *step = c->step;
   return s;
 }
 
 lbm_status lbm_set_state(lbm_ctx* c, const void* host_buf, size_t bytes, int64_t step) {
-  if (!c || !host_buf || bytes != c->pl.pop_bytes || step < 0) return LBM_EINVAL;
-  HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], host_buf, bytes, hipMemcpyHostToDevice, c->stream));
+  if (!c || !host_buf || step < 0) return LBM_EINVAL;
+  if (bytes != state_bytes(c))
+    return c->fail(LBM_EINVAL, "state holds %zu bytes (electron lines %s)", state_bytes(c),
+                   c->elec ? "on" : "off");
+  const char* h = static_cast<const char*>(host_buf);
+  const Plan& pl = c->pl;
+  HIPCHK(c, hipMemcpyAsync(c->pop[c->cur], h, pl.pop_bytes, hipMemcpyHostToDevice, c->stream));
+  if (c->elec) {
+    const size_t eb = (size_t)pl.nsheet * 6 * sizeof(double);
+    HIPCHK(c, hipMemcpyAsync(c->at<double>(pl.off_e[c->cur]), h + pl.pop_bytes, eb,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->at<double>(pl.off_ue), h + pl.pop_bytes + eb,
+                             (size_t)pl.nsheet * 2 * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+  }
   lbm_status s = sync(c);
   if (s == LBM_OK) c->step = step;
   c->bmom_ok = false;

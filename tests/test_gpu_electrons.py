@@ -313,3 +313,27 @@ def test_phonons_with_half_storage_water(lbm):
     e = max(np.abs(upg - upo).max() / np.abs(upo).max(), np.abs(ueg - ueo).max() / np.abs(ueo).max())
     say(f"  u_e, u_p {e:.2e}")
     assert e < 1.8e-3  # measured 5.8e-4
+
+
+@pytest.mark.parametrize("precision", ["f64", "f16s"])
+def test_checkpoint_holds_the_lines(lbm, precision):
+    # with electron and phonon lines on, a checkpoint restores water, lines
+    # and the lines' last velocities: the restored run continues bit for bit
+    say("checkpoint with lines", precision)
+    A, _ = build(lbm, "duct", precision)
+    A.set_phonons(*PHON)
+    A.step(50)
+    buf, step = A.get_state()
+    B, _ = build(lbm, "duct", precision)
+    B.set_phonons(*PHON)
+    B.set_state(buf, step)
+    for L in (A, B):
+        L.step(70)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+    for fa, fb in ((A.electrons(), B.electrons()), (A.phonons(), B.phonons())):
+        assert np.array_equal(fa[0], fb[0]) and np.array_equal(fa[1], fb[1])
+    # a state taken with the lines on does not fit a context without them
+    C, _ = build(lbm, "duct", precision)
+    C.set_electrons(0.0)
+    with pytest.raises(lbm.LBMError):
+        C.set_state(buf, step)
