@@ -320,7 +320,12 @@ def batch_throughput(args, specs):
             for k, ch in enumerate(chs):
                 ch.set_thermal(1e-6, args.thermal, k)
         b = lbm.Batch(chs)
-        shape = b.tune()
+        if args.no_tune:
+            shape = 4
+            b.tuning = {"group_bytes": b.settings()["group_bytes"], "streams": 2,
+                        "us_per_step": 0.0, "us_per_step_default": 0.0}
+        else:
+            shape = b.tune()
         b.step(64)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -546,6 +551,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--serving-queries", type=int, default=40,
                     help="queries per serving trace in the headline line")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default kernel shapes (no autotuner launches: for counter runs)")
     ap.add_argument("--no-whole-metric", action="store_true",
                     help="headline line without the batch run-to-steady and serving parts")
     args = ap.parse_args()
@@ -592,7 +599,7 @@ def main():
         ch.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
     cells = ch.fluid_count
     # the step kernel's block width from the autotuner (searched here, once)
-    block, _ = ch.tune(retime=True)
+    block = 0 if args.no_tune else ch.tune(retime=True)[0]
     ch.step(args.warmup)
     ch.invariants()
     wall, kernel_ms = timed_run(torch, ch, args.steps, args.check_every)

@@ -435,6 +435,9 @@ void fill_args(lbm_ctx* c) {
   a.bmom = nullptr;  // set per launch (open ends)
   a.bmom_out = nullptr;
   a.partials = nullptr;  // set for a checked step only
+  // a state (both buffers) of twice the last-level cache or more goes out
+  // with nontemporal stores
+  a.ntstore = 2 * pl.pop_bytes >= ((size_t)512 << 20) ? 1 : 0;
   for (int i = 0; i < 19; i++)
     a.nboff[i] = i < pl.Q ? (int64_t)lat_row(pl.Q, i) * pl.sI - lat_c(pl.Q, i, 1) * pl.sC -
                                 lat_c(pl.Q, i, 2) * (int64_t)pl.ny * pl.sC
@@ -519,7 +522,8 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   hipGraph_t g = nullptr;
   HIPCHK(c, hipGraphCreate(&g, 0));
   const void* fn = lbm::step_kernel_ptr(c->pl.Q, c->pl.prec, c->pl.bouz, c->args.th_mode,
-                                        c->elec, c->pl.masked, c->args.open != 0);
+                                        c->elec, c->pl.masked, c->args.open != 0,
+                                        c->args.ntstore != 0);
   const void* fe = c->elec ? lbm::electron_kernel_ptr(c->pl.Q, c->pl.prec) : nullptr;
   double* bm[2] = {bmom_buf(c, parity), bmom_buf(c, 1 - parity)};
   const double* esrc[2] = {c->at<double>(c->pl.off_e[parity]), c->at<double>(c->pl.off_e[1 - parity])};

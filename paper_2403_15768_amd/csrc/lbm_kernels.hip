@@ -34,7 +34,8 @@ namespace lbm {
 // returns, in FP64, j_x (with the half-force) and rho - rho0 of the
 // populations its collision sees, as k_moments forms them (0 on padding
 // lanes).
-template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN, bool CHECK>
+template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN, bool CHECK,
+          bool NT = false>
 __device__ __forceinline__ void step_cell(const S* __restrict__ src, S* __restrict__ dst,
                                           const StepArgs& a, int slot, int x, double* jx_c,
                                           double* dr_c) {
@@ -70,8 +71,9 @@ __device__ __forceinline__ void step_cell(const S* __restrict__ src, S* __restri
     }
   }
   M rec[4];
-  collide_store<L, M, S, TH, OPEN>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                                   (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi, rec);
+  collide_store<L, M, S, TH, OPEN, NT>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                                       (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi,
+                                       rec);
   // open ends: the end nodes leave the record of what they stored (the same
   // sums end_record forms) for the ghosts of the next step
   if constexpr (OPEN)
@@ -117,7 +119,7 @@ __device__ __forceinline__ void block_partials(double s0, double s1, double* __r
 }
 
 template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC, bool OPEN,
-          bool CHECK = false>
+          bool CHECK = false, bool NT = false>
 __device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restrict__ dst,
                                            const StepArgs& a) {
   // grid (fluid columns, segments per x-line).  Wall columns go first (their
@@ -141,14 +143,14 @@ __device__ __forceinline__ void step_cells(const S* __restrict__ src, S* __restr
     return;
   }
   if (x >= a.nxp) return;
-  step_cell<L, S, M, BOUZ, TH, ELEC, OPEN, false>(src, dst, a, slot, x, nullptr, nullptr);
+  step_cell<L, S, M, BOUZ, TH, ELEC, OPEN, false, NT>(src, dst, a, slot, x, nullptr, nullptr);
 }
 
 template <class L, typename S, typename M, bool BOUZ, int TH, bool ELEC = false,
-          bool CHECK = false>
+          bool CHECK = false, bool NT = false>
 __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __restrict__ dst,
                                               StepArgs a) {
-  step_cells<L, S, M, BOUZ, TH, ELEC, false, CHECK>(src, dst, a);
+  step_cells<L, S, M, BOUZ, TH, ELEC, false, CHECK, NT>(src, dst, a);
 }
 
 // Open x ends: the same update with the ghost pulls at both ends of every
@@ -912,8 +914,11 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 }
 
 // the step kernel for a wall kind and a noise form (0: none)
+// nt: nontemporal stores (plain steps of states far beyond the last-level
+// cache, no noise or sheets)
 template <class L, typename S, typename M>
-static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked, bool open) {
+static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked, bool open,
+                                 bool nt) {
   if (open) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, 1>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, 2>);
@@ -932,10 +937,12 @@ static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked,
   if (bouz) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 1>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 2>);
+    if (nt) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 0, false, false, true>);
     return reinterpret_cast<const void*>(&k_step<L, S, M, true, 0>);
   }
   if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 1>);
   if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 2>);
+  if (nt) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 0, false, false, true>);
   return reinterpret_cast<const void*>(&k_step<L, S, M, false, 0>);
 }
 
@@ -948,7 +955,8 @@ static hipError_t launch_step_t(const void* src, void* dst, const StepArgs& a, b
   StepArgs args = a;
   void* kargs[3] = {(void*)&s, (void*)&d, (void*)&args};
   return hipLaunchKernel(
-      step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr, a.cellw != nullptr, a.open != 0),
+      step_kernel_t<L, S, M>(bouz, a.th_mode, a.ue != nullptr, a.cellw != nullptr, a.open != 0,
+                             a.ntstore != 0),
       grid, block, kargs, 0, st);
 }
 
@@ -992,8 +1000,8 @@ hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepAr
 }
 
 const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec, bool masked,
-                            bool open) {
-#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec, masked, open)
+                            bool open, bool nt) {
+#define KP(L, S, M) step_kernel_t<L, S, M>(bouz, th_mode, elec, masked, open, nt)
   if (q == 9) {
     if (prec == 0) return KP(D2Q9, double, double);
     if (prec == 1) return KP(D2Q9, float, double);

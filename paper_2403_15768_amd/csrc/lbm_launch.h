@@ -46,7 +46,7 @@ hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepAr
 hipError_t launch_step_checked(int q, int prec, const void* src, void* dst, const StepArgs& a,
                                bool bouz, hipStream_t st);
 const void* step_kernel_ptr(int q, int prec, bool bouz, int th_mode, bool elec,
-                            bool masked, bool open);
+                            bool masked, bool open, bool nt);
 // one electron step from the water state g (step n): e_src -> e_dst, u_e of
 // step n -> ue; the water step of step n then reads ue
 hipError_t launch_electron_step(int q, int prec, const void* g, const double* e_src,
