@@ -38,11 +38,15 @@ DUCT = (256, 128, 64)
 KERNEL_SOURCES = ["paper_2403_15768_amd/csrc/lbm_device.h",
                   "paper_2403_15768_amd/csrc/lbm_kernels.hip"]
 # counter-measured HBM bytes per launch of the dominant kernel, per workload
-# (FP32 storage, no noise, periodic ends); used while the kernel sources match
+# and storage (no noise, periodic ends); used while the kernel sources match
 COUNTERS = {
-    "duct": os.path.join(ROOT, "profiles", "stream_collide_duct_256x128x64_f32.counters.json"),
-    "corrugated": os.path.join(ROOT, "profiles",
-                               "stream_collide_masked_corrugated_256x128x64_f32.counters.json"),
+    ("duct", "f32"): os.path.join(ROOT, "profiles",
+                                  "stream_collide_duct_256x128x64_f32.counters.json"),
+    ("duct", "f64"): os.path.join(ROOT, "profiles",
+                                  "stream_collide_duct_256x128x64_f64.counters.json"),
+    ("corrugated", "f32"): os.path.join(ROOT, "profiles",
+                                        "stream_collide_masked_corrugated_256x128x64_f32"
+                                        ".counters.json"),
 }
 
 
@@ -617,9 +621,8 @@ def main():
     log(f"bench: {mlups:.1f} MLUPS, step kernel {kern_s * 1e6:.2f} us, {achieved:.0f} GB/s")
 
     traffic = None
-    cfile = COUNTERS.get(args.workload)
-    if (cfile and os.path.exists(cfile) and args.precision == "f32" and not args.thermal
-            and not args.open_ends):
+    cfile = COUNTERS.get((args.workload, args.precision))
+    if cfile and os.path.exists(cfile) and not args.thermal and not args.open_ends:
         c = json.load(open(cfile))
         if c.get("kernel_hash") == kernel_hash():
             traffic = c.get("bytes_per_launch")
