@@ -333,9 +333,12 @@ lbm_status lbm_get_phonons(lbm_ctx *ctx, double *up, double *pops);
  * step kernel of this kind of channel (lattice, storage, geometry, noise
  * form, electron lines, open ends, and a size bucket: log2 of nx and of the
  * fluid columns).  Takes the width a previous search chose in this process,
- * else times every allowed width on this channel (launches that write only
- * the buffer the next step overwrites: no state, counter or electron line
- * changes) and keeps and caches the fastest; flags LBM_TUNE_RETIME searches
+ * else times 20 real steps of this channel at every allowed width and keeps
+ * and caches the fastest, the default width unless another is more than 1 %
+ * faster.  The search starts from a host copy of the checkpoint
+ * (lbm_state_bytes of host memory, LBM_ENOMEM without it) and puts it back:
+ * state, electron and phonon lines, step count and a pending checked step
+ * are as before the call.  flags LBM_TUNE_RETIME searches
  * even if cached.  *bx and *us (the chosen width's step time in
  * microseconds, 0 when taken from the cache) may be NULL.  Results never
  * depend on the width: the step's arithmetic is per cell, and the
@@ -539,7 +542,9 @@ typedef struct {
  * the setting a previous search chose in this process, else search: every
  * combination of 2, 4 or 8 waves per workgroup, groups of 64, 96, 128 or
  * 192 MiB of state and 1, 2 or 3 streams is laid out and timed on this
- * batch, the fastest kept and cached.  flags LBM_TUNE_RETIME: search even if
+ * batch, the fastest kept and cached (the default, 4 waves, 128 MiB or 96
+ * MiB for F16S, 2 streams, unless another is more than 1 % faster).
+ * flags LBM_TUNE_RETIME: search even if
  * cached.  The timed launches write only the buffers the next step
  * overwrites: no state or counter changes, and no setting changes results.
  * *chosen may be NULL.  Synchronous. */

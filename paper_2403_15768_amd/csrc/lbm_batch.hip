@@ -1098,6 +1098,10 @@ lbm_status lbm_batch_tune(lbm_batch* b, int flags, lbm_batch_tuning* chosen) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != LBM_OK) return s;
+  // the default setting stays unless another is faster by more than 1 %
+  // (the spread of repeated timings of one setting)
+  if (at_default > 0 && best > 0.99 * at_default)
+    pick = lbm_batch_tuning{4, dflt, 2, at_default, 0, 0, 0};
   pick.us_per_step_default = at_default;
   if ((s = apply_setting(b, pick.waves_per_group, pick.group_bytes, pick.streams)) != LBM_OK)
     return s;
