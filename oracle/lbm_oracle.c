@@ -481,6 +481,9 @@ int ora_set_friction(ora_ctx *o, const double *lambda) {
 
 /* Value of the incoming population i at fluid cell (x,y,z) whose upstream
  * point is solid: the Navier-slip wall rule. */
+static real open_ghost(const ora_ctx *o, const real *g, int xb, int yb, int zb,
+                       int i, double rho_bc);
+
 static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
                        int i, int sy) {
   long n = cell(o, x, y, z);
@@ -497,14 +500,22 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
     bb = g[(long)ib * o->ncell + n]; /* half-way bounce-back */
   } else if (qv < (real)0.5) {
     /* wall closer than half a link: interpolate between this node's and the
-     * next node's (along +c_i) populations heading into the wall */
-    int xn = ((x + o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
+     * next node's (along +c_i) populations heading into the wall; with open
+     * ends, a next node beyond x = 0 or x = nx - 1 is a ghost node, whose
+     * population is the open_ghost of the boundary node of its column */
+    int xr = x + o->c[i][0];
+    int xn = (xr % o->p.nx + o->p.nx) % o->p.nx;
     int yn = y + o->c[i][1], zn = z + o->c[i][2];
-    if (is_solid(o, xn, yn, zn))
+    if (is_solid(o, xn, yn, zn)) {
       bb = g[(long)ib * o->ncell + n];
-    else
-      bb = 2 * qv * g[(long)ib * o->ncell + n] +
-           (1 - 2 * qv) * g[(long)ib * o->ncell + cell(o, xn, yn, zn)];
+    } else {
+      real behind;
+      if (o->open && (xr < 0 || xr >= o->p.nx))
+        behind = open_ghost(o, g, x, yn, zn, ib, xr < 0 ? o->rho_in : o->rho_out);
+      else
+        behind = g[(long)ib * o->ncell + cell(o, xn, yn, zn)];
+      bb = 2 * qv * g[(long)ib * o->ncell + n] + (1 - 2 * qv) * behind;
+    }
   } else {
     /* wall farther than half a link: interpolate between the bounced
      * population and this node's own outgoing population i */
@@ -536,7 +547,7 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
  * moments of b's stored populations.  rho_bc is rho_in at x = -1 and rho_out
  * at x = nx; the pressure c_s^2 rho_bc is the drive. */
 int ora_set_open_ends(ora_ctx *o, int open, double rho_in, double rho_out) {
-  if (open && (o->p.geometry == ORA_TUBE || o->p.geometry == ORA_MASKED || o->elec ||
+  if (open && (o->p.geometry == ORA_MASKED || o->elec ||
                o->p.nx < 2 || !(rho_in > 0) || !(rho_out > 0) || !isfinite(rho_in) ||
                !isfinite(rho_out)))
     return ORA_EINVAL;
