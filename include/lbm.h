@@ -264,11 +264,13 @@ lbm_status lbm_set_noise_closure(lbm_ctx *ctx, const double *gamma, int nr, int 
  * rho_b = rho0 + sum_k g_k(b), u_b = sum_k g_k(b) c_k / rho_b, rho_bc =
  * rho_in at x = -1 and rho_out at x = nx.  A pressure drop rho_in > rho_out
  * then drives the flow of the body force c_s^2 (rho_in - rho_out) / (nx + 1).
+ * On a TUBE an interpolated wall link whose node behind (x + c_i) lies
+ * beyond an end reads the ghost there (of the boundary node of that column).
  * Fields, flux and mass take the ghosts too; mass is no longer conserved.
  * open = 0 restores periodic x (the densities are then ignored).  Requires
- * a SLAB or DUCT, nx >= 2, no electron sheets, finite densities > 0 (else
- * LBM_EINVAL); batches refuse such channels.  Synchronous (finishes queued
- * work). */
+ * a SLAB, DUCT or TUBE, nx >= 2, no electron sheets, finite densities > 0
+ * (else LBM_EINVAL); batches refuse such channels.  Synchronous (finishes
+ * queued work). */
 lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_out);
 
 /* Electron wind (SLAB and DUCT).  Sec. 3.3 describes the electrons of the solid

@@ -542,40 +542,72 @@ __device__ __forceinline__ M cdot(int i, M vx, M vy, M vz) {
 //   ghost_i = g_i(b) + w_i (drho_bc - drho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2
 //                                               - 1.5 u_b.u_b),
 // drho_b = sum_k g_k(b), u_b = sum_k g_k(b) c_k / (rho0 + drho_b).  Replaces
-// df_i of those links after the periodic gather (which read x = nx - 1 or 0);
-// x is the lane's cell, the column is uniform.
-template <class L, typename S, typename M>
+// df_i of those links after the gather, which must be the OPEN one (reads
+// clamped at the ends); x is the lane's cell, the column is uniform.  On a
+// tube (BOUZ) an interpolated wall link whose node behind lies beyond the
+// end reads that ghost too.
+template <class L, typename S, typename M, bool BOUZ = false, typename W = M>
 __device__ __forceinline__ void open_patch(const S* __restrict__ g0, const StepArgs& a, int col,
-                                           int x, uint32_t mask, M* df) {
+                                           int x, ColInfo info, M* df) {
   const bool in = x == 0, out = x == a.nx - 1;
   if (!in && !out) return;
-  const LBM_GLOBAL S* gown = gbl(g0) + (int64_t)col * a.sC;
+  const uint32_t mask = info.mask;
+  const LBM_GLOBAL S* g = gbl(g0);
+  const LBM_GLOBAL S* gown = g + (int64_t)col * a.sC;
   const int z = col / a.ny;
   const bool wrap = (mask & kWrapColumn) != 0u;
   const unsigned ux = (unsigned)x;
+  // the ghost value of population k of a ghost next to the end node of the
+  // column whose base is cb (the end of this lane's x)
+  auto ghost_shift = [&](const LBM_GLOBAL S* cb, int k, bool at_in, M* gk) {
+    M drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int m = 0; m < L::Q; m++) {
+      const M v = ld<S, M>(sbase(cb + L::row[m] * a.sI), ux);
+      drho += v;
+      if (L::cx[m]) jx += L::cx[m] > 0 ? v : -v;
+      if (L::cy[m]) jy += L::cy[m] > 0 ? v : -v;
+      if (L::cz[m]) jz += L::cz[m] > 0 ? v : -v;
+      if (m == k) *gk = v;
+    }
+    const M rho = static_cast<M>(a.rho0) + drho;
+    const M ux_ = jx / rho, uy_ = jy / rho, uz_ = jz / rho;
+    const M cu = cdot<L, M>(k, ux_, uy_, uz_);
+    const M usq = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
+    const M dbc = static_cast<M>(at_in ? a.drho_in : a.drho_out);
+    return static_cast<M>(L::w[k]) * (dbc - drho) *
+           (M(1) + M(3) * cu + M(4.5) * cu * cu - M(1.5) * usq);
+  };
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     if (L::cx[i] == 0 || (mask & (1u << i))) continue;
     if (!((L::cx[i] > 0 && in) || (L::cx[i] < 0 && out))) continue;
     // the source column of link i
     const LBM_GLOBAL S* cb = gown + src_off<L>(a, i, z, wrap) - L::row[i] * a.sI;
-    M drho = 0, jx = 0, jy = 0, jz = 0, gi = 0;
+    M gi = 0;
+    const M sh = ghost_shift(cb, i, in, &gi);
+    df[i] = gi + sh;
+  }
+  if constexpr (BOUZ) {
+    // interpolated wall links whose node behind, x + c_i, lies beyond this
+    // end: the gather (clamped at the ends) read g_opp(i) of the boundary
+    // node of that column; the ghost adds its shift, weighted as the gather
+    // weighted the value (r times the interpolation coefficient)
+    if ((mask & kLinkBits) == 0u) return;
+    const int y = col - z * a.ny;
+    const LBM_GLOBAL W* cw = gbl(static_cast<const W*>(a.bz)) + (int64_t)info.wallcol * L::Q * 2;
+    const M r = static_cast<M>(gbl(static_cast<const W*>(a.rwall))[(int64_t)info.wallcol * a.nx + x]);
 #pragma unroll
-    for (int k = 0; k < L::Q; k++) {
-      const M v = ld<S, M>(sbase(cb + L::row[k] * a.sI), ux);
-      drho += v;
-      if (L::cx[k]) jx += L::cx[k] > 0 ? v : -v;
-      if (L::cy[k]) jy += L::cy[k] > 0 ? v : -v;
-      if (L::cz[k]) jz += L::cz[k] > 0 ? v : -v;
-      if (k == i) gi = v;
+    for (int i = 0; i < L::Q; i++) {
+      if (L::cx[i] == 0 || !(mask & (1u << i))) continue;
+      if (!((L::cx[i] > 0 && out) || (L::cx[i] < 0 && in))) continue;
+      const M cbz = static_cast<M>(cw[2 * i]);
+      if (cbz == M(0)) continue;
+      const int nc = (y + L::cy[i]) + a.ny * (z + L::cz[i]);
+      M gk = 0;
+      const M sh = ghost_shift(g + (int64_t)nc * a.sC, L::opp[i], in, &gk);
+      df[i] += r * cbz * sh;
     }
-    const M rho = static_cast<M>(a.rho0) + drho;
-    const M ux_ = jx / rho, uy_ = jy / rho, uz_ = jz / rho;
-    const M cu = cdot<L, M>(i, ux_, uy_, uz_);
-    const M usq = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
-    const M dbc = static_cast<M>(in ? a.drho_in : a.drho_out);
-    df[i] = gi + static_cast<M>(L::w[i]) * (dbc - drho) *
-                     (M(1) + M(3) * cu + M(4.5) * cu * cu - M(1.5) * usq);
   }
 }
 
@@ -611,29 +643,53 @@ __device__ __forceinline__ void end_record(const LBM_GLOBAL S* gc, const StepArg
 // would pull from x = -1 (x = nx) gains
 //   w_i (drho_bc - drho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2 - 1.5 u_b.u_b)
 // from b's record (a.bmom).  Lanes inside the line return at once.
-template <class L, typename M>
-__device__ __forceinline__ void open_correct(const StepArgs& a, int col, int x, uint32_t mask,
+template <class L, typename M, bool BOUZ = false>
+__device__ __forceinline__ void open_correct(const StepArgs& a, int col, int x, ColInfo info,
                                              M* df) {
   const bool in = x == 0, out = x == a.nx - 1;
   if (!in && !out) return;
+  const uint32_t mask = info.mask;
   const int z = col / a.ny;
   const int y = col - z * a.ny;
-  const LBM_GLOBAL double* bm = gbl(a.bmom) + (out ? (int64_t)a.ny * a.nz * 4 : 0);
-  const M dbc = static_cast<M>(in ? a.drho_in : a.drho_out);
+  const LBM_GLOBAL double* bm_in = gbl(a.bmom);
+  const LBM_GLOBAL double* bm_out = bm_in + (int64_t)a.ny * a.nz * 4;
+  // w_k (drho_bc - drho_b) (1 + 3 c_k.u_b + 4.5 (c_k.u_b)^2 - 1.5 u_b.u_b)
+  auto shift = [&](const LBM_GLOBAL double* r, int k, bool at_in) {
+    const M drho = static_cast<M>(r[0]);
+    const M ux_ = static_cast<M>(r[1]), uy_ = static_cast<M>(r[2]), uz_ = static_cast<M>(r[3]);
+    const M cu = cdot<L, M>(k, ux_, uy_, uz_);
+    const M usq = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
+    const M dbc = static_cast<M>(at_in ? a.drho_in : a.drho_out);
+    return static_cast<M>(L::w[k]) * (dbc - drho) *
+           (M(1) + M(3) * cu + M(4.5) * cu * cu - M(1.5) * usq);
+  };
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     if (L::cx[i] == 0 || (mask & (1u << i))) continue;
     if (!((L::cx[i] > 0 && in) || (L::cx[i] < 0 && out))) continue;
     int zb = z - L::cz[i];
-    if (zb < 0) zb += a.nz;  // z periodic (slab; a duct never pulls across z)
+    if (zb < 0) zb += a.nz;  // z periodic (slab; a duct or tube never pulls across z)
     if (zb >= a.nz) zb -= a.nz;
-    const LBM_GLOBAL double* r = bm + ((int64_t)(y - L::cy[i]) + (int64_t)a.ny * zb) * 4;
-    const M drho = static_cast<M>(r[0]);
-    const M ux_ = static_cast<M>(r[1]), uy_ = static_cast<M>(r[2]), uz_ = static_cast<M>(r[3]);
-    const M cu = cdot<L, M>(i, ux_, uy_, uz_);
-    const M usq = ux_ * ux_ + uy_ * uy_ + uz_ * uz_;
-    df[i] += static_cast<M>(L::w[i]) * (dbc - drho) *
-             (M(1) + M(3) * cu + M(4.5) * cu * cu - M(1.5) * usq);
+    const LBM_GLOBAL double* r = (in ? bm_in : bm_out) +
+                                 ((int64_t)(y - L::cy[i]) + (int64_t)a.ny * zb) * 4;
+    df[i] += shift(r, i, in);
+  }
+  if constexpr (BOUZ) {
+    // interpolated wall links whose node behind, x + c_i, lies beyond this
+    // end (the OPEN gather read g_opp(i) of the boundary node of that
+    // column): the ghost's shift, weighted as the gather weighted the value
+    if ((mask & kLinkBits) == 0u) return;
+    const LBM_GLOBAL M* cw = gbl(static_cast<const M*>(a.bz)) + (int64_t)info.wallcol * L::Q * 2;
+    const M rw = gbl(static_cast<const M*>(a.rwall))[(int64_t)info.wallcol * a.nx + x];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+      if (L::cx[i] == 0 || !(mask & (1u << i))) continue;
+      if (!((L::cx[i] > 0 && out) || (L::cx[i] < 0 && in))) continue;
+      const M cbz = cw[2 * i];
+      if (cbz == M(0)) continue;
+      const int64_t nc = (int64_t)(y + L::cy[i]) + (int64_t)a.ny * (z + L::cz[i]);
+      df[i] += rw * cbz * shift((in ? bm_in : bm_out) + nc * 4, L::opp[i], in);
+    }
   }
 }
 

@@ -57,7 +57,7 @@ __device__ __forceinline__ void step_cell(const S* __restrict__ src, S* __restri
   if constexpr (TH != 0)
     thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
   gather<L, S, M, M, BOUZ, ELEC, OPEN>(src, a, col, xc, info, df);
-  if constexpr (OPEN) open_correct<L, M>(a, col, xc, info.mask, df);
+  if constexpr (OPEN) open_correct<L, M, BOUZ>(a, col, xc, info, df);
   if constexpr (CHECK) {
     if (x < a.nx) {
       double dr = 0, jx = 0;
@@ -155,11 +155,12 @@ __global__ void __launch_bounds__(512) k_step(const S* __restrict__ src, S* __re
 
 // Open x ends: the same update with the ghost pulls at both ends of every
 // x-line (the end-node records hold a few more registers: four waves per
-// SIMD instead of five; asking for five makes the compiler spill)
-template <class L, typename S, typename M, int TH>
+// SIMD instead of five; asking for five makes the compiler spill).  BOUZ:
+// tubes, whose interpolated wall links at the ends also read ghosts.
+template <class L, typename S, typename M, bool BOUZ, int TH>
 __global__ void __launch_bounds__(512) k_step_open(const S* __restrict__ src,
                                                       S* __restrict__ dst, StepArgs a) {
-  step_cells<L, S, M, false, TH, false, true>(src, dst, a);
+  step_cells<L, S, M, BOUZ, TH, false, true>(src, dst, a);
 }
 
 // Masked walls: the same update on every fluid point of the columns that
@@ -330,8 +331,12 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
       info.wallcol = uniform(cs.wallcol);
       info.mask = (uint32_t)uniform((int)cs.mask);
       // with electron sheets the wall moves with u_e of the last step
-      gather<L, S, double, W, BOUZ, ELEC>(src, a, col, x, info, df);
-      if (a.open) open_patch<L, S, double>(src, a, col, x, info.mask, df);
+      if (a.open) {  // reads clamped at the ends, then the ghosts
+        gather<L, S, double, W, BOUZ, ELEC, true>(src, a, col, x, info, df);
+        open_patch<L, S, double, BOUZ, W>(src, a, col, x, info, df);
+      } else {
+        gather<L, S, double, W, BOUZ, ELEC>(src, a, col, x, info, df);
+      }
     }
     double drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -919,10 +924,15 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 template <class L, typename S, typename M>
 static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked, bool open,
                                  bool nt) {
+  if (open && bouz) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, true, 1>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, true, 2>);
+    return reinterpret_cast<const void*>(&k_step_open<L, S, M, true, 0>);
+  }
   if (open) {
-    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, 1>);
-    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, 2>);
-    return reinterpret_cast<const void*>(&k_step_open<L, S, M, 0>);
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 1>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 2>);
+    return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 0>);
   }
   if (masked) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 1>);
