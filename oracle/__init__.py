@@ -241,8 +241,9 @@ class Lattice:
         rho_out); open_=False restores periodic x."""
         if self._lib.ora_set_open_ends(self._h, int(bool(open_)), float(rho_in),
                                        float(rho_out)) != 0:
-            raise OracleError("open ends need a SLAB, DUCT or TUBE without electron sheets, nx >= 2 "
-                              "and finite densities > 0")
+            raise OracleError("open ends need a SLAB, DUCT, TUBE or MASKED channel (a mask "
+                              "with equal first and last rows) without electron sheets, "
+                              "nx >= 2 and finite densities > 0")
 
     def set_phonons(self, tau_p: float, rho_p0: float = 1.0, gamma_pc: float = 0.0,
                     gamma_ep: float = 0.0) -> None:

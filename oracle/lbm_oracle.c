@@ -33,7 +33,8 @@
  *    interpolation on the circular tube.  Inlet/outlet are periodic in x (the
  *    first option of Sec. 4.2), or open (its Neumann-like option: ghost
  *    nodes rebuilt from the boundary node at a prescribed density, see
- *    open_ghost).  Walls that vary along x (a solid mask in
+ *    open_ghost; a masked wall continues past an open end as that end's row
+ *    of the mask).  Walls that vary along x (a solid mask in
  *    the (x, y) plane: corrugated, wrinkled or stepped walls) take the slip
  *    half from a pairing of the node's wall links (pair_slip_links) that
  *    keeps mass exact.
@@ -546,8 +547,19 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
  * with rho_b = rho0 + sum_k g_k(b) and u_b = sum_k g_k(b) c_k / rho_b the
  * moments of b's stored populations.  rho_bc is rho_in at x = -1 and rho_out
  * at x = nx; the pressure c_s^2 rho_bc is the drive. */
+/* Masked walls continue past each open end as that end's row of the mask;
+ * with equal first and last rows this continuation and the periodic one
+ * give every node the same wall links (and slip pairs). */
+static int mask_ends_equal(const ora_ctx *o) {
+  int y;
+  for (y = 0; y < o->p.ny; y++)
+    if ((o->mask[(long)o->p.nx * y] != 0) != (o->mask[(long)o->p.nx * y + o->p.nx - 1] != 0))
+      return 0;
+  return 1;
+}
+
 int ora_set_open_ends(ora_ctx *o, int open, double rho_in, double rho_out) {
-  if (open && (o->p.geometry == ORA_MASKED || o->elec ||
+  if (open && ((o->p.geometry == ORA_MASKED && !mask_ends_equal(o)) || o->elec ||
                o->p.nx < 2 || !(rho_in > 0) || !(rho_out > 0) || !isfinite(rho_in) ||
                !isfinite(rho_out)))
     return ORA_EINVAL;

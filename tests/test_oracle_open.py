@@ -19,7 +19,14 @@ What fixes it independently of the oracle's own open-end code:
     linear over every cross-section and add no resistance at the ends: the
     flux times (nx + 1) is the same for any tube length.  Reading the node
     behind an interpolated link at the ends from the periodic image instead
-    of the ghost breaks both (slope off by 1 %, flux by 2e-4).
+    of the ghost breaks both (slope off by 1 %, flux by 2e-4);
+  - masked walls continue past an open end as that end's row of the mask
+    (first and last rows equal): an x-uniform mask is then the open slab
+    shifted, bit for bit; a mask, friction field and drive mirrored in x
+    with the end densities swapped give the mirrored flow; through a
+    wrinkled channel the pressure drop drives the flux of the equivalent
+    body force up to an end effect that halves when the channel doubles,
+    and follows lubrication theory to the staircase correction.
 """
 import math
 
@@ -170,11 +177,89 @@ def test_tube_pressure_drop_against_body_force():
     assert 1.8 < rel[0] / rel[1] < 2.2
 
 
+@pytest.mark.parametrize("q,nz", [(9, 1), (19, 4)])
+def test_x_uniform_mask_with_open_ends_is_the_open_slab_bitwise(q, nz):
+    nx, ny, lo, hi = 13, 14, 3, 2
+    solid = np.zeros((ny, nx), dtype=bool)
+    solid[:lo] = True
+    solid[ny - hi:] = True
+    h = ny - lo - hi
+    A = oracle.Lattice(q, oracle.SLAB, nx, h, nz, tau=0.9, force=(2e-5, 0, 0))
+    B = oracle.Lattice(q, oracle.MASKED, nx, ny, nz, tau=0.9, force=(2e-5, 0, 0), solid=solid)
+    lam = np.random.default_rng(2).uniform(0, 0.5, A.wall_count)
+    for L in (A, B):
+        L.set_friction(lam)
+        L.set_open_ends(1.0 + 3e-5, 1.0 - 2e-5)
+    A.step(90)
+    B.step(90)
+    assert np.array_equal(A.get_populations(), B.get_populations()[:, :, lo:ny - hi, :])
+
+
+@pytest.mark.parametrize("q,nz", [(9, 1), (19, 3)])
+def test_masked_open_ends_mirror_x(q, nz):
+    nx, ny = 20, 12
+    solid = np.zeros((ny, nx), dtype=bool)
+    solid[:2] = True
+    for x in range(nx):
+        d = min(x, nx - 1 - x)
+        if 3 <= d <= 6:
+            solid[:4, x] = True
+        if d == 8:
+            solid[ny - 3:, x] = True
+    assert np.array_equal(solid, solid[:, ::-1])
+    F, rin, rout = 1e-5, 1.0 + 2e-5, 1.0 - 1e-5
+    runs = []
+    for sgn in (1, -1):
+        L = oracle.Lattice(q, oracle.MASKED, nx, ny, nz, tau=0.8, force=(sgn * F, 0, 0),
+                           solid=solid)
+        xyz = L.wall_coords()
+        d = np.minimum(xyz[:, 0], nx - 1 - xyz[:, 0])
+        L.set_friction(0.05 + 0.02 * d + 0.01 * xyz[:, 1] + 0.003 * xyz[:, 2])
+        L.set_open_ends(*((rin, rout) if sgn > 0 else (rout, rin)))
+        L.step(300)
+        runs.append(L.fields())
+    (ra, uxa, uya, _), (rb, uxb, uyb, _) = runs
+    ref = np.abs(uxa).max()
+    assert ref > 1e-5
+    assert np.abs(uxb + uxa[:, :, ::-1]).max() < 1e-12 * ref
+    assert np.abs(uyb - uya[:, :, ::-1]).max() < 1e-12 * ref
+    assert np.abs(rb - ra[:, :, ::-1]).max() < 1e-13
+
+
+def test_pressure_drop_through_wrinkled_walls():
+    from test_oracle_masked import corrugated_mask
+
+    ny, tau, drho = 26, 1.0, 1e-6
+    nu = (tau - 0.5) / 3
+    diff = []
+    for period in (128, 256):
+        nx = period + 1  # one or two whole wrinkles plus the repeated first row
+        solid = corrugated_mask(nx, ny, amp_lo=2.0, amp_hi=2.0, base=3, period=period)
+        assert np.array_equal(solid[:, 0], solid[:, -1])
+        L = oracle.Lattice(9, oracle.MASKED, nx, ny, 1, tau=tau, solid=solid)
+        L.set_friction(math.inf)
+        L.set_open_ends(1.0 + drho / 2, 1.0 - drho / 2)
+        q = run_steady(L, tol=1e-10)
+        G = drho / 3 / (nx + 1)
+        P = oracle.Lattice(9, oracle.MASKED, period, ny, 1, tau=tau, force=(G, 0, 0),
+                           solid=solid[:, :period])
+        P.set_friction(math.inf)
+        diff.append(q / run_steady(P, tol=1e-10) - 1)
+        h = (~solid).sum(axis=0).astype(float)
+        assert abs(q / (G / (12 * nu) / np.mean(h ** -3.0)) - 1) < 0.03
+    assert abs(diff[0]) < 0.005
+    assert 1.8 < diff[0] / diff[1] < 2.2
+
+
 def test_open_ends_rejections():
     solid = np.zeros((6, 8), dtype=bool)
     solid[0, :] = solid[-1, :] = True
+    solid[1, 3] = True
     M = oracle.Lattice(19, oracle.MASKED, 8, 6, 2, tau=0.8, solid=solid)
-    with pytest.raises(oracle.OracleError):
+    M.set_open_ends(1.0, 1.0)  # equal first and last rows
+    solid[1, 7] = True
+    M = oracle.Lattice(19, oracle.MASKED, 8, 6, 2, tau=0.8, solid=solid)
+    with pytest.raises(oracle.OracleError):  # the last row differs from the first
         M.set_open_ends(1.0, 1.0)
     S = oracle.Lattice(9, oracle.SLAB, 1, 6, 1, tau=0.8)
     with pytest.raises(oracle.OracleError):  # nx = 1
