@@ -171,7 +171,10 @@ def cpu_baseline(steps):
 
 def extras(torch, lbm, inputs, args):
     """Secondary measurements: FP64 duct, the R = 32 nanotube with its
-    spectral friction quadrature."""
+    spectral friction quadrature, and the other wall kinds, ends, noise forms
+    and line species."""
+    import numpy as np
+
     out = {}
     ch = make_duct(lbm, inputs, "f64")
     ch.step(200)
@@ -299,6 +302,24 @@ def extras(torch, lbm, inputs, args):
                              "kernel_us": round(kms * 1e3 / 2000, 2),
                              "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
                                                / HBM_PEAK_GBS, 4)}
+    ch.close()
+    # a wrinkled slab of the same size whose last row repeats its first (255
+    # rows of the mask above, then the first again), between two reservoirs
+    # at a density drop: masked walls with open ends
+    nx, ny, nz = DUCT
+    m = inputs.corrugated_mask(nx - 1, ny, inputs.rng_for("corrugated", 0))
+    solid = np.concatenate([m, m[:, :1]], axis=1)
+    ch = lbm.Channel(lbm.D3Q19, lbm.MASKED, nx, ny, nz, tau=0.7, force=(0.0, 0.0, 0.0),
+                     precision="f32", solid=solid)
+    ch.set_friction(0.05)
+    ch.set_open_ends(1.0 + 1e-5, 1.0 - 1e-5)
+    ch.step(200)
+    wall, kms = timed_run(torch, ch, 2000, 1000)
+    cells = ch.fluid_count
+    out["corrugated_f32_open_ends"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                                       "kernel_us": round(kms * 1e3 / 2000, 2),
+                                       "hbm_frac": round(152 * cells / (kms * 1e-3 / 2000) / 1e9
+                                                         / HBM_PEAK_GBS, 4)}
     ch.close()
     # the benchmark duct with electron lines on all four walls
     ch = make_duct(lbm, inputs, "f32")

@@ -266,11 +266,13 @@ lbm_status lbm_set_noise_closure(lbm_ctx *ctx, const double *gamma, int nr, int 
  * then drives the flow of the body force c_s^2 (rho_in - rho_out) / (nx + 1).
  * On a TUBE an interpolated wall link whose node behind (x + c_i) lies
  * beyond an end reads the ghost there (of the boundary node of that column).
- * Fields, flux and mass take the ghosts too; mass is no longer conserved.
- * open = 0 restores periodic x (the densities are then ignored).  Requires
- * a SLAB, DUCT or TUBE, nx >= 2, no electron sheets, finite densities > 0
- * (else LBM_EINVAL); batches refuse such channels.  Synchronous (finishes
- * queued work). */
+ * A MASKED wall continues past each end as that end's row of the mask, which
+ * must be the same at both ends (x = 0 and x = nx - 1): the wall links are
+ * then those of the periodic channel.  Fields, flux and mass take the ghosts
+ * too; mass is no longer conserved.  open = 0 restores periodic x (the
+ * densities are then ignored).  Requires nx >= 2, no electron sheets, finite
+ * densities > 0, equal end rows of a mask (else LBM_EINVAL); batches refuse
+ * such channels.  Synchronous (finishes queued work). */
 lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_out);
 
 /* Electron wind (SLAB and DUCT).  Sec. 3.3 describes the electrons of the solid

@@ -941,8 +941,14 @@ lbm_status lbm_set_noise_closure(lbm_ctx* c, const double* gamma, int nr, int ns
 lbm_status lbm_set_open_ends(lbm_ctx* c, int open, double rho_in, double rho_out) {
   if (!c) return LBM_EINVAL;
   if (open) {
-    if (c->p.geometry == LBM_MASKED)
-      return c->fail(LBM_EINVAL, "open ends need a SLAB, DUCT or TUBE");
+    if (c->p.geometry == LBM_MASKED) {
+      // the wall continues past each end as that end's row of the mask; with
+      // equal first and last rows it has the periodic channel's wall links
+      const std::vector<unsigned char>& m = c->pl.solid;
+      for (int y = 0; y < c->pl.ny; y++)
+        if ((m[(size_t)c->pl.nx * y] != 0) != (m[(size_t)c->pl.nx * y + c->pl.nx - 1] != 0))
+          return c->fail(LBM_EINVAL, "open ends on masked walls need equal first and last rows");
+    }
     if (c->elec) return c->fail(LBM_EINVAL, "open ends need the electron sheets off");
     if (c->pl.nx < 2) return c->fail(LBM_EINVAL, "open ends need nx >= 2");
     if (!(rho_in > 0.0) || !(rho_out > 0.0) || !std::isfinite(rho_in) || !std::isfinite(rho_out))

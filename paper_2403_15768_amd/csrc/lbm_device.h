@@ -431,14 +431,15 @@ constexpr int ptab_words() {
 }
 
 // Pulls only: a column none of whose points is a wall node (all of them
-// interior; the block's branch is uniform).  z is periodic.
-template <class L, typename S, typename M>
+// interior; the block's branch is uniform).  z is periodic.  OPEN: the pulls
+// that would wrap around x read the node itself (as gather<OPEN>).
+template <class L, typename S, typename M, bool OPEN = false>
 __device__ __forceinline__ void gather_masked_interior(const S* __restrict__ g0, const StepArgs& a,
                                                        int col, int z, int x, M* df) {
   const LBM_GLOBAL S* gown = gbl(g0) + (int64_t)col * a.sC;
   const unsigned ux = (unsigned)x;
-  const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
-  const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
+  const unsigned xm = (x == 0) ? (OPEN ? 0u : (unsigned)a.nx - 1u) : ux - 1u;
+  const unsigned xp = (x == a.nx - 1) ? (OPEN ? ux : 0u) : ux + 1u;
   const bool wrap = L::Q == 19 && (z == 0 || z == a.nz - 1);
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
@@ -453,15 +454,18 @@ __device__ __forceinline__ void gather_masked_interior(const S* __restrict__ g0,
 // p(i) its slip partner, evaluated as g + r (bb - g) like the column-wide
 // rule.  Lanes of one wave may be wall nodes or not: every lane issues one
 // load per link (its pull, or its partner's own population) and wall lanes
-// one more (the bounced population), all before any is combined.
-template <class L, typename S, typename M, typename W>
+// one more (the bounced population), all before any is combined.  OPEN:
+// the pulls that would wrap around x read the node itself (as gather<OPEN>).
+// *wlinks (if given) receives the lane's wall links (bit i: upstream solid).
+template <class L, typename S, typename M, typename W, bool OPEN = false>
 __device__ __forceinline__ void gather_masked(const S* __restrict__ g0, const StepArgs& a,
-                                              int col, int z, int x, int cw, M* df) {
+                                              int col, int z, int x, int cw, M* df,
+                                              uint32_t* wlinks = nullptr) {
   const LBM_GLOBAL S* gown = gbl(g0) + (int64_t)col * a.sC;
   const int64_t sI = a.sI;
   const unsigned ux = (unsigned)x;
-  const unsigned xm = (x == 0) ? (unsigned)a.nx - 1u : ux - 1u;
-  const unsigned xp = (x == a.nx - 1) ? 0u : ux + 1u;
+  const unsigned xm = (x == 0) ? (OPEN ? 0u : (unsigned)a.nx - 1u) : ux - 1u;
+  const unsigned xp = (x == a.nx - 1) ? (OPEN ? ux : 0u) : ux + 1u;
   const bool wrap = L::Q == 19 && (z == 0 || z == a.nz - 1);
   const bool wall = cw >= 0;
   constexpr int kWords = ptab_words<L>();
@@ -483,6 +487,7 @@ __device__ __forceinline__ void gather_masked(const S* __restrict__ g0, const St
     A[i] = *(wl ? own : pull);
     if (wl) B[i] = *at(gown + L::row[L::opp[i]] * sI, ux);
   }
+  uint32_t links = 0u;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     const unsigned prow = (pw[i >> 2] >> (8 * (i & 3))) & 0xffu;
@@ -490,10 +495,12 @@ __device__ __forceinline__ void gather_masked(const S* __restrict__ g0, const St
     if (prow != kNoLink) {
       const M bb = dec<S, M>(B[i]);
       df[i] = gs + r * (bb - gs);
+      links |= 1u << i;
     } else {
       df[i] = gs;
     }
   }
+  if (wlinks) *wlinks = links;
 }
 
 // Weights of the terms linear in c_i (3 w_i), chosen so that

@@ -168,8 +168,11 @@ __global__ void __launch_bounds__(512) k_step_open(const S* __restrict__ src,
 // class of each point (solid, interior, wall node) comes from a table of the
 // (x, y) plane, so a wave may hold all three, and solid points are neither
 // computed nor stored (nothing reads them).  The other columns are wholly
-// interior and only pull.  Their order alternates as in k_step.
-template <class L, typename S, typename M, int TH>
+// interior and only pull.  Their order alternates as in k_step.  OPEN: open x
+// ends (the mask's first and last rows are equal, so the wall links are
+// those of the periodic channel): the ghost pulls and the end-node records as
+// in the open step kernel.
+template <class L, typename S, typename M, int TH, bool OPEN = false>
 __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
                                                      S* __restrict__ dst, StepArgs a) {
   int slot = blockIdx.x;
@@ -189,12 +192,30 @@ __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
   M xi[L::Q];
   if constexpr (TH != 0)
     thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+  uint32_t wl = 0u;
   if (wallcol)
-    gather_masked<L, S, M, M>(src, a, col, z, xc, cw, df);
+    gather_masked<L, S, M, M, OPEN>(src, a, col, z, xc, cw, df, &wl);
   else
-    gather_masked_interior<L, S, M>(src, a, col, z, xc, df);
-  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
-                             (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
+    gather_masked_interior<L, S, M, OPEN>(src, a, col, z, xc, df);
+  if constexpr (OPEN) {
+    ColInfo info;
+    info.wallcol = 0;
+    info.mask = wl;
+    open_correct<L, M>(a, col, xc, info, df);
+  }
+  M rec[4];
+  collide_store<L, M, S, TH, OPEN>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
+                                   (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi, rec);
+  if constexpr (OPEN)
+    if (x == xc && (x == 0 || x == a.nx - 1)) {
+      LBM_GLOBAL double* o =
+          gbl(a.bmom_out) + ((x == 0 ? 0 : (int64_t)a.ny * a.nz) + col) * 4;
+      const M rho = static_cast<M>(a.rho0) + rec[0];
+      o[0] = static_cast<double>(rec[0]);
+      o[1] = static_cast<double>(rec[1] / rho);
+      o[2] = static_cast<double>(rec[2] / rho);
+      o[3] = static_cast<double>(rec[3] / rho);
+    }
 }
 
 // Open x ends: the records (sum g, u) of the first and last node of every
@@ -325,7 +346,20 @@ __global__ void __launch_bounds__(512) k_moments(const S* __restrict__ src, Step
   if (x < a.nx && !(MASKED && cw == kCellSolid)) {
     double df[L::Q];
     if constexpr (MASKED) {
-      gather_masked<L, S, double, W>(src, a, col, col / a.ny, x, cw, df);
+      const int z = col / a.ny;
+      if (a.open) {  // reads clamped at the ends, then the ghosts
+        uint32_t wl = 0u;
+        if (cw >= 0)
+          gather_masked<L, S, double, W, true>(src, a, col, z, x, cw, df, &wl);
+        else
+          gather_masked_interior<L, S, double, true>(src, a, col, z, x, df);
+        ColInfo info;
+        info.wallcol = 0;
+        info.mask = wl | ((L::Q == 19 && (z == 0 || z == a.nz - 1)) ? kWrapColumn : 0u);
+        open_patch<L, S, double>(src, a, col, x, info, df);
+      } else {
+        gather_masked<L, S, double, W>(src, a, col, z, x, cw, df);
+      }
     } else {
       ColInfo info;
       info.wallcol = uniform(cs.wallcol);
@@ -924,6 +958,16 @@ hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t st
 template <class L, typename S, typename M>
 static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked, bool open,
                                  bool nt) {
+  if (masked && open) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 1, true>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 2, true>);
+    return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 0, true>);
+  }
+  if (masked) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 1>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 2>);
+    return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 0>);
+  }
   if (open && bouz) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, true, 1>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, true, 2>);
@@ -933,11 +977,6 @@ static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked,
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 1>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 2>);
     return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 0>);
-  }
-  if (masked) {
-    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 1>);
-    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 2>);
-    return reinterpret_cast<const void*>(&k_step_masked<L, S, M, 0>);
   }
   if (elec) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 1, true>);

@@ -139,8 +139,13 @@ def test_open_ends_settings(lbm):
     T = lbm.Channel(19, lbm.TUBE, 8, 12, 12, tau=0.8, precision="f64", tube_radius=4.0,
                     tube_cy=5.5, tube_cz=5.5)
     T.set_open_ends(1.0, 1.0)  # tubes take open ends
-    M = lbm.Channel(9, lbm.MASKED, 8, 6, 1, tau=0.8, precision="f64", solid=np.zeros((6, 8)))
-    with pytest.raises(lbm.LBMError):
+    solid = np.zeros((6, 8), dtype=bool)
+    solid[0] = True
+    M = lbm.Channel(9, lbm.MASKED, 8, 6, 1, tau=0.8, precision="f64", solid=solid)
+    M.set_open_ends(1.0, 1.0)  # equal first and last rows of the mask
+    solid[1, 7] = True
+    M = lbm.Channel(9, lbm.MASKED, 8, 6, 1, tau=0.8, precision="f64", solid=solid)
+    with pytest.raises(lbm.LBMError):  # the last row differs from the first
         M.set_open_ends(1.0, 1.0)
     S1 = lbm.Channel(9, lbm.SLAB, 1, 6, 1, tau=0.8, precision="f64")
     with pytest.raises(lbm.LBMError):
