@@ -465,22 +465,20 @@ lbm_status upload_wall_r(lbm_ctx* c, const double* lambda_dev, int64_t n) {
 
 namespace {
 
-double* bmom_buf(lbm_ctx* c, int b) {
-  return c->at<double>(c->pl.off_bmom) + (size_t)b * 2 * c->pl.ncolbox * 4;
-}
+double* bmom_buf(lbm_ctx* c, int b) { return lbm_host::end_records(c, b); }
+
+}  // namespace
 
 // Open ends: the step kernels leave the end-node records of the buffer they
 // write; after the state was set from outside, rebuild them for the current
 // buffer once.
-lbm_status ensure_end_records(lbm_ctx* c) {
+lbm_status lbm_host::ensure_end_records(lbm_ctx* c) {
   if (c->bmom_ok) return LBM_OK;
   HIPCHK(c, lbm::launch_open_moments(c->pl.Q, c->pl.prec, c->pop[c->cur], c->args,
                                      bmom_buf(c, c->cur), c->stream));
   c->bmom_ok = true;
   return LBM_OK;
 }
-
-}  // namespace
 
 lbm_status lbm_host::launch_one_step(lbm_ctx* c, bool check) {
   StepArgs a = c->args;

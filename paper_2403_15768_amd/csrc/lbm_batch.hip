@@ -56,7 +56,8 @@ struct lbm_batch {
   char* arena = nullptr;
   int Q = 0, prec = 0;
   bool bouz = false;
-  int th = 0;  // every member's thermal-noise form (0: none)
+  int th = 0;         // every member's thermal-noise form (0: none)
+  bool open = false;  // every member's x ends open (else periodic)
   int cap_members = 0;
   int64_t cap_items = 0, cap_cols = 0;
   // member slots (nullptr: free) and what the member table on the device
@@ -66,6 +67,7 @@ struct lbm_batch {
   std::vector<double> th_amp;
   std::vector<uint64_t> th_seed;
   std::vector<std::array<double, 6>> th_fac;
+  std::vector<std::array<double, 2>> ends;  // the open ends' densities (rho - rho0)
   std::vector<int> gof;                // group of each slot (-1: free)
   std::vector<int64_t> mstart, mcount;  // each slot's entries in the order array
   struct Group {
@@ -268,9 +270,11 @@ lbm_status check_member(const lbm_batch* b, const lbm_ctx* c) {
   if (c->p.lattice != b->Q || c->p.precision != b->prec ||
       (c->p.geometry == LBM_TUBE) != b->bouz)
     return LBM_EINVAL;
-  // one noise form for the whole batch (each member its own kT and seed);
-  // the batch kernel has no electron sheets, masked walls or open ends
-  if (c->args.th_mode != b->th || c->elec || c->pl.masked || c->args.open) return LBM_EINVAL;
+  // one noise form and one kind of x ends for the whole batch (each member
+  // its own kT, seed and end densities); the batch kernel has no electron
+  // sheets or masked walls
+  if (c->args.th_mode != b->th || (c->args.open != 0) != b->open || c->elec || c->pl.masked)
+    return LBM_EINVAL;
   return LBM_OK;
 }
 
@@ -298,7 +302,7 @@ void layout(lbm_batch* b) {
 lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, hipStream_t st) {
   const lbm_batch::Group& g = b->groups[gi];
   if (g.n == 0) return LBM_OK;
-  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th);
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th, b->open);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int32_t* cols = b->at<int32_t>(b->off_cols);
@@ -395,6 +399,8 @@ MemberDesc describe(const lbm_ctx* c, int64_t k) {
   d.a.step_off = 0;
   d.pop[0] = c->pop[0];
   d.pop[1] = c->pop[1];
+  d.bmom[0] = end_records(const_cast<lbm_ctx*>(c), 0);
+  d.bmom[1] = end_records(const_cast<lbm_ctx*>(c), 1);
   d.base_step = c->step - k;
   d.cur_base = (int32_t)((c->cur + k) & 1);  // (cur_base + k) & 1 == cur
   return d;
@@ -404,7 +410,9 @@ MemberDesc describe(const lbm_ctx* c, int64_t k) {
 // its own queued work)
 lbm_status write_desc(lbm_batch* b, int s) {
   lbm_ctx* c = b->m[s];
-  lbm_status st = sync(c);
+  // open ends: the records of the buffer the member's next step reads
+  lbm_status st = c->args.open ? ensure_end_records(c) : LBM_OK;
+  if (st == LBM_OK) st = sync(c);
   if (st != LBM_OK) return b->fail(st, "member stream failed");
   const MemberDesc d = describe(c, b->k);
   BCHK(b, hipMemcpyAsync(b->at<MemberDesc>(b->off_desc) + s, &d, sizeof d, hipMemcpyHostToDevice,
@@ -414,6 +422,7 @@ lbm_status write_desc(lbm_batch* b, int s) {
   b->th_amp[s] = c->args.th_amp;
   b->th_seed[s] = c->args.th_seed;
   std::copy(c->args.th_fac, c->args.th_fac + 6, b->th_fac[s].begin());
+  b->ends[s] = {c->args.drho_in, c->args.drho_out};
   return LBM_OK;
 }
 
@@ -425,7 +434,9 @@ lbm_status resync(lbm_batch* b) {
     if (!c) continue;
     if (c->step == b->base[s] + b->k && c->args.th_amp == b->th_amp[s] &&
         c->args.th_seed == b->th_seed[s] &&
-        std::equal(b->th_fac[s].begin(), b->th_fac[s].end(), c->args.th_fac))
+        std::equal(b->th_fac[s].begin(), b->th_fac[s].end(), c->args.th_fac) &&
+        c->args.drho_in == b->ends[s][0] && c->args.drho_out == b->ends[s][1] &&
+        (!c->args.open || c->bmom_ok))
       continue;
     lbm_status st = write_desc(b, (int)s);
     if (st != LBM_OK) return st;
@@ -439,7 +450,7 @@ lbm_status build_graph(lbm_batch* b, size_t gi) {
   lbm_batch::Group& grp = b->groups[gi];
   hipGraph_t g = nullptr;
   BCHK(b, hipGraphCreate(&g, 0));
-  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th);
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th, b->open);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int32_t* cols = b->at<int32_t>(b->off_cols);
@@ -635,6 +646,7 @@ lbm_status init_batch(lbm_batch* b, void* arena, size_t arena_bytes, void* hip_s
   b->th_amp.assign(b->cap_members, 0.0);
   b->th_seed.assign(b->cap_members, 0);
   b->th_fac.assign(b->cap_members, std::array<double, 6>{});
+  b->ends.assign(b->cap_members, std::array<double, 2>{});
   b->gof.assign(b->cap_members, -1);
   b->mstart.assign(b->cap_members, 0);
   b->mcount.assign(b->cap_members, 0);
@@ -667,10 +679,10 @@ lbm_status take_member(lbm_batch* b, int s, lbm_ctx* c) {
 // noise form and the size bucket (log2 of the fluid cells, log2 of the
 // members).  Shared by every batch of the process.
 struct TuneKey {
-  int Q, prec, bouz, th, cells_log2, members_log2;
+  int Q, prec, bouz, th, open, cells_log2, members_log2;
   bool operator<(const TuneKey& o) const {
-    return std::tie(Q, prec, bouz, th, cells_log2, members_log2) <
-           std::tie(o.Q, o.prec, o.bouz, o.th, o.cells_log2, o.members_log2);
+    return std::tie(Q, prec, bouz, th, open, cells_log2, members_log2) <
+           std::tie(o.Q, o.prec, o.bouz, o.th, o.open, o.cells_log2, o.members_log2);
   }
 };
 std::mutex g_tune_mu;
@@ -692,7 +704,7 @@ TuneKey tune_key(const lbm_batch* b) {
       cells += c->pl.nfluid;
       n++;
     }
-  return TuneKey{b->Q, b->prec, b->bouz ? 1 : 0, b->th, ilog2(cells), ilog2(n)};
+  return TuneKey{b->Q, b->prec, b->bouz ? 1 : 0, b->th, b->open ? 1 : 0, ilog2(cells), ilog2(n)};
 }
 
 // Time `reps` steps of every group with the current shape, grouping and
@@ -765,8 +777,8 @@ lbm_status lbm_batch_create_spec(const lbm_batch_spec* sp, void* arena, size_t a
   if (!out) return LBM_EINVAL;
   *out = nullptr;
   if (!sp || (sp->lattice != 9 && sp->lattice != 19) || sp->precision < 0 || sp->precision > 2 ||
-      sp->noise < 0 || sp->noise > 2 || sp->max_members < 1 || sp->max_items < 0 ||
-      sp->max_columns < 0)
+      sp->noise < 0 || sp->noise > 2 || (sp->open_ends != 0 && sp->open_ends != 1) ||
+      sp->max_members < 1 || sp->max_items < 0 || sp->max_columns < 0)
     return LBM_EINVAL;
   if (!arena || reinterpret_cast<uintptr_t>(arena) % kAlign) return LBM_EINVAL;
   lbm_batch* b = new (std::nothrow) lbm_batch();
@@ -775,6 +787,7 @@ lbm_status lbm_batch_create_spec(const lbm_batch_spec* sp, void* arena, size_t a
   b->prec = sp->precision;
   b->bouz = sp->tube != 0;
   b->th = sp->noise;
+  b->open = sp->open_ends != 0;
   b->cap_members = sp->max_members;
   b->cap_items = sp->max_items;
   b->cap_cols = sp->max_columns;
@@ -798,6 +811,7 @@ lbm_status lbm_batch_footprint(lbm_ctx* const* ctxs, int n, size_t* bytes) {
   kind.prec = ctxs[0]->p.precision;
   kind.bouz = ctxs[0]->p.geometry == LBM_TUBE;
   kind.th = ctxs[0]->args.th_mode;
+  kind.open = ctxs[0]->args.open != 0;
   for (int i = 0; i < n; i++) {
     if (!ctxs[i] || check_member(&kind, ctxs[i]) != LBM_OK) return LBM_EINVAL;
     sp.max_items += member_items_max(ctxs[i]);
@@ -816,6 +830,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   sp.precision = ctxs[0]->p.precision;
   sp.tube = ctxs[0]->p.geometry == LBM_TUBE;
   sp.noise = ctxs[0]->args.th_mode;
+  sp.open_ends = ctxs[0]->args.open != 0;
   sp.max_members = n;
   for (int i = 0; i < n; i++) {
     if (!ctxs[i]) return LBM_EINVAL;
@@ -857,8 +872,8 @@ lbm_status lbm_batch_add(lbm_batch* b, lbm_ctx* c, int* slot) {
     if (x == c) return b->fail(LBM_EINVAL, "the context is a member already");
   if (check_member(b, c) != LBM_OK)
     return b->fail(LBM_EINVAL, "the context differs from the batch in lattice, precision, wall "
-                               "kind or noise form, or has electron lines, masked walls or open "
-                               "ends");
+                               "kind, noise form or kind of x ends, or has electron lines or "
+                               "masked walls");
   int s = -1;
   for (int i = 0; i < b->cap_members && s < 0; i++)
     if (!b->m[i]) s = i;
@@ -958,8 +973,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0 || b->groups.empty()) return LBM_OK;
   for (const lbm_ctx* c : b->m)
-    if (c && (c->args.th_mode != b->th || c->elec || c->args.open)) {
-      b->err = "a member's noise form changed or its electron sheets or open ends are on; "
+    if (c && (c->args.th_mode != b->th || c->elec || (c->args.open != 0) != b->open)) {
+      b->err = "a member's noise form or kind of x ends changed or its electron sheets are on; "
                "remove it from the batch";
       return LBM_EINVAL;
     }

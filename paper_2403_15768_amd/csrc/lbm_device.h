@@ -169,6 +169,7 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 struct MemberDesc {
   StepArgs a;
   const void* pop[2];
+  double* bmom[2];  // open ends: the end-node records of pop[0] and pop[1]
   int64_t base_step;
   int32_t cur_base;
   int32_t pad;
@@ -565,12 +566,13 @@ __device__ __forceinline__ void open_patch(const S* __restrict__ g0, const StepA
   const bool wrap = (mask & kWrapColumn) != 0u;
   const unsigned ux = (unsigned)x;
   // the ghost value of population k of a ghost next to the end node of the
-  // column whose base is cb (the end of this lane's x)
+  // column whose base is cb (the end of this lane's x).  Per-lane pointers:
+  // the lanes of a batch work item may sit in different columns.
   auto ghost_shift = [&](const LBM_GLOBAL S* cb, int k, bool at_in, M* gk) {
     M drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int m = 0; m < L::Q; m++) {
-      const M v = ld<S, M>(sbase(cb + L::row[m] * a.sI), ux);
+      const M v = ld<S, M>(cb + L::row[m] * a.sI, ux);
       drho += v;
       if (L::cx[m]) jx += L::cx[m] > 0 ? v : -v;
       if (L::cy[m]) jy += L::cy[m] > 0 ? v : -v;
@@ -649,16 +651,17 @@ __device__ __forceinline__ void end_record(const LBM_GLOBAL S* gc, const StepArg
 // read g_i(b)): for the first (last) node of an x-line, each fluid link that
 // would pull from x = -1 (x = nx) gains
 //   w_i (drho_bc - drho_b) (1 + 3 c_i.u_b + 4.5 (c_i.u_b)^2 - 1.5 u_b.u_b)
-// from b's record (a.bmom).  Lanes inside the line return at once.
+// from b's record (bmom: the records of the buffer the step reads,
+// [side][column][4]).  Lanes inside the line return at once.
 template <class L, typename M, bool BOUZ = false>
-__device__ __forceinline__ void open_correct(const StepArgs& a, int col, int x, ColInfo info,
-                                             M* df) {
+__device__ __forceinline__ void open_correct(const StepArgs& a, const double* bmom, int col, int x,
+                                             ColInfo info, M* df) {
   const bool in = x == 0, out = x == a.nx - 1;
   if (!in && !out) return;
   const uint32_t mask = info.mask;
   const int z = col / a.ny;
   const int y = col - z * a.ny;
-  const LBM_GLOBAL double* bm_in = gbl(a.bmom);
+  const LBM_GLOBAL double* bm_in = gbl(bmom);
   const LBM_GLOBAL double* bm_out = bm_in + (int64_t)a.ny * a.nz * 4;
   // w_k (drho_bc - drho_b) (1 + 3 c_k.u_b + 4.5 (c_k.u_b)^2 - 1.5 u_b.u_b)
   auto shift = [&](const LBM_GLOBAL double* r, int k, bool at_in) {

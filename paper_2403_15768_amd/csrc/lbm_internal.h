@@ -127,6 +127,13 @@ inline lbm::SpecArgs spec_args(const lbm_spectral* sp) {
                        sp->w_max, sp->lambda_target, sp->dispersion, sp->coupling, sp->v_l};
 }
 lbm_status sync(lbm_ctx* c);
+// open ends: the end-node records ([side][column][4]) of population buffer b
+inline double* end_records(lbm_ctx* c, int b) {
+  return c->at<double>(c->pl.off_bmom) + (size_t)b * 2 * c->pl.ncolbox * 4;
+}
+// rebuild the records of the current buffer if no step has left them
+// (asynchronous, on the context's stream)
+lbm_status ensure_end_records(lbm_ctx* c);
 // one plain step launch; check: the step also leaves the per-block partials
 // of the invariants of the state it reads (see lbm_step_checked)
 lbm_status launch_one_step(lbm_ctx* c, bool check = false);

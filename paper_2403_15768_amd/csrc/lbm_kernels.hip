@@ -57,7 +57,7 @@ __device__ __forceinline__ void step_cell(const S* __restrict__ src, S* __restri
   if constexpr (TH != 0)
     thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)col * (uint32_t)a.nx + (uint32_t)x, step, xi);
   gather<L, S, M, M, BOUZ, ELEC, OPEN>(src, a, col, xc, info, df);
-  if constexpr (OPEN) open_correct<L, M, BOUZ>(a, col, xc, info, df);
+  if constexpr (OPEN) open_correct<L, M, BOUZ>(a, a.bmom, col, xc, info, df);
   if constexpr (CHECK) {
     if (x < a.nx) {
       double dr = 0, jx = 0;
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
     ColInfo info;
     info.wallcol = 0;
     info.mask = wl;
-    open_correct<L, M>(a, col, xc, info, df);
+    open_correct<L, M>(a, a.bmom, col, xc, info, df);
   }
   M rec[4];
   collide_store<L, M, S, TH, OPEN>(df, a, gbl(dst) + (int64_t)col * a.sC, (unsigned)x,
@@ -723,7 +723,7 @@ __device__ __forceinline__ void run_cols(const int32_t* cols, const WorkItem& it
   *cc = item.c0 + 2 < item.ncols ? uniform(cl[2]) : *ca;
 }
 
-template <class L, typename S, typename M, bool BOUZ, int TH = 0>
+template <class L, typename S, typename M, bool BOUZ, int TH = 0, bool OPEN = false>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ cols,
@@ -765,10 +765,24 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   if constexpr (TH != 0)
     thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
                             xi);
-  gather<L, S, M, M, BOUZ>(src, a, colA, xc, info, df, c.dl);
-  collide_store<L, M, S, TH>(df, a, gbl(dst) + (int64_t)colA * a.sC, c.dl + (unsigned)c.x,
-                             (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
-                             xi);
+  gather<L, S, M, M, BOUZ, false, OPEN>(src, a, colA, xc, info, df, c.dl);
+  // open ends: the ghosts from the records of the buffer read (the lane's own
+  // column: runs of plain columns have no wall links or z wrap)
+  if constexpr (OPEN) open_correct<L, M, BOUZ>(a, d.bmom[odd ? 1 : 0], c.col, xc, info, df);
+  M rec[4];
+  collide_store<L, M, S, TH, OPEN>(df, a, gbl(dst) + (int64_t)colA * a.sC, c.dl + (unsigned)c.x,
+                                   (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x,
+                                   d.base_step + k, xi, rec);
+  if constexpr (OPEN)
+    if (c.x == xc && (c.x == 0 || c.x == a.nx - 1)) {
+      LBM_GLOBAL double* o = gbl(d.bmom[odd ? 0 : 1]) +
+                             ((c.x == 0 ? 0 : (int64_t)a.ny * a.nz) + c.col) * 4;
+      const M rho = static_cast<M>(a.rho0) + rec[0];
+      o[0] = static_cast<double>(rec[0]);
+      o[1] = static_cast<double>(rec[1] / rho);
+      o[2] = static_cast<double>(rec[2] / rho);
+      o[3] = static_cast<double>(rec[3] / rho);
+    }
 }
 
 // per-item partial sums of (j_x, rho - rho0) of items [first, first + count);
@@ -799,7 +813,12 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
     info.wallcol = item.wallcol;
     info.mask = item.mask;
     double df[L::Q];
-    gather<L, S, double, W, BOUZ>(src, a, colA, c.x, info, df, c.dl);
+    if (a.open) {  // reads clamped at the ends, then the ghosts
+      gather<L, S, double, W, BOUZ, false, true>(src, a, colA, c.x, info, df, c.dl);
+      open_patch<L, S, double, BOUZ, W>(src, a, c.col, c.x, info, df);
+    } else {
+      gather<L, S, double, W, BOUZ>(src, a, colA, c.x, info, df, c.dl);
+    }
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
       dr += df[i];
@@ -863,7 +882,17 @@ hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st) {
 const void* add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_add_step); }
 
 template <class L, typename S, typename M>
-static const void* batch_kernel_t(bool bouz, int th) {
+static const void* batch_kernel_t(bool bouz, int th, bool open) {
+  if (open && bouz) {
+    if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 1, true>);
+    if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 2, true>);
+    return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 0, true>);
+  }
+  if (open) {
+    if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 1, true>);
+    if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 2, true>);
+    return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 0, true>);
+  }
   if (bouz) {
     if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 1>);
     if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 2>);
@@ -873,15 +902,15 @@ static const void* batch_kernel_t(bool bouz, int th) {
   if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 2>);
   return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 0>);
 }
-const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th) {
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th, bool open) {
   if (q == 9) {
-    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz, th);
-    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz, th);
-    return batch_kernel_t<D2Q9, _Float16, float>(bouz, th);
+    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz, th, open);
+    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz, th, open);
+    return batch_kernel_t<D2Q9, _Float16, float>(bouz, th, open);
   }
-  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz, th);
-  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz, th);
-  return batch_kernel_t<D3Q19, _Float16, float>(bouz, th);
+  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz, th, open);
+  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz, th, open);
+  return batch_kernel_t<D3Q19, _Float16, float>(bouz, th, open);
 }
 
 template <class L, typename S, typename W>

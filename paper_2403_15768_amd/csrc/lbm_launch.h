@@ -72,7 +72,8 @@ const void* add_step_kernel_ptr();  // k_add_step(int64_t* d, int64_t v)
 hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* out, int nxp_out,
                           int64_t rows, int nx, hipStream_t st);
 // batches
-const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th);  // th: noise form
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th,
+                                  bool open);  // th: noise form; open: open x ends
 // k_batch_step(const MemberDesc*, const WorkItem*, const int32_t* cols, int64_t first,
 //              int64_t nwall, int64_t last, const int64_t* bstep, int64_t step_off, int wpb)
 // per-item partials of the flux and mass of items [first, first + count)

@@ -451,3 +451,119 @@ def test_tuning_is_cached_and_never_changes_results(lbm):
         (t["waves_per_group"], t["group_bytes"], t["streams"])
     b.close()
     b2.close()
+
+
+# ---------------------------------------------------------- open x ends
+# members with open ends (each its own end densities) step bit for bit as
+# alone: the batch kernel takes the ghosts from each member's end-node records
+OPEN_SPECS = SPECS + [(150, 9, 7, 0.8, 1e-6)]  # and one padded x-line
+
+
+def open_ducts(lbm, precision):
+    chans = make_ducts(lbm, OPEN_SPECS, precision)
+    for k, ch in enumerate(chans):
+        ch.set_open_ends(1.0 + 1e-5 * (k + 1), 1.0 - 0.7e-5 * (k + 1))
+    return chans
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_open_end_batch_bit_identical_to_alone(lbm, precision):
+    say("open batch vs alone", precision)
+    alone = open_ducts(lbm, precision)
+    mixed = open_ducts(lbm, precision)
+    for ch in alone + mixed:
+        ch.step(20)
+    alone[2].step(1)
+    mixed[2].step(1)
+    b = lbm.Batch(mixed)
+    b.step(150)
+    for ch in alone:
+        ch.step(150)
+    for a, m in zip(alone, mixed):
+        assert m.step_count == a.step_count
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    inv = b.invariants()
+    for k, a in enumerate(alone):
+        q, mass, _ = a.invariants()
+        assert abs(inv[k, 0] / q - 1) < 1e-13
+        assert abs(inv[k, 1] / mass - 1) < 1e-14
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16s"])
+def test_open_end_tube_batch_bit_identical_to_alone(lbm, precision):
+    say("open tube batch vs alone", precision)
+
+    def tubes():
+        out = []
+        for k, (R, nx, seed) in enumerate(TUBES):
+            n = int(2 * R + 4)
+            c = (n - 1) / 2
+            t = lbm.Channel(19, lbm.TUBE, nx, n, n, tau=0.8, force=(1e-6, 0, 0),
+                            precision=precision, tube_radius=float(R), tube_cy=c, tube_cz=c)
+            t.set_friction(np.random.default_rng(seed).uniform(0.0, 0.3, t.wall_count))
+            t.set_open_ends(1.0 + 2e-5, 1.0 - 1e-5 * (k + 1))
+            out.append(t)
+        return out
+
+    alone, mixed = tubes(), tubes()
+    b = lbm.Batch(mixed)
+    b.step(137)
+    for a, m in zip(alone, mixed):
+        a.step(137)
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    b.close()
+
+
+def test_open_end_batch_fp64_against_oracle(lbm):
+    say("open batch vs oracle")
+    chans = open_ducts(lbm, "f64")
+    b = lbm.Batch(chans)
+    b.step(229)
+    for k in (0, 3, 5):
+        nx, ny, nz, tau, g = OPEN_SPECS[k]
+        o = oracle.Lattice(19, oracle.DUCT, nx, ny, nz, tau=tau, force=(g, 0, 0))
+        o.set_friction(inputs.duct_friction(o.wall_coords(), nx, ny, nz,
+                                            inputs.rng_for("batch", 100 + k), sigma=6.0))
+        o.set_open_ends(1.0 + 1e-5 * (k + 1), 1.0 - 0.7e-5 * (k + 1))
+        o.step(229)
+        ug, uo = chans[k].field(1), o.fields()[1]
+        err = np.max(np.abs(ug - uo)) / np.max(np.abs(uo))
+        say(f"  member {k}: {err:.2e}")
+        assert err < 1e-12
+    b.close()
+
+
+def test_open_end_members_join_leave_and_change_densities(lbm):
+    # open-ended members join a running batch, one changes its end densities
+    # between batch steps, one leaves and steps alone: bit for bit the
+    # channels stepped alone; periodic channels are refused
+    say("open batch add / remove")
+    alone = open_ducts(lbm, "f32")
+    mixed = open_ducts(lbm, "f32")
+    cap = capacity_for(lbm, mixed, members=4, slack=2)
+    b = lbm.Batch.empty(19, "f32", False, open_ends=True, **cap)
+    periodic = make_ducts(lbm, SPECS[:1], "f32")[0]
+    with pytest.raises(lbm.LBMError):
+        b.add(periodic)
+    for k in (0, 1, 5):
+        b.add(mixed[k])
+    b.step(70)
+    for k in (0, 1, 5):
+        alone[k].step(70)
+    for ch in (mixed[1], alone[1]):
+        ch.set_open_ends(1.0 + 4e-5, 1.0 - 1e-5)
+    b.step(64)
+    for k in (0, 1, 5):
+        alone[k].step(64)
+    b.remove(mixed[0])
+    mixed[0].step(9)
+    alone[0].step(9)
+    b.add(mixed[0])
+    b.add(mixed[3])
+    b.step(131)
+    for k in (0, 1, 3, 5):
+        alone[k].step(131)
+    for k in (0, 1, 3, 5):
+        assert np.array_equal(alone[k].get_state()[0], mixed[k].get_state()[0]), k
+    b.close()
