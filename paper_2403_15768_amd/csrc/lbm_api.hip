@@ -635,22 +635,30 @@ lbm_status do_steps(lbm_ctx* c, int64_t n) {
 }
 
 // the fixed-order reduction of the per-block partials in the arena; the
-// device out slot then holds (sums, flux, mass, mass deviation)
-lbm_status launch_reduce(lbm_ctx* c) {
+// device out slot (and with to_host the context's pinned host buffer) then
+// holds (sums, flux, mass, mass deviation)
+lbm_status launch_reduce(lbm_ctx* c, bool to_host = false) {
   HIPCHK(c, lbm::launch_reduce_final(c->at<double>(c->pl.off_partials), c->pl.nblocks,
                                      c->at<double>(c->pl.off_out), c->pl.nx,
-                                     (double)c->pl.nfluid * c->p.rho0, c->stream));
+                                     (double)c->pl.nfluid * c->p.rho0, c->stream,
+                                     to_host ? c->fin_host_dev : nullptr));
   return LBM_OK;
 }
 
 // The per-block partials in the arena -> (flux, mass, mass deviation):
-// fixed-order reduction, copy to the host, synchronise.
+// fixed-order reduction, synchronise; the reduce kernel writes the result
+// straight into pinned host memory (else it is copied from the device).
 lbm_status reduce_partials(lbm_ctx* c, double out[3]) {
-  lbm_status s = launch_reduce(c);
+  lbm_status s = launch_reduce(c, c->fin_host != nullptr);
   if (s != LBM_OK) return s;
-  HIPCHK(c, hipMemcpyAsync(out, c->at<double>(c->pl.off_out) + 2, 3 * sizeof(double),
-                           hipMemcpyDeviceToHost, c->stream));
-  if ((s = sync(c)) != LBM_OK) return s;
+  if (c->fin_host) {
+    if ((s = sync(c)) != LBM_OK) return s;
+    std::copy(c->fin_host + 2, c->fin_host + 5, out);
+  } else {
+    HIPCHK(c, hipMemcpyAsync(out, c->at<double>(c->pl.off_out) + 2, 3 * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    if ((s = sync(c)) != LBM_OK) return s;
+  }
   if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
     return c->fail(LBM_EDIVERGED, "flux or mass is not finite");
   return LBM_OK;
@@ -752,12 +760,29 @@ lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void
     lbm_destroy(c);
     return st;
   }
+  // pinned host memory the reduce kernel writes its result to; without it
+  // the result is copied from the device
+  void* h = nullptr;
+  if (hipHostMalloc(&h, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess && h) {
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess && d) {
+      c->fin_host = static_cast<double*>(h);
+      c->fin_host_dev = static_cast<double*>(d);
+    } else {
+      (void)hipHostFree(h);
+    }
+  }
+  (void)hipGetLastError();
   *out = c;
   return LBM_OK;
 }
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
+  if (c->fin_host) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipHostFree(c->fin_host);
+  }
   for (int k = 0; k < 2; k++) {
     if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
     if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);

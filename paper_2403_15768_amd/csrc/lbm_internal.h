@@ -81,6 +81,10 @@ struct lbm_ctx {
   bool elec = false;        // electron sheets on (SLAB)
   bool bmom_ok = false;     // open ends: end-node records of pop[cur] are current
   int64_t checked_step = -1;  // step whose invariants' partials the arena holds (-1: none)
+  // 8 doubles of pinned host memory the reduce kernel writes the invariants
+  // to, through fin_host_dev (null if none could be had)
+  double* fin_host = nullptr;
+  double* fin_host_dev = nullptr;
   int step_bx = 0;  // threads per block of the plain step launches (0: the plan's default)
   lbm::ElecArgs ea{};
 

@@ -404,7 +404,8 @@ constexpr int kReduceThreads = 1024;
 __global__ void __launch_bounds__(kReduceThreads) k_reduce_final(const double* __restrict__ partials,
                                                                  int64_t nblocks,
                                                                  double* __restrict__ out, int nx,
-                                                                 double mass0) {
+                                                                 double mass0,
+                                                                 double* __restrict__ out_host) {
   __shared__ double red[2][kReduceThreads / 64];
   const double2* p2 = reinterpret_cast<const double2*>(partials);
   double t0 = 0, t1 = 0;
@@ -428,11 +429,11 @@ __global__ void __launch_bounds__(kReduceThreads) k_reduce_final(const double* _
       s0 += red[0][k];
       s1 += red[1][k];
     }
-    out[0] = s0;
-    out[1] = s1;
-    out[2] = s0 / nx;
-    out[3] = mass0 + s1;
-    out[4] = s1;
+    const double v[5] = {s0, s1, s0 / nx, mass0 + s1, s1};
+    for (int k = 0; k < 5; k++) {
+      out[k] = v[k];
+      if (out_host) out_host[k] = v[k];  // pinned host memory: no copy needed
+    }
   }
 }
 
@@ -1165,9 +1166,9 @@ hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, b
 }
 
 hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out, int nx,
-                               double mass0, hipStream_t st) {
+                               double mass0, hipStream_t st, double* out_host) {
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, st, partials, nblocks, out,
-                     nx, mass0);
+                     nx, mass0, out_host);
   return hipGetLastError();
 }
 

@@ -60,9 +60,10 @@ const void* open_moments_kernel_ptr(int q, int prec);  // (src, StepArgs, bmom)
 hipError_t launch_moments(int q, int prec, const void* src, const StepArgs& a, bool bouz,
                           int which, double* field, double* partials, hipStream_t st);
 // out[0..4]: sum j_x, sum (rho - rho0), then flux (sum j_x / nx), mass
-// (mass0 + sum (rho - rho0)) and the mass deviation
+// (mass0 + sum (rho - rho0)) and the mass deviation; out_host (pinned host
+// memory, device pointer) receives the same if not null
 hipError_t launch_reduce_final(const double* partials, int64_t nblocks, double* out, int nx,
-                               double mass0, hipStream_t st);
+                               double mass0, hipStream_t st, double* out_host = nullptr);
 hipError_t launch_friction(const SpecArgs& s, const double* omega, int64_t n, double* raw,
                            double* lambda, hipStream_t st);
 hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st);
