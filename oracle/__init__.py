@@ -107,6 +107,8 @@ def _lib(kind: str = "f64") -> C.CDLL:
     lib.ora_get_electrons.argtypes = [vp, dp, dp]
     lib.ora_shell_count.argtypes = [vp]
     lib.ora_shell_count.restype = lp
+    lib.ora_set_electron_populations.argtypes = [vp, dp]
+    lib.ora_set_electron_populations.restype = C.c_int
     lib.ora_sizeof_real.restype = C.c_int
     lib.ora_set_open_ends.argtypes = [vp, C.c_int, C.c_double, C.c_double]
     lib.ora_set_noise_closure.argtypes = [vp, dp, C.c_int, C.c_int, dp, dp]
@@ -212,13 +214,20 @@ class Lattice:
 
     def set_electrons(self, tau_e: float, rho_e0: float, gamma_e: float,
                       force_e: float = 0.0) -> None:
-        """Electron lines in the solid columns next to the water (slab and duct
-        walls), coupled to the water by the relative-velocity wall drag
-        (state reset to rest)."""
+        """Electron lines in the solid columns next to the water (slab, duct
+        and tube walls), coupled to the water by the relative-velocity wall
+        drag (state reset to rest)."""
         if self._lib.ora_set_electrons(self._h, float(tau_e), float(rho_e0), float(gamma_e),
                                        float(force_e)) != 0:
-            raise OracleError("electron sheets need a SLAB or DUCT without moving wall, "
-                              "tau_e > 1/2, rho_e0 > 0, gamma_e >= 0")
+            raise OracleError("electron sheets need a SLAB, DUCT or TUBE without moving wall "
+                              "or open ends, tau_e > 1/2, rho_e0 > 0, gamma_e >= 0")
+
+    def set_electron_populations(self, pops: np.ndarray) -> None:
+        """Replace the electron populations (shifted, [i][shell][x])."""
+        e = np.ascontiguousarray(pops, dtype=np.float64)
+        assert e.shape == (3, self.shell_count, self.nx)
+        if self._lib.ora_set_electron_populations(self._h, _dptr(e)) != 0:
+            raise OracleError("the electron lines are off")
 
     def set_noise_closure(self, gamma=None, wx=None, wt=None) -> None:
         """One-point closure of the quantum noise: gamma shaped (6, nr, ns) (the
@@ -267,7 +276,8 @@ class Lattice:
     def electrons(self):
         """(u_e of the last step [shell][x], shifted populations [i][shell][x]);
         shells: y = -1 (by z), y = ny (by z), then for a duct z = -1 (by y),
-        z = nz (by y)."""
+        z = nz (by y); for a tube the solid columns next to a fluid column
+        along y or z, in increasing y + ny z."""
         ue = np.zeros((self.shell_count, self.nx))
         pops = np.zeros((3, self.shell_count, self.nx))
         self._lib.ora_get_electrons(self._h, _dptr(ue), _dptr(pops))

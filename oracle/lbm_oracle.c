@@ -149,8 +149,11 @@ typedef struct {
    * m_c by which the stress components' variances are scaled, in the order
    * xx, yy, zz, xy, xz, yz (1 = classical) */
   real qfac[6];
-  /* electron shells (SLAB and DUCT): the solid columns next to the water,
-   * each with an electron line along x, D1Q3 (see shell_of) */
+  /* electron shells (SLAB, DUCT and TUBE): the solid columns next to the
+   * water, each with an electron line along x, D1Q3 (see shell_of); TUBE:
+   * their number and the shell of each column of the box (-1: none) */
+  long tube_nsh;
+  long *tube_shell;
   int elec;
   double tau_e, rho_e0, gamma_e, force_e;
   real *e, *en; /* shifted populations [i][shell][x], i = 0, +x, -x */
@@ -216,12 +219,19 @@ static long cell(const ora_ctx *o, int x, int y, int z) {
 
 /* Electron shells: the solid columns next to the water that carry an
  * electron line along x.  Numbering: y = -1 (z = 0..nz-1), then y = ny,
- * then (DUCT only) z = -1 (y = 0..ny-1), then z = nz.  -1 if (ys, zs) is
- * none of them. */
+ * then (DUCT only) z = -1 (y = 0..ny-1), then z = nz.  TUBE: the solid
+ * columns of the box with a fluid column next to them along +-y or +-z (the
+ * only transverse steps of the links that cross x), in increasing y + ny z.
+ * -1 if (ys, zs) is none of them. */
 static long nshell(const ora_ctx *o) {
+  if (o->p.geometry == ORA_TUBE) return o->tube_nsh;
   return 2L * o->p.nz + (o->p.geometry == ORA_DUCT ? 2L * o->p.ny : 0);
 }
 static long shell_of(const ora_ctx *o, int ys, int zs) {
+  if (o->p.geometry == ORA_TUBE) {
+    if (ys < 0 || ys >= o->p.ny || zs < 0 || zs >= o->p.nz) return -1;
+    return o->tube_shell[(long)ys + (long)o->p.ny * zs];
+  }
   if (zs >= 0 && zs < o->p.nz) {
     if (ys == -1) return zs;
     if (ys == o->p.ny) return o->p.nz + zs;
@@ -235,6 +245,15 @@ static long shell_of(const ora_ctx *o, int ys, int zs) {
 /* the shell's solid column (ys, zs) */
 static void shell_column(const ora_ctx *o, long s, int *ys, int *zs) {
   long nz = o->p.nz, ny = o->p.ny;
+  if (o->p.geometry == ORA_TUBE) {
+    long c;
+    for (c = 0; c < ny * nz; c++)
+      if (o->tube_shell[c] == s) {
+        *ys = (int)(c % ny);
+        *zs = (int)(c / ny);
+        return;
+      }
+  }
   if (s < 2 * nz) {
     *ys = s < nz ? -1 : (int)ny;
     *zs = (int)(s % nz);
@@ -406,6 +425,23 @@ int ora_create(const ora_params *p, ora_ctx **out) {
     ora_destroy(o);
     return ORA_EINVAL;
   }
+  if (p->geometry == ORA_TUBE) {
+    o->tube_shell = (long *)malloc(sizeof(long) * p->ny * p->nz);
+    if (!o->tube_shell) {
+      ora_destroy(o);
+      return ORA_ENOMEM;
+    }
+    o->tube_nsh = 0;
+    for (z = 0; z < p->nz; z++)
+      for (y = 0; y < p->ny; y++) {
+        long c = (long)y + (long)p->ny * z;
+        o->tube_shell[c] = -1;
+        if (!is_solid(o, 0, y, z)) continue;
+        if (!is_solid(o, 0, y - 1, z) || !is_solid(o, 0, y + 1, z) ||
+            !is_solid(o, 0, y, z - 1) || !is_solid(o, 0, y, z + 1))
+          o->tube_shell[c] = o->tube_nsh++;
+      }
+  }
   *out = o;
   return ORA_OK;
 }
@@ -418,6 +454,7 @@ void ora_destroy(ora_ctx *o) {
   free(o->ph);
   free(o->phn);
   free(o->up);
+  free(o->tube_shell);
   free(o->fluid);
   free(o->wall_id);
   free(o->r);
@@ -489,7 +526,7 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
                        int i, int sy) {
   long n = cell(o, x, y, z);
   int ib = o->opp[i];
-  real bb, qv;
+  real bb, qv, mw;
   /* moving top wall (Couette check): bounce-back plus the momentum the wall
    * hands over, 6 w_i rho0 (c_i . U) with U along x */
   if (o->p.wall_velocity_top != 0.0 && sy >= o->p.ny)
@@ -497,6 +534,7 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
            6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
                (real)o->p.wall_velocity_top;
   qv = o->qlink[n * 19 + i];
+  mw = 1; /* weight of the moving-wall term in bb */
   if (o->p.geometry != ORA_TUBE) {
     bb = g[(long)ib * o->ncell + n]; /* half-way bounce-back */
   } else if (qv < (real)0.5) {
@@ -519,16 +557,19 @@ static real wall_value(const ora_ctx *o, const real *g, int x, int y, int z,
     }
   } else {
     /* wall farther than half a link: interpolate between the bounced
-     * population and this node's own outgoing population i */
+     * population and this node's own outgoing population i; a moving wall's
+     * term is divided by 2q as well (Bouzidi, Firdaouss and Lallemand), so
+     * that a uniform flow at the wall's velocity stays exact */
     bb = g[(long)ib * o->ncell + n] / (2 * qv) +
          (2 * qv - 1) / (2 * qv) * g[(long)i * o->ncell + n];
+    mw = 1 / (2 * qv);
   }
   if (o->elec && o->c[i][0] != 0) {
     /* the wall moves with the electrons of the solid point x - c_i */
     int xs = ((x - o->c[i][0]) % o->p.nx + o->p.nx) % o->p.nx;
     int zs = z - o->c[i][2];
     if (o->p.geometry == ORA_SLAB) zs = (zs % o->p.nz + o->p.nz) % o->p.nz;
-    bb += 6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
+    bb += mw * 6 * o->w[i] * (real)o->p.rho0 * (real)o->c[i][0] *
           o->ue[shell_of(o, sy, zs) * o->p.nx + xs];
   }
   if (o->p.geometry == ORA_MASKED)
@@ -807,8 +848,7 @@ static void thermal_noise(const ora_ctx *o, long n, long step, real *xi) {
 int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
                       double force_e) {
   long n = nshell(o) * o->p.nx;
-  if (o->p.geometry == ORA_TUBE || o->p.geometry == ORA_MASKED || o->p.wall_velocity_top != 0.0 ||
-      o->open)
+  if (o->p.geometry == ORA_MASKED || o->p.wall_velocity_top != 0.0 || o->open)
     return ORA_EINVAL;
   if (!(tau_e > 0.5) || !(rho_e0 > 0) || !(gamma_e >= 0) || !isfinite(force_e) ||
       !isfinite(tau_e) || !isfinite(rho_e0) || !isfinite(gamma_e))
@@ -861,14 +901,34 @@ static void electron_step(ora_ctx *o) {
       for (k = 0; k < o->q; k++) {
         long cf;
         int xf, yf = ys + o->c[k][1], zf = zs + o->c[k][2];
+        real gob, term, mw = 1;
         if (o->c[k][0] == 0) continue;
         if (o->p.geometry == ORA_SLAB) zf = (zf % o->p.nz + o->p.nz) % o->p.nz;
         if (yf < 0 || yf >= o->p.ny || zf < 0 || zf >= o->p.nz) continue;
         xf = ((x + o->c[k][0]) % o->p.nx + o->p.nx) % o->p.nx;
         cf = cell(o, xf, yf, zf);
         if (!o->fluid[cf]) continue;
-        F0 -= 2 * o->r[cf] * o->g[(long)o->opp[k] * o->ncell + cf] * (real)o->c[k][0];
-        K += 6 * (real)o->p.rho0 * o->r[cf] * o->w[k];
+        /* the axial momentum the water at cf gains through its wall link k
+         * (pulling from this shell node): r c_kx (bb_k + g_opp(k)) summed
+         * over the node's links (the slip half cancels within the node, the
+         * transverse reversal pairing each wall link with an into-wall one
+         * of the same c_x); bb_k's moving-wall part is mw 6 w_k rho0 c_kx u */
+        gob = o->g[(long)o->opp[k] * o->ncell + cf];
+        term = 2 * gob;
+        if (o->p.geometry == ORA_TUBE) {
+          real qv = o->qlink[cf * 19 + k];
+          if (qv < (real)0.5) {
+            int xb = ((xf + o->c[k][0]) % o->p.nx + o->p.nx) % o->p.nx;
+            int yb = yf + o->c[k][1], zb = zf + o->c[k][2];
+            if (!is_solid(o, xb, yb, zb))
+              term += (1 - 2 * qv) * (o->g[(long)o->opp[k] * o->ncell + cell(o, xb, yb, zb)] - gob);
+          } else {
+            term += (2 * qv - 1) / (2 * qv) * (o->g[(long)k * o->ncell + cf] - gob);
+            mw = 1 / (2 * qv);
+          }
+        }
+        F0 -= o->r[cf] * term * (real)o->c[k][0];
+        K += 6 * (real)o->p.rho0 * o->r[cf] * o->w[k] * mw;
       }
       if (!o->phon) {
         u = (j + ((real)o->force_e + F0) / 2) / (rho * (1 + gam / 2) + K / 2);
@@ -973,6 +1033,15 @@ void ora_get_phonons(const ora_ctx *o, double *up, double *pops) {
 /* electron velocity of the last step [shell][x] and the shifted populations
  * [i][shell][x] of the current state (either may be NULL) */
 long ora_shell_count(const ora_ctx *o) { return nshell(o); }
+
+/* Replace the electron populations (shifted, [i][shell][x], 3 nshell nx
+ * values) of a context whose electron lines are on. */
+int ora_set_electron_populations(ora_ctx *o, const double *pops) {
+  long k, n = nshell(o) * o->p.nx;
+  if (!o->elec || !pops) return ORA_EINVAL;
+  for (k = 0; k < 3 * n; k++) o->e[k] = (real)pops[k];
+  return ORA_OK;
+}
 
 void ora_get_electrons(const ora_ctx *o, double *ue, double *pops) {
   long k, n = nshell(o) * o->p.nx;
