@@ -293,6 +293,19 @@ def extras(torch, lbm, inputs, args):
                                      "hbm_frac_fluid_bytes": round(152 * cells / (kms * 1e-3 / 2000)
                                                                    / 1e9 / HBM_PEAK_GBS, 4)}
     tb.close()
+    # the R = 32 nanotube with electron lines in the solid around its wall
+    # (the electron wind of a carbon nanotube): water step plus line step
+    tb = lbm.Channel(lbm.D3Q19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), precision="f32",
+                     tube_radius=float(R), tube_cy=cy, tube_cz=cz)
+    tb.set_friction(0.05)
+    tb.set_electrons(0.9, 1.0, 0.05, 1e-6)
+    tb.step(200)
+    wall, kms = timed_run(torch, tb, 2000, 1000)
+    cells = tb.fluid_count
+    out["tube_r32_f32_electrons"] = {"mlups": round(cells * 2000 / wall / 1e6, 1),
+                                     "step_us": round(kms * 1e3 / 2000, 2),
+                                     "shells": tb.shell_count}
+    tb.close()
     # walls that vary along x: the wrinkled slab (masked walls)
     ch = make_corrugated(lbm, inputs, "f32")
     ch.step(200)

@@ -331,6 +331,10 @@ lbm_status lbm_set_phonons(lbm_ctx *ctx, double tau_p, double rho_p0, double gam
  * populations (3 * nshell * nx, [i][shell][x]); host arrays, either may be
  * NULL.  LBM_ESTATE if the phonons are off.  Synchronous. */
 lbm_status lbm_get_phonons(lbm_ctx *ctx, double *up, double *pops);
+/* Number of electron shells (lines along x) of the channel: SLAB 2 nz, DUCT
+ * 2 nz + 2 ny, TUBE the solid columns with a fluid column next to them along
+ * y or z (numbered by increasing y + ny z), 0 otherwise. */
+lbm_status lbm_shell_count(const lbm_ctx *ctx, size_t *n);
 
 /* Autotuner of the channel kernels: the block width (threads per workgroup
  * along an x-line: 64, 128, 256 or 512, no wider than the x-line) of the

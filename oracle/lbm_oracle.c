@@ -850,6 +850,18 @@ int ora_set_electrons(ora_ctx *o, double tau_e, double rho_e0, double gamma_e,
   long n = nshell(o) * o->p.nx;
   if (o->p.geometry == ORA_MASKED || o->p.wall_velocity_top != 0.0 || o->open)
     return ORA_EINVAL;
+  if (o->p.geometry == ORA_TUBE) {
+    /* every wall link that crosses x must pull from a shell in the box */
+    int y, z, i;
+    for (z = 0; z < o->p.nz; z++)
+      for (y = 0; y < o->p.ny; y++) {
+        if (is_solid(o, 0, y, z)) continue;
+        for (i = 0; i < o->q; i++)
+          if (o->c[i][0] != 0 && is_solid(o, 0, y - o->c[i][1], z - o->c[i][2]) &&
+              shell_of(o, y - o->c[i][1], z - o->c[i][2]) < 0)
+            return ORA_EINVAL;
+      }
+  }
   if (!(tau_e > 0.5) || !(rho_e0 > 0) || !(gamma_e >= 0) || !isfinite(force_e) ||
       !isfinite(tau_e) || !isfinite(rho_e0) || !isfinite(gamma_e))
     return ORA_EINVAL;

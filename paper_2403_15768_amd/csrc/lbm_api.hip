@@ -343,6 +343,50 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
         return LBM_EINVAL;
       }
     }
+  } else if (p->geometry == LBM_TUBE) {
+    // electron shells: the solid columns with a fluid column next to them
+    // along y or z (the transverse steps of the links that cross x), in
+    // increasing column index; each records its fluid neighbours
+    pl.shellof.assign(pl.ncolbox, -1);
+    pl.sheet_wc.clear();
+    int64_t nshell = 0;
+    const int dy[4] = {-1, 1, 0, 0}, dz[4] = {0, 0, -1, 1};
+    for (int z = 0; z < p->nz; z++)
+      for (int y = 0; y < p->ny; y++) {
+        if (fluid_at(y, z)) continue;
+        int32_t nb[8];
+        bool any = false;
+        for (int d = 0; d < 4; d++) {
+          const int yf = y + dy[d], zf = z + dz[d];
+          nb[2 * d] = nb[2 * d + 1] = -1;
+          if (!fluid_at(yf, zf)) continue;
+          const int64_t cf = yf + (int64_t)p->ny * zf;
+          if (pl.colinfo[cf].wallcol < 0) {
+            if (err) *err = "internal: fluid column next to the wall without wall links";
+            return LBM_EINVAL;
+          }
+          nb[2 * d] = (int32_t)cf;
+          nb[2 * d + 1] = pl.colinfo[cf].wallcol;
+          any = true;
+        }
+        if (!any) continue;
+        pl.shellof[y + (int64_t)p->ny * z] = (int32_t)nshell++;
+        pl.sheet_wc.insert(pl.sheet_wc.end(), nb, nb + 8);
+      }
+    pl.nsheet = nshell * pl.nx;
+    // electron lines need every wall link that crosses x to pull from a
+    // shell inside the box (a tube touching the box's edge has none there)
+    for (const lbm::ColSlot& cs : pl.slots) {
+      if (cs.wallcol < 0) continue;
+      const int y = cs.col % p->ny, z = cs.col / p->ny;
+      for (int i = 0; i < pl.Q; i++) {
+        if (!(cs.mask & (1u << i)) || lat_c(pl.Q, i, 0) == 0) continue;
+        const int ys = y - lat_c(pl.Q, i, 1), zs = z - lat_c(pl.Q, i, 2);
+        if (ys < 0 || ys >= p->ny || zs < 0 || zs >= p->nz ||
+            pl.shellof[ys + (int64_t)p->ny * zs] < 0)
+          pl.shells_whole = false;
+      }
+    }
   }
 
   size_t off = 0;
@@ -368,6 +412,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_e[1] = take((size_t)pl.nsheet * 6 * sizeof(double));
   pl.off_ue = take((size_t)pl.nsheet * 2 * sizeof(double));
   pl.off_swc = take(pl.sheet_wc.size() * sizeof(int32_t));
+  pl.off_shellof = take(pl.shellof.size() * sizeof(int32_t));
   pl.off_cellw = take(pl.cellw.size() * sizeof(int32_t));
   // open ends: per population buffer, [side][column][4] records of the end nodes
   pl.off_bmom = take((size_t)2 * 2 * pl.ncolbox * 4 * sizeof(double));
@@ -426,6 +471,7 @@ void fill_args(lbm_ctx* c) {
   a.th_seed = 0;
   for (int k = 0; k < 6; k++) a.th_fac[k] = 1.0;
   a.ue = nullptr;
+  a.shellof = pl.shellof.empty() ? nullptr : c->at<int32_t>(pl.off_shellof);
   a.cellw = pl.masked ? c->at<int32_t>(pl.off_cellw) : nullptr;
   a.ptab = pl.masked ? c->at<uint8_t>(pl.off_ptab) : nullptr;
   a.nw2d = pl.nw2d;
@@ -738,6 +784,9 @@ lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void
     if (!pl.sheet_wc.empty() &&
         (st = upload(c, pl.off_swc, pl.sheet_wc.data(), pl.sheet_wc.size() * sizeof(int32_t))) != LBM_OK)
       break;
+    if (!pl.shellof.empty() &&
+        (st = upload(c, pl.off_shellof, pl.shellof.data(), pl.shellof.size() * sizeof(int32_t))) != LBM_OK)
+      break;
     if (pl.masked &&
         ((st = upload(c, pl.off_cellw, pl.cellw.data(), pl.cellw.size() * sizeof(int32_t))) != LBM_OK ||
          (st = upload(c, pl.off_ptab, pl.ptab.data(), pl.ptab.size())) != LBM_OK))
@@ -997,8 +1046,10 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   if (!c) return LBM_EINVAL;
   const bool on = tau_e != 0.0;
   if (on) {
-    if ((c->p.geometry != LBM_SLAB && c->p.geometry != LBM_DUCT) || c->p.wall_velocity_top != 0.0)
-      return c->fail(LBM_EINVAL, "electron sheets need a SLAB or DUCT without a moving wall");
+    if (c->p.geometry == LBM_MASKED || c->p.wall_velocity_top != 0.0)
+      return c->fail(LBM_EINVAL, "electron sheets need a SLAB, DUCT or TUBE without a moving wall");
+    if (c->pl.nsheet <= 0 || !c->pl.shells_whole)
+      return c->fail(LBM_EINVAL, "electron lines need solid columns around the wall inside the box");
     if (c->args.open) return c->fail(LBM_EINVAL, "electron sheets need periodic x ends");
     if (!(tau_e > 0.5) || !(rho_e0 > 0.0) || !(gamma_e >= 0.0) || !std::isfinite(tau_e) ||
         !std::isfinite(rho_e0) || !std::isfinite(gamma_e) || !std::isfinite(force_e))
@@ -1025,6 +1076,8 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   ea.nshell = (int)(pl.nsheet / pl.nx);
   ea.rwall = c->at<void>(pl.off_r);
   ea.swc = c->at<int32_t>(pl.off_swc);
+  ea.tube = pl.bouz ? 1 : 0;
+  ea.bz = pl.bouz ? c->at<void>(pl.off_bz) : nullptr;
   ea.rho0 = c->p.rho0;
   ea.omega_e = 1.0 / tau_e;
   ea.rho_e0 = rho_e0;
@@ -1038,6 +1091,12 @@ lbm_status lbm_set_electrons(lbm_ctx* c, double tau_e, double rho_e0, double gam
   HIPCHK(c, hipMemsetAsync(c->at<void>(pl.off_ue), 0, (size_t)pl.nsheet * 2 * sizeof(double),
                            c->stream));
   return sync(c);
+}
+
+lbm_status lbm_shell_count(const lbm_ctx* c, size_t* n) {
+  if (!c || !n) return LBM_EINVAL;
+  *n = c->pl.nx > 0 ? (size_t)(c->pl.nsheet / c->pl.nx) : 0;
+  return LBM_OK;
 }
 
 lbm_status lbm_set_phonons(lbm_ctx* c, double tau_p, double rho_p0, double gamma_pc,

@@ -117,10 +117,12 @@ struct StepArgs {
   // one-point closure of the quantum noise (form 1): factors on the random
   // stress components xx, yy, zz, xy, xz, yz (1: classical)
   double th_fac[6];
-  // electron shells (slab and duct walls): x velocity of each shell node in
-  // the step being taken, [shell][x]; shells y = -1, y = ny (by z), then for
-  // a duct z = -1, z = nz (by y)
+  // electron shells: x velocity of each shell node in the step being taken,
+  // [shell][x]; slab and duct: shells y = -1, y = ny (by z), then for a duct
+  // z = -1, z = nz (by y); tube: shellof[y + ny z] is the shell of a solid
+  // column (-1: none)
   const double* ue;
+  const int32_t* shellof;
   // masked walls (walls that vary along x; null for the other geometries):
   // cellw[x + nx y] is the class of the point (kCellSolid, kCellInterior or
   // the 2-D wall-node index k), ptab[k Q + i] the storage row of the slip
@@ -335,10 +337,13 @@ __device__ __forceinline__ int64_t src_off(const StepArgs& a, int i, int z, bool
 // column col + k takes the lines of column col shifted by dl = k sC, which is
 // the same shift for every source column away from periodic wrap in z.
 //
-// With ELEC (slab or duct walls with electron shells) the bounce-back half
-// reflects off a wall moving with the electrons of the solid point x - c_i:
+// With ELEC (walls with electron shells) the bounce-back half reflects off a
+// wall moving with the electrons of the solid point x - c_i:
 //   BB_i = g_opp(i)(x) + 6 w_i rho0 c_ix u_e(x - c_i)
-// (a wall link with c_ix != 0 crosses a y wall or a z wall, never both).
+// (a wall link with c_ix != 0 crosses a y wall or a z wall, never both); on
+// a tube the term is scaled by 1 - cc (1 / 2q where the wall lies farther
+// than half a link), so that a uniform flow at the wall's velocity stays
+// exact.
 //
 // With OPEN (open x ends) the pulls of the first and last node that would
 // wrap around x read the node itself instead (x - c_i clamped into the box):
@@ -406,10 +411,18 @@ __device__ __forceinline__ void gather(const S* __restrict__ g0, const StepArgs&
     }
     M bb = gb;
     if (ELEC && L::cx[i] != 0) {
-      const int64_t shell = L::cy[i] != 0 ? (int64_t)(L::cy[i] > 0 ? 0 : a.nz) + z
-                                          : 2LL * a.nz + (L::cz[i] > 0 ? 0 : a.ny) + y;
+      int64_t shell;
+      if constexpr (BOUZ)  // a tube: the shell of the solid column the link pulls from
+        shell = gbl(a.shellof)[(int64_t)(y - L::cy[i]) + (int64_t)a.ny * (z - L::cz[i])];
+      else
+        shell = L::cy[i] != 0 ? (int64_t)(L::cy[i] > 0 ? 0 : a.nz) + z
+                              : 2LL * a.nz + (L::cz[i] > 0 ? 0 : a.ny) + y;
       const int64_t sn = shell * a.nx + (L::cx[i] > 0 ? xm : xp);
-      bb += static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i]) * static_cast<M>(gbl(a.ue)[sn]);
+      M mv = static_cast<M>(6.0 * L::w[i] * a.rho0 * L::cx[i]) * static_cast<M>(gbl(a.ue)[sn]);
+      // interpolated walls: where the wall lies farther than half a link the
+      // moving wall's term is divided by 2q, i.e. scaled by 1 - cc
+      if constexpr (BOUZ) mv *= M(1) - static_cast<M>(cw[2 * i + 1]);
+      bb += mv;
     }
     if (BOUZ) {
       const M cb = static_cast<M>(cw[2 * i]), cc = static_cast<M>(cw[2 * i + 1]);

@@ -51,13 +51,18 @@ struct Plan {
   int64_t nwallslots = 0;  // leading slots whose columns hold wall nodes
   size_t off_cellw = 0, off_ptab = 0;
   size_t off_bmom = 0;  // open ends: [side][column][4] moments of the end nodes
-  int64_t nsheet = 0;               // electron sheet nodes (SLAB: 2 nz nx; else 0)
-  std::vector<int32_t> sheet_wc;    // [sheet][z]: wall column next to the sheet
+  int64_t nsheet = 0;               // electron shell nodes (nshell nx)
+  // per shell: the wall column of the fluid column next to it (SLAB, DUCT);
+  // TUBE: for the fluid columns at -y, +y, -z, +z of it, (column, wall
+  // column) or (-1, -1)
+  std::vector<int32_t> sheet_wc;
+  std::vector<int32_t> shellof;     // TUBE: shell of each box column (-1: none)
+  bool shells_whole = true;         // every wall link crossing x pulls from a shell
   // arena offsets
   size_t off_pop[2] = {0, 0}, pop_bytes = 0;
   size_t off_slots = 0, off_r = 0, off_bz = 0, off_lambda = 0, off_raw = 0,
          off_partials = 0, off_out = 0, off_flag = 0, off_step = 0, total = 0;
-  size_t off_e[2] = {0, 0}, off_ue = 0, off_swc = 0;  // electron sheets
+  size_t off_e[2] = {0, 0}, off_ue = 0, off_swc = 0, off_shellof = 0;  // electron shells
 };
 
 }  // namespace lbm_host

@@ -258,32 +258,71 @@ __global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
   const double d0 = es[s], d1 = es[n + line + xm], d2 = es[2 * n + line + xp];
   const double drho = d0 + d1 + d2, j = d1 - d2;
   const double rho = ea.rho_e0 + drho;
-  // the fluid column next to the shell and the (c_y, c_z) of the links to it
-  int cy, cz;
-  int64_t col;
-  if (sh < 2LL * ea.nz) {
-    const bool low = sh < ea.nz;
-    cy = low ? 1 : -1;
-    cz = 0;
-    col = (low ? 0 : ea.ny - 1) + (int64_t)ea.ny * (sh % ea.nz);
-  } else {
-    const int64_t t = sh - 2LL * ea.nz;
-    const bool low = t < ea.ny;
-    cy = 0;
-    cz = low ? 1 : -1;
-    col = t % ea.ny + (int64_t)ea.ny * (low ? 0 : ea.nz - 1);
-  }
-  const LBM_GLOBAL W* rw = gbl(static_cast<const W*>(ea.rwall)) + (int64_t)ea.swc[sh] * ea.nx;
   double F0 = 0.0, K = 0.0;
+  if (ea.tube) {
+    // a tube: up to four fluid columns next to the shell (at -y, +y, -z,
+    // +z); through each link k from the shell into one of them the water
+    // gains r c_kx (bb_k + g_opp(k)) of axial momentum, bb_k the interpolated
+    // bounce-back (coefficients cb on the node behind, cc on g_k) whose
+    // moving-wall part is (1 - cc) 6 w_k rho0 c_kx u
+    const LBM_GLOBAL int32_t* ts = gbl(ea.swc) + sh * 8;
+    const LBM_GLOBAL W* rwall = gbl(static_cast<const W*>(ea.rwall));
+    const LBM_GLOBAL W* bz = gbl(static_cast<const W*>(ea.bz));
+    const LBM_GLOBAL S* gg = gbl(g);
 #pragma unroll
-  for (int k = 0; k < L::Q; k++) {
-    if (L::cx[k] == 0 || (L::cy[k] == 0 && L::cz[k] == 0)) continue;
-    if (L::cy[k] != cy || L::cz[k] != cz) continue;
-    const int xf = L::cx[k] > 0 ? xp : xm;
-    const double r = static_cast<double>(rw[xf]);
-    const double go = dec<S, double>(gbl(g)[col * ea.sC + L::row[L::opp[k]] * ea.sI + xf]);
-    F0 -= 2.0 * r * go * L::cx[k];
-    K += 6.0 * ea.rho0 * r * L::w[k];
+    for (int d = 0; d < 4; d++) {
+      const int fc = ts[2 * d], wc = ts[2 * d + 1];
+      if (fc < 0) continue;
+      const int dy = d == 0 ? -1 : (d == 1 ? 1 : 0), dz = d == 2 ? -1 : (d == 3 ? 1 : 0);
+#pragma unroll
+      for (int k = 0; k < L::Q; k++) {
+        if (L::cx[k] == 0 || L::cy[k] != dy || L::cz[k] != dz) continue;
+        const int xf = L::cx[k] > 0 ? xp : xm;
+        const double r = static_cast<double>(rwall[(int64_t)wc * ea.nx + xf]);
+        const double gob =
+            dec<S, double>(gg[(int64_t)fc * ea.sC + L::row[L::opp[k]] * ea.sI + xf]);
+        const double cbz = static_cast<double>(bz[((int64_t)wc * L::Q + k) * 2]);
+        const double ccz = static_cast<double>(bz[((int64_t)wc * L::Q + k) * 2 + 1]);
+        double term = 2.0 * gob;
+        if (cbz != 0.0) {  // the node behind, x_f + c_k, in the column beyond
+          const int xb = L::cx[k] > 0 ? (xf == ea.nx - 1 ? 0 : xf + 1)
+                                      : (xf == 0 ? ea.nx - 1 : xf - 1);
+          const int64_t cbk = (int64_t)fc + dy + (int64_t)ea.ny * dz;
+          term += cbz * (dec<S, double>(gg[cbk * ea.sC + L::row[L::opp[k]] * ea.sI + xb]) - gob);
+        }
+        if (ccz != 0.0)
+          term += ccz * (dec<S, double>(gg[(int64_t)fc * ea.sC + L::row[k] * ea.sI + xf]) - gob);
+        F0 -= r * term * L::cx[k];
+        K += 6.0 * ea.rho0 * r * L::w[k] * (1.0 - ccz);
+      }
+    }
+  } else {
+    // the fluid column next to the shell and the (c_y, c_z) of the links to it
+    int cy, cz;
+    int64_t col;
+    if (sh < 2LL * ea.nz) {
+      const bool low = sh < ea.nz;
+      cy = low ? 1 : -1;
+      cz = 0;
+      col = (low ? 0 : ea.ny - 1) + (int64_t)ea.ny * (sh % ea.nz);
+    } else {
+      const int64_t t = sh - 2LL * ea.nz;
+      const bool low = t < ea.ny;
+      cy = 0;
+      cz = low ? 1 : -1;
+      col = t % ea.ny + (int64_t)ea.ny * (low ? 0 : ea.nz - 1);
+    }
+    const LBM_GLOBAL W* rw = gbl(static_cast<const W*>(ea.rwall)) + (int64_t)ea.swc[sh] * ea.nx;
+#pragma unroll
+    for (int k = 0; k < L::Q; k++) {
+      if (L::cx[k] == 0 || (L::cy[k] == 0 && L::cz[k] == 0)) continue;
+      if (L::cy[k] != cy || L::cz[k] != cz) continue;
+      const int xf = L::cx[k] > 0 ? xp : xm;
+      const double r = static_cast<double>(rw[xf]);
+      const double go = dec<S, double>(gbl(g)[col * ea.sC + L::row[L::opp[k]] * ea.sI + xf]);
+      F0 -= 2.0 * r * go * L::cx[k];
+      K += 6.0 * ea.rho0 * r * L::w[k];
+    }
   }
   const double gam = ea.gamma_e;
   const double c[3] = {0.0, 1.0, -1.0}, w[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
@@ -1008,6 +1047,11 @@ static const void* step_kernel_t(bool bouz, int th_mode, bool elec, bool masked,
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 2>);
     return reinterpret_cast<const void*>(&k_step_open<L, S, M, false, 0>);
   }
+  if (elec && bouz) {
+    if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 1, true>);
+    if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, true, 2, true>);
+    return reinterpret_cast<const void*>(&k_step<L, S, M, true, 0, true>);
+  }
   if (elec) {
     if (th_mode == 1) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 1, true>);
     if (th_mode == 2) return reinterpret_cast<const void*>(&k_step<L, S, M, false, 2, true>);
@@ -1141,6 +1185,9 @@ static hipError_t launch_moments_t(const void* src, const StepArgs& a, bool bouz
   if (a.cellw)
     hipLaunchKernelGGL((k_moments<L, S, W, false, false, true>), grid, block, 0, st,
                        (const S*)src, a, which, field, partials);
+  else if (bouz && a.ue)
+    hipLaunchKernelGGL((k_moments<L, S, W, true, true>), grid, block, 0, st, (const S*)src, a,
+                       which, field, partials);
   else if (bouz)
     hipLaunchKernelGGL((k_moments<L, S, W, true>), grid, block, 0, st, (const S*)src, a, which,
                        field, partials);

@@ -20,14 +20,20 @@ struct SpecArgs {
   double v_l;    // liquid mode dispersion
 };
 
-// Electron shells (the solid columns next to the water of a slab or duct,
-// one line along x each, D1Q3): y = -1 and y = ny (by z), then for a duct
-// z = -1 and z = nz (by y)
+// Electron shells (the solid columns next to the water, one line along x
+// each, D1Q3): slab and duct y = -1 and y = ny (by z), then for a duct
+// z = -1 and z = nz (by y); tube: the solid columns with a fluid column next
+// to them along y or z, by increasing column index
 struct ElecArgs {
   int nx, ny, nz, nshell;
   int64_t sI, sC;        // water layout
   const void* rwall;     // water wall weights r [wallcol][nx] (double, float for F16S)
-  const int32_t* swc;    // [shell]: wall column of the fluid column next to the shell
+  // slab and duct: [shell] the wall column of the fluid column next to the
+  // shell; tube: [shell][8] (column, wall column) of the fluid columns at
+  // -y, +y, -z, +z of the shell, -1 where solid
+  const int32_t* swc;
+  int tube;              // interpolated walls: bz holds their coefficients
+  const void* bz;        // [wallcol][Q][2] (double, float for F16S)
   double rho0;           // water reference density
   double omega_e, rho_e0, gamma_e, force_e;
   // phonon lines beside the electron lines (rows 3..5 of the state, their

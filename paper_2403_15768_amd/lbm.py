@@ -66,7 +66,7 @@ EXPORTS = [
     "lbm_batch_set_shape", "lbm_batch_set_group_bytes", "lbm_batch_groups", "lbm_batch_set_streams",
     "lbm_batch_last_error", "lbm_set_thermal", "lbm_set_populations", "lbm_set_electrons",
     "lbm_get_electrons", "lbm_set_open_ends", "lbm_set_noise_closure", "lbm_set_phonons",
-    "lbm_get_phonons", "lbm_step_checked", "lbm_checked_invariants",
+    "lbm_get_phonons", "lbm_shell_count", "lbm_step_checked", "lbm_checked_invariants",
     "lbm_friction_quadrature_static", "lbm_batch_member_cost", "lbm_batch_spec_footprint",
     "lbm_batch_create_spec", "lbm_batch_add", "lbm_batch_remove", "lbm_batch_size",
     "lbm_batch_settings", "lbm_invariants_async", "lbm_tune", "lbm_set_block",
@@ -109,6 +109,7 @@ def load() -> C.CDLL:
         "lbm_get_electrons": [vp, dp, dp],
         "lbm_set_phonons": [vp, C.c_double, C.c_double, C.c_double, C.c_double],
         "lbm_get_phonons": [vp, dp, dp],
+        "lbm_shell_count": [vp, C.POINTER(C.c_size_t)],
         "lbm_set_open_ends": [vp, C.c_int, C.c_double, C.c_double],
         "lbm_set_noise_closure": [vp, dp, C.c_int, C.c_int, dp, dp],
         "lbm_run_to_steady": [vp, C.c_double, i64, i64, C.POINTER(i64)],
@@ -359,8 +360,12 @@ class Channel:
 
     @property
     def shell_count(self) -> int:
-        """Electron lines: y = -1, y = ny (by z), then for a duct z = -1, z = nz (by y)."""
-        return 2 * self.nz + (2 * self.ny if self.params.geometry == DUCT else 0)
+        """Electron lines: y = -1, y = ny (by z), then for a duct z = -1, z = nz
+        (by y); a tube's: its solid columns next to the water along y or z, by
+        increasing y + ny z."""
+        n = C.c_size_t()
+        self._ck(self._lib.lbm_shell_count(self._h, C.byref(n)), "lbm_shell_count")
+        return int(n.value)
 
     def electrons(self):
         """(u_e of the last step [shell][x], populations [i][shell][x])."""

@@ -1,5 +1,5 @@
-"""GPU parity of the electron wind (electron sheets on slab walls) against the
-oracle, through the C ABI.
+"""GPU parity of the electron wind (electron lines in the solid next to slab,
+duct and tube walls) against the oracle, through the C ABI.
 
 Tolerances: FP64 water fields and electron state within 1e-12 relative of the
 oracle (same arithmetic, summation order aside); FP32 water storage within
@@ -136,10 +136,14 @@ def test_full_size_momentum_bookkeeping_fp64(lbm, geom):
 
 
 def test_electron_settings_and_batches(lbm):
-    D = lbm.Channel(19, lbm.TUBE, 8, 12, 12, tau=0.8, precision="f64", tube_radius=3.0,
+    # a tube whose wall touches the box's edge has no solid to hold lines there
+    D = lbm.Channel(19, lbm.TUBE, 8, 12, 12, tau=0.8, precision="f64", tube_radius=5.9,
                     tube_cy=5.5, tube_cz=5.5)
     with pytest.raises(lbm.LBMError):
         D.set_electrons(*ELEC)
+    M = lbm.Channel(9, lbm.MASKED, 8, 6, 1, tau=0.8, precision="f64", solid=np.eye(6, 8) > 0)
+    with pytest.raises(lbm.LBMError):
+        M.set_electrons(*ELEC)
     S = lbm.Channel(9, lbm.SLAB, 8, 4, 1, tau=0.8, precision="f64")
     for args in [(0.5, 1.0, 0.1, 0.0), (0.8, 0.0, 0.1, 0.0), (0.8, 1.0, -0.1, 0.0),
                  (0.8, 1.0, 0.1, float("nan"))]:
@@ -337,3 +341,119 @@ def test_checkpoint_holds_the_lines(lbm, precision):
     C.set_electrons(0.0)
     with pytest.raises(lbm.LBMError):
         C.set_state(buf, step)
+
+
+# ------------------------------------------------------------------ nanotubes
+# electron lines in the solid columns around the circular wall (interpolated
+# bounce-back with the moving-wall term scaled by 1 - cc)
+def build_tube(lbm, precision, nx=37, R=5.0, fh=2e-6):
+    n = int(2 * R + 4)
+    c = (n - 1) / 2
+    kw = dict(tau=0.75, force=(fh, 0, 0), tube_radius=R, tube_cy=c, tube_cz=c)
+    G = lbm.Channel(19, lbm.TUBE, nx, n, n, precision=precision, **kw)
+    O = oracle.Lattice(19, oracle.TUBE, nx, n, n, **kw)
+    lam = np.random.default_rng(8).uniform(0.0, 0.3, G.wall_count)
+    for L in (G, O):
+        L.set_friction(lam)
+        L.set_electrons(*ELEC)
+    assert G.shell_count == O.shell_count > 0
+    return G, O
+
+
+@pytest.mark.parametrize("phonons", [False, True])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tube_parity_over_graph_and_plain_steps(lbm, precision, phonons):
+    say("tube electrons parity", precision, "phonons" if phonons else "")
+    G, O = build_tube(lbm, precision)
+    if phonons:
+        for L in (G, O):
+            L.set_phonons(*PHON)
+    n = 101
+    G.step(n)
+    O.step(n)
+    rg, ro = G.fields(), O.fields()
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / np.abs(ro[1]).max()
+    ueg, pg = G.electrons()
+    ueo, po = O.electrons()
+    eu = np.abs(ueg - ueo).max() / np.abs(ueo).max()
+    ep = np.abs(pg - po).max() / np.abs(po).max()
+    say(f"  water {err:.2e}  u_e {eu:.2e}  electron pops {ep:.2e}")
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert err < tol and eu < tol and ep < tol
+    if phonons:
+        upg, _ = G.phonons()
+        upo, _ = O.phonons()
+        assert np.abs(upg - upo).max() < tol * np.abs(upo).max()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16s"])
+def test_tube_graph_plain_and_restart_bitwise(lbm, precision):
+    say("tube electrons bitwise", precision)
+    A, _ = build_tube(lbm, precision)
+    B, _ = build_tube(lbm, precision)
+    C, _ = build_tube(lbm, precision)
+    A.step(70)
+    for _ in range(70):
+        B.step(1)
+    assert np.array_equal(A.get_state()[0], B.get_state()[0])
+    buf, step = A.get_state()
+    C.set_state(buf, step)
+    A.step(64)
+    C.step(64)
+    assert np.array_equal(A.get_state()[0], C.get_state()[0])
+    assert np.array_equal(A.electrons()[1], C.electrons()[1])
+
+
+def test_tube_electrons_with_thermal_noise_fp64(lbm):
+    say("tube electrons + thermal")
+    G, O = build_tube(lbm, "f64", nx=20)
+    for L in (G, O):
+        L.set_thermal(1e-7, 1, 33)
+    G.step(101)
+    O.step(101)
+    rg, ro = G.fields(), O.fields()
+    err = max(np.abs(rg[k] - ro[k]).max() for k in (1, 2, 3)) / np.abs(ro[1]).max()
+    ueg, _ = G.electrons()
+    ueo, _ = O.electrons()
+    say(f"  water {err:.2e}")
+    assert err < 1e-12
+    assert np.abs(ueg - ueo).max() < 1e-12 * np.abs(ueo).max()
+
+
+def test_tube_half_storage_electrons_track_the_oracle(lbm):
+    say("tube electrons half storage")
+    G, O = build_tube(lbm, "f16s")
+    G.step(300)
+    O.step(300)
+    ueg, _ = G.electrons()
+    ueo, _ = O.electrons()
+    e = np.abs(ueg - ueo).max() / np.abs(ueo).max()
+    say(f"  u_e {e:.2e}")
+    assert e < 6.5e-4  # measured 2.1e-4
+
+
+def test_tube_full_size_momentum_bookkeeping_fp64(lbm):
+    # the 512 x 72 x 72 nanotube (R = 32): over one step water plus electron
+    # lines change axial momentum by exactly the forces minus the lattice drag
+    say("tube electrons full size momentum")
+    nx, fh = 512, 2e-6
+    tau_e, rho_e, gam, fe = ELEC
+    G = lbm.Channel(19, lbm.TUBE, nx, 72, 72, tau=0.8, force=(fh, 0, 0), precision="f64",
+                    tube_radius=32.0, tube_cy=35.5, tube_cz=35.5)
+    G.set_friction(np.random.default_rng(3).uniform(0.0, 0.2, G.wall_count))
+    G.set_electrons(tau_e, rho_e, gam, fe)
+    G.step(200)
+
+    def totals():
+        g = G.populations()
+        _, p = G.electrons()
+        return float(np.tensordot(C19X, g, axes=(0, 0)).sum()), float((p[1] - p[2]).sum()), p
+    w0, e0, p = totals()
+    rho = rho_e + p[0] + np.roll(p[1], 1, axis=-1) + np.roll(p[2], -1, axis=-1)
+    G.step(1)
+    w1, e1, _ = totals()
+    ue, _ = G.electrons()
+    expect = fh * G.fluid_count + fe * G.shell_count * nx - gam * float((rho * ue).sum())
+    say(f"  shells {G.shell_count}, residual {(w1 + e1) - (w0 + e0) - expect:.3e} of {abs(w0):.3e}")
+    assert abs((w1 + e1) - (w0 + e0) - expect) < 1e-12 * abs(w0)
+    assert abs((w1 - w0) - fh * G.fluid_count) > 1e-6 * abs(fh * G.fluid_count)
