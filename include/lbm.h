@@ -476,11 +476,13 @@ lbm_status lbm_transfer_state(lbm_ctx *dst, lbm_ctx *src);
  * Members join (lbm_batch_add) and leave (lbm_batch_remove) while the batch
  * runs: only the groups they touch get new work lists and graphs.  Members
  * must outlive their membership.  The members of a batch share the noise
- * form and the kind of x ends (all periodic or all open; each its own end
- * densities).  Batches refuse members with electron lines or MASKED walls
- * (LBM_EINVAL); lbm_batch_step refuses a member whose noise form or kind of
- * ends changed or whose sheets were switched on after it joined, and takes
- * up a changed kT, seed, noise closure or end densities. */
+ * form, the kind of x ends (all periodic or all open; each its own end
+ * densities) and electron lines (on all or none; each its own line
+ * parameters, and phonon lines or not; a step runs the group's line steps,
+ * then its water step).  Batches refuse MASKED members (LBM_EINVAL);
+ * lbm_batch_step refuses a member whose noise form, kind of ends or
+ * electron lines changed after it joined, and takes up a changed kT, seed,
+ * noise closure, end densities or line parameters. */
 typedef struct lbm_batch lbm_batch; /* opaque */
 
 /* Capacity of a batch made empty (lbm_batch_create_spec): the kind of its
@@ -492,6 +494,7 @@ typedef struct {
   int tube;        /* 1: TUBE members (interpolated walls), 0: SLAB / DUCT */
   int noise;       /* thermal-noise form of every member: 0 none, LBM_NOISE_* */
   int open_ends;   /* 1: every member has open x ends (lbm_set_open_ends), 0: periodic */
+  int electrons;   /* 1: every member has electron lines (lbm_set_electrons), 0: none */
   int max_members;
   int64_t max_items, max_columns;
 } lbm_batch_spec;

@@ -58,6 +58,7 @@ struct lbm_batch {
   bool bouz = false;
   int th = 0;         // every member's thermal-noise form (0: none)
   bool open = false;  // every member's x ends open (else periodic)
+  bool elec = false;  // every member has electron lines (else none)
   int cap_members = 0;
   int64_t cap_items = 0, cap_cols = 0;
   // member slots (nullptr: free) and what the member table on the device
@@ -68,6 +69,7 @@ struct lbm_batch {
   std::vector<uint64_t> th_seed;
   std::vector<std::array<double, 6>> th_fac;
   std::vector<std::array<double, 2>> ends;  // the open ends' densities (rho - rho0)
+  std::vector<lbm::ElecArgs> eargs;         // the electron lines' arguments
   std::vector<int> gof;                // group of each slot (-1: free)
   std::vector<int64_t> mstart, mcount;  // each slot's entries in the order array
   struct Group {
@@ -270,10 +272,11 @@ lbm_status check_member(const lbm_batch* b, const lbm_ctx* c) {
   if (c->p.lattice != b->Q || c->p.precision != b->prec ||
       (c->p.geometry == LBM_TUBE) != b->bouz)
     return LBM_EINVAL;
-  // one noise form and one kind of x ends for the whole batch (each member
-  // its own kT, seed and end densities); the batch kernel has no electron
-  // sheets or masked walls
-  if (c->args.th_mode != b->th || (c->args.open != 0) != b->open || c->elec || c->pl.masked)
+  // one noise form, one kind of x ends and electron lines on all or none
+  // (each member its own kT, seed, end densities and line parameters); the
+  // batch kernel has no masked walls
+  if (c->args.th_mode != b->th || (c->args.open != 0) != b->open || c->elec != b->elec ||
+      c->pl.masked)
     return LBM_EINVAL;
   return LBM_OK;
 }
@@ -299,10 +302,45 @@ void layout(lbm_batch* b) {
 }
 
 // one step (step_off steps past the device counter) of group gi
-lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, hipStream_t st) {
+// The group's members with electron lines, in launches of at most
+// kEGroupMax: (member slots, grid) of each.
+struct ELaunch {
+  lbm::EGroup eg;
+  dim3 grid;
+};
+std::vector<ELaunch> electron_launches(const lbm_batch* b, const lbm_batch::Group& g) {
+  std::vector<ELaunch> out;
+  if (!b->elec) return out;
+  for (size_t j = 0; j < g.slots.size(); j += lbm::kEGroupMax) {
+    ELaunch l{};
+    int64_t most = 0;
+    for (size_t t = j; t < g.slots.size() && l.eg.n < lbm::kEGroupMax; t++) {
+      const lbm_ctx* c = b->m[g.slots[t]];
+      l.eg.slot[l.eg.n++] = g.slots[t];
+      most = std::max<int64_t>(most, c->pl.nsheet);
+    }
+    l.grid = dim3((unsigned)((most + 255) / 256), (unsigned)l.eg.n);
+    out.push_back(l);
+  }
+  return out;
+}
+
+// one step (step_off steps past the device counter) of group gi: with
+// electron lines their step first (the water step reads their velocity);
+// water_only: the water step alone (the autotuner's timings)
+lbm_status launch_batch(lbm_batch* b, size_t gi, int64_t step_off, hipStream_t st,
+                        bool water_only = false) {
   const lbm_batch::Group& g = b->groups[gi];
   if (g.n == 0) return LBM_OK;
-  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th, b->open);
+  const MemberDesc* mde = b->at<MemberDesc>(b->off_desc);
+  const int64_t* bse = b->at<int64_t>(b->off_bstep);
+  if (!water_only)
+    for (ELaunch& l : electron_launches(b, g)) {
+      void* eargs[4] = {(void*)&mde, (void*)&l.eg, (void*)&bse, (void*)&step_off};
+      BCHK(b, hipLaunchKernel(lbm::batch_electron_kernel_ptr(b->Q, b->prec), l.grid, dim3(256),
+                              eargs, 0, st));
+    }
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th, b->open, b->elec);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int32_t* cols = b->at<int32_t>(b->off_cols);
@@ -401,6 +439,12 @@ MemberDesc describe(const lbm_ctx* c, int64_t k) {
   d.pop[1] = c->pop[1];
   d.bmom[0] = end_records(const_cast<lbm_ctx*>(c), 0);
   d.bmom[1] = end_records(const_cast<lbm_ctx*>(c), 1);
+  if (c->elec) {
+    d.ea = c->ea;
+    d.eline[0] = c->at<double>(c->pl.off_e[0]);
+    d.eline[1] = c->at<double>(c->pl.off_e[1]);
+    d.uel = c->at<double>(c->pl.off_ue);
+  }
   d.base_step = c->step - k;
   d.cur_base = (int32_t)((c->cur + k) & 1);  // (cur_base + k) & 1 == cur
   return d;
@@ -423,7 +467,17 @@ lbm_status write_desc(lbm_batch* b, int s) {
   b->th_seed[s] = c->args.th_seed;
   std::copy(c->args.th_fac, c->args.th_fac + 6, b->th_fac[s].begin());
   b->ends[s] = {c->args.drho_in, c->args.drho_out};
+  b->eargs[s] = c->ea;
   return LBM_OK;
+}
+
+// the electron lines' parameters as the member table holds them
+bool same_lines(const lbm::ElecArgs& a, const lbm::ElecArgs& e) {
+  return a.nshell == e.nshell && a.rwall == e.rwall && a.swc == e.swc && a.tube == e.tube &&
+         a.bz == e.bz && a.rho0 == e.rho0 && a.omega_e == e.omega_e && a.rho_e0 == e.rho_e0 &&
+         a.gamma_e == e.gamma_e && a.force_e == e.force_e && a.phon == e.phon &&
+         a.omega_p == e.omega_p && a.rho_p0 == e.rho_p0 && a.gamma_pc == e.gamma_pc &&
+         a.gamma_ep == e.gamma_ep;
 }
 
 // A member stepped, restored or overwritten outside the batch no longer sits
@@ -436,7 +490,8 @@ lbm_status resync(lbm_batch* b) {
         c->args.th_seed == b->th_seed[s] &&
         std::equal(b->th_fac[s].begin(), b->th_fac[s].end(), c->args.th_fac) &&
         c->args.drho_in == b->ends[s][0] && c->args.drho_out == b->ends[s][1] &&
-        (!c->args.open || c->bmom_ok))
+        (!c->args.open || c->bmom_ok) &&
+        (!c->elec || same_lines(c->ea, b->eargs[s])))
       continue;
     lbm_status st = write_desc(b, (int)s);
     if (st != LBM_OK) return st;
@@ -450,17 +505,34 @@ lbm_status build_graph(lbm_batch* b, size_t gi) {
   lbm_batch::Group& grp = b->groups[gi];
   hipGraph_t g = nullptr;
   BCHK(b, hipGraphCreate(&g, 0));
-  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th, b->open);
+  const void* fn = lbm::batch_step_kernel_ptr(b->Q, b->prec, b->bouz, b->th, b->open, b->elec);
+  const void* fe = lbm::batch_electron_kernel_ptr(b->Q, b->prec);
   const MemberDesc* md = b->at<MemberDesc>(b->off_desc);
   const WorkItem* items = b->at<WorkItem>(b->off_items);
   const int32_t* cols = b->at<int32_t>(b->off_cols);
   const int64_t* bstep = b->at<int64_t>(b->off_bstep);
   int64_t first = grp.istart, nwall = grp.istart + grp.nwall, last = grp.istart + grp.n;
   int wpb = b->wpb;
+  std::vector<ELaunch> el = electron_launches(b, grp);
   hipGraphNode_t prev = nullptr;
   int64_t offs[kGraphSteps];
   for (int j = 0; j < kGraphSteps; j++) {
     offs[j] = j;
+    for (ELaunch& l : el) {  // the electron lines' step before the water's
+      void* eargs[4] = {(void*)&md, (void*)&l.eg, (void*)&bstep, (void*)&offs[j]};
+      hipKernelNodeParams ep{};
+      ep.func = const_cast<void*>(fe);
+      ep.gridDim = l.grid;
+      ep.blockDim = dim3(256);
+      ep.kernelParams = eargs;
+      hipGraphNode_t node = nullptr;
+      hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &ep);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return b->hip(e, "hipGraphAddKernelNode");
+      }
+      prev = node;
+    }
     void* args[9] = {(void*)&md,   (void*)&items, (void*)&cols,    (void*)&first, (void*)&nwall,
                      (void*)&last, (void*)&bstep, (void*)&offs[j], (void*)&wpb};
     hipKernelNodeParams kp{};
@@ -647,6 +719,7 @@ lbm_status init_batch(lbm_batch* b, void* arena, size_t arena_bytes, void* hip_s
   b->th_seed.assign(b->cap_members, 0);
   b->th_fac.assign(b->cap_members, std::array<double, 6>{});
   b->ends.assign(b->cap_members, std::array<double, 2>{});
+  b->eargs.assign(b->cap_members, lbm::ElecArgs{});
   b->gof.assign(b->cap_members, -1);
   b->mstart.assign(b->cap_members, 0);
   b->mcount.assign(b->cap_members, 0);
@@ -679,10 +752,10 @@ lbm_status take_member(lbm_batch* b, int s, lbm_ctx* c) {
 // noise form and the size bucket (log2 of the fluid cells, log2 of the
 // members).  Shared by every batch of the process.
 struct TuneKey {
-  int Q, prec, bouz, th, open, cells_log2, members_log2;
+  int Q, prec, bouz, th, open, elec, cells_log2, members_log2;
   bool operator<(const TuneKey& o) const {
-    return std::tie(Q, prec, bouz, th, open, cells_log2, members_log2) <
-           std::tie(o.Q, o.prec, o.bouz, o.th, o.open, o.cells_log2, o.members_log2);
+    return std::tie(Q, prec, bouz, th, open, elec, cells_log2, members_log2) <
+           std::tie(o.Q, o.prec, o.bouz, o.th, o.open, o.elec, o.cells_log2, o.members_log2);
   }
 };
 std::mutex g_tune_mu;
@@ -704,7 +777,8 @@ TuneKey tune_key(const lbm_batch* b) {
       cells += c->pl.nfluid;
       n++;
     }
-  return TuneKey{b->Q, b->prec, b->bouz ? 1 : 0, b->th, b->open ? 1 : 0, ilog2(cells), ilog2(n)};
+  return TuneKey{b->Q, b->prec,         b->bouz ? 1 : 0, b->th, b->open ? 1 : 0,
+                 b->elec ? 1 : 0, ilog2(cells), ilog2(n)};
 }
 
 // Time `reps` steps of every group with the current shape, grouping and
@@ -720,7 +794,7 @@ lbm_status time_steps(lbm_batch* b, int reps, hipEvent_t e0, hipEvent_t e1, doub
     if (s != LBM_OK) return s;
     for (size_t gi = 0; gi < b->groups.size(); gi++)
       for (int j = 0; j < kTuneRun; j++)
-        if ((s = launch_batch(b, gi, 0, group_stream(b, gi))) != LBM_OK) return s;
+        if ((s = launch_batch(b, gi, 0, group_stream(b, gi), true)) != LBM_OK) return s;
     return join_streams(b);
   };
   lbm_status s0 = round();  // warm
@@ -778,6 +852,7 @@ lbm_status lbm_batch_create_spec(const lbm_batch_spec* sp, void* arena, size_t a
   *out = nullptr;
   if (!sp || (sp->lattice != 9 && sp->lattice != 19) || sp->precision < 0 || sp->precision > 2 ||
       sp->noise < 0 || sp->noise > 2 || (sp->open_ends != 0 && sp->open_ends != 1) ||
+      (sp->electrons != 0 && sp->electrons != 1) || (sp->open_ends && sp->electrons) ||
       sp->max_members < 1 || sp->max_items < 0 || sp->max_columns < 0)
     return LBM_EINVAL;
   if (!arena || reinterpret_cast<uintptr_t>(arena) % kAlign) return LBM_EINVAL;
@@ -788,6 +863,7 @@ lbm_status lbm_batch_create_spec(const lbm_batch_spec* sp, void* arena, size_t a
   b->bouz = sp->tube != 0;
   b->th = sp->noise;
   b->open = sp->open_ends != 0;
+  b->elec = sp->electrons != 0;
   b->cap_members = sp->max_members;
   b->cap_items = sp->max_items;
   b->cap_cols = sp->max_columns;
@@ -812,6 +888,7 @@ lbm_status lbm_batch_footprint(lbm_ctx* const* ctxs, int n, size_t* bytes) {
   kind.bouz = ctxs[0]->p.geometry == LBM_TUBE;
   kind.th = ctxs[0]->args.th_mode;
   kind.open = ctxs[0]->args.open != 0;
+  kind.elec = ctxs[0]->elec;
   for (int i = 0; i < n; i++) {
     if (!ctxs[i] || check_member(&kind, ctxs[i]) != LBM_OK) return LBM_EINVAL;
     sp.max_items += member_items_max(ctxs[i]);
@@ -831,6 +908,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* arena, size_t are
   sp.tube = ctxs[0]->p.geometry == LBM_TUBE;
   sp.noise = ctxs[0]->args.th_mode;
   sp.open_ends = ctxs[0]->args.open != 0;
+  sp.electrons = ctxs[0]->elec ? 1 : 0;
   sp.max_members = n;
   for (int i = 0; i < n; i++) {
     if (!ctxs[i]) return LBM_EINVAL;
@@ -872,8 +950,8 @@ lbm_status lbm_batch_add(lbm_batch* b, lbm_ctx* c, int* slot) {
     if (x == c) return b->fail(LBM_EINVAL, "the context is a member already");
   if (check_member(b, c) != LBM_OK)
     return b->fail(LBM_EINVAL, "the context differs from the batch in lattice, precision, wall "
-                               "kind, noise form or kind of x ends, or has electron lines or "
-                               "masked walls");
+                               "kind, noise form, kind of x ends or electron lines, or has masked "
+                               "walls");
   int s = -1;
   for (int i = 0; i < b->cap_members && s < 0; i++)
     if (!b->m[i]) s = i;
@@ -973,8 +1051,9 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   if (nsteps == 0 || b->groups.empty()) return LBM_OK;
   for (const lbm_ctx* c : b->m)
-    if (c && (c->args.th_mode != b->th || c->elec || (c->args.open != 0) != b->open)) {
-      b->err = "a member's noise form or kind of x ends changed or its electron sheets are on; "
+    if (c && (c->args.th_mode != b->th || c->elec != b->elec ||
+              (c->args.open != 0) != b->open)) {
+      b->err = "a member's noise form, kind of x ends or electron lines changed; "
                "remove it from the batch";
       return LBM_EINVAL;
     }

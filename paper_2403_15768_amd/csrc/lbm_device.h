@@ -163,7 +163,38 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// ------------------------------------------------------------------ electron lines
+// Electron shells (the solid columns next to the water, one line along x
+// each, D1Q3): slab and duct y = -1 and y = ny (by z), then for a duct
+// z = -1 and z = nz (by y); tube: the solid columns with a fluid column next
+// to them along y or z, by increasing column index
+struct ElecArgs {
+  int nx, ny, nz, nshell;
+  int64_t sI, sC;        // water layout
+  const void* rwall;     // water wall weights r [wallcol][nx] (double, float for F16S)
+  // slab and duct: [shell] the wall column of the fluid column next to the
+  // shell; tube: [shell][8] (column, wall column) of the fluid columns at
+  // -y, +y, -z, +z of the shell, -1 where solid
+  const int32_t* swc;
+  int tube;              // interpolated walls: bz holds their coefficients
+  const void* bz;        // [wallcol][Q][2] (double, float for F16S)
+  double rho0;           // water reference density
+  double omega_e, rho_e0, gamma_e, force_e;
+  // phonon lines beside the electron lines (rows 3..5 of the state, their
+  // velocity after the electrons'): on/off, 1/tau_p, rho_p0, crystal drag,
+  // electron-phonon drag coefficient
+  int phon;
+  double omega_p, rho_p0, gamma_pc, gamma_ep;
+};
+
 // ------------------------------------------------------------------ batches
+// The members of a batch group whose electron lines one launch steps.
+constexpr int kEGroupMax = 32;
+struct EGroup {
+  int n;
+  int slot[kEGroupMax];
+};
+
 // One member of a batch: its step arguments, its two population buffers,
 // its step and current buffer when the batch was built.  With k the steps
 // the batch has taken since (one device counter for the whole batch), the
@@ -172,6 +203,12 @@ struct MemberDesc {
   StepArgs a;
   const void* pop[2];
   double* bmom[2];  // open ends: the end-node records of pop[0] and pop[1]
+  // electron lines: their arguments, populations beside pop[0] and pop[1]
+  // (electron rows 0..2, phonon rows 3..5) and the velocities of the last
+  // step (u_e, then u_p)
+  ElecArgs ea;
+  double* eline[2];
+  double* uel;
   int64_t base_step;
   int32_t cur_base;
   int32_t pad;

@@ -244,13 +244,11 @@ __global__ void __launch_bounds__(256) k_open_moments(const S* __restrict__ src,
 //     rho u = j + (force + F0 - K u - gamma rho u) / 2
 //   linear in u; then BGK + Guo with F = force + F0 - K u - gamma rho u.
 template <class L, typename S, typename W>
-__global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
-                                                       const double* __restrict__ es,
-                                                       double* __restrict__ ed,
-                                                       double* __restrict__ ue, ElecArgs ea) {
+__device__ __forceinline__ void electron_node(const S* __restrict__ g,
+                                              const double* __restrict__ es,
+                                              double* __restrict__ ed, double* __restrict__ ue,
+                                              const ElecArgs& ea, int64_t s) {
   const int64_t n = (int64_t)ea.nshell * ea.nx;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
   const int64_t sh = s / ea.nx;  // shell
   const int x = (int)(s - sh * ea.nx);
   const int64_t line = sh * ea.nx;
@@ -366,6 +364,35 @@ __global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
     ed[i * n + s] = d[i] - om * (d[i] - eq) + src;
   }
   ue[s] = u;
+}
+
+template <class L, typename S, typename W>
+__global__ void __launch_bounds__(256) k_electron_step(const S* __restrict__ g,
+                                                       const double* __restrict__ es,
+                                                       double* __restrict__ ed,
+                                                       double* __restrict__ ue, ElecArgs ea) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (int64_t)ea.nshell * ea.nx) return;
+  electron_node<L, S, W>(g, es, ed, ue, ea, s);
+}
+
+// The electron step of up to kEGroupMax members of a batch group (blockIdx.y
+// picks the member, blockIdx.x a block of its line nodes), each from the
+// water state and line buffer of its current parity, before the group's
+// water step: as k_electron_step for each member alone.
+template <class L, typename S, typename W>
+__global__ void __launch_bounds__(256) k_batch_electrons(const MemberDesc* __restrict__ md,
+                                                         EGroup eg,
+                                                         const int64_t* __restrict__ bstep,
+                                                         int64_t step_off) {
+  if ((int)blockIdx.y >= eg.n) return;
+  const MemberDesc& d = md[eg.slot[blockIdx.y]];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (int64_t)d.ea.nshell * d.ea.nx) return;
+  const int64_t k = *bstep + step_off;
+  const int odd = (int)((d.cur_base + k) & 1);
+  electron_node<L, S, W>(static_cast<const S*>(d.pop[odd]), d.eline[odd], d.eline[1 - odd], d.uel,
+                         d.ea, s);
 }
 
 // ------------------------------------------------------------ moments
@@ -763,7 +790,8 @@ __device__ __forceinline__ void run_cols(const int32_t* cols, const WorkItem& it
   *cc = item.c0 + 2 < item.ncols ? uniform(cl[2]) : *ca;
 }
 
-template <class L, typename S, typename M, bool BOUZ, int TH = 0, bool OPEN = false>
+template <class L, typename S, typename M, bool BOUZ, int TH = 0, bool OPEN = false,
+          bool ELEC = false>
 __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict__ md,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ cols,
@@ -805,7 +833,7 @@ __global__ void __launch_bounds__(512) k_batch_step(const MemberDesc* __restrict
   if constexpr (TH != 0)
     thermal_noise<L, M, TH, NormalT<S>>(a, (uint32_t)c.col * (uint32_t)a.nx + (uint32_t)c.x, d.base_step + k,
                             xi);
-  gather<L, S, M, M, BOUZ, false, OPEN>(src, a, colA, xc, info, df, c.dl);
+  gather<L, S, M, M, BOUZ, ELEC, OPEN>(src, a, colA, xc, info, df, c.dl);
   // open ends: the ghosts from the records of the buffer read (the lane's own
   // column: runs of plain columns have no wall links or z wrap)
   if constexpr (OPEN) open_correct<L, M, BOUZ>(a, d.bmom[odd ? 1 : 0], c.col, xc, info, df);
@@ -856,6 +884,8 @@ __global__ void __launch_bounds__(256) k_batch_moments(const MemberDesc* __restr
     if (a.open) {  // reads clamped at the ends, then the ghosts
       gather<L, S, double, W, BOUZ, false, true>(src, a, colA, c.x, info, df, c.dl);
       open_patch<L, S, double, BOUZ, W>(src, a, c.col, c.x, info, df);
+    } else if (a.ue) {  // walls moving with the electron lines of the last step
+      gather<L, S, double, W, BOUZ, true>(src, a, colA, c.x, info, df, c.dl);
     } else {
       gather<L, S, double, W, BOUZ>(src, a, colA, c.x, info, df, c.dl);
     }
@@ -922,7 +952,17 @@ hipError_t launch_set_step(int64_t* d, int64_t v, hipStream_t st) {
 const void* add_step_kernel_ptr() { return reinterpret_cast<const void*>(&k_add_step); }
 
 template <class L, typename S, typename M>
-static const void* batch_kernel_t(bool bouz, int th, bool open) {
+static const void* batch_kernel_t(bool bouz, int th, bool open, bool elec) {
+  if (elec && bouz) {
+    if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 1, false, true>);
+    if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 2, false, true>);
+    return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 0, false, true>);
+  }
+  if (elec) {
+    if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 1, false, true>);
+    if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 2, false, true>);
+    return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 0, false, true>);
+  }
   if (open && bouz) {
     if (th == 1) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 1, true>);
     if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, true, 2, true>);
@@ -942,15 +982,26 @@ static const void* batch_kernel_t(bool bouz, int th, bool open) {
   if (th == 2) return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 2>);
   return reinterpret_cast<const void*>(&k_batch_step<L, S, M, false, 0>);
 }
-const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th, bool open) {
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th, bool open, bool elec) {
   if (q == 9) {
-    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz, th, open);
-    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz, th, open);
-    return batch_kernel_t<D2Q9, _Float16, float>(bouz, th, open);
+    if (prec == 0) return batch_kernel_t<D2Q9, double, double>(bouz, th, open, elec);
+    if (prec == 1) return batch_kernel_t<D2Q9, float, double>(bouz, th, open, elec);
+    return batch_kernel_t<D2Q9, _Float16, float>(bouz, th, open, elec);
   }
-  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz, th, open);
-  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz, th, open);
-  return batch_kernel_t<D3Q19, _Float16, float>(bouz, th, open);
+  if (prec == 0) return batch_kernel_t<D3Q19, double, double>(bouz, th, open, elec);
+  if (prec == 1) return batch_kernel_t<D3Q19, float, double>(bouz, th, open, elec);
+  return batch_kernel_t<D3Q19, _Float16, float>(bouz, th, open, elec);
+}
+
+const void* batch_electron_kernel_ptr(int q, int prec) {
+  if (q == 9) {
+    if (prec == 0) return reinterpret_cast<const void*>(&k_batch_electrons<D2Q9, double, double>);
+    if (prec == 1) return reinterpret_cast<const void*>(&k_batch_electrons<D2Q9, float, double>);
+    return reinterpret_cast<const void*>(&k_batch_electrons<D2Q9, _Float16, float>);
+  }
+  if (prec == 0) return reinterpret_cast<const void*>(&k_batch_electrons<D3Q19, double, double>);
+  if (prec == 1) return reinterpret_cast<const void*>(&k_batch_electrons<D3Q19, float, double>);
+  return reinterpret_cast<const void*>(&k_batch_electrons<D3Q19, _Float16, float>);
 }
 
 template <class L, typename S, typename W>

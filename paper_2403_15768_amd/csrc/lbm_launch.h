@@ -20,28 +20,6 @@ struct SpecArgs {
   double v_l;    // liquid mode dispersion
 };
 
-// Electron shells (the solid columns next to the water, one line along x
-// each, D1Q3): slab and duct y = -1 and y = ny (by z), then for a duct
-// z = -1 and z = nz (by y); tube: the solid columns with a fluid column next
-// to them along y or z, by increasing column index
-struct ElecArgs {
-  int nx, ny, nz, nshell;
-  int64_t sI, sC;        // water layout
-  const void* rwall;     // water wall weights r [wallcol][nx] (double, float for F16S)
-  // slab and duct: [shell] the wall column of the fluid column next to the
-  // shell; tube: [shell][8] (column, wall column) of the fluid columns at
-  // -y, +y, -z, +z of the shell, -1 where solid
-  const int32_t* swc;
-  int tube;              // interpolated walls: bz holds their coefficients
-  const void* bz;        // [wallcol][Q][2] (double, float for F16S)
-  double rho0;           // water reference density
-  double omega_e, rho_e0, gamma_e, force_e;
-  // phonon lines beside the electron lines (rows 3..5 of the state, their
-  // velocity after the electrons'): on/off, 1/tau_p, rho_p0, crystal drag,
-  // electron-phonon drag coefficient
-  int phon;
-  double omega_p, rho_p0, gamma_pc, gamma_ep;
-};
 
 // q: 9 or 19; prec: 0 F64, 1 F32, 2 F16S
 hipError_t launch_step(int q, int prec, const void* src, void* dst, const StepArgs& a, bool bouz,
@@ -79,8 +57,11 @@ const void* add_step_kernel_ptr();  // k_add_step(int64_t* d, int64_t v)
 hipError_t launch_convert(int pin, const void* in, int nxp_in, int pout, void* out, int nxp_out,
                           int64_t rows, int nx, hipStream_t st);
 // batches
-const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th,
-                                  bool open);  // th: noise form; open: open x ends
+const void* batch_step_kernel_ptr(int q, int prec, bool bouz, int th, bool open,
+                                  bool elec);  // th: noise form; open: open x ends
+// k_batch_electrons: grid (blocks of 256 line nodes of the largest member,
+// members), arguments (md, EGroup, bstep, step_off)
+const void* batch_electron_kernel_ptr(int q, int prec);
 // k_batch_step(const MemberDesc*, const WorkItem*, const int32_t* cols, int64_t first,
 //              int64_t nwall, int64_t last, const int64_t* bstep, int64_t step_off, int wpb)
 // per-item partials of the flux and mass of items [first, first + count)

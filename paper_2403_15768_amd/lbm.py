@@ -504,7 +504,8 @@ class Channel:
 
 class BatchSpec(C.Structure):
     _fields_ = [("lattice", C.c_int), ("precision", C.c_int), ("tube", C.c_int),
-                ("noise", C.c_int), ("open_ends", C.c_int), ("max_members", C.c_int),
+                ("noise", C.c_int), ("open_ends", C.c_int), ("electrons", C.c_int),
+                ("max_members", C.c_int),
                 ("max_items", C.c_int64), ("max_columns", C.c_int64)]
 
 
@@ -561,8 +562,8 @@ class Batch:
 
     @classmethod
     def empty(cls, lattice: int, precision, tube: bool, max_members: int, max_items: int,
-              max_columns: int, noise: int = 0, open_ends: bool = False, stream=None,
-              device: str = "cuda") -> "Batch":
+              max_columns: int, noise: int = 0, open_ends: bool = False,
+              electrons: bool = False, stream=None, device: str = "cuda") -> "Batch":
         """An empty batch of this kind and capacity (see lbm_batch_create_spec)."""
         import torch
 
@@ -571,6 +572,7 @@ class Batch:
         sp = BatchSpec()
         sp.lattice, sp.tube, sp.noise = int(lattice), int(bool(tube)), int(noise)
         sp.open_ends = int(bool(open_ends))
+        sp.electrons = int(bool(electrons))
         sp.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
         sp.max_members, sp.max_items, sp.max_columns = int(max_members), int(max_items), int(max_columns)
         nb = C.c_size_t()

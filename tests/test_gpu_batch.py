@@ -567,3 +567,124 @@ def test_open_end_members_join_leave_and_change_densities(lbm):
     for k in (0, 1, 3, 5):
         assert np.array_equal(alone[k].get_state()[0], mixed[k].get_state()[0]), k
     b.close()
+
+
+# ------------------------------------------------------------ electron lines
+# members with electron lines (each its own line parameters, some with
+# phonon lines): a batch step runs each group's line step, then its water
+# step, bit for bit as the channels alone
+ELEC_SPECS = [(37, 12, 9, 0.65, 2e-6, "duct"), (64, 10, 14, 0.9, 1e-6, "slab"),
+              (100, 8, 8, 1.1, 1.5e-6, "duct"), (33, 9, 11, 0.6, 1.2e-6, "slab"),
+              (150, 9, 7, 0.8, 1e-6, "duct")]
+
+
+def electron_channels(lbm, precision):
+    out = []
+    for k, (nx, ny, nz, tau, g, geom) in enumerate(ELEC_SPECS):
+        ch = lbm.Channel(19, lbm.DUCT if geom == "duct" else lbm.SLAB, nx, ny, nz, tau=tau,
+                         force=(g, 0, 0), precision=precision)
+        ch.set_friction(np.random.default_rng(40 + k).uniform(0.0, 0.3, ch.wall_count))
+        ch.set_electrons(0.8 + 0.05 * k, 0.7 + 0.2 * k, 0.03, -1e-6 * (k - 2))
+        if k % 2:
+            ch.set_phonons(0.7, 1.3, 0.02, 0.08)
+        out.append(ch)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16s"])
+def test_electron_batch_bit_identical_to_alone(lbm, precision):
+    say("electron batch vs alone", precision)
+    alone = electron_channels(lbm, precision)
+    mixed = electron_channels(lbm, precision)
+    for ch in alone + mixed:
+        ch.step(20)
+    alone[1].step(1)
+    mixed[1].step(1)
+    b = lbm.Batch(mixed)
+    b.step(150)
+    for ch in alone:
+        ch.step(150)
+    for a, m in zip(alone, mixed):
+        assert m.step_count == a.step_count
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])  # water and lines
+        assert np.array_equal(a.electrons()[0], m.electrons()[0])
+    inv = b.invariants()
+    for k, a in enumerate(alone):
+        assert abs(inv[k, 0] / a.invariants()[0] - 1) < 1e-13
+    b.close()
+
+
+def test_electron_tube_batch_bit_identical_to_alone(lbm):
+    say("electron tube batch vs alone")
+
+    def tubes():
+        out = []
+        for k, (R, nx, seed) in enumerate(TUBES):
+            n = int(2 * R + 4)
+            c = (n - 1) / 2
+            t = lbm.Channel(19, lbm.TUBE, nx, n, n, tau=0.8, force=(1e-6, 0, 0),
+                            precision="f32", tube_radius=float(R), tube_cy=c, tube_cz=c)
+            t.set_friction(np.random.default_rng(seed).uniform(0.0, 0.3, t.wall_count))
+            t.set_electrons(0.85, 0.9 + 0.3 * k, 0.05, 2e-6)
+            out.append(t)
+        return out
+
+    alone, mixed = tubes(), tubes()
+    b = lbm.Batch(mixed)
+    b.step(137)
+    for a, m in zip(alone, mixed):
+        a.step(137)
+        assert np.array_equal(a.get_state()[0], m.get_state()[0])
+    b.close()
+
+
+def test_electron_batch_fp64_against_oracle(lbm):
+    say("electron batch vs oracle")
+    chans = electron_channels(lbm, "f64")
+    b = lbm.Batch(chans)
+    b.step(101)
+    for k in (0, 1):
+        nx, ny, nz, tau, g, geom = ELEC_SPECS[k]
+        o = oracle.Lattice(19, oracle.DUCT if geom == "duct" else oracle.SLAB, nx, ny, nz,
+                           tau=tau, force=(g, 0, 0))
+        o.set_friction(np.random.default_rng(40 + k).uniform(0.0, 0.3, o.wall_count))
+        o.set_electrons(0.8 + 0.05 * k, 0.7 + 0.2 * k, 0.03, -1e-6 * (k - 2))
+        if k % 2:
+            o.set_phonons(0.7, 1.3, 0.02, 0.08)
+        o.step(101)
+        ug, uo = chans[k].field(1), o.fields()[1]
+        err = np.max(np.abs(ug - uo)) / np.max(np.abs(uo))
+        eg, eo = chans[k].electrons()[0], o.electrons()[0]
+        eerr = np.abs(eg - eo).max() / np.abs(eo).max()
+        say(f"  member {k}: water {err:.2e} u_e {eerr:.2e}")
+        assert err < 1e-12 and eerr < 1e-12
+    b.close()
+
+
+def test_electron_members_join_leave_and_change(lbm):
+    say("electron batch add / remove")
+    alone = electron_channels(lbm, "f32")
+    mixed = electron_channels(lbm, "f32")
+    cap = capacity_for(lbm, mixed, members=3, slack=2)
+    b = lbm.Batch.empty(19, "f32", False, electrons=True, **cap)
+    plain = make_ducts(lbm, SPECS[:1], "f32")[0]
+    with pytest.raises(lbm.LBMError):
+        b.add(plain)  # no electron lines
+    for k in (0, 2, 3):
+        b.add(mixed[k])
+    b.step(70)
+    for k in (0, 2, 3):
+        alone[k].step(70)
+    for ch in (mixed[2], alone[2]):  # new line parameters (lines reset to rest)
+        ch.set_electrons(0.9, 1.1, 0.01, 3e-6)
+    b.step(64)
+    for k in (0, 2, 3):
+        alone[k].step(64)
+    b.remove(mixed[0])
+    b.add(mixed[4])
+    b.step(65)
+    for k in (2, 3, 4):
+        alone[k].step(65)
+    for k in (0, 2, 3, 4):
+        assert np.array_equal(alone[k].get_state()[0], mixed[k].get_state()[0]), k
+    b.close()
