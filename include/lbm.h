@@ -275,13 +275,15 @@ lbm_status lbm_set_noise_closure(lbm_ctx *ctx, const double *gamma, int nr, int 
  * such channels.  Synchronous (finishes queued work). */
 lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_out);
 
-/* Electron wind (SLAB and DUCT).  Sec. 3.3 describes the electrons of the solid
+/* Electron wind (SLAB, DUCT and TUBE).  Sec. 3.3 describes the electrons of the solid
  * as a fluid dragged by, and dragging, the water; Sec. 4 gives each species
  * its own set of distributions; Eq. 5 / Eq. 27 make the interfacial force a
  * drag on the relative velocity, equal and opposite for the two species.
  * Every solid column next to the water (a "shell") carries one electron line
  * along x -- shells y = -1 and y = ny (by z), then for a duct z = -1 and
- * z = nz (by y), nshell = 2 nz (+ 2 ny for a duct): D1Q3
+ * z = nz (by y), nshell = 2 nz (+ 2 ny for a duct); for a TUBE the solid
+ * columns with a fluid column next to them along y or z, by increasing
+ * y + ny z (lbm_shell_count): D1Q3
  * populations (c = 0, +1, -1; w = 2/3, 1/6, 1/6; stored as deviations from
  * w_i rho_e0, double), BGK with tau_e, Guo forcing with
  *   F = force_e (a field drive along x) + F_wall - gamma_e rho_e u_e
@@ -289,6 +291,9 @@ lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_o
  * mixture r BB + (1 - r) (transverse reversal), but the bounce-back half
  * reflects off a wall moving with the electrons of the solid point x - c_i,
  *   BB_i = g_opp(i)(x) + 6 w_i rho0 c_ix u_e(x - c_i),
+ * (on a TUBE the interpolated bounce-back, the moving-wall term divided by
+ * 2q where the wall lies farther than half a link, as Bouzidi, Firdaouss and
+ * Lallemand move their walls, so that a uniform flow at u_e stays exact),
  * and F_wall hands the electrons exactly the axial momentum the water gains
  * there (the free-slip half exchanges none), so water plus electrons change
  * axial momentum only by the external forces and the lattice drag.  Each
@@ -297,15 +302,17 @@ lbm_status lbm_set_open_ends(lbm_ctx *ctx, int open, double rho_in, double rho_o
  * what the forces put in, gamma_e sum rho_e u_e = F_x N_fluid + force_e
  * N_lines; in a slab the sheets then move at one U_e and the water is the
  * slip-Poiseuille profile shifted by it.
- * Requires a SLAB or DUCT (a TUBE or MASKED gives LBM_EINVAL), wall_velocity_top == 0,
- * tau_e > 1/2, rho_e0 > 0, gamma_e >= 0, finite values (else LBM_EINVAL);
- * tau_e == 0 switches the sheets off.
+ * Requires a SLAB, DUCT or TUBE (MASKED gives LBM_EINVAL; so does a TUBE
+ * whose wall touches the box's edge, where no solid column holds a line),
+ * wall_velocity_top == 0, periodic x ends, tau_e > 1/2, rho_e0 > 0,
+ * gamma_e >= 0, finite values (else LBM_EINVAL); tau_e == 0 switches the
+ * sheets off.
  * Fields, flux and mass (the moments the next collision would see) take
  * the wall velocity from the last step's u_e.
  * Switching on resets the electrons to rest.  The electron and phonon lines
  * are part of the checkpoint (lbm_get_state / lbm_set_state) while they are
- * on; lbm_transfer_state copies the water only, and batches refuse channels
- * with sheets.  Synchronous. */
+ * on; lbm_transfer_state copies the water only; a batch takes channels with
+ * lines when all its members have them.  Synchronous. */
 lbm_status lbm_set_electrons(lbm_ctx *ctx, double tau_e, double rho_e0,
                              double gamma_e, double force_e);
 /* u_e of the last step (nshell * nx doubles, [shell][x]) and the current
@@ -331,9 +338,10 @@ lbm_status lbm_set_phonons(lbm_ctx *ctx, double tau_p, double rho_p0, double gam
  * populations (3 * nshell * nx, [i][shell][x]); host arrays, either may be
  * NULL.  LBM_ESTATE if the phonons are off.  Synchronous. */
 lbm_status lbm_get_phonons(lbm_ctx *ctx, double *up, double *pops);
-/* Number of electron shells (lines along x) of the channel: SLAB 2 nz, DUCT
- * 2 nz + 2 ny, TUBE the solid columns with a fluid column next to them along
- * y or z (numbered by increasing y + ny z), 0 otherwise. */
+/* Number of electron shells (lines along x; Sec. 3.3, the electrons of the
+ * solid next to the water) of the channel: SLAB 2 nz, DUCT 2 nz + 2 ny, TUBE
+ * the solid columns with a fluid column next to them along y or z (numbered
+ * by increasing y + ny z), 0 otherwise. */
 lbm_status lbm_shell_count(const lbm_ctx *ctx, size_t *n);
 
 /* Autotuner of the channel kernels: the block width (threads per workgroup
