@@ -462,6 +462,9 @@ void fill_args(lbm_ctx* c) {
   a.rho0 = c->p.rho0;
   a.omega = 1.0 / c->p.tau;
   for (int i = 0; i < 3; i++) a.F[i] = c->p.force[i];
+  a.rho0_f = (float)a.rho0;
+  a.omega_f = (float)a.omega;
+  for (int i = 0; i < 3; i++) a.F_f[i] = (float)a.F[i];
   a.utop = c->p.wall_velocity_top;
   a.dstep = nullptr;
   a.step_off = 0;

@@ -150,6 +150,8 @@ struct StepArgs {
   // element offset, from the start of a column, of the x-line of g_i in the
   // column the pull of link i reads: row(i) sI - c_iy sC - c_iz ny sC (no wrap)
   int64_t nboff[19];
+  // rho0, omega and F rounded to float (the float arithmetic's parameters)
+  float rho0_f, omega_f, F_f[3];
 };
 
 // ------------------------------------------------------------------ uniformity
@@ -307,35 +309,87 @@ __device__ __forceinline__ float sr_float(double v, uint32_t r16) {
   b = (b + ((uint64_t)r16 << 13)) & ~((1ull << 29) - 1ull);
   return (float)__longlong_as_double((long long)b);
 }
-// float -> half of v * 2^12, stochastic over the 13 discarded bits
-__device__ __forceinline__ _Float16 sr_half(float v, uint32_t r16) {
-  uint32_t b = __float_as_uint(v * kHalfScale);
-  b = (b + (r16 >> 3)) & ~0x1fffu;
-  return (_Float16)__uint_as_float(b);
+// float -> half, stochastic: gfx950's conversion with a stochastic-rounding
+// operand adds the top 13 bits of r (bits 19..31) to the 13 discarded
+// mantissa bits and truncates (checked bit for bit against that rule on
+// random inputs over the normal half range; results in the subnormal half
+// range are rounded stochastically at the subnormal spacing).  It writes
+// one half of a register and keeps the other; the register of the value
+// itself is passed as the kept one (no register has to be cleared first).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ _Float16 sr_half(float s, uint32_t r) {
+  return __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, s), s, r, false)[0];
 }
 
+// Store<S, M>: kScale is the factor between a population and what is stored
+// (2^12 for half storage); the collision forms its results already scaled
+// (every scaled term is a power-of-two multiple of the unscaled one, so
+// this is exact), and enc(v, bits) / enc2 (a pair from one random word)
+// round the scaled values to the storage type.
 template <typename S, typename M>
 struct Store {  // same precision: plain store
   static constexpr bool kRandom = false;
+  static constexpr float kScale = 1.0f;
   __device__ __forceinline__ static S enc(M v, uint32_t) { return static_cast<S>(v); }
+  __device__ __forceinline__ static void enc2(M vi, M vo, uint32_t, S* ei, S* eo) {
+    *ei = static_cast<S>(vi);
+    *eo = static_cast<S>(vo);
+  }
 };
 template <>
-struct Store<float, double> {
+struct Store<float, double> {  // 16 bits each: the low and the high half of the word
   static constexpr bool kRandom = true;
-  __device__ __forceinline__ static float enc(double v, uint32_t r) { return sr_float(v, r); }
+  static constexpr float kScale = 1.0f;
+  __device__ __forceinline__ static float enc(double v, uint32_t w) {
+    return sr_float(v, w & 0xffffu);
+  }
+  __device__ __forceinline__ static void enc2(double vi, double vo, uint32_t w, float* ei,
+                                              float* eo) {
+    *ei = sr_float(vi, w & 0xffffu);
+    *eo = sr_float(vo, w >> 16);
+  }
 };
 template <>
 struct Store<_Float16, float> {
   static constexpr bool kRandom = true;
-  __device__ __forceinline__ static _Float16 enc(float v, uint32_t r) { return sr_half(v, r); }
+  static constexpr float kScale = kHalfScale;
+  __device__ __forceinline__ static _Float16 enc(float s, uint32_t w) { return sr_half(s, w); }
+  // the word and the word rotated by 16: bits 19..31 and 3..15 of the
+  // word; both results in the halves of one register
+  __device__ __forceinline__ static void enc2(float si, float so, uint32_t w, _Float16* ei,
+                                              _Float16* eo) {
+    half2_t p = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, si), si, w, false);
+    p = __builtin_amdgcn_cvt_sr_f16_f32(p, so, __builtin_amdgcn_alignbit(w, w, 16), true);
+    *ei = p[0];
+    *eo = p[1];
+  }
 };
+// a parameter in the arithmetic type: float arithmetic takes the float copy
+template <typename M>
+__device__ __forceinline__ M par(double d, float) {
+  return static_cast<M>(d);
+}
+template <>
+__device__ __forceinline__ float par<float>(double, float f) {
+  return f;
+}
 template <typename S, typename M>
 __device__ __forceinline__ M dec(S v) {
   return static_cast<M>(v);
 }
+// -0.0f in a register the compiler cannot see into (a constant -0 addend
+// would be folded away, and with it the one-instruction decode below)
+__device__ __forceinline__ float opaque_neg_zero() {
+  float z;
+  asm("v_mov_b32 %0, 0x80000000" : "=v"(z));
+  return z;
+}
+// v * 2^-12 + (-0) is v * 2^-12 exactly (the product is exact and adding -0
+// keeps every value, the sign of zero included); in this form the
+// conversion and the scaling are one mixed-precision multiply-add
 template <>
 __device__ __forceinline__ float dec<_Float16, float>(_Float16 v) {
-  return static_cast<float>(v) * kHalfUnscale;
+  return __builtin_fmaf(static_cast<float>(v), kHalfUnscale, opaque_neg_zero());
 }
 template <>
 __device__ __forceinline__ double dec<_Float16, double>(_Float16 v) {
@@ -962,30 +1016,34 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
     if (L::cy[i]) jy += L::cy[i] > 0 ? df[i] : -df[i];
     if (L::cz[i]) jz += L::cz[i] > 0 ? df[i] : -df[i];
   }
-  const M Fx = static_cast<M>(a.F[0]), Fy = static_cast<M>(a.F[1]), Fz = static_cast<M>(a.F[2]);
+  const M Fx = par<M>(a.F[0], a.F_f[0]), Fy = par<M>(a.F[1], a.F_f[1]),
+          Fz = par<M>(a.F[2], a.F_f[2]);
   jx += Fx * M(0.5);
   jy += Fy * M(0.5);
   jz += Fz * M(0.5);
-  const M rho = static_cast<M>(a.rho0) + drho;
+  const M rho = par<M>(a.rho0, a.rho0_f) + drho;
   const M irho = M(1) / rho;
   const M ux = jx * irho, uy = jy * irho, uz = jz * irho;
-  const M om = static_cast<M>(a.omega);
+  const M om = par<M>(a.omega, a.omega_f);
   const M A = M(1) - M(0.5) * om;
   const M usq15 = M(1.5) * (ux * ux + uy * uy + uz * uz);
   const M uF3 = M(3) * (ux * Fx + uy * Fy + uz * Fz);
-  const M C0 = om * (drho - rho * usq15) - A * uF3;
-  const M k45 = M(4.5) * om * rho, a9 = M(9) * A;
+  // the terms of the new populations, each times the storage scale sc
+  constexpr M sc = static_cast<M>(Store<S, M>::kScale);
+  const M C0 = (om * (drho - rho * usq15) - A * uF3) * sc;
+  const M k45 = M(4.5) * om * rho * sc, a9 = M(9) * A * sc;
   const M Ux = k45 * ux + a9 * Fx, Uy = k45 * uy + a9 * Fy, Uz = k45 * uz + a9 * Fz;
-  const M Jx = om * jx + A * Fx, Jy = om * jy + A * Fy, Jz = om * jz + A * Fz;
-  const M keep = M(1) - om;
+  const M oms = om * sc, As = A * sc;
+  const M Jx = oms * jx + As * Fx, Jy = oms * jy + As * Fy, Jz = oms * jz + As * Fz;
+  const M keep = (M(1) - om) * sc;
   // rounding bits: one 32-bit word for the rest population, then one per
   // opposite pair (low half for the first direction, high half for its opposite)
   RoundBits rb(a.seed, step, Store<S, M>::kRandom ? cell : 0u);
   {
     const uint32_t w0 = Store<S, M>::kRandom ? rb.next() : 0u;
     M v = keep * df[0] + static_cast<M>(L::w[0]) * C0;
-    if constexpr (THERM) v += xi[0];
-    const S e = Store<S, M>::enc(v, w0 & 0xffffu);
+    if constexpr (THERM) v += xi[0] * sc;
+    const S e = Store<S, M>::enc(v, w0);
     store_pop<NT>(at(sbase(out_col + L::row[0] * a.sI), x), e);
     if constexpr (REC) {
       rec[0] = dec<S, M>(e);
@@ -1005,12 +1063,12 @@ __device__ __forceinline__ void collide_store(const M* df, const StepArgs& a, LB
     M vi = (keep * df[i] + E) + O;
     M vo = (keep * df[o] + E) - O;
     if constexpr (THERM) {
-      vi += xi[i];
-      vo += xi[o];
+      vi += xi[i] * sc;
+      vo += xi[o] * sc;
     }
     const uint32_t word = Store<S, M>::kRandom ? rb.next() : 0u;
-    const S ei = Store<S, M>::enc(vi, word & 0xffffu);
-    const S eo = Store<S, M>::enc(vo, word >> 16);
+    S ei, eo;
+    Store<S, M>::enc2(vi, vo, word, &ei, &eo);
     store_pop<NT>(at(sbase(out_col + L::row[i] * a.sI), x), ei);
     store_pop<NT>(at(sbase(out_col + L::row[o] * a.sI), x), eo);
     if constexpr (REC) {  // c_o = -c_i
