@@ -512,6 +512,21 @@ struct OmegaEntry {
   double s, t, v, pad;  // w^2, gamma_s^2 w^2, gamma_s w Im g_l(w) / sinh^2(w/2T)
 };
 
+// 1/d for the integrands' denominators (positive, far inside the normal
+// range: at least gamma_s^2 (dw/2)^2): the hardware reciprocal refined by
+// two Newton-Raphson steps r <- r + r (1 - d r), each of which squares the
+// relative error, so the result is within about an ulp of 1/d.  Four fused
+// multiply-adds and one reciprocal instead of the scaled, fixed-up IEEE
+// division; the sums it feeds hold positive terms, so their relative error
+// stays at that level.
+__device__ __forceinline__ double recip_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
 // raw[k] for k < n uses omega[k]; raw[n] is the reference at omega0.
 __global__ void __launch_bounds__(kQuadThreads) k_friction_raw(SpecArgs s,
                                                                const double* __restrict__ omega,
@@ -567,7 +582,7 @@ __global__ void __launch_bounds__(kQuadThreads) k_friction_raw(SpecArgs s,
 #pragma unroll
         for (int j = 0; j < kQuadNodes; j++) {
           const double dd = P[j] - e.s;
-          S[j] += e.v / (dd * dd + e.t);
+          S[j] = __builtin_fma(e.v, recip_nr(dd * dd + e.t), S[j]);
         }
       }
 #pragma unroll
@@ -674,9 +689,9 @@ __global__ void __launch_bounds__(kQuadThreads) k_friction_full(SpecArgs s,
           if constexpr (SCREEN) {
             const double a = dd * Rl - c1, bb = dd * Il + c2;
             const double A = D - eP[j] * a, B = eP[j] * bb;
-            S[j] += vI * D / (A * A + B * B);
+            S[j] = __builtin_fma(vI * D, recip_nr(A * A + B * B), S[j]);
           } else {
-            S[j] += vI / D;
+            S[j] = __builtin_fma(vI, recip_nr(D), S[j]);
           }
         }
       }
