@@ -453,6 +453,57 @@ def test_f16s_storage_error_bounded(lbm):
     assert eu < 1.1e-3 and abs(qg / qo - 1) < 1e-5
 
 
+@pytest.mark.parametrize("precision", ["f16s", "f32"])
+def test_stored_values_are_stochastically_rounded(lbm, precision):
+    # one step from a random state that the storage holds exactly: every
+    # stored population against the FP64 oracle's value of the same step,
+    # in units of the storage spacing there.  Stochastic rounding keeps each
+    # value at one of the two neighbours of the exact one (|r| < 1), with no
+    # bias (mean r = 0) and, unlike round-to-nearest (|r| <= 1/2, mean |r| =
+    # 1/4), lands on the farther neighbour a quarter of the time (mean |r| =
+    # 1/3).  Half storage holds the deviations times 2^12, its arithmetic is
+    # float (about 2^-13 of a half spacing off the FP64 value).
+    say("stochastic rounding", precision)
+    nx, ny, nz = 40, 12, 10
+    G, O = pair(lbm, 19, lbm.DUCT, nx, ny, nz, 0.8, 1e-5, precision)
+    lam = inputs.duct_friction(G.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 13))
+    G.set_friction(lam)
+    O.set_friction(lam)
+    rng = np.random.default_rng(21)
+    g0 = rng.normal(0.0, 1e-3, (19, nz, ny, nx))
+    if precision == "f16s":
+        scale, st = 4096.0, np.float16
+    else:
+        scale, st = 1.0, np.float32
+    g0 = (g0 * scale).astype(st).astype(np.float64) / scale  # exactly representable
+    G.set_populations(g0, step=5)
+    O.set_populations(g0, step=5)
+    assert np.array_equal(G.populations(), g0)
+    G.step(1)
+    O.step(1)
+    stored = (G.populations() * scale).ravel()
+    exact = (O.get_populations() * scale).ravel()
+    assert np.array_equal(stored.astype(st).astype(np.float64), stored)
+    lo = np.minimum(np.abs(stored), np.abs(exact)).astype(st)
+    sp = np.spacing(lo).astype(np.float64)
+    # float arithmetic is a few float ulps of the terms it adds off the FP64
+    # value: where they cancel to a result near zero that can exceed the
+    # (tiny) spacing there, so the bound carries it and the statistics skip
+    # those values
+    slack = 8 * 2.0**-24 * np.max(np.abs(exact)) if precision == "f16s" else 0.0
+    assert np.all(np.abs(stored - exact) <= 1.001 * sp + slack)
+    keep = sp > 64 * slack
+    r = (stored - exact)[keep] / sp[keep]
+    far = np.mean(np.abs(r) > 0.5)
+    say("  values", r.size, "max |r|", np.max(np.abs(r)), "mean r", np.mean(r), "mean |r|",
+        np.mean(np.abs(r)), "share |r| > 1/2", far)
+    assert r.size > stored.size // 2  # measured: 57,158 of 91,200 for half storage
+    assert np.max(np.abs(r)) < 1.001
+    assert abs(np.mean(r)) < 0.01  # 0.5 / sqrt(45,600) = 0.0023 per standard deviation
+    assert 0.31 < np.mean(np.abs(r)) < 0.36
+    assert 0.22 < far < 0.28
+
+
 @pytest.mark.parametrize("nx", [40, 72])  # 72: the half and float x-lines are padded differently
 def test_transfer_state_across_precisions(lbm, nx):
     say("transfer", nx)
