@@ -185,22 +185,26 @@ def extras(torch, lbm, inputs, args):
                        "hbm_frac": round(304 * cells / (kms * 1e-3 / 2000) / 1e9 / HBM_PEAK_GBS, 4)}
     ch.close()
     del ch
-    # the FP32 duct far beyond the 256 MB last-level cache (512 x 256 x 128,
-    # 2.55 GB of state, nontemporal stores): the step kernel against HBM alone
+    # the duct far beyond the 256 MB last-level cache (512 x 256 x 128: 2.55
+    # GB of FP32 state, 1.27 GB of half state; nontemporal stores): the step
+    # kernel against HBM alone, in float and half storage
     nx, ny, nz = 512, 256, 128
-    ch = lbm.Channel(lbm.D3Q19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
-                     precision="f32")
-    ch.set_friction(inputs.duct_friction(ch.wall_coords(), nx, ny, nz, inputs.rng_for("duct", 0)))
-    ch.step(100)
-    wall, kms = timed_run(torch, ch, 1000, 1000)
-    cells = ch.fluid_count
-    out["duct_512x256x128_f32"] = {
-        "mlups": round(cells * 1000 / wall / 1e6, 1), "kernel_us": round(kms * 1e3 / 1000, 2),
-        "hbm_frac": round(152 * cells / (kms * 1e-3 / 1000) / 1e9 / HBM_PEAK_GBS, 4),
-        "state_gb": round(2 * 76 * cells / 1e9, 2)}
-    ch.close()
-    del ch
-    torch.cuda.empty_cache()
+    for prec in ("f32", "f16s"):
+        ch = lbm.Channel(lbm.D3Q19, lbm.DUCT, nx, ny, nz, tau=0.7, force=(1e-6, 0.0, 0.0),
+                         precision=prec)
+        ch.set_friction(inputs.duct_friction(ch.wall_coords(), nx, ny, nz,
+                                             inputs.rng_for("duct", 0)))
+        ch.step(100)
+        wall, kms = timed_run(torch, ch, 1000, 1000)
+        cells = ch.fluid_count
+        bpu = BYTES_PER_UPDATE[prec]
+        out[f"duct_512x256x128_{prec}"] = {
+            "mlups": round(cells * 1000 / wall / 1e6, 1), "kernel_us": round(kms * 1e3 / 1000, 2),
+            "hbm_frac": round(bpu * cells / (kms * 1e-3 / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+            "state_gb": round(bpu * cells / 1e9, 2)}
+        ch.close()
+        del ch
+        torch.cuda.empty_cache()
     R, nx = 32, 512
     ny, nz, cy, cz = inputs.tube_box(R)
     tb = lbm.Channel(lbm.D3Q19, lbm.TUBE, nx, ny, nz, tau=0.8, force=(1e-6, 0, 0), precision="f32",
