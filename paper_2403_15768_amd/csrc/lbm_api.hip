@@ -287,6 +287,20 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     pl.nwallslots = (int64_t)first.size();
     pl.slots = first;
     pl.slots.insert(pl.slots.end(), rest.begin(), rest.end());
+    // the points a wall row's columns compute, packed to the front of the
+    // column's lanes (the waves past them have nothing to do and leave):
+    // the non-solid x, then the padding lanes (x >= nx, computing cell
+    // nx - 1 again) where that cell is fluid
+    const int64_t rs = (int64_t)pl.nxp + 1;
+    pl.rowx.assign((size_t)(ny * rs), 0);
+    for (int y = 0; y < ny; y++) {
+      if (!wallrow[y]) continue;
+      int32_t* r = pl.rowx.data() + y * rs;
+      for (int x = 0; x < pl.nxp; x++) {
+        const int xc = x < nx ? x : nx - 1;
+        if (pl.cellw[xc + (int64_t)nx * y] != lbm::kCellSolid) r[1 + r[0]++] = x;
+      }
+    }
   }
   pl.bx = std::min((pl.nx + 63) / 64 * 64, 512);
   pl.segs = (pl.nx + pl.bx - 1) / pl.bx;
@@ -414,6 +428,7 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
   pl.off_swc = take(pl.sheet_wc.size() * sizeof(int32_t));
   pl.off_shellof = take(pl.shellof.size() * sizeof(int32_t));
   pl.off_cellw = take(pl.cellw.size() * sizeof(int32_t));
+  pl.off_rowx = take(pl.rowx.size() * sizeof(int32_t));
   // open ends: per population buffer, [side][column][4] records of the end nodes
   pl.off_bmom = take((size_t)2 * 2 * pl.ncolbox * 4 * sizeof(double));
   pl.off_ptab = take(pl.ptab.size());
@@ -476,6 +491,7 @@ void fill_args(lbm_ctx* c) {
   a.ue = nullptr;
   a.shellof = pl.shellof.empty() ? nullptr : c->at<int32_t>(pl.off_shellof);
   a.cellw = pl.masked ? c->at<int32_t>(pl.off_cellw) : nullptr;
+  a.rowx = pl.masked ? c->at<int32_t>(pl.off_rowx) : nullptr;
   a.ptab = pl.masked ? c->at<uint8_t>(pl.off_ptab) : nullptr;
   a.nw2d = pl.nw2d;
   a.open = 0;
@@ -792,6 +808,7 @@ lbm_status lbm_create(const lbm_params* p, void* arena, size_t arena_bytes, void
       break;
     if (pl.masked &&
         ((st = upload(c, pl.off_cellw, pl.cellw.data(), pl.cellw.size() * sizeof(int32_t))) != LBM_OK ||
+         (st = upload(c, pl.off_rowx, pl.rowx.data(), pl.rowx.size() * sizeof(int32_t))) != LBM_OK ||
          (st = upload(c, pl.off_ptab, pl.ptab.data(), pl.ptab.size())) != LBM_OK))
       break;
     std::vector<double> inf(pl.nwall, INFINITY);

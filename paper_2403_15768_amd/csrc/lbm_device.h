@@ -152,6 +152,11 @@ struct StepArgs {
   int64_t nboff[19];
   // rho0, omega and F rounded to float (the float arithmetic's parameters)
   float rho0_f, omega_f, F_f[3];
+  // masked walls: per row y of the (x, y) plane that holds wall nodes, its
+  // count of points to compute and their x, packed: rowx[y (nxp + 1)] is
+  // the count, rowx[y (nxp + 1) + 1 + k] the k-th x (the non-solid points
+  // in increasing x, then the padding lanes if the last point is fluid)
+  const int32_t* rowx;
 };
 
 // ------------------------------------------------------------------ uniformity

@@ -49,7 +49,8 @@ struct Plan {
   int64_t nw2d = 0;
   int pstride = 0;         // partner-table bytes per 2-D wall node (whole words)
   int64_t nwallslots = 0;  // leading slots whose columns hold wall nodes
-  size_t off_cellw = 0, off_ptab = 0;
+  std::vector<int32_t> rowx;  // per wall row: count, then the x of its points ([y][nxp + 1])
+  size_t off_cellw = 0, off_ptab = 0, off_rowx = 0;
   size_t off_bmom = 0;  // open ends: [side][column][4] moments of the end nodes
   int64_t nsheet = 0;               // electron shell nodes (nshell nx)
   // per shell: the wall column of the fluid column next to it (SLAB, DUCT);

@@ -164,11 +164,12 @@ __global__ void __launch_bounds__(512) k_step_open(const S* __restrict__ src,
 }
 
 // Masked walls: the same update on every fluid point of the columns that
-// hold one.  Columns with wall nodes come first (slot mask != 0); there the
-// class of each point (solid, interior, wall node) comes from a table of the
-// (x, y) plane, so a wave may hold all three, and solid points are neither
-// computed nor stored (nothing reads them).  The other columns are wholly
-// interior and only pull.  Their order alternates as in k_step.  OPEN: open x
+// hold one.  Columns with wall nodes come first (slot mask != 0); their
+// lanes take the row's non-solid points from a packed list (solid points
+// are neither computed nor stored: nothing reads them), and the class of
+// each point (interior or wall node) comes from a table of the (x, y)
+// plane, so a wave may hold both.  The other columns are wholly interior
+// and only pull.  Their order alternates as in k_step.  OPEN: open x
 // ends (the mask's first and last rows are equal, so the wall links are
 // those of the periodic channel): the ghost pulls and the end-node records as
 // in the open step kernel.
@@ -177,14 +178,22 @@ __global__ void __launch_bounds__(512) k_step_masked(const S* __restrict__ src,
                                                      S* __restrict__ dst, StepArgs a) {
   int slot = blockIdx.x;
   if (a.rev && slot >= a.nwallcols) slot = a.nactive - 1 - slot + a.nwallcols;
-  const int x = blockIdx.y * a.bx + threadIdx.x;
-  if (x >= a.nxp) return;
-  const int xc = x < a.nx ? x : a.nx - 1;  // padding lanes: cell nx - 1 again
   const LBM_GLOBAL ColSlot& cs = gbl(a.slots)[slot];
   const int col = uniform(cs.col);
   const bool wallcol = uniform((int)cs.mask) != 0;
   const int z = col / a.ny;
   const int y = col - z * a.ny;
+  // a column of a wall row takes its points from the row's packed list, so
+  // that its solid points hold no lanes (whole waves past the list leave)
+  int x = blockIdx.y * a.bx + threadIdx.x;
+  if (wallcol) {
+    const LBM_GLOBAL int32_t* rx = gbl(a.rowx) + (int64_t)y * (a.nxp + 1);
+    if (x >= uniform(rx[0])) return;
+    x = rx[1 + x];
+  } else if (x >= a.nxp) {
+    return;
+  }
+  const int xc = x < a.nx ? x : a.nx - 1;  // padding lanes: cell nx - 1 again
   const int cw = wallcol ? gbl(a.cellw)[xc + (int64_t)a.nx * y] : kCellInterior;
   if (cw == kCellSolid) return;
   const int64_t step = (a.dstep ? uniform64(*gbl(a.dstep)) : 0) + a.step_off;
