@@ -295,10 +295,12 @@ lbm_status make_plan(const lbm_params* p, Plan* P, std::string* err) {
     pl.rowx.assign((size_t)(ny * rs), 0);
     for (int y = 0; y < ny; y++) {
       if (!wallrow[y]) continue;
-      int32_t* r = pl.rowx.data() + y * rs;
+      int32_t* r = pl.rowx.data() + y * rs;  // r[0]: count, r[1..]: the points' x
       for (int x = 0; x < pl.nxp; x++) {
         const int xc = x < nx ? x : nx - 1;
-        if (pl.cellw[xc + (int64_t)nx * y] != lbm::kCellSolid) r[1 + r[0]++] = x;
+        if (pl.cellw[xc + (int64_t)nx * y] == lbm::kCellSolid) continue;
+        r[1 + r[0]] = x;
+        r[0]++;
       }
     }
   }
